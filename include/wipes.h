@@ -1,0 +1,257 @@
+/*
+ * wipes.h -- C ABI of the MI355X (gfx950) wavelet rasterizer.
+ *
+ * The library renders, and differentiates, images made of wavelet
+ * primitives as defined in "WIPES: Wavelet-based Visual Primitives"
+ * (arXiv 2508.12615):
+ *   - primitive:   W(x) = 1/2 [cos(f.(x - mu)) + 1] G(x; mu, Sigma)      Sec. 4.1, Eq. 6
+ *   - projection:  Sigma' = 2x2 block of J W Sigma W^T J^T; f goes through
+ *                  the same ray-space map                                 Sec. 3.1 Eq. 2; Sec. 4.1 Eq. 7
+ *   - blending:    additive weighted sum (2D images)                      Sec. 3.2, Eq. 4
+ *                  front-to-back alpha compositing (3D scenes)           Sec. 3.1, Eq. 3
+ *   - rasterizer:  tile binning + depth-keyed sort + per-tile blending,
+ *                  "a similar pipeline as in 3D GS"                        Sec. 4.1
+ *   - backward:    explicit gradients for every parameter                 Sec. 1 (contributions)
+ *
+ * Conventions for every call:
+ *   - All pointers named "device" are HIP device pointers owned by the
+ *     caller; the library never allocates on the render path.  Host
+ *     structs (params, camera, batch) are read during the call only.
+ *   - Every call returns a wipes_status and never throws.  Host-side
+ *     validation (NULL pointers, sizes, mode mismatches) returns
+ *     WIPES_ERR_INVALID before any work is queued.  A HIP failure returns
+ *     WIPES_ERR_DEVICE; wipes_last_error() then holds the HIP message.
+ *   - Calls are asynchronous on the given hipStream_t (passed as void*;
+ *     NULL = the default stream) unless stated otherwise.
+ *   - A wipes_ctx is used by one host thread at a time.  A wipes_server is
+ *     internally synchronised.
+ *   - Arrays are row-major; "[n, k]" means n rows of k float32 values.
+ *
+ * The per-pixel rule, identical for every tile shape and launch form:
+ *   pixel (x, y) has centre p = (x + 1/2, y + 1/2); d = p - mu'; q = d^T A d
+ *   with A = Sigma'^-1; phi = f'.d; W' = 1/2 (1 + cos phi) exp(-q/2).
+ *   Additive:  C = sum_i c_i o_i W'_i over primitives with q_i <= q_add, in
+ *              primitive order.
+ *   Alpha:     primitives in ascending depth key (ties by index); a = o W';
+ *              skip if a < alpha_min; alpha = min(a, alpha_max);
+ *              C += T alpha c; T *= 1 - alpha; stop after the pair that
+ *              leaves T < T_min; finally C += T bg.
+ */
+#ifndef WIPES_H
+#define WIPES_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---------------------------------------------------------------- status */
+
+typedef enum {
+    WIPES_OK = 0,
+    WIPES_ERR_INVALID = 1,   /* bad argument; nothing was queued */
+    WIPES_ERR_NOMEM = 2,     /* a buffer is too small, or a server arena is full */
+    WIPES_ERR_CAPACITY = 3,  /* more tile instances than the bins buffer holds */
+    WIPES_ERR_DEVICE = 4,    /* HIP runtime error (see wipes_last_error) */
+    WIPES_ERR_BUSY = 5,      /* server queue full, or scene still in use */
+    WIPES_ERR_NOTFOUND = 6   /* unknown scene or request id */
+} wipes_status;
+
+typedef enum {
+    WIPES_2D_ADDITIVE = 0,   /* 2D primitives on the image plane, Eq. 4 with W' (Sec. 4.3) */
+    WIPES_3D_ALPHA = 1       /* 3D primitives, EWA projection, Eq. 3 with W' (Sec. 4.1) */
+} wipes_mode;
+
+typedef enum {
+    WIPES_COV_CHOLESKY = 0,  /* 2D: cov = (l11, l21, l22), Sigma = L L^T (Sec. 5.1) */
+    WIPES_COV_RS = 1,        /* 2D: cov = (s1, s2, theta), Sigma = R diag(s1^2, s2^2) R^T (Sec. 5.1) */
+    WIPES_COV_QUAT_SCALE = 2 /* 3D: Sigma = R(q) S S^T R(q)^T, q = (w,x,y,z) normalised inside (Sec. 3.1) */
+} wipes_cov;
+
+typedef enum {
+    WIPES_FREQ_VECTOR = 0,   /* f' = J W f, the ray-space map applied to f as to Sigma (Sec. 4.1) */
+    WIPES_FREQ_COVECTOR = 1  /* reserved: phase-preserving variant; rejected with WIPES_ERR_INVALID */
+} wipes_freq_xform;
+
+/* ---------------------------------------------------------------- inputs */
+
+/* Rasterizer constants.  wipes_params_default() fills the documented defaults. */
+typedef struct {
+    int32_t mode;         /* wipes_mode */
+    int32_t cov;          /* wipes_cov; must be QUAT_SCALE for 3D, CHOLESKY or RS for 2D */
+    int32_t freq_xform;   /* wipes_freq_xform */
+    int32_t tile_w;       /* tile width in pixels: 8, 16 or 32 */
+    int32_t tile_h;       /* tile height in pixels: 8 or 16; tile_w * tile_h in {64, 128, 256, 512} */
+    int32_t persistent;   /* 0: one wave per tile, grid launch; 1: persistent tile queue */
+    float alpha_min;      /* 1/255: pairs with o W' below it are skipped (alpha) */
+    float alpha_max;      /* 0.99: clamp of o W' (alpha) */
+    float T_min;          /* 1e-4: termination threshold on transmittance (alpha) */
+    float q_add;          /* 9: additive support q <= q_add (3-sigma ellipse) */
+    float blur_eps;       /* Sigma' += eps I: 0.3 px^2 (3D), 0 (2D) */
+    float near_plane;     /* 0.01: cull primitives with camera z <= near */
+    float fov_guard;      /* 1.3: x/z, y/z clamped to +-guard*half-fov inside J */
+    float bg[3];          /* background colour added with the final T (alpha) */
+} wipes_params;
+
+/* Pinhole camera.  viewmat is world->camera, row-major 4x4, OpenCV axes
+ * (x right, y down, z forward).  2D mode uses width/height only. */
+typedef struct {
+    int32_t width, height;
+    float fx, fy, cx, cy;
+    float viewmat[16];
+    float time;           /* tau: means move as mu0 + v tau when velocity != NULL */
+} wipes_camera;
+
+/* Device arrays of one image's primitives (structure of arrays, float32).
+ * D = 2 (2D) or 3 (3D).  Unused members may be NULL.
+ *   mean [n, D], cov [n, 3] (2D), quat [n, 4] (3D), scale [n, 3] (3D),
+ *   freq [n, D] (rad per pixel in 2D, rad per world unit in 3D),
+ *   color [n, 3], opacity [n], velocity [n, 3] (3D, optional). */
+typedef struct {
+    int64_t n;
+    const float* mean;
+    const float* cov;
+    const float* quat;
+    const float* scale;
+    const float* freq;
+    const float* color;
+    const float* opacity;
+    const float* velocity;
+} wipes_prims;
+
+/* Device gradient outputs, same shapes as wipes_prims; NULL members are skipped.
+ * render_bwd overwrites (does not accumulate into) every non-NULL array. */
+typedef struct {
+    float* mean;
+    float* cov;
+    float* quat;
+    float* scale;
+    float* freq;
+    float* color;
+    float* opacity;
+    float* velocity;
+} wipes_prims_grad;
+
+typedef struct {
+    wipes_camera cam;
+    wipes_prims prims;
+    wipes_prims_grad grads;   /* read by wipes_render_bwd only */
+} wipes_image;
+
+/* A batch of images rendered together (B = 1 is the plain rasterizer).
+ * Pixels of image b occupy [pix_b, pix_b + W_b H_b) of every per-pixel
+ * array, pix_b = sum of W H over earlier images; tiles are numbered the same
+ * way (global tile = tiles of earlier images + ty * tiles_x + tx). */
+typedef struct {
+    int32_t n_images;
+    const wipes_image* images;   /* host array of n_images */
+} wipes_batch;
+
+/* Caller-allocated device workspace.  For the bins buffer, capacity and
+ * with_backward must be the values passed to wipes_workspace_size (the
+ * buffer layout depends on them); the screen buffer ignores both. */
+typedef struct {
+    void* base;
+    size_t bytes;
+    int64_t capacity;        /* bins: instance capacity */
+    int32_t with_backward;   /* bins: sized for the backward pass */
+    int32_t reserved;
+} wipes_buffer;
+
+/* Screen-space record written by wipes_project, one per primitive, 64 bytes,
+ * at the start of the screen buffer in batch order (image 0's primitives
+ * first).  The mean is mx + mx_lo (an FP32 pair carrying an FP64 value, so
+ * the carrier phase stays exact at 1080p).  box0/box1 pack the pixel box
+ * (x0 | y0 << 16, x1 | y1 << 16) and are written by wipes_bin_sort. */
+typedef struct {
+    float mx, my;          /* mu' (pixels), FP32 rounding */
+    float ca, cb, cc;      /* conic A = Sigma'^-1 = [[ca, cb], [cb, cc]] */
+    float fx, fy;          /* f' (rad per pixel) */
+    float opacity;
+    float r, g, b;
+    float mx_lo, my_lo;    /* mu' - (mx, my) */
+    float reserved;
+    uint32_t box0, box1;
+} wipes_screen_record;
+
+/* Binning inputs written by wipes_project right after the records
+ * (screen buffer offset sum_n * 64), one per primitive, 16 bytes. */
+typedef struct {
+    float rx, ry;          /* half-extents of the support box (pixels); rx < 0: culled */
+    float depth;           /* FP32 depth key (3D), 0 (2D) */
+    float reserved;
+} wipes_bin_input;
+
+/* ------------------------------------------------------------- context */
+
+typedef struct wipes_ctx wipes_ctx;
+
+/* Fill p with the defaults listed in wipes_params for the given mode. */
+void wipes_params_default(int32_t mode, wipes_params* p);
+
+/* Create a context on HIP device `device` (made current for the call). */
+wipes_status wipes_ctx_create(int32_t device, wipes_ctx** out);
+void wipes_ctx_destroy(wipes_ctx* ctx);
+/* Message of the last failing call on this context ("" if none).  Owned by ctx. */
+const char* wipes_last_error(const wipes_ctx* ctx);
+
+/* Bytes of the screen and bins buffers for a batch and an instance capacity
+ * (number of (primitive, tile) pairs).  with_backward != 0 adds room for the
+ * backward pass.  Host only; no device work. */
+wipes_status wipes_workspace_size(const wipes_params* p, const wipes_batch* batch, int64_t capacity_instances,
+                                  int32_t with_backward, size_t* screen_bytes, size_t* bins_bytes);
+
+/* ---------------------------------------------------------- render path */
+
+/* Project every primitive of the batch to its screen record (Eq. 2, Eq. 7 and
+ * the frequency transform of Sec. 4.1 for 3D; identity placement for 2D). */
+wipes_status wipes_project(wipes_ctx* ctx, const wipes_params* p, const wipes_batch* batch, wipes_buffer* screen,
+                           void* stream);
+
+/* Tile binning and sort: pixel boxes, per-primitive tile counts, instance
+ * emission, stable sort by (tile, depth key, index), per-tile ranges.
+ * n_instances_out != NULL: the call synchronises the stream once to read the
+ * instance count K into *n_instances_out, and returns WIPES_ERR_CAPACITY
+ * (with *n_instances_out = K) if K exceeds the bins buffer's capacity.
+ * n_instances_out == NULL: no host synchronisation (graph capture); an
+ * overflow sets a device flag that turns the later stages into no-ops and is
+ * reported by wipes_check_overflow. */
+wipes_status wipes_bin_sort(wipes_ctx* ctx, const wipes_params* p, const wipes_batch* batch, wipes_buffer* screen,
+                            wipes_buffer* bins, int64_t* n_instances_out, void* stream);
+
+/* Forward blend (Eq. 3 or Eq. 4 with W').  image: device [sum W H, 3];
+ * T_final, last: device [sum W H] (alpha mode; may be NULL in additive mode).
+ * last holds the sorted-list position of the last contributing pair (-1: none). */
+wipes_status wipes_render_fwd(wipes_ctx* ctx, const wipes_params* p, const wipes_batch* batch,
+                              const wipes_buffer* screen, const wipes_buffer* bins, float* image, float* T_final,
+                              int32_t* last, void* stream);
+
+/* Backward pass: dL/dimage (device [sum W H, 3]) -> parameter gradients
+ * written to each image's grads.  Alpha mode walks each pixel's list back
+ * to front from `last`, recovering transmittance by division (nothing per
+ * pair is stored by the forward).  dscreen (optional, device [sum n, 11])
+ * receives the screen-space gradients d/d(mu'x, mu'y, ca, cb, cc, f'x, f'y,
+ * opacity, r, g, b).  Needs the bins buffer sized with_backward. */
+wipes_status wipes_render_bwd(wipes_ctx* ctx, const wipes_params* p, const wipes_batch* batch,
+                              const wipes_buffer* screen, const wipes_buffer* bins, const float* T_final,
+                              const int32_t* last, const float* dL_dimage, float* dscreen, void* stream);
+
+/* Read back the instance count K and the overflow flag of the last bin_sort
+ * on this screen buffer (synchronises the stream).  Returns WIPES_ERR_CAPACITY
+ * if K exceeded the bins capacity, WIPES_OK otherwise. */
+wipes_status wipes_check_overflow(wipes_ctx* ctx, const wipes_params* p, const wipes_batch* batch,
+                                  const wipes_buffer* screen, int64_t* required_instances, void* stream);
+
+/* Device views into the bins buffer after bin_sort (for inspection and tests):
+ * sorted tile keys and primitive indices [K] and tile ranges [n_tiles, 2]. */
+wipes_status wipes_bins_view(const wipes_params* p, const wipes_batch* batch, const wipes_buffer* screen,
+                             const wipes_buffer* bins, const uint32_t** keys, const uint32_t** vals,
+                             const uint32_t** ranges, int64_t* n_tiles);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* WIPES_H */

@@ -1,0 +1,466 @@
+// C ABI of the wavelet rasterizer: argument validation, workspace layout,
+// descriptor upload and stage sequencing.  No allocation on the render path:
+// every device buffer is the caller's.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "api_internal.hpp"
+
+using namespace wipes;
+
+// --------------------------------------------------------------- helpers
+
+namespace wipes {
+
+static thread_local std::string g_err_no_ctx;
+
+wipes_status fail(wipes_ctx* ctx, wipes_status st, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    if (ctx) ctx->err = buf; else g_err_no_ctx = buf;
+    return st;
+}
+
+wipes_status hip_fail(wipes_ctx* ctx, hipError_t e, const char* where)
+{
+    return fail(ctx, WIPES_ERR_DEVICE, "%s: %s", where, hipGetErrorString(e));
+}
+
+static size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+static int ilog2(int v)
+{
+    int r = 0;
+    while ((1 << r) < v) ++r;
+    return r;
+}
+
+bool tile_ok(int tw, int th)
+{
+    return (tw == 8 && th == 8) || (tw == 16 && th == 8) || (tw == 16 && th == 16) || (tw == 32 && th == 8) ||
+           (tw == 8 && th == 16) || (tw == 32 && th == 16);
+}
+
+KParams kparams(const wipes_params* p)
+{
+    KParams k;
+    k.mode = p->mode;
+    k.cov = p->cov;
+    k.tile_w = p->tile_w;
+    k.tile_h = p->tile_h;
+    k.log2_tw = ilog2(p->tile_w);
+    k.log2_th = ilog2(p->tile_h);
+    k.alpha_min = p->alpha_min;
+    k.alpha_max = p->alpha_max;
+    k.T_min = p->T_min;
+    k.q_add = p->q_add;
+    k.blur_eps = p->blur_eps;
+    k.near_plane = p->near_plane;
+    k.bg[0] = p->bg[0];
+    k.bg[1] = p->bg[1];
+    k.bg[2] = p->bg[2];
+    return k;
+}
+
+wipes_status validate(wipes_ctx* ctx, const wipes_params* p, const wipes_batch* b, bool need_grads)
+{
+    if (!p || !b) return fail(ctx, WIPES_ERR_INVALID, "params and batch must not be NULL");
+    if (p->mode != WIPES_2D_ADDITIVE && p->mode != WIPES_3D_ALPHA) return fail(ctx, WIPES_ERR_INVALID, "bad mode");
+    if (p->mode == WIPES_2D_ADDITIVE && p->cov != WIPES_COV_CHOLESKY && p->cov != WIPES_COV_RS)
+        return fail(ctx, WIPES_ERR_INVALID, "2D mode needs cov CHOLESKY or RS");
+    if (p->mode == WIPES_3D_ALPHA && p->cov != WIPES_COV_QUAT_SCALE)
+        return fail(ctx, WIPES_ERR_INVALID, "3D mode needs cov QUAT_SCALE");
+    if (p->freq_xform != WIPES_FREQ_VECTOR) return fail(ctx, WIPES_ERR_INVALID, "only WIPES_FREQ_VECTOR is built");
+    if (!tile_ok(p->tile_w, p->tile_h)) return fail(ctx, WIPES_ERR_INVALID, "unsupported tile %dx%d", p->tile_w, p->tile_h);
+    if (!(p->alpha_min > 0.0f) || !(p->alpha_max > p->alpha_min) || !(p->alpha_max < 1.0f) || !(p->T_min > 0.0f) ||
+        !(p->q_add > 0.0f) || !(p->blur_eps >= 0.0f) || !(p->near_plane > 0.0f) || !(p->fov_guard > 0.0f))
+        return fail(ctx, WIPES_ERR_INVALID, "rasterizer constants out of range");
+    if (b->n_images < 1 || b->n_images > kMaxImages || !b->images)
+        return fail(ctx, WIPES_ERR_INVALID, "batch must hold 1..%d images", kMaxImages);
+    int64_t prims = 0, pix = 0, tiles = 0;
+    for (int i = 0; i < b->n_images; ++i) {
+        const wipes_image& im = b->images[i];
+        const wipes_prims& q = im.prims;
+        if (im.cam.width < 1 || im.cam.height < 1 || im.cam.width > 32768 || im.cam.height > 32768)
+            return fail(ctx, WIPES_ERR_INVALID, "image %d: size %dx%d out of range", i, im.cam.width, im.cam.height);
+        if (q.n < 0) return fail(ctx, WIPES_ERR_INVALID, "image %d: negative primitive count", i);
+        if (q.n > 0) {
+            if (!q.mean || !q.freq || !q.color || !q.opacity)
+                return fail(ctx, WIPES_ERR_INVALID, "image %d: mean/freq/color/opacity must be set", i);
+            if (p->mode == WIPES_2D_ADDITIVE && !q.cov) return fail(ctx, WIPES_ERR_INVALID, "image %d: cov missing", i);
+            if (p->mode == WIPES_3D_ALPHA) {
+                if (!q.quat || !q.scale) return fail(ctx, WIPES_ERR_INVALID, "image %d: quat/scale missing", i);
+                if (!(im.cam.fx > 0.0f) || !(im.cam.fy > 0.0f))
+                    return fail(ctx, WIPES_ERR_INVALID, "image %d: focal lengths must be positive", i);
+            }
+        }
+        if (need_grads) {
+            const wipes_prims_grad& g = im.grads;
+            if (g.velocity && !q.velocity)
+                return fail(ctx, WIPES_ERR_INVALID, "image %d: velocity gradient without velocity", i);
+        }
+        prims += q.n;
+        pix += (int64_t)im.cam.width * im.cam.height;
+        tiles += (int64_t)((im.cam.width + p->tile_w - 1) / p->tile_w) * ((im.cam.height + p->tile_h - 1) / p->tile_h);
+    }
+    if (prims >= (1ll << 31) || pix * 3 >= (1ll << 31) || tiles >= (1ll << 31))
+        return fail(ctx, WIPES_ERR_INVALID, "batch too large (primitives, pixels*3 and tiles must stay below 2^31)");
+    return WIPES_OK;
+}
+
+Layout layout_of(const wipes_params* p, const wipes_batch* b, int64_t cap, int with_bwd)
+{
+    Layout L{};
+    L.B = b->n_images;
+    L.alpha = p->mode == WIPES_3D_ALPHA;
+    for (int i = 0; i < b->n_images; ++i) {
+        const wipes_camera& c = b->images[i].cam;
+        L.n += b->images[i].prims.n;
+        L.pixels += (int64_t)c.width * c.height;
+        L.tiles += (int64_t)((c.width + p->tile_w - 1) / p->tile_w) * ((c.height + p->tile_h - 1) / p->tile_h);
+    }
+    L.cap = cap;
+    const int64_t n = L.n;
+    const int64_t nb_n = (n + 4095) / 4096 + 1;
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = o;
+        o = align_up(o + bytes, 256);
+        return at;
+    };
+    L.s_recs = take((size_t)n * 64);
+    L.s_aux = take((size_t)n * 16);
+    L.s_count = take((size_t)n * 4);
+    L.s_off_id = take((size_t)n * 4);
+    if (L.alpha) {
+        L.s_dkey_a = take((size_t)n * 4);
+        L.s_dval_a = take((size_t)n * 4);
+        L.s_dkey_b = take((size_t)n * 4);
+        L.s_dval_b = take((size_t)n * 4);
+        L.s_off_rank = take((size_t)n * 4);
+        L.s_dhist = take((size_t)256 * nb_n * 4);
+        L.s_ddtot = take(256 * 4);
+    }
+    L.s_bsum = take((size_t)(nb_n + 1) * 4);
+    L.s_bsum2 = take((size_t)(nb_n + 1) * 4);
+    L.s_ctrl = take(kCtrlWords * 4);
+    L.s_descs = take((size_t)L.B * sizeof(ImgDesc));
+    L.screen_bytes = o;
+
+    const int64_t nb_k = (cap + 4095) / 4096 + 1;
+    const int64_t nb_t = (L.tiles + 4095) / 4096 + 1;
+    o = 0;
+    L.b_keys_a = take((size_t)cap * 4);
+    L.b_vals_a = take((size_t)cap * 4);
+    L.b_keys_b = take((size_t)cap * 4);
+    L.b_vals_b = take((size_t)cap * 4);
+    L.b_hist = take((size_t)256 * std::max(nb_k, nb_t) * 4);
+    L.b_dtot = take(256 * 4);
+    L.b_ranges = take((size_t)L.tiles * 8);
+    L.b_order = take((size_t)L.tiles * 4 * 4);   // LPT order + sort scratch (4 arrays)
+    L.b_tbsum = take((size_t)(nb_t + 1) * 4);
+    if (with_bwd) {
+        L.b_inv = take((size_t)cap * 4);
+        L.b_slots = take((size_t)cap * 48);
+    }
+    L.bins_bytes = o;
+    L.with_bwd = with_bwd;
+    // tile sort bits and where its result lands
+    int bits = 0;
+    while (bits < 32 && (1ll << bits) < L.tiles) ++bits;
+    L.tile_bits = std::max(bits, 1);
+    L.tile_result_b = radix_passes(L.tile_bits) & 1;
+    L.depth_result_b = radix_passes(32) & 1;
+    return L;
+}
+
+void fill_descs(const wipes_params* p, const wipes_batch* b, std::vector<ImgDesc>& out)
+{
+    out.resize(b->n_images);
+    int32_t prim = 0, pix = 0, tile = 0;
+    for (int i = 0; i < b->n_images; ++i) {
+        const wipes_image& im = b->images[i];
+        ImgDesc& d = out[i];
+        memset(&d, 0, sizeof(d));
+        d.mean = im.prims.mean;
+        d.cov = im.prims.cov;
+        d.quat = im.prims.quat;
+        d.scale = im.prims.scale;
+        d.freq = im.prims.freq;
+        d.color = im.prims.color;
+        d.opac = im.prims.opacity;
+        d.vel = im.prims.velocity;
+        d.g_mean = im.grads.mean;
+        d.g_cov = im.grads.cov;
+        d.g_quat = im.grads.quat;
+        d.g_scale = im.grads.scale;
+        d.g_freq = im.grads.freq;
+        d.g_color = im.grads.color;
+        d.g_opac = im.grads.opacity;
+        d.g_vel = im.grads.velocity;
+        d.prim_begin = prim;
+        d.n = (int32_t)im.prims.n;
+        d.pix_begin = pix;
+        d.tile_begin = tile;
+        d.W = im.cam.width;
+        d.H = im.cam.height;
+        d.tiles_x = (d.W + p->tile_w - 1) / p->tile_w;
+        d.tiles_y = (d.H + p->tile_h - 1) / p->tile_h;
+        d.fx = im.cam.fx;
+        d.fy = im.cam.fy;
+        d.cx = im.cam.cx;
+        d.cy = im.cam.cy;
+        for (int k = 0; k < 12; ++k) d.view[k] = im.cam.viewmat[k];
+        d.time = im.cam.time;
+        d.limx = p->mode == WIPES_3D_ALPHA ? p->fov_guard * 0.5f * (float)d.W / im.cam.fx : 0.0f;
+        d.limy = p->mode == WIPES_3D_ALPHA ? p->fov_guard * 0.5f * (float)d.H / im.cam.fy : 0.0f;
+        prim += d.n;
+        pix += d.W * d.H;
+        tile += d.tiles_x * d.tiles_y;
+    }
+}
+
+// Copy the descriptor table into the screen buffer (stream-ordered).  Uses a
+// ring of pinned staging slots; a slot is reused only after its previous copy
+// has completed.  Skipped while a graph is being captured (the table is
+// uploaded before capture and stays valid for the graph's lifetime).
+wipes_status upload_descs(wipes_ctx* ctx, const wipes_params* p, const wipes_batch* b, const Layout& L, void* screen,
+                          hipStream_t s)
+{
+    if (ctx->capturing) return WIPES_OK;
+    std::vector<ImgDesc> h;
+    fill_descs(p, b, h);
+    const size_t bytes = h.size() * sizeof(ImgDesc);
+    StagingSlot& slot = ctx->ring[ctx->ring_next];
+    ctx->ring_next = (ctx->ring_next + 1) % kRing;
+    hipError_t e;
+    if (slot.used) {
+        e = hipEventSynchronize(slot.ev);
+        if (e != hipSuccess) return hip_fail(ctx, e, "staging event");
+    }
+    memcpy(slot.host, h.data(), bytes);
+    e = hipMemcpyAsync((char*)screen + L.s_descs, slot.host, bytes, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_fail(ctx, e, "descriptor upload");
+    e = hipEventRecord(slot.ev, s);
+    if (e != hipSuccess) return hip_fail(ctx, e, "staging event record");
+    slot.used = true;
+    return WIPES_OK;
+}
+
+}  // namespace wipes
+
+// --------------------------------------------------------------- C ABI
+
+extern "C" {
+
+void wipes_params_default(int32_t mode, wipes_params* p)
+{
+    if (!p) return;
+    memset(p, 0, sizeof(*p));
+    p->mode = mode;
+    p->cov = mode == WIPES_3D_ALPHA ? WIPES_COV_QUAT_SCALE : WIPES_COV_RS;
+    p->freq_xform = WIPES_FREQ_VECTOR;
+    p->tile_w = 16;
+    p->tile_h = 16;
+    p->persistent = 0;
+    p->alpha_min = 1.0f / 255.0f;
+    p->alpha_max = 0.99f;
+    p->T_min = 1e-4f;
+    p->q_add = 9.0f;
+    p->blur_eps = mode == WIPES_3D_ALPHA ? 0.3f : 0.0f;
+    p->near_plane = 0.01f;
+    p->fov_guard = 1.3f;
+}
+
+wipes_status wipes_ctx_create(int32_t device, wipes_ctx** out)
+{
+    if (!out) return fail(nullptr, WIPES_ERR_INVALID, "out must not be NULL");
+    *out = nullptr;
+    int ndev = 0;
+    hipError_t e = hipGetDeviceCount(&ndev);
+    if (e != hipSuccess) return hip_fail(nullptr, e, "hipGetDeviceCount");
+    if (device < 0 || device >= ndev) return fail(nullptr, WIPES_ERR_INVALID, "device %d out of range", device);
+    e = hipSetDevice(device);
+    if (e != hipSuccess) return hip_fail(nullptr, e, "hipSetDevice");
+    wipes_ctx* c = new wipes_ctx();
+    c->device = device;
+    hipDeviceProp_t prop;
+    e = hipGetDeviceProperties(&prop, device);
+    if (e != hipSuccess) {
+        delete c;
+        return hip_fail(nullptr, e, "hipGetDeviceProperties");
+    }
+    c->n_cu = prop.multiProcessorCount;
+    for (int i = 0; i < kRing; ++i) {
+        e = hipHostMalloc(&c->ring[i].host, kStagingBytes, hipHostMallocDefault);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ring[i].ev, hipEventDisableTiming);
+        if (e != hipSuccess) {
+            wipes_ctx_destroy(c);
+            return hip_fail(nullptr, e, "staging allocation");
+        }
+    }
+    *out = c;
+    return WIPES_OK;
+}
+
+void wipes_ctx_destroy(wipes_ctx* ctx)
+{
+    if (!ctx) return;
+    for (int i = 0; i < kRing; ++i) {
+        if (ctx->ring[i].ev) {
+            hipEventSynchronize(ctx->ring[i].ev);
+            hipEventDestroy(ctx->ring[i].ev);
+        }
+        if (ctx->ring[i].host) hipHostFree(ctx->ring[i].host);
+    }
+    delete ctx;
+}
+
+const char* wipes_last_error(const wipes_ctx* ctx)
+{
+    return ctx ? ctx->err.c_str() : g_err_no_ctx.c_str();
+}
+
+wipes_status wipes_workspace_size(const wipes_params* p, const wipes_batch* b, int64_t capacity_instances,
+                                  int32_t with_backward, size_t* screen_bytes, size_t* bins_bytes)
+{
+    wipes_status st = validate(nullptr, p, b, false);
+    if (st != WIPES_OK) return st;
+    if (capacity_instances < 0 || capacity_instances >= (1ll << 31))
+        return fail(nullptr, WIPES_ERR_INVALID, "capacity out of range");
+    const Layout L = layout_of(p, b, capacity_instances, with_backward);
+    if (screen_bytes) *screen_bytes = L.screen_bytes;
+    if (bins_bytes) *bins_bytes = L.bins_bytes;
+    return WIPES_OK;
+}
+
+static wipes_status check_buf(wipes_ctx* ctx, const wipes_buffer* buf, size_t need, const char* what)
+{
+    if (!buf || !buf->base) return fail(ctx, WIPES_ERR_INVALID, "%s buffer missing", what);
+    if (buf->bytes < need) return fail(ctx, WIPES_ERR_NOMEM, "%s buffer too small (%zu < %zu)", what, buf->bytes, need);
+    return WIPES_OK;
+}
+
+// Common prologue: ctx, params, batch, buffers; returns the layout for the bins capacity.
+static wipes_status prologue(wipes_ctx* ctx, const wipes_params* p, const wipes_batch* b, const wipes_buffer* screen,
+                             const wipes_buffer* bins, bool need_grads, bool need_bwd_bins, Layout* L)
+{
+    if (!ctx) return fail(nullptr, WIPES_ERR_INVALID, "ctx must not be NULL");
+    wipes_status st = validate(ctx, p, b, need_grads);
+    if (st != WIPES_OK) return st;
+    int64_t cap = 0;
+    int wb = 0;
+    if (bins) {
+        if (bins->capacity < 0 || bins->capacity >= (1ll << 31))
+            return fail(ctx, WIPES_ERR_INVALID, "bins capacity out of range");
+        cap = bins->capacity;
+        wb = bins->with_backward != 0;
+        if (need_bwd_bins && !wb) return fail(ctx, WIPES_ERR_INVALID, "bins buffer was not sized with_backward");
+    }
+    *L = layout_of(p, b, cap, wb);
+    if ((st = check_buf(ctx, screen, L->screen_bytes, "screen")) != WIPES_OK) return st;
+    if (bins && (st = check_buf(ctx, bins, L->bins_bytes, "bins")) != WIPES_OK) return st;
+    return WIPES_OK;
+}
+
+wipes_status wipes_project(wipes_ctx* ctx, const wipes_params* p, const wipes_batch* b, wipes_buffer* screen,
+                           void* stream)
+{
+    Layout L;
+    wipes_status st = prologue(ctx, p, b, screen, nullptr, false, false, &L);
+    if (st != WIPES_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    if ((st = upload_descs(ctx, p, b, L, screen->base, s)) != WIPES_OK) return st;
+    char* base = (char*)screen->base;
+    hipError_t e = launch_project((const ImgDesc*)(base + L.s_descs), L.B, (int32_t)L.n, kparams(p),
+                                  (Rec*)(base + L.s_recs), (Aux*)(base + L.s_aux), s);
+    if (e != hipSuccess) return hip_fail(ctx, e, "project");
+    return WIPES_OK;
+}
+
+wipes_status wipes_bin_sort(wipes_ctx* ctx, const wipes_params* p, const wipes_batch* b, wipes_buffer* screen,
+                            wipes_buffer* bins, int64_t* n_instances_out, void* stream)
+{
+    Layout L;
+    if (!bins) return fail(ctx, WIPES_ERR_INVALID, "bins buffer missing");
+    wipes_status st = prologue(ctx, p, b, screen, bins, false, false, &L);
+    if (st != WIPES_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    if ((st = upload_descs(ctx, p, b, L, screen->base, s)) != WIPES_OK) return st;
+    return bin_sort_core(ctx, p, b, L, screen->base, bins->base, n_instances_out, s);
+}
+
+wipes_status wipes_render_fwd(wipes_ctx* ctx, const wipes_params* p, const wipes_batch* b, const wipes_buffer* screen,
+                              const wipes_buffer* bins, float* image, float* T_final, int32_t* last, void* stream)
+{
+    Layout L;
+    if (!bins) return fail(ctx, WIPES_ERR_INVALID, "bins buffer missing");
+    wipes_status st = prologue(ctx, p, b, screen, bins, false, false, &L);
+    if (st != WIPES_OK) return st;
+    if (!image) return fail(ctx, WIPES_ERR_INVALID, "image must not be NULL");
+    if (p->mode == WIPES_3D_ALPHA && (!T_final || !last))
+        return fail(ctx, WIPES_ERR_INVALID, "alpha mode needs T_final and last");
+    hipStream_t s = (hipStream_t)stream;
+    if ((st = upload_descs(ctx, p, b, L, screen->base, s)) != WIPES_OK) return st;
+    return render_fwd_core(ctx, p, b, L, screen->base, bins->base, image, T_final, last, s);
+}
+
+wipes_status wipes_render_bwd(wipes_ctx* ctx, const wipes_params* p, const wipes_batch* b, const wipes_buffer* screen,
+                              const wipes_buffer* bins, const float* T_final, const int32_t* last,
+                              const float* dL_dimage, float* dscreen, void* stream)
+{
+    Layout L;
+    if (!bins) return fail(ctx, WIPES_ERR_INVALID, "bins buffer missing");
+    wipes_status st = prologue(ctx, p, b, screen, bins, true, true, &L);
+    if (st != WIPES_OK) return st;
+    if (!dL_dimage) return fail(ctx, WIPES_ERR_INVALID, "dL_dimage must not be NULL");
+    if (p->mode == WIPES_3D_ALPHA && (!T_final || !last))
+        return fail(ctx, WIPES_ERR_INVALID, "alpha mode needs T_final and last");
+    hipStream_t s = (hipStream_t)stream;
+    if ((st = upload_descs(ctx, p, b, L, screen->base, s)) != WIPES_OK) return st;
+    return render_bwd_core(ctx, p, b, L, screen->base, bins->base, T_final, last, dL_dimage, dscreen, s);
+}
+
+wipes_status wipes_check_overflow(wipes_ctx* ctx, const wipes_params* p, const wipes_batch* b,
+                                  const wipes_buffer* screen, int64_t* required_instances, void* stream)
+{
+    Layout L;
+    wipes_status st = prologue(ctx, p, b, screen, nullptr, false, false, &L);
+    if (st != WIPES_OK) return st;
+    if (!required_instances) return fail(ctx, WIPES_ERR_INVALID, "required_instances must not be NULL");
+    uint32_t ctrl[kCtrlWords];
+    hipError_t e = hipMemcpyAsync(ctrl, (char*)screen->base + L.s_ctrl, sizeof(ctrl), hipMemcpyDeviceToHost,
+                                  (hipStream_t)stream);
+    if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "check_overflow");
+    *required_instances = ctrl[kCtrlK];
+    return ctrl[kCtrlOverflow] ? WIPES_ERR_CAPACITY : WIPES_OK;
+}
+
+wipes_status wipes_bins_view(const wipes_params* p, const wipes_batch* b, const wipes_buffer* screen,
+                             const wipes_buffer* bins, const uint32_t** keys, const uint32_t** vals,
+                             const uint32_t** ranges, int64_t* n_tiles)
+{
+    Layout L;
+    wipes_ctx tmp;
+    wipes_status st = prologue(&tmp, p, b, screen, bins, false, false, &L);
+    if (!bins) return fail(nullptr, WIPES_ERR_INVALID, "bins buffer missing");
+    if (st != WIPES_OK) return fail(nullptr, st, "%s", tmp.err.c_str());
+    const char* base = (const char*)bins->base;
+    if (keys) *keys = (const uint32_t*)(base + (L.tile_result_b ? L.b_keys_b : L.b_keys_a));
+    if (vals) *vals = (const uint32_t*)(base + (L.tile_result_b ? L.b_vals_b : L.b_vals_a));
+    if (ranges) *ranges = (const uint32_t*)(base + L.b_ranges);
+    if (n_tiles) *n_tiles = L.tiles;
+    return WIPES_OK;
+}
+
+}  // extern "C"

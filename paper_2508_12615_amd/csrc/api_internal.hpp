@@ -1,0 +1,106 @@
+// Host-side internals of the C ABI: workspace layout, context, stage
+// sequencing and the launchers each kernel file provides.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <string>
+#include <vector>
+
+#include "common.hpp"
+
+constexpr int kMaxImages = 1024;
+constexpr int kRing = 8;
+constexpr size_t kStagingBytes = (size_t)kMaxImages * sizeof(wipes::ImgDesc);
+
+// device control words at Layout::s_ctrl
+enum { kCtrlK = 0, kCtrlNEff = 1, kCtrlOverflow = 2, kCtrlQueueFwd = 4, kCtrlQueueBwd = 5, kCtrlWords = 16 };
+
+struct StagingSlot {
+    void* host = nullptr;
+    hipEvent_t ev = nullptr;
+    bool used = false;
+};
+
+struct wipes_ctx {
+    int device = 0;
+    int n_cu = 256;
+    std::string err;
+    StagingSlot ring[kRing];
+    int ring_next = 0;
+    bool capturing = false;      // descriptor uploads are skipped while capturing a graph
+};
+
+namespace wipes {
+
+// Byte offsets of every array in the screen and bins buffers.
+struct Layout {
+    int B = 0;
+    bool alpha = false;
+    int with_bwd = 0;
+    int64_t n = 0, pixels = 0, tiles = 0, cap = 0;
+    // screen buffer
+    size_t s_recs, s_aux, s_count, s_off_id, s_dkey_a, s_dval_a, s_dkey_b, s_dval_b, s_off_rank, s_dhist, s_ddtot;
+    size_t s_bsum, s_bsum2, s_ctrl, s_descs, screen_bytes;
+    // bins buffer
+    size_t b_keys_a, b_vals_a, b_keys_b, b_vals_b, b_hist, b_dtot, b_ranges, b_order, b_tbsum, b_inv, b_slots;
+    size_t bins_bytes;
+    int tile_bits = 1;
+    int tile_result_b = 0;    // tile sort result in the *_b arrays
+    int depth_result_b = 0;   // depth sort result in the *_b arrays
+};
+
+wipes_status fail(wipes_ctx* ctx, wipes_status st, const char* fmt, ...);
+wipes_status hip_fail(wipes_ctx* ctx, hipError_t e, const char* where);
+wipes_status validate(wipes_ctx* ctx, const wipes_params* p, const wipes_batch* b, bool need_grads);
+bool tile_ok(int tw, int th);
+KParams kparams(const wipes_params* p);
+Layout layout_of(const wipes_params* p, const wipes_batch* b, int64_t cap, int with_bwd);
+void fill_descs(const wipes_params* p, const wipes_batch* b, std::vector<ImgDesc>& out);
+wipes_status upload_descs(wipes_ctx* ctx, const wipes_params* p, const wipes_batch* b, const Layout& L, void* screen,
+                          hipStream_t s);
+
+// stage sequencing (pipeline.hip)
+wipes_status bin_sort_core(wipes_ctx* ctx, const wipes_params* p, const wipes_batch* b, const Layout& L,
+                           void* screen, void* bins, int64_t* n_instances_out, hipStream_t s);
+wipes_status render_fwd_core(wipes_ctx* ctx, const wipes_params* p, const wipes_batch* b, const Layout& L,
+                             const void* screen, const void* bins, float* image, float* T_final, int32_t* last,
+                             hipStream_t s);
+wipes_status render_bwd_core(wipes_ctx* ctx, const wipes_params* p, const wipes_batch* b, const Layout& L,
+                             const void* screen, const void* bins, const float* T_final, const int32_t* last,
+                             const float* dLdC, float* dscreen, hipStream_t s);
+
+// kernel launchers
+hipError_t launch_project(const ImgDesc* descs, int B, int32_t n_total, const KParams& kp, Rec* recs, Aux* aux,
+                          hipStream_t s);
+hipError_t launch_bin_count(const ImgDesc* descs, int B, int32_t n_total, const KParams& kp, Rec* recs,
+                            const void* aux, uint32_t* count, uint32_t* dkey, uint32_t* dval, hipStream_t s);
+hipError_t launch_emit(const ImgDesc* descs, int B, int32_t n_total, const KParams& kp, const Rec* recs,
+                       const uint32_t* count, const uint32_t* order, const uint32_t* offs, const uint32_t* n_eff,
+                       uint32_t* keys, uint32_t* vals, hipStream_t s);
+hipError_t launch_fill_u32(uint32_t* p, uint32_t n, uint32_t v, hipStream_t s);
+hipError_t launch_ranges(const ImgDesc* descs, int B, const KParams& kp, const uint32_t* keys, const uint32_t* vals,
+                         const uint32_t* n_eff, uint32_t max_k, const Rec* recs, const uint32_t* off_id,
+                         uint2* ranges, uint32_t* inv, hipStream_t s);
+uint32_t scan_blocks(uint32_t max_n);
+hipError_t scan_excl(const uint32_t* vals, const uint32_t* gather, uint32_t n_host, const uint32_t* n_dev,
+                     uint32_t max_n, uint32_t* block_sums, uint32_t* out, uint32_t* total, uint32_t cap,
+                     uint32_t* n_eff, uint32_t* overflow, hipStream_t s);
+int radix_passes(int nbits);
+hipError_t radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, uint32_t n_host,
+                      const uint32_t* n_dev, uint32_t max_n, int nbits, uint32_t* hist, uint32_t* dtot,
+                      int* result_in_1, hipStream_t s);
+hipError_t launch_blend_fwd(const ImgDesc* descs, int B, const KParams& kp, const Rec* recs, const uint32_t* vals,
+                            const uint2* ranges, const uint32_t* ovf, uint32_t n_tiles, const uint32_t* order,
+                            uint32_t* queue, uint32_t persistent_blocks, float* image, float* T_final, int32_t* last,
+                            hipStream_t s);
+hipError_t launch_blend_bwd(const ImgDesc* descs, int B, const KParams& kp, const Rec* recs, const uint32_t* vals,
+                            const uint2* ranges, const uint32_t* ovf, uint32_t n_tiles, const uint32_t* order,
+                            uint32_t* queue, uint32_t persistent_blocks, const float* T_final, const int32_t* last,
+                            const float* dLdC, float* slots, hipStream_t s);
+hipError_t launch_project_bwd(const ImgDesc* descs, int B, int32_t n_total, const KParams& kp, const Rec* recs,
+                              const uint32_t* count, const uint32_t* off_id, const uint32_t* inv, const float* slots,
+                              const uint32_t* overflow, float* dscreen, hipStream_t s);
+
+}  // namespace wipes

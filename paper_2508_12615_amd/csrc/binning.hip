@@ -1,0 +1,164 @@
+// Tile binning: pixel boxes, per-primitive tile counts, instance emission,
+// per-tile ranges and the instance -> sorted-position map used by the backward.
+//
+// The binning rule (a reading of the 3DGS-style pipeline the paper follows,
+// Sec. 4.1), in FP32 with exactly these operations so that it is reproducible:
+//   x0 = max(ceil((mx - rx) - 1/2), 0), x1 = min(floor((mx + rx) - 1/2), W - 1)
+//   (same for y); empty unless x0 <= x1 and y0 <= y1; tile rect = box / tile size.
+// (mx, rx) are the FP32 record mean and padded support half-extent, so the box
+// holds every pixel whose centre can pass the per-pixel test.
+//
+// Emission order defines the order of equal keys after the stable sort:
+//   additive: primitive index order, key = global tile;
+//   alpha:    ascending (depth key, index) order (primitives pre-sorted by
+//             depth), key = global tile.  The stable tile sort then leaves
+//             every tile's list in (depth key, index) order -- the same list a
+//             single sort on (tile << 32 | depth bits) would give.
+#include "common.hpp"
+
+namespace wipes {
+
+constexpr uint32_t kEmptyBox0 = 0x0000ffffu;   // x0 = 65535 > x1 = 0
+constexpr uint32_t kEmptyBox1 = 0u;
+
+// count[i] = tiles touched; writes the pixel box into the record.  Alpha mode
+// also emits (depth key, index) pairs for the depth sort, with culled or
+// off-screen primitives keyed to the end.
+__global__ void __launch_bounds__(256) k_bin_count(const ImgDesc* __restrict__ descs, int B, int32_t n_total,
+                                                    KParams kp, Rec* __restrict__ recs,
+                                                    const Aux* __restrict__ aux, uint32_t* __restrict__ count,
+                                                    uint32_t* __restrict__ dkey, uint32_t* __restrict__ dval)
+{
+    const int32_t i = (int32_t)(blockIdx.x * 256u + threadIdx.x);
+    if (i >= n_total) return;
+    const ImgDesc& d = descs[image_of_prim(descs, B, i)];
+    const Aux a = aux[i];
+    const float mx = recs[i].mx, my = recs[i].my;
+    uint32_t c = 0, b0 = kEmptyBox0, b1 = kEmptyBox1;
+    if (a.rx >= 0.0f && a.ry >= 0.0f && fabsf(mx) < 1e30f && fabsf(my) < 1e30f) {
+        float x0 = ceilf((mx - a.rx) - 0.5f), x1 = floorf((mx + a.rx) - 0.5f);
+        float y0 = ceilf((my - a.ry) - 0.5f), y1 = floorf((my + a.ry) - 0.5f);
+        x0 = fmaxf(x0, 0.0f);
+        y0 = fmaxf(y0, 0.0f);
+        x1 = fminf(x1, (float)(d.W - 1));
+        y1 = fminf(y1, (float)(d.H - 1));
+        if (x0 <= x1 && y0 <= y1) {
+            const int32_t ix0 = (int32_t)x0, iy0 = (int32_t)y0, ix1 = (int32_t)x1, iy1 = (int32_t)y1;
+            b0 = pack16(ix0, iy0);
+            b1 = pack16(ix1, iy1);
+            c = (uint32_t)(((ix1 >> kp.log2_tw) - (ix0 >> kp.log2_tw) + 1) *
+                           ((iy1 >> kp.log2_th) - (iy0 >> kp.log2_th) + 1));
+        }
+    }
+    recs[i].box0 = b0;
+    recs[i].box1 = b1;
+    count[i] = c;
+    if (dkey) {
+        dkey[i] = c ? __float_as_uint(a.depth) : 0xffffffffu;
+        dval[i] = (uint32_t)i;
+    }
+}
+
+// One thread per primitive in emission order (order == NULL: index order).
+// Writes that primitive's instances at offs[r], tiles row-major.
+__global__ void __launch_bounds__(256) k_emit(const ImgDesc* __restrict__ descs, int B, int32_t n_total,
+                                               KParams kp, const Rec* __restrict__ recs,
+                                               const uint32_t* __restrict__ count,
+                                               const uint32_t* __restrict__ order,
+                                               const uint32_t* __restrict__ offs,
+                                               const uint32_t* __restrict__ n_eff, uint32_t* __restrict__ keys,
+                                               uint32_t* __restrict__ vals)
+{
+    const int32_t r = (int32_t)(blockIdx.x * 256u + threadIdx.x);
+    if (r >= n_total || *n_eff == 0u) return;
+    const uint32_t prim = order ? order[r] : (uint32_t)r;
+    const uint32_t c = count[prim];
+    if (c == 0) return;
+    const ImgDesc& d = descs[image_of_prim(descs, B, (int32_t)prim)];
+    const uint32_t b0 = recs[prim].box0, b1 = recs[prim].box1;
+    const int32_t tx0 = lo16(b0) >> kp.log2_tw, ty0 = hi16(b0) >> kp.log2_th;
+    const int32_t tx1 = lo16(b1) >> kp.log2_tw, ty1 = hi16(b1) >> kp.log2_th;
+    uint32_t k = offs[r];
+    for (int32_t ty = ty0; ty <= ty1; ++ty) {
+        const uint32_t row = (uint32_t)(d.tile_begin + ty * d.tiles_x);
+        for (int32_t tx = tx0; tx <= tx1; ++tx, ++k) {
+            keys[k] = row + (uint32_t)tx;
+            vals[k] = prim;
+        }
+    }
+}
+
+// ranges[t] = [first, last + 1) of tile t in the sorted keys (pre-zeroed).
+// With inv != NULL also inv[off_id[prim] + local tile index] = sorted position.
+__global__ void __launch_bounds__(256) k_ranges(const ImgDesc* __restrict__ descs, int B, KParams kp,
+                                                 const uint32_t* __restrict__ keys,
+                                                 const uint32_t* __restrict__ vals,
+                                                 const uint32_t* __restrict__ n_eff, const Rec* __restrict__ recs,
+                                                 const uint32_t* __restrict__ off_id, uint2* __restrict__ ranges,
+                                                 uint32_t* __restrict__ inv)
+{
+    const uint32_t s = blockIdx.x * 256u + threadIdx.x;
+    const uint32_t K = *n_eff;
+    if (s >= K) return;
+    const uint32_t t = keys[s];
+    if (s == 0 || keys[s - 1] != t) ranges[t].x = s;
+    if (s == K - 1 || keys[s + 1] != t) ranges[t].y = s + 1;
+    if (inv) {
+        const uint32_t prim = vals[s];
+        const ImgDesc& d = descs[image_of_tile(descs, B, (int32_t)t)];
+        const int32_t lt = (int32_t)t - d.tile_begin;
+        const int32_t ty = lt / d.tiles_x, tx = lt - ty * d.tiles_x;
+        const uint32_t b0 = recs[prim].box0, b1 = recs[prim].box1;
+        const int32_t tx0 = lo16(b0) >> kp.log2_tw, ty0 = hi16(b0) >> kp.log2_th;
+        const int32_t tx1 = lo16(b1) >> kp.log2_tw;
+        inv[off_id[prim] + (uint32_t)((ty - ty0) * (tx1 - tx0 + 1) + (tx - tx0))] = s;
+    }
+}
+
+// Fill kernel (used instead of memset so the sequence can live in a graph).
+__global__ void __launch_bounds__(256) k_fill_u32(uint32_t* __restrict__ p, uint32_t n, uint32_t v)
+{
+    const uint32_t i = blockIdx.x * 256u + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// ------------------------------------------------------------- host side
+
+static inline uint32_t blocks_of(uint32_t n) { return (n + 255u) / 256u; }
+
+hipError_t launch_bin_count(const ImgDesc* descs, int B, int32_t n_total, const KParams& kp, Rec* recs,
+                            const void* aux, uint32_t* count, uint32_t* dkey, uint32_t* dval, hipStream_t s)
+{
+    if (n_total > 0)
+        hipLaunchKernelGGL(k_bin_count, dim3(blocks_of((uint32_t)n_total)), dim3(256), 0, s, descs, B, n_total, kp,
+                           recs, (const Aux*)aux, count, dkey, dval);
+    return hipGetLastError();
+}
+
+hipError_t launch_emit(const ImgDesc* descs, int B, int32_t n_total, const KParams& kp, const Rec* recs,
+                       const uint32_t* count, const uint32_t* order, const uint32_t* offs, const uint32_t* n_eff,
+                       uint32_t* keys, uint32_t* vals, hipStream_t s)
+{
+    if (n_total > 0)
+        hipLaunchKernelGGL(k_emit, dim3(blocks_of((uint32_t)n_total)), dim3(256), 0, s, descs, B, n_total, kp, recs,
+                           count, order, offs, n_eff, keys, vals);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u32(uint32_t* p, uint32_t n, uint32_t v, hipStream_t s)
+{
+    if (n > 0) hipLaunchKernelGGL(k_fill_u32, dim3(blocks_of(n)), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_ranges(const ImgDesc* descs, int B, const KParams& kp, const uint32_t* keys, const uint32_t* vals,
+                         const uint32_t* n_eff, uint32_t max_k, const Rec* recs, const uint32_t* off_id,
+                         uint2* ranges, uint32_t* inv, hipStream_t s)
+{
+    if (max_k > 0)
+        hipLaunchKernelGGL(k_ranges, dim3(blocks_of(max_k)), dim3(256), 0, s, descs, B, kp, keys, vals, n_eff, recs,
+                           off_id, ranges, inv);
+    return hipGetLastError();
+}
+
+}  // namespace wipes

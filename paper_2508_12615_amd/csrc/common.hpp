@@ -1,0 +1,134 @@
+// Device-side definitions shared by the gfx950 kernels of the wavelet rasterizer.
+//
+// Layout decisions (MI355X / CDNA4):
+//  * one 64-byte screen record per primitive, so a wave fetches a whole
+//    record with wave-uniform (scalar) loads while blending;
+//  * per-image descriptors in device memory, so a single launch covers a
+//    batch of images of different sizes;
+//  * all integer index arithmetic in 32 bits (instances, tiles, pixels of one
+//    launch stay below 2^31; the host checks).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/wipes.h"
+
+namespace wipes {
+
+constexpr int kWave = 64;
+constexpr float kLog2e = 1.4426950408889634f;
+constexpr float kInv2Pi = 0.15915494309189535f;
+
+// Screen record (mirrors wipes_screen_record).  The mean is mx + mxl in
+// exact arithmetic (mx = FP32 rounding, mxl = FP32 rounding of the rest).
+struct __align__(64) Rec {
+    float mx, my, ca, cb, cc, fx, fy, op, r, g, b, mxl, myl, reserved;
+    uint32_t box0, box1;
+};
+static_assert(sizeof(Rec) == 64, "screen record must be 64 bytes");
+
+// Per-primitive inputs of the binning stage, written by the projection.
+struct Aux {
+    float rx, ry;   // padded support half-extents (pixels); rx < 0 marks a culled primitive
+    float depth;    // FP32 depth key (alpha mode)
+    float pad;
+};
+
+// Per-image descriptor, uploaded once per call into the screen buffer.
+struct __align__(16) ImgDesc {
+    const float* mean;
+    const float* cov;
+    const float* quat;
+    const float* scale;
+    const float* freq;
+    const float* color;
+    const float* opac;
+    const float* vel;
+    float* g_mean;
+    float* g_cov;
+    float* g_quat;
+    float* g_scale;
+    float* g_freq;
+    float* g_color;
+    float* g_opac;
+    float* g_vel;
+    int32_t prim_begin;   // first global record index of this image
+    int32_t n;            // primitives of this image
+    int32_t pix_begin;    // first pixel of this image in the per-pixel arrays
+    int32_t tile_begin;   // first global tile of this image
+    int32_t W, H, tiles_x, tiles_y;
+    float fx, fy, cx, cy;
+    float view[12];       // rows 0..2 of the world->camera matrix
+    float time;
+    float limx, limy;     // guard band of x/z and y/z
+    int32_t pad_;
+};
+
+// Rasterizer constants as the kernels see them.
+struct KParams {
+    int32_t mode, cov, tile_w, tile_h, log2_tw, log2_th;
+    float alpha_min, alpha_max, T_min, q_add, blur_eps, near_plane;
+    float bg[3];
+};
+
+// Index of the image owning global element `i` given ascending begin offsets.
+// B is small (<= a few hundred); the search is wave-uniform in practice.
+template <typename GetBegin>
+__device__ __forceinline__ int find_owner(int B, int32_t i, GetBegin begin)
+{
+    int lo = 0, hi = B - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (begin(mid) <= i) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ int image_of_prim(const ImgDesc* __restrict__ d, int B, int32_t i)
+{
+    return find_owner(B, i, [&](int b) { return d[b].prim_begin; });
+}
+
+__device__ __forceinline__ int image_of_tile(const ImgDesc* __restrict__ d, int B, int32_t t)
+{
+    return find_owner(B, t, [&](int b) { return d[b].tile_begin; });
+}
+
+__device__ __forceinline__ uint32_t pack16(int32_t a, int32_t b)
+{
+    return (uint32_t)(a & 0xffff) | ((uint32_t)(b & 0xffff) << 16);
+}
+
+__device__ __forceinline__ int32_t lo16(uint32_t v) { return (int32_t)(v & 0xffffu); }
+__device__ __forceinline__ int32_t hi16(uint32_t v) { return (int32_t)(v >> 16); }
+
+__device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
+
+// Wave-wide sum, max (results in every lane).
+__device__ __forceinline__ int32_t wave_max_i32(int32_t v)
+{
+    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, kWave));
+    return v;
+}
+
+__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v)
+{
+    for (int o = 32; o > 0; o >>= 1) v += (uint32_t)__shfl_xor((int)v, o, kWave);
+    return v;
+}
+
+// Exclusive prefix sum within the wave; returns the wave total in *total.
+__device__ __forceinline__ uint32_t wave_excl_scan_u32(uint32_t v, uint32_t* total)
+{
+    const int l = lane_id();
+    uint32_t x = v;
+    for (int o = 1; o < kWave; o <<= 1) {
+        uint32_t y = (uint32_t)__shfl_up((int)x, o, kWave);
+        if (l >= o) x += y;
+    }
+    *total = (uint32_t)__shfl((int)x, kWave - 1, kWave);
+    return x - v;
+}
+
+}  // namespace wipes

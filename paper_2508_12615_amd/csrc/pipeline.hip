@@ -1,0 +1,166 @@
+// Stage sequencing of the render path: bin/sort, forward blend, backward.
+//
+// bin_sort (one stream, no allocation):
+//   count  -> scan (index order, capacity check)   -> [alpha: depth sort of all
+//   primitives by FP32 key, then scan in depth order] -> emit -> tile sort ->
+//   ranges (+ instance -> sorted-position map for the backward).
+// The tile sort's key is the global tile index only; depth order comes from
+// emitting instances in depth order into a stable sort (see binning.hip), so
+// the 45-bit (tile, depth) sort of the 3DGS pipeline becomes a 32-bit sort over
+// primitives plus a ceil(log2 tiles)-bit sort over instances.
+#include <hip/hip_runtime.h>
+
+#include "api_internal.hpp"
+
+namespace wipes {
+
+struct Views {
+    Rec* recs;
+    Aux* aux;
+    uint32_t *count, *off_id, *dkey_a, *dval_a, *dkey_b, *dval_b, *off_rank, *dhist, *ddtot, *bsum, *bsum2, *ctrl;
+    ImgDesc* descs;
+    uint32_t *keys_a, *vals_a, *keys_b, *vals_b, *hist, *dtot, *order, *tbsum, *inv;
+    uint2* ranges;
+    float* slots;
+};
+
+static Views views(const Layout& L, const void* screen, const void* bins)
+{
+    char* s = (char*)screen;
+    char* b = (char*)bins;
+    Views v{};
+    v.recs = (Rec*)(s + L.s_recs);
+    v.aux = (Aux*)(s + L.s_aux);
+    v.count = (uint32_t*)(s + L.s_count);
+    v.off_id = (uint32_t*)(s + L.s_off_id);
+    if (L.alpha) {
+        v.dkey_a = (uint32_t*)(s + L.s_dkey_a);
+        v.dval_a = (uint32_t*)(s + L.s_dval_a);
+        v.dkey_b = (uint32_t*)(s + L.s_dkey_b);
+        v.dval_b = (uint32_t*)(s + L.s_dval_b);
+        v.off_rank = (uint32_t*)(s + L.s_off_rank);
+        v.dhist = (uint32_t*)(s + L.s_dhist);
+        v.ddtot = (uint32_t*)(s + L.s_ddtot);
+    }
+    v.bsum = (uint32_t*)(s + L.s_bsum);
+    v.bsum2 = (uint32_t*)(s + L.s_bsum2);
+    v.ctrl = (uint32_t*)(s + L.s_ctrl);
+    v.descs = (ImgDesc*)(s + L.s_descs);
+    if (b) {
+        v.keys_a = (uint32_t*)(b + L.b_keys_a);
+        v.vals_a = (uint32_t*)(b + L.b_vals_a);
+        v.keys_b = (uint32_t*)(b + L.b_keys_b);
+        v.vals_b = (uint32_t*)(b + L.b_vals_b);
+        v.hist = (uint32_t*)(b + L.b_hist);
+        v.dtot = (uint32_t*)(b + L.b_dtot);
+        v.ranges = (uint2*)(b + L.b_ranges);
+        v.order = (uint32_t*)(b + L.b_order);
+        v.tbsum = (uint32_t*)(b + L.b_tbsum);
+        if (L.with_bwd) {
+            v.inv = (uint32_t*)(b + L.b_inv);
+            v.slots = (float*)(b + L.b_slots);
+        }
+    }
+    return v;
+}
+
+#define HIP_TRY(call, what)                                    \
+    do {                                                       \
+        hipError_t e_ = (call);                                \
+        if (e_ != hipSuccess) return hip_fail(ctx, e_, what);  \
+    } while (0)
+
+wipes_status bin_sort_core(wipes_ctx* ctx, const wipes_params* p, const wipes_batch* b, const Layout& L,
+                           void* screen, void* bins, int64_t* n_instances_out, hipStream_t s)
+{
+    (void)b;
+    const Views v = views(L, screen, bins);
+    const KParams kp = kparams(p);
+    const uint32_t n = (uint32_t)L.n;
+    HIP_TRY(launch_bin_count(v.descs, L.B, (int32_t)n, kp, v.recs, v.aux, v.count, v.dkey_a, v.dval_a, s), "count");
+    // K, capacity check -> n_eff, overflow flag
+    HIP_TRY(scan_excl(v.count, nullptr, n, nullptr, n, v.bsum, v.off_id, v.ctrl + kCtrlK, (uint32_t)L.cap,
+                      v.ctrl + kCtrlNEff, v.ctrl + kCtrlOverflow, s),
+            "scan");
+    const uint32_t* order = nullptr;
+    const uint32_t* offs = v.off_id;
+    if (L.alpha) {
+        int in_b = 0;
+        HIP_TRY(radix_sort(v.dkey_a, v.dval_a, v.dkey_b, v.dval_b, n, nullptr, n, 32, v.dhist, v.ddtot, &in_b, s),
+                "depth sort");
+        order = in_b ? v.dval_b : v.dval_a;
+        HIP_TRY(scan_excl(v.count, order, n, nullptr, n, v.bsum2, v.off_rank, v.ctrl + 3, 0, nullptr, nullptr, s),
+                "rank scan");
+        offs = v.off_rank;
+    }
+    uint32_t max_k = (uint32_t)L.cap;
+    if (n_instances_out) {
+        uint32_t K = 0;
+        HIP_TRY(hipMemcpyAsync(&K, v.ctrl + kCtrlK, 4, hipMemcpyDeviceToHost, s), "read K");
+        HIP_TRY(hipStreamSynchronize(s), "sync K");
+        *n_instances_out = K;
+        if ((int64_t)K > L.cap) return fail(ctx, WIPES_ERR_CAPACITY, "%u instances exceed capacity %lld", K, (long long)L.cap);
+        max_k = K;
+    }
+    HIP_TRY(launch_emit(v.descs, L.B, (int32_t)n, kp, v.recs, v.count, order, offs, v.ctrl + kCtrlNEff, v.keys_a,
+                        v.vals_a, s),
+            "emit");
+    int in_b = 0;
+    HIP_TRY(radix_sort(v.keys_a, v.vals_a, v.keys_b, v.vals_b, 0, v.ctrl + kCtrlNEff, max_k, L.tile_bits, v.hist,
+                       v.dtot, &in_b, s),
+            "tile sort");
+    const uint32_t* skeys = in_b ? v.keys_b : v.keys_a;
+    const uint32_t* svals = in_b ? v.vals_b : v.vals_a;
+    HIP_TRY(launch_fill_u32((uint32_t*)v.ranges, (uint32_t)(2 * L.tiles), 0u, s), "ranges fill");
+    HIP_TRY(launch_ranges(v.descs, L.B, kp, skeys, svals, v.ctrl + kCtrlNEff, max_k, v.recs, v.off_id, v.ranges,
+                          L.with_bwd ? v.inv : nullptr, s),
+            "ranges");
+    return WIPES_OK;
+}
+
+wipes_status render_fwd_core(wipes_ctx* ctx, const wipes_params* p, const wipes_batch* b, const Layout& L,
+                             const void* screen, const void* bins, float* image, float* T_final, int32_t* last,
+                             hipStream_t s)
+{
+    (void)b;
+    const Views v = views(L, screen, bins);
+    const KParams kp = kparams(p);
+    const uint32_t* svals = L.tile_result_b ? v.vals_b : v.vals_a;
+    uint32_t* queue = nullptr;
+    uint32_t pblocks = 0;
+    if (p->persistent) {
+        queue = v.ctrl + kCtrlQueueFwd;
+        HIP_TRY(launch_fill_u32(queue, 1, 0u, s), "queue reset");
+        pblocks = (uint32_t)ctx->n_cu * 8u;
+    }
+    HIP_TRY(launch_blend_fwd(v.descs, L.B, kp, v.recs, svals, v.ranges, v.ctrl + kCtrlOverflow, (uint32_t)L.tiles,
+                             nullptr, queue, pblocks, image, T_final, last, s),
+            "blend fwd");
+    return WIPES_OK;
+}
+
+wipes_status render_bwd_core(wipes_ctx* ctx, const wipes_params* p, const wipes_batch* b, const Layout& L,
+                             const void* screen, const void* bins, const float* T_final, const int32_t* last,
+                             const float* dLdC, float* dscreen, hipStream_t s)
+{
+    (void)b;
+    const Views v = views(L, screen, bins);
+    const KParams kp = kparams(p);
+    const uint32_t* svals = L.tile_result_b ? v.vals_b : v.vals_a;
+    uint32_t* queue = nullptr;
+    uint32_t pblocks = 0;
+    if (p->persistent) {
+        queue = v.ctrl + kCtrlQueueBwd;
+        HIP_TRY(launch_fill_u32(queue, 1, 0u, s), "queue reset");
+        pblocks = (uint32_t)ctx->n_cu * 8u;
+    }
+    HIP_TRY(launch_blend_bwd(v.descs, L.B, kp, v.recs, svals, v.ranges, v.ctrl + kCtrlOverflow, (uint32_t)L.tiles,
+                             nullptr, queue, pblocks, T_final, last, dLdC, v.slots, s),
+            "blend bwd");
+    HIP_TRY(launch_project_bwd(v.descs, L.B, (int32_t)L.n, kp, v.recs, v.count, v.off_id, v.inv, v.slots,
+                               v.ctrl + kCtrlOverflow, dscreen, s),
+            "project bwd");
+    return WIPES_OK;
+}
+
+}  // namespace wipes

@@ -1,0 +1,186 @@
+// Projection of 2D and 3D wavelet primitives to 64-byte screen records.
+//
+// 2D (Sec. 5.1, Eq. 4 with W'): the primitive lives on the image plane, so
+// mu' = mu and f' = f; Sigma comes from a Cholesky factor or a rotation and
+// two scales.  3D (Sec. 3.1 Eq. 2, Sec. 4.1 Eq. 7): EWA splatting,
+// Sigma' = M Sigma M^T + eps I with M = J W (J the local affine Jacobian of
+// the perspective map, W the camera rotation), and the frequency goes
+// through the same map, f' = M f.
+//
+// One thread per primitive.  The arithmetic runs in FP64 (about a hundred
+// flops per primitive, invisible next to the record traffic) because the
+// records feed a carrier of up to half a cycle per pixel: an FP32 mean at
+// x ~ 1000 px is off by up to 3e-5 px, i.e. ~1e-4 rad of phase.  The mean is
+// stored as an FP32 pair (hi, lo) so the blend can rebuild it exactly.
+// The depth key is the one exception: it is defined as an FP32 evaluation
+// (fused multiply-adds in a fixed order) so that the compositing order is
+// reproducible bit for bit.
+#include "common.hpp"
+
+namespace wipes {
+
+__device__ __forceinline__ void store_record(Rec* __restrict__ recs, int32_t i, double mx, double my, double ca,
+                                             double cb, double cc, float fx, float fy, float op, float r, float g,
+                                             float b)
+{
+    float mxh = (float)mx, myh = (float)my;
+    float mxl = (float)(mx - (double)mxh), myl = (float)(my - (double)myh);
+    float4* o = reinterpret_cast<float4*>(recs + i);
+    o[0] = make_float4(mxh, myh, (float)ca, (float)cb);
+    o[1] = make_float4((float)cc, fx, fy, op);
+    o[2] = make_float4(r, g, b, mxl);
+    o[3] = make_float4(myl, 0.0f, 0.0f, 0.0f);
+}
+
+__device__ __forceinline__ void store_culled(Rec* __restrict__ recs, Aux* __restrict__ aux, int32_t i, float depth)
+{
+    float4* o = reinterpret_cast<float4*>(recs + i);
+    const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
+    o[0] = z; o[1] = z; o[2] = z; o[3] = z;
+    aux[i] = Aux{-1.0f, -1.0f, depth, 0.0f};
+}
+
+// Half-extents of the support box q <= Q of Sigma', padded so that the FP32
+// per-pixel test can never accept a pixel outside it.
+__device__ __forceinline__ void support_box(double sxx, double syy, double Q, float* rx, float* ry)
+{
+    *rx = (float)(sqrt(Q * sxx) * 1.0001 + 1e-3);
+    *ry = (float)(sqrt(Q * syy) * 1.0001 + 1e-3);
+}
+
+__global__ void __launch_bounds__(256) k_project_2d(const ImgDesc* __restrict__ descs, int B, int32_t n_total,
+                                                     KParams kp, Rec* __restrict__ recs, Aux* __restrict__ aux)
+{
+    const int32_t i = (int32_t)(blockIdx.x * 256u + threadIdx.x);
+    if (i >= n_total) return;
+    const ImgDesc& d = descs[image_of_prim(descs, B, i)];
+    const int32_t j = i - d.prim_begin;
+    const double c0 = d.cov[3 * j], c1 = d.cov[3 * j + 1], c2 = d.cov[3 * j + 2];
+    double sxx, sxy, syy;
+    if (kp.cov == WIPES_COV_CHOLESKY) {          // L = [[c0, 0], [c1, c2]]
+        sxx = c0 * c0;
+        sxy = c0 * c1;
+        syy = c1 * c1 + c2 * c2;
+    } else {                                     // (s1, s2, theta)
+        double sn, cs;
+        sincos(c2, &sn, &cs);
+        const double a = c0 * c0, e = c1 * c1;
+        sxx = cs * cs * a + sn * sn * e;
+        sxy = cs * sn * (a - e);
+        syy = sn * sn * a + cs * cs * e;
+    }
+    sxx += kp.blur_eps;
+    syy += kp.blur_eps;
+    const double det = sxx * syy - sxy * sxy;
+    if (!(det > 0.0)) {
+        store_culled(recs, aux, i, 0.0f);
+        return;
+    }
+    const double inv = 1.0 / det;
+    const float2 mu = reinterpret_cast<const float2*>(d.mean)[j];
+    const float2 f = reinterpret_cast<const float2*>(d.freq)[j];
+    store_record(recs, i, mu.x, mu.y, syy * inv, -sxy * inv, sxx * inv, f.x, f.y, d.opac[j], d.color[3 * j],
+                 d.color[3 * j + 1], d.color[3 * j + 2]);
+    float rx, ry;
+    support_box(sxx, syy, kp.q_add, &rx, &ry);
+    aux[i] = Aux{rx, ry, 0.0f, 0.0f};
+}
+
+// FP32 depth key: z = fma(V20, m_x, fma(V21, m_y, fma(V22, m_z, V23))), m = fma(v, tau, mu).
+__device__ __forceinline__ float depth_key(const float* __restrict__ V, float mx, float my, float mz)
+{
+    return fmaf(V[8], mx, fmaf(V[9], my, fmaf(V[10], mz, V[11])));
+}
+
+__global__ void __launch_bounds__(256) k_project_3d(const ImgDesc* __restrict__ descs, int B, int32_t n_total,
+                                                     KParams kp, Rec* __restrict__ recs, Aux* __restrict__ aux)
+{
+    const int32_t i = (int32_t)(blockIdx.x * 256u + threadIdx.x);
+    if (i >= n_total) return;
+    const ImgDesc& d = descs[image_of_prim(descs, B, i)];
+    const int32_t j = i - d.prim_begin;
+    float m32[3] = {d.mean[3 * j], d.mean[3 * j + 1], d.mean[3 * j + 2]};
+    if (d.vel) {
+        for (int k = 0; k < 3; ++k) m32[k] = fmaf(d.vel[3 * j + k], d.time, m32[k]);
+    }
+    const float zkey = depth_key(d.view, m32[0], m32[1], m32[2]);
+    const float op = d.opac[j];
+    // camera-space mean in FP64
+    double m[3];
+    for (int k = 0; k < 3; ++k)
+        m[k] = (double)d.mean[3 * j + k] + (d.vel ? (double)d.vel[3 * j + k] * (double)d.time : 0.0);
+    double t[3];
+    for (int r = 0; r < 3; ++r)
+        t[r] = (double)d.view[4 * r] * m[0] + (double)d.view[4 * r + 1] * m[1] + (double)d.view[4 * r + 2] * m[2] +
+               (double)d.view[4 * r + 3];
+    if (!(zkey > kp.near_plane) || !(op >= kp.alpha_min)) {
+        store_culled(recs, aux, i, zkey);
+        return;
+    }
+    const double tz = t[2], iz = 1.0 / tz;
+    double u = t[0] * iz, v = t[1] * iz;
+    const double lx = d.limx, ly = d.limy;
+    u = u < -lx ? -lx : (u > lx ? lx : u);
+    v = v < -ly ? -ly : (v > ly ? ly : v);
+    const double fxc = d.fx, fyc = d.fy;
+    const double J00 = fxc * iz, J02 = -fxc * u * iz, J11 = fyc * iz, J12 = -fyc * v * iz;
+    // M = J W (2x3); W rows are view[0..2], view[4..6], view[8..10]
+    double M[2][3];
+    for (int c = 0; c < 3; ++c) {
+        M[0][c] = J00 * d.view[c] + J02 * d.view[8 + c];
+        M[1][c] = J11 * d.view[4 + c] + J12 * d.view[8 + c];
+    }
+    double q0 = d.quat[4 * j], q1 = d.quat[4 * j + 1], q2 = d.quat[4 * j + 2], q3 = d.quat[4 * j + 3];
+    const double qq = q0 * q0 + q1 * q1 + q2 * q2 + q3 * q3;
+    if (!(qq > 0.0)) {
+        store_culled(recs, aux, i, zkey);
+        return;
+    }
+    const double qi = 1.0 / sqrt(qq);
+    q0 *= qi; q1 *= qi; q2 *= qi; q3 *= qi;
+    const double Rq[3][3] = {
+        {1.0 - 2.0 * (q2 * q2 + q3 * q3), 2.0 * (q1 * q2 - q0 * q3), 2.0 * (q1 * q3 + q0 * q2)},
+        {2.0 * (q1 * q2 + q0 * q3), 1.0 - 2.0 * (q1 * q1 + q3 * q3), 2.0 * (q2 * q3 - q0 * q1)},
+        {2.0 * (q1 * q3 - q0 * q2), 2.0 * (q2 * q3 + q0 * q1), 1.0 - 2.0 * (q1 * q1 + q2 * q2)}};
+    const double s[3] = {d.scale[3 * j], d.scale[3 * j + 1], d.scale[3 * j + 2]};
+    // T = M Rq diag(s): Sigma' = T T^T + eps I
+    double T[2][3];
+    for (int r = 0; r < 2; ++r)
+        for (int k = 0; k < 3; ++k) T[r][k] = (M[r][0] * Rq[0][k] + M[r][1] * Rq[1][k] + M[r][2] * Rq[2][k]) * s[k];
+    const double sxx = T[0][0] * T[0][0] + T[0][1] * T[0][1] + T[0][2] * T[0][2] + kp.blur_eps;
+    const double sxy = T[0][0] * T[1][0] + T[0][1] * T[1][1] + T[0][2] * T[1][2];
+    const double syy = T[1][0] * T[1][0] + T[1][1] * T[1][1] + T[1][2] * T[1][2] + kp.blur_eps;
+    const double det = sxx * syy - sxy * sxy;
+    if (!(det > 0.0)) {
+        store_culled(recs, aux, i, zkey);
+        return;
+    }
+    const double inv = 1.0 / det;
+    const double f0 = d.freq[3 * j], f1 = d.freq[3 * j + 1], f2 = d.freq[3 * j + 2];
+    const float fx = (float)(M[0][0] * f0 + M[0][1] * f1 + M[0][2] * f2);
+    const float fy = (float)(M[1][0] * f0 + M[1][1] * f1 + M[1][2] * f2);
+    const double mx = fxc * t[0] * iz + d.cx, my = fyc * t[1] * iz + d.cy;
+    store_record(recs, i, mx, my, syy * inv, -sxy * inv, sxx * inv, fx, fy, op, d.color[3 * j],
+                 d.color[3 * j + 1], d.color[3 * j + 2]);
+    float rx, ry;
+    support_box(sxx, syy, 2.0 * log((double)op / (double)kp.alpha_min), &rx, &ry);
+    aux[i] = Aux{rx, ry, zkey, 0.0f};
+}
+
+}  // namespace wipes
+
+namespace wipes {
+
+hipError_t launch_project(const ImgDesc* descs, int B, int32_t n_total, const KParams& kp, Rec* recs, Aux* aux,
+                          hipStream_t s)
+{
+    if (n_total <= 0) return hipGetLastError();
+    const dim3 grid(((uint32_t)n_total + 255u) / 256u);
+    if (kp.mode == WIPES_2D_ADDITIVE)
+        hipLaunchKernelGGL(k_project_2d, grid, dim3(256), 0, s, descs, B, n_total, kp, recs, aux);
+    else
+        hipLaunchKernelGGL(k_project_3d, grid, dim3(256), 0, s, descs, B, n_total, kp, recs, aux);
+    return hipGetLastError();
+}
+
+}  // namespace wipes

@@ -1,0 +1,344 @@
+// Device-wide exclusive scan and stable LSD radix sort of (uint32 key, uint32 value).
+//
+// Both are written for 64-lane waves: a workgroup of 256 threads owns a tile
+// of 4096 elements, each wave a contiguous quarter of it, so loads are fully
+// coalesced and the in-tile order (wave, round, lane) is the element order.
+// The radix pass ranks a wave's 64 elements per round with ballot-based digit
+// matching (one ballot per digit bit), accumulates per-wave digit counters in
+// LDS, then stages the tile in LDS in sorted order and writes it out so that
+// runs of equal digits go to HBM as contiguous stores.
+//
+// Element counts may live in device memory (instance counts produced on the
+// device are never read back inside a captured graph); grids are sized by an
+// upper bound and surplus workgroups exit.
+#include "common.hpp"
+
+namespace wipes {
+
+constexpr int kTile = 4096;      // elements per workgroup
+constexpr int kItems = 16;       // per thread
+constexpr int kBlock = 256;
+
+__device__ __forceinline__ uint32_t load_n(uint32_t n_host, const uint32_t* __restrict__ n_dev)
+{
+    return n_dev ? *n_dev : n_host;
+}
+
+// ------------------------------------------------------------------ scan
+
+// block_sums[b] = sum of vals[gather ? gather[i] : i] over the tile of block b.
+__global__ void __launch_bounds__(kBlock) k_block_reduce(const uint32_t* __restrict__ vals,
+                                                         const uint32_t* __restrict__ gather, uint32_t n_host,
+                                                         const uint32_t* __restrict__ n_dev,
+                                                         uint32_t* __restrict__ block_sums)
+{
+    __shared__ uint32_t s_w[kBlock / kWave];
+    const uint32_t n = load_n(n_host, n_dev);
+    const uint32_t base = blockIdx.x * kTile;
+    uint32_t acc = 0;
+    for (int j = 0; j < kItems; ++j) {
+        const uint32_t i = base + j * kBlock + threadIdx.x;
+        if (i < n) acc += vals[gather ? gather[i] : i];
+    }
+    acc = wave_sum_u32(acc);
+    if (lane_id() == 0) s_w[threadIdx.x / kWave] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t t = 0;
+        for (int w = 0; w < kBlock / kWave; ++w) t += s_w[w];
+        block_sums[blockIdx.x] = t;
+    }
+}
+
+// Exclusive scan of block_sums[0..nb) in place (one workgroup); *total = sum.
+// If cap != 0 and the total exceeds it, *n_eff = 0 and *overflow = 1, else
+// *n_eff = total (n_eff/overflow may be NULL).
+__global__ void __launch_bounds__(kBlock) k_scan_block_sums(uint32_t* __restrict__ block_sums, uint32_t nb,
+                                                            uint32_t* __restrict__ total, uint32_t cap,
+                                                            uint32_t* __restrict__ n_eff,
+                                                            uint32_t* __restrict__ overflow)
+{
+    __shared__ uint32_t s_w[kBlock / kWave];
+    __shared__ uint32_t s_carry;
+    if (threadIdx.x == 0) s_carry = 0;
+    __syncthreads();
+    for (uint32_t c = 0; c < nb; c += kBlock) {
+        const uint32_t i = c + threadIdx.x;
+        const uint32_t v = i < nb ? block_sums[i] : 0u;
+        uint32_t wt;
+        const uint32_t ex = wave_excl_scan_u32(v, &wt);
+        if (lane_id() == 0) s_w[threadIdx.x / kWave] = wt;
+        __syncthreads();
+        uint32_t off = s_carry;
+        for (int w = 0; w < (int)(threadIdx.x / kWave); ++w) off += s_w[w];
+        if (i < nb) block_sums[i] = off + ex;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint32_t t = 0;
+            for (int w = 0; w < kBlock / kWave; ++w) t += s_w[w];
+            s_carry += t;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const uint32_t t = s_carry;
+        *total = t;
+        if (n_eff) {
+            const bool over = cap != 0u && t > cap;
+            *n_eff = over ? 0u : t;
+            if (overflow) *overflow = over ? 1u : 0u;
+        }
+    }
+}
+
+// out[i] = exclusive prefix of vals (through gather) + scanned block sum.
+__global__ void __launch_bounds__(kBlock) k_scan_apply(const uint32_t* __restrict__ vals,
+                                                       const uint32_t* __restrict__ gather, uint32_t n_host,
+                                                       const uint32_t* __restrict__ n_dev,
+                                                       const uint32_t* __restrict__ block_sums,
+                                                       uint32_t* __restrict__ out)
+{
+    __shared__ uint32_t s_w[kBlock / kWave];
+    const uint32_t n = load_n(n_host, n_dev);
+    const uint32_t base = blockIdx.x * kTile;
+    // each wave owns a contiguous quarter of the tile: 16 rounds of 64
+    const int w = threadIdx.x / kWave, l = lane_id();
+    const uint32_t wbase = base + (uint32_t)w * (kTile / 4);
+    uint32_t v[kItems];
+    uint32_t wsum = 0;
+    for (int j = 0; j < kItems; ++j) {
+        const uint32_t i = wbase + j * kWave + l;
+        v[j] = i < n ? vals[gather ? gather[i] : i] : 0u;
+        wsum += v[j];
+    }
+    wsum = wave_sum_u32(wsum);
+    if (l == 0) s_w[w] = wsum;
+    __syncthreads();
+    uint32_t run = block_sums[blockIdx.x];
+    for (int k = 0; k < w; ++k) run += s_w[k];
+    for (int j = 0; j < kItems; ++j) {
+        uint32_t t;
+        const uint32_t ex = wave_excl_scan_u32(v[j], &t);
+        const uint32_t i = wbase + j * kWave + l;
+        if (i < n) out[i] = run + ex;
+        run += t;
+    }
+}
+
+// ------------------------------------------------------------ radix sort
+
+// hist[d * nblocks + b] = number of elements of tile b with digit d.
+template <int BITS>
+__global__ void __launch_bounds__(kBlock) k_radix_hist(const uint32_t* __restrict__ keys, uint32_t n_host,
+                                                       const uint32_t* __restrict__ n_dev, int shift,
+                                                       uint32_t nblocks, uint32_t* __restrict__ hist)
+{
+    constexpr int ND = 1 << BITS;
+    __shared__ uint32_t s_h[ND];
+    for (int d = threadIdx.x; d < ND; d += kBlock) s_h[d] = 0;
+    __syncthreads();
+    const uint32_t n = load_n(n_host, n_dev);
+    const uint32_t base = blockIdx.x * kTile;
+    for (int j = 0; j < kItems; ++j) {
+        const uint32_t i = base + j * kBlock + threadIdx.x;
+        if (i < n) atomicAdd(&s_h[(keys[i] >> shift) & (ND - 1)], 1u);
+    }
+    __syncthreads();
+    for (int d = threadIdx.x; d < ND; d += kBlock) hist[(uint32_t)d * nblocks + blockIdx.x] = s_h[d];
+}
+
+// Exclusive scan of each digit's row of hist across blocks; row totals to dtot.
+__global__ void __launch_bounds__(kBlock) k_radix_rowscan(uint32_t* __restrict__ hist, uint32_t nblocks,
+                                                          uint32_t* __restrict__ dtot)
+{
+    __shared__ uint32_t s_w[kBlock / kWave];
+    __shared__ uint32_t s_carry;
+    uint32_t* row = hist + (uint32_t)blockIdx.x * nblocks;
+    if (threadIdx.x == 0) s_carry = 0;
+    __syncthreads();
+    for (uint32_t c = 0; c < nblocks; c += kBlock) {
+        const uint32_t i = c + threadIdx.x;
+        const uint32_t v = i < nblocks ? row[i] : 0u;
+        uint32_t wt;
+        const uint32_t ex = wave_excl_scan_u32(v, &wt);
+        if (lane_id() == 0) s_w[threadIdx.x / kWave] = wt;
+        __syncthreads();
+        uint32_t off = s_carry;
+        for (int w = 0; w < (int)(threadIdx.x / kWave); ++w) off += s_w[w];
+        if (i < nblocks) row[i] = off + ex;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint32_t t = 0;
+            for (int w = 0; w < kBlock / kWave; ++w) t += s_w[w];
+            s_carry += t;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) dtot[blockIdx.x] = s_carry;
+}
+
+template <int BITS>
+__global__ void __launch_bounds__(kBlock) k_radix_scatter(const uint32_t* __restrict__ keys_in,
+                                                          const uint32_t* __restrict__ vals_in, uint32_t n_host,
+                                                          const uint32_t* __restrict__ n_dev, int shift,
+                                                          uint32_t nblocks, const uint32_t* __restrict__ hist,
+                                                          const uint32_t* __restrict__ dtot,
+                                                          uint32_t* __restrict__ keys_out,
+                                                          uint32_t* __restrict__ vals_out)
+{
+    constexpr int ND = 1 << BITS;
+    constexpr int NW = kBlock / kWave;
+    __shared__ uint32_t s_keys[kTile];
+    __shared__ uint32_t s_vals[kTile];
+    __shared__ uint32_t s_wcnt[NW][ND];
+    __shared__ uint32_t s_dbase[ND];
+    __shared__ uint32_t s_gbase[ND];
+
+    const uint32_t n = load_n(n_host, n_dev);
+    const uint32_t base = blockIdx.x * kTile;
+    if (base >= n) return;
+    const int w = threadIdx.x / kWave, l = lane_id();
+    for (int d = threadIdx.x; d < NW * ND; d += kBlock) (&s_wcnt[0][0])[d] = 0;
+    __syncthreads();
+
+    const uint32_t wbase = base + (uint32_t)w * (kTile / NW);
+    const uint64_t lt_mask = (l == 0) ? 0ull : (~0ull >> (64 - l));
+    uint32_t k[kItems], v[kItems], rk[kItems];
+    for (int j = 0; j < kItems; ++j) {
+        const uint32_t i = wbase + j * kWave + l;
+        const bool ok = i < n;
+        k[j] = ok ? keys_in[i] : 0u;
+        v[j] = ok ? vals_in[i] : 0u;
+    }
+    for (int j = 0; j < kItems; ++j) {
+        const uint32_t i = wbase + j * kWave + l;
+        const bool ok = i < n;
+        const uint32_t dig = (k[j] >> shift) & (ND - 1);
+        uint64_t peers = __ballot(ok);
+        for (int b = 0; b < BITS; ++b) {
+            const bool bit = (dig >> b) & 1u;
+            const uint64_t bb = __ballot(bit);
+            peers &= bit ? bb : ~bb;
+        }
+        const uint32_t before = (uint32_t)__popcll(peers & lt_mask);
+        uint32_t old = 0;
+        if (ok) old = s_wcnt[w][dig];
+        rk[j] = old + before;
+        // the lowest lane of each digit group publishes the new count; every
+        // lane of the wave has read the old value above (in-order LDS per wave)
+        if (ok && before == 0) s_wcnt[w][dig] = old + (uint32_t)__popcll(peers);
+    }
+    __syncthreads();
+    // per digit: exclusive prefix over waves, then over digits within the tile
+    for (int d = threadIdx.x; d < ND; d += kBlock) {
+        uint32_t run = 0;
+        for (int ww = 0; ww < NW; ++ww) {
+            const uint32_t c = s_wcnt[ww][d];
+            s_wcnt[ww][d] = run;
+            run += c;
+        }
+        s_dbase[d] = run;   // tile total of digit d (scanned below)
+    }
+    __syncthreads();
+    if (threadIdx.x < kWave) {
+        // exclusive scan of the ND tile totals and of the ND global digit totals, 64 at a time
+        uint32_t carry_t = 0, carry_g = 0;
+        for (int c = 0; c < ND; c += kWave) {
+            const int d = c + l;
+            const uint32_t tt = d < ND ? s_dbase[d] : 0u;
+            const uint32_t gt = d < ND ? dtot[d] : 0u;
+            uint32_t wt, wg;
+            const uint32_t et = wave_excl_scan_u32(tt, &wt);
+            const uint32_t eg = wave_excl_scan_u32(gt, &wg);
+            if (d < ND) {
+                s_dbase[d] = carry_t + et;
+                s_gbase[d] = carry_g + eg + hist[(uint32_t)d * nblocks + blockIdx.x];
+            }
+            carry_t += wt;
+            carry_g += wg;
+        }
+    }
+    __syncthreads();
+    for (int j = 0; j < kItems; ++j) {
+        const uint32_t i = wbase + j * kWave + l;
+        if (i < n) {
+            const uint32_t dig = (k[j] >> shift) & (ND - 1);
+            const uint32_t pos = s_dbase[dig] + s_wcnt[w][dig] + rk[j];
+            s_keys[pos] = k[j];
+            s_vals[pos] = v[j];
+        }
+    }
+    __syncthreads();
+    const uint32_t cnt = min((uint32_t)kTile, n - base);
+    for (uint32_t p = threadIdx.x; p < cnt; p += kBlock) {
+        const uint32_t key = s_keys[p];
+        const uint32_t dig = (key >> shift) & (ND - 1);
+        const uint32_t g = s_gbase[dig] + (p - s_dbase[dig]);
+        keys_out[g] = key;
+        vals_out[g] = s_vals[p];
+    }
+}
+
+// ------------------------------------------------------------- host side
+
+uint32_t scan_blocks(uint32_t max_n) { return (max_n + kTile - 1) / kTile; }
+
+hipError_t scan_excl(const uint32_t* vals, const uint32_t* gather, uint32_t n_host, const uint32_t* n_dev,
+                     uint32_t max_n, uint32_t* block_sums, uint32_t* out, uint32_t* total, uint32_t cap,
+                     uint32_t* n_eff, uint32_t* overflow, hipStream_t s)
+{
+    const uint32_t nb = scan_blocks(max_n);
+    if (nb > 0) {
+        hipLaunchKernelGGL(k_block_reduce, dim3(nb), dim3(kBlock), 0, s, vals, gather, n_host, n_dev, block_sums);
+    }
+    hipLaunchKernelGGL(k_scan_block_sums, dim3(1), dim3(kBlock), 0, s, block_sums, nb, total, cap, n_eff, overflow);
+    if (nb > 0) {
+        hipLaunchKernelGGL(k_scan_apply, dim3(nb), dim3(kBlock), 0, s, vals, gather, n_host, n_dev, block_sums,
+                           out);
+    }
+    return hipGetLastError();
+}
+
+template <int BITS>
+static void radix_pass(const uint32_t* ki, const uint32_t* vi, uint32_t* ko, uint32_t* vo, uint32_t n_host,
+                       const uint32_t* n_dev, uint32_t nb, int shift, uint32_t* hist, uint32_t* dtot, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_radix_hist<BITS>, dim3(nb), dim3(kBlock), 0, s, ki, n_host, n_dev, shift, nb, hist);
+    hipLaunchKernelGGL(k_radix_rowscan, dim3(1 << BITS), dim3(kBlock), 0, s, hist, nb, dtot);
+    hipLaunchKernelGGL(k_radix_scatter<BITS>, dim3(nb), dim3(kBlock), 0, s, ki, vi, n_host, n_dev, shift, nb, hist,
+                       dtot, ko, vo);
+}
+
+int radix_passes(int nbits) { return nbits <= 0 ? 0 : (nbits + 7) / 8; }
+
+hipError_t radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, uint32_t n_host,
+                      const uint32_t* n_dev, uint32_t max_n, int nbits, uint32_t* hist, uint32_t* dtot,
+                      int* result_in_1, hipStream_t s)
+{
+    const int np = radix_passes(nbits);
+    *result_in_1 = 0;
+    const uint32_t nb = scan_blocks(max_n);
+    if (np == 0 || nb == 0) return hipGetLastError();
+    const int bits = (nbits + np - 1) / np;
+    uint32_t *ki = k0, *vi = v0, *ko = k1, *vo = v1;
+    for (int p = 0; p < np; ++p) {
+        const int shift = p * bits;
+        switch (bits) {
+        case 1: radix_pass<1>(ki, vi, ko, vo, n_host, n_dev, nb, shift, hist, dtot, s); break;
+        case 2: radix_pass<2>(ki, vi, ko, vo, n_host, n_dev, nb, shift, hist, dtot, s); break;
+        case 3: radix_pass<3>(ki, vi, ko, vo, n_host, n_dev, nb, shift, hist, dtot, s); break;
+        case 4: radix_pass<4>(ki, vi, ko, vo, n_host, n_dev, nb, shift, hist, dtot, s); break;
+        case 5: radix_pass<5>(ki, vi, ko, vo, n_host, n_dev, nb, shift, hist, dtot, s); break;
+        case 6: radix_pass<6>(ki, vi, ko, vo, n_host, n_dev, nb, shift, hist, dtot, s); break;
+        case 7: radix_pass<7>(ki, vi, ko, vo, n_host, n_dev, nb, shift, hist, dtot, s); break;
+        default: radix_pass<8>(ki, vi, ko, vo, n_host, n_dev, nb, shift, hist, dtot, s); break;
+        }
+        uint32_t* t;
+        t = ki; ki = ko; ko = t;
+        t = vi; vi = vo; vo = t;
+    }
+    *result_in_1 = (np & 1);
+    return hipGetLastError();
+}
+
+}  // namespace wipes
