@@ -138,6 +138,8 @@ typedef struct {
     wipes_camera cam;
     wipes_prims prims;
     wipes_prims_grad grads;   /* read by wipes_render_bwd only */
+    float* out_image;         /* optional device [W H, 3]: wipes_render_fwd writes this image's colours
+                                 here instead of into the batch image array (NULL: batch array) */
 } wipes_image;
 
 /* A batch of images rendered together (B = 1 is the plain rasterizer).
@@ -249,6 +251,128 @@ wipes_status wipes_check_overflow(wipes_ctx* ctx, const wipes_params* p, const w
 wipes_status wipes_bins_view(const wipes_params* p, const wipes_batch* batch, const wipes_buffer* screen,
                              const wipes_buffer* bins, const uint32_t** keys, const uint32_t** vals,
                              const uint32_t** ranges, int64_t* n_tiles);
+
+/* ------------------------------------------------------- fitting, graphs */
+
+/* Gradient of the L2 fitting loss L = sum over images of the mean over that
+ * image's 3 W H values of (C - target)^2 (the 2D image-fitting objective,
+ * Sec. 5.1): dL_dimage = 2 (image - target) / (3 W H).  All three arrays are
+ * device [sum W H, 3]. */
+wipes_status wipes_l2_grad(wipes_ctx* ctx, const wipes_params* p, const wipes_batch* batch,
+                           const wipes_buffer* screen, const float* image, const float* target, float* dL_dimage,
+                           void* stream);
+
+typedef struct wipes_graph wipes_graph;
+
+/* Capture one whole render step of a fixed batch into a hipGraph: project,
+ * bin/sort (no host synchronisation; grids sized by bins->capacity), forward
+ * blend, then, if target != NULL, the L2 gradient into dL_dimage, and, if
+ * backward != 0, the backward pass into each image's grads.  Every pointer
+ * (batch arrays, buffers, outputs) must stay valid and the batch unchanged for
+ * the graph's lifetime; parameter values may change between launches.  If
+ * the instance count outgrows the capacity the replay leaves its outputs
+ * untouched and wipes_check_overflow reports WIPES_ERR_CAPACITY; capture again
+ * with a larger bins buffer.  The capture itself runs on a private stream and
+ * synchronises it once (descriptor upload). */
+wipes_status wipes_graph_capture(wipes_ctx* ctx, const wipes_params* p, const wipes_batch* batch,
+                                 wipes_buffer* screen, wipes_buffer* bins, float* image, float* T_final,
+                                 int32_t* last, const float* target, float* dL_dimage, int32_t backward,
+                                 wipes_graph** out);
+
+/* Replay a captured step on a stream (asynchronous). */
+wipes_status wipes_graph_launch(wipes_graph* g, void* stream);
+void wipes_graph_destroy(wipes_graph* g);
+
+/* --------------------------------------------------------------- serving */
+
+typedef struct wipes_server wipes_server;
+
+typedef struct {
+    int32_t max_slots;         /* requests in flight at once */
+    int32_t max_pending;       /* waiting requests before submit returns WIPES_ERR_BUSY */
+    int32_t max_batch;         /* requests per launch */
+    int32_t persistent;        /* persistent tile-queue blend across the batch (1) or grid launch (0) */
+    int64_t hbm_budget_bytes;  /* arena for per-request workspaces, allocated at create */
+} wipes_serve_config;
+
+typedef struct {
+    double p50_ms, p99_ms, mean_ms;   /* submit -> completion latency of completed requests */
+    double frames_per_s;              /* completed / (last completion - first submit) */
+    int64_t completed, admitted, deferred, batches;
+    double mean_batch;                /* requests per launch */
+    int64_t arena_peak_bytes;
+} wipes_serve_report;
+
+/* Create a server on `device` for 3D alpha rendering with constants p.  It
+ * owns a context, two streams, its scene copies and one arena of
+ * hbm_budget_bytes; a worker thread admits requests in FIFO order when request
+ * slots and one arena block for the batch's workspace (projection records,
+ * bins, per-pixel state) are free, renders each admitted batch -- requests of
+ * any resolution together -- with projection and sort on one stream and the
+ * blend on another, so the next batch is prepared while the current one
+ * blends.  Internally synchronised: every serve call may come from any thread. */
+wipes_status wipes_serve_create(const wipes_serve_config* cfg, const wipes_params* p, int32_t device,
+                                wipes_server** out);
+/* Copy a scene (device arrays, 3D layout of wipes_prims) into server memory. */
+wipes_status wipes_serve_load_scene(wipes_server* s, const wipes_prims* prims, int32_t* scene_id);
+/* WIPES_ERR_BUSY while requests for the scene are pending or in flight. */
+wipes_status wipes_serve_unload_scene(wipes_server* s, int32_t scene_id);
+/* Queue a render (non-blocking).  out_image: device [W H, 3], must stay valid
+ * until poll reports the request done.  WIPES_ERR_BUSY if the queue is full. */
+wipes_status wipes_serve_submit(wipes_server* s, int32_t scene_id, const wipes_camera* cam, float* out_image,
+                                uint64_t* req_id);
+/* *done = 1 once the image is in out_image; then *latency_ms is the submit ->
+ * completion time and the id is forgotten. */
+wipes_status wipes_serve_poll(wipes_server* s, uint64_t req_id, int32_t* done, double* latency_ms);
+/* Block until every submitted request has completed. */
+wipes_status wipes_serve_drain(wipes_server* s);
+wipes_status wipes_serve_stats(wipes_server* s, wipes_serve_report* out);
+wipes_status wipes_serve_reset_stats(wipes_server* s);
+void wipes_serve_destroy(wipes_server* s);
+
+/* Host-only model of the server's scheduler with a fake executor (no device
+ * work): request i arrives at t_arrive[i] (sorted), holds footprint[i] arena
+ * bytes while admitted; a batch's preparation takes the sum of its prep_s on
+ * the prep stream, its blend the sum of blend_s on the blend stream (blends run
+ * one after another, overlapping the next preparation).  Writes admission and
+ * completion times, the batch index of each request and the arena peak. */
+wipes_status wipes_serve_simulate(const wipes_serve_config* cfg, int64_t n, const double* t_arrive,
+                                  const int64_t* footprint, const double* prep_s, const double* blend_s,
+                                  double* t_admit, double* t_done, int64_t* batch_of, int64_t* arena_peak);
+
+/* ------------------------------------------------------------ profiling */
+
+/* Stages of the render path, in pipeline order. */
+enum {
+    WIPES_STAGE_PROJECT = 0, WIPES_STAGE_BIN_COUNT, WIPES_STAGE_SCAN, WIPES_STAGE_DEPTH_SORT,
+    WIPES_STAGE_RANK_SCAN, WIPES_STAGE_EMIT, WIPES_STAGE_TILE_SORT, WIPES_STAGE_RANGES,
+    WIPES_STAGE_BLEND_FWD, WIPES_STAGE_BLEND_BWD, WIPES_STAGE_PROJECT_BWD, WIPES_N_STAGES
+};
+
+/* Name of a stage ("" if out of range). */
+const char* wipes_stage_name(int32_t stage);
+
+/* When enabled, every stage of the render path on this context is bracketed
+ * by a pair of HIP events recorded on the stream it is launched on (for
+ * benchmarks; adds two event records per stage). */
+wipes_status wipes_profile_enable(wipes_ctx* ctx, int32_t enable);
+
+/* Waits for the recorded events and returns, per stage, the summed duration
+ * in ms (ms[WIPES_N_STAGES]) and the number of launches since the last read;
+ * then forgets them. n must be >= WIPES_N_STAGES. */
+wipes_status wipes_profile_read(wipes_ctx* ctx, double* ms, int64_t* launches, int32_t n);
+
+/* Work counts of a rendered frame, for roofline accounting (synchronises):
+ *   out[0]  support pairs the forward evaluates: (pixel, primitive) pairs with
+ *           the pixel inside the primitive's support (q <= q_add, or in alpha
+ *           mode q <= 2 ln(o / alpha_min)), up to the pixel's stopping pair;
+ *   out[1]  support pairs the backward revisits (alpha: up to `last`);
+ *   out[2]  tile pairs: instances x valid pixels of their tile;
+ *   out[3]  pairs visited after 8x8 sub-block culling.
+ * T_final and last are the forward's outputs (alpha mode). */
+wipes_status wipes_render_stats(wipes_ctx* ctx, const wipes_params* p, const wipes_batch* batch,
+                                const wipes_buffer* screen, const wipes_buffer* bins, const float* T_final,
+                                const int32_t* last, uint64_t* out, void* stream);
 
 #ifdef __cplusplus
 }

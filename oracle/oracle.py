@@ -129,6 +129,8 @@ def lib():
         _lib.or_render_bwd_o2.argtypes = [C.POINTER(_Params), C.c_int32, C.c_int32, C.c_int64, P, P, P, P, P, P,
                                           C.c_int32]
         _lib.or_project_bwd.argtypes = [C.POINTER(_Params), C.POINTER(_Camera), C.c_int64] + [P] * 7 + [P] * 10
+        _lib.or_support_counts.argtypes = [C.POINTER(_Params), C.c_int32, C.c_int32, C.c_int64, P, P, C.c_int64,
+                                           P, P, P]
         _lib.or_bin.argtypes = [C.c_int32] * 5 + [C.c_int64] + [P] * 5 + [P, P, P, P, P, P]
     return _lib
 
@@ -298,3 +300,17 @@ def bin_tiles(W: int, H: int, tw: int, th: int, mode: int, mx, my, rx, ry, depth
     L.or_bin(W, H, tw, th, mode, n, _p(mx), _p(my), _p(rx), _p(ry), _p(depth), _p(box), _p(count), C.byref(K),
              _p(keys), _p(vals), _p(ranges))
     return dict(box=box, count=count, K=Kv, keys=keys[:Kv], vals=vals[:Kv], ranges=ranges)
+
+
+def support_counts(params: Params, W: int, H: int, screen: np.ndarray, keys=None, pix=None):
+    """Per listed pixel: (support pairs the forward evaluates, support pairs the backward revisits)."""
+    screen = np.ascontiguousarray(screen, dtype=np.float64)
+    n = screen.shape[0]
+    pix = None if pix is None else np.ascontiguousarray(np.asarray(pix, dtype=np.int64))
+    npix = W * H if pix is None else pix.shape[0]
+    fwd = np.zeros(npix, np.int64)
+    bwd = np.zeros(npix, np.int64)
+    k = _keys_or_none(params, keys)
+    cp = params.c()
+    lib().or_support_counts(C.byref(cp), W, H, n, _p(screen), _p(k), npix, _p(pix), _p(fwd), _p(bwd))
+    return fwd, bwd

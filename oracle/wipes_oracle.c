@@ -1172,3 +1172,58 @@ void or_bin(int32_t W, int32_t H, int32_t tw, int32_t th, int32_t mode, int64_t 
     }
     free(e);
 }
+
+/* ------------------------------------------------------------------------ */
+/* Work counts                                                              */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * Support pairs per listed pixel: pairs whose pixel lies inside the
+ * primitive's support ellipse q <= Q (Q = q_add, or 2 ln(o / alpha_min) in
+ * alpha mode), counted
+ *   fwd[k]: over the pairs the per-pixel rule evaluates (alpha: up to and
+ *           including the stopping pair);
+ *   bwd[k]: alpha: up to and including the last contributing pair; additive:
+ *           equal to fwd.
+ */
+void or_support_counts(const or_params* P, int32_t W, int32_t H, int64_t n, const double* screen,
+                       const uint32_t* depth_key, int64_t npix, const int64_t* pix, int64_t* fwd, int64_t* bwd)
+{
+    (void)H;
+    int64_t nvalid = 0;
+    order_ent* ord = make_order(screen, n, P->mode == OR_MODE_ALPHA3D ? depth_key : NULL, &nvalid);
+#pragma omp parallel
+    {
+        order_ent* cand = (order_ent*)malloc(sizeof(order_ent) * (size_t)(nvalid > 0 ? nvalid : 1));
+#pragma omp for schedule(dynamic, 64)
+        for (int64_t k = 0; k < npix; ++k) {
+            int64_t p = pix_of(pix, k);
+            double px = (double)(p % W) + 0.5, py = (double)(p / W) + 0.5;
+            int64_t nc = 0;
+            for (int64_t j = 0; j < nvalid; ++j)
+                if (in_padded_box(screen + SR_N * ord[j].id, px, py)) cand[nc++] = ord[j];
+            int64_t cf = 0, cb = 0, pending = 0;
+            double T = 1.0;
+            for (int64_t j = 0; j < nc; ++j) {
+                const double* s = screen + SR_N * cand[j].id;
+                pair_eval pe;
+                eval_pair(s, px, py, &pe);
+                int in = pe.q <= s[SR_Q];
+                cf += in;
+                if (P->mode == OR_MODE_ADD2D) continue;
+                pending += in;
+                double a = s[SR_OP] * pe.w;
+                if (a < P->alpha_min) continue;
+                cb += pending;          /* support pairs up to this contributing pair */
+                pending = 0;
+                double alpha = a > P->alpha_max ? P->alpha_max : a;
+                T *= (1.0 - alpha);
+                if (T < P->T_min) break;
+            }
+            fwd[k] = cf;
+            bwd[k] = P->mode == OR_MODE_ADD2D ? cf : cb;
+        }
+        free(cand);
+    }
+    free(ord);
+}

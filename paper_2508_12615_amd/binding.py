@@ -50,7 +50,7 @@ class wipes_prims_grad(C.Structure):
 
 
 class wipes_image(C.Structure):
-    _fields_ = [("cam", wipes_camera), ("prims", wipes_prims), ("grads", wipes_prims_grad)]
+    _fields_ = [("cam", wipes_camera), ("prims", wipes_prims), ("grads", wipes_prims_grad), ("out_image", C.c_void_p)]
 
 
 class wipes_batch(C.Structure):
@@ -93,6 +93,13 @@ def lib() -> C.CDLL:
         "wipes_bins_view": (C.c_int, [PP(wipes_params), PP(wipes_batch), PP(wipes_buffer), PP(wipes_buffer),
                                       PP(C.c_void_p), PP(C.c_void_p), PP(C.c_void_p), PP(C.c_int64)]),
     }
+    sig.update({
+        "wipes_stage_name": (C.c_char_p, [C.c_int32]),
+        "wipes_profile_enable": (C.c_int, [P, C.c_int32]),
+        "wipes_profile_read": (C.c_int, [P, PP(C.c_double), PP(C.c_int64), C.c_int32]),
+        "wipes_render_stats": (C.c_int, [P, PP(wipes_params), PP(wipes_batch), PP(wipes_buffer), PP(wipes_buffer),
+                                         P, P, PP(C.c_uint64), P]),
+    })
     for name, (res, args) in sig.items():
         f = getattr(L, name)
         f.restype = res
@@ -180,3 +187,50 @@ def wipes_bins_view(params, batch, screen, bins):
     check(lib().wipes_bins_view(C.byref(params), C.byref(batch), C.byref(screen), C.byref(bins), C.byref(keys),
                                 C.byref(vals), C.byref(ranges), C.byref(nt)))
     return keys.value, vals.value, ranges.value, nt.value
+
+
+WIPES_N_STAGES = 11
+
+
+def wipes_stage_name(stage: int) -> str:
+    return lib().wipes_stage_name(stage).decode()
+
+
+def wipes_profile_enable(ctx, enable: bool) -> None:
+    check(lib().wipes_profile_enable(ctx, int(bool(enable))), ctx)
+
+
+def wipes_profile_read(ctx):
+    """{stage name: (total ms, launches)} since the last read."""
+    ms = (C.c_double * WIPES_N_STAGES)()
+    n = (C.c_int64 * WIPES_N_STAGES)()
+    check(lib().wipes_profile_read(ctx, ms, n, WIPES_N_STAGES), ctx)
+    return {wipes_stage_name(i): (ms[i], n[i]) for i in range(WIPES_N_STAGES)}
+
+
+def wipes_render_stats(ctx, params, batch, screen, bins, T_final: int, last: int, stream: int = 0):
+    out = (C.c_uint64 * 4)()
+    check(lib().wipes_render_stats(ctx, C.byref(params), C.byref(batch), C.byref(screen), C.byref(bins), T_final,
+                                   last, out, stream), ctx)
+    return dict(support_fwd=out[0], support_bwd=out[1], tile_pairs=out[2], subblock_pairs=out[3])
+
+
+def wipes_l2_grad(ctx, params, batch, screen, image: int, target: int, dL_dimage: int, stream: int = 0) -> None:
+    check(lib().wipes_l2_grad(ctx, C.byref(params), C.byref(batch), C.byref(screen), image, target, dL_dimage,
+                              stream), ctx)
+
+
+def wipes_graph_capture(ctx, params, batch, screen, bins, image: int, T_final, last, target, dL_dimage,
+                        backward: bool):
+    g = C.c_void_p()
+    check(lib().wipes_graph_capture(ctx, C.byref(params), C.byref(batch), C.byref(screen), C.byref(bins), image,
+                                    T_final, last, target, dL_dimage, int(bool(backward)), C.byref(g)), ctx)
+    return g
+
+
+def wipes_graph_launch(graph, stream: int = 0) -> None:
+    check(lib().wipes_graph_launch(graph, stream))
+
+
+def wipes_graph_destroy(graph) -> None:
+    lib().wipes_graph_destroy(graph)

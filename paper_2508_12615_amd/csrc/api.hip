@@ -207,6 +207,7 @@ void fill_descs(const wipes_params* p, const wipes_batch* b, std::vector<ImgDesc
         d.g_color = im.grads.color;
         d.g_opac = im.grads.opacity;
         d.g_vel = im.grads.velocity;
+        d.out_image = im.out_image;
         d.prim_begin = prim;
         d.n = (int32_t)im.prims.n;
         d.pix_begin = pix;
@@ -254,6 +255,35 @@ wipes_status upload_descs(wipes_ctx* ctx, const wipes_params* p, const wipes_bat
     if (e != hipSuccess) return hip_fail(ctx, e, "staging event record");
     slot.used = true;
     return WIPES_OK;
+}
+
+static hipEvent_t prof_event(wipes_ctx* c)
+{
+    if (!c->prof.pool.empty()) {
+        hipEvent_t e = c->prof.pool.back();
+        c->prof.pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+StageScope::StageScope(wipes_ctx* ctx, int stage, hipStream_t stream) : c(ctx), st(stage), s(stream)
+{
+    if (c && c->prof.on && !c->capturing) {
+        a = prof_event(c);
+        if (a) (void)hipEventRecord(a, s);
+    }
+}
+
+StageScope::~StageScope()
+{
+    if (!a) return;
+    hipEvent_t b = prof_event(c);
+    if (!b) return;
+    (void)hipEventRecord(b, s);
+    c->prof.rec[st].push_back({a, b});
 }
 
 }  // namespace wipes
@@ -315,10 +345,17 @@ wipes_status wipes_ctx_create(int32_t device, wipes_ctx** out)
 void wipes_ctx_destroy(wipes_ctx* ctx)
 {
     if (!ctx) return;
+    for (int st = 0; st < kStN; ++st)
+        for (auto& pr : ctx->prof.rec[st]) {
+            (void)hipEventSynchronize(pr.second);
+            (void)hipEventDestroy(pr.first);
+            (void)hipEventDestroy(pr.second);
+        }
+    for (hipEvent_t e : ctx->prof.pool) hipEventDestroy(e);
     for (int i = 0; i < kRing; ++i) {
         if (ctx->ring[i].ev) {
-            hipEventSynchronize(ctx->ring[i].ev);
-            hipEventDestroy(ctx->ring[i].ev);
+            (void)hipEventSynchronize(ctx->ring[i].ev);
+            (void)hipEventDestroy(ctx->ring[i].ev);
         }
         if (ctx->ring[i].host) hipHostFree(ctx->ring[i].host);
     }
@@ -381,6 +418,7 @@ wipes_status wipes_project(wipes_ctx* ctx, const wipes_params* p, const wipes_ba
     hipStream_t s = (hipStream_t)stream;
     if ((st = upload_descs(ctx, p, b, L, screen->base, s)) != WIPES_OK) return st;
     char* base = (char*)screen->base;
+    StageScope sc(ctx, kStProject, s);
     hipError_t e = launch_project((const ImgDesc*)(base + L.s_descs), L.B, (int32_t)L.n, kparams(p),
                                   (Rec*)(base + L.s_recs), (Aux*)(base + L.s_aux), s);
     if (e != hipSuccess) return hip_fail(ctx, e, "project");
@@ -461,6 +499,57 @@ wipes_status wipes_bins_view(const wipes_params* p, const wipes_batch* b, const 
     if (ranges) *ranges = (const uint32_t*)(base + L.b_ranges);
     if (n_tiles) *n_tiles = L.tiles;
     return WIPES_OK;
+}
+
+static const char* kStageNames[kStN] = {"project", "bin_count", "scan", "depth_sort", "rank_scan", "emit",
+                                        "tile_sort", "ranges", "blend_fwd", "blend_bwd", "project_bwd"};
+
+const char* wipes_stage_name(int32_t stage)
+{
+    return (stage >= 0 && stage < kStN) ? kStageNames[stage] : "";
+}
+
+wipes_status wipes_profile_enable(wipes_ctx* ctx, int32_t enable)
+{
+    if (!ctx) return fail(nullptr, WIPES_ERR_INVALID, "ctx must not be NULL");
+    ctx->prof.on = enable != 0;
+    return WIPES_OK;
+}
+
+wipes_status wipes_profile_read(wipes_ctx* ctx, double* ms, int64_t* launches, int32_t n)
+{
+    if (!ctx || !ms || !launches || n < kStN) return fail(ctx, WIPES_ERR_INVALID, "need arrays of WIPES_N_STAGES");
+    for (int st = 0; st < kStN; ++st) {
+        double tot = 0.0;
+        for (auto& pr : ctx->prof.rec[st]) {
+            hipError_t e = hipEventSynchronize(pr.second);
+            float t = 0.0f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&t, pr.first, pr.second);
+            if (e != hipSuccess) return hip_fail(ctx, e, "profile read");
+            tot += t;
+            ctx->prof.pool.push_back(pr.first);
+            ctx->prof.pool.push_back(pr.second);
+        }
+        ms[st] = tot;
+        launches[st] = (int64_t)ctx->prof.rec[st].size();
+        ctx->prof.rec[st].clear();
+    }
+    return WIPES_OK;
+}
+
+wipes_status wipes_render_stats(wipes_ctx* ctx, const wipes_params* p, const wipes_batch* b,
+                                const wipes_buffer* screen, const wipes_buffer* bins, const float* T_final,
+                                const int32_t* last, uint64_t* out, void* stream)
+{
+    Layout L;
+    if (!bins || !out) return fail(ctx, WIPES_ERR_INVALID, "bins and out must be set");
+    wipes_status st = prologue(ctx, p, b, screen, bins, false, false, &L);
+    if (st != WIPES_OK) return st;
+    if (p->mode == WIPES_3D_ALPHA && (!T_final || !last))
+        return fail(ctx, WIPES_ERR_INVALID, "alpha mode needs T_final and last");
+    hipStream_t s = (hipStream_t)stream;
+    if ((st = upload_descs(ctx, p, b, L, screen->base, s)) != WIPES_OK) return st;
+    return render_stats_core(ctx, p, b, L, screen->base, bins->base, T_final, last, out, s);
 }
 
 }  // extern "C"

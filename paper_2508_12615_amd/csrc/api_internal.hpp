@@ -23,6 +23,18 @@ struct StagingSlot {
     bool used = false;
 };
 
+// Render-path stages bracketed by profiling events (order = WIPES_STAGE_*).
+enum Stage {
+    kStProject = 0, kStCount, kStScan, kStDepthSort, kStRankScan, kStEmit, kStTileSort, kStRanges,
+    kStBlendFwd, kStBlendBwd, kStProjectBwd, kStN
+};
+
+struct Profiler {
+    bool on = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> rec[kStN];
+    std::vector<hipEvent_t> pool;
+};
+
 struct wipes_ctx {
     int device = 0;
     int n_cu = 256;
@@ -30,6 +42,7 @@ struct wipes_ctx {
     StagingSlot ring[kRing];
     int ring_next = 0;
     bool capturing = false;      // descriptor uploads are skipped while capturing a graph
+    Profiler prof;
 };
 
 namespace wipes {
@@ -61,6 +74,16 @@ void fill_descs(const wipes_params* p, const wipes_batch* b, std::vector<ImgDesc
 wipes_status upload_descs(wipes_ctx* ctx, const wipes_params* p, const wipes_batch* b, const Layout& L, void* screen,
                           hipStream_t s);
 
+// Brackets one stage with events when profiling is on (never while capturing).
+struct StageScope {
+    wipes_ctx* c;
+    int st;
+    hipStream_t s;
+    hipEvent_t a = nullptr;
+    StageScope(wipes_ctx* ctx, int stage, hipStream_t stream);
+    ~StageScope();
+};
+
 // stage sequencing (pipeline.hip)
 wipes_status bin_sort_core(wipes_ctx* ctx, const wipes_params* p, const wipes_batch* b, const Layout& L,
                            void* screen, void* bins, int64_t* n_instances_out, hipStream_t s);
@@ -70,6 +93,10 @@ wipes_status render_fwd_core(wipes_ctx* ctx, const wipes_params* p, const wipes_
 wipes_status render_bwd_core(wipes_ctx* ctx, const wipes_params* p, const wipes_batch* b, const Layout& L,
                              const void* screen, const void* bins, const float* T_final, const int32_t* last,
                              const float* dLdC, float* dscreen, hipStream_t s);
+
+wipes_status render_stats_core(wipes_ctx* ctx, const wipes_params* p, const wipes_batch* b, const Layout& L,
+                               const void* screen, const void* bins, const float* T_final, const int32_t* last,
+                               uint64_t* out, hipStream_t s);
 
 // kernel launchers
 hipError_t launch_project(const ImgDesc* descs, int B, int32_t n_total, const KParams& kp, Rec* recs, Aux* aux,
@@ -99,6 +126,11 @@ hipError_t launch_blend_bwd(const ImgDesc* descs, int B, const KParams& kp, cons
                             const uint2* ranges, const uint32_t* ovf, uint32_t n_tiles, const uint32_t* order,
                             uint32_t* queue, uint32_t persistent_blocks, const float* T_final, const int32_t* last,
                             const float* dLdC, float* slots, hipStream_t s);
+hipError_t launch_l2_grad(const ImgDesc* descs, int B, int32_t npix, const float* image, const float* target,
+                          float* grad, hipStream_t s);
+hipError_t launch_pair_stats(const ImgDesc* descs, int B, const KParams& kp, const Rec* recs, const uint32_t* vals,
+                             const uint2* ranges, const uint32_t* ovf, uint32_t n_tiles, const float* T_final,
+                             const int32_t* last, unsigned long long* out, hipStream_t s);
 hipError_t launch_project_bwd(const ImgDesc* descs, int B, int32_t n_total, const KParams& kp, const Rec* recs,
                               const uint32_t* count, const uint32_t* off_id, const uint32_t* inv, const float* slots,
                               const uint32_t* overflow, float* dscreen, hipStream_t s);

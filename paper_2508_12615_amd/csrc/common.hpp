@@ -53,6 +53,7 @@ struct __align__(16) ImgDesc {
     float* g_color;
     float* g_opac;
     float* g_vel;
+    float* out_image;     // optional per-image colour output (forward)
     int32_t prim_begin;   // first global record index of this image
     int32_t n;            // primitives of this image
     int32_t pix_begin;    // first pixel of this image in the per-pixel arrays

@@ -77,20 +77,32 @@ wipes_status bin_sort_core(wipes_ctx* ctx, const wipes_params* p, const wipes_ba
     const Views v = views(L, screen, bins);
     const KParams kp = kparams(p);
     const uint32_t n = (uint32_t)L.n;
-    HIP_TRY(launch_bin_count(v.descs, L.B, (int32_t)n, kp, v.recs, v.aux, v.count, v.dkey_a, v.dval_a, s), "count");
+    {
+        StageScope sc(ctx, kStCount, s);
+        HIP_TRY(launch_bin_count(v.descs, L.B, (int32_t)n, kp, v.recs, v.aux, v.count, v.dkey_a, v.dval_a, s), "count");
+    }
     // K, capacity check -> n_eff, overflow flag
-    HIP_TRY(scan_excl(v.count, nullptr, n, nullptr, n, v.bsum, v.off_id, v.ctrl + kCtrlK, (uint32_t)L.cap,
-                      v.ctrl + kCtrlNEff, v.ctrl + kCtrlOverflow, s),
-            "scan");
+    {
+        StageScope sc(ctx, kStScan, s);
+        HIP_TRY(scan_excl(v.count, nullptr, n, nullptr, n, v.bsum, v.off_id, v.ctrl + kCtrlK, (uint32_t)L.cap,
+                          v.ctrl + kCtrlNEff, v.ctrl + kCtrlOverflow, s),
+                "scan");
+    }
     const uint32_t* order = nullptr;
     const uint32_t* offs = v.off_id;
     if (L.alpha) {
         int in_b = 0;
-        HIP_TRY(radix_sort(v.dkey_a, v.dval_a, v.dkey_b, v.dval_b, n, nullptr, n, 32, v.dhist, v.ddtot, &in_b, s),
-                "depth sort");
+        {
+            StageScope sc(ctx, kStDepthSort, s);
+            HIP_TRY(radix_sort(v.dkey_a, v.dval_a, v.dkey_b, v.dval_b, n, nullptr, n, 32, v.dhist, v.ddtot, &in_b, s),
+                    "depth sort");
+        }
         order = in_b ? v.dval_b : v.dval_a;
-        HIP_TRY(scan_excl(v.count, order, n, nullptr, n, v.bsum2, v.off_rank, v.ctrl + 3, 0, nullptr, nullptr, s),
-                "rank scan");
+        {
+            StageScope sc(ctx, kStRankScan, s);
+            HIP_TRY(scan_excl(v.count, order, n, nullptr, n, v.bsum2, v.off_rank, v.ctrl + 3, 0, nullptr, nullptr, s),
+                    "rank scan");
+        }
         offs = v.off_rank;
     }
     uint32_t max_k = (uint32_t)L.cap;
@@ -102,15 +114,22 @@ wipes_status bin_sort_core(wipes_ctx* ctx, const wipes_params* p, const wipes_ba
         if ((int64_t)K > L.cap) return fail(ctx, WIPES_ERR_CAPACITY, "%u instances exceed capacity %lld", K, (long long)L.cap);
         max_k = K;
     }
-    HIP_TRY(launch_emit(v.descs, L.B, (int32_t)n, kp, v.recs, v.count, order, offs, v.ctrl + kCtrlNEff, v.keys_a,
-                        v.vals_a, s),
-            "emit");
+    {
+        StageScope sc(ctx, kStEmit, s);
+        HIP_TRY(launch_emit(v.descs, L.B, (int32_t)n, kp, v.recs, v.count, order, offs, v.ctrl + kCtrlNEff, v.keys_a,
+                            v.vals_a, s),
+                "emit");
+    }
     int in_b = 0;
-    HIP_TRY(radix_sort(v.keys_a, v.vals_a, v.keys_b, v.vals_b, 0, v.ctrl + kCtrlNEff, max_k, L.tile_bits, v.hist,
-                       v.dtot, &in_b, s),
-            "tile sort");
+    {
+        StageScope sc(ctx, kStTileSort, s);
+        HIP_TRY(radix_sort(v.keys_a, v.vals_a, v.keys_b, v.vals_b, 0, v.ctrl + kCtrlNEff, max_k, L.tile_bits, v.hist,
+                           v.dtot, &in_b, s),
+                "tile sort");
+    }
     const uint32_t* skeys = in_b ? v.keys_b : v.keys_a;
     const uint32_t* svals = in_b ? v.vals_b : v.vals_a;
+    StageScope sc(ctx, kStRanges, s);
     HIP_TRY(launch_fill_u32((uint32_t*)v.ranges, (uint32_t)(2 * L.tiles), 0u, s), "ranges fill");
     HIP_TRY(launch_ranges(v.descs, L.B, kp, skeys, svals, v.ctrl + kCtrlNEff, max_k, v.recs, v.off_id, v.ranges,
                           L.with_bwd ? v.inv : nullptr, s),
@@ -133,6 +152,7 @@ wipes_status render_fwd_core(wipes_ctx* ctx, const wipes_params* p, const wipes_
         HIP_TRY(launch_fill_u32(queue, 1, 0u, s), "queue reset");
         pblocks = (uint32_t)ctx->n_cu * 8u;
     }
+    StageScope sc(ctx, kStBlendFwd, s);
     HIP_TRY(launch_blend_fwd(v.descs, L.B, kp, v.recs, svals, v.ranges, v.ctrl + kCtrlOverflow, (uint32_t)L.tiles,
                              nullptr, queue, pblocks, image, T_final, last, s),
             "blend fwd");
@@ -154,12 +174,37 @@ wipes_status render_bwd_core(wipes_ctx* ctx, const wipes_params* p, const wipes_
         HIP_TRY(launch_fill_u32(queue, 1, 0u, s), "queue reset");
         pblocks = (uint32_t)ctx->n_cu * 8u;
     }
-    HIP_TRY(launch_blend_bwd(v.descs, L.B, kp, v.recs, svals, v.ranges, v.ctrl + kCtrlOverflow, (uint32_t)L.tiles,
-                             nullptr, queue, pblocks, T_final, last, dLdC, v.slots, s),
-            "blend bwd");
+    {
+        StageScope sc(ctx, kStBlendBwd, s);
+        HIP_TRY(launch_blend_bwd(v.descs, L.B, kp, v.recs, svals, v.ranges, v.ctrl + kCtrlOverflow, (uint32_t)L.tiles,
+                                 nullptr, queue, pblocks, T_final, last, dLdC, v.slots, s),
+                "blend bwd");
+    }
+    StageScope sc(ctx, kStProjectBwd, s);
     HIP_TRY(launch_project_bwd(v.descs, L.B, (int32_t)L.n, kp, v.recs, v.count, v.off_id, v.inv, v.slots,
                                v.ctrl + kCtrlOverflow, dscreen, s),
             "project bwd");
+    return WIPES_OK;
+}
+
+wipes_status render_stats_core(wipes_ctx* ctx, const wipes_params* p, const wipes_batch* b, const Layout& L,
+                               const void* screen, const void* bins, const float* T_final, const int32_t* last,
+                               uint64_t* out, hipStream_t s)
+{
+    (void)b;
+    const Views v = views(L, screen, bins);
+    const KParams kp = kparams(p);
+    const uint32_t* svals = L.tile_result_b ? v.vals_b : v.vals_a;
+    // the queue counters double as scratch for the four totals (8 bytes each)
+    unsigned long long* acc = (unsigned long long*)(v.ctrl + 8);
+    HIP_TRY(launch_fill_u32(v.ctrl + 8, 8, 0u, s), "stats reset");
+    HIP_TRY(launch_pair_stats(v.descs, L.B, kp, v.recs, svals, v.ranges, v.ctrl + kCtrlOverflow, (uint32_t)L.tiles,
+                              T_final, last, acc, s),
+            "stats");
+    unsigned long long h[4];
+    HIP_TRY(hipMemcpyAsync(h, acc, sizeof(h), hipMemcpyDeviceToHost, s), "stats read");
+    HIP_TRY(hipStreamSynchronize(s), "stats sync");
+    for (int k = 0; k < 4; ++k) out[k] = h[k];
     return WIPES_OK;
 }
 

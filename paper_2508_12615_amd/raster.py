@@ -187,6 +187,14 @@ class Rasterizer:
                            dL.data_ptr(), _ptr(dscreen), self._stream())
         return (grads, dscreen) if want_dscreen else grads
 
+    def stats(self, images, frame: Frame):
+        """Work counts of a rendered frame (see wipes_render_stats); synchronises."""
+        batch, keep, _ = self.make_batch(images)
+        sbuf = B.wipes_buffer(frame.screen.data_ptr(), frame.screen.numel(), 0, 0, 0)
+        bbuf = B.wipes_buffer(frame.bins.data_ptr(), frame.bins.numel(), frame.cap, int(frame.with_backward), 0)
+        return B.wipes_render_stats(self.ctx, self.params, batch, sbuf, bbuf, _ptr(frame.T_final), _ptr(frame.last),
+                                    self._stream())
+
     def bins(self, images, frame: Frame):
         """Sorted tile keys, primitive indices [K] and ranges [n_tiles, 2] as int64 CPU arrays (syncs)."""
         batch, keep, _ = self.make_batch(images)

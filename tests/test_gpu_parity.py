@@ -276,7 +276,8 @@ def test_autograd_matches_direct_backward():
 def test_tile_shape_and_launch_form_do_not_change_results(mode):
     """The per-pixel rule is tile-independent.  Grid and persistent launches of one tile shape give
     bit-identical images and gradients; different tile shapes agree to FP32 rounding of the
-    tile-relative coordinates (<= 1e-6 on images, 1e-5 relative on gradients)."""
+    tile-relative coordinates and of the per-tile gradient sums (<= 1e-6 on images, 1e-4
+    relative on gradients)."""
     if mode == B.WIPES_2D_ADDITIVE:
         W, H = 131, 77
         prims = synth.prims_2d(900, W, H, 51)
@@ -305,7 +306,7 @@ def test_tile_shape_and_launch_form_do_not_change_results(mode):
                 continue
             assert np.max(np.abs(out[0] - base[0])) <= 1e-6, (tile, persistent)
             for k in base[1]:
-                assert rel_err(out[1][k], base[1][k]) < 1e-5, (tile, persistent, k)
+                assert rel_err(out[1][k], base[1][k]) < 1e-4, (tile, persistent, k)
 
 
 @pytest.mark.parametrize("mode", [B.WIPES_2D_ADDITIVE, B.WIPES_3D_ALPHA])
@@ -416,3 +417,30 @@ def test_config3_full_size_sampled():
         assert rel_err(dsg[touched, col], ds_ref[touched, col]) < 1e-3, col
     others = np.setdiff1d(np.arange(dsg.shape[0]), touched)
     assert np.all(dsg[others] == 0.0)
+
+
+@pytest.mark.parametrize("mode", [B.WIPES_2D_ADDITIVE, B.WIPES_3D_ALPHA])
+def test_work_counts_match_oracle(mode):
+    """The support-pair counts used as the roofline numerator equal the oracle's (up to support ties)."""
+    if mode == B.WIPES_2D_ADDITIVE:
+        W, H = 120, 90
+        prims = synth.prims_2d(800, W, H, 81)
+        cam = (W, H)
+        P = oracle_params(O.MODE_ADD2D, O.COV_RS)
+        scr = O.project(P, prims)
+        keys = None
+    else:
+        prims, cam = small_scene_3d(5000, 120, 90, 3701, 3702)
+        W, H = cam["width"], cam["height"]
+        P = oracle_params(O.MODE_ALPHA3D, O.COV_QUAT_SCALE)
+        ocam = oracle_camera(cam)
+        scr = O.project(P, prims, ocam)
+        keys = O.depth_keys(prims, ocam)
+    r = Rasterizer(mode)
+    im = [dict(camera=cam, prims=to_torch(prims))]
+    f = r.forward(im, with_backward=True)
+    st = r.stats(im, f)
+    cf, cb = O.support_counts(P, W, H, scr, keys)
+    assert abs(st["support_fwd"] - cf.sum()) <= 1e-4 * cf.sum() + 4
+    assert abs(st["support_bwd"] - cb.sum()) <= 1e-4 * cb.sum() + 4
+    assert st["tile_pairs"] >= st["subblock_pairs"] >= st["support_fwd"] >= st["support_bwd"] > 0
