@@ -46,15 +46,126 @@ def parse():
     ap.add_argument("--tile", type=str, default="16x16")
     ap.add_argument("--persistent", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-crop", type=int, default=16, help="CPU baseline crop = 1/cpu-crop of the frame")
+    ap.add_argument("--extras", type=str, default="serve,batched,fit",
+                    help="comma list of secondary workloads to add to the JSON line (serve, batched, fit) or none")
+    ap.add_argument("--serve-requests", type=int, default=240)
+    ap.add_argument("--fit-steps", type=int, default=200)
     return ap.parse_args()
 
 
-def cpu_baseline(prims, cam, crop_div):
-    """The FP64 oracle on a bounded sample: projection of all primitives, then the
-    per-pixel rule forward + backward over a centred crop of 1/crop_div of the
-    frame (primitives whose support box misses the crop cannot touch it and are
-    dropped first), extrapolated to a full frame."""
+def bench_serving(n_req, log):
+    """Config 5: 8 resident scenes (0.1-2M primitives, linear motion), Poisson requests at
+    540p-1080p; the library's continuously batching server vs the plain rasterizer serving one
+    request at a time, at the same offered load (80 % of the plain rasterizer's capacity)."""
+    import torch
+    from paper_2508_12615_amd import binding as B
+    from paper_2508_12615_amd import synth
+    from paper_2508_12615_amd.raster import Rasterizer
+    from paper_2508_12615_amd.serve import Server, run_plain, run_served
+    dev = torch.device("cuda", 0)
+    scenes = [{k: torch.from_numpy(v).to(dev) for k, v in synth.serve_scene(s).items()} for s in range(8)]
+    log("serving: scenes ready")
+    probe = synth.serve_requests(48, 1000.0, seed_arrivals=5101, seed_poses=5201)
+    rast = Rasterizer(B.WIPES_3D_ALPHA, device=dev)
+    outs = [torch.empty((r["camera"]["height"], r["camera"]["width"], 3), device=dev) for r in probe]
+    for r in probe:
+        r["t_arrive"] = 0.0
+    run_plain(rast, scenes, probe[:8], outs[:8])                     # warm-up
+    lat, span = run_plain(rast, scenes, probe, outs)
+    service_ms = span * 1e3 / len(probe)
+    rate = 0.8 / (service_ms * 1e-3)
+    reqs = synth.serve_requests(n_req, rate)
+    outs = [torch.empty((r["camera"]["height"], r["camera"]["width"], 3), device=dev) for r in reqs]
+    lat_p, span_p = run_plain(rast, scenes, reqs, outs)
+    log("serving: plain done")
+    srv = Server(max_slots=16, max_batch=8, persistent=1, hbm_budget_bytes=4 << 30)
+    ids = [srv.load_scene(sc) for sc in scenes]
+    run_served(srv, ids, [dict(r, t_arrive=0.0) for r in probe[:16]], outs[:16])   # warm-up
+    srv.reset_stats()
+    lat_s, span_s = run_served(srv, ids, reqs, outs)
+    st = srv.stats()
+    srv.close()
+    log("serving: served done")
+    pct = lambda v, q: float(np.percentile(v, q))  # noqa: E731
+    return dict(workload="8 resident scenes of 0.1-2M wavelet primitives with linear motion, %d Poisson requests at "
+                         "%.0f/s (80%% of plain capacity), 960x540-1920x1080" % (n_req, rate),
+                plain_service_ms=service_ms,
+                served=dict(p50_ms=pct(lat_s, 50), p99_ms=pct(lat_s, 99), frames_per_s=n_req / span_s,
+                            mean_batch=st["mean_batch"], deferred=st["deferred"],
+                            arena_peak_mb=st["arena_peak_bytes"] / 2**20),
+                plain=dict(p50_ms=pct(lat_p, 50), p99_ms=pct(lat_p, 99), frames_per_s=n_req / span_p))
+
+
+def bench_batched(log):
+    """Config 4: 64 uneven 2D fits (256-1024 px sides, 2k-50k primitives), one fwd+L2+bwd step
+    as one hipGraph replay vs 64 plain per-image steps."""
+    import torch
+    from paper_2508_12615_amd import binding as B
+    from paper_2508_12615_amd import synth
+    from paper_2508_12615_amd.fit import BatchedFit
+    from paper_2508_12615_amd.raster import Rasterizer
+    dev = torch.device("cuda", 0)
+    ims = []
+    for im in synth.config4():
+        ims.append(dict(width=im["width"], height=im["height"], target=torch.from_numpy(im["target"]).to(dev),
+                        prims={k: torch.from_numpy(v).to(dev) for k, v in im["prims"].items()}))
+    log("batched: inputs ready")
+    fit = BatchedFit(ims, persistent=2)
+    for _ in range(3):
+        fit.render_grads()
+    torch.cuda.synchronize()
+    fit.check_capacity()
+    reps = 10
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        fit.render_grads()
+    torch.cuda.synchronize()
+    t_graph = (time.perf_counter() - t0) / reps
+    fit.check_capacity()
+    rast = Rasterizer(B.WIPES_2D_ADDITIVE, device=dev)
+    views = fit._image_views()
+    def plain_all():
+        for b, v in enumerate(views):
+            f = rast.forward([v], with_backward=True)
+            W, H = fit.sizes[b]
+            o = sum(w * h for (w, h) in fit.sizes[:b])
+            dL = 2.0 * (f.image - fit.target[o:o + W * H]) / (3 * W * H)
+            rast.backward([v], f, dL)
+    plain_all()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(2):
+        plain_all()
+    torch.cuda.synchronize()
+    t_plain = (time.perf_counter() - t0) / 2
+    fit.close()
+    npx = sum(w * h for (w, h) in fit.sizes)
+    return dict(workload="64 uneven 2D fits (%d pixels, %d primitives) fwd+L2+bwd" % (npx, int(fit.offsets[-1])),
+                graph_ms=t_graph * 1e3, plain_ms=t_plain * 1e3, images_per_s_graph=64 / t_graph,
+                images_per_s_plain=64 / t_plain, speedup=t_plain / t_graph)
+
+
+def bench_fit(steps, log):
+    """Config 2: 768x512 1/f texture with stripe patches, 70k primitives, Adam on the L2 loss."""
+    import torch
+    from paper_2508_12615_amd import synth
+    from paper_2508_12615_amd.fit import fit_plain
+    dev = torch.device("cuda", 0)
+    c = synth.config2()
+    target = torch.from_numpy(c["target"]).to(dev)
+    prims = {k: torch.from_numpy(v).to(dev) for k, v in c["prims"].items()}
+    fit_plain({k: v.clone() for k, v in prims.items()}, target, 5)
+    out = fit_plain(prims, target, steps)
+    log("fit: done")
+    return dict(workload="768x512 fit, 70k primitives, %d Adam steps" % steps, steps_per_s=steps / out["seconds"],
+                ms_per_step=out["seconds"] * 1e3 / steps, psnr_db=out["psnr"])
+
+
+def cpu_baseline(prims, cam):
+    """The FP64 oracle on the full frame: projection of every primitive, then the
+    per-pixel rule forward and backward in its support-scatter organisation
+    (O2: primitives in compositing order update the pixels of their support
+    boxes), on all host threads."""
     sys.path.insert(0, os.path.join(ROOT, "oracle"))
     sys.path.insert(0, os.path.join(ROOT, "tests"))
     import oracle as O
@@ -62,31 +173,20 @@ def cpu_baseline(prims, cam, crop_div):
     P = oracle_params(O.MODE_ALPHA3D, O.COV_QUAT_SCALE)
     ocam = oracle_camera(cam)
     W, H = cam["width"], cam["height"]
-    s = math.sqrt(crop_div)
-    cw, ch = int(round(W / s)), int(round(H / s))
-    x0, y0 = (W - cw) // 2, (H - ch) // 2
+    g = np.random.default_rng(1).normal(0, 1.0 / (3 * W * H), (H, W, 3))
     t0 = time.perf_counter()
     scr = O.project(P, prims, ocam)
     keys = O.depth_keys(prims, ocam)
-    t_proj = time.perf_counter() - t0
-    hit = (scr[:, 15] != 0) & (scr[:, 0] + scr[:, 12] + 0.02 >= x0) & (scr[:, 0] - scr[:, 12] - 0.02 <= x0 + cw) & \
-          (scr[:, 1] + scr[:, 13] + 0.02 >= y0) & (scr[:, 1] - scr[:, 13] - 0.02 <= y0 + ch)
-    idx = np.flatnonzero(hit)
-    sub = np.ascontiguousarray(scr[idx])
-    subkeys = np.ascontiguousarray(keys[idx])
-    ys, xs = np.mgrid[y0:y0 + ch, x0:x0 + cw]
-    pix = (ys * W + xs).reshape(-1).astype(np.int64)
-    g = np.random.default_rng(0).normal(0, 1, (pix.size, 3))
     t1 = time.perf_counter()
-    O.render_o1(P, W, H, sub, subkeys, pix=pix)
-    O.render_bwd_o1(P, W, H, sub, g, subkeys, pix=pix)
-    t_pix = time.perf_counter() - t1
-    frame_s = t_proj + t_pix * (W * H) / pix.size
-    return dict(value=1.0 / frame_s, unit="frames/s", cores=int(os.environ.get("OMP_NUM_THREADS", os.cpu_count())),
+    img, T, last, tie = O.render_o2(P, W, H, scr, keys)
+    t2 = time.perf_counter()
+    O.render_bwd_o2(P, W, H, scr, T, last, g, keys)
+    t3 = time.perf_counter()
+    return dict(value=1.0 / (t3 - t0), unit="frames/s", cores=int(os.environ.get("OMP_NUM_THREADS", os.cpu_count())),
                 kind="oracle",
-                sample="FP64 oracle: projection of all %d primitives (%.2f s) + per-pixel forward+backward over a "
-                       "centred %dx%d crop (1/%d of the frame, %d primitives reach it; %.2f s), extrapolated to the "
-                       "full frame" % (prims["opacity"].shape[0], t_proj, cw, ch, crop_div, idx.size, t_pix))
+                sample="full frame, %d primitives, %dx%d: FP64 projection %.2f s, forward %.2f s, backward %.2f s "
+                       "(support-scatter organisation of the oracle)" % (prims["opacity"].shape[0], W, H,
+                                                                         t1 - t0, t2 - t1, t3 - t2))
 
 
 def main():
@@ -158,9 +258,19 @@ def main():
                roofline_blend={k: alu_roof(k, stages["blend_" + k]) for k in ("fwd", "bwd")
                                if "blend_" + k in stages},
                work=stats)
-    print("gpu: %.3f ms/step, stages %s" % (ms_step, out["stages_ms"]), file=sys.stderr, flush=True)
+    log = lambda m: print(m, file=sys.stderr, flush=True)  # noqa: E731
+    log("gpu: %.3f ms/step, stages %s" % (ms_step, out["stages_ms"]))
+    del prims, r
+    torch.cuda.empty_cache()
+    extras = [] if a.extras == "none" else a.extras.split(",")
+    if "batched" in extras:
+        out["batched"] = bench_batched(log)
+    if "fit" in extras:
+        out["fit_loop"] = bench_fit(a.fit_steps, log)
+    if "serve" in extras:
+        out["serving"] = bench_serving(a.serve_requests, log)
     if not a.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(c["prims"], cam, a.cpu_crop)
+        out["cpu_baseline"] = cpu_baseline(c["prims"], cam)
     print(json.dumps(out), flush=True)
 
 

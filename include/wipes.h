@@ -84,7 +84,8 @@ typedef struct {
     int32_t freq_xform;   /* wipes_freq_xform */
     int32_t tile_w;       /* tile width in pixels: 8, 16 or 32 */
     int32_t tile_h;       /* tile height in pixels: 8 or 16; tile_w * tile_h in {64, 128, 256, 512} */
-    int32_t persistent;   /* 0: one wave per tile, grid launch; 1: persistent tile queue */
+    int32_t persistent;   /* 0: one wave per tile, grid launch; 1: persistent tile queue in tile
+                             order; 2: persistent queue, longest tile list first */
     float alpha_min;      /* 1/255: pairs with o W' below it are skipped (alpha) */
     float alpha_max;      /* 0.99: clamp of o W' (alpha) */
     float T_min;          /* 1e-4: termination threshold on transmittance (alpha) */
@@ -282,6 +283,24 @@ wipes_status wipes_graph_capture(wipes_ctx* ctx, const wipes_params* p, const wi
 /* Replay a captured step on a stream (asynchronous). */
 wipes_status wipes_graph_launch(wipes_graph* g, void* stream);
 void wipes_graph_destroy(wipes_graph* g);
+
+/* ------------------------------------------------------------ autotuning */
+
+/* Candidates the autotuner tries, in the order of its times_ms output:
+ * tile shapes 8x8, 16x8, 8x16, 16x16, 32x8, 32x16, each as a grid launch
+ * (persistent 0), a persistent queue in tile order (1) and a persistent queue
+ * longest list first (2).  Fills up to max entries; returns the count. */
+int32_t wipes_autotune_candidates(int32_t* tile_w, int32_t* tile_h, int32_t* persistent, int32_t max);
+
+/* Time the render path of this batch (project, bin/sort, forward, and the
+ * backward if with_backward) for every candidate, reps timed runs each after
+ * one warm-up, and copy p with the fastest tile shape and launch form into
+ * *best.  times_ms (optional) receives each candidate's mean.  Offline call:
+ * allocates and frees its own scratch and synchronises the stream.  The
+ * per-pixel rule is tile-independent, so every candidate renders the same
+ * image. */
+wipes_status wipes_autotune(wipes_ctx* ctx, const wipes_params* p, const wipes_batch* batch, int32_t with_backward,
+                            int32_t reps, wipes_params* best, double* times_ms, void* stream);
 
 /* --------------------------------------------------------------- serving */
 

@@ -117,7 +117,10 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        _lib = C.CDLL(build())
+        # WIPES_ORACLE_LIB points the harness at another build of the same source
+        # (used by the mutation tests, which plant mistakes in a temporary copy)
+        alt = os.environ.get("WIPES_ORACLE_LIB")
+        _lib = C.CDLL(alt if alt else build())
         P = C.c_void_p
         _lib.or_project.argtypes = [C.POINTER(_Params), C.POINTER(_Camera), C.c_int64] + [P] * 8 + [P]
         _lib.or_depth_keys.argtypes = [C.c_int64, P, P, C.c_float, P, P]

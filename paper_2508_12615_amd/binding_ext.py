@@ -20,6 +20,9 @@ def declare(L) -> None:
     P, PP = C.c_void_p, C.POINTER
     D, I64 = PP(C.c_double), PP(C.c_int64)
     table = {
+        "wipes_autotune_candidates": (C.c_int32, [P, P, P, C.c_int32]),
+        "wipes_autotune": (C.c_int, [P, PP(wipes_params), PP(wipes_batch), C.c_int32, C.c_int32, PP(wipes_params),
+                                     D, P]),
         "wipes_serve_create": (C.c_int, [PP(wipes_serve_config), PP(wipes_params), C.c_int32, PP(C.c_void_p)]),
         "wipes_serve_load_scene": (C.c_int, [P, PP(wipes_prims), PP(C.c_int32)]),
         "wipes_serve_unload_scene": (C.c_int, [P, C.c_int32]),

@@ -115,6 +115,20 @@ __global__ void __launch_bounds__(256) k_ranges(const ImgDesc* __restrict__ desc
     }
 }
 
+// Keys for a longest-list-first tile order: key = 2^24 - 1 - min(list length,
+// 2^24 - 1), value = tile; a stable ascending sort then lists long tiles first
+// (ties in tile order).
+__global__ void __launch_bounds__(256) k_tile_lpt_keys(const uint2* __restrict__ ranges, uint32_t n_tiles,
+                                                        uint32_t* __restrict__ keys, uint32_t* __restrict__ vals)
+{
+    const uint32_t t = blockIdx.x * 256u + threadIdx.x;
+    if (t >= n_tiles) return;
+    const uint2 r = ranges[t];
+    const uint32_t len = min(r.y - r.x, 0xffffffu);
+    keys[t] = 0xffffffu - len;
+    vals[t] = t;
+}
+
 // Fill kernel (used instead of memset so the sequence can live in a graph).
 __global__ void __launch_bounds__(256) k_fill_u32(uint32_t* __restrict__ p, uint32_t n, uint32_t v)
 {
@@ -142,6 +156,13 @@ hipError_t launch_emit(const ImgDesc* descs, int B, int32_t n_total, const KPara
     if (n_total > 0)
         hipLaunchKernelGGL(k_emit, dim3(blocks_of((uint32_t)n_total)), dim3(256), 0, s, descs, B, n_total, kp, recs,
                            count, order, offs, n_eff, keys, vals);
+    return hipGetLastError();
+}
+
+hipError_t launch_tile_lpt_keys(const uint2* ranges, uint32_t n_tiles, uint32_t* keys, uint32_t* vals, hipStream_t s)
+{
+    if (n_tiles > 0)
+        hipLaunchKernelGGL(k_tile_lpt_keys, dim3(blocks_of(n_tiles)), dim3(256), 0, s, ranges, n_tiles, keys, vals);
     return hipGetLastError();
 }
 

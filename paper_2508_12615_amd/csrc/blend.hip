@@ -490,6 +490,51 @@ __device__ __forceinline__ void wave_reduce16(float v[16])
     v[0] += __shfl_xor(v[0], 1, kWave);
 }
 
+// The same reduction on VALU cross-lane paths only (no LDS): gfx950's
+// permlane32/permlane16 swaps exchange the two halves / row pairs of two
+// registers in one instruction, and DPP row_mirror, row_half_mirror and
+// quad_perm pair lanes inside a 16-lane row.  Pairing lanes by a mirror flips
+// several low bits at once, which is still a valid butterfly as long as the
+// kept half is chosen by the bit the pairing flips last; the final layout is
+// the same as wave_reduce16's (lane l holds value (l >> 2) & 15).
+template <int CTRL>
+__device__ __forceinline__ float dpp_mov(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, false));
+}
+
+__device__ __forceinline__ void wave_reduce16_valu(float v[16])
+{
+    const int l = lane_id();
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {   // lanes 0-31 keep v[j], lanes 32-63 keep v[j + 8]
+        const auto r = __builtin_amdgcn_permlane32_swap(__float_as_int(v[j]), __float_as_int(v[j + 8]), false, false);
+        v[j] = __int_as_float(r[0]) + __int_as_float(r[1]);
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {   // even rows keep v[j], odd rows keep v[j + 4]
+        const auto r = __builtin_amdgcn_permlane16_swap(__float_as_int(v[j]), __float_as_int(v[j + 4]), false, false);
+        v[j] = __int_as_float(r[0]) + __int_as_float(r[1]);
+    }
+    {
+        const bool h = (l & 8) != 0;   // row_mirror pairs i with 15 - i
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const float a = v[j] + dpp_mov<0x140>(v[j]);
+            const float b = v[j + 2] + dpp_mov<0x140>(v[j + 2]);
+            v[j] = h ? b : a;
+        }
+    }
+    {
+        const bool h = (l & 4) != 0;   // row_half_mirror pairs i with 7 - i inside each half row
+        const float a = v[0] + dpp_mov<0x141>(v[0]);
+        const float b = v[1] + dpp_mov<0x141>(v[1]);
+        v[0] = h ? b : a;
+    }
+    v[0] += dpp_mov<0x4e>(v[0]);      // quad_perm [2, 3, 0, 1]
+    v[0] += dpp_mov<0xb1>(v[0]);      // quad_perm [1, 0, 3, 2]
+}
+
 // Gradient slot layout per instance: 12 floats, the first 11 used, in the
 // order d/d(mu'x, mu'y, ca, cb, cc, f'x, f'y, opacity, r, g, b).
 constexpr int kSlot = 12;
@@ -602,7 +647,7 @@ __device__ __forceinline__ void bwd_tile(const ImgDesc* __restrict__ descs, int 
         }
         float* o = slots + (size_t)s * kSlot;
         if (__ballot(any)) {
-            wave_reduce16(v);
+            wave_reduce16_valu(v);
             const int idx = l >> 2;
             if ((l & 3) == 0 && idx < kSlot) o[idx] = v[0];
         } else if (l < kSlot) {
@@ -746,7 +791,7 @@ __device__ __forceinline__ void bwd_tile_alpha(const ImgDesc* __restrict__ descs
         }
         float* o = slots + (size_t)s * kSlot;
         if (__ballot(any)) {
-            wave_reduce16(v);
+            wave_reduce16_valu(v);
             const int id = l >> 2;
             if ((l & 3) == 0 && id < kSlot) o[id] = v[0];
         } else if (l < kSlot) {

@@ -64,6 +64,14 @@ static Views views(const Layout& L, const void* screen, const void* bins)
     return v;
 }
 
+// Where the longest-first tile order lands: the sort ping-pongs between
+// order[nt..2nt) / order[2nt..3nt) (values) -- see bin_sort_core.
+static const uint32_t* tile_order(const Layout& L, const Views& v)
+{
+    const size_t nt = (size_t)L.tiles;
+    return L.order_result_b ? v.order + 3 * nt : v.order + nt;
+}
+
 #define HIP_TRY(call, what)                                    \
     do {                                                       \
         hipError_t e_ = (call);                                \
@@ -134,6 +142,16 @@ wipes_status bin_sort_core(wipes_ctx* ctx, const wipes_params* p, const wipes_ba
     HIP_TRY(launch_ranges(v.descs, L.B, kp, skeys, svals, v.ctrl + kCtrlNEff, max_k, v.recs, v.off_id, v.ranges,
                           L.with_bwd ? v.inv : nullptr, s),
             "ranges");
+    if (p->persistent == 2) {
+        // longest tile list first for the persistent queue
+        const uint32_t nt = (uint32_t)L.tiles;
+        uint32_t* ok = v.order;
+        uint32_t* ov = v.order + nt;
+        HIP_TRY(launch_tile_lpt_keys(v.ranges, nt, ok, ov, s), "lpt keys");
+        int in_b2 = 0;
+        HIP_TRY(radix_sort(ok, ov, ov + nt, ov + 2 * (size_t)nt, nt, nullptr, nt, 24, v.hist, v.dtot, &in_b2, s),
+                "lpt sort");
+    }
     return WIPES_OK;
 }
 
@@ -147,6 +165,7 @@ wipes_status render_fwd_core(wipes_ctx* ctx, const wipes_params* p, const wipes_
     const uint32_t* svals = L.tile_result_b ? v.vals_b : v.vals_a;
     uint32_t* queue = nullptr;
     uint32_t pblocks = 0;
+    const uint32_t* order = p->persistent == 2 ? tile_order(L, v) : nullptr;
     if (p->persistent) {
         queue = v.ctrl + kCtrlQueueFwd;
         HIP_TRY(launch_fill_u32(queue, 1, 0u, s), "queue reset");
@@ -154,7 +173,7 @@ wipes_status render_fwd_core(wipes_ctx* ctx, const wipes_params* p, const wipes_
     }
     StageScope sc(ctx, kStBlendFwd, s);
     HIP_TRY(launch_blend_fwd(v.descs, L.B, kp, v.recs, svals, v.ranges, v.ctrl + kCtrlOverflow, (uint32_t)L.tiles,
-                             nullptr, queue, pblocks, image, T_final, last, s),
+                             order, queue, pblocks, image, T_final, last, s),
             "blend fwd");
     return WIPES_OK;
 }
@@ -169,6 +188,7 @@ wipes_status render_bwd_core(wipes_ctx* ctx, const wipes_params* p, const wipes_
     const uint32_t* svals = L.tile_result_b ? v.vals_b : v.vals_a;
     uint32_t* queue = nullptr;
     uint32_t pblocks = 0;
+    const uint32_t* order = p->persistent == 2 ? tile_order(L, v) : nullptr;
     if (p->persistent) {
         queue = v.ctrl + kCtrlQueueBwd;
         HIP_TRY(launch_fill_u32(queue, 1, 0u, s), "queue reset");
@@ -177,7 +197,7 @@ wipes_status render_bwd_core(wipes_ctx* ctx, const wipes_params* p, const wipes_
     {
         StageScope sc(ctx, kStBlendBwd, s);
         HIP_TRY(launch_blend_bwd(v.descs, L.B, kp, v.recs, svals, v.ranges, v.ctrl + kCtrlOverflow, (uint32_t)L.tiles,
-                                 nullptr, queue, pblocks, T_final, last, dLdC, v.slots, s),
+                                 order, queue, pblocks, T_final, last, dLdC, v.slots, s),
                 "blend bwd");
     }
     StageScope sc(ctx, kStProjectBwd, s);

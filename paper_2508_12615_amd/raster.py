@@ -209,6 +209,59 @@ class Rasterizer:
         return view(kp, frame.K), view(vp, frame.K), view(rp, 2 * nt).reshape(nt, 2)
 
 
+# ------------------------------------------------------------------ autotuning
+
+def autotune_candidates():
+    n = B.lib().wipes_autotune_candidates(None, None, None, 0)
+    tw, th, pe = (C.c_int32 * n)(), (C.c_int32 * n)(), (C.c_int32 * n)()
+    B.lib().wipes_autotune_candidates(tw, th, pe, n)
+    return [(tw[i], th[i], pe[i]) for i in range(n)]
+
+
+def workload_signature(rast: Rasterizer, images, with_backward: bool) -> str:
+    """Key of the autotune cache: mode, image sizes and primitive counts (rounded to 2 significant digits)."""
+    def r2(x):
+        return 0 if x == 0 else int(float("%.2g" % x))
+    parts = ["m%d" % rast.params.mode, "b%d" % int(with_backward)]
+    for im in images:
+        cam = make_camera(im["camera"])
+        parts.append("%dx%d:%d" % (cam.width, cam.height, r2(int(im["prims"]["opacity"].shape[0]))))
+    return "|".join(parts)
+
+
+def autotune(rast: Rasterizer, images, with_backward: bool = True, reps: int = 3, cache_path: str | None = None):
+    """Time every tile shape / launch form on this workload (wipes_autotune), set the fastest
+    on `rast` and return {(tw, th, persistent): ms}.  Results are cached as JSON at cache_path."""
+    import json
+    import os
+    key = workload_signature(rast, images, with_backward)
+    if cache_path and os.path.exists(cache_path):
+        with open(cache_path) as fh:
+            cache = json.load(fh)
+        if key in cache:
+            tw, th, pe = cache[key]["best"]
+            rast.params.tile_w, rast.params.tile_h, rast.params.persistent = tw, th, pe
+            return {tuple(map(int, k.split(","))): v for k, v in cache[key]["times"].items()}
+    cands = autotune_candidates()
+    batch, keep, _ = rast.make_batch(images)
+    best = B.wipes_params()
+    times = (C.c_double * len(cands))()
+    B.check(B.lib().wipes_autotune(rast.ctx, C.byref(rast.params), C.byref(batch), int(bool(with_backward)), reps,
+                                   C.byref(best), times, rast._stream()), rast.ctx)
+    rast.params.tile_w, rast.params.tile_h, rast.params.persistent = best.tile_w, best.tile_h, best.persistent
+    out = {c: times[i] for i, c in enumerate(cands)}
+    if cache_path:
+        cache = {}
+        if os.path.exists(cache_path):
+            with open(cache_path) as fh:
+                cache = json.load(fh)
+        cache[key] = dict(best=[best.tile_w, best.tile_h, best.persistent],
+                          times={"%d,%d,%d" % c: t for c, t in out.items()})
+        with open(cache_path, "w") as fh:
+            json.dump(cache, fh, indent=1)
+    return out
+
+
 # ------------------------------------------------------------------ autograd
 
 class _RenderFn(torch.autograd.Function):

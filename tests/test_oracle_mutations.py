@@ -1,0 +1,56 @@
+"""The oracle's pins catch plausible mistakes.
+
+Each case copies wipes_oracle.c to a temporary directory, plants one mistake
+by replacing one expression, builds it, and runs the pins that are meant to
+catch it against that build (WIPES_ORACLE_LIB).  The pins must fail.  The
+mistakes live only in the temporary copy, on the CPU."""
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "oracle", "wipes_oracle.c")
+
+MUTATIONS = {
+    "dropped_half_of_carrier": ("pe->kappa = 0.5 * (1.0 + cos(pe->phi));", "pe->kappa = (1.0 + cos(pe->phi));",
+                                "test_pixel_sum_matches_poisson_closed_form"),
+    "phase_sign": ("pe->phi = s[SR_FX] * pe->dx + s[SR_FY] * pe->dy;", "pe->phi = s[SR_FX] * pe->dx - s[SR_FY] * pe->dy;",
+                   "test_pixel_sum_matches_poisson_closed_form or test_pixel_sum_gradient_closed_form"),
+    "transposed_conic": ("s[SR_CA] = Syy / det;\n    s[SR_CB] = -Sxy / det;\n    s[SR_CC] = Sxx / det;",
+                         "s[SR_CA] = Sxx / det;\n    s[SR_CB] = -Sxy / det;\n    s[SR_CC] = Syy / det;",
+                         "test_pixel_sum_matches_poisson_closed_form or test_zero_frequency_is_gaussian_image"),
+    "jacobian_column_sign": ("pj->J[2] = -cam->fx * uc / tz;", "pj->J[2] = cam->fx * uc / tz;",
+                             "test_projection_off_axis_matches_linearised_pinhole"),
+    "quaternion_order": ("R[1] = 2.0 * (x * y - w * z);", "R[1] = 2.0 * (x * y + w * z);",
+                         "test_projection_off_axis_matches_linearised_pinhole"),
+    "transmittance_update": ("T *= (1.0 - alpha);\n        if (fabs(T - P->T_min)", "T *= alpha;\n        if (fabs(T - P->T_min)",
+                             "test_alpha_two_primitives_order_and_ties or test_alpha_termination_count"),
+    "gradient_sign_of_mean": ("g[SG_MX] += dq * (-2.0 * Adx) + dphi * (-s[SR_FX]);",
+                              "g[SG_MX] += dq * (2.0 * Adx) + dphi * (-s[SR_FX]);",
+                              "test_fd_gradients_additive"),
+    "scale_gradient_factor": ("dscale[3 * i + k] = 2.0 * pj.sc[k] * acc;", "dscale[3 * i + k] = pj.sc[k] * acc;",
+                              "test_fd_gradients_alpha"),
+    "binning_rounding": ("float x0 = ceilf((x - ex) - 0.5f), x1 = floorf((x + ex) - 0.5f);",
+                         "float x0 = floorf((x - ex) - 0.5f), x1 = floorf((x + ex) - 0.5f);",
+                         "test_binning_brute_force"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(MUTATIONS))
+def test_pins_catch_planted_mistake(name, tmp_path):
+    old, new, selector = MUTATIONS[name]
+    src = open(SRC).read()
+    assert src.count(old) == 1, "mutation anchor must be unique: %s" % name
+    mutated = tmp_path / "wipes_oracle.c"
+    mutated.write_text(src.replace(old, new))
+    lib = tmp_path / "liboracle_mut.so"
+    subprocess.check_call(["gcc", "-O2", "-fopenmp", "-ffp-contract=off", "-fPIC", "-shared", "-std=c99", "-o",
+                           str(lib), str(mutated), "-lm"])
+    env = dict(os.environ, WIPES_ORACLE_LIB=str(lib), OMP_NUM_THREADS="4")
+    r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-p", "no:cacheprovider",
+                        os.path.join(ROOT, "tests", "test_oracle_pins.py"), "-k", selector],
+                       cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
+    assert r.returncode == 1, "pins did not catch %s:\n%s" % (name, r.stdout[-2000:])
+    assert "failed" in r.stdout
