@@ -169,7 +169,8 @@ Layout layout_of(const wipes_params* p, const wipes_batch* b, int64_t cap, int w
     L.b_order = take((size_t)L.tiles * 4 * 4);   // LPT order + sort scratch (4 arrays)
     L.b_tbsum = take((size_t)(nb_t + 1) * 4);
     if (with_bwd) {
-        L.b_inv = take((size_t)cap * 4);
+        L.b_w_a = take((size_t)cap * 4);
+        L.b_w_b = take((size_t)cap * 4);
         L.b_slots = take((size_t)cap * 48);
     }
     L.bins_bytes = o;

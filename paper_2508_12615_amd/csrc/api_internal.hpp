@@ -57,7 +57,7 @@ struct Layout {
     size_t s_recs, s_aux, s_count, s_off_id, s_dkey_a, s_dval_a, s_dkey_b, s_dval_b, s_off_rank, s_dhist, s_ddtot;
     size_t s_bsum, s_bsum2, s_ctrl, s_descs, screen_bytes;
     // bins buffer
-    size_t b_keys_a, b_vals_a, b_keys_b, b_vals_b, b_hist, b_dtot, b_ranges, b_order, b_tbsum, b_inv, b_slots;
+    size_t b_keys_a, b_vals_a, b_keys_b, b_vals_b, b_hist, b_dtot, b_ranges, b_order, b_tbsum, b_w_a, b_w_b, b_slots;
     size_t bins_bytes;
     int tile_bits = 1;
     int tile_result_b = 0;    // tile sort result in the *_b arrays
@@ -105,36 +105,36 @@ hipError_t launch_project(const ImgDesc* descs, int B, int32_t n_total, const KP
 hipError_t launch_bin_count(const ImgDesc* descs, int B, int32_t n_total, const KParams& kp, Rec* recs,
                             const void* aux, uint32_t* count, uint32_t* dkey, uint32_t* dval, hipStream_t s);
 hipError_t launch_emit(const ImgDesc* descs, int B, int32_t n_total, const KParams& kp, const Rec* recs,
-                       const uint32_t* count, const uint32_t* order, const uint32_t* offs, const uint32_t* n_eff,
-                       uint32_t* keys, uint32_t* vals, hipStream_t s);
+                       const uint32_t* count, const uint32_t* order, const uint32_t* offs, const uint32_t* off_id,
+                       const uint32_t* n_eff, uint32_t* keys, uint32_t* vals, uint32_t* eidx, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t n, uint32_t v, hipStream_t s);
 hipError_t launch_tile_lpt_keys(const uint2* ranges, uint32_t n_tiles, uint32_t* keys, uint32_t* vals, hipStream_t s);
-hipError_t launch_ranges(const ImgDesc* descs, int B, const KParams& kp, const uint32_t* keys, const uint32_t* vals,
-                         const uint32_t* n_eff, uint32_t max_k, const Rec* recs, const uint32_t* off_id,
-                         uint2* ranges, uint32_t* inv, hipStream_t s);
+hipError_t launch_ranges(const uint32_t* keys, const uint32_t* n_eff, uint32_t max_k, uint2* ranges, hipStream_t s);
 uint32_t scan_blocks(uint32_t max_n);
 hipError_t scan_excl(const uint32_t* vals, const uint32_t* gather, uint32_t n_host, const uint32_t* n_dev,
                      uint32_t max_n, uint32_t* block_sums, uint32_t* out, uint32_t* total, uint32_t cap,
                      uint32_t* n_eff, uint32_t* overflow, hipStream_t s);
 int radix_passes(int nbits);
+// Stable LSD sort of (key, value[, w]) over the low nbits of the keys; ping-pongs
+// between the *0 and *1 arrays, *result_in_1 tells where the result is.
 hipError_t radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, uint32_t n_host,
                       const uint32_t* n_dev, uint32_t max_n, int nbits, uint32_t* hist, uint32_t* dtot,
-                      int* result_in_1, hipStream_t s);
+                      int* result_in_1, hipStream_t s, uint32_t* w0 = nullptr, uint32_t* w1 = nullptr);
 hipError_t launch_blend_fwd(const ImgDesc* descs, int B, const KParams& kp, const Rec* recs, const uint32_t* vals,
                             const uint2* ranges, const uint32_t* ovf, uint32_t n_tiles, const uint32_t* order,
                             uint32_t* queue, uint32_t persistent_blocks, float* image, float* T_final, int32_t* last,
                             hipStream_t s);
 hipError_t launch_blend_bwd(const ImgDesc* descs, int B, const KParams& kp, const Rec* recs, const uint32_t* vals,
-                            const uint2* ranges, const uint32_t* ovf, uint32_t n_tiles, const uint32_t* order,
-                            uint32_t* queue, uint32_t persistent_blocks, const float* T_final, const int32_t* last,
-                            const float* dLdC, float* slots, hipStream_t s);
+                            const uint32_t* eidx, const uint2* ranges, const uint32_t* ovf, uint32_t n_tiles,
+                            const uint32_t* order, uint32_t* queue, uint32_t persistent_blocks, const float* T_final,
+                            const int32_t* last, const float* dLdC, float* slots, hipStream_t s);
 hipError_t launch_l2_grad(const ImgDesc* descs, int B, int32_t npix, const float* image, const float* target,
                           float* grad, hipStream_t s);
 hipError_t launch_pair_stats(const ImgDesc* descs, int B, const KParams& kp, const Rec* recs, const uint32_t* vals,
                              const uint2* ranges, const uint32_t* ovf, uint32_t n_tiles, const float* T_final,
                              const int32_t* last, unsigned long long* out, hipStream_t s);
 hipError_t launch_project_bwd(const ImgDesc* descs, int B, int32_t n_total, const KParams& kp, const Rec* recs,
-                              const uint32_t* count, const uint32_t* off_id, const uint32_t* inv, const float* slots,
+                              const uint32_t* count, const uint32_t* off_id, const float* slots,
                               const uint32_t* overflow, float* dscreen, hipStream_t s);
 
 }  // namespace wipes

@@ -1,5 +1,5 @@
-// Tile binning: pixel boxes, per-primitive tile counts, instance emission,
-// per-tile ranges and the instance -> sorted-position map used by the backward.
+// Tile binning: pixel boxes, per-primitive tile counts, instance emission and
+// per-tile ranges.
 //
 // The binning rule (a reading of the 3DGS-style pipeline the paper follows,
 // Sec. 4.1), in FP32 with exactly these operations so that it is reproducible:
@@ -60,14 +60,19 @@ __global__ void __launch_bounds__(256) k_bin_count(const ImgDesc* __restrict__ d
 }
 
 // One thread per primitive in emission order (order == NULL: index order).
-// Writes that primitive's instances at offs[r], tiles row-major.
+// Writes that primitive's instances at offs[r], tiles row-major.  With eidx
+// set, also the instance's index in primitive-index emission order,
+// off_id[prim] + (position in the tile rectangle): the slot the backward
+// writes that instance's gradients to, so the projection backward reads each
+// primitive's slots contiguously.
 __global__ void __launch_bounds__(256) k_emit(const ImgDesc* __restrict__ descs, int B, int32_t n_total,
                                                KParams kp, const Rec* __restrict__ recs,
                                                const uint32_t* __restrict__ count,
                                                const uint32_t* __restrict__ order,
                                                const uint32_t* __restrict__ offs,
+                                               const uint32_t* __restrict__ off_id,
                                                const uint32_t* __restrict__ n_eff, uint32_t* __restrict__ keys,
-                                               uint32_t* __restrict__ vals)
+                                               uint32_t* __restrict__ vals, uint32_t* __restrict__ eidx)
 {
     const int32_t r = (int32_t)(blockIdx.x * 256u + threadIdx.x);
     if (r >= n_total || *n_eff == 0u) return;
@@ -79,23 +84,21 @@ __global__ void __launch_bounds__(256) k_emit(const ImgDesc* __restrict__ descs,
     const int32_t tx0 = lo16(b0) >> kp.log2_tw, ty0 = hi16(b0) >> kp.log2_th;
     const int32_t tx1 = lo16(b1) >> kp.log2_tw, ty1 = hi16(b1) >> kp.log2_th;
     uint32_t k = offs[r];
+    const uint32_t e0 = eidx ? off_id[prim] : 0u;
+    uint32_t local = 0;
     for (int32_t ty = ty0; ty <= ty1; ++ty) {
         const uint32_t row = (uint32_t)(d.tile_begin + ty * d.tiles_x);
-        for (int32_t tx = tx0; tx <= tx1; ++tx, ++k) {
+        for (int32_t tx = tx0; tx <= tx1; ++tx, ++k, ++local) {
             keys[k] = row + (uint32_t)tx;
             vals[k] = prim;
+            if (eidx) eidx[k] = e0 + local;
         }
     }
 }
 
 // ranges[t] = [first, last + 1) of tile t in the sorted keys (pre-zeroed).
-// With inv != NULL also inv[off_id[prim] + local tile index] = sorted position.
-__global__ void __launch_bounds__(256) k_ranges(const ImgDesc* __restrict__ descs, int B, KParams kp,
-                                                 const uint32_t* __restrict__ keys,
-                                                 const uint32_t* __restrict__ vals,
-                                                 const uint32_t* __restrict__ n_eff, const Rec* __restrict__ recs,
-                                                 const uint32_t* __restrict__ off_id, uint2* __restrict__ ranges,
-                                                 uint32_t* __restrict__ inv)
+__global__ void __launch_bounds__(256) k_ranges(const uint32_t* __restrict__ keys,
+                                                 const uint32_t* __restrict__ n_eff, uint2* __restrict__ ranges)
 {
     const uint32_t s = blockIdx.x * 256u + threadIdx.x;
     const uint32_t K = *n_eff;
@@ -103,16 +106,6 @@ __global__ void __launch_bounds__(256) k_ranges(const ImgDesc* __restrict__ desc
     const uint32_t t = keys[s];
     if (s == 0 || keys[s - 1] != t) ranges[t].x = s;
     if (s == K - 1 || keys[s + 1] != t) ranges[t].y = s + 1;
-    if (inv) {
-        const uint32_t prim = vals[s];
-        const ImgDesc& d = descs[image_of_tile(descs, B, (int32_t)t)];
-        const int32_t lt = (int32_t)t - d.tile_begin;
-        const int32_t ty = lt / d.tiles_x, tx = lt - ty * d.tiles_x;
-        const uint32_t b0 = recs[prim].box0, b1 = recs[prim].box1;
-        const int32_t tx0 = lo16(b0) >> kp.log2_tw, ty0 = hi16(b0) >> kp.log2_th;
-        const int32_t tx1 = lo16(b1) >> kp.log2_tw;
-        inv[off_id[prim] + (uint32_t)((ty - ty0) * (tx1 - tx0 + 1) + (tx - tx0))] = s;
-    }
 }
 
 // Keys for a longest-list-first tile order: key = 2^24 - 1 - min(list length,
@@ -150,12 +143,12 @@ hipError_t launch_bin_count(const ImgDesc* descs, int B, int32_t n_total, const 
 }
 
 hipError_t launch_emit(const ImgDesc* descs, int B, int32_t n_total, const KParams& kp, const Rec* recs,
-                       const uint32_t* count, const uint32_t* order, const uint32_t* offs, const uint32_t* n_eff,
-                       uint32_t* keys, uint32_t* vals, hipStream_t s)
+                       const uint32_t* count, const uint32_t* order, const uint32_t* offs, const uint32_t* off_id,
+                       const uint32_t* n_eff, uint32_t* keys, uint32_t* vals, uint32_t* eidx, hipStream_t s)
 {
     if (n_total > 0)
         hipLaunchKernelGGL(k_emit, dim3(blocks_of((uint32_t)n_total)), dim3(256), 0, s, descs, B, n_total, kp, recs,
-                           count, order, offs, n_eff, keys, vals);
+                           count, order, offs, off_id, n_eff, keys, vals, eidx);
     return hipGetLastError();
 }
 
@@ -172,13 +165,9 @@ hipError_t launch_fill_u32(uint32_t* p, uint32_t n, uint32_t v, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_ranges(const ImgDesc* descs, int B, const KParams& kp, const uint32_t* keys, const uint32_t* vals,
-                         const uint32_t* n_eff, uint32_t max_k, const Rec* recs, const uint32_t* off_id,
-                         uint2* ranges, uint32_t* inv, hipStream_t s)
+hipError_t launch_ranges(const uint32_t* keys, const uint32_t* n_eff, uint32_t max_k, uint2* ranges, hipStream_t s)
 {
-    if (max_k > 0)
-        hipLaunchKernelGGL(k_ranges, dim3(blocks_of(max_k)), dim3(256), 0, s, descs, B, kp, keys, vals, n_eff, recs,
-                           off_id, ranges, inv);
+    if (max_k > 0) hipLaunchKernelGGL(k_ranges, dim3(blocks_of(max_k)), dim3(256), 0, s, keys, n_eff, ranges);
     return hipGetLastError();
 }
 

@@ -16,9 +16,11 @@
 //    exact to FP32 rounding of d itself;
 //  * the backward reduces the eleven per-pair gradients of a primitive over
 //    the wave with a halving butterfly (each step exchanges half the values),
-//    and writes them, without atomics, to a per-instance slot; the projection
-//    backward sums those slots per primitive in a fixed order, so gradients are
-//    deterministic and independent of the batch a primitive is rendered in.
+//    and writes them, without atomics, to the instance's slot -- slots are
+//    numbered in primitive order (the sort carries each instance's slot index),
+//    so the projection backward sums a primitive's slots from one contiguous
+//    run in a fixed order: gradients are deterministic and independent of the
+//    batch a primitive is rendered in.
 //
 // Per-pair rule (shared by forward and backward through eval_pair so their
 // FP32 decisions agree bit for bit):
@@ -542,7 +544,8 @@ constexpr int kSlot = 12;
 template <int MODE, int TW, int TH>
 __device__ __forceinline__ void bwd_tile(const ImgDesc* __restrict__ descs, int B, const KParams& kp,
                                          const Rec* __restrict__ recs, const uint32_t* __restrict__ vals,
-                                         const uint2* __restrict__ ranges, uint32_t t,
+                                         const uint32_t* __restrict__ eidx, const uint2* __restrict__ ranges,
+                                         uint32_t t,
                                          const float* __restrict__ T_final, const int32_t* __restrict__ last,
                                          const float* __restrict__ dLdC, float* __restrict__ slots)
 {
@@ -585,7 +588,7 @@ __device__ __forceinline__ void bwd_tile(const ImgDesc* __restrict__ descs, int 
     }
     // positions no pixel reached get zero gradient slots
     for (uint32_t s = s_hi + (uint32_t)l; s < G.end; s += kWave) {
-        float4* o = reinterpret_cast<float4*>(slots + (size_t)s * kSlot);
+        float4* o = reinterpret_cast<float4*>(slots + (size_t)eidx[s] * kSlot);
         o[0] = make_float4(0.f, 0.f, 0.f, 0.f);
         o[1] = make_float4(0.f, 0.f, 0.f, 0.f);
         o[2] = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -645,7 +648,7 @@ __device__ __forceinline__ void bwd_tile(const ImgDesc* __restrict__ descs, int 
             v[5] = fmaf(dph, p.dx, v[5]);
             v[6] = fmaf(dph, p.dy, v[6]);
         }
-        float* o = slots + (size_t)s * kSlot;
+        float* o = slots + (size_t)eidx[s] * kSlot;
         if (__ballot(any)) {
             wave_reduce16_valu(v);
             const int idx = l >> 2;
@@ -665,6 +668,7 @@ __device__ __forceinline__ void bwd_tile(const ImgDesc* __restrict__ descs, int 
 template <int TW, int TH>
 __device__ __forceinline__ void bwd_tile_alpha(const ImgDesc* __restrict__ descs, int B, const KParams& kp,
                                                const Rec* __restrict__ recs, const uint32_t* __restrict__ vals,
+                                               const uint32_t* __restrict__ eidx,
                                                const uint2* __restrict__ ranges, uint32_t t,
                                                const float* __restrict__ T_final, const int32_t* __restrict__ last,
                                                const float* __restrict__ dLdC, float* __restrict__ slots,
@@ -735,7 +739,7 @@ __device__ __forceinline__ void bwd_tile_alpha(const ImgDesc* __restrict__ descs
     }
     const uint32_t s_hi = (A > 0u) ? (uint32_t)rowmax[0] + 1u : G.start;
     for (uint32_t s = s_hi + (uint32_t)l; s < G.end; s += kWave) {
-        float4* o = reinterpret_cast<float4*>(slots + (size_t)s * kSlot);
+        float4* o = reinterpret_cast<float4*>(slots + (size_t)eidx[s] * kSlot);
         o[0] = make_float4(0.f, 0.f, 0.f, 0.f);
         o[1] = make_float4(0.f, 0.f, 0.f, 0.f);
         o[2] = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -789,7 +793,7 @@ __device__ __forceinline__ void bwd_tile_alpha(const ImgDesc* __restrict__ descs
             v[5] = fmaf(dph, p.dx, v[5]);
             v[6] = fmaf(dph, p.dy, v[6]);
         }
-        float* o = slots + (size_t)s * kSlot;
+        float* o = slots + (size_t)eidx[s] * kSlot;
         if (__ballot(any)) {
             wave_reduce16_valu(v);
             const int id = l >> 2;
@@ -804,6 +808,7 @@ template <int MODE, int TW, int TH>
 __global__ void __launch_bounds__(kWave * kWpb) k_blend_bwd(const ImgDesc* __restrict__ descs, int B, KParams kp,
                                                             const Rec* __restrict__ recs,
                                                             const uint32_t* __restrict__ vals,
+                                                            const uint32_t* __restrict__ eidx,
                                                             const uint2* __restrict__ ranges,
                                                             const uint32_t* __restrict__ ovf, uint32_t n_tiles,
                                                             const float* __restrict__ T_final,
@@ -816,15 +821,17 @@ __global__ void __launch_bounds__(kWave * kWpb) k_blend_bwd(const ImgDesc* __res
     const uint32_t t = grid_tile_of_wave();
     if (t >= n_tiles) return;
     if (MODE == WIPES_3D_ALPHA)
-        bwd_tile_alpha<TW, TH>(descs, B, kp, recs, vals, ranges, t, T_final, last, dLdC, slots, lds[threadIdx.x >> 6]);
+        bwd_tile_alpha<TW, TH>(descs, B, kp, recs, vals, eidx, ranges, t, T_final, last, dLdC, slots,
+                               lds[threadIdx.x >> 6]);
     else
-        bwd_tile<MODE, TW, TH>(descs, B, kp, recs, vals, ranges, t, T_final, last, dLdC, slots);
+        bwd_tile<MODE, TW, TH>(descs, B, kp, recs, vals, eidx, ranges, t, T_final, last, dLdC, slots);
 }
 
 template <int MODE, int TW, int TH>
 __global__ void __launch_bounds__(kWave * kWpb) k_blend_bwd_q(const ImgDesc* __restrict__ descs, int B, KParams kp,
                                                               const Rec* __restrict__ recs,
                                                               const uint32_t* __restrict__ vals,
+                                                              const uint32_t* __restrict__ eidx,
                                                               const uint2* __restrict__ ranges,
                                                               const uint32_t* __restrict__ ovf, uint32_t n_tiles,
                                                               const uint32_t* __restrict__ order,
@@ -843,10 +850,10 @@ __global__ void __launch_bounds__(kWave * kWpb) k_blend_bwd_q(const ImgDesc* __r
         if (idx >= n_tiles) break;
         const uint32_t t = order ? order[idx] : idx;
         if (MODE == WIPES_3D_ALPHA)
-            bwd_tile_alpha<TW, TH>(descs, B, kp, recs, vals, ranges, t, T_final, last, dLdC, slots,
+            bwd_tile_alpha<TW, TH>(descs, B, kp, recs, vals, eidx, ranges, t, T_final, last, dLdC, slots,
                                    lds[threadIdx.x >> 6]);
         else
-            bwd_tile<MODE, TW, TH>(descs, B, kp, recs, vals, ranges, t, T_final, last, dLdC, slots);
+            bwd_tile<MODE, TW, TH>(descs, B, kp, recs, vals, eidx, ranges, t, T_final, last, dLdC, slots);
     }
 }
 
@@ -944,20 +951,20 @@ static void launch_fwd_t(const ImgDesc* descs, int B, const KParams& kp, const R
 
 template <int MODE, int TW, int TH>
 static void launch_bwd_t(const ImgDesc* descs, int B, const KParams& kp, const Rec* recs, const uint32_t* vals,
-                         const uint2* ranges, const uint32_t* ovf, uint32_t n_tiles, const uint32_t* order,
-                         uint32_t* queue, uint32_t persistent_blocks, const float* T_final, const int32_t* last,
-                         const float* dLdC, float* slots, hipStream_t s)
+                         const uint32_t* eidx, const uint2* ranges, const uint32_t* ovf, uint32_t n_tiles,
+                         const uint32_t* order, uint32_t* queue, uint32_t persistent_blocks, const float* T_final,
+                         const int32_t* last, const float* dLdC, float* slots, hipStream_t s)
 {
     if (queue) {
         if (persistent_blocks == 0) return;
         hipLaunchKernelGGL((k_blend_bwd_q<MODE, TW, TH>), dim3(persistent_blocks), dim3(kWave * kWpb), 0, s, descs, B,
-                           kp, recs, vals, ranges, ovf, n_tiles, order, queue, T_final, last, dLdC, slots);
+                           kp, recs, vals, eidx, ranges, ovf, n_tiles, order, queue, T_final, last, dLdC, slots);
         return;
     }
     const uint32_t nb = (n_tiles + kWpb - 1) / kWpb;
     if (nb == 0) return;
     hipLaunchKernelGGL((k_blend_bwd<MODE, TW, TH>), dim3(nb), dim3(kWave * kWpb), 0, s, descs, B, kp, recs, vals,
-                       ranges, ovf, n_tiles, T_final, last, dLdC, slots);
+                       eidx, ranges, ovf, n_tiles, T_final, last, dLdC, slots);
 }
 
 #define WIPES_TILE_DISPATCH(FN, MODE, ...)                                          \
@@ -1009,15 +1016,15 @@ hipError_t launch_blend_fwd(const ImgDesc* descs, int B, const KParams& kp, cons
 }
 
 hipError_t launch_blend_bwd(const ImgDesc* descs, int B, const KParams& kp, const Rec* recs, const uint32_t* vals,
-                            const uint2* ranges, const uint32_t* ovf, uint32_t n_tiles, const uint32_t* order,
-                            uint32_t* queue, uint32_t persistent_blocks, const float* T_final, const int32_t* last,
-                            const float* dLdC, float* slots, hipStream_t s)
+                            const uint32_t* eidx, const uint2* ranges, const uint32_t* ovf, uint32_t n_tiles,
+                            const uint32_t* order, uint32_t* queue, uint32_t persistent_blocks, const float* T_final,
+                            const int32_t* last, const float* dLdC, float* slots, hipStream_t s)
 {
     if (kp.mode == WIPES_2D_ADDITIVE)
-        WIPES_TILE_DISPATCH(launch_bwd_t, WIPES_2D_ADDITIVE, descs, B, kp, recs, vals, ranges, ovf, n_tiles, order,
-                            queue, persistent_blocks, T_final, last, dLdC, slots, s);
+        WIPES_TILE_DISPATCH(launch_bwd_t, WIPES_2D_ADDITIVE, descs, B, kp, recs, vals, eidx, ranges, ovf, n_tiles,
+                            order, queue, persistent_blocks, T_final, last, dLdC, slots, s);
     else
-        WIPES_TILE_DISPATCH(launch_bwd_t, WIPES_3D_ALPHA, descs, B, kp, recs, vals, ranges, ovf, n_tiles, order,
+        WIPES_TILE_DISPATCH(launch_bwd_t, WIPES_3D_ALPHA, descs, B, kp, recs, vals, eidx, ranges, ovf, n_tiles, order,
                             queue, persistent_blocks, T_final, last, dLdC, slots, s);
     return hipGetLastError();
 }

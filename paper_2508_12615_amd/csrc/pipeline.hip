@@ -19,7 +19,7 @@ struct Views {
     Aux* aux;
     uint32_t *count, *off_id, *dkey_a, *dval_a, *dkey_b, *dval_b, *off_rank, *dhist, *ddtot, *bsum, *bsum2, *ctrl;
     ImgDesc* descs;
-    uint32_t *keys_a, *vals_a, *keys_b, *vals_b, *hist, *dtot, *order, *tbsum, *inv;
+    uint32_t *keys_a, *vals_a, *keys_b, *vals_b, *hist, *dtot, *order, *tbsum, *w_a, *w_b;
     uint2* ranges;
     float* slots;
 };
@@ -57,7 +57,8 @@ static Views views(const Layout& L, const void* screen, const void* bins)
         v.order = (uint32_t*)(b + L.b_order);
         v.tbsum = (uint32_t*)(b + L.b_tbsum);
         if (L.with_bwd) {
-            v.inv = (uint32_t*)(b + L.b_inv);
+            v.w_a = (uint32_t*)(b + L.b_w_a);
+            v.w_b = (uint32_t*)(b + L.b_w_b);
             v.slots = (float*)(b + L.b_slots);
         }
     }
@@ -124,24 +125,21 @@ wipes_status bin_sort_core(wipes_ctx* ctx, const wipes_params* p, const wipes_ba
     }
     {
         StageScope sc(ctx, kStEmit, s);
-        HIP_TRY(launch_emit(v.descs, L.B, (int32_t)n, kp, v.recs, v.count, order, offs, v.ctrl + kCtrlNEff, v.keys_a,
-                            v.vals_a, s),
+        HIP_TRY(launch_emit(v.descs, L.B, (int32_t)n, kp, v.recs, v.count, order, offs, v.off_id, v.ctrl + kCtrlNEff,
+                            v.keys_a, v.vals_a, v.w_a, s),
                 "emit");
     }
     int in_b = 0;
     {
         StageScope sc(ctx, kStTileSort, s);
         HIP_TRY(radix_sort(v.keys_a, v.vals_a, v.keys_b, v.vals_b, 0, v.ctrl + kCtrlNEff, max_k, L.tile_bits, v.hist,
-                           v.dtot, &in_b, s),
+                           v.dtot, &in_b, s, v.w_a, v.w_b),
                 "tile sort");
     }
     const uint32_t* skeys = in_b ? v.keys_b : v.keys_a;
-    const uint32_t* svals = in_b ? v.vals_b : v.vals_a;
     StageScope sc(ctx, kStRanges, s);
     HIP_TRY(launch_fill_u32((uint32_t*)v.ranges, (uint32_t)(2 * L.tiles), 0u, s), "ranges fill");
-    HIP_TRY(launch_ranges(v.descs, L.B, kp, skeys, svals, v.ctrl + kCtrlNEff, max_k, v.recs, v.off_id, v.ranges,
-                          L.with_bwd ? v.inv : nullptr, s),
-            "ranges");
+    HIP_TRY(launch_ranges(skeys, v.ctrl + kCtrlNEff, max_k, v.ranges, s), "ranges");
     if (p->persistent == 2) {
         // longest tile list first for the persistent queue
         const uint32_t nt = (uint32_t)L.tiles;
@@ -196,12 +194,13 @@ wipes_status render_bwd_core(wipes_ctx* ctx, const wipes_params* p, const wipes_
     }
     {
         StageScope sc(ctx, kStBlendBwd, s);
-        HIP_TRY(launch_blend_bwd(v.descs, L.B, kp, v.recs, svals, v.ranges, v.ctrl + kCtrlOverflow, (uint32_t)L.tiles,
-                                 order, queue, pblocks, T_final, last, dLdC, v.slots, s),
+        const uint32_t* seidx = L.tile_result_b ? v.w_b : v.w_a;
+        HIP_TRY(launch_blend_bwd(v.descs, L.B, kp, v.recs, svals, seidx, v.ranges, v.ctrl + kCtrlOverflow,
+                                 (uint32_t)L.tiles, order, queue, pblocks, T_final, last, dLdC, v.slots, s),
                 "blend bwd");
     }
     StageScope sc(ctx, kStProjectBwd, s);
-    HIP_TRY(launch_project_bwd(v.descs, L.B, (int32_t)L.n, kp, v.recs, v.count, v.off_id, v.inv, v.slots,
+    HIP_TRY(launch_project_bwd(v.descs, L.B, (int32_t)L.n, kp, v.recs, v.count, v.off_id, v.slots,
                                v.ctrl + kCtrlOverflow, dscreen, s),
             "project bwd");
     return WIPES_OK;

@@ -1,7 +1,8 @@
 // Projection backward: per primitive, sum the gradient slots of its instances
-// (in the fixed order of its tile rectangle, so the result does not depend on
-// launch order or on the batch) and apply the chain rule back to the
-// primitive's parameters.
+// -- stored contiguously at [off_id, off_id + count) in the order of its tile
+// rectangle, so the sum reads one run of memory and does not depend on launch
+// order or on the batch -- and apply the chain rule back to the primitive's
+// parameters.
 //
 // Screen-space gradient -> parameters:
 //   conic A = Sigma'^-1:  dL/dSigma' = -A (dL/dA) A, dL/dA = [[da, db/2], [db/2, dc]]
@@ -24,7 +25,6 @@ __global__ void __launch_bounds__(256) k_project_bwd(const ImgDesc* __restrict__
                                                       KParams kp, const Rec* __restrict__ recs,
                                                       const uint32_t* __restrict__ count,
                                                       const uint32_t* __restrict__ off_id,
-                                                      const uint32_t* __restrict__ inv,
                                                       const float* __restrict__ slots,
                                                       const uint32_t* __restrict__ overflow,
                                                       float* __restrict__ dscreen)
@@ -40,7 +40,7 @@ __global__ void __launch_bounds__(256) k_project_bwd(const ImgDesc* __restrict__
     if (c) {
         const uint32_t base = off_id[i];
         for (uint32_t e = 0; e < c; ++e) {
-            const float4* sl = reinterpret_cast<const float4*>(slots + (size_t)inv[base + e] * kSlotB);
+            const float4* sl = reinterpret_cast<const float4*>(slots + (size_t)(base + e) * kSlotB);
             const float4 a0 = sl[0], a1 = sl[1], a2 = sl[2];
             acc[0] += a0.x; acc[1] += a0.y; acc[2] += a0.z; acc[3] += a0.w;
             acc[4] += a1.x; acc[5] += a1.y; acc[6] += a1.z; acc[7] += a1.w;
@@ -207,12 +207,12 @@ __global__ void __launch_bounds__(256) k_project_bwd(const ImgDesc* __restrict__
 }
 
 hipError_t launch_project_bwd(const ImgDesc* descs, int B, int32_t n_total, const KParams& kp, const Rec* recs,
-                              const uint32_t* count, const uint32_t* off_id, const uint32_t* inv, const float* slots,
+                              const uint32_t* count, const uint32_t* off_id, const float* slots,
                               const uint32_t* overflow, float* dscreen, hipStream_t s)
 {
     if (n_total > 0)
         hipLaunchKernelGGL(k_project_bwd, dim3(((uint32_t)n_total + 255u) / 256u), dim3(256), 0, s, descs, B, n_total,
-                           kp, recs, count, off_id, inv, slots, overflow, dscreen);
+                           kp, recs, count, off_id, slots, overflow, dscreen);
     return hipGetLastError();
 }
 

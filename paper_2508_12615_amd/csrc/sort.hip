@@ -177,19 +177,23 @@ __global__ void __launch_bounds__(kBlock) k_radix_rowscan(uint32_t* __restrict__
     if (threadIdx.x == 0) dtot[blockIdx.x] = s_carry;
 }
 
-template <int BITS>
+// W: a second payload (w_in/w_out) is permuted with the values.
+template <int BITS, bool W>
 __global__ void __launch_bounds__(kBlock) k_radix_scatter(const uint32_t* __restrict__ keys_in,
-                                                          const uint32_t* __restrict__ vals_in, uint32_t n_host,
+                                                          const uint32_t* __restrict__ vals_in,
+                                                          const uint32_t* __restrict__ w_in, uint32_t n_host,
                                                           const uint32_t* __restrict__ n_dev, int shift,
                                                           uint32_t nblocks, const uint32_t* __restrict__ hist,
                                                           const uint32_t* __restrict__ dtot,
                                                           uint32_t* __restrict__ keys_out,
-                                                          uint32_t* __restrict__ vals_out)
+                                                          uint32_t* __restrict__ vals_out,
+                                                          uint32_t* __restrict__ w_out)
 {
     constexpr int ND = 1 << BITS;
     constexpr int NW = kBlock / kWave;
     __shared__ uint32_t s_keys[kTile];
     __shared__ uint32_t s_vals[kTile];
+    __shared__ uint32_t s_w[W ? kTile : 1];
     __shared__ uint32_t s_wcnt[NW][ND];
     __shared__ uint32_t s_dbase[ND];
     __shared__ uint32_t s_gbase[ND];
@@ -203,12 +207,13 @@ __global__ void __launch_bounds__(kBlock) k_radix_scatter(const uint32_t* __rest
 
     const uint32_t wbase = base + (uint32_t)w * (kTile / NW);
     const uint64_t lt_mask = (l == 0) ? 0ull : (~0ull >> (64 - l));
-    uint32_t k[kItems], v[kItems], rk[kItems];
+    uint32_t k[kItems], v[kItems], ww[W ? kItems : 1], rk[kItems];
     for (int j = 0; j < kItems; ++j) {
         const uint32_t i = wbase + j * kWave + l;
         const bool ok = i < n;
         k[j] = ok ? keys_in[i] : 0u;
         v[j] = ok ? vals_in[i] : 0u;
+        if (W) ww[j] = ok ? w_in[i] : 0u;
     }
     for (int j = 0; j < kItems; ++j) {
         const uint32_t i = wbase + j * kWave + l;
@@ -266,6 +271,7 @@ __global__ void __launch_bounds__(kBlock) k_radix_scatter(const uint32_t* __rest
             const uint32_t pos = s_dbase[dig] + s_wcnt[w][dig] + rk[j];
             s_keys[pos] = k[j];
             s_vals[pos] = v[j];
+            if (W) s_w[pos] = ww[j];
         }
     }
     __syncthreads();
@@ -276,6 +282,7 @@ __global__ void __launch_bounds__(kBlock) k_radix_scatter(const uint32_t* __rest
         const uint32_t g = s_gbase[dig] + (p - s_dbase[dig]);
         keys_out[g] = key;
         vals_out[g] = s_vals[p];
+        if (W) w_out[g] = s_w[p];
     }
 }
 
@@ -300,42 +307,48 @@ hipError_t scan_excl(const uint32_t* vals, const uint32_t* gather, uint32_t n_ho
 }
 
 template <int BITS>
-static void radix_pass(const uint32_t* ki, const uint32_t* vi, uint32_t* ko, uint32_t* vo, uint32_t n_host,
-                       const uint32_t* n_dev, uint32_t nb, int shift, uint32_t* hist, uint32_t* dtot, hipStream_t s)
+static void radix_pass(const uint32_t* ki, const uint32_t* vi, const uint32_t* wi, uint32_t* ko, uint32_t* vo,
+                       uint32_t* wo, uint32_t n_host, const uint32_t* n_dev, uint32_t nb, int shift, uint32_t* hist,
+                       uint32_t* dtot, hipStream_t s)
 {
     hipLaunchKernelGGL(k_radix_hist<BITS>, dim3(nb), dim3(kBlock), 0, s, ki, n_host, n_dev, shift, nb, hist);
     hipLaunchKernelGGL(k_radix_rowscan, dim3(1 << BITS), dim3(kBlock), 0, s, hist, nb, dtot);
-    hipLaunchKernelGGL(k_radix_scatter<BITS>, dim3(nb), dim3(kBlock), 0, s, ki, vi, n_host, n_dev, shift, nb, hist,
-                       dtot, ko, vo);
+    if (wi)
+        hipLaunchKernelGGL((k_radix_scatter<BITS, true>), dim3(nb), dim3(kBlock), 0, s, ki, vi, wi, n_host, n_dev,
+                           shift, nb, hist, dtot, ko, vo, wo);
+    else
+        hipLaunchKernelGGL((k_radix_scatter<BITS, false>), dim3(nb), dim3(kBlock), 0, s, ki, vi, nullptr, n_host,
+                           n_dev, shift, nb, hist, dtot, ko, vo, nullptr);
 }
 
 int radix_passes(int nbits) { return nbits <= 0 ? 0 : (nbits + 7) / 8; }
 
 hipError_t radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, uint32_t n_host,
                       const uint32_t* n_dev, uint32_t max_n, int nbits, uint32_t* hist, uint32_t* dtot,
-                      int* result_in_1, hipStream_t s)
+                      int* result_in_1, hipStream_t s, uint32_t* w0, uint32_t* w1)
 {
     const int np = radix_passes(nbits);
     *result_in_1 = 0;
     const uint32_t nb = scan_blocks(max_n);
     if (np == 0 || nb == 0) return hipGetLastError();
     const int bits = (nbits + np - 1) / np;
-    uint32_t *ki = k0, *vi = v0, *ko = k1, *vo = v1;
+    uint32_t *ki = k0, *vi = v0, *wi = w0, *ko = k1, *vo = v1, *wo = w1;
     for (int p = 0; p < np; ++p) {
         const int shift = p * bits;
         switch (bits) {
-        case 1: radix_pass<1>(ki, vi, ko, vo, n_host, n_dev, nb, shift, hist, dtot, s); break;
-        case 2: radix_pass<2>(ki, vi, ko, vo, n_host, n_dev, nb, shift, hist, dtot, s); break;
-        case 3: radix_pass<3>(ki, vi, ko, vo, n_host, n_dev, nb, shift, hist, dtot, s); break;
-        case 4: radix_pass<4>(ki, vi, ko, vo, n_host, n_dev, nb, shift, hist, dtot, s); break;
-        case 5: radix_pass<5>(ki, vi, ko, vo, n_host, n_dev, nb, shift, hist, dtot, s); break;
-        case 6: radix_pass<6>(ki, vi, ko, vo, n_host, n_dev, nb, shift, hist, dtot, s); break;
-        case 7: radix_pass<7>(ki, vi, ko, vo, n_host, n_dev, nb, shift, hist, dtot, s); break;
-        default: radix_pass<8>(ki, vi, ko, vo, n_host, n_dev, nb, shift, hist, dtot, s); break;
+        case 1: radix_pass<1>(ki, vi, wi, ko, vo, wo, n_host, n_dev, nb, shift, hist, dtot, s); break;
+        case 2: radix_pass<2>(ki, vi, wi, ko, vo, wo, n_host, n_dev, nb, shift, hist, dtot, s); break;
+        case 3: radix_pass<3>(ki, vi, wi, ko, vo, wo, n_host, n_dev, nb, shift, hist, dtot, s); break;
+        case 4: radix_pass<4>(ki, vi, wi, ko, vo, wo, n_host, n_dev, nb, shift, hist, dtot, s); break;
+        case 5: radix_pass<5>(ki, vi, wi, ko, vo, wo, n_host, n_dev, nb, shift, hist, dtot, s); break;
+        case 6: radix_pass<6>(ki, vi, wi, ko, vo, wo, n_host, n_dev, nb, shift, hist, dtot, s); break;
+        case 7: radix_pass<7>(ki, vi, wi, ko, vo, wo, n_host, n_dev, nb, shift, hist, dtot, s); break;
+        default: radix_pass<8>(ki, vi, wi, ko, vo, wo, n_host, n_dev, nb, shift, hist, dtot, s); break;
         }
         uint32_t* t;
         t = ki; ki = ko; ko = t;
         t = vi; vi = vo; vo = t;
+        t = wi; wi = wo; wo = t;
     }
     *result_in_1 = (np & 1);
     return hipGetLastError();
