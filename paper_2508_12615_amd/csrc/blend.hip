@@ -1,12 +1,13 @@
 // Per-tile blending of wavelet primitives, forward and backward, for gfx950.
 //
-// Work decomposition (CDNA4-first, no LDS, no workgroup barriers):
+// Work decomposition (CDNA4-first, no workgroup barriers):
 //  * one 64-lane wave owns one TW x TH tile; the tile is split into 8 x 8
 //    sub-blocks and lane l owns pixel (l & 7, l >> 3) of every sub-block, so
 //    a lane carries TW*TH/64 pixels;
 //  * the wave walks the tile's sorted primitive list with wave-uniform
 //    indices, so the list entries and the 64-byte records arrive through the
-//    scalar data cache straight into SGPRs -- nothing is staged in LDS;
+//    scalar data cache straight into SGPRs -- no record is staged in LDS (a
+//    small per-wave LDS buffer only repacks live pixels, see "pixel rows");
 //  * before touching pixels the wave intersects the primitive's pixel box with
 //    each sub-block (scalar integer compares) and skips sub-blocks it misses;
 //  * alpha mode keeps a uniform mask of sub-blocks that still have live
@@ -409,7 +410,7 @@ __global__ void __launch_bounds__(kWave * kWpb) k_blend_fwd(const ImgDesc* __res
                                                             float* __restrict__ image, float* __restrict__ T_final,
                                                             int32_t* __restrict__ last)
 {
-    __shared__ uint32_t lds[kWpb][TW * TH];
+    __shared__ __attribute__((aligned(16))) uint32_t lds[kWpb][TW * TH];
     if (*ovf) return;   // instance overflow: the sort produced nothing usable
     const uint32_t t = grid_tile_of_wave();
     if (t >= n_tiles) return;
@@ -431,7 +432,7 @@ __global__ void __launch_bounds__(kWave * kWpb) k_blend_fwd_q(const ImgDesc* __r
                                                               uint32_t* __restrict__ queue, float* __restrict__ image,
                                                               float* __restrict__ T_final, int32_t* __restrict__ last)
 {
-    __shared__ uint32_t lds[kWpb][TW * TH];
+    __shared__ __attribute__((aligned(16))) uint32_t lds[kWpb][TW * TH];
     if (*ovf) return;
     for (;;) {
         uint32_t idx = 0;
@@ -582,7 +583,9 @@ __device__ __forceinline__ void bwd_tile(const ImgDesc* __restrict__ descs, int 
     uint32_t s_hi;   // one past the last list position any pixel of the tile used
     if (MODE == WIPES_3D_ALPHA) {
         smax = __builtin_amdgcn_readfirstlane(wave_max_i32(smax));
-        s_hi = smax < (int32_t)G.start ? G.start : (uint32_t)smax + 1u;
+        // clamped to the tile's range, so a `last` from a mismatched forward
+        // can only give wrong gradients, never an access outside the list
+        s_hi = smax < (int32_t)G.start ? G.start : min((uint32_t)smax + 1u, G.end);
     } else {
         s_hi = G.end;
     }
@@ -737,7 +740,9 @@ __device__ __forceinline__ void bwd_tile_alpha(const ImgDesc* __restrict__ descs
         Sg[r] = kp.bg[0] * __uint_as_float(g0[r]) + kp.bg[1] * __uint_as_float(g1[r]) +
                 kp.bg[2] * __uint_as_float(g2[r]);
     }
-    const uint32_t s_hi = (A > 0u) ? (uint32_t)rowmax[0] + 1u : G.start;
+    // clamped to the tile's range (a `last` from a mismatched forward gives
+    // wrong gradients, never an access outside the list)
+    const uint32_t s_hi = (A > 0u && rowmax[0] >= (int32_t)G.start) ? min((uint32_t)rowmax[0] + 1u, G.end) : G.start;
     for (uint32_t s = s_hi + (uint32_t)l; s < G.end; s += kWave) {
         float4* o = reinterpret_cast<float4*>(slots + (size_t)eidx[s] * kSlot);
         o[0] = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -816,7 +821,7 @@ __global__ void __launch_bounds__(kWave * kWpb) k_blend_bwd(const ImgDesc* __res
                                                             const float* __restrict__ dLdC,
                                                             float* __restrict__ slots)
 {
-    __shared__ uint32_t lds[kWpb][TW * TH];
+    __shared__ __attribute__((aligned(16))) uint32_t lds[kWpb][TW * TH];
     if (*ovf) return;
     const uint32_t t = grid_tile_of_wave();
     if (t >= n_tiles) return;
@@ -841,7 +846,7 @@ __global__ void __launch_bounds__(kWave * kWpb) k_blend_bwd_q(const ImgDesc* __r
                                                               const float* __restrict__ dLdC,
                                                               float* __restrict__ slots)
 {
-    __shared__ uint32_t lds[kWpb][TW * TH];
+    __shared__ __attribute__((aligned(16))) uint32_t lds[kWpb][TW * TH];
     if (*ovf) return;
     for (;;) {
         uint32_t idx = 0;
