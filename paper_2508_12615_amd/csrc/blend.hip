@@ -1,46 +1,61 @@
 // Per-tile blending of wavelet primitives, forward and backward, for gfx950.
 //
-// Work decomposition (CDNA4-first, no workgroup barriers):
-//  * one 64-lane wave owns one TW x TH tile; the tile is split into 8 x 8
-//    sub-blocks and lane l owns pixel (l & 7, l >> 3) of every sub-block, so
-//    a lane carries TW*TH/64 pixels;
-//  * the wave walks the tile's sorted primitive list with wave-uniform
-//    indices, so the list entries and the 64-byte records arrive through the
-//    scalar data cache straight into SGPRs -- no record is staged in LDS (a
-//    small per-wave LDS buffer only repacks live pixels, see "pixel rows");
-//  * before touching pixels the wave intersects the primitive's pixel box with
-//    each sub-block (scalar integer compares) and skips sub-blocks it misses;
-//  * alpha mode keeps a uniform mask of sub-blocks that still have live
-//    pixels (ballots) and leaves the list when none is left;
-//  * coordinates are made tile-relative once per primitive with the record's
-//    (hi, lo) mean, so d = p - mu' costs one subtraction per pixel and stays
-//    exact to FP32 rounding of d itself;
-//  * the backward reduces the eleven per-pair gradients of a primitive over
-//    the wave with a halving butterfly (each step exchanges half the values),
-//    and writes them, without atomics, to the instance's slot -- slots are
-//    numbered in primitive order (the sort carries each instance's slot index),
-//    so the projection backward sums a primitive's slots from one contiguous
-//    run in a fixed order: gradients are deterministic and independent of the
-//    batch a primitive is rendered in.
+// Paper: W' of Eq. 7 (Sec. 4.1) blended by Eq. 4 (additive, 2D fitting) or by
+// Eq. 3 (front-to-back alpha compositing, view synthesis).
 //
-// Per-pair rule (shared by forward and backward through eval_pair so their
-// FP32 decisions agree bit for bit):
-//   e2 = -q/2 log2(e) from the pre-scaled conic, E = exp2(e2),
-//   phase in revolutions ph = (f'/2pi).d, K = (1 + cos 2pi ph)/2, W' = K E.
-// Paper: W' of Eq. 7 (Sec. 4.1), blended by Eq. 4 (additive) or Eq. 3 (alpha).
+// Additive mode (every pixel sees its whole tile list, no early exit):
+//  * one 64-lane wave owns one TW x TH tile; the tile is split into 8 x 8
+//    sub-blocks and lane l owns pixel (l & 7, l >> 3) of every sub-block;
+//  * the wave walks the tile's sorted list with wave-uniform indices, so list
+//    entries and 64-byte records arrive through the scalar data cache straight
+//    into SGPRs; sub-blocks the primitive's pixel box misses are skipped with
+//    scalar integer compares.
+//
+// Alpha mode (lists are long and skewed -- a few tiles hold most instances --
+// and pixels stop early):
+//  * every 8 x 8 block of a tile gets its own wave (the tile is one
+//    workgroup), so the serial walk of a heavy tile is split four ways (16 x 16
+//    tiles) without lengthening the sort;
+//  * the wave walks the list in chunks of 64 entries: each lane gathers one
+//    entry's record (vector loads; the next chunk's entries and records are in
+//    flight while the current chunk blends), tests its pixel box against the
+//    bounding box of the block pixels still in play, and the hits are packed
+//    (ballot + prefix count) into a per-wave LDS stage holding their
+//    block-relative, pre-scaled values.  The wave then blends the staged
+//    primitives in list order; all lanes read the same LDS address, which the
+//    LDS broadcasts.  A primitive that misses the block costs one lane of one
+//    box test instead of a serial round trip through memory;
+//  * the forward shrinks the box as pixels terminate and leaves when none is
+//    left; the backward walks the same chunks top down (from the last
+//    contributing position of the tile) with all block waves in step, each
+//    wave reducing a primitive's eleven gradients over its block into LDS,
+//    and the workgroup sums the blocks in a fixed order into the instance's
+//    slot.
+//
+// Gradient slots are numbered in primitive order (the sort carries each
+// instance's slot index), so the projection backward sums a primitive's slots
+// from one contiguous run in a fixed order: gradients are deterministic,
+// atomic-free and independent of the batch a primitive is rendered in.
+//
+// Per-pair rule (shared by forward and backward so their FP32 decisions agree
+// bit for bit): e2 = -q/2 log2(e) from the pre-scaled conic, E = exp2(e2),
+// phase in revolutions ph = (f'/2pi).d, K = (1 + cos 2pi ph)/2, W' = K E.
 #include "common.hpp"
 
 namespace wipes {
 
-constexpr int kWpb = 4;   // waves (tiles) per workgroup
+constexpr int kWpb = 4;   // waves (tiles) per workgroup, additive mode
 
-struct PrimU {            // per-primitive, wave-uniform values
+// Per-primitive, wave-uniform values of the additive path.
+struct PrimU {
     float mrx, mry;       // mean relative to the tile origin
     float ca2, cb2, cc2;  // conic scaled by -log2(e)/2 (cb2 includes the factor 2)
     float fxr, fyr;       // frequency in revolutions per pixel
     float op, r, g, b;
     float ca, cb, cc, fx, fy;   // raw values for the backward
 };
+
+constexpr float kConicScale = -0.5f * kLog2e;
 
 __device__ __forceinline__ PrimU load_prim(const Rec* __restrict__ recs, uint32_t prim, int ox, int oy,
                                            uint32_t* box0, uint32_t* box1)
@@ -49,10 +64,9 @@ __device__ __forceinline__ PrimU load_prim(const Rec* __restrict__ recs, uint32_
     PrimU u;
     u.mrx = (R.mx - (float)ox) + R.mxl;
     u.mry = (R.my - (float)oy) + R.myl;
-    const float k = -0.5f * kLog2e;
-    u.ca2 = R.ca * k;
-    u.cb2 = R.cb * (2.0f * k);
-    u.cc2 = R.cc * k;
+    u.ca2 = R.ca * kConicScale;
+    u.cb2 = R.cb * (2.0f * kConicScale);
+    u.cc2 = R.cc * kConicScale;
     u.fxr = R.fx * kInv2Pi;
     u.fyr = R.fy * kInv2Pi;
     u.op = R.op;
@@ -67,18 +81,24 @@ struct PairEval {
     float dx, dy, e2, E, ph, K, W;
 };
 
-__device__ __forceinline__ PairEval eval_pair(const PrimU& u, float lx, float ly)
+__device__ __forceinline__ PairEval eval_at(float mrx, float mry, float ca2, float cb2, float cc2, float fxr, float fyr,
+                                            float lx, float ly)
 {
     PairEval p;
-    p.dx = lx - u.mrx;
-    p.dy = ly - u.mry;
-    const float t = fmaf(u.ca2, p.dx, u.cb2 * p.dy);
-    p.e2 = fmaf(t, p.dx, (u.cc2 * p.dy) * p.dy);
-    p.ph = fmaf(u.fxr, p.dx, u.fyr * p.dy);
+    p.dx = lx - mrx;
+    p.dy = ly - mry;
+    const float t = fmaf(ca2, p.dx, cb2 * p.dy);
+    p.e2 = fmaf(t, p.dx, (cc2 * p.dy) * p.dy);
+    p.ph = fmaf(fxr, p.dx, fyr * p.dy);
     p.E = __builtin_amdgcn_exp2f(p.e2);
     p.K = fmaf(0.5f, __builtin_amdgcn_cosf(__builtin_amdgcn_fractf(p.ph)), 0.5f);
     p.W = p.K * p.E;
     return p;
+}
+
+__device__ __forceinline__ PairEval eval_pair(const PrimU& u, float lx, float ly)
+{
+    return eval_at(u.mrx, u.mry, u.ca2, u.cb2, u.cc2, u.fxr, u.fyr, lx, ly);
 }
 
 // Sub-blocks (8 x 8) of a TW x TH tile hit by the pixel box, as a bit mask.
@@ -97,9 +117,10 @@ __device__ __forceinline__ uint32_t subblock_mask(uint32_t box0, uint32_t box1, 
     return m;
 }
 
-// Map a wave to its tile.  Grid mode remaps workgroups so that each of the 8
-// XCDs (which receive workgroups round-robin) walks a contiguous band of
-// tiles and its L2 sees the primitives of neighbouring tiles.
+// Map a wave to its tile (additive mode).  Workgroups are remapped so that
+// each of the 8 XCDs (which receive workgroups round-robin) walks a
+// contiguous band of tiles and its L2 sees the primitives of neighbouring
+// tiles; additive lists are roughly uniform, so bands do not unbalance XCDs.
 __device__ __forceinline__ uint32_t grid_tile_of_wave()
 {
     const uint32_t nb = gridDim.x, b = blockIdx.x;
@@ -132,74 +153,27 @@ __device__ __forceinline__ TileGeo tile_geo(const ImgDesc* __restrict__ descs, i
     return g;
 }
 
-// ------------------------------------------------------------ pixel rows
-//
-// Alpha mode keeps the tile's live pixels in "rows": row r, lane l holds one
-// pixel (packed local coordinates x | y << 8) or nothing (-1).  A row is only
-// evaluated against a primitive whose pixel box meets the row's bounding box
-// (wave-uniform, recomputed whenever rows are rebuilt).  Rows are rebuilt
-// through a per-wave LDS buffer of one word per tile pixel.
-
 __device__ __forceinline__ int32_t wave_min_i32(int32_t v)
 {
     for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, kWave));
     return v;
 }
 
-struct RowBox {
-    int x0, y0, x1, y1;
-};
-
-// Bounding box of the occupied slots of one row (uniform); empty rows get an
-// inverted box that no primitive meets.
-__device__ __forceinline__ RowBox row_box(int32_t pk)
+// Orders this wave's LDS accesses (one wave's LDS instructions execute in
+// program order; the fences keep the compiler from moving them).
+__device__ __forceinline__ void wave_lds_sync()
 {
-    const bool on = pk >= 0;
-    const int x = pk & 255, y = pk >> 8;
-    RowBox b;
-    b.x0 = __builtin_amdgcn_readfirstlane(wave_min_i32(on ? x : 1 << 20));
-    b.y0 = __builtin_amdgcn_readfirstlane(wave_min_i32(on ? y : 1 << 20));
-    b.x1 = __builtin_amdgcn_readfirstlane(wave_max_i32(on ? x : -(1 << 20)));
-    b.y1 = __builtin_amdgcn_readfirstlane(wave_max_i32(on ? y : -(1 << 20)));
-    return b;
-}
-
-__device__ __forceinline__ bool box_meets(const RowBox& r, int x0, int y0, int x1, int y1)
-{
-    return x0 <= r.x1 && x1 >= r.x0 && y0 <= r.y1 && y1 >= r.y0;
-}
-
-// Move one per-slot value of the occupied slots (dst index idx[r]) to the
-// compacted layout: slot j = r * 64 + l of the first `rows_out` rows receives
-// the value with idx == j (j < count), or `fill`.
-template <int NR>
-__device__ __forceinline__ void route(uint32_t* lds, const bool on[NR], const uint32_t idx[NR], uint32_t v[NR],
-                                      int rows_in, int rows_out, uint32_t count, uint32_t fill)
-{
-#pragma unroll
-    for (int r = 0; r < NR; ++r)
-        if (r < rows_in && on[r]) lds[idx[r]] = v[r];
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    const uint32_t l = (uint32_t)lane_id();
-#pragma unroll
-    for (int r = 0; r < NR; ++r) {
-        const uint32_t j = (uint32_t)r * kWave + l;
-        v[r] = (r < rows_out && j < count) ? lds[j] : fill;
-    }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// ------------------------------------------------------------ forward
+// ------------------------------------------------------------ additive mode
 
-template <int MODE, int TW, int TH>
-__device__ __forceinline__ void fwd_tile(const ImgDesc* __restrict__ descs, int B, const KParams& kp,
-                                         const Rec* __restrict__ recs, const uint32_t* __restrict__ vals,
-                                         const uint2* __restrict__ ranges, uint32_t t, float* __restrict__ image,
-                                         float* __restrict__ T_final, int32_t* __restrict__ last)
+template <int TW, int TH>
+__device__ __forceinline__ void fwd_tile_add(const ImgDesc* __restrict__ descs, int B, const KParams& kp,
+                                             const Rec* __restrict__ recs, const uint32_t* __restrict__ vals,
+                                             const uint2* __restrict__ ranges, uint32_t t, float* __restrict__ image)
 {
     constexpr int SBX = TW / 8, NSB = (TW / 8) * (TH / 8);
     const TileGeo G = tile_geo(descs, B, ranges, t, TW, TH);
@@ -207,9 +181,7 @@ __device__ __forceinline__ void fwd_tile(const ImgDesc* __restrict__ descs, int 
     const int l = lane_id();
     float lx[NSB], ly[NSB];
     bool valid[NSB];
-    float C[NSB][3], T[NSB];
-    int32_t lst[NSB];
-    bool alive[NSB];
+    float C[NSB][3];
 #pragma unroll
     for (int k = 0; k < NSB; ++k) {
         const int px = (k % SBX) * 8 + (l & 7), py = (k / SBX) * 8 + (l >> 3);
@@ -217,60 +189,23 @@ __device__ __forceinline__ void fwd_tile(const ImgDesc* __restrict__ descs, int 
         ly[k] = (float)py + 0.5f;
         valid[k] = (G.ox + px) < d.W && (G.oy + py) < d.H;
         C[k][0] = C[k][1] = C[k][2] = 0.0f;
-        T[k] = 1.0f;
-        lst[k] = -1;
-        alive[k] = valid[k];
     }
-    uint32_t live = 0;
-#pragma unroll
-    for (int k = 0; k < NSB; ++k) live |= __ballot(alive[k]) ? (1u << k) : 0u;
-    const float thr2 = kp.q_add * (-0.5f * kLog2e);
-
+    const float thr2 = kp.q_add * kConicScale;
     for (uint32_t s = G.start; s < G.end; ++s) {
-        if (MODE == WIPES_3D_ALPHA && live == 0u) break;
         const uint32_t prim = vals[s];
         uint32_t b0, b1;
         const PrimU u = load_prim(recs, prim, G.ox, G.oy, &b0, &b1);
-        uint32_t m = subblock_mask<TW, TH>(b0, b1, G.ox, G.oy);
-        if (MODE == WIPES_3D_ALPHA) m &= live;
+        const uint32_t m = subblock_mask<TW, TH>(b0, b1, G.ox, G.oy);
         if (m == 0u) continue;
-        if (MODE == WIPES_2D_ADDITIVE) {
-            const float cr = u.r * u.op, cg = u.g * u.op, cb = u.b * u.op;
+        const float cr = u.r * u.op, cg = u.g * u.op, cb = u.b * u.op;
 #pragma unroll
-            for (int k = 0; k < NSB; ++k) {
-                if (!(m & (1u << k))) continue;
-                const PairEval p = eval_pair(u, lx[k], ly[k]);
-                const float w = p.e2 >= thr2 ? p.W : 0.0f;
-                C[k][0] = fmaf(cr, w, C[k][0]);
-                C[k][1] = fmaf(cg, w, C[k][1]);
-                C[k][2] = fmaf(cb, w, C[k][2]);
-            }
-        } else {
-            bool changed = false;
-#pragma unroll
-            for (int k = 0; k < NSB; ++k) {
-                if (!(m & (1u << k))) continue;
-                const PairEval p = eval_pair(u, lx[k], ly[k]);
-                const float a = u.op * p.W;
-                if (alive[k] && a >= kp.alpha_min) {
-                    const float al = fminf(a, kp.alpha_max);
-                    const float wt = T[k] * al;
-                    C[k][0] = fmaf(wt, u.r, C[k][0]);
-                    C[k][1] = fmaf(wt, u.g, C[k][1]);
-                    C[k][2] = fmaf(wt, u.b, C[k][2]);
-                    T[k] = T[k] * (1.0f - al);
-                    lst[k] = (int32_t)s;
-                    if (T[k] < kp.T_min) {
-                        alive[k] = false;
-                        changed = true;
-                    }
-                }
-            }
-            if (__ballot(changed)) {
-                live = 0;
-#pragma unroll
-                for (int k = 0; k < NSB; ++k) live |= __ballot(alive[k]) ? (1u << k) : 0u;
-            }
+        for (int k = 0; k < NSB; ++k) {
+            if (!(m & (1u << k))) continue;
+            const PairEval p = eval_pair(u, lx[k], ly[k]);
+            const float w = p.e2 >= thr2 ? p.W : 0.0f;
+            C[k][0] = fmaf(cr, w, C[k][0]);
+            C[k][1] = fmaf(cg, w, C[k][1]);
+            C[k][2] = fmaf(cb, w, C[k][2]);
         }
     }
 #pragma unroll
@@ -278,228 +213,267 @@ __device__ __forceinline__ void fwd_tile(const ImgDesc* __restrict__ descs, int 
         if (!valid[k]) continue;
         const int px = G.ox + (k % SBX) * 8 + (l & 7), py = G.oy + (k / SBX) * 8 + (l >> 3);
         const uint32_t pix = (uint32_t)d.pix_begin + (uint32_t)(py * d.W + px);
-        float c0 = C[k][0], c1 = C[k][1], c2 = C[k][2];
-        if (MODE == WIPES_3D_ALPHA) {
-            c0 = fmaf(T[k], kp.bg[0], c0);
-            c1 = fmaf(T[k], kp.bg[1], c1);
-            c2 = fmaf(T[k], kp.bg[2], c2);
-            if (T_final) T_final[pix] = T[k];
-            if (last) last[pix] = lst[k];
-        }
         float* o = d.out_image ? d.out_image + 3 * (pix - (uint32_t)d.pix_begin) : image + 3 * pix;
-        o[0] = c0;
-        o[1] = c1;
-        o[2] = c2;
+        o[0] = C[k][0];
+        o[1] = C[k][1];
+        o[2] = C[k][2];
     }
 }
 
-// Alpha forward with live-pixel compaction.  A pixel writes its outputs the
-// moment it terminates and leaves its row; whenever the live pixels fit in
-// fewer rows the wave repacks them (row-major order, so rows stay spatially
-// coherent) and recomputes the row boxes.  The wave leaves the list as soon as
-// no pixel is live.
 template <int TW, int TH>
-__device__ __forceinline__ void fwd_tile_alpha(const ImgDesc* __restrict__ descs, int B, const KParams& kp,
-                                               const Rec* __restrict__ recs, const uint32_t* __restrict__ vals,
-                                               const uint2* __restrict__ ranges, uint32_t t,
-                                               float* __restrict__ image, float* __restrict__ T_final,
-                                               int32_t* __restrict__ last, uint32_t* lds)
+__global__ void __launch_bounds__(kWave * kWpb) k_blend_fwd_add(const ImgDesc* __restrict__ descs, int B, KParams kp,
+                                                                const Rec* __restrict__ recs,
+                                                                const uint32_t* __restrict__ vals,
+                                                                const uint2* __restrict__ ranges,
+                                                                const uint32_t* __restrict__ ovf, uint32_t n_tiles,
+                                                                float* __restrict__ image)
 {
-    constexpr int SBX = TW / 8, NR = (TW / 8) * (TH / 8);
-    const TileGeo G = tile_geo(descs, B, ranges, t, TW, TH);
-    const ImgDesc& d = descs[G.b];
-    const int l = lane_id();
-    const uint64_t lt_mask = (l == 0) ? 0ull : (~0ull >> (64 - l));
-    uint32_t pk[NR], c0[NR], c1[NR], c2[NR], tt[NR], ls[NR];   // FP32 values travel as bits
-    RowBox rb[NR];
-    uint32_t A = 0;
-#pragma unroll
-    for (int r = 0; r < NR; ++r) {
-        const int px = (r % SBX) * 8 + (l & 7), py = (r / SBX) * 8 + (l >> 3);
-        const bool valid = (G.ox + px) < d.W && (G.oy + py) < d.H;
-        pk[r] = valid ? (uint32_t)(px | (py << 8)) : 0xffffffffu;
-        c0[r] = c1[r] = c2[r] = __float_as_uint(0.0f);
-        tt[r] = __float_as_uint(1.0f);
-        ls[r] = 0xffffffffu;
-        rb[r] = row_box((int32_t)pk[r]);
-        A += (uint32_t)__popcll(__ballot(valid));
-    }
-    int nrows = NR;
-
-    auto emit = [&](int r) {
-        const int px = (int)(pk[r] & 255u), py = (int)(pk[r] >> 8);
-        const uint32_t pix = (uint32_t)d.pix_begin + (uint32_t)((G.oy + py) * d.W + (G.ox + px));
-        const float T = __uint_as_float(tt[r]);
-        float* o = d.out_image ? d.out_image + 3 * (pix - (uint32_t)d.pix_begin) : image + 3 * pix;
-        o[0] = fmaf(T, kp.bg[0], __uint_as_float(c0[r]));
-        o[1] = fmaf(T, kp.bg[1], __uint_as_float(c1[r]));
-        o[2] = fmaf(T, kp.bg[2], __uint_as_float(c2[r]));
-        T_final[pix] = T;
-        last[pix] = (int32_t)ls[r];
-    };
-
-    for (uint32_t s = G.start; s < G.end && A > 0u; ++s) {
-        const uint32_t prim = vals[s];
-        uint32_t b0, b1;
-        const PrimU u = load_prim(recs, prim, G.ox, G.oy, &b0, &b1);
-        const int x0 = lo16(b0) - G.ox, y0 = hi16(b0) - G.oy, x1 = lo16(b1) - G.ox, y1 = hi16(b1) - G.oy;
-        bool died = false;
-#pragma unroll
-        for (int r = 0; r < NR; ++r) {
-            if (r >= nrows) break;
-            if (!box_meets(rb[r], x0, y0, x1, y1)) continue;
-            if ((int32_t)pk[r] < 0) continue;
-            const float lx = (float)(pk[r] & 255u) + 0.5f, ly = (float)(pk[r] >> 8) + 0.5f;
-            const PairEval p = eval_pair(u, lx, ly);
-            const float a = u.op * p.W;
-            if (a >= kp.alpha_min) {
-                const float al = fminf(a, kp.alpha_max);
-                const float T = __uint_as_float(tt[r]);
-                const float wt = T * al;
-                c0[r] = __float_as_uint(fmaf(wt, u.r, __uint_as_float(c0[r])));
-                c1[r] = __float_as_uint(fmaf(wt, u.g, __uint_as_float(c1[r])));
-                c2[r] = __float_as_uint(fmaf(wt, u.b, __uint_as_float(c2[r])));
-                const float Tn = T * (1.0f - al);
-                tt[r] = __float_as_uint(Tn);
-                ls[r] = s;
-                if (Tn < kp.T_min) {
-                    emit(r);
-                    pk[r] = 0xffffffffu;
-                    died = true;
-                }
-            }
-        }
-        if (!__ballot(died)) continue;
-        // live count per row; repack when fewer rows suffice
-        uint32_t idx[NR];
-        bool on[NR];
-        uint32_t base = 0;
-#pragma unroll
-        for (int r = 0; r < NR; ++r) {
-            on[r] = r < nrows && (int32_t)pk[r] >= 0;
-            const uint64_t m = __ballot(on[r]);
-            idx[r] = base + (uint32_t)__popcll(m & lt_mask);
-            base += (uint32_t)__popcll(m);
-        }
-        A = base;
-        const int want = (int)((A + kWave - 1) / kWave);
-        if (want < nrows) {
-            route<NR>(lds, on, idx, pk, nrows, want, A, 0xffffffffu);
-            route<NR>(lds, on, idx, c0, nrows, want, A, 0u);
-            route<NR>(lds, on, idx, c1, nrows, want, A, 0u);
-            route<NR>(lds, on, idx, c2, nrows, want, A, 0u);
-            route<NR>(lds, on, idx, tt, nrows, want, A, 0u);
-            route<NR>(lds, on, idx, ls, nrows, want, A, 0u);
-            nrows = want;
-#pragma unroll
-            for (int r = 0; r < NR; ++r)
-                if (r < nrows) rb[r] = row_box((int32_t)pk[r]);
-        }
-    }
-#pragma unroll
-    for (int r = 0; r < NR; ++r)
-        if (r < nrows && (int32_t)pk[r] >= 0) emit(r);
-}
-
-template <int MODE, int TW, int TH>
-__global__ void __launch_bounds__(kWave * kWpb) k_blend_fwd(const ImgDesc* __restrict__ descs, int B, KParams kp,
-                                                            const Rec* __restrict__ recs,
-                                                            const uint32_t* __restrict__ vals,
-                                                            const uint2* __restrict__ ranges,
-                                                            const uint32_t* __restrict__ ovf, uint32_t n_tiles,
-                                                            float* __restrict__ image, float* __restrict__ T_final,
-                                                            int32_t* __restrict__ last)
-{
-    __shared__ __attribute__((aligned(16))) uint32_t lds[kWpb][TW * TH];
     if (*ovf) return;   // instance overflow: the sort produced nothing usable
     const uint32_t t = grid_tile_of_wave();
     if (t >= n_tiles) return;
-    if (MODE == WIPES_3D_ALPHA)
-        fwd_tile_alpha<TW, TH>(descs, B, kp, recs, vals, ranges, t, image, T_final, last, lds[threadIdx.x >> 6]);
-    else
-        fwd_tile<MODE, TW, TH>(descs, B, kp, recs, vals, ranges, t, image, T_final, last);
+    fwd_tile_add<TW, TH>(descs, B, kp, recs, vals, ranges, t, image);
 }
 
 // Persistent variant: a grid sized to the machine pulls tiles from a queue
 // (longest list first when `order` is given) until it is empty.
-template <int MODE, int TW, int TH>
-__global__ void __launch_bounds__(kWave * kWpb) k_blend_fwd_q(const ImgDesc* __restrict__ descs, int B, KParams kp,
-                                                              const Rec* __restrict__ recs,
-                                                              const uint32_t* __restrict__ vals,
-                                                              const uint2* __restrict__ ranges,
-                                                              const uint32_t* __restrict__ ovf, uint32_t n_tiles,
-                                                              const uint32_t* __restrict__ order,
-                                                              uint32_t* __restrict__ queue, float* __restrict__ image,
-                                                              float* __restrict__ T_final, int32_t* __restrict__ last)
+template <int TW, int TH>
+__global__ void __launch_bounds__(kWave * kWpb) k_blend_fwd_add_q(const ImgDesc* __restrict__ descs, int B,
+                                                                  KParams kp, const Rec* __restrict__ recs,
+                                                                  const uint32_t* __restrict__ vals,
+                                                                  const uint2* __restrict__ ranges,
+                                                                  const uint32_t* __restrict__ ovf, uint32_t n_tiles,
+                                                                  const uint32_t* __restrict__ order,
+                                                                  uint32_t* __restrict__ queue,
+                                                                  float* __restrict__ image)
 {
-    __shared__ __attribute__((aligned(16))) uint32_t lds[kWpb][TW * TH];
     if (*ovf) return;
     for (;;) {
         uint32_t idx = 0;
         if (lane_id() == 0) idx = atomicAdd(queue, 1u);
         idx = (uint32_t)__builtin_amdgcn_readfirstlane((int)idx);
         if (idx >= n_tiles) break;
-        const uint32_t t = order ? order[idx] : idx;
-        if (MODE == WIPES_3D_ALPHA)
-            fwd_tile_alpha<TW, TH>(descs, B, kp, recs, vals, ranges, t, image, T_final, last, lds[threadIdx.x >> 6]);
-        else
-            fwd_tile<MODE, TW, TH>(descs, B, kp, recs, vals, ranges, t, image, T_final, last);
+        fwd_tile_add<TW, TH>(descs, B, kp, recs, vals, ranges, order ? order[idx] : idx, image);
     }
 }
 
-// ------------------------------------------------------------ backward
+// ------------------------------------------------------------ alpha mode
 
-// Sum 16 per-lane values over the wave.  Each step pairs lanes across one
-// bit, keeps half the values and adds the partner's copy of that half, so 16
-// values cost 8+4+2+1 exchanges instead of 16*6.  On return lane l holds, in
-// v[0], the wave total of value (l >> 2) & 15.
-__device__ __forceinline__ void wave_reduce16(float v[16])
+// One staged primitive (48 bytes).  The forward stages the conic and the
+// frequency pre-scaled as load_prim does; the backward stages them raw and
+// rebuilds the scaled values with the same operations, so both passes take
+// identical FP32 decisions.
+struct __align__(16) Staged {
+    float mrx, mry;     // mean relative to the block origin
+    float c0, c1, c2;   // conic
+    float f0, f1;       // frequency
+    float op, r, g, b;
+    uint32_t pos;       // list position
+};
+static_assert(sizeof(Staged) == 48, "staged record must be 48 bytes");
+
+struct PixBox {
+    int x0, y0, x1, y1;
+};
+
+// Bounding box (image pixels) of the lanes with `on` set, wave-uniform; an
+// empty set gives an inverted box that no primitive meets.
+__device__ __forceinline__ PixBox pix_box(bool on, int px, int py)
 {
-    const int l = lane_id();
-    {
-        const bool h = (l & 32) != 0;
-#pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            const float send = h ? v[j] : v[j + 8];
-            const float keep = h ? v[j + 8] : v[j];
-            v[j] = keep + __shfl_xor(send, 32, kWave);
-        }
-    }
-    {
-        const bool h = (l & 16) != 0;
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const float send = h ? v[j] : v[j + 4];
-            const float keep = h ? v[j + 4] : v[j];
-            v[j] = keep + __shfl_xor(send, 16, kWave);
-        }
-    }
-    {
-        const bool h = (l & 8) != 0;
-#pragma unroll
-        for (int j = 0; j < 2; ++j) {
-            const float send = h ? v[j] : v[j + 2];
-            const float keep = h ? v[j + 2] : v[j];
-            v[j] = keep + __shfl_xor(send, 8, kWave);
-        }
-    }
-    {
-        const bool h = (l & 4) != 0;
-        const float send = h ? v[0] : v[1];
-        const float keep = h ? v[1] : v[0];
-        v[0] = keep + __shfl_xor(send, 4, kWave);
-    }
-    v[0] += __shfl_xor(v[0], 2, kWave);
-    v[0] += __shfl_xor(v[0], 1, kWave);
+    PixBox b;
+    b.x0 = __builtin_amdgcn_readfirstlane(wave_min_i32(on ? px : 1 << 20));
+    b.y0 = __builtin_amdgcn_readfirstlane(wave_min_i32(on ? py : 1 << 20));
+    b.x1 = __builtin_amdgcn_readfirstlane(wave_max_i32(on ? px : -(1 << 20)));
+    b.y1 = __builtin_amdgcn_readfirstlane(wave_max_i32(on ? py : -(1 << 20)));
+    return b;
 }
 
-// The same reduction on VALU cross-lane paths only (no LDS): gfx950's
+__device__ __forceinline__ bool box_meets(uint32_t b0, uint32_t b1, const PixBox& q)
+{
+    return lo16(b0) <= q.x1 && lo16(b1) >= q.x0 && hi16(b0) <= q.y1 && hi16(b1) >= q.y0;
+}
+
+// box0 of a lane past the end of a chunk: x0 = y0 = 65535 lies beyond every
+// image (pixel coordinates stay below 2^15), so it meets no pixel box.
+constexpr uint32_t kNoBox = 0xffffffffu;
+
+__device__ __forceinline__ Staged stage_fwd(const Rec& R, int bx, int by, uint32_t pos)
+{
+    Staged w;
+    w.mrx = (R.mx - (float)bx) + R.mxl;
+    w.mry = (R.my - (float)by) + R.myl;
+    w.c0 = R.ca * kConicScale;
+    w.c1 = R.cb * (2.0f * kConicScale);
+    w.c2 = R.cc * kConicScale;
+    w.f0 = R.fx * kInv2Pi;
+    w.f1 = R.fy * kInv2Pi;
+    w.op = R.op;
+    w.r = R.r;
+    w.g = R.g;
+    w.b = R.b;
+    w.pos = pos;
+    return w;
+}
+
+__device__ __forceinline__ Staged stage_raw(const Rec& R, int bx, int by, uint32_t pos)
+{
+    Staged w;
+    w.mrx = (R.mx - (float)bx) + R.mxl;
+    w.mry = (R.my - (float)by) + R.myl;
+    w.c0 = R.ca;
+    w.c1 = R.cb;
+    w.c2 = R.cc;
+    w.f0 = R.fx;
+    w.f1 = R.fy;
+    w.op = R.op;
+    w.r = R.r;
+    w.g = R.g;
+    w.b = R.b;
+    w.pos = pos;
+    return w;
+}
+
+// Forward of one 8 x 8 block `blk` of tile t (one wave).
+template <int TW, int TH>
+__device__ __forceinline__ void fwd_block_alpha(const ImgDesc* __restrict__ descs, int B, const KParams& kp,
+                                                const Rec* __restrict__ recs, const uint32_t* __restrict__ vals,
+                                                const uint2* __restrict__ ranges, uint32_t t, int blk,
+                                                float* __restrict__ image, float* __restrict__ T_final,
+                                                int32_t* __restrict__ last, Staged* __restrict__ stage)
+{
+    const TileGeo G = tile_geo(descs, B, ranges, t, TW, TH);
+    const ImgDesc& d = descs[G.b];
+    const int l = lane_id();
+    const int bx = G.ox + (blk % (TW / 8)) * 8, by = G.oy + (blk / (TW / 8)) * 8;
+    const int px = bx + (l & 7), py = by + (l >> 3);
+    const bool valid = px < d.W && py < d.H;
+    if (__ballot(valid) == 0ull) return;   // block past the image edge
+    const float lx = (float)(l & 7) + 0.5f, ly = (float)(l >> 3) + 0.5f;
+    const uint64_t below = (1ull << l) - 1ull;
+    float C0 = 0.0f, C1 = 0.0f, C2 = 0.0f, T = 1.0f;
+    int32_t lst = -1;
+    bool alive = valid;
+    PixBox live = pix_box(alive, px, py);
+    if (G.start < G.end) {
+        const uint32_t e1 = G.end - 1u;
+        // records of the current chunk; list entries of the next one
+        Rec cur = recs[vals[min(G.start + (uint32_t)l, e1)]];
+        if (G.start + (uint32_t)l > e1) cur.box0 = kNoBox;
+        uint32_t pn = vals[min(G.start + (uint32_t)(kWave + l), e1)];
+        for (uint32_t c = G.start;;) {
+            const bool hit = box_meets(cur.box0, cur.box1, live);
+            const uint64_t m = __ballot(hit);
+            if (hit) stage[__popcll(m & below)] = stage_fwd(cur, bx, by, c + (uint32_t)l);
+            const uint32_t cn = c + kWave;
+            const bool more = cn < G.end;
+            Rec nx{};
+            if (more) {   // the next chunk is in flight while this one blends
+                nx = recs[pn];
+                if (cn + (uint32_t)l > e1) nx.box0 = kNoBox;
+                pn = vals[min(cn + (uint32_t)(kWave + l), e1)];
+            }
+            wave_lds_sync();
+            const int nh = __popcll(m);
+            bool left = true;
+            for (int j = 0; j < nh; ++j) {
+                const Staged S = stage[j];
+                const PairEval p = eval_at(S.mrx, S.mry, S.c0, S.c1, S.c2, S.f0, S.f1, lx, ly);
+                const float a = S.op * p.W;
+                bool died = false;
+                if (alive && a >= kp.alpha_min) {
+                    const float al = fminf(a, kp.alpha_max);
+                    const float wt = T * al;
+                    C0 = fmaf(wt, S.r, C0);
+                    C1 = fmaf(wt, S.g, C1);
+                    C2 = fmaf(wt, S.b, C2);
+                    T = T * (1.0f - al);
+                    lst = (int32_t)S.pos;
+                    if (T < kp.T_min) {
+                        alive = false;
+                        died = true;
+                    }
+                }
+                if (__ballot(died)) {
+                    if (__ballot(alive) == 0ull) {
+                        left = false;
+                        break;
+                    }
+                    live = pix_box(alive, px, py);
+                }
+            }
+            if (!left || !more) break;
+            wave_lds_sync();   // the stage is rewritten next
+            cur = nx;
+            c = cn;
+        }
+    }
+    if (valid) {
+        const uint32_t pix = (uint32_t)d.pix_begin + (uint32_t)(py * d.W + px);
+        float* o = d.out_image ? d.out_image + 3 * (pix - (uint32_t)d.pix_begin) : image + 3 * pix;
+        o[0] = fmaf(T, kp.bg[0], C0);
+        o[1] = fmaf(T, kp.bg[1], C1);
+        o[2] = fmaf(T, kp.bg[2], C2);
+        T_final[pix] = T;
+        last[pix] = lst;
+    }
+}
+
+// Grid form: one workgroup per tile, one wave per block.  Tiles map to
+// workgroups one to one, so the XCDs (which take workgroups round-robin)
+// share the heavy tiles of a cluster instead of one XCD taking a whole band.
+template <int TW, int TH>
+__global__ void __launch_bounds__(TW * TH) k_blend_fwd_alpha(const ImgDesc* __restrict__ descs, int B, KParams kp,
+                                                             const Rec* __restrict__ recs,
+                                                             const uint32_t* __restrict__ vals,
+                                                             const uint2* __restrict__ ranges,
+                                                             const uint32_t* __restrict__ ovf, uint32_t n_tiles,
+                                                             float* __restrict__ image, float* __restrict__ T_final,
+                                                             int32_t* __restrict__ last)
+{
+    __shared__ Staged stage[(TW / 8) * (TH / 8)][kWave];
+    if (*ovf) return;
+    const uint32_t t = blockIdx.x;
+    if (t >= n_tiles) return;
+    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    fwd_block_alpha<TW, TH>(descs, B, kp, recs, vals, ranges, t, w, image, T_final, last, stage[w]);
+}
+
+// Persistent form: every wave pulls (tile, block) items from a queue, tiles
+// in `order` (longest list first) when given.
+template <int TW, int TH>
+__global__ void __launch_bounds__(TW * TH) k_blend_fwd_alpha_q(const ImgDesc* __restrict__ descs, int B, KParams kp,
+                                                               const Rec* __restrict__ recs,
+                                                               const uint32_t* __restrict__ vals,
+                                                               const uint2* __restrict__ ranges,
+                                                               const uint32_t* __restrict__ ovf, uint32_t n_tiles,
+                                                               const uint32_t* __restrict__ order,
+                                                               uint32_t* __restrict__ queue,
+                                                               float* __restrict__ image, float* __restrict__ T_final,
+                                                               int32_t* __restrict__ last)
+{
+    constexpr uint32_t NB = (TW / 8) * (TH / 8);
+    __shared__ Staged stage[NB][kWave];
+    if (*ovf) return;
+    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    for (;;) {
+        uint32_t idx = 0;
+        if (lane_id() == 0) idx = atomicAdd(queue, 1u);
+        idx = (uint32_t)__builtin_amdgcn_readfirstlane((int)idx);
+        if (idx >= n_tiles * NB) break;
+        const uint32_t ti = idx / NB;
+        fwd_block_alpha<TW, TH>(descs, B, kp, recs, vals, ranges, order ? order[ti] : ti, (int)(idx - ti * NB), image,
+                                T_final, last, stage[w]);
+    }
+}
+
+// Sum 16 per-lane values over the wave with a halving butterfly on VALU
+// cross-lane paths only (no LDS round trips): each step pairs lanes, keeps
+// half the values and adds the partner's copy of that half.  gfx950's
 // permlane32/permlane16 swaps exchange the two halves / row pairs of two
 // registers in one instruction, and DPP row_mirror, row_half_mirror and
 // quad_perm pair lanes inside a 16-lane row.  Pairing lanes by a mirror flips
 // several low bits at once, which is still a valid butterfly as long as the
 // kept half is chosen by the bit the pairing flips last; the final layout is
-// the same as wave_reduce16's (lane l holds value (l >> 2) & 15).
+// lane l holds, in v[0], the wave total of value (l >> 2) & 15.
 template <int CTRL>
 __device__ __forceinline__ float dpp_mov(float v)
 {
@@ -538,66 +512,56 @@ __device__ __forceinline__ void wave_reduce16_valu(float v[16])
     v[0] += dpp_mov<0xb1>(v[0]);      // quad_perm [1, 0, 3, 2]
 }
 
+// ------------------------------------------------------------ backward
+
 // Gradient slot layout per instance: 12 floats, the first 11 used, in the
 // order d/d(mu'x, mu'y, ca, cb, cc, f'x, f'y, opacity, r, g, b).
 constexpr int kSlot = 12;
 
-template <int MODE, int TW, int TH>
-__device__ __forceinline__ void bwd_tile(const ImgDesc* __restrict__ descs, int B, const KParams& kp,
-                                         const Rec* __restrict__ recs, const uint32_t* __restrict__ vals,
-                                         const uint32_t* __restrict__ eidx, const uint2* __restrict__ ranges,
-                                         uint32_t t,
-                                         const float* __restrict__ T_final, const int32_t* __restrict__ last,
-                                         const float* __restrict__ dLdC, float* __restrict__ slots)
+// Per-pair gradient terms shared by both modes: dW = dL/dW' of the pair.
+__device__ __forceinline__ void pair_grads(float v[16], const PairEval& p, float dW, float ca, float cb, float cc,
+                                           float fx, float fy)
+{
+    const float sn = __builtin_amdgcn_sinf(__builtin_amdgcn_fractf(p.ph));
+    const float dq = dW * (-0.5f * p.W);             // dL/dq
+    const float dph = dW * (-0.5f * p.E * sn);       // dL/dphi (radians)
+    const float Adx = fmaf(ca, p.dx, cb * p.dy), Ady = fmaf(cb, p.dx, cc * p.dy);
+    v[0] = fmaf(-2.0f * dq, Adx, fmaf(-dph, fx, v[0]));
+    v[1] = fmaf(-2.0f * dq, Ady, fmaf(-dph, fy, v[1]));
+    v[2] = fmaf(dq * p.dx, p.dx, v[2]);
+    v[3] = fmaf(2.0f * dq * p.dx, p.dy, v[3]);
+    v[4] = fmaf(dq * p.dy, p.dy, v[4]);
+    v[5] = fmaf(dph, p.dx, v[5]);
+    v[6] = fmaf(dph, p.dy, v[6]);
+}
+
+template <int TW, int TH>
+__device__ __forceinline__ void bwd_tile_add(const ImgDesc* __restrict__ descs, int B, const KParams& kp,
+                                             const Rec* __restrict__ recs, const uint32_t* __restrict__ vals,
+                                             const uint32_t* __restrict__ eidx, const uint2* __restrict__ ranges,
+                                             uint32_t t, const float* __restrict__ dLdC, float* __restrict__ slots)
 {
     constexpr int SBX = TW / 8, NSB = (TW / 8) * (TH / 8);
     const TileGeo G = tile_geo(descs, B, ranges, t, TW, TH);
     const ImgDesc& d = descs[G.b];
     const int l = lane_id();
-    float lx[NSB], ly[NSB], g[NSB][3], T[NSB], Sg[NSB];
-    int32_t lst[NSB];
-    int32_t smax = -1;
+    float lx[NSB], ly[NSB], g[NSB][3];
+    bool ok[NSB];
     uint32_t sb_valid = 0;
 #pragma unroll
     for (int k = 0; k < NSB; ++k) {
         const int px = (k % SBX) * 8 + (l & 7), py = (k / SBX) * 8 + (l >> 3);
         lx[k] = (float)px + 0.5f;
         ly[k] = (float)py + 0.5f;
-        const bool ok = (G.ox + px) < d.W && (G.oy + py) < d.H;
+        ok[k] = (G.ox + px) < d.W && (G.oy + py) < d.H;
         const uint32_t pix = (uint32_t)d.pix_begin + (uint32_t)((G.oy + py) * d.W + (G.ox + px));
-        g[k][0] = ok ? dLdC[3 * pix] : 0.0f;
-        g[k][1] = ok ? dLdC[3 * pix + 1] : 0.0f;
-        g[k][2] = ok ? dLdC[3 * pix + 2] : 0.0f;
-        if (MODE == WIPES_3D_ALPHA) {
-            T[k] = ok ? T_final[pix] : 1.0f;
-            lst[k] = ok ? last[pix] : -1;
-            Sg[k] = kp.bg[0] * g[k][0] + kp.bg[1] * g[k][1] + kp.bg[2] * g[k][2];
-            smax = max(smax, lst[k]);
-        } else {
-            T[k] = 1.0f;
-            lst[k] = ok ? 0x7fffffff : -1;
-            Sg[k] = 0.0f;
-        }
-        sb_valid |= __ballot(ok) ? (1u << k) : 0u;
+        g[k][0] = ok[k] ? dLdC[3 * pix] : 0.0f;
+        g[k][1] = ok[k] ? dLdC[3 * pix + 1] : 0.0f;
+        g[k][2] = ok[k] ? dLdC[3 * pix + 2] : 0.0f;
+        sb_valid |= __ballot(ok[k]) ? (1u << k) : 0u;
     }
-    uint32_t s_hi;   // one past the last list position any pixel of the tile used
-    if (MODE == WIPES_3D_ALPHA) {
-        smax = __builtin_amdgcn_readfirstlane(wave_max_i32(smax));
-        // clamped to the tile's range, so a `last` from a mismatched forward
-        // can only give wrong gradients, never an access outside the list
-        s_hi = smax < (int32_t)G.start ? G.start : min((uint32_t)smax + 1u, G.end);
-    } else {
-        s_hi = G.end;
-    }
-    // positions no pixel reached get zero gradient slots
-    for (uint32_t s = s_hi + (uint32_t)l; s < G.end; s += kWave) {
-        float4* o = reinterpret_cast<float4*>(slots + (size_t)eidx[s] * kSlot);
-        o[0] = make_float4(0.f, 0.f, 0.f, 0.f);
-        o[1] = make_float4(0.f, 0.f, 0.f, 0.f);
-        o[2] = make_float4(0.f, 0.f, 0.f, 0.f);
-    }
-    const float thr2 = kp.q_add * (-0.5f * kLog2e);
-    for (uint32_t s = s_hi; s-- > G.start;) {
+    const float thr2 = kp.q_add * kConicScale;
+    for (uint32_t s = G.end; s-- > G.start;) {
         const uint32_t prim = vals[s];
         uint32_t b0, b1;
         const PrimU u = load_prim(recs, prim, G.ox, G.oy, &b0, &b1);
@@ -608,48 +572,17 @@ __device__ __forceinline__ void bwd_tile(const ImgDesc* __restrict__ descs, int 
         bool any = false;
 #pragma unroll
         for (int k = 0; k < NSB; ++k) {
-            if (!(m & (1u << k))) continue;
-            if ((int32_t)s > lst[k]) continue;
+            if (!(m & (1u << k)) || !ok[k]) continue;
             const PairEval p = eval_pair(u, lx[k], ly[k]);
-            float dW;   // dL/dW'
-            if (MODE == WIPES_2D_ADDITIVE) {
-                if (!(p.e2 >= thr2)) continue;
-                const float cg = u.r * g[k][0] + u.g * g[k][1] + u.b * g[k][2];
-                const float ow = u.op * p.W;
-                v[8] = fmaf(ow, g[k][0], v[8]);
-                v[9] = fmaf(ow, g[k][1], v[9]);
-                v[10] = fmaf(ow, g[k][2], v[10]);
-                v[7] = fmaf(p.W, cg, v[7]);
-                dW = u.op * cg;
-            } else {
-                const float a = u.op * p.W;
-                if (!(a >= kp.alpha_min)) continue;
-                const float al = fminf(a, kp.alpha_max);
-                const float Tb = T[k] / (1.0f - al);
-                const float cg = u.r * g[k][0] + u.g * g[k][1] + u.b * g[k][2];
-                const float dal = Tb * (cg - Sg[k]);
-                const float wt = Tb * al;
-                v[8] = fmaf(wt, g[k][0], v[8]);
-                v[9] = fmaf(wt, g[k][1], v[9]);
-                v[10] = fmaf(wt, g[k][2], v[10]);
-                Sg[k] = fmaf(al, cg - Sg[k], Sg[k]);
-                T[k] = Tb;
-                const float da = a <= kp.alpha_max ? dal : 0.0f;
-                v[7] = fmaf(p.W, da, v[7]);
-                dW = u.op * da;
-            }
+            if (!(p.e2 >= thr2)) continue;
+            const float cg = u.r * g[k][0] + u.g * g[k][1] + u.b * g[k][2];
+            const float ow = u.op * p.W;
+            v[8] = fmaf(ow, g[k][0], v[8]);
+            v[9] = fmaf(ow, g[k][1], v[9]);
+            v[10] = fmaf(ow, g[k][2], v[10]);
+            v[7] = fmaf(p.W, cg, v[7]);
             any = true;
-            const float sn = __builtin_amdgcn_sinf(__builtin_amdgcn_fractf(p.ph));
-            const float dq = dW * (-0.5f * p.W);             // dL/dq
-            const float dph = dW * (-0.5f * p.E * sn);       // dL/dphi (radians)
-            const float Adx = fmaf(u.ca, p.dx, u.cb * p.dy), Ady = fmaf(u.cb, p.dx, u.cc * p.dy);
-            v[0] = fmaf(-2.0f * dq, Adx, fmaf(-dph, u.fx, v[0]));
-            v[1] = fmaf(-2.0f * dq, Ady, fmaf(-dph, u.fy, v[1]));
-            v[2] = fmaf(dq * p.dx, p.dx, v[2]);
-            v[3] = fmaf(2.0f * dq * p.dx, p.dy, v[3]);
-            v[4] = fmaf(dq * p.dy, p.dy, v[4]);
-            v[5] = fmaf(dph, p.dx, v[5]);
-            v[6] = fmaf(dph, p.dy, v[6]);
+            pair_grads(v, p, u.op * cg, u.ca, u.cb, u.cc, u.fx, u.fy);
         }
         float* o = slots + (size_t)eidx[s] * kSlot;
         if (__ballot(any)) {
@@ -662,203 +595,238 @@ __device__ __forceinline__ void bwd_tile(const ImgDesc* __restrict__ descs, int 
     }
 }
 
-// Alpha backward with pixels ranked by `last`.  A pixel only takes part in
-// list positions s <= last (it walks back to front from its last contributing
-// pair), so the tile's pixels are ranked by descending last (ties by pixel
-// order) and dealt to rows in that order: at position s exactly the rows whose
-// first pixel has last >= s are active, and they form a prefix.  Pixels that
-// never contributed take no part at all.
 template <int TW, int TH>
-__device__ __forceinline__ void bwd_tile_alpha(const ImgDesc* __restrict__ descs, int B, const KParams& kp,
-                                               const Rec* __restrict__ recs, const uint32_t* __restrict__ vals,
-                                               const uint32_t* __restrict__ eidx,
-                                               const uint2* __restrict__ ranges, uint32_t t,
-                                               const float* __restrict__ T_final, const int32_t* __restrict__ last,
-                                               const float* __restrict__ dLdC, float* __restrict__ slots,
-                                               uint32_t* lds)
+__global__ void __launch_bounds__(kWave * kWpb) k_blend_bwd_add(const ImgDesc* __restrict__ descs, int B, KParams kp,
+                                                                const Rec* __restrict__ recs,
+                                                                const uint32_t* __restrict__ vals,
+                                                                const uint32_t* __restrict__ eidx,
+                                                                const uint2* __restrict__ ranges,
+                                                                const uint32_t* __restrict__ ovf, uint32_t n_tiles,
+                                                                const float* __restrict__ dLdC,
+                                                                float* __restrict__ slots)
 {
-    constexpr int SBX = TW / 8, NR = (TW / 8) * (TH / 8), P = TW * TH;
-    const TileGeo G = tile_geo(descs, B, ranges, t, TW, TH);
-    const ImgDesc& d = descs[G.b];
-    const int l = lane_id();
-    uint32_t pk[NR], ls[NR], tt[NR], g0[NR], g1[NR], g2[NR];
-    bool on[NR];
-    uint32_t A = 0;
-#pragma unroll
-    for (int r = 0; r < NR; ++r) {
-        const int px = (r % SBX) * 8 + (l & 7), py = (r / SBX) * 8 + (l >> 3);
-        const bool valid = (G.ox + px) < d.W && (G.oy + py) < d.H;
-        const uint32_t pix = (uint32_t)d.pix_begin + (uint32_t)((G.oy + py) * d.W + (G.ox + px));
-        const int32_t lv = valid ? last[pix] : -1;
-        on[r] = lv >= 0;
-        pk[r] = (uint32_t)(px | (py << 8));
-        ls[r] = (uint32_t)lv;
-        tt[r] = on[r] ? __float_as_uint(T_final[pix]) : 0u;
-        g0[r] = on[r] ? __float_as_uint(dLdC[3 * pix]) : 0u;
-        g1[r] = on[r] ? __float_as_uint(dLdC[3 * pix + 1]) : 0u;
-        g2[r] = on[r] ? __float_as_uint(dLdC[3 * pix + 2]) : 0u;
-        A += (uint32_t)__popcll(__ballot(on[r]));
-    }
-    // rank: number of pixels with larger last, or equal last and smaller slot
-#pragma unroll
-    for (int r = 0; r < NR; ++r) lds[r * kWave + l] = ls[r];
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    uint32_t idx[NR];
-#pragma unroll
-    for (int r = 0; r < NR; ++r) idx[r] = 0;
-    for (int q = 0; q < P; q += 4) {
-        const uint4 v4 = *reinterpret_cast<const uint4*>(lds + q);
-        const int32_t lq[4] = {(int32_t)v4.x, (int32_t)v4.y, (int32_t)v4.z, (int32_t)v4.w};
-#pragma unroll
-        for (int r = 0; r < NR; ++r) {
-            const int self = r * kWave + l;
-            const int32_t lv = (int32_t)ls[r];
-#pragma unroll
-            for (int k = 0; k < 4; ++k)
-                idx[r] += (lq[k] > lv || (lq[k] == lv && q + k < self)) ? 1u : 0u;
-        }
-    }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    const int nrows = (int)((A + kWave - 1) / kWave);
-    route<NR>(lds, on, idx, pk, NR, nrows, A, 0xffffffffu);
-    route<NR>(lds, on, idx, ls, NR, nrows, A, 0xffffffffu);
-    route<NR>(lds, on, idx, tt, NR, nrows, A, 0u);
-    route<NR>(lds, on, idx, g0, NR, nrows, A, 0u);
-    route<NR>(lds, on, idx, g1, NR, nrows, A, 0u);
-    route<NR>(lds, on, idx, g2, NR, nrows, A, 0u);
-    RowBox rb[NR];
-    int32_t rowmax[NR];
-    float Sg[NR];
-#pragma unroll
-    for (int r = 0; r < NR; ++r) {
-        rb[r] = row_box(r < nrows ? (int32_t)pk[r] : -1);
-        rowmax[r] = r < nrows ? __builtin_amdgcn_readfirstlane((int32_t)ls[r]) : -1;
-        Sg[r] = kp.bg[0] * __uint_as_float(g0[r]) + kp.bg[1] * __uint_as_float(g1[r]) +
-                kp.bg[2] * __uint_as_float(g2[r]);
-    }
-    // clamped to the tile's range (a `last` from a mismatched forward gives
-    // wrong gradients, never an access outside the list)
-    const uint32_t s_hi = (A > 0u && rowmax[0] >= (int32_t)G.start) ? min((uint32_t)rowmax[0] + 1u, G.end) : G.start;
-    for (uint32_t s = s_hi + (uint32_t)l; s < G.end; s += kWave) {
-        float4* o = reinterpret_cast<float4*>(slots + (size_t)eidx[s] * kSlot);
-        o[0] = make_float4(0.f, 0.f, 0.f, 0.f);
-        o[1] = make_float4(0.f, 0.f, 0.f, 0.f);
-        o[2] = make_float4(0.f, 0.f, 0.f, 0.f);
-    }
-    int nact = 0;
-    for (uint32_t s = s_hi; s-- > G.start;) {
-#pragma unroll
-        for (int r = 0; r < NR; ++r)
-            if (nact == r && r < nrows && rowmax[r] >= (int32_t)s) nact = r + 1;
-        const uint32_t prim = vals[s];
-        uint32_t b0, b1;
-        const PrimU u = load_prim(recs, prim, G.ox, G.oy, &b0, &b1);
-        const int x0 = lo16(b0) - G.ox, y0 = hi16(b0) - G.oy, x1 = lo16(b1) - G.ox, y1 = hi16(b1) - G.oy;
-        float v[16];
-#pragma unroll
-        for (int k = 0; k < 16; ++k) v[k] = 0.0f;
-        bool any = false;
-#pragma unroll
-        for (int r = 0; r < NR; ++r) {
-            if (r >= nact) break;
-            if (!box_meets(rb[r], x0, y0, x1, y1)) continue;
-            if ((int32_t)ls[r] < (int32_t)s) continue;      // not reached yet (or empty slot)
-            const float lx = (float)(pk[r] & 255u) + 0.5f, ly = (float)(pk[r] >> 8) + 0.5f;
-            const PairEval p = eval_pair(u, lx, ly);
-            const float a = u.op * p.W;
-            if (!(a >= kp.alpha_min)) continue;
-            const float gr = __uint_as_float(g0[r]), gg = __uint_as_float(g1[r]), gb = __uint_as_float(g2[r]);
-            const float al = fminf(a, kp.alpha_max);
-            const float Tb = __uint_as_float(tt[r]) / (1.0f - al);
-            const float cg = u.r * gr + u.g * gg + u.b * gb;
-            const float dal = Tb * (cg - Sg[r]);
-            const float wt = Tb * al;
-            v[8] = fmaf(wt, gr, v[8]);
-            v[9] = fmaf(wt, gg, v[9]);
-            v[10] = fmaf(wt, gb, v[10]);
-            Sg[r] = fmaf(al, cg - Sg[r], Sg[r]);
-            tt[r] = __float_as_uint(Tb);
-            const float da = a <= kp.alpha_max ? dal : 0.0f;
-            v[7] = fmaf(p.W, da, v[7]);
-            const float dW = u.op * da;
-            any = true;
-            const float sn = __builtin_amdgcn_sinf(__builtin_amdgcn_fractf(p.ph));
-            const float dq = dW * (-0.5f * p.W);
-            const float dph = dW * (-0.5f * p.E * sn);
-            const float Adx = fmaf(u.ca, p.dx, u.cb * p.dy), Ady = fmaf(u.cb, p.dx, u.cc * p.dy);
-            v[0] = fmaf(-2.0f * dq, Adx, fmaf(-dph, u.fx, v[0]));
-            v[1] = fmaf(-2.0f * dq, Ady, fmaf(-dph, u.fy, v[1]));
-            v[2] = fmaf(dq * p.dx, p.dx, v[2]);
-            v[3] = fmaf(2.0f * dq * p.dx, p.dy, v[3]);
-            v[4] = fmaf(dq * p.dy, p.dy, v[4]);
-            v[5] = fmaf(dph, p.dx, v[5]);
-            v[6] = fmaf(dph, p.dy, v[6]);
-        }
-        float* o = slots + (size_t)eidx[s] * kSlot;
-        if (__ballot(any)) {
-            wave_reduce16_valu(v);
-            const int id = l >> 2;
-            if ((l & 3) == 0 && id < kSlot) o[id] = v[0];
-        } else if (l < kSlot) {
-            o[l] = 0.0f;
-        }
-    }
-}
-
-template <int MODE, int TW, int TH>
-__global__ void __launch_bounds__(kWave * kWpb) k_blend_bwd(const ImgDesc* __restrict__ descs, int B, KParams kp,
-                                                            const Rec* __restrict__ recs,
-                                                            const uint32_t* __restrict__ vals,
-                                                            const uint32_t* __restrict__ eidx,
-                                                            const uint2* __restrict__ ranges,
-                                                            const uint32_t* __restrict__ ovf, uint32_t n_tiles,
-                                                            const float* __restrict__ T_final,
-                                                            const int32_t* __restrict__ last,
-                                                            const float* __restrict__ dLdC,
-                                                            float* __restrict__ slots)
-{
-    __shared__ __attribute__((aligned(16))) uint32_t lds[kWpb][TW * TH];
     if (*ovf) return;
     const uint32_t t = grid_tile_of_wave();
     if (t >= n_tiles) return;
-    if (MODE == WIPES_3D_ALPHA)
-        bwd_tile_alpha<TW, TH>(descs, B, kp, recs, vals, eidx, ranges, t, T_final, last, dLdC, slots,
-                               lds[threadIdx.x >> 6]);
-    else
-        bwd_tile<MODE, TW, TH>(descs, B, kp, recs, vals, eidx, ranges, t, T_final, last, dLdC, slots);
+    bwd_tile_add<TW, TH>(descs, B, kp, recs, vals, eidx, ranges, t, dLdC, slots);
 }
 
-template <int MODE, int TW, int TH>
-__global__ void __launch_bounds__(kWave * kWpb) k_blend_bwd_q(const ImgDesc* __restrict__ descs, int B, KParams kp,
-                                                              const Rec* __restrict__ recs,
-                                                              const uint32_t* __restrict__ vals,
-                                                              const uint32_t* __restrict__ eidx,
-                                                              const uint2* __restrict__ ranges,
-                                                              const uint32_t* __restrict__ ovf, uint32_t n_tiles,
-                                                              const uint32_t* __restrict__ order,
-                                                              uint32_t* __restrict__ queue,
-                                                              const float* __restrict__ T_final,
-                                                              const int32_t* __restrict__ last,
-                                                              const float* __restrict__ dLdC,
-                                                              float* __restrict__ slots)
+template <int TW, int TH>
+__global__ void __launch_bounds__(kWave * kWpb) k_blend_bwd_add_q(const ImgDesc* __restrict__ descs, int B,
+                                                                  KParams kp, const Rec* __restrict__ recs,
+                                                                  const uint32_t* __restrict__ vals,
+                                                                  const uint32_t* __restrict__ eidx,
+                                                                  const uint2* __restrict__ ranges,
+                                                                  const uint32_t* __restrict__ ovf, uint32_t n_tiles,
+                                                                  const uint32_t* __restrict__ order,
+                                                                  uint32_t* __restrict__ queue,
+                                                                  const float* __restrict__ dLdC,
+                                                                  float* __restrict__ slots)
 {
-    __shared__ __attribute__((aligned(16))) uint32_t lds[kWpb][TW * TH];
     if (*ovf) return;
     for (;;) {
         uint32_t idx = 0;
         if (lane_id() == 0) idx = atomicAdd(queue, 1u);
         idx = (uint32_t)__builtin_amdgcn_readfirstlane((int)idx);
         if (idx >= n_tiles) break;
-        const uint32_t t = order ? order[idx] : idx;
-        if (MODE == WIPES_3D_ALPHA)
-            bwd_tile_alpha<TW, TH>(descs, B, kp, recs, vals, eidx, ranges, t, T_final, last, dLdC, slots,
-                                   lds[threadIdx.x >> 6]);
-        else
-            bwd_tile<MODE, TW, TH>(descs, B, kp, recs, vals, eidx, ranges, t, T_final, last, dLdC, slots);
+        bwd_tile_add<TW, TH>(descs, B, kp, recs, vals, eidx, ranges, order ? order[idx] : idx, dLdC, slots);
+    }
+}
+
+// Alpha backward of tile t by the whole workgroup (wave w = block w).  The
+// waves walk the tile's list in the same chunks of 64 positions, top down
+// from the tile's last contributing position; each wave stages the chunk's
+// primitives that meet its contributing pixels, replays them back to front
+// (recovering T and the colour behind from the forward's T_final), reduces
+// each primitive's gradients over the block, and leaves them in LDS; then the
+// workgroup adds the blocks in a fixed order and writes the chunk's slots.
+template <int TW, int TH>
+__device__ __forceinline__ void bwd_tile_alpha(const ImgDesc* __restrict__ descs, int B, const KParams& kp,
+                                               const Rec* __restrict__ recs, const uint32_t* __restrict__ vals,
+                                               const uint32_t* __restrict__ eidx, const uint2* __restrict__ ranges,
+                                               uint32_t t, const float* __restrict__ T_final,
+                                               const int32_t* __restrict__ last, const float* __restrict__ dLdC,
+                                               float* __restrict__ slots, Staged (*stage)[kWave],
+                                               float* __restrict__ part, uint32_t* __restrict__ top)
+{
+    constexpr int NBX = TW / 8, NB = (TW / 8) * (TH / 8), NT = NB * kWave;
+    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int l = lane_id(), tid = (int)threadIdx.x;
+    const TileGeo G = tile_geo(descs, B, ranges, t, TW, TH);
+    const ImgDesc& d = descs[G.b];
+    const int bx = G.ox + (w % NBX) * 8, by = G.oy + (w / NBX) * 8;
+    const int px = bx + (l & 7), py = by + (l >> 3);
+    const bool valid = px < d.W && py < d.H;
+    const uint32_t pix = valid ? (uint32_t)d.pix_begin + (uint32_t)(py * d.W + px) : 0u;
+    // a `last` outside this tile's list (from a mismatched forward) can only
+    // give wrong gradients, never an access outside the list
+    const int32_t lst = min(valid ? last[pix] : -1, (int32_t)G.end - 1);
+    const bool on = lst >= (int32_t)G.start;
+    float T = 0.0f, g0 = 0.0f, g1 = 0.0f, g2 = 0.0f;
+    if (on) {
+        T = T_final[pix];
+        g0 = dLdC[3 * pix];
+        g1 = dLdC[3 * pix + 1];
+        g2 = dLdC[3 * pix + 2];
+    }
+    float Sg = kp.bg[0] * g0 + kp.bg[1] * g1 + kp.bg[2] * g2;   // dL/dC . colour behind
+    const float lx = (float)(l & 7) + 0.5f, ly = (float)(l >> 3) + 0.5f;
+    const int32_t btop = __builtin_amdgcn_readfirstlane(wave_max_i32(on ? lst : -1));
+    const PixBox cbox = pix_box(on, px, py);
+    if (l == 0) top[w] = (uint32_t)(btop + 1);
+    __syncthreads();
+    uint32_t hi = G.start;
+#pragma unroll
+    for (int k = 0; k < NB; ++k) hi = max(hi, top[k]);
+    // positions no pixel reached get zero slots
+    for (uint32_t s = hi + (uint32_t)tid; s < G.end; s += NT) {
+        float4* o = reinterpret_cast<float4*>(slots + (size_t)eidx[s] * kSlot);
+        o[0] = make_float4(0.f, 0.f, 0.f, 0.f);
+        o[1] = make_float4(0.f, 0.f, 0.f, 0.f);
+        o[2] = make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+    if (hi <= G.start) return;   // uniform over the workgroup
+    const uint64_t below = (1ull << l) - 1ull;
+    float* mine = part + (size_t)w * kWave * kSlot;
+    Staged* st = stage[w];
+    auto down = [&](uint32_t c) { return c - min(c - G.start, (uint32_t)kWave); };
+    uint32_t c1 = hi, c0 = down(hi);
+    Rec cur{};
+    cur.box0 = kNoBox;
+    if (btop >= (int32_t)c0) {
+        cur = recs[vals[min(c0 + (uint32_t)l, c1 - 1u)]];
+        if (c0 + (uint32_t)l >= c1) cur.box0 = kNoBox;
+    }
+    uint32_t pn = 0;
+    if (c0 > G.start && btop >= (int32_t)down(c0)) pn = vals[min(down(c0) + (uint32_t)l, c0 - 1u)];
+    for (;;) {
+        const uint32_t s = c0 + (uint32_t)l;
+        const bool hit = (int32_t)s <= btop && box_meets(cur.box0, cur.box1, cbox);
+        const uint64_t m = __ballot(hit);
+        if (hit) {
+            st[__popcll(m & below)] = stage_raw(cur, bx, by, s);
+        } else {
+            float4* z = reinterpret_cast<float4*>(mine + l * kSlot);
+            z[0] = make_float4(0.f, 0.f, 0.f, 0.f);
+            z[1] = make_float4(0.f, 0.f, 0.f, 0.f);
+            z[2] = make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+        const uint32_t n1 = c0, n0 = down(c0);
+        const bool more = n1 > G.start;   // uniform over the workgroup
+        Rec nx{};
+        nx.box0 = kNoBox;
+        if (more) {   // the next chunk is in flight while this one is replayed
+            if (btop >= (int32_t)n0) {
+                nx = recs[pn];
+                if (n0 + (uint32_t)l >= n1) nx.box0 = kNoBox;
+            }
+            if (n0 > G.start && btop >= (int32_t)down(n0)) pn = vals[min(down(n0) + (uint32_t)l, n0 - 1u)];
+        }
+        wave_lds_sync();
+        for (int j = __popcll(m) - 1; j >= 0; --j) {
+            const Staged S = st[j];
+            float v[16];
+#pragma unroll
+            for (int k = 0; k < 16; ++k) v[k] = 0.0f;
+            bool any = false;
+            if (on && (int32_t)S.pos <= lst) {
+                const PairEval p = eval_at(S.mrx, S.mry, S.c0 * kConicScale, S.c1 * (2.0f * kConicScale),
+                                           S.c2 * kConicScale, S.f0 * kInv2Pi, S.f1 * kInv2Pi, lx, ly);
+                const float a = S.op * p.W;
+                if (a >= kp.alpha_min) {
+                    const float al = fminf(a, kp.alpha_max);
+                    const float Tb = T / (1.0f - al);
+                    const float cg = S.r * g0 + S.g * g1 + S.b * g2;
+                    const float dal = Tb * (cg - Sg);
+                    const float wt = Tb * al;
+                    v[8] = wt * g0;
+                    v[9] = wt * g1;
+                    v[10] = wt * g2;
+                    Sg = fmaf(al, cg - Sg, Sg);
+                    T = Tb;
+                    const float da = a <= kp.alpha_max ? dal : 0.0f;
+                    v[7] = p.W * da;
+                    any = true;
+                    pair_grads(v, p, S.op * da, S.c0, S.c1, S.c2, S.f0, S.f1);
+                }
+            }
+            float* o = mine + (S.pos - c0) * kSlot;
+            if (__ballot(any)) {
+                wave_reduce16_valu(v);
+                const int id = l >> 2;
+                if ((l & 3) == 0 && id < kSlot) o[id] = v[0];
+            } else if (l < kSlot) {
+                o[l] = 0.0f;
+            }
+        }
+        __syncthreads();
+        const uint32_t n = c1 - c0;
+        for (uint32_t q = (uint32_t)tid; q < n * kSlot; q += NT) {
+            const uint32_t pp = q / kSlot;
+            float sum = part[q];
+#pragma unroll
+            for (int k = 1; k < NB; ++k) sum += part[(size_t)k * kWave * kSlot + q];
+            slots[(size_t)eidx[c0 + pp] * kSlot + (q - pp * kSlot)] = sum;
+        }
+        __syncthreads();
+        if (!more) break;
+        cur = nx;
+        c1 = n1;
+        c0 = n0;
+    }
+}
+
+template <int TW, int TH>
+__global__ void __launch_bounds__(TW * TH) k_blend_bwd_alpha(const ImgDesc* __restrict__ descs, int B, KParams kp,
+                                                             const Rec* __restrict__ recs,
+                                                             const uint32_t* __restrict__ vals,
+                                                             const uint32_t* __restrict__ eidx,
+                                                             const uint2* __restrict__ ranges,
+                                                             const uint32_t* __restrict__ ovf, uint32_t n_tiles,
+                                                             const float* __restrict__ T_final,
+                                                             const int32_t* __restrict__ last,
+                                                             const float* __restrict__ dLdC,
+                                                             float* __restrict__ slots)
+{
+    constexpr int NB = (TW / 8) * (TH / 8);
+    __shared__ Staged stage[NB][kWave];
+    __shared__ __attribute__((aligned(16))) float part[NB * kWave * kSlot];
+    __shared__ uint32_t top[NB];
+    if (*ovf) return;
+    const uint32_t t = blockIdx.x;
+    if (t >= n_tiles) return;
+    bwd_tile_alpha<TW, TH>(descs, B, kp, recs, vals, eidx, ranges, t, T_final, last, dLdC, slots, stage, part, top);
+}
+
+// Persistent form: each workgroup pulls whole tiles from the queue.
+template <int TW, int TH>
+__global__ void __launch_bounds__(TW * TH) k_blend_bwd_alpha_q(const ImgDesc* __restrict__ descs, int B, KParams kp,
+                                                               const Rec* __restrict__ recs,
+                                                               const uint32_t* __restrict__ vals,
+                                                               const uint32_t* __restrict__ eidx,
+                                                               const uint2* __restrict__ ranges,
+                                                               const uint32_t* __restrict__ ovf, uint32_t n_tiles,
+                                                               const uint32_t* __restrict__ order,
+                                                               uint32_t* __restrict__ queue,
+                                                               const float* __restrict__ T_final,
+                                                               const int32_t* __restrict__ last,
+                                                               const float* __restrict__ dLdC,
+                                                               float* __restrict__ slots)
+{
+    constexpr int NB = (TW / 8) * (TH / 8);
+    __shared__ Staged stage[NB][kWave];
+    __shared__ __attribute__((aligned(16))) float part[NB * kWave * kSlot];
+    __shared__ uint32_t top[NB];
+    __shared__ uint32_t qnext;
+    if (*ovf) return;
+    for (;;) {
+        if (threadIdx.x == 0) qnext = atomicAdd(queue, 1u);
+        __syncthreads();
+        const uint32_t idx = qnext;
+        __syncthreads();   // every wave has read `qnext` before it is rewritten
+        if (idx >= n_tiles) break;
+        bwd_tile_alpha<TW, TH>(descs, B, kp, recs, vals, eidx, ranges, order ? order[idx] : idx, T_final, last, dLdC,
+                               slots, stage, part, top);
     }
 }
 
@@ -942,16 +910,31 @@ static void launch_fwd_t(const ImgDesc* descs, int B, const KParams& kp, const R
                          uint32_t* queue, uint32_t persistent_blocks, float* image, float* T_final, int32_t* last,
                          hipStream_t s)
 {
-    if (queue) {
-        if (persistent_blocks == 0) return;
-        hipLaunchKernelGGL((k_blend_fwd_q<MODE, TW, TH>), dim3(persistent_blocks), dim3(kWave * kWpb), 0, s, descs, B,
-                           kp, recs, vals, ranges, ovf, n_tiles, order, queue, image, T_final, last);
-        return;
+    constexpr uint32_t NB = (TW / 8) * (TH / 8);
+    if constexpr (MODE == WIPES_3D_ALPHA) {
+        if (queue) {
+            const uint32_t nb = max(1u, persistent_blocks * kWpb / NB);   // same number of waves
+            hipLaunchKernelGGL((k_blend_fwd_alpha_q<TW, TH>), dim3(nb), dim3(TW * TH), 0, s, descs, B, kp, recs, vals,
+                               ranges, ovf, n_tiles, order, queue, image, T_final, last);
+            return;
+        }
+        if (n_tiles == 0) return;
+        hipLaunchKernelGGL((k_blend_fwd_alpha<TW, TH>), dim3(n_tiles), dim3(TW * TH), 0, s, descs, B, kp, recs, vals,
+                           ranges, ovf, n_tiles, image, T_final, last);
+    } else {
+        (void)T_final;
+        (void)last;
+        if (queue) {
+            if (persistent_blocks == 0) return;
+            hipLaunchKernelGGL((k_blend_fwd_add_q<TW, TH>), dim3(persistent_blocks), dim3(kWave * kWpb), 0, s, descs,
+                               B, kp, recs, vals, ranges, ovf, n_tiles, order, queue, image);
+            return;
+        }
+        const uint32_t nb = (n_tiles + kWpb - 1) / kWpb;
+        if (nb == 0) return;
+        hipLaunchKernelGGL((k_blend_fwd_add<TW, TH>), dim3(nb), dim3(kWave * kWpb), 0, s, descs, B, kp, recs, vals,
+                           ranges, ovf, n_tiles, image);
     }
-    const uint32_t nb = (n_tiles + kWpb - 1) / kWpb;
-    if (nb == 0) return;
-    hipLaunchKernelGGL((k_blend_fwd<MODE, TW, TH>), dim3(nb), dim3(kWave * kWpb), 0, s, descs, B, kp, recs, vals,
-                       ranges, ovf, n_tiles, image, T_final, last);
 }
 
 template <int MODE, int TW, int TH>
@@ -960,16 +943,31 @@ static void launch_bwd_t(const ImgDesc* descs, int B, const KParams& kp, const R
                          const uint32_t* order, uint32_t* queue, uint32_t persistent_blocks, const float* T_final,
                          const int32_t* last, const float* dLdC, float* slots, hipStream_t s)
 {
-    if (queue) {
-        if (persistent_blocks == 0) return;
-        hipLaunchKernelGGL((k_blend_bwd_q<MODE, TW, TH>), dim3(persistent_blocks), dim3(kWave * kWpb), 0, s, descs, B,
-                           kp, recs, vals, eidx, ranges, ovf, n_tiles, order, queue, T_final, last, dLdC, slots);
-        return;
+    constexpr uint32_t NB = (TW / 8) * (TH / 8);
+    if constexpr (MODE == WIPES_3D_ALPHA) {
+        if (queue) {
+            const uint32_t nb = max(1u, persistent_blocks * kWpb / NB);
+            hipLaunchKernelGGL((k_blend_bwd_alpha_q<TW, TH>), dim3(nb), dim3(TW * TH), 0, s, descs, B, kp, recs, vals,
+                               eidx, ranges, ovf, n_tiles, order, queue, T_final, last, dLdC, slots);
+            return;
+        }
+        if (n_tiles == 0) return;
+        hipLaunchKernelGGL((k_blend_bwd_alpha<TW, TH>), dim3(n_tiles), dim3(TW * TH), 0, s, descs, B, kp, recs, vals,
+                           eidx, ranges, ovf, n_tiles, T_final, last, dLdC, slots);
+    } else {
+        (void)T_final;
+        (void)last;
+        if (queue) {
+            if (persistent_blocks == 0) return;
+            hipLaunchKernelGGL((k_blend_bwd_add_q<TW, TH>), dim3(persistent_blocks), dim3(kWave * kWpb), 0, s, descs,
+                               B, kp, recs, vals, eidx, ranges, ovf, n_tiles, order, queue, dLdC, slots);
+            return;
+        }
+        const uint32_t nb = (n_tiles + kWpb - 1) / kWpb;
+        if (nb == 0) return;
+        hipLaunchKernelGGL((k_blend_bwd_add<TW, TH>), dim3(nb), dim3(kWave * kWpb), 0, s, descs, B, kp, recs, vals,
+                           eidx, ranges, ovf, n_tiles, dLdC, slots);
     }
-    const uint32_t nb = (n_tiles + kWpb - 1) / kWpb;
-    if (nb == 0) return;
-    hipLaunchKernelGGL((k_blend_bwd<MODE, TW, TH>), dim3(nb), dim3(kWave * kWpb), 0, s, descs, B, kp, recs, vals,
-                       eidx, ranges, ovf, n_tiles, T_final, last, dLdC, slots);
 }
 
 #define WIPES_TILE_DISPATCH(FN, MODE, ...)                                          \
