@@ -49,7 +49,7 @@ def parse():
     ap.add_argument("--extras", type=str, default="serve,batched,fit",
                     help="comma list of secondary workloads to add to the JSON line (serve, batched, fit) or none")
     ap.add_argument("--serve-requests", type=int, default=240)
-    ap.add_argument("--fit-steps", type=int, default=200)
+    ap.add_argument("--fit-steps", type=int, default=1000)
     return ap.parse_args()
 
 
@@ -146,19 +146,31 @@ def bench_batched(log):
 
 
 def bench_fit(steps, log):
-    """Config 2: 768x512 1/f texture with stripe patches, 70k primitives, Adam on the L2 loss."""
+    """Config 2: 768x512 1/f texture with stripe patches, 70k primitives, Adam on the L2 loss,
+    as the plain autograd loop and as one hipGraph replay per step, from the same start."""
     import torch
+    from paper_2508_12615_amd import binding as Bd
     from paper_2508_12615_amd import synth
-    from paper_2508_12615_amd.fit import fit_plain
+    from paper_2508_12615_amd.fit import fit_graph, fit_plain, psnr
+    from paper_2508_12615_amd.raster import Rasterizer, render
     dev = torch.device("cuda", 0)
     c = synth.config2()
     target = torch.from_numpy(c["target"]).to(dev)
     prims = {k: torch.from_numpy(v).to(dev) for k, v in c["prims"].items()}
+    with torch.no_grad():
+        p0 = psnr(render(Rasterizer(Bd.WIPES_2D_ADDITIVE, device=dev), (c["width"], c["height"]), **prims), target)
     fit_plain({k: v.clone() for k, v in prims.items()}, target, 5)
-    out = fit_plain(prims, target, steps)
-    log("fit: done")
-    return dict(workload="768x512 fit, 70k primitives, %d Adam steps" % steps, steps_per_s=steps / out["seconds"],
-                ms_per_step=out["seconds"] * 1e3 / steps, psnr_db=out["psnr"])
+    fit_graph({k: v.clone() for k, v in prims.items()}, target, 5)
+    plain = fit_plain({k: v.clone() for k, v in prims.items()}, target, steps, log_every=max(1, steps // 4))
+    log("fit: plain done")
+    graph = fit_graph({k: v.clone() for k, v in prims.items()}, target, steps, log_every=max(1, steps // 4))
+    log("fit: graph done")
+    return dict(workload="768x512 fit, 70k primitives, %d Adam steps" % steps, psnr_init_db=p0,
+                plain=dict(steps_per_s=steps / plain["seconds"], ms_per_step=plain["seconds"] * 1e3 / steps,
+                           psnr_db=plain["psnr"], loss=[(i, round(v, 6)) for i, v in plain["history"]]),
+                graph=dict(steps_per_s=steps / graph["seconds"], ms_per_step=graph["seconds"] * 1e3 / steps,
+                           psnr_db=graph["psnr"], loss=[(i, round(v, 6)) for i, v in graph["history"]],
+                           recaptures=graph["recaptures"]))
 
 
 def cpu_baseline(prims, cam):

@@ -5,6 +5,8 @@ Two drivers over the same rasterizer:
 * ``fit_plain``    -- one image, one step = render (autograd) -> L2 loss ->
                       backward -> Adam; the plain per-image rasterizer with one
                       host synchronisation per step (instance count readback).
+* ``fit_graph``    -- one image, one step = one hipGraph replay of the whole
+                      render step + Adam (a BatchedFit of one image).
 * ``BatchedFit``   -- many images of uneven size fitted together; one step is a
                       single replay of a hipGraph holding projection, binning,
                       sorting, forward blend, L2 gradient, backward blend and
@@ -43,6 +45,46 @@ def psnr(img: torch.Tensor, target: torch.Tensor) -> float:
     return 10.0 * math.log10(1.0 / max(mse, 1e-20))
 
 
+def fit_graph(prims: dict, target: torch.Tensor, steps: int, tile=(16, 16), cov: int = B.WIPES_COV_RS,
+              log_every: int = 0):
+    """Fit one image with one hipGraph replay per step (projection, binning,
+    sorting, forward, L2 gradient, backward, projection backward), then Adam.
+    The instance count is checked after every replay, before the optimiser
+    step; a replay that overflowed the capacity is redone after recapturing
+    with more room, so no step uses gradients of a truncated render.
+    prims is modified in place.  Returns dict(history, psnr, seconds, steps,
+    recaptures)."""
+    H, W, _ = target.shape
+    fit = BatchedFit([dict(width=W, height=H, target=target.contiguous(), prims=prims)], tile=tile, cov=cov)
+    hist = []
+    grown = 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    it = 0
+    while it < steps:
+        fit.render_grads()
+        st, K = B.wipes_check_overflow(fit.rast.ctx, fit.rast.params, fit.batch, fit.sbuf,
+                                       torch.cuda.current_stream(fit.device).cuda_stream)
+        if st != B.WIPES_OK:
+            fit.grow(K)
+            grown += 1
+            continue
+        fit.opt.step()
+        if log_every and (it % log_every == 0 or it == steps - 1):
+            hist.append((it, fit.loss()))
+        it += 1
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    with torch.no_grad():
+        for k in KEYS_2D:
+            prims[k].copy_(fit.params[k])
+    fit.render_grads()
+    torch.cuda.synchronize()
+    final = psnr(fit.image.view(H, W, 3), target)
+    fit.close()
+    return dict(history=hist, psnr=final, seconds=dt, steps=steps, recaptures=grown)
+
+
 def fit_plain(prims: dict, target: torch.Tensor, steps: int, rast: Rasterizer | None = None, cov: int = B.WIPES_COV_RS,
               log_every: int = 0):
     """Fit one image.  prims: dict of float32 CUDA tensors (modified in place).
@@ -61,7 +103,7 @@ def fit_plain(prims: dict, target: torch.Tensor, steps: int, rast: Rasterizer | 
         loss.backward()
         opt.step()
         if log_every and (it % log_every == 0 or it == steps - 1):
-            hist.append((it, float(loss)))
+            hist.append((it, float(loss.detach())))
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     with torch.no_grad():
@@ -101,8 +143,15 @@ class BatchedFit:
         # size the instance capacity from one plain pass
         f = self.rast.forward(self._views)
         self.K0 = f.K
-        self.capacity = int(f.K * capacity_margin) + 4096
+        self.capacity_margin = capacity_margin
         self.batch, self._keep, _ = self.rast.make_batch(self._views, self._grad_views())
+        self.graph = None
+        self._capture(int(f.K * capacity_margin) + 4096)
+
+    def _capture(self, capacity: int) -> None:
+        """(Re)build the workspace for `capacity` instances and capture the step."""
+        self.close()
+        self.capacity = int(capacity)
         sb, bb = B.wipes_workspace_size(self.rast.params, self.batch, self.capacity, True)
         self.screen = torch.empty(sb, dtype=torch.uint8, device=self.device)
         self.bins = torch.empty(bb, dtype=torch.uint8, device=self.device)
@@ -111,6 +160,10 @@ class BatchedFit:
         self.graph = B.wipes_graph_capture(self.rast.ctx, self.rast.params, self.batch, self.sbuf, self.bbuf,
                                            self.image.data_ptr(), None, None, self.target.data_ptr(),
                                            self.dL.data_ptr(), True)
+
+    def grow(self, needed: int) -> None:
+        """Recapture with room for `needed` instances (parameters and optimiser state are kept)."""
+        self._capture(int(needed * self.capacity_margin) + 4096)
 
     def _image_views(self):
         out = []
