@@ -53,7 +53,7 @@ def parse():
     return ap.parse_args()
 
 
-def bench_serving(n_req, log):
+def bench_serving(n_req, log, persistent=1, load=0.8):
     """Config 5: 8 resident scenes (0.1-2M primitives, linear motion), Poisson requests at
     540p-1080p; the library's continuously batching server vs the plain rasterizer serving one
     request at a time, at the same offered load (80 % of the plain rasterizer's capacity)."""
@@ -73,12 +73,12 @@ def bench_serving(n_req, log):
     run_plain(rast, scenes, probe[:8], outs[:8])                     # warm-up
     lat, span = run_plain(rast, scenes, probe, outs)
     service_ms = span * 1e3 / len(probe)
-    rate = 0.8 / (service_ms * 1e-3)
+    rate = load / (service_ms * 1e-3)
     reqs = synth.serve_requests(n_req, rate)
     outs = [torch.empty((r["camera"]["height"], r["camera"]["width"], 3), device=dev) for r in reqs]
     lat_p, span_p = run_plain(rast, scenes, reqs, outs)
     log("serving: plain done")
-    srv = Server(max_slots=16, max_batch=8, persistent=1, hbm_budget_bytes=4 << 30)
+    srv = Server(max_slots=16, max_batch=8, persistent=persistent, hbm_budget_bytes=4 << 30)
     ids = [srv.load_scene(sc) for sc in scenes]
     run_served(srv, ids, [dict(r, t_arrive=0.0) for r in probe[:16]], outs[:16])   # warm-up
     srv.reset_stats()
@@ -88,7 +88,7 @@ def bench_serving(n_req, log):
     log("serving: served done")
     pct = lambda v, q: float(np.percentile(v, q))  # noqa: E731
     return dict(workload="8 resident scenes of 0.1-2M wavelet primitives with linear motion, %d Poisson requests at "
-                         "%.0f/s (80%% of plain capacity), 960x540-1920x1080" % (n_req, rate),
+                         "%.0f/s (%.0f%% of plain capacity), 960x540-1920x1080" % (n_req, rate, 100 * load),
                 plain_service_ms=service_ms,
                 served=dict(p50_ms=pct(lat_s, 50), p99_ms=pct(lat_s, 99), frames_per_s=n_req / span_s,
                             mean_batch=st["mean_batch"], deferred=st["deferred"],

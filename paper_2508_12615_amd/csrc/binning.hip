@@ -59,12 +59,18 @@ __global__ void __launch_bounds__(256) k_bin_count(const ImgDesc* __restrict__ d
     }
 }
 
-// One thread per primitive in emission order (order == NULL: index order).
-// Writes that primitive's instances at offs[r], tiles row-major.  With eidx
-// set, also the instance's index in primitive-index emission order,
+// Writes the instances of the primitive of rank r (ranks are primitive
+// indices, or depth order when `order` is given) at offs[r]..: key = global
+// tile, value = primitive, tiles of the pixel box row-major.  With eidx set,
+// also each instance's index in primitive-index emission order,
 // off_id[prim] + (position in the tile rectangle): the slot the backward
 // writes that instance's gradients to, so the projection backward reads each
 // primitive's slots contiguously.
+//
+// A wave owns 64 consecutive ranks, whose instances form one contiguous run;
+// it walks that run 64 entries at a time and each lane finds its entry's
+// primitive by a binary search over the 64 start offsets in LDS, so every
+// store is coalesced however uneven the per-primitive counts are.
 __global__ void __launch_bounds__(256) k_emit(const ImgDesc* __restrict__ descs, int B, int32_t n_total,
                                                KParams kp, const Rec* __restrict__ recs,
                                                const uint32_t* __restrict__ count,
@@ -74,25 +80,59 @@ __global__ void __launch_bounds__(256) k_emit(const ImgDesc* __restrict__ descs,
                                                const uint32_t* __restrict__ n_eff, uint32_t* __restrict__ keys,
                                                uint32_t* __restrict__ vals, uint32_t* __restrict__ eidx)
 {
-    const int32_t r = (int32_t)(blockIdx.x * 256u + threadIdx.x);
-    if (r >= n_total || *n_eff == 0u) return;
-    const uint32_t prim = order ? order[r] : (uint32_t)r;
-    const uint32_t c = count[prim];
-    if (c == 0) return;
-    const ImgDesc& d = descs[image_of_prim(descs, B, (int32_t)prim)];
-    const uint32_t b0 = recs[prim].box0, b1 = recs[prim].box1;
-    const int32_t tx0 = lo16(b0) >> kp.log2_tw, ty0 = hi16(b0) >> kp.log2_th;
-    const int32_t tx1 = lo16(b1) >> kp.log2_tw, ty1 = hi16(b1) >> kp.log2_th;
-    uint32_t k = offs[r];
-    const uint32_t e0 = eidx ? off_id[prim] : 0u;
-    uint32_t local = 0;
-    for (int32_t ty = ty0; ty <= ty1; ++ty) {
-        const uint32_t row = (uint32_t)(d.tile_begin + ty * d.tiles_x);
-        for (int32_t tx = tx0; tx <= tx1; ++tx, ++k, ++local) {
-            keys[k] = row + (uint32_t)tx;
-            vals[k] = prim;
-            if (eidx) eidx[k] = e0 + local;
+    __shared__ uint32_t s_start[4][kWave], s_prim[4][kWave], s_base[4][kWave], s_tx[4][kWave], s_w[4][kWave],
+        s_e0[4][kWave];
+    const int w = (int)(threadIdx.x >> 6), l = lane_id();
+    const int32_t r0 = (int32_t)(blockIdx.x * 256u + (uint32_t)w * kWave);   // rank of lane 0
+    if (r0 >= n_total || *n_eff == 0u) return;   // wave-uniform
+    const int32_t r = r0 + l;
+    uint32_t c = 0, prim = 0, base = 0, tilesx = 1, wd = 1, e0 = 0, off = 0xffffffffu;
+    if (r < n_total) {
+        prim = order ? order[r] : (uint32_t)r;
+        c = count[prim];
+        off = offs[r];
+        if (c) {
+            const ImgDesc& d = descs[image_of_prim(descs, B, (int32_t)prim)];
+            const uint32_t b0 = recs[prim].box0, b1 = recs[prim].box1;
+            const int32_t tx0 = lo16(b0) >> kp.log2_tw, ty0 = hi16(b0) >> kp.log2_th;
+            const int32_t tx1 = lo16(b1) >> kp.log2_tw;
+            wd = (uint32_t)(tx1 - tx0 + 1);
+            tilesx = (uint32_t)d.tiles_x;
+            base = (uint32_t)(d.tile_begin + ty0 * d.tiles_x + tx0);
+            e0 = eidx ? off_id[prim] : 0u;
         }
+    }
+    const uint32_t first = (uint32_t)__builtin_amdgcn_readfirstlane((int)off);   // lane 0 is in range
+    const uint32_t total = wave_sum_u32(c);
+    // ranks past the end never match (start beyond every entry)
+    s_start[w][l] = r < n_total ? off - first : 0xffffffffu;
+    s_prim[w][l] = prim;
+    s_base[w][l] = base;
+    s_tx[w][l] = tilesx;
+    s_w[w][l] = wd;
+    s_e0[w][l] = e0;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    for (uint32_t k0 = 0; k0 < total; k0 += kWave) {
+        const uint32_t k = k0 + (uint32_t)l;
+        if (k >= total) break;
+        // largest j with start[j] <= k (start[0] = 0; a rank with no instances
+        // shares its start with the next one, which the search prefers)
+        int j = 0;
+#pragma unroll
+        for (int step = 32; step > 0; step >>= 1)
+            if (s_start[w][j + step] <= k) j += step;
+        const uint32_t local = k - s_start[w][j];
+        const uint32_t wj = s_w[w][j];
+        uint32_t dy = (uint32_t)((float)local / (float)wj);   // corrected to the exact quotient below
+        if (dy * wj > local) --dy;
+        else if ((dy + 1u) * wj <= local) ++dy;
+        const uint32_t dx = local - dy * wj;
+        const uint32_t o = first + k;
+        keys[o] = s_base[w][j] + dy * s_tx[w][j] + dx;
+        vals[o] = s_prim[w][j];
+        if (eidx) eidx[o] = s_e0[w][j] + local;
     }
 }
 

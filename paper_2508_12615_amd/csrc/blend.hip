@@ -3,34 +3,27 @@
 // Paper: W' of Eq. 7 (Sec. 4.1) blended by Eq. 4 (additive, 2D fitting) or by
 // Eq. 3 (front-to-back alpha compositing, view synthesis).
 //
-// Additive mode (every pixel sees its whole tile list, no early exit):
-//  * one 64-lane wave owns one TW x TH tile; the tile is split into 8 x 8
-//    sub-blocks and lane l owns pixel (l & 7, l >> 3) of every sub-block;
-//  * the wave walks the tile's sorted list with wave-uniform indices, so list
-//    entries and 64-byte records arrive through the scalar data cache straight
-//    into SGPRs; sub-blocks the primitive's pixel box misses are skipped with
-//    scalar integer compares.
-//
-// Alpha mode (lists are long and skewed -- a few tiles hold most instances --
-// and pixels stop early):
+// Work decomposition (both modes):
 //  * every 8 x 8 block of a tile gets its own wave (the tile is one
-//    workgroup), so the serial walk of a heavy tile is split four ways (16 x 16
-//    tiles) without lengthening the sort;
-//  * the wave walks the list in chunks of 64 entries: each lane gathers one
-//    entry's record (vector loads; the next chunk's entries and records are in
-//    flight while the current chunk blends), tests its pixel box against the
-//    bounding box of the block pixels still in play, and the hits are packed
-//    (ballot + prefix count) into a per-wave LDS stage holding their
-//    block-relative, pre-scaled values.  The wave then blends the staged
+//    workgroup), lane l holding pixel (l & 7, l >> 3) of the block, so the
+//    serial walk of a long list is split four ways (16 x 16 tiles) without
+//    lengthening the sort, and a small frame still fills the machine;
+//  * the wave walks the tile's list in chunks of 64 entries: each lane
+//    gathers one entry's record (vector loads; the next chunk's entries and
+//    records are in flight while the current chunk blends), tests its pixel
+//    box against the bounding box of the block pixels still in play, and the
+//    hits are packed (ballot + prefix count) into a per-wave LDS stage holding
+//    their block-relative, pre-scaled values.  The wave then blends the staged
 //    primitives in list order; all lanes read the same LDS address, which the
 //    LDS broadcasts.  A primitive that misses the block costs one lane of one
 //    box test instead of a serial round trip through memory;
-//  * the forward shrinks the box as pixels terminate and leaves when none is
-//    left; the backward walks the same chunks top down (from the last
-//    contributing position of the tile) with all block waves in step, each
-//    wave reducing a primitive's eleven gradients over its block into LDS,
-//    and the workgroup sums the blocks in a fixed order into the instance's
-//    slot.
+//  * alpha mode shrinks the box as pixels terminate and leaves when none is
+//    left (lists are long and skewed in clustered scenes, and pixels stop
+//    early); additive mode keeps the box of the block's pixels;
+//  * the backward walks the same chunks top down (alpha: from the tile's last
+//    contributing position) with all block waves in step, each wave reducing
+//    a primitive's eleven gradients over its block into LDS, and the
+//    workgroup sums the blocks in a fixed order into the instance's slot.
 //
 // Gradient slots are numbered in primitive order (the sort carries each
 // instance's slot index), so the projection backward sums a primitive's slots
@@ -44,9 +37,9 @@
 
 namespace wipes {
 
-constexpr int kWpb = 4;   // waves (tiles) per workgroup, additive mode
+constexpr int kWpb = 4;   // waves (tiles) per workgroup of the work-counting kernel
 
-// Per-primitive, wave-uniform values of the additive path.
+// Per-primitive, wave-uniform values (work counting).
 struct PrimU {
     float mrx, mry;       // mean relative to the tile origin
     float ca2, cb2, cc2;  // conic scaled by -log2(e)/2 (cb2 includes the factor 2)
@@ -117,10 +110,9 @@ __device__ __forceinline__ uint32_t subblock_mask(uint32_t box0, uint32_t box1, 
     return m;
 }
 
-// Map a wave to its tile (additive mode).  Workgroups are remapped so that
-// each of the 8 XCDs (which receive workgroups round-robin) walks a
-// contiguous band of tiles and its L2 sees the primitives of neighbouring
-// tiles; additive lists are roughly uniform, so bands do not unbalance XCDs.
+// Map a wave to its tile (work counting, one wave per tile).  Workgroups are
+// remapped so that each of the 8 XCDs (which receive workgroups round-robin)
+// walks a contiguous band of tiles.
 __device__ __forceinline__ uint32_t grid_tile_of_wave()
 {
     const uint32_t nb = gridDim.x, b = blockIdx.x;
@@ -168,95 +160,7 @@ __device__ __forceinline__ void wave_lds_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// ------------------------------------------------------------ additive mode
-
-template <int TW, int TH>
-__device__ __forceinline__ void fwd_tile_add(const ImgDesc* __restrict__ descs, int B, const KParams& kp,
-                                             const Rec* __restrict__ recs, const uint32_t* __restrict__ vals,
-                                             const uint2* __restrict__ ranges, uint32_t t, float* __restrict__ image)
-{
-    constexpr int SBX = TW / 8, NSB = (TW / 8) * (TH / 8);
-    const TileGeo G = tile_geo(descs, B, ranges, t, TW, TH);
-    const ImgDesc& d = descs[G.b];
-    const int l = lane_id();
-    float lx[NSB], ly[NSB];
-    bool valid[NSB];
-    float C[NSB][3];
-#pragma unroll
-    for (int k = 0; k < NSB; ++k) {
-        const int px = (k % SBX) * 8 + (l & 7), py = (k / SBX) * 8 + (l >> 3);
-        lx[k] = (float)px + 0.5f;
-        ly[k] = (float)py + 0.5f;
-        valid[k] = (G.ox + px) < d.W && (G.oy + py) < d.H;
-        C[k][0] = C[k][1] = C[k][2] = 0.0f;
-    }
-    const float thr2 = kp.q_add * kConicScale;
-    for (uint32_t s = G.start; s < G.end; ++s) {
-        const uint32_t prim = vals[s];
-        uint32_t b0, b1;
-        const PrimU u = load_prim(recs, prim, G.ox, G.oy, &b0, &b1);
-        const uint32_t m = subblock_mask<TW, TH>(b0, b1, G.ox, G.oy);
-        if (m == 0u) continue;
-        const float cr = u.r * u.op, cg = u.g * u.op, cb = u.b * u.op;
-#pragma unroll
-        for (int k = 0; k < NSB; ++k) {
-            if (!(m & (1u << k))) continue;
-            const PairEval p = eval_pair(u, lx[k], ly[k]);
-            const float w = p.e2 >= thr2 ? p.W : 0.0f;
-            C[k][0] = fmaf(cr, w, C[k][0]);
-            C[k][1] = fmaf(cg, w, C[k][1]);
-            C[k][2] = fmaf(cb, w, C[k][2]);
-        }
-    }
-#pragma unroll
-    for (int k = 0; k < NSB; ++k) {
-        if (!valid[k]) continue;
-        const int px = G.ox + (k % SBX) * 8 + (l & 7), py = G.oy + (k / SBX) * 8 + (l >> 3);
-        const uint32_t pix = (uint32_t)d.pix_begin + (uint32_t)(py * d.W + px);
-        float* o = d.out_image ? d.out_image + 3 * (pix - (uint32_t)d.pix_begin) : image + 3 * pix;
-        o[0] = C[k][0];
-        o[1] = C[k][1];
-        o[2] = C[k][2];
-    }
-}
-
-template <int TW, int TH>
-__global__ void __launch_bounds__(kWave * kWpb) k_blend_fwd_add(const ImgDesc* __restrict__ descs, int B, KParams kp,
-                                                                const Rec* __restrict__ recs,
-                                                                const uint32_t* __restrict__ vals,
-                                                                const uint2* __restrict__ ranges,
-                                                                const uint32_t* __restrict__ ovf, uint32_t n_tiles,
-                                                                float* __restrict__ image)
-{
-    if (*ovf) return;   // instance overflow: the sort produced nothing usable
-    const uint32_t t = grid_tile_of_wave();
-    if (t >= n_tiles) return;
-    fwd_tile_add<TW, TH>(descs, B, kp, recs, vals, ranges, t, image);
-}
-
-// Persistent variant: a grid sized to the machine pulls tiles from a queue
-// (longest list first when `order` is given) until it is empty.
-template <int TW, int TH>
-__global__ void __launch_bounds__(kWave * kWpb) k_blend_fwd_add_q(const ImgDesc* __restrict__ descs, int B,
-                                                                  KParams kp, const Rec* __restrict__ recs,
-                                                                  const uint32_t* __restrict__ vals,
-                                                                  const uint2* __restrict__ ranges,
-                                                                  const uint32_t* __restrict__ ovf, uint32_t n_tiles,
-                                                                  const uint32_t* __restrict__ order,
-                                                                  uint32_t* __restrict__ queue,
-                                                                  float* __restrict__ image)
-{
-    if (*ovf) return;
-    for (;;) {
-        uint32_t idx = 0;
-        if (lane_id() == 0) idx = atomicAdd(queue, 1u);
-        idx = (uint32_t)__builtin_amdgcn_readfirstlane((int)idx);
-        if (idx >= n_tiles) break;
-        fwd_tile_add<TW, TH>(descs, B, kp, recs, vals, ranges, order ? order[idx] : idx, image);
-    }
-}
-
-// ------------------------------------------------------------ alpha mode
+// ------------------------------------------------------------ block waves
 
 // One staged primitive (48 bytes).  The forward stages the conic and the
 // frequency pre-scaled as load_prim does; the backward stages them raw and
@@ -314,6 +218,16 @@ __device__ __forceinline__ Staged stage_fwd(const Rec& R, int bx, int by, uint32
     return w;
 }
 
+// Additive forward: colour premultiplied by the opacity (Eq. 4's weight).
+__device__ __forceinline__ Staged stage_add(const Rec& R, int bx, int by, uint32_t pos)
+{
+    Staged w = stage_fwd(R, bx, by, pos);
+    w.r = R.r * R.op;
+    w.g = R.g * R.op;
+    w.b = R.b * R.op;
+    return w;
+}
+
 __device__ __forceinline__ Staged stage_raw(const Rec& R, int bx, int by, uint32_t pos)
 {
     Staged w;
@@ -332,9 +246,12 @@ __device__ __forceinline__ Staged stage_raw(const Rec& R, int bx, int by, uint32
     return w;
 }
 
-// Forward of one 8 x 8 block `blk` of tile t (one wave).
-template <int TW, int TH>
-__device__ __forceinline__ void fwd_block_alpha(const ImgDesc* __restrict__ descs, int B, const KParams& kp,
+// Forward of one 8 x 8 block `blk` of tile t (one wave).  Additive mode
+// tests primitives against the box of the block's pixels inside the image;
+// alpha mode against the box of its pixels still transmitting, which shrinks
+// as pixels terminate.
+template <int MODE, int TW, int TH>
+__device__ __forceinline__ void fwd_block(const ImgDesc* __restrict__ descs, int B, const KParams& kp,
                                                 const Rec* __restrict__ recs, const uint32_t* __restrict__ vals,
                                                 const uint2* __restrict__ ranges, uint32_t t, int blk,
                                                 float* __restrict__ image, float* __restrict__ T_final,
@@ -353,6 +270,7 @@ __device__ __forceinline__ void fwd_block_alpha(const ImgDesc* __restrict__ desc
     int32_t lst = -1;
     bool alive = valid;
     PixBox live = pix_box(alive, px, py);
+    const float thr2 = kp.q_add * kConicScale;
     if (G.start < G.end) {
         const uint32_t e1 = G.end - 1u;
         // records of the current chunk; list entries of the next one
@@ -362,7 +280,9 @@ __device__ __forceinline__ void fwd_block_alpha(const ImgDesc* __restrict__ desc
         for (uint32_t c = G.start;;) {
             const bool hit = box_meets(cur.box0, cur.box1, live);
             const uint64_t m = __ballot(hit);
-            if (hit) stage[__popcll(m & below)] = stage_fwd(cur, bx, by, c + (uint32_t)l);
+            if (hit)
+                stage[__popcll(m & below)] = MODE == WIPES_2D_ADDITIVE ? stage_add(cur, bx, by, c + (uint32_t)l)
+                                                                       : stage_fwd(cur, bx, by, c + (uint32_t)l);
             const uint32_t cn = c + kWave;
             const bool more = cn < G.end;
             Rec nx{};
@@ -377,6 +297,13 @@ __device__ __forceinline__ void fwd_block_alpha(const ImgDesc* __restrict__ desc
             for (int j = 0; j < nh; ++j) {
                 const Staged S = stage[j];
                 const PairEval p = eval_at(S.mrx, S.mry, S.c0, S.c1, S.c2, S.f0, S.f1, lx, ly);
+                if constexpr (MODE == WIPES_2D_ADDITIVE) {
+                    const float w = p.e2 >= thr2 ? p.W : 0.0f;
+                    C0 = fmaf(S.r, w, C0);
+                    C1 = fmaf(S.g, w, C1);
+                    C2 = fmaf(S.b, w, C2);
+                    continue;
+                }
                 const float a = S.op * p.W;
                 bool died = false;
                 if (alive && a >= kp.alpha_min) {
@@ -409,19 +336,25 @@ __device__ __forceinline__ void fwd_block_alpha(const ImgDesc* __restrict__ desc
     if (valid) {
         const uint32_t pix = (uint32_t)d.pix_begin + (uint32_t)(py * d.W + px);
         float* o = d.out_image ? d.out_image + 3 * (pix - (uint32_t)d.pix_begin) : image + 3 * pix;
-        o[0] = fmaf(T, kp.bg[0], C0);
-        o[1] = fmaf(T, kp.bg[1], C1);
-        o[2] = fmaf(T, kp.bg[2], C2);
-        T_final[pix] = T;
-        last[pix] = lst;
+        if constexpr (MODE == WIPES_2D_ADDITIVE) {
+            o[0] = C0;
+            o[1] = C1;
+            o[2] = C2;
+        } else {
+            o[0] = fmaf(T, kp.bg[0], C0);
+            o[1] = fmaf(T, kp.bg[1], C1);
+            o[2] = fmaf(T, kp.bg[2], C2);
+            T_final[pix] = T;
+            last[pix] = lst;
+        }
     }
 }
 
 // Grid form: one workgroup per tile, one wave per block.  Tiles map to
 // workgroups one to one, so the XCDs (which take workgroups round-robin)
 // share the heavy tiles of a cluster instead of one XCD taking a whole band.
-template <int TW, int TH>
-__global__ void __launch_bounds__(TW * TH) k_blend_fwd_alpha(const ImgDesc* __restrict__ descs, int B, KParams kp,
+template <int MODE, int TW, int TH>
+__global__ void __launch_bounds__(TW * TH) k_blend_fwd(const ImgDesc* __restrict__ descs, int B, KParams kp,
                                                              const Rec* __restrict__ recs,
                                                              const uint32_t* __restrict__ vals,
                                                              const uint2* __restrict__ ranges,
@@ -434,13 +367,13 @@ __global__ void __launch_bounds__(TW * TH) k_blend_fwd_alpha(const ImgDesc* __re
     const uint32_t t = blockIdx.x;
     if (t >= n_tiles) return;
     const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-    fwd_block_alpha<TW, TH>(descs, B, kp, recs, vals, ranges, t, w, image, T_final, last, stage[w]);
+    fwd_block<MODE, TW, TH>(descs, B, kp, recs, vals, ranges, t, w, image, T_final, last, stage[w]);
 }
 
 // Persistent form: every wave pulls (tile, block) items from a queue, tiles
 // in `order` (longest list first) when given.
-template <int TW, int TH>
-__global__ void __launch_bounds__(TW * TH) k_blend_fwd_alpha_q(const ImgDesc* __restrict__ descs, int B, KParams kp,
+template <int MODE, int TW, int TH>
+__global__ void __launch_bounds__(TW * TH) k_blend_fwd_q(const ImgDesc* __restrict__ descs, int B, KParams kp,
                                                                const Rec* __restrict__ recs,
                                                                const uint32_t* __restrict__ vals,
                                                                const uint2* __restrict__ ranges,
@@ -460,7 +393,7 @@ __global__ void __launch_bounds__(TW * TH) k_blend_fwd_alpha_q(const ImgDesc* __
         idx = (uint32_t)__builtin_amdgcn_readfirstlane((int)idx);
         if (idx >= n_tiles * NB) break;
         const uint32_t ti = idx / NB;
-        fwd_block_alpha<TW, TH>(descs, B, kp, recs, vals, ranges, order ? order[ti] : ti, (int)(idx - ti * NB), image,
+        fwd_block<MODE, TW, TH>(descs, B, kp, recs, vals, ranges, order ? order[ti] : ti, (int)(idx - ti * NB), image,
                                 T_final, last, stage[w]);
     }
 }
@@ -535,113 +468,16 @@ __device__ __forceinline__ void pair_grads(float v[16], const PairEval& p, float
     v[6] = fmaf(dph, p.dy, v[6]);
 }
 
-template <int TW, int TH>
-__device__ __forceinline__ void bwd_tile_add(const ImgDesc* __restrict__ descs, int B, const KParams& kp,
-                                             const Rec* __restrict__ recs, const uint32_t* __restrict__ vals,
-                                             const uint32_t* __restrict__ eidx, const uint2* __restrict__ ranges,
-                                             uint32_t t, const float* __restrict__ dLdC, float* __restrict__ slots)
-{
-    constexpr int SBX = TW / 8, NSB = (TW / 8) * (TH / 8);
-    const TileGeo G = tile_geo(descs, B, ranges, t, TW, TH);
-    const ImgDesc& d = descs[G.b];
-    const int l = lane_id();
-    float lx[NSB], ly[NSB], g[NSB][3];
-    bool ok[NSB];
-    uint32_t sb_valid = 0;
-#pragma unroll
-    for (int k = 0; k < NSB; ++k) {
-        const int px = (k % SBX) * 8 + (l & 7), py = (k / SBX) * 8 + (l >> 3);
-        lx[k] = (float)px + 0.5f;
-        ly[k] = (float)py + 0.5f;
-        ok[k] = (G.ox + px) < d.W && (G.oy + py) < d.H;
-        const uint32_t pix = (uint32_t)d.pix_begin + (uint32_t)((G.oy + py) * d.W + (G.ox + px));
-        g[k][0] = ok[k] ? dLdC[3 * pix] : 0.0f;
-        g[k][1] = ok[k] ? dLdC[3 * pix + 1] : 0.0f;
-        g[k][2] = ok[k] ? dLdC[3 * pix + 2] : 0.0f;
-        sb_valid |= __ballot(ok[k]) ? (1u << k) : 0u;
-    }
-    const float thr2 = kp.q_add * kConicScale;
-    for (uint32_t s = G.end; s-- > G.start;) {
-        const uint32_t prim = vals[s];
-        uint32_t b0, b1;
-        const PrimU u = load_prim(recs, prim, G.ox, G.oy, &b0, &b1);
-        const uint32_t m = subblock_mask<TW, TH>(b0, b1, G.ox, G.oy) & sb_valid;
-        float v[16];
-#pragma unroll
-        for (int j = 0; j < 16; ++j) v[j] = 0.0f;
-        bool any = false;
-#pragma unroll
-        for (int k = 0; k < NSB; ++k) {
-            if (!(m & (1u << k)) || !ok[k]) continue;
-            const PairEval p = eval_pair(u, lx[k], ly[k]);
-            if (!(p.e2 >= thr2)) continue;
-            const float cg = u.r * g[k][0] + u.g * g[k][1] + u.b * g[k][2];
-            const float ow = u.op * p.W;
-            v[8] = fmaf(ow, g[k][0], v[8]);
-            v[9] = fmaf(ow, g[k][1], v[9]);
-            v[10] = fmaf(ow, g[k][2], v[10]);
-            v[7] = fmaf(p.W, cg, v[7]);
-            any = true;
-            pair_grads(v, p, u.op * cg, u.ca, u.cb, u.cc, u.fx, u.fy);
-        }
-        float* o = slots + (size_t)eidx[s] * kSlot;
-        if (__ballot(any)) {
-            wave_reduce16_valu(v);
-            const int idx = l >> 2;
-            if ((l & 3) == 0 && idx < kSlot) o[idx] = v[0];
-        } else if (l < kSlot) {
-            o[l] = 0.0f;
-        }
-    }
-}
-
-template <int TW, int TH>
-__global__ void __launch_bounds__(kWave * kWpb) k_blend_bwd_add(const ImgDesc* __restrict__ descs, int B, KParams kp,
-                                                                const Rec* __restrict__ recs,
-                                                                const uint32_t* __restrict__ vals,
-                                                                const uint32_t* __restrict__ eidx,
-                                                                const uint2* __restrict__ ranges,
-                                                                const uint32_t* __restrict__ ovf, uint32_t n_tiles,
-                                                                const float* __restrict__ dLdC,
-                                                                float* __restrict__ slots)
-{
-    if (*ovf) return;
-    const uint32_t t = grid_tile_of_wave();
-    if (t >= n_tiles) return;
-    bwd_tile_add<TW, TH>(descs, B, kp, recs, vals, eidx, ranges, t, dLdC, slots);
-}
-
-template <int TW, int TH>
-__global__ void __launch_bounds__(kWave * kWpb) k_blend_bwd_add_q(const ImgDesc* __restrict__ descs, int B,
-                                                                  KParams kp, const Rec* __restrict__ recs,
-                                                                  const uint32_t* __restrict__ vals,
-                                                                  const uint32_t* __restrict__ eidx,
-                                                                  const uint2* __restrict__ ranges,
-                                                                  const uint32_t* __restrict__ ovf, uint32_t n_tiles,
-                                                                  const uint32_t* __restrict__ order,
-                                                                  uint32_t* __restrict__ queue,
-                                                                  const float* __restrict__ dLdC,
-                                                                  float* __restrict__ slots)
-{
-    if (*ovf) return;
-    for (;;) {
-        uint32_t idx = 0;
-        if (lane_id() == 0) idx = atomicAdd(queue, 1u);
-        idx = (uint32_t)__builtin_amdgcn_readfirstlane((int)idx);
-        if (idx >= n_tiles) break;
-        bwd_tile_add<TW, TH>(descs, B, kp, recs, vals, eidx, ranges, order ? order[idx] : idx, dLdC, slots);
-    }
-}
-
-// Alpha backward of tile t by the whole workgroup (wave w = block w).  The
-// waves walk the tile's list in the same chunks of 64 positions, top down
-// from the tile's last contributing position; each wave stages the chunk's
-// primitives that meet its contributing pixels, replays them back to front
-// (recovering T and the colour behind from the forward's T_final), reduces
-// each primitive's gradients over the block, and leaves them in LDS; then the
-// workgroup adds the blocks in a fixed order and writes the chunk's slots.
-template <int TW, int TH>
-__device__ __forceinline__ void bwd_tile_alpha(const ImgDesc* __restrict__ descs, int B, const KParams& kp,
+// Backward of tile t by the whole workgroup (wave w = block w).  The waves
+// walk the tile's list in the same chunks of 64 positions, top down from the
+// tile's last contributing position (alpha; the list end for additive); each
+// wave stages the chunk's primitives that meet its contributing pixels,
+// replays them back to front (alpha: recovering T and the colour behind from
+// the forward's T_final), reduces each primitive's gradients over the block,
+// and leaves them in LDS; then the workgroup adds the blocks in a fixed order
+// and writes the chunk's slots.
+template <int MODE, int TW, int TH>
+__device__ __forceinline__ void bwd_tile(const ImgDesc* __restrict__ descs, int B, const KParams& kp,
                                                const Rec* __restrict__ recs, const uint32_t* __restrict__ vals,
                                                const uint32_t* __restrict__ eidx, const uint2* __restrict__ ranges,
                                                uint32_t t, const float* __restrict__ T_final,
@@ -660,16 +496,18 @@ __device__ __forceinline__ void bwd_tile_alpha(const ImgDesc* __restrict__ descs
     const uint32_t pix = valid ? (uint32_t)d.pix_begin + (uint32_t)(py * d.W + px) : 0u;
     // a `last` outside this tile's list (from a mismatched forward) can only
     // give wrong gradients, never an access outside the list
-    const int32_t lst = min(valid ? last[pix] : -1, (int32_t)G.end - 1);
+    const int32_t lst = MODE == WIPES_2D_ADDITIVE ? (valid ? (int32_t)G.end - 1 : -1)
+                                                  : min(valid ? last[pix] : -1, (int32_t)G.end - 1);
     const bool on = lst >= (int32_t)G.start;
     float T = 0.0f, g0 = 0.0f, g1 = 0.0f, g2 = 0.0f;
     if (on) {
-        T = T_final[pix];
+        if constexpr (MODE == WIPES_3D_ALPHA) T = T_final[pix];
         g0 = dLdC[3 * pix];
         g1 = dLdC[3 * pix + 1];
         g2 = dLdC[3 * pix + 2];
     }
-    float Sg = kp.bg[0] * g0 + kp.bg[1] * g1 + kp.bg[2] * g2;   // dL/dC . colour behind
+    float Sg = kp.bg[0] * g0 + kp.bg[1] * g1 + kp.bg[2] * g2;   // dL/dC . colour behind (alpha)
+    const float thr2 = kp.q_add * kConicScale;
     const float lx = (float)(l & 7) + 0.5f, ly = (float)(l >> 3) + 0.5f;
     const int32_t btop = __builtin_amdgcn_readfirstlane(wave_max_i32(on ? lst : -1));
     const PixBox cbox = pix_box(on, px, py);
@@ -701,7 +539,10 @@ __device__ __forceinline__ void bwd_tile_alpha(const ImgDesc* __restrict__ descs
     if (c0 > G.start && btop >= (int32_t)down(c0)) pn = vals[min(down(c0) + (uint32_t)l, c0 - 1u)];
     for (;;) {
         const uint32_t s = c0 + (uint32_t)l;
-        const bool hit = (int32_t)s <= btop && box_meets(cur.box0, cur.box1, cbox);
+        // only pixels whose last contributing position reaches this chunk can
+        // take part in it (alpha; every pixel in additive mode)
+        const PixBox abox = MODE == WIPES_2D_ADDITIVE ? cbox : pix_box(on && lst >= (int32_t)c0, px, py);
+        const bool hit = (int32_t)s <= btop && box_meets(cur.box0, cur.box1, abox);
         const uint64_t m = __ballot(hit);
         if (hit) {
             st[__popcll(m & below)] = stage_raw(cur, bx, by, s);
@@ -733,9 +574,21 @@ __device__ __forceinline__ void bwd_tile_alpha(const ImgDesc* __restrict__ descs
                 const PairEval p = eval_at(S.mrx, S.mry, S.c0 * kConicScale, S.c1 * (2.0f * kConicScale),
                                            S.c2 * kConicScale, S.f0 * kInv2Pi, S.f1 * kInv2Pi, lx, ly);
                 const float a = S.op * p.W;
-                if (a >= kp.alpha_min) {
+                if constexpr (MODE == WIPES_2D_ADDITIVE) {
+                    if (p.e2 >= thr2) {
+                        const float cg = S.r * g0 + S.g * g1 + S.b * g2;
+                        v[8] = a * g0;
+                        v[9] = a * g1;
+                        v[10] = a * g2;
+                        v[7] = p.W * cg;
+                        any = true;
+                        pair_grads(v, p, S.op * cg, S.c0, S.c1, S.c2, S.f0, S.f1);
+                    }
+                } else if (a >= kp.alpha_min) {
                     const float al = fminf(a, kp.alpha_max);
-                    const float Tb = T / (1.0f - al);
+                    // T before this pair; the hardware reciprocal (1 ulp) keeps the
+                    // recovery within a few ulp of the forward's T per step
+                    const float Tb = T * __builtin_amdgcn_rcpf(1.0f - al);
                     const float cg = S.r * g0 + S.g * g1 + S.b * g2;
                     const float dal = Tb * (cg - Sg);
                     const float wt = Tb * al;
@@ -776,8 +629,8 @@ __device__ __forceinline__ void bwd_tile_alpha(const ImgDesc* __restrict__ descs
     }
 }
 
-template <int TW, int TH>
-__global__ void __launch_bounds__(TW * TH) k_blend_bwd_alpha(const ImgDesc* __restrict__ descs, int B, KParams kp,
+template <int MODE, int TW, int TH>
+__global__ void __launch_bounds__(TW * TH) k_blend_bwd(const ImgDesc* __restrict__ descs, int B, KParams kp,
                                                              const Rec* __restrict__ recs,
                                                              const uint32_t* __restrict__ vals,
                                                              const uint32_t* __restrict__ eidx,
@@ -795,12 +648,12 @@ __global__ void __launch_bounds__(TW * TH) k_blend_bwd_alpha(const ImgDesc* __re
     if (*ovf) return;
     const uint32_t t = blockIdx.x;
     if (t >= n_tiles) return;
-    bwd_tile_alpha<TW, TH>(descs, B, kp, recs, vals, eidx, ranges, t, T_final, last, dLdC, slots, stage, part, top);
+    bwd_tile<MODE, TW, TH>(descs, B, kp, recs, vals, eidx, ranges, t, T_final, last, dLdC, slots, stage, part, top);
 }
 
 // Persistent form: each workgroup pulls whole tiles from the queue.
-template <int TW, int TH>
-__global__ void __launch_bounds__(TW * TH) k_blend_bwd_alpha_q(const ImgDesc* __restrict__ descs, int B, KParams kp,
+template <int MODE, int TW, int TH>
+__global__ void __launch_bounds__(TW * TH) k_blend_bwd_q(const ImgDesc* __restrict__ descs, int B, KParams kp,
                                                                const Rec* __restrict__ recs,
                                                                const uint32_t* __restrict__ vals,
                                                                const uint32_t* __restrict__ eidx,
@@ -825,7 +678,7 @@ __global__ void __launch_bounds__(TW * TH) k_blend_bwd_alpha_q(const ImgDesc* __
         const uint32_t idx = qnext;
         __syncthreads();   // every wave has read `qnext` before it is rewritten
         if (idx >= n_tiles) break;
-        bwd_tile_alpha<TW, TH>(descs, B, kp, recs, vals, eidx, ranges, order ? order[idx] : idx, T_final, last, dLdC,
+        bwd_tile<MODE, TW, TH>(descs, B, kp, recs, vals, eidx, ranges, order ? order[idx] : idx, T_final, last, dLdC,
                                slots, stage, part, top);
     }
 }
@@ -911,30 +764,15 @@ static void launch_fwd_t(const ImgDesc* descs, int B, const KParams& kp, const R
                          hipStream_t s)
 {
     constexpr uint32_t NB = (TW / 8) * (TH / 8);
-    if constexpr (MODE == WIPES_3D_ALPHA) {
-        if (queue) {
-            const uint32_t nb = max(1u, persistent_blocks * kWpb / NB);   // same number of waves
-            hipLaunchKernelGGL((k_blend_fwd_alpha_q<TW, TH>), dim3(nb), dim3(TW * TH), 0, s, descs, B, kp, recs, vals,
-                               ranges, ovf, n_tiles, order, queue, image, T_final, last);
-            return;
-        }
-        if (n_tiles == 0) return;
-        hipLaunchKernelGGL((k_blend_fwd_alpha<TW, TH>), dim3(n_tiles), dim3(TW * TH), 0, s, descs, B, kp, recs, vals,
-                           ranges, ovf, n_tiles, image, T_final, last);
-    } else {
-        (void)T_final;
-        (void)last;
-        if (queue) {
-            if (persistent_blocks == 0) return;
-            hipLaunchKernelGGL((k_blend_fwd_add_q<TW, TH>), dim3(persistent_blocks), dim3(kWave * kWpb), 0, s, descs,
-                               B, kp, recs, vals, ranges, ovf, n_tiles, order, queue, image);
-            return;
-        }
-        const uint32_t nb = (n_tiles + kWpb - 1) / kWpb;
-        if (nb == 0) return;
-        hipLaunchKernelGGL((k_blend_fwd_add<TW, TH>), dim3(nb), dim3(kWave * kWpb), 0, s, descs, B, kp, recs, vals,
-                           ranges, ovf, n_tiles, image);
+    if (queue) {
+        const uint32_t nb = max(1u, persistent_blocks * kWpb / NB);   // same number of waves
+        hipLaunchKernelGGL((k_blend_fwd_q<MODE, TW, TH>), dim3(nb), dim3(TW * TH), 0, s, descs, B, kp, recs, vals,
+                           ranges, ovf, n_tiles, order, queue, image, T_final, last);
+        return;
     }
+    if (n_tiles == 0) return;
+    hipLaunchKernelGGL((k_blend_fwd<MODE, TW, TH>), dim3(n_tiles), dim3(TW * TH), 0, s, descs, B, kp, recs, vals,
+                       ranges, ovf, n_tiles, image, T_final, last);
 }
 
 template <int MODE, int TW, int TH>
@@ -944,30 +782,15 @@ static void launch_bwd_t(const ImgDesc* descs, int B, const KParams& kp, const R
                          const int32_t* last, const float* dLdC, float* slots, hipStream_t s)
 {
     constexpr uint32_t NB = (TW / 8) * (TH / 8);
-    if constexpr (MODE == WIPES_3D_ALPHA) {
-        if (queue) {
-            const uint32_t nb = max(1u, persistent_blocks * kWpb / NB);
-            hipLaunchKernelGGL((k_blend_bwd_alpha_q<TW, TH>), dim3(nb), dim3(TW * TH), 0, s, descs, B, kp, recs, vals,
-                               eidx, ranges, ovf, n_tiles, order, queue, T_final, last, dLdC, slots);
-            return;
-        }
-        if (n_tiles == 0) return;
-        hipLaunchKernelGGL((k_blend_bwd_alpha<TW, TH>), dim3(n_tiles), dim3(TW * TH), 0, s, descs, B, kp, recs, vals,
-                           eidx, ranges, ovf, n_tiles, T_final, last, dLdC, slots);
-    } else {
-        (void)T_final;
-        (void)last;
-        if (queue) {
-            if (persistent_blocks == 0) return;
-            hipLaunchKernelGGL((k_blend_bwd_add_q<TW, TH>), dim3(persistent_blocks), dim3(kWave * kWpb), 0, s, descs,
-                               B, kp, recs, vals, eidx, ranges, ovf, n_tiles, order, queue, dLdC, slots);
-            return;
-        }
-        const uint32_t nb = (n_tiles + kWpb - 1) / kWpb;
-        if (nb == 0) return;
-        hipLaunchKernelGGL((k_blend_bwd_add<TW, TH>), dim3(nb), dim3(kWave * kWpb), 0, s, descs, B, kp, recs, vals,
-                           eidx, ranges, ovf, n_tiles, dLdC, slots);
+    if (queue) {
+        const uint32_t nb = max(1u, persistent_blocks * kWpb / NB);
+        hipLaunchKernelGGL((k_blend_bwd_q<MODE, TW, TH>), dim3(nb), dim3(TW * TH), 0, s, descs, B, kp, recs, vals,
+                           eidx, ranges, ovf, n_tiles, order, queue, T_final, last, dLdC, slots);
+        return;
     }
+    if (n_tiles == 0) return;
+    hipLaunchKernelGGL((k_blend_bwd<MODE, TW, TH>), dim3(n_tiles), dim3(TW * TH), 0, s, descs, B, kp, recs, vals,
+                       eidx, ranges, ovf, n_tiles, T_final, last, dLdC, slots);
 }
 
 #define WIPES_TILE_DISPATCH(FN, MODE, ...)                                          \

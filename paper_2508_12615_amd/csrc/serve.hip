@@ -1,16 +1,17 @@
 // Serving: resident scenes, render requests admitted by HBM footprint, and
 // continuous batching over two HIP streams.
 //
-// A worker thread owns the device work.  Each turn it
-//   1. retires finished batches (their requests complete, arena memory and
-//      request slots return),
-//   2. admits the longest FIFO prefix of pending requests that fits the free
-//      slots, the batch limit and one contiguous arena block (head-of-line:
-//      a request that does not fit blocks those behind it, so nothing starves),
-//   3. runs projection and binning of the admitted batch on the prep stream
-//      (one host synchronisation for the instance count) and the persistent
-//      tile-queue forward blend of all its requests -- mixed resolutions, one
-//      launch -- on the blend stream, ordered by an event.
+// Two threads own the device work:
+//  * the worker admits the longest FIFO prefix of pending requests that fits
+//    the free request slots, the batch limit and one contiguous arena block
+//    (head-of-line: a request that does not fit blocks those behind it, so
+//    nothing starves), then runs projection and binning of the batch on the
+//    prep stream (one host synchronisation for the instance count) and the
+//    tile-queue forward blend of all its requests -- mixed resolutions, one
+//    launch -- on the blend stream, ordered by an event;
+//  * the completion thread waits on the oldest in-flight batch's event and
+//    retires it the moment the GPU is done (its requests complete, arena
+//    memory and request slots return, the worker is woken).
 // While batch k blends, batch k+1 is already being projected and sorted, so
 // requests that arrive during a launch are admitted as soon as slots and
 // memory allow.  Every request's image depends only on its scene, camera and
@@ -152,9 +153,10 @@ struct wipes_server {
     std::deque<uint64_t> pending;
     uint64_t next_id = 1;
     std::deque<SBatch> inflight;
+    int launching = 0;        // batches taken off `pending` and not yet in flight
     int slots_used = 0;
-    std::thread worker;
-    bool stop = false;
+    std::thread worker, completer;
+    bool stop = false, worker_done = false;
     std::string err;
     std::vector<double> lat_ms;
     double t_first = -1.0, t_last = -1.0;
@@ -164,6 +166,8 @@ struct wipes_server {
 
 namespace {
 
+// Takes an event from the pool (caller holds the lock: the completion thread
+// returns events to the pool concurrently).
 hipEvent_t get_event(wipes_server* S)
 {
     if (!S->ev_pool.empty()) {
@@ -194,30 +198,46 @@ int64_t capacity_for(const std::vector<wipes_image>& ims, const std::vector<doub
     return (int64_t)std::min(k * 1.15 + 4096.0, 2.0e9);
 }
 
-void retire(wipes_server* S)
+// Completes the oldest in-flight batch (its done event has been reached).
+// Called with the lock held.
+void retire_front(wipes_server* S)
 {
-    while (!S->inflight.empty()) {
-        SBatch& b = S->inflight.front();
-        if (hipEventQuery(b.done) != hipSuccess) break;
-        const double t = now_s();
-        for (uint64_t id : b.ids) {
-            SReq& r = S->reqs[id];
-            r.t_done = t;
-            S->lat_ms.push_back((t - r.t_submit) * 1e3);
-            S->scenes[r.scene].refs--;
-            S->slots_used--;
-        }
-        S->t_last = t;
-        S->arena.release(b.off, b.bytes);
-        S->ev_pool.push_back(b.prep);
-        S->ev_pool.push_back(b.done);
-        S->inflight.pop_front();
+    SBatch& b = S->inflight.front();
+    const double t = now_s();
+    for (uint64_t id : b.ids) {
+        SReq& r = S->reqs[id];
+        r.t_done = t;
+        S->lat_ms.push_back((t - r.t_submit) * 1e3);
+        S->scenes[r.scene].refs--;
+        S->slots_used--;
+    }
+    S->t_last = t;
+    S->arena.release(b.off, b.bytes);
+    S->ev_pool.push_back(b.prep);
+    S->ev_pool.push_back(b.done);
+    S->inflight.pop_front();
+}
+
+void completer_main(wipes_server* S)
+{
+    (void)hipSetDevice(S->device);
+    std::unique_lock<std::mutex> lk(S->mu);
+    for (;;) {
+        S->cv.wait(lk, [&] { return !S->inflight.empty() || (S->stop && S->worker_done); });
+        if (S->inflight.empty()) break;   // stopping, nothing left in flight
+        hipEvent_t done = S->inflight.front().done;
+        lk.unlock();
+        const hipError_t e = hipEventSynchronize(done);
+        lk.lock();
+        if (e != hipSuccess && S->err.empty()) S->err = hipGetErrorString(e);
+        retire_front(S);
+        S->cv.notify_all();
     }
 }
 
 // Project, bin, sort (prep stream) and blend (blend stream) one batch.
-// Called without the lock; touches only worker-owned state (arena, streams,
-// context).  *K_out receives the batch's instance count.
+// Called without the lock; takes it only for the arena (shared with the
+// completion thread).  *K_out receives the batch's instance count.
 wipes_status launch_batch(wipes_server* S, std::vector<wipes_image>& ims, int64_t cap, SBatch& B, int64_t* K_out)
 {
     wipes_batch b{(int32_t)ims.size(), ims.data()};
@@ -225,20 +245,15 @@ wipes_status launch_batch(wipes_server* S, std::vector<wipes_image>& ims, int64_
         Layout L;
         const size_t bytes = batch_bytes(&S->params, ims, cap, &L);
         size_t off = 0;
-        while (!S->arena.alloc(bytes, &off)) {
-            // wait for the oldest in-flight batch to free memory
-            bool empty;
-            {
-                std::lock_guard<std::mutex> lk(S->mu);
-                empty = S->inflight.empty();
-            }
-            if (empty) return fail(S->ctx, WIPES_ERR_NOMEM, "batch exceeds the serving arena");
-            (void)hipEventSynchronize(S->inflight.front().done);
-            std::lock_guard<std::mutex> lk(S->mu);
-            retire(S);
-            S->cv.notify_all();
+        {
+            // wait for in-flight batches to free memory (the completion thread
+            // releases it and notifies)
+            std::unique_lock<std::mutex> lk(S->mu);
+            bool ok = false;
+            S->cv.wait(lk, [&] { return (ok = S->arena.alloc(bytes, &off)) || S->inflight.empty(); });
+            if (!ok) return fail(S->ctx, WIPES_ERR_NOMEM, "batch exceeds the serving arena");
+            S->arena_peak = std::max(S->arena_peak, S->arena.used());
         }
-        S->arena_peak = std::max(S->arena_peak, S->arena.used());
         char* base = (char*)S->arena_mem + off;
         wipes_buffer sb{base, L.screen_bytes, 0, 0, 0};
         wipes_buffer bb{base + al(L.screen_bytes), L.bins_bytes, cap, 0, 0};
@@ -247,18 +262,17 @@ wipes_status launch_batch(wipes_server* S, std::vector<wipes_image>& ims, int64_
         wipes_status st = wipes_project(S->ctx, &S->params, &b, &sb, S->s_prep);
         int64_t K = 0;
         if (st == WIPES_OK) st = wipes_bin_sort(S->ctx, &S->params, &b, &sb, &bb, &K, S->s_prep);
-        if (st == WIPES_ERR_CAPACITY) {
+        if (st == WIPES_ERR_CAPACITY || st != WIPES_OK) {
+            std::lock_guard<std::mutex> lk(S->mu);
             S->arena.release(off, bytes);
+            S->cv.notify_all();
+        }
+        if (st == WIPES_ERR_CAPACITY) {
             cap = (int64_t)(K * 1.1) + 4096;
             continue;
         }
-        if (st != WIPES_OK) {
-            S->arena.release(off, bytes);
-            return st;
-        }
+        if (st != WIPES_OK) return st;
         *K_out = K;
-        B.prep = get_event(S);
-        B.done = get_event(S);
         (void)hipEventRecord(B.prep, S->s_prep);
         (void)hipStreamWaitEvent(S->s_blend, B.prep, 0);
         // every image writes to its request's buffer; the batch image array is unused
@@ -266,7 +280,9 @@ wipes_status launch_batch(wipes_server* S, std::vector<wipes_image>& ims, int64_
         (void)hipEventRecord(B.done, S->s_blend);
         if (st != WIPES_OK) {
             (void)hipStreamSynchronize(S->s_blend);
+            std::lock_guard<std::mutex> lk(S->mu);
             S->arena.release(off, bytes);
+            S->cv.notify_all();
             return st;
         }
         B.off = off;
@@ -281,9 +297,10 @@ void worker_main(wipes_server* S)
     (void)hipSetDevice(S->device);
     std::unique_lock<std::mutex> lk(S->mu);
     for (;;) {
-        retire(S);
-        S->cv.notify_all();
-        if (S->stop && S->pending.empty() && S->inflight.empty()) break;
+        S->cv.wait(lk, [&] {
+            return (S->stop && S->pending.empty()) || (!S->pending.empty() && S->slots_used < S->cfg.max_slots);
+        });
+        if (S->pending.empty()) break;   // stopping with nothing pending
         // admission
         const size_t free_slots = (size_t)std::max(0, S->cfg.max_slots - S->slots_used);
         const size_t max_take = std::min(free_slots, (size_t)S->cfg.max_batch);
@@ -315,7 +332,19 @@ void worker_main(wipes_server* S)
             }
         }
         if (take == 0) {
-            S->cv.wait_for(lk, std::chrono::microseconds(S->inflight.empty() ? 1000 : 50));
+            if (S->inflight.empty()) {
+                // the head request does not fit even an empty arena: it fails
+                SReq& r = S->reqs[S->pending.front()];
+                r.t_done = now_s();
+                S->scenes[r.scene].refs--;
+                S->pending.pop_front();
+                S->err = "request exceeds the serving arena";
+                S->cv.notify_all();
+                continue;
+            }
+            // wait for the completion thread to free memory
+            const size_t n_inflight = S->inflight.size();
+            S->cv.wait(lk, [&] { return S->inflight.size() < n_inflight; });
             continue;
         }
         SBatch B;
@@ -330,12 +359,19 @@ void worker_main(wipes_server* S)
         const int64_t cap = capacity_for(cand, ratio);
         S->slots_used += (int)take;
         S->n_admitted += (int64_t)take;
+        S->launching++;
+        // the batch's events come from the pool while the lock is held
+        B.prep = get_event(S);
+        B.done = get_event(S);
         lk.unlock();
         int64_t K = 0;
         wipes_status st = launch_batch(S, cand, cap, B, &K);
         lk.lock();
+        S->launching--;
         if (st != WIPES_OK) {
             // the batch failed: its requests complete without an image; the error is kept
+            S->ev_pool.push_back(B.prep);
+            S->ev_pool.push_back(B.done);
             S->err = S->ctx->err;
             for (uint64_t id : B.ids) {
                 SReq& r = S->reqs[id];
@@ -343,6 +379,7 @@ void worker_main(wipes_server* S)
                 S->scenes[r.scene].refs--;
                 S->slots_used--;
             }
+            S->cv.notify_all();
             continue;
         }
         // learn instances per primitive for the next footprint estimates
@@ -358,7 +395,10 @@ void worker_main(wipes_server* S)
         S->n_batches++;
         S->n_batched += (int64_t)take;
         S->inflight.push_back(std::move(B));
+        S->cv.notify_all();
     }
+    S->worker_done = true;
+    S->cv.notify_all();
 }
 
 }  // namespace
@@ -396,6 +436,7 @@ wipes_status wipes_serve_create(const wipes_serve_config* cfg, const wipes_param
     }
     S->arena.reset((size_t)cfg->hbm_budget_bytes);
     S->worker = std::thread(worker_main, S);
+    S->completer = std::thread(completer_main, S);
     *out = S;
     return WIPES_OK;
 }
@@ -492,7 +533,7 @@ wipes_status wipes_serve_drain(wipes_server* S)
 {
     if (!S) return fail(nullptr, WIPES_ERR_INVALID, "server must be set");
     std::unique_lock<std::mutex> lk(S->mu);
-    S->cv.wait(lk, [&] { return S->pending.empty() && S->inflight.empty(); });
+    S->cv.wait(lk, [&] { return S->pending.empty() && S->launching == 0 && S->inflight.empty(); });
     if (!S->err.empty()) return fail(nullptr, WIPES_ERR_DEVICE, "%s", S->err.c_str());
     return WIPES_OK;
 }
@@ -543,6 +584,7 @@ void wipes_serve_destroy(wipes_server* S)
         S->cv.notify_all();
     }
     if (S->worker.joinable()) S->worker.join();
+    if (S->completer.joinable()) S->completer.join();
     (void)hipSetDevice(S->device);
     for (auto& kv : S->scenes) hipFree(kv.second.mem);
     for (hipEvent_t e : S->ev_pool) hipEventDestroy(e);

@@ -121,14 +121,17 @@ def run_plain(rast: Rasterizer, scenes: list, requests: list, outs: list):
 
 def run_served(server: Server, scene_ids: list, requests: list, outs: list):
     """Submit requests at their arrival times (client thread = caller), then drain.
-    Returns latencies (ms) as measured by the server and the makespan."""
+    Returns latencies (ms, scheduled arrival -> completion, like run_plain: the
+    server's submit -> completion time plus the client's delay from the
+    scheduled arrival to the submit call) and the makespan."""
     t0 = time.perf_counter()
-    ids = []
+    ids, late = [], []
     for req, out in zip(requests, outs):
         now = time.perf_counter() - t0
         if req["t_arrive"] > now:
             time.sleep(req["t_arrive"] - now)
+        late.append((time.perf_counter() - t0 - req["t_arrive"]) * 1e3)
         ids.append(server.submit(scene_ids[req["scene"]], req["camera"], out))
     server.drain()
-    lat = [server.poll(i)[1] for i in ids]
+    lat = [server.poll(i)[1] + d for i, d in zip(ids, late)]
     return np.array(lat), time.perf_counter() - t0
