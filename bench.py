@@ -80,7 +80,8 @@ def bench_serving(n_req, log, persistent=1, load=0.8):
     log("serving: plain done")
     srv = Server(max_slots=16, max_batch=8, persistent=persistent, hbm_budget_bytes=4 << 30)
     ids = [srv.load_scene(sc) for sc in scenes]
-    run_served(srv, ids, [dict(r, t_arrive=0.0) for r in probe[:16]], outs[:16])   # warm-up
+    warm = [torch.empty((r["camera"]["height"], r["camera"]["width"], 3), device=dev) for r in probe[:16]]
+    run_served(srv, ids, [dict(r, t_arrive=0.0) for r in probe[:16]], warm)   # warm-up
     srv.reset_stats()
     lat_s, span_s = run_served(srv, ids, reqs, outs)
     st = srv.stats()

@@ -353,7 +353,7 @@ void wipes_ctx_destroy(wipes_ctx* ctx)
             (void)hipEventDestroy(pr.first);
             (void)hipEventDestroy(pr.second);
         }
-    for (hipEvent_t e : ctx->prof.pool) hipEventDestroy(e);
+    for (hipEvent_t e : ctx->prof.pool) (void)hipEventDestroy(e);
     for (int i = 0; i < kRing; ++i) {
         if (ctx->ring[i].ev) {
             (void)hipEventSynchronize(ctx->ring[i].ev);
@@ -477,7 +477,7 @@ wipes_status wipes_check_overflow(wipes_ctx* ctx, const wipes_params* p, const w
     wipes_status st = prologue(ctx, p, b, screen, nullptr, false, false, &L);
     if (st != WIPES_OK) return st;
     if (!required_instances) return fail(ctx, WIPES_ERR_INVALID, "required_instances must not be NULL");
-    uint32_t ctrl[kCtrlWords];
+    uint32_t ctrl[kCtrlHead];
     hipError_t e = hipMemcpyAsync(ctrl, (char*)screen->base + L.s_ctrl, sizeof(ctrl), hipMemcpyDeviceToHost,
                                   (hipStream_t)stream);
     if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)stream);

@@ -15,7 +15,18 @@ constexpr int kRing = 8;
 constexpr size_t kStagingBytes = (size_t)kMaxImages * sizeof(wipes::ImgDesc);
 
 // device control words at Layout::s_ctrl
-enum { kCtrlK = 0, kCtrlNEff = 1, kCtrlOverflow = 2, kCtrlQueueFwd = 4, kCtrlQueueBwd = 5, kCtrlWords = 16 };
+// (words 0..kCtrlHead-1 are read back by wipes_check_overflow; 8..15 hold
+// the work-count totals; the two persistent queues follow, one 256-byte line
+// per counter)
+enum {
+    kCtrlK = 0,
+    kCtrlNEff = 1,
+    kCtrlOverflow = 2,
+    kCtrlHead = 16,
+    kCtrlQueueFwd = 64,
+    kCtrlQueueBwd = kCtrlQueueFwd + wipes::kQueueLanes * wipes::kQueueStride,
+    kCtrlWords = kCtrlQueueBwd + wipes::kQueueLanes * wipes::kQueueStride
+};
 
 struct StagingSlot {
     void* host = nullptr;

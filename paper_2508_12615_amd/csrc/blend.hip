@@ -160,6 +160,27 @@ __device__ __forceinline__ void wave_lds_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Next tile from the persistent queue (called by one thread): counter
+// `lane` first, then the others in turn once it runs dry, so every tile is
+// handed out exactly once and a workgroup never waits on an empty lane while
+// another has work.  Returns n_tiles when all are taken.
+__device__ __forceinline__ uint32_t pull_tile(uint32_t* __restrict__ queue, uint32_t n_tiles,
+                                              const uint32_t* __restrict__ order, uint32_t& lane)
+{
+    for (int tries = 0; tries < kQueueLanes; ++tries) {
+        const uint32_t x = (lane + (uint32_t)tries) % kQueueLanes;
+        const uint32_t nx = n_tiles > x ? (n_tiles - x + kQueueLanes - 1) / kQueueLanes : 0u;
+        if (nx == 0) continue;
+        const uint32_t j = atomicAdd(queue + x * kQueueStride, 1u);
+        if (j < nx) {
+            lane = x;
+            const uint32_t i = x + kQueueLanes * j;
+            return order ? order[i] : i;
+        }
+    }
+    return n_tiles;
+}
+
 // ------------------------------------------------------------ block waves
 
 // One staged primitive (48 bytes).  The forward stages the conic and the
@@ -370,31 +391,31 @@ __global__ void __launch_bounds__(TW * TH) k_blend_fwd(const ImgDesc* __restrict
     fwd_block<MODE, TW, TH>(descs, B, kp, recs, vals, ranges, t, w, image, T_final, last, stage[w]);
 }
 
-// Persistent form: every wave pulls (tile, block) items from a queue, tiles
-// in `order` (longest list first) when given.
+// Persistent form: each workgroup pulls whole tiles from the queue (tiles in
+// `order`, longest list first, when given).
 template <int MODE, int TW, int TH>
 __global__ void __launch_bounds__(TW * TH) k_blend_fwd_q(const ImgDesc* __restrict__ descs, int B, KParams kp,
-                                                               const Rec* __restrict__ recs,
-                                                               const uint32_t* __restrict__ vals,
-                                                               const uint2* __restrict__ ranges,
-                                                               const uint32_t* __restrict__ ovf, uint32_t n_tiles,
-                                                               const uint32_t* __restrict__ order,
-                                                               uint32_t* __restrict__ queue,
-                                                               float* __restrict__ image, float* __restrict__ T_final,
-                                                               int32_t* __restrict__ last)
+                                                         const Rec* __restrict__ recs,
+                                                         const uint32_t* __restrict__ vals,
+                                                         const uint2* __restrict__ ranges,
+                                                         const uint32_t* __restrict__ ovf, uint32_t n_tiles,
+                                                         const uint32_t* __restrict__ order,
+                                                         uint32_t* __restrict__ queue, float* __restrict__ image,
+                                                         float* __restrict__ T_final, int32_t* __restrict__ last)
 {
-    constexpr uint32_t NB = (TW / 8) * (TH / 8);
+    constexpr int NB = (TW / 8) * (TH / 8);
     __shared__ Staged stage[NB][kWave];
+    __shared__ uint32_t qtile;
     if (*ovf) return;
     const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    uint32_t lane = blockIdx.x % kQueueLanes;
     for (;;) {
-        uint32_t idx = 0;
-        if (lane_id() == 0) idx = atomicAdd(queue, 1u);
-        idx = (uint32_t)__builtin_amdgcn_readfirstlane((int)idx);
-        if (idx >= n_tiles * NB) break;
-        const uint32_t ti = idx / NB;
-        fwd_block<MODE, TW, TH>(descs, B, kp, recs, vals, ranges, order ? order[ti] : ti, (int)(idx - ti * NB), image,
-                                T_final, last, stage[w]);
+        if (threadIdx.x == 0) qtile = pull_tile(queue, n_tiles, order, lane);
+        __syncthreads();
+        const uint32_t t = qtile;
+        __syncthreads();   // every wave has read `qtile` before it is rewritten
+        if (t >= n_tiles) break;
+        fwd_block<MODE, TW, TH>(descs, B, kp, recs, vals, ranges, t, w, image, T_final, last, stage[w]);
     }
 }
 
@@ -670,16 +691,17 @@ __global__ void __launch_bounds__(TW * TH) k_blend_bwd_q(const ImgDesc* __restri
     __shared__ Staged stage[NB][kWave];
     __shared__ __attribute__((aligned(16))) float part[NB * kWave * kSlot];
     __shared__ uint32_t top[NB];
-    __shared__ uint32_t qnext;
+    __shared__ uint32_t qtile;
     if (*ovf) return;
+    uint32_t lane = blockIdx.x % kQueueLanes;
     for (;;) {
-        if (threadIdx.x == 0) qnext = atomicAdd(queue, 1u);
+        if (threadIdx.x == 0) qtile = pull_tile(queue, n_tiles, order, lane);
         __syncthreads();
-        const uint32_t idx = qnext;
-        __syncthreads();   // every wave has read `qnext` before it is rewritten
-        if (idx >= n_tiles) break;
-        bwd_tile<MODE, TW, TH>(descs, B, kp, recs, vals, eidx, ranges, order ? order[idx] : idx, T_final, last, dLdC,
-                               slots, stage, part, top);
+        const uint32_t t = qtile;
+        __syncthreads();   // every wave has read `qtile` before it is rewritten
+        if (t >= n_tiles) break;
+        bwd_tile<MODE, TW, TH>(descs, B, kp, recs, vals, eidx, ranges, t, T_final, last, dLdC, slots, stage, part,
+                               top);
     }
 }
 

@@ -17,6 +17,13 @@
 namespace wipes {
 
 constexpr int kWave = 64;
+
+// Persistent tile queue: kQueueLanes counters, kQueueStride words apart (one
+// 256-byte line each); counter x hands out the tiles at positions x, x + 8,
+// x + 16, ... of the tile order, so the XCDs (which take workgroups
+// round-robin) pull from different lines instead of all contending for one.
+constexpr int kQueueLanes = 8;
+constexpr int kQueueStride = 64;
 constexpr float kLog2e = 1.4426950408889634f;
 constexpr float kInv2Pi = 0.15915494309189535f;
 

@@ -166,7 +166,7 @@ wipes_status render_fwd_core(wipes_ctx* ctx, const wipes_params* p, const wipes_
     const uint32_t* order = p->persistent == 2 ? tile_order(L, v) : nullptr;
     if (p->persistent) {
         queue = v.ctrl + kCtrlQueueFwd;
-        HIP_TRY(launch_fill_u32(queue, 1, 0u, s), "queue reset");
+        HIP_TRY(launch_fill_u32(queue, kQueueLanes * kQueueStride, 0u, s), "queue reset");
         pblocks = (uint32_t)ctx->n_cu * 8u;
     }
     StageScope sc(ctx, kStBlendFwd, s);
@@ -189,7 +189,7 @@ wipes_status render_bwd_core(wipes_ctx* ctx, const wipes_params* p, const wipes_
     const uint32_t* order = p->persistent == 2 ? tile_order(L, v) : nullptr;
     if (p->persistent) {
         queue = v.ctrl + kCtrlQueueBwd;
-        HIP_TRY(launch_fill_u32(queue, 1, 0u, s), "queue reset");
+        HIP_TRY(launch_fill_u32(queue, kQueueLanes * kQueueStride, 0u, s), "queue reset");
         pblocks = (uint32_t)ctx->n_cu * 8u;
     }
     {

@@ -71,6 +71,14 @@ class Server:
         return B.check(B.lib().wipes_serve_unload_scene(self.h, sid), allow=(B.WIPES_ERR_BUSY,))
 
     def submit(self, sid: int, camera: dict, out: torch.Tensor) -> int:
+        """Queue a render of scene `sid` from `camera` into `out`, a contiguous
+        float32 device tensor of height * width * 3 elements (checked here: the
+        library writes through the raw pointer)."""
+        W, H = int(camera["width"]), int(camera["height"])
+        if (out.dtype != torch.float32 or not out.is_cuda or not out.is_contiguous()
+                or out.numel() != W * H * 3):
+            raise ValueError("out must be a contiguous float32 CUDA tensor of %dx%dx3 elements, got %s %s"
+                             % (H, W, tuple(out.shape), out.dtype))
         rid = C.c_uint64()
         B.check(B.lib().wipes_serve_submit(self.h, sid, C.byref(make_camera(camera)), out.data_ptr(), C.byref(rid)))
         return rid.value

@@ -74,6 +74,21 @@ def test_scene_lifetime_and_queue_limits():
     srv.close()
 
 
+def test_submit_rejects_mis_sized_output():
+    """The library writes through the raw output pointer, so the client checks
+    the buffer against the camera before anything is queued."""
+    sc = scenes()
+    srv = Server(max_slots=2, max_batch=1, hbm_budget_bytes=1 << 30)
+    a = srv.load_scene(sc[0])
+    cam = synth.orbit_camera(5, 640, 360)
+    for bad in (torch.empty((180, 320, 3), device="cuda"), torch.empty((360, 640, 3), device="cuda").t(),
+                torch.empty((360, 640, 3), dtype=torch.float64, device="cuda")):
+        with pytest.raises(ValueError):
+            srv.submit(a, cam, bad)
+    assert srv.stats()["admitted"] == 0
+    srv.close()
+
+
 def test_small_budget_defers_but_completes():
     """With an arena that holds about one request's workspace, requests wait for memory and still
     all complete."""
