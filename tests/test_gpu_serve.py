@@ -81,7 +81,7 @@ def test_submit_rejects_mis_sized_output():
     srv = Server(max_slots=2, max_batch=1, hbm_budget_bytes=1 << 30)
     a = srv.load_scene(sc[0])
     cam = synth.orbit_camera(5, 640, 360)
-    for bad in (torch.empty((180, 320, 3), device="cuda"), torch.empty((360, 640, 3), device="cuda").t(),
+    for bad in (torch.empty((180, 320, 3), device="cuda"), torch.empty((640, 360, 3), device="cuda").transpose(0, 1),
                 torch.empty((360, 640, 3), dtype=torch.float64, device="cuda")):
         with pytest.raises(ValueError):
             srv.submit(a, cam, bad)
