@@ -226,17 +226,22 @@ wipes_status wipes_bin_sort(wipes_ctx* ctx, const wipes_params* p, const wipes_b
 
 /* Forward blend (Eq. 3 or Eq. 4 with W').  image: device [sum W H, 3];
  * T_final, last: device [sum W H] (alpha mode; may be NULL in additive mode).
- * last holds the sorted-list position of the last contributing pair (-1: none). */
+ * last holds the sorted-list position of the last contributing pair (-1: none).
+ * With a bins buffer sized with_backward, the forward also records, per 8 x 8
+ * pixel block of each tile, which list positions contributed to a pixel of the
+ * block; wipes_render_bwd replays exactly those. */
 wipes_status wipes_render_fwd(wipes_ctx* ctx, const wipes_params* p, const wipes_batch* batch,
                               const wipes_buffer* screen, const wipes_buffer* bins, float* image, float* T_final,
                               int32_t* last, void* stream);
 
 /* Backward pass: dL/dimage (device [sum W H, 3]) -> parameter gradients
  * written to each image's grads.  Alpha mode walks each pixel's list back
- * to front from `last`, recovering transmittance by division (nothing per
- * pair is stored by the forward).  dscreen (optional, device [sum n, 11])
- * receives the screen-space gradients d/d(mu'x, mu'y, ca, cb, cc, f'x, f'y,
- * opacity, r, g, b).  Needs the bins buffer sized with_backward. */
+ * to front from `last`, recovering transmittance by dividing by (1 - alpha)
+ * (nothing per pair is stored by the forward).  dscreen (optional, device
+ * [sum n, 11]) receives the screen-space gradients d/d(mu'x, mu'y, ca, cb, cc,
+ * f'x, f'y, opacity, r, g, b).  Needs the bins buffer sized with_backward, on
+ * which wipes_render_fwd has run after the last wipes_bin_sort (the backward
+ * reads the forward's per-block contribution record from it). */
 wipes_status wipes_render_bwd(wipes_ctx* ctx, const wipes_params* p, const wipes_batch* batch,
                               const wipes_buffer* screen, const wipes_buffer* bins, const float* T_final,
                               const int32_t* last, const float* dL_dimage, float* dscreen, void* stream);

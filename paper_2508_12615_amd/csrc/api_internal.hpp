@@ -69,6 +69,8 @@ struct Layout {
     size_t s_bsum, s_bsum2, s_ctrl, s_descs, screen_bytes;
     // bins buffer
     size_t b_keys_a, b_vals_a, b_keys_b, b_vals_b, b_hist, b_dtot, b_ranges, b_order, b_tbsum, b_w_a, b_w_b, b_slots;
+    size_t b_cmask;           // per 8x8 block of a tile, one bit per list position (backward only)
+    uint32_t cmask_words;     // 64-bit words per block row of the mask
     size_t bins_bytes;
     int tile_bits = 1;
     int tile_result_b = 0;    // tile sort result in the *_b arrays
@@ -134,11 +136,12 @@ hipError_t radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, ui
 hipError_t launch_blend_fwd(const ImgDesc* descs, int B, const KParams& kp, const Rec* recs, const uint32_t* vals,
                             const uint2* ranges, const uint32_t* ovf, uint32_t n_tiles, const uint32_t* order,
                             uint32_t* queue, uint32_t persistent_blocks, float* image, float* T_final, int32_t* last,
-                            hipStream_t s);
+                            unsigned long long* cmask, uint32_t cmask_words, hipStream_t s);
 hipError_t launch_blend_bwd(const ImgDesc* descs, int B, const KParams& kp, const Rec* recs, const uint32_t* vals,
                             const uint32_t* eidx, const uint2* ranges, const uint32_t* ovf, uint32_t n_tiles,
                             const uint32_t* order, uint32_t* queue, uint32_t persistent_blocks, const float* T_final,
-                            const int32_t* last, const float* dLdC, float* slots, hipStream_t s);
+                            const int32_t* last, const float* dLdC, float* slots, const unsigned long long* cmask,
+                            uint32_t cmask_words, hipStream_t s);
 hipError_t launch_l2_grad(const ImgDesc* descs, int B, int32_t npix, const float* image, const float* target,
                           float* grad, hipStream_t s);
 hipError_t launch_pair_stats(const ImgDesc* descs, int B, const KParams& kp, const Rec* recs, const uint32_t* vals,

@@ -273,10 +273,11 @@ __device__ __forceinline__ Staged stage_raw(const Rec& R, int bx, int by, uint32
 // as pixels terminate.
 template <int MODE, int TW, int TH>
 __device__ __forceinline__ void fwd_block(const ImgDesc* __restrict__ descs, int B, const KParams& kp,
-                                                const Rec* __restrict__ recs, const uint32_t* __restrict__ vals,
-                                                const uint2* __restrict__ ranges, uint32_t t, int blk,
-                                                float* __restrict__ image, float* __restrict__ T_final,
-                                                int32_t* __restrict__ last, Staged* __restrict__ stage)
+                                          const Rec* __restrict__ recs, const uint32_t* __restrict__ vals,
+                                          const uint2* __restrict__ ranges, uint32_t t, int blk,
+                                          float* __restrict__ image, float* __restrict__ T_final,
+                                          int32_t* __restrict__ last, unsigned long long* __restrict__ cmask,
+                                          uint32_t cmask_words, Staged* __restrict__ stage)
 {
     const TileGeo G = tile_geo(descs, B, ranges, t, TW, TH);
     const ImgDesc& d = descs[G.b];
@@ -292,19 +293,25 @@ __device__ __forceinline__ void fwd_block(const ImgDesc* __restrict__ descs, int
     bool alive = valid;
     PixBox live = pix_box(alive, px, py);
     const float thr2 = kp.q_add * kConicScale;
+    unsigned long long* cm_row = cmask ? cmask + (size_t)blk * cmask_words : nullptr;
     if (G.start < G.end) {
         const uint32_t e1 = G.end - 1u;
-        // records of the current chunk; list entries of the next one
-        Rec cur = recs[vals[min(G.start + (uint32_t)l, e1)]];
-        if (G.start + (uint32_t)l > e1) cur.box0 = kNoBox;
-        uint32_t pn = vals[min(G.start + (uint32_t)(kWave + l), e1)];
-        for (uint32_t c = G.start;;) {
+        // Chunks are the 64-position words of the global list ([base, base +
+        // 64) with base a multiple of 64, clipped to the tile's range), so a
+        // chunk's contribution bits form one word of the mask.  Lane l holds
+        // position base + l.  Records of the current chunk and list entries of
+        // the next one are loaded ahead.
+        uint32_t base = G.start & ~63u;
+        Rec cur = recs[vals[min(max(base + (uint32_t)l, G.start), e1)]];
+        if (base + (uint32_t)l < G.start || base + (uint32_t)l > e1) cur.box0 = kNoBox;
+        uint32_t pn = vals[min(base + (uint32_t)(kWave + l), e1)];
+        for (;;) {
             const bool hit = box_meets(cur.box0, cur.box1, live);
             const uint64_t m = __ballot(hit);
             if (hit)
-                stage[__popcll(m & below)] = MODE == WIPES_2D_ADDITIVE ? stage_add(cur, bx, by, c + (uint32_t)l)
-                                                                       : stage_fwd(cur, bx, by, c + (uint32_t)l);
-            const uint32_t cn = c + kWave;
+                stage[__popcll(m & below)] = MODE == WIPES_2D_ADDITIVE ? stage_add(cur, bx, by, base + (uint32_t)l)
+                                                                       : stage_fwd(cur, bx, by, base + (uint32_t)l);
+            const uint32_t cn = base + kWave;
             const bool more = cn < G.end;
             Rec nx{};
             if (more) {   // the next chunk is in flight while this one blends
@@ -315,19 +322,23 @@ __device__ __forceinline__ void fwd_block(const ImgDesc* __restrict__ descs, int
             wave_lds_sync();
             const int nh = __popcll(m);
             bool left = true;
+            uint64_t contrib = 0;   // bit (pos & 63): the primitive at pos contributed to a pixel of the block
             for (int j = 0; j < nh; ++j) {
                 const Staged S = stage[j];
                 const PairEval p = eval_at(S.mrx, S.mry, S.c0, S.c1, S.c2, S.f0, S.f1, lx, ly);
                 if constexpr (MODE == WIPES_2D_ADDITIVE) {
-                    const float w = p.e2 >= thr2 ? p.W : 0.0f;
+                    const bool in = p.e2 >= thr2;
+                    const float w = in ? p.W : 0.0f;
                     C0 = fmaf(S.r, w, C0);
                     C1 = fmaf(S.g, w, C1);
                     C2 = fmaf(S.b, w, C2);
+                    if (__ballot(in && valid)) contrib |= 1ull << (S.pos & 63u);
                     continue;
                 }
                 const float a = S.op * p.W;
                 bool died = false;
-                if (alive && a >= kp.alpha_min) {
+                const bool adds = alive && a >= kp.alpha_min;
+                if (adds) {
                     const float al = fminf(a, kp.alpha_max);
                     const float wt = T * al;
                     C0 = fmaf(wt, S.r, C0);
@@ -340,6 +351,7 @@ __device__ __forceinline__ void fwd_block(const ImgDesc* __restrict__ descs, int
                         died = true;
                     }
                 }
+                if (__ballot(adds)) contrib |= 1ull << (S.pos & 63u);
                 if (__ballot(died)) {
                     if (__ballot(alive) == 0ull) {
                         left = false;
@@ -348,10 +360,12 @@ __device__ __forceinline__ void fwd_block(const ImgDesc* __restrict__ descs, int
                     live = pix_box(alive, px, py);
                 }
             }
+            // a word can be shared with the neighbouring tile's list: OR, not store
+            if (cm_row && contrib && l == 0) atomicOr(cm_row + (base >> 6), (unsigned long long)contrib);
             if (!left || !more) break;
             wave_lds_sync();   // the stage is rewritten next
             cur = nx;
-            c = cn;
+            base = cn;
         }
     }
     if (valid) {
@@ -381,14 +395,17 @@ __global__ void __launch_bounds__(TW * TH) k_blend_fwd(const ImgDesc* __restrict
                                                              const uint2* __restrict__ ranges,
                                                              const uint32_t* __restrict__ ovf, uint32_t n_tiles,
                                                              float* __restrict__ image, float* __restrict__ T_final,
-                                                             int32_t* __restrict__ last)
+                                                             int32_t* __restrict__ last,
+                                                             unsigned long long* __restrict__ cmask,
+                                                             uint32_t cmask_words)
 {
     __shared__ Staged stage[(TW / 8) * (TH / 8)][kWave];
     if (*ovf) return;
     const uint32_t t = blockIdx.x;
     if (t >= n_tiles) return;
     const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-    fwd_block<MODE, TW, TH>(descs, B, kp, recs, vals, ranges, t, w, image, T_final, last, stage[w]);
+    fwd_block<MODE, TW, TH>(descs, B, kp, recs, vals, ranges, t, w, image, T_final, last, cmask, cmask_words,
+                            stage[w]);
 }
 
 // Persistent form: each workgroup pulls whole tiles from the queue (tiles in
@@ -401,7 +418,9 @@ __global__ void __launch_bounds__(TW * TH) k_blend_fwd_q(const ImgDesc* __restri
                                                          const uint32_t* __restrict__ ovf, uint32_t n_tiles,
                                                          const uint32_t* __restrict__ order,
                                                          uint32_t* __restrict__ queue, float* __restrict__ image,
-                                                         float* __restrict__ T_final, int32_t* __restrict__ last)
+                                                         float* __restrict__ T_final, int32_t* __restrict__ last,
+                                                         unsigned long long* __restrict__ cmask,
+                                                         uint32_t cmask_words)
 {
     constexpr int NB = (TW / 8) * (TH / 8);
     __shared__ Staged stage[NB][kWave];
@@ -415,7 +434,8 @@ __global__ void __launch_bounds__(TW * TH) k_blend_fwd_q(const ImgDesc* __restri
         const uint32_t t = qtile;
         __syncthreads();   // every wave has read `qtile` before it is rewritten
         if (t >= n_tiles) break;
-        fwd_block<MODE, TW, TH>(descs, B, kp, recs, vals, ranges, t, w, image, T_final, last, stage[w]);
+        fwd_block<MODE, TW, TH>(descs, B, kp, recs, vals, ranges, t, w, image, T_final, last, cmask, cmask_words,
+                                stage[w]);
     }
 }
 
@@ -503,8 +523,10 @@ __device__ __forceinline__ void bwd_tile(const ImgDesc* __restrict__ descs, int 
                                                const uint32_t* __restrict__ eidx, const uint2* __restrict__ ranges,
                                                uint32_t t, const float* __restrict__ T_final,
                                                const int32_t* __restrict__ last, const float* __restrict__ dLdC,
-                                               float* __restrict__ slots, Staged (*stage)[kWave],
-                                               float* __restrict__ part, uint32_t* __restrict__ top)
+                                               float* __restrict__ slots,
+                                               const unsigned long long* __restrict__ cmask, uint32_t cmask_words,
+                                               Staged (*stage)[kWave], float* __restrict__ part,
+                                               uint32_t* __restrict__ top)
 {
     constexpr int NBX = TW / 8, NB = (TW / 8) * (TH / 8), NT = NB * kWave;
     const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
@@ -531,7 +553,6 @@ __device__ __forceinline__ void bwd_tile(const ImgDesc* __restrict__ descs, int 
     const float thr2 = kp.q_add * kConicScale;
     const float lx = (float)(l & 7) + 0.5f, ly = (float)(l >> 3) + 0.5f;
     const int32_t btop = __builtin_amdgcn_readfirstlane(wave_max_i32(on ? lst : -1));
-    const PixBox cbox = pix_box(on, px, py);
     if (l == 0) top[w] = (uint32_t)(btop + 1);
     __syncthreads();
     uint32_t hi = G.start;
@@ -548,41 +569,48 @@ __device__ __forceinline__ void bwd_tile(const ImgDesc* __restrict__ descs, int 
     const uint64_t below = (1ull << l) - 1ull;
     float* mine = part + (size_t)w * kWave * kSlot;
     Staged* st = stage[w];
-    auto down = [&](uint32_t c) { return c - min(c - G.start, (uint32_t)kWave); };
-    uint32_t c1 = hi, c0 = down(hi);
+    const unsigned long long* cm_row = cmask + (size_t)w * cmask_words;
+    // Chunks are the 64-position words of the global list clipped to [start,
+    // hi), walked top down; lane l holds position (c0 & ~63) + l.  A chunk's
+    // hits are the positions whose primitive the forward found contributing
+    // to this block (its contribution word), up to the block's last position.
+    auto lo_of = [&](uint32_t c1) { return max(G.start, (c1 - 1u) & ~63u); };
+    auto hits_of = [&](uint32_t c0, uint32_t c1) -> uint64_t {
+        if (btop < (int32_t)c0) return 0ull;
+        const uint32_t b = c0 & ~63u;
+        const uint32_t lo = c0 - b, hb = min(c1 - 1u, (uint32_t)btop) - b;
+        return cm_row[b >> 6] & ((~0ull >> (63u - hb)) & (~0ull << lo));
+    };
+    uint32_t c1 = hi, c0 = lo_of(hi);
+    uint64_t m = hits_of(c0, c1);
     Rec cur{};
-    cur.box0 = kNoBox;
-    if (btop >= (int32_t)c0) {
-        cur = recs[vals[min(c0 + (uint32_t)l, c1 - 1u)]];
-        if (c0 + (uint32_t)l >= c1) cur.box0 = kNoBox;
-    }
+    if ((m >> l) & 1ull) cur = recs[vals[(c0 & ~63u) + (uint32_t)l]];
+    // the next chunk's hits and list entries
+    uint32_t n1 = c0, n0 = c0 > G.start ? lo_of(c0) : c0;
+    uint64_t mn = c0 > G.start ? hits_of(n0, n1) : 0ull;
     uint32_t pn = 0;
-    if (c0 > G.start && btop >= (int32_t)down(c0)) pn = vals[min(down(c0) + (uint32_t)l, c0 - 1u)];
+    if ((mn >> l) & 1ull) pn = vals[(n0 & ~63u) + (uint32_t)l];
     for (;;) {
-        const uint32_t s = c0 + (uint32_t)l;
-        // only pixels whose last contributing position reaches this chunk can
-        // take part in it (alpha; every pixel in additive mode)
-        const PixBox abox = MODE == WIPES_2D_ADDITIVE ? cbox : pix_box(on && lst >= (int32_t)c0, px, py);
-        const bool hit = (int32_t)s <= btop && box_meets(cur.box0, cur.box1, abox);
-        const uint64_t m = __ballot(hit);
-        if (hit) {
-            st[__popcll(m & below)] = stage_raw(cur, bx, by, s);
+        const uint32_t b = c0 & ~63u;
+        if ((m >> l) & 1ull) {
+            st[__popcll(m & below)] = stage_raw(cur, bx, by, b + (uint32_t)l);
         } else {
             float4* z = reinterpret_cast<float4*>(mine + l * kSlot);
             z[0] = make_float4(0.f, 0.f, 0.f, 0.f);
             z[1] = make_float4(0.f, 0.f, 0.f, 0.f);
             z[2] = make_float4(0.f, 0.f, 0.f, 0.f);
         }
-        const uint32_t n1 = c0, n0 = down(c0);
-        const bool more = n1 > G.start;   // uniform over the workgroup
+        const bool more = c0 > G.start;   // uniform over the workgroup
         Rec nx{};
-        nx.box0 = kNoBox;
-        if (more) {   // the next chunk is in flight while this one is replayed
-            if (btop >= (int32_t)n0) {
-                nx = recs[pn];
-                if (n0 + (uint32_t)l >= n1) nx.box0 = kNoBox;
+        uint32_t nn1 = n0, nn0 = n0, pnn = 0;
+        uint64_t mnn = 0ull;
+        if (more) {   // the next chunk's records (and the one after's entries) are in flight
+            if ((mn >> l) & 1ull) nx = recs[pn];
+            if (n0 > G.start) {
+                nn0 = lo_of(n0);
+                mnn = hits_of(nn0, nn1);
+                if ((mnn >> l) & 1ull) pnn = vals[(nn0 & ~63u) + (uint32_t)l];
             }
-            if (n0 > G.start && btop >= (int32_t)down(n0)) pn = vals[min(down(n0) + (uint32_t)l, n0 - 1u)];
         }
         wave_lds_sync();
         for (int j = __popcll(m) - 1; j >= 0; --j) {
@@ -624,7 +652,7 @@ __device__ __forceinline__ void bwd_tile(const ImgDesc* __restrict__ descs, int 
                     pair_grads(v, p, S.op * da, S.c0, S.c1, S.c2, S.f0, S.f1);
                 }
             }
-            float* o = mine + (S.pos - c0) * kSlot;
+            float* o = mine + (S.pos & 63u) * kSlot;
             if (__ballot(any)) {
                 wave_reduce16_valu(v);
                 const int id = l >> 2;
@@ -634,19 +662,24 @@ __device__ __forceinline__ void bwd_tile(const ImgDesc* __restrict__ descs, int 
             }
         }
         __syncthreads();
-        const uint32_t n = c1 - c0;
+        const uint32_t n = c1 - c0, r0 = (c0 & 63u) * kSlot;
         for (uint32_t q = (uint32_t)tid; q < n * kSlot; q += NT) {
             const uint32_t pp = q / kSlot;
-            float sum = part[q];
+            float sum = part[r0 + q];
 #pragma unroll
-            for (int k = 1; k < NB; ++k) sum += part[(size_t)k * kWave * kSlot + q];
+            for (int k = 1; k < NB; ++k) sum += part[(size_t)k * kWave * kSlot + r0 + q];
             slots[(size_t)eidx[c0 + pp] * kSlot + (q - pp * kSlot)] = sum;
         }
         __syncthreads();
         if (!more) break;
         cur = nx;
+        m = mn;
         c1 = n1;
         c0 = n0;
+        mn = mnn;
+        pn = pnn;
+        n1 = nn1;
+        n0 = nn0;
     }
 }
 
@@ -660,7 +693,9 @@ __global__ void __launch_bounds__(TW * TH) k_blend_bwd(const ImgDesc* __restrict
                                                              const float* __restrict__ T_final,
                                                              const int32_t* __restrict__ last,
                                                              const float* __restrict__ dLdC,
-                                                             float* __restrict__ slots)
+                                                             float* __restrict__ slots,
+                                                             const unsigned long long* __restrict__ cmask,
+                                                             uint32_t cmask_words)
 {
     constexpr int NB = (TW / 8) * (TH / 8);
     __shared__ Staged stage[NB][kWave];
@@ -669,7 +704,8 @@ __global__ void __launch_bounds__(TW * TH) k_blend_bwd(const ImgDesc* __restrict
     if (*ovf) return;
     const uint32_t t = blockIdx.x;
     if (t >= n_tiles) return;
-    bwd_tile<MODE, TW, TH>(descs, B, kp, recs, vals, eidx, ranges, t, T_final, last, dLdC, slots, stage, part, top);
+    bwd_tile<MODE, TW, TH>(descs, B, kp, recs, vals, eidx, ranges, t, T_final, last, dLdC, slots, cmask, cmask_words,
+                           stage, part, top);
 }
 
 // Persistent form: each workgroup pulls whole tiles from the queue.
@@ -685,7 +721,9 @@ __global__ void __launch_bounds__(TW * TH) k_blend_bwd_q(const ImgDesc* __restri
                                                                const float* __restrict__ T_final,
                                                                const int32_t* __restrict__ last,
                                                                const float* __restrict__ dLdC,
-                                                               float* __restrict__ slots)
+                                                               float* __restrict__ slots,
+                                                               const unsigned long long* __restrict__ cmask,
+                                                               uint32_t cmask_words)
 {
     constexpr int NB = (TW / 8) * (TH / 8);
     __shared__ Staged stage[NB][kWave];
@@ -700,8 +738,8 @@ __global__ void __launch_bounds__(TW * TH) k_blend_bwd_q(const ImgDesc* __restri
         const uint32_t t = qtile;
         __syncthreads();   // every wave has read `qtile` before it is rewritten
         if (t >= n_tiles) break;
-        bwd_tile<MODE, TW, TH>(descs, B, kp, recs, vals, eidx, ranges, t, T_final, last, dLdC, slots, stage, part,
-                               top);
+        bwd_tile<MODE, TW, TH>(descs, B, kp, recs, vals, eidx, ranges, t, T_final, last, dLdC, slots, cmask,
+                               cmask_words, stage, part, top);
     }
 }
 
@@ -783,36 +821,38 @@ template <int MODE, int TW, int TH>
 static void launch_fwd_t(const ImgDesc* descs, int B, const KParams& kp, const Rec* recs, const uint32_t* vals,
                          const uint2* ranges, const uint32_t* ovf, uint32_t n_tiles, const uint32_t* order,
                          uint32_t* queue, uint32_t persistent_blocks, float* image, float* T_final, int32_t* last,
-                         hipStream_t s)
+                         unsigned long long* cmask, uint32_t cmask_words, hipStream_t s)
 {
     constexpr uint32_t NB = (TW / 8) * (TH / 8);
     if (queue) {
         const uint32_t nb = max(1u, persistent_blocks * kWpb / NB);   // same number of waves
         hipLaunchKernelGGL((k_blend_fwd_q<MODE, TW, TH>), dim3(nb), dim3(TW * TH), 0, s, descs, B, kp, recs, vals,
-                           ranges, ovf, n_tiles, order, queue, image, T_final, last);
+                           ranges, ovf, n_tiles, order, queue, image, T_final, last, cmask, cmask_words);
         return;
     }
     if (n_tiles == 0) return;
     hipLaunchKernelGGL((k_blend_fwd<MODE, TW, TH>), dim3(n_tiles), dim3(TW * TH), 0, s, descs, B, kp, recs, vals,
-                       ranges, ovf, n_tiles, image, T_final, last);
+                       ranges, ovf, n_tiles, image, T_final, last, cmask, cmask_words);
 }
 
 template <int MODE, int TW, int TH>
 static void launch_bwd_t(const ImgDesc* descs, int B, const KParams& kp, const Rec* recs, const uint32_t* vals,
                          const uint32_t* eidx, const uint2* ranges, const uint32_t* ovf, uint32_t n_tiles,
                          const uint32_t* order, uint32_t* queue, uint32_t persistent_blocks, const float* T_final,
-                         const int32_t* last, const float* dLdC, float* slots, hipStream_t s)
+                         const int32_t* last, const float* dLdC, float* slots, const unsigned long long* cmask,
+                         uint32_t cmask_words, hipStream_t s)
 {
     constexpr uint32_t NB = (TW / 8) * (TH / 8);
     if (queue) {
         const uint32_t nb = max(1u, persistent_blocks * kWpb / NB);
         hipLaunchKernelGGL((k_blend_bwd_q<MODE, TW, TH>), dim3(nb), dim3(TW * TH), 0, s, descs, B, kp, recs, vals,
-                           eidx, ranges, ovf, n_tiles, order, queue, T_final, last, dLdC, slots);
+                           eidx, ranges, ovf, n_tiles, order, queue, T_final, last, dLdC, slots, cmask,
+                           cmask_words);
         return;
     }
     if (n_tiles == 0) return;
     hipLaunchKernelGGL((k_blend_bwd<MODE, TW, TH>), dim3(n_tiles), dim3(TW * TH), 0, s, descs, B, kp, recs, vals,
-                       eidx, ranges, ovf, n_tiles, T_final, last, dLdC, slots);
+                       eidx, ranges, ovf, n_tiles, T_final, last, dLdC, slots, cmask, cmask_words);
 }
 
 #define WIPES_TILE_DISPATCH(FN, MODE, ...)                                          \
@@ -852,28 +892,29 @@ hipError_t launch_pair_stats(const ImgDesc* descs, int B, const KParams& kp, con
 hipError_t launch_blend_fwd(const ImgDesc* descs, int B, const KParams& kp, const Rec* recs, const uint32_t* vals,
                             const uint2* ranges, const uint32_t* ovf, uint32_t n_tiles, const uint32_t* order,
                             uint32_t* queue, uint32_t persistent_blocks, float* image, float* T_final, int32_t* last,
-                            hipStream_t s)
+                            unsigned long long* cmask, uint32_t cmask_words, hipStream_t s)
 {
     if (kp.mode == WIPES_2D_ADDITIVE)
         WIPES_TILE_DISPATCH(launch_fwd_t, WIPES_2D_ADDITIVE, descs, B, kp, recs, vals, ranges, ovf, n_tiles, order,
-                            queue, persistent_blocks, image, T_final, last, s);
+                            queue, persistent_blocks, image, T_final, last, cmask, cmask_words, s);
     else
         WIPES_TILE_DISPATCH(launch_fwd_t, WIPES_3D_ALPHA, descs, B, kp, recs, vals, ranges, ovf, n_tiles, order,
-                            queue, persistent_blocks, image, T_final, last, s);
+                            queue, persistent_blocks, image, T_final, last, cmask, cmask_words, s);
     return hipGetLastError();
 }
 
 hipError_t launch_blend_bwd(const ImgDesc* descs, int B, const KParams& kp, const Rec* recs, const uint32_t* vals,
                             const uint32_t* eidx, const uint2* ranges, const uint32_t* ovf, uint32_t n_tiles,
                             const uint32_t* order, uint32_t* queue, uint32_t persistent_blocks, const float* T_final,
-                            const int32_t* last, const float* dLdC, float* slots, hipStream_t s)
+                            const int32_t* last, const float* dLdC, float* slots, const unsigned long long* cmask,
+                            uint32_t cmask_words, hipStream_t s)
 {
     if (kp.mode == WIPES_2D_ADDITIVE)
         WIPES_TILE_DISPATCH(launch_bwd_t, WIPES_2D_ADDITIVE, descs, B, kp, recs, vals, eidx, ranges, ovf, n_tiles,
-                            order, queue, persistent_blocks, T_final, last, dLdC, slots, s);
+                            order, queue, persistent_blocks, T_final, last, dLdC, slots, cmask, cmask_words, s);
     else
         WIPES_TILE_DISPATCH(launch_bwd_t, WIPES_3D_ALPHA, descs, B, kp, recs, vals, eidx, ranges, ovf, n_tiles, order,
-                            queue, persistent_blocks, T_final, last, dLdC, slots, s);
+                            queue, persistent_blocks, T_final, last, dLdC, slots, cmask, cmask_words, s);
     return hipGetLastError();
 }
 

@@ -22,6 +22,7 @@ struct Views {
     uint32_t *keys_a, *vals_a, *keys_b, *vals_b, *hist, *dtot, *order, *tbsum, *w_a, *w_b;
     uint2* ranges;
     float* slots;
+    unsigned long long* cmask;
 };
 
 static Views views(const Layout& L, const void* screen, const void* bins)
@@ -60,6 +61,7 @@ static Views views(const Layout& L, const void* screen, const void* bins)
             v.w_a = (uint32_t*)(b + L.b_w_a);
             v.w_b = (uint32_t*)(b + L.b_w_b);
             v.slots = (float*)(b + L.b_slots);
+            v.cmask = (unsigned long long*)(b + L.b_cmask);
         }
     }
     return v;
@@ -170,8 +172,13 @@ wipes_status render_fwd_core(wipes_ctx* ctx, const wipes_params* p, const wipes_
         pblocks = (uint32_t)ctx->n_cu * 8u;
     }
     StageScope sc(ctx, kStBlendFwd, s);
+    if (v.cmask) {
+        // the forward records which primitives contribute to each block, for the backward
+        const size_t words = (size_t)(p->tile_w / 8) * (p->tile_h / 8) * L.cmask_words;
+        HIP_TRY(launch_fill_u32((uint32_t*)v.cmask, (uint32_t)(2 * words), 0u, s), "mask clear");
+    }
     HIP_TRY(launch_blend_fwd(v.descs, L.B, kp, v.recs, svals, v.ranges, v.ctrl + kCtrlOverflow, (uint32_t)L.tiles,
-                             order, queue, pblocks, image, T_final, last, s),
+                             order, queue, pblocks, image, T_final, last, v.cmask, L.cmask_words, s),
             "blend fwd");
     return WIPES_OK;
 }
@@ -196,7 +203,8 @@ wipes_status render_bwd_core(wipes_ctx* ctx, const wipes_params* p, const wipes_
         StageScope sc(ctx, kStBlendBwd, s);
         const uint32_t* seidx = L.tile_result_b ? v.w_b : v.w_a;
         HIP_TRY(launch_blend_bwd(v.descs, L.B, kp, v.recs, svals, seidx, v.ranges, v.ctrl + kCtrlOverflow,
-                                 (uint32_t)L.tiles, order, queue, pblocks, T_final, last, dLdC, v.slots, s),
+                                 (uint32_t)L.tiles, order, queue, pblocks, T_final, last, dLdC, v.slots, v.cmask,
+                                 L.cmask_words, s),
                 "blend bwd");
     }
     StageScope sc(ctx, kStProjectBwd, s);
