@@ -151,15 +151,6 @@ __device__ __forceinline__ int32_t wave_min_i32(int32_t v)
     return v;
 }
 
-// Orders this wave's LDS accesses (one wave's LDS instructions execute in
-// program order; the fences keep the compiler from moving them).
-__device__ __forceinline__ void wave_lds_sync()
-{
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 // Next tile from the persistent queue (called by one thread): counter
 // `lane` first, then the others in turn once it runs dry, so every tile is
 // handed out exactly once and a workgroup never waits on an empty lane while

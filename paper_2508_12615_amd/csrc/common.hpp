@@ -113,6 +113,15 @@ __device__ __forceinline__ int32_t hi16(uint32_t v) { return (int32_t)(v >> 16);
 
 __device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
 
+// Orders this wave's LDS accesses (one wave's LDS instructions execute in
+// program order; the fences keep the compiler from moving them).
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Wave-wide sum, max (results in every lane).
 __device__ __forceinline__ int32_t wave_max_i32(int32_t v)
 {

@@ -29,24 +29,44 @@ __global__ void __launch_bounds__(256) k_project_bwd(const ImgDesc* __restrict__
                                                       const uint32_t* __restrict__ overflow,
                                                       float* __restrict__ dscreen)
 {
-    const int32_t i = (int32_t)(blockIdx.x * 256u + threadIdx.x);
-    if (i >= n_total || *overflow) return;
-    const ImgDesc& d = descs[image_of_prim(descs, B, i)];
-    const int32_t j = i - d.prim_begin;
+    __shared__ float4 s_slot[4][kWave][3];
+    const int wv = (int)(threadIdx.x >> 6), l = lane_id();
+    const int32_t i0 = (int32_t)(blockIdx.x * 256u + (uint32_t)wv * kWave);
+    if (i0 >= n_total || *overflow) return;   // wave-uniform
+    const int32_t i = i0 + l;
+    const bool inr = i < n_total;
+    // The slots of the wave's 64 primitives form one contiguous run (they are
+    // numbered in primitive order).  The wave streams the run through LDS 64
+    // slots at a time with coalesced loads, and each lane adds up its own
+    // primitive's slots in ascending order (the same order at any batch size).
+    const uint32_t c = inr ? count[i] : 0u;
+    const uint32_t base = inr ? off_id[i] : 0u;
+    const uint32_t first = (uint32_t)__builtin_amdgcn_readfirstlane((int)base);   // lane 0 is in range
+    const uint32_t total = wave_sum_u32(c);
+    const uint32_t my0 = base - first, my1 = my0 + c;
     float acc[11];
 #pragma unroll
     for (int k = 0; k < 11; ++k) acc[k] = 0.0f;
-    const uint32_t c = count[i];
-    if (c) {
-        const uint32_t base = off_id[i];
-        for (uint32_t e = 0; e < c; ++e) {
-            const float4* sl = reinterpret_cast<const float4*>(slots + (size_t)(base + e) * kSlotB);
-            const float4 a0 = sl[0], a1 = sl[1], a2 = sl[2];
+    for (uint32_t k0 = 0; k0 < total; k0 += kWave) {
+        if (k0 + (uint32_t)l < total) {
+            const float4* sl = reinterpret_cast<const float4*>(slots + (size_t)(first + k0 + (uint32_t)l) * kSlotB);
+            s_slot[wv][l][0] = sl[0];
+            s_slot[wv][l][1] = sl[1];
+            s_slot[wv][l][2] = sl[2];
+        }
+        wave_lds_sync();
+        const uint32_t e1 = min(my1, k0 + kWave);
+        for (uint32_t e = max(my0, k0); e < e1; ++e) {
+            const float4 a0 = s_slot[wv][e - k0][0], a1 = s_slot[wv][e - k0][1], a2 = s_slot[wv][e - k0][2];
             acc[0] += a0.x; acc[1] += a0.y; acc[2] += a0.z; acc[3] += a0.w;
             acc[4] += a1.x; acc[5] += a1.y; acc[6] += a1.z; acc[7] += a1.w;
             acc[8] += a2.x; acc[9] += a2.y; acc[10] += a2.z;
         }
+        wave_lds_sync();   // the stage is rewritten next
     }
+    if (!inr) return;
+    const ImgDesc& d = descs[image_of_prim(descs, B, i)];
+    const int32_t j = i - d.prim_begin;
     if (dscreen) {
 #pragma unroll
         for (int k = 0; k < 11; ++k) dscreen[(size_t)i * 11 + k] = acc[k];
