@@ -50,7 +50,32 @@ def parse():
                     help="comma list of secondary workloads to add to the JSON line (serve, batched, fit) or none")
     ap.add_argument("--serve-requests", type=int, default=240)
     ap.add_argument("--fit-steps", type=int, default=1000)
+    ap.add_argument("--copy-probe-mb", type=int, default=0,
+                    help="copy this many MiB device to device once before the run (a kernel of known traffic that "
+                         "calibrates hardware byte counters)")
     return ap.parse_args()
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pmc_traffic_3d_1080p_1M_alpha.md")
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary, or None when there
+    is none or the kernel source changed since the counters were taken."""
+    import hashlib
+    import re
+    try:
+        text = open(TRAFFIC_FILE).read()
+    except OSError:
+        return None
+    m = re.search(r"source_sha256 = ([0-9a-f]{64})", text)
+    t = re.search(r"traffic_bytes_per_launch\[%s\] = ([0-9.eE+]+)" % kernel, text)
+    if not m or not t:
+        return None
+    src = open(os.path.join(ROOT, "paper_2508_12615_amd", "csrc", "blend.hip"), "rb").read()
+    if hashlib.sha256(src).hexdigest() != m.group(1):
+        return None
+    return float(t.group(1))
 
 
 def bench_serving(n_req, log, persistent=1, load=0.8):
@@ -214,6 +239,12 @@ def main():
     from paper_2508_12615_amd.raster import Rasterizer
 
     dev = torch.device("cuda", 0)
+    if a.copy_probe_mb > 0:
+        src = torch.ones(a.copy_probe_mb << 18, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     c = synth.config3(a.prims)
     cam = c["camera"]
     W, H = cam["width"], cam["height"]
@@ -252,8 +283,8 @@ def main():
         slots = ALU_PER_PAIR[("alpha", kind)] + TRANS_SLOTS * TRANS_PER_PAIR[("alpha", kind)]
         ach = pairs * slots / (ms * 1e-3)
         return dict(bound="alu", achieved=ach / 1e12, peak=VALU_PEAK / 1e12, unit="T lane-op/s",
-                    frac=ach / VALU_PEAK, traffic=None, kernel="blend_" + kind, support_pairs=pairs,
-                    ops_per_pair=slots)
+                    frac=ach / VALU_PEAK, traffic=measured_traffic("blend_" + kind), kernel="blend_" + kind,
+                    support_pairs=pairs, ops_per_pair=slots)
 
     if dom in ("blend_fwd", "blend_bwd"):
         roof = alu_roof(dom.split("_")[1], stages[dom])

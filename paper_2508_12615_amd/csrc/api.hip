@@ -175,6 +175,7 @@ Layout layout_of(const wipes_params* p, const wipes_batch* b, int64_t cap, int w
         // contribution mask: (tile_w/8)(tile_h/8) block rows of cap/64 + 2 words
         L.cmask_words = (uint32_t)(cap / 64 + 2);
         L.b_cmask = take((size_t)(p->tile_w / 8) * (p->tile_h / 8) * L.cmask_words * 8);
+        L.b_svalid = take((size_t)(cap / 32 + 2) * 4);
     }
     L.bins_bytes = o;
     L.with_bwd = with_bwd;

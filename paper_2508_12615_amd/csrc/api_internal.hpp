@@ -70,6 +70,7 @@ struct Layout {
     // bins buffer
     size_t b_keys_a, b_vals_a, b_keys_b, b_vals_b, b_hist, b_dtot, b_ranges, b_order, b_tbsum, b_w_a, b_w_b, b_slots;
     size_t b_cmask;           // per 8x8 block of a tile, one bit per list position (backward only)
+    size_t b_svalid;          // one bit per gradient slot: written by this backward (backward only)
     uint32_t cmask_words;     // 64-bit words per block row of the mask
     size_t bins_bytes;
     int tile_bits = 1;
@@ -140,8 +141,8 @@ hipError_t launch_blend_fwd(const ImgDesc* descs, int B, const KParams& kp, cons
 hipError_t launch_blend_bwd(const ImgDesc* descs, int B, const KParams& kp, const Rec* recs, const uint32_t* vals,
                             const uint32_t* eidx, const uint2* ranges, const uint32_t* ovf, uint32_t n_tiles,
                             const uint32_t* order, uint32_t* queue, uint32_t persistent_blocks, const float* T_final,
-                            const int32_t* last, const float* dLdC, float* slots, const unsigned long long* cmask,
-                            uint32_t cmask_words, hipStream_t s);
+                            const int32_t* last, const float* dLdC, float* slots, uint32_t* valid,
+                            const unsigned long long* cmask, uint32_t cmask_words, hipStream_t s);
 hipError_t launch_l2_grad(const ImgDesc* descs, int B, int32_t npix, const float* image, const float* target,
                           float* grad, hipStream_t s);
 hipError_t launch_pair_stats(const ImgDesc* descs, int B, const KParams& kp, const Rec* recs, const uint32_t* vals,
@@ -149,6 +150,6 @@ hipError_t launch_pair_stats(const ImgDesc* descs, int B, const KParams& kp, con
                              const int32_t* last, unsigned long long* out, hipStream_t s);
 hipError_t launch_project_bwd(const ImgDesc* descs, int B, int32_t n_total, const KParams& kp, const Rec* recs,
                               const uint32_t* count, const uint32_t* off_id, const float* slots,
-                              const uint32_t* overflow, float* dscreen, hipStream_t s);
+                              const uint32_t* valid, const uint32_t* overflow, float* dscreen, hipStream_t s);
 
 }  // namespace wipes

@@ -514,10 +514,10 @@ __device__ __forceinline__ void bwd_tile(const ImgDesc* __restrict__ descs, int 
                                                const uint32_t* __restrict__ eidx, const uint2* __restrict__ ranges,
                                                uint32_t t, const float* __restrict__ T_final,
                                                const int32_t* __restrict__ last, const float* __restrict__ dLdC,
-                                               float* __restrict__ slots,
+                                               float* __restrict__ slots, uint32_t* __restrict__ smark,
                                                const unsigned long long* __restrict__ cmask, uint32_t cmask_words,
                                                Staged (*stage)[kWave], float* __restrict__ part,
-                                               uint32_t* __restrict__ top)
+                                               uint32_t* __restrict__ top, uint64_t* __restrict__ hitm)
 {
     constexpr int NBX = TW / 8, NB = (TW / 8) * (TH / 8), NT = NB * kWave;
     const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
@@ -549,13 +549,8 @@ __device__ __forceinline__ void bwd_tile(const ImgDesc* __restrict__ descs, int 
     uint32_t hi = G.start;
 #pragma unroll
     for (int k = 0; k < NB; ++k) hi = max(hi, top[k]);
-    // positions no pixel reached get zero slots
-    for (uint32_t s = hi + (uint32_t)tid; s < G.end; s += NT) {
-        float4* o = reinterpret_cast<float4*>(slots + (size_t)eidx[s] * kSlot);
-        o[0] = make_float4(0.f, 0.f, 0.f, 0.f);
-        o[1] = make_float4(0.f, 0.f, 0.f, 0.f);
-        o[2] = make_float4(0.f, 0.f, 0.f, 0.f);
-    }
+    // positions no pixel reached write nothing: their slots stay unmarked in
+    // `smark` and the projection backward reads them as zero
     if (hi <= G.start) return;   // uniform over the workgroup
     const uint64_t below = (1ull << l) - 1ull;
     float* mine = part + (size_t)w * kWave * kSlot;
@@ -603,9 +598,13 @@ __device__ __forceinline__ void bwd_tile(const ImgDesc* __restrict__ descs, int 
                 if ((mnn >> l) & 1ull) pnn = vals[(nn0 & ~63u) + (uint32_t)l];
             }
         }
+        if (l == 0) hitm[w] = m;
         wave_lds_sync();
-        for (int j = __popcll(m) - 1; j >= 0; --j) {
-            const Staged S = st[j];
+        const int nh = __popcll(m);
+        Staged Sn = st[nh > 0 ? nh - 1 : 0];   // the next staged primitive is read while the current one replays
+        for (int j = nh - 1; j >= 0; --j) {
+            const Staged S = Sn;
+            Sn = st[j > 0 ? j - 1 : 0];
             float v[16];
 #pragma unroll
             for (int k = 0; k < 16; ++k) v[k] = 0.0f;
@@ -653,13 +652,20 @@ __device__ __forceinline__ void bwd_tile(const ImgDesc* __restrict__ descs, int 
             }
         }
         __syncthreads();
+        // positions some block staged get their slot written and marked
+        uint64_t anyhit = 0ull;
+#pragma unroll
+        for (int k = 0; k < NB; ++k) anyhit |= hitm[k];
         const uint32_t n = c1 - c0, r0 = (c0 & 63u) * kSlot;
         for (uint32_t q = (uint32_t)tid; q < n * kSlot; q += NT) {
-            const uint32_t pp = q / kSlot;
+            const uint32_t pp = q / kSlot, pos = c0 + pp;
+            if (!((anyhit >> (pos & 63u)) & 1ull)) continue;
             float sum = part[r0 + q];
 #pragma unroll
             for (int k = 1; k < NB; ++k) sum += part[(size_t)k * kWave * kSlot + r0 + q];
-            slots[(size_t)eidx[c0 + pp] * kSlot + (q - pp * kSlot)] = sum;
+            const uint32_t e = eidx[pos], comp = q - pp * kSlot;
+            slots[(size_t)e * kSlot + comp] = sum;
+            if (comp == 0) atomicOr(smark + (e >> 5), 1u << (e & 31u));
         }
         __syncthreads();
         if (!more) break;
@@ -685,6 +691,7 @@ __global__ void __launch_bounds__(TW * TH) k_blend_bwd(const ImgDesc* __restrict
                                                              const int32_t* __restrict__ last,
                                                              const float* __restrict__ dLdC,
                                                              float* __restrict__ slots,
+                                                             uint32_t* __restrict__ valid,
                                                              const unsigned long long* __restrict__ cmask,
                                                              uint32_t cmask_words)
 {
@@ -692,11 +699,12 @@ __global__ void __launch_bounds__(TW * TH) k_blend_bwd(const ImgDesc* __restrict
     __shared__ Staged stage[NB][kWave];
     __shared__ __attribute__((aligned(16))) float part[NB * kWave * kSlot];
     __shared__ uint32_t top[NB];
+    __shared__ uint64_t hitm[NB];
     if (*ovf) return;
     const uint32_t t = blockIdx.x;
     if (t >= n_tiles) return;
-    bwd_tile<MODE, TW, TH>(descs, B, kp, recs, vals, eidx, ranges, t, T_final, last, dLdC, slots, cmask, cmask_words,
-                           stage, part, top);
+    bwd_tile<MODE, TW, TH>(descs, B, kp, recs, vals, eidx, ranges, t, T_final, last, dLdC, slots, valid, cmask,
+                           cmask_words, stage, part, top, hitm);
 }
 
 // Persistent form: each workgroup pulls whole tiles from the queue.
@@ -713,6 +721,7 @@ __global__ void __launch_bounds__(TW * TH) k_blend_bwd_q(const ImgDesc* __restri
                                                                const int32_t* __restrict__ last,
                                                                const float* __restrict__ dLdC,
                                                                float* __restrict__ slots,
+                                                               uint32_t* __restrict__ valid,
                                                                const unsigned long long* __restrict__ cmask,
                                                                uint32_t cmask_words)
 {
@@ -720,6 +729,7 @@ __global__ void __launch_bounds__(TW * TH) k_blend_bwd_q(const ImgDesc* __restri
     __shared__ Staged stage[NB][kWave];
     __shared__ __attribute__((aligned(16))) float part[NB * kWave * kSlot];
     __shared__ uint32_t top[NB];
+    __shared__ uint64_t hitm[NB];
     __shared__ uint32_t qtile;
     if (*ovf) return;
     uint32_t lane = blockIdx.x % kQueueLanes;
@@ -729,8 +739,8 @@ __global__ void __launch_bounds__(TW * TH) k_blend_bwd_q(const ImgDesc* __restri
         const uint32_t t = qtile;
         __syncthreads();   // every wave has read `qtile` before it is rewritten
         if (t >= n_tiles) break;
-        bwd_tile<MODE, TW, TH>(descs, B, kp, recs, vals, eidx, ranges, t, T_final, last, dLdC, slots, cmask,
-                               cmask_words, stage, part, top);
+        bwd_tile<MODE, TW, TH>(descs, B, kp, recs, vals, eidx, ranges, t, T_final, last, dLdC, slots, valid, cmask,
+                               cmask_words, stage, part, top, hitm);
     }
 }
 
@@ -830,20 +840,20 @@ template <int MODE, int TW, int TH>
 static void launch_bwd_t(const ImgDesc* descs, int B, const KParams& kp, const Rec* recs, const uint32_t* vals,
                          const uint32_t* eidx, const uint2* ranges, const uint32_t* ovf, uint32_t n_tiles,
                          const uint32_t* order, uint32_t* queue, uint32_t persistent_blocks, const float* T_final,
-                         const int32_t* last, const float* dLdC, float* slots, const unsigned long long* cmask,
-                         uint32_t cmask_words, hipStream_t s)
+                         const int32_t* last, const float* dLdC, float* slots, uint32_t* valid,
+                         const unsigned long long* cmask, uint32_t cmask_words, hipStream_t s)
 {
     constexpr uint32_t NB = (TW / 8) * (TH / 8);
     if (queue) {
         const uint32_t nb = max(1u, persistent_blocks * kWpb / NB);
         hipLaunchKernelGGL((k_blend_bwd_q<MODE, TW, TH>), dim3(nb), dim3(TW * TH), 0, s, descs, B, kp, recs, vals,
-                           eidx, ranges, ovf, n_tiles, order, queue, T_final, last, dLdC, slots, cmask,
+                           eidx, ranges, ovf, n_tiles, order, queue, T_final, last, dLdC, slots, valid, cmask,
                            cmask_words);
         return;
     }
     if (n_tiles == 0) return;
     hipLaunchKernelGGL((k_blend_bwd<MODE, TW, TH>), dim3(n_tiles), dim3(TW * TH), 0, s, descs, B, kp, recs, vals,
-                       eidx, ranges, ovf, n_tiles, T_final, last, dLdC, slots, cmask, cmask_words);
+                       eidx, ranges, ovf, n_tiles, T_final, last, dLdC, slots, valid, cmask, cmask_words);
 }
 
 #define WIPES_TILE_DISPATCH(FN, MODE, ...)                                          \
@@ -897,15 +907,15 @@ hipError_t launch_blend_fwd(const ImgDesc* descs, int B, const KParams& kp, cons
 hipError_t launch_blend_bwd(const ImgDesc* descs, int B, const KParams& kp, const Rec* recs, const uint32_t* vals,
                             const uint32_t* eidx, const uint2* ranges, const uint32_t* ovf, uint32_t n_tiles,
                             const uint32_t* order, uint32_t* queue, uint32_t persistent_blocks, const float* T_final,
-                            const int32_t* last, const float* dLdC, float* slots, const unsigned long long* cmask,
-                            uint32_t cmask_words, hipStream_t s)
+                            const int32_t* last, const float* dLdC, float* slots, uint32_t* valid,
+                            const unsigned long long* cmask, uint32_t cmask_words, hipStream_t s)
 {
     if (kp.mode == WIPES_2D_ADDITIVE)
         WIPES_TILE_DISPATCH(launch_bwd_t, WIPES_2D_ADDITIVE, descs, B, kp, recs, vals, eidx, ranges, ovf, n_tiles,
-                            order, queue, persistent_blocks, T_final, last, dLdC, slots, cmask, cmask_words, s);
+                            order, queue, persistent_blocks, T_final, last, dLdC, slots, valid, cmask, cmask_words, s);
     else
         WIPES_TILE_DISPATCH(launch_bwd_t, WIPES_3D_ALPHA, descs, B, kp, recs, vals, eidx, ranges, ovf, n_tiles, order,
-                            queue, persistent_blocks, T_final, last, dLdC, slots, cmask, cmask_words, s);
+                            queue, persistent_blocks, T_final, last, dLdC, slots, valid, cmask, cmask_words, s);
     return hipGetLastError();
 }
 

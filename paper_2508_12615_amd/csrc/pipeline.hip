@@ -23,6 +23,7 @@ struct Views {
     uint2* ranges;
     float* slots;
     unsigned long long* cmask;
+    uint32_t* svalid;
 };
 
 static Views views(const Layout& L, const void* screen, const void* bins)
@@ -62,6 +63,7 @@ static Views views(const Layout& L, const void* screen, const void* bins)
             v.w_b = (uint32_t*)(b + L.b_w_b);
             v.slots = (float*)(b + L.b_slots);
             v.cmask = (unsigned long long*)(b + L.b_cmask);
+            v.svalid = (uint32_t*)(b + L.b_svalid);
         }
     }
     return v;
@@ -202,13 +204,14 @@ wipes_status render_bwd_core(wipes_ctx* ctx, const wipes_params* p, const wipes_
     {
         StageScope sc(ctx, kStBlendBwd, s);
         const uint32_t* seidx = L.tile_result_b ? v.w_b : v.w_a;
+        HIP_TRY(launch_fill_u32(v.svalid, (uint32_t)(L.cap / 32 + 2), 0u, s), "slot marks clear");
         HIP_TRY(launch_blend_bwd(v.descs, L.B, kp, v.recs, svals, seidx, v.ranges, v.ctrl + kCtrlOverflow,
-                                 (uint32_t)L.tiles, order, queue, pblocks, T_final, last, dLdC, v.slots, v.cmask,
-                                 L.cmask_words, s),
+                                 (uint32_t)L.tiles, order, queue, pblocks, T_final, last, dLdC, v.slots, v.svalid,
+                                 v.cmask, L.cmask_words, s),
                 "blend bwd");
     }
     StageScope sc(ctx, kStProjectBwd, s);
-    HIP_TRY(launch_project_bwd(v.descs, L.B, (int32_t)L.n, kp, v.recs, v.count, v.off_id, v.slots,
+    HIP_TRY(launch_project_bwd(v.descs, L.B, (int32_t)L.n, kp, v.recs, v.count, v.off_id, v.slots, v.svalid,
                                v.ctrl + kCtrlOverflow, dscreen, s),
             "project bwd");
     return WIPES_OK;

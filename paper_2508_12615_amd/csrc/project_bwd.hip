@@ -26,6 +26,7 @@ __global__ void __launch_bounds__(256) k_project_bwd(const ImgDesc* __restrict__
                                                       const uint32_t* __restrict__ count,
                                                       const uint32_t* __restrict__ off_id,
                                                       const float* __restrict__ slots,
+                                                      const uint32_t* __restrict__ valid,
                                                       const uint32_t* __restrict__ overflow,
                                                       float* __restrict__ dscreen)
 {
@@ -49,10 +50,16 @@ __global__ void __launch_bounds__(256) k_project_bwd(const ImgDesc* __restrict__
     for (int k = 0; k < 11; ++k) acc[k] = 0.0f;
     for (uint32_t k0 = 0; k0 < total; k0 += kWave) {
         if (k0 + (uint32_t)l < total) {
-            const float4* sl = reinterpret_cast<const float4*>(slots + (size_t)(first + k0 + (uint32_t)l) * kSlotB);
-            s_slot[wv][l][0] = sl[0];
-            s_slot[wv][l][1] = sl[1];
-            s_slot[wv][l][2] = sl[2];
+            // a slot the backward did not write (no pixel of its tile reached it) is zero
+            const uint32_t e = first + k0 + (uint32_t)l;
+            if ((valid[e >> 5] >> (e & 31u)) & 1u) {
+                const float4* sl = reinterpret_cast<const float4*>(slots + (size_t)e * kSlotB);
+                s_slot[wv][l][0] = sl[0];
+                s_slot[wv][l][1] = sl[1];
+                s_slot[wv][l][2] = sl[2];
+            } else {
+                s_slot[wv][l][0] = s_slot[wv][l][1] = s_slot[wv][l][2] = make_float4(0.f, 0.f, 0.f, 0.f);
+            }
         }
         wave_lds_sync();
         const uint32_t e1 = min(my1, k0 + kWave);
@@ -228,11 +235,11 @@ __global__ void __launch_bounds__(256) k_project_bwd(const ImgDesc* __restrict__
 
 hipError_t launch_project_bwd(const ImgDesc* descs, int B, int32_t n_total, const KParams& kp, const Rec* recs,
                               const uint32_t* count, const uint32_t* off_id, const float* slots,
-                              const uint32_t* overflow, float* dscreen, hipStream_t s)
+                              const uint32_t* valid, const uint32_t* overflow, float* dscreen, hipStream_t s)
 {
     if (n_total > 0)
         hipLaunchKernelGGL(k_project_bwd, dim3(((uint32_t)n_total + 255u) / 256u), dim3(256), 0, s, descs, B, n_total,
-                           kp, recs, count, off_id, slots, overflow, dscreen);
+                           kp, recs, count, off_id, slots, valid, overflow, dscreen);
     return hipGetLastError();
 }
 
