@@ -145,12 +145,6 @@ __device__ __forceinline__ TileGeo tile_geo(const ImgDesc* __restrict__ descs, i
     return g;
 }
 
-__device__ __forceinline__ int32_t wave_min_i32(int32_t v)
-{
-    for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, kWave));
-    return v;
-}
-
 // Next tile from the persistent queue (called by one thread): counter
 // `lane` first, then the others in turn once it runs dry, so every tile is
 // handed out exactly once and a workgroup never waits on an empty lane while
@@ -191,15 +185,29 @@ struct PixBox {
     int x0, y0, x1, y1;
 };
 
-// Bounding box (image pixels) of the lanes with `on` set, wave-uniform; an
-// empty set gives an inverted box that no primitive meets.
-__device__ __forceinline__ PixBox pix_box(bool on, int px, int py)
+// Bounding box (image pixels) of the set lanes of the ballot m of an 8 x 8
+// block at (bx, by) whose lane l holds pixel (l & 7, l >> 3): columns are the
+// OR of the eight bytes, rows the non-zero bytes -- scalar bit operations
+// only.  An empty set gives an inverted box that no primitive meets.
+__device__ __forceinline__ PixBox block_box(uint64_t m, int bx, int by)
 {
     PixBox b;
-    b.x0 = __builtin_amdgcn_readfirstlane(wave_min_i32(on ? px : 1 << 20));
-    b.y0 = __builtin_amdgcn_readfirstlane(wave_min_i32(on ? py : 1 << 20));
-    b.x1 = __builtin_amdgcn_readfirstlane(wave_max_i32(on ? px : -(1 << 20)));
-    b.y1 = __builtin_amdgcn_readfirstlane(wave_max_i32(on ? py : -(1 << 20)));
+    if (m == 0ull) {
+        b.x0 = b.y0 = 1 << 20;
+        b.x1 = b.y1 = -(1 << 20);
+        return b;
+    }
+    uint64_t t = m | (m >> 32);
+    t |= t >> 16;
+    t |= t >> 8;
+    const uint32_t cols = (uint32_t)t & 0xffu;
+    uint32_t rows = 0;
+#pragma unroll
+    for (int r = 0; r < 8; ++r) rows |= ((m >> (8 * r)) & 0xffull) ? (1u << r) : 0u;
+    b.x0 = bx + __builtin_ctz(cols);
+    b.x1 = bx + 31 - __builtin_clz(cols);
+    b.y0 = by + __builtin_ctz(rows);
+    b.y1 = by + 31 - __builtin_clz(rows);
     return b;
 }
 
@@ -282,7 +290,7 @@ __device__ __forceinline__ void fwd_block(const ImgDesc* __restrict__ descs, int
     float C0 = 0.0f, C1 = 0.0f, C2 = 0.0f, T = 1.0f;
     int32_t lst = -1;
     bool alive = valid;
-    PixBox live = pix_box(alive, px, py);
+    PixBox live = block_box(__ballot(alive), bx, by);
     const float thr2 = kp.q_add * kConicScale;
     unsigned long long* cm_row = cmask ? cmask + (size_t)blk * cmask_words : nullptr;
     if (G.start < G.end) {
@@ -344,11 +352,12 @@ __device__ __forceinline__ void fwd_block(const ImgDesc* __restrict__ descs, int
                 }
                 if (__ballot(adds)) contrib |= 1ull << (S.pos & 63u);
                 if (__ballot(died)) {
-                    if (__ballot(alive) == 0ull) {
+                    const uint64_t am = __ballot(alive);
+                    if (am == 0ull) {
                         left = false;
                         break;
                     }
-                    live = pix_box(alive, px, py);
+                    live = block_box(am, bx, by);
                 }
             }
             // a word can be shared with the neighbouring tile's list: OR, not store
