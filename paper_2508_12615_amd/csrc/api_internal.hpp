@@ -66,6 +66,7 @@ struct Layout {
     int64_t n = 0, pixels = 0, tiles = 0, cap = 0;
     // screen buffer
     size_t s_recs, s_aux, s_count, s_off_id, s_dkey_a, s_dval_a, s_dkey_b, s_dval_b, s_off_rank, s_dhist, s_ddtot;
+    size_t s_pk, s_pkr, s_cnt_r;   // packed {count, box0, box1, slot base} per primitive / per depth rank
     size_t s_bsum, s_bsum2, s_ctrl, s_descs, screen_bytes;
     // bins buffer
     size_t b_keys_a, b_vals_a, b_keys_b, b_vals_b, b_hist, b_dtot, b_ranges, b_order, b_tbsum, b_w_a, b_w_b, b_slots;
@@ -117,10 +118,12 @@ wipes_status render_stats_core(wipes_ctx* ctx, const wipes_params* p, const wipe
 hipError_t launch_project(const ImgDesc* descs, int B, int32_t n_total, const KParams& kp, Rec* recs, Aux* aux,
                           hipStream_t s);
 hipError_t launch_bin_count(const ImgDesc* descs, int B, int32_t n_total, const KParams& kp, Rec* recs,
-                            const void* aux, uint32_t* count, uint32_t* dkey, uint32_t* dval, hipStream_t s);
-hipError_t launch_emit(const ImgDesc* descs, int B, int32_t n_total, const KParams& kp, const Rec* recs,
-                       const uint32_t* count, const uint32_t* order, const uint32_t* offs, const uint32_t* off_id,
-                       const uint32_t* n_eff, uint32_t* keys, uint32_t* vals, uint32_t* eidx, hipStream_t s);
+                            const void* aux, uint32_t* count, uint4* pk, uint32_t* dkey, uint32_t* dval, hipStream_t s);
+hipError_t launch_rank_pack(int32_t n_total, const uint32_t* order, const uint4* pk, const uint32_t* off_id,
+                            uint4* pkr, uint32_t* cnt_r, hipStream_t s);
+hipError_t launch_emit(const ImgDesc* descs, int B, int32_t n_total, const KParams& kp, const uint4* pkx,
+                       const uint32_t* order, const uint32_t* offs, const uint32_t* n_eff, uint32_t* keys,
+                       uint32_t* vals, uint32_t* eidx, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t n, uint32_t v, hipStream_t s);
 hipError_t launch_tile_lpt_keys(const uint2* ranges, uint32_t n_tiles, uint32_t* keys, uint32_t* vals, hipStream_t s);
 hipError_t launch_ranges(const uint32_t* keys, const uint32_t* n_eff, uint32_t max_k, uint2* ranges, hipStream_t s);

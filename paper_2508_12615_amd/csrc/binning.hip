@@ -21,13 +21,15 @@ namespace wipes {
 constexpr uint32_t kEmptyBox0 = 0x0000ffffu;   // x0 = 65535 > x1 = 0
 constexpr uint32_t kEmptyBox1 = 0u;
 
-// count[i] = tiles touched; writes the pixel box into the record.  Alpha mode
-// also emits (depth key, index) pairs for the depth sort, with culled or
-// off-screen primitives keyed to the end.
+// count[i] = tiles touched; writes the pixel box into the record and
+// {count, box0, box1, -} into pk[i] (read by the emission in one 16-byte
+// load).  Alpha mode also emits (depth key, index) pairs for the depth sort,
+// with culled or off-screen primitives keyed to the end.
 __global__ void __launch_bounds__(256) k_bin_count(const ImgDesc* __restrict__ descs, int B, int32_t n_total,
                                                     KParams kp, Rec* __restrict__ recs,
                                                     const Aux* __restrict__ aux, uint32_t* __restrict__ count,
-                                                    uint32_t* __restrict__ dkey, uint32_t* __restrict__ dval)
+                                                    uint4* __restrict__ pk, uint32_t* __restrict__ dkey,
+                                                    uint32_t* __restrict__ dval)
 {
     const int32_t i = (int32_t)(blockIdx.x * 256u + threadIdx.x);
     if (i >= n_total) return;
@@ -53,30 +55,47 @@ __global__ void __launch_bounds__(256) k_bin_count(const ImgDesc* __restrict__ d
     recs[i].box0 = b0;
     recs[i].box1 = b1;
     count[i] = c;
+    pk[i] = make_uint4(c, b0, b1, 0u);
     if (dkey) {
         dkey[i] = c ? __float_as_uint(a.depth) : 0xffffffffu;
         dval[i] = (uint32_t)i;
     }
 }
 
-// Writes the instances of the primitive of rank r (ranks are primitive
-// indices, or depth order when `order` is given) at offs[r]..: key = global
-// tile, value = primitive, tiles of the pixel box row-major.  With eidx set,
-// also each instance's index in primitive-index emission order,
-// off_id[prim] + (position in the tile rectangle): the slot the backward
-// writes that instance's gradients to, so the projection backward reads each
-// primitive's slots contiguously.
+// Depth-rank order of the packed per-primitive data: pkr[r] = {count, box0,
+// box1, slot base off_id} of primitive order[r], cnt_r[r] its count.  One
+// gather here lets the rank scan and the emission read coalesced.
+__global__ void __launch_bounds__(256) k_rank_pack(int32_t n_total, const uint32_t* __restrict__ order,
+                                                    const uint4* __restrict__ pk,
+                                                    const uint32_t* __restrict__ off_id, uint4* __restrict__ pkr,
+                                                    uint32_t* __restrict__ cnt_r)
+{
+    const int32_t r = (int32_t)(blockIdx.x * 256u + threadIdx.x);
+    if (r >= n_total) return;
+    const uint32_t prim = order[r];
+    uint4 q = pk[prim];
+    q.w = off_id[prim];
+    pkr[r] = q;
+    cnt_r[r] = q.x;
+}
+
+// Writes the instances of the primitive of rank r at offs[r]..: key = global
+// tile, value = primitive, tiles of the pixel box row-major.  Ranks are
+// primitive indices (order == NULL; pkx = per-primitive pack, offs = off_id)
+// or depth ranks (pkx = per-rank pack, prim = order[r]).  With eidx set, also
+// each instance's index in primitive-index emission order, slot base +
+// (position in the tile rectangle): the slot the backward writes that
+// instance's gradients to, so the projection backward reads each primitive's
+// slots contiguously.
 //
 // A wave owns 64 consecutive ranks, whose instances form one contiguous run;
 // it walks that run 64 entries at a time and each lane finds its entry's
 // primitive by a binary search over the 64 start offsets in LDS, so every
 // store is coalesced however uneven the per-primitive counts are.
 __global__ void __launch_bounds__(256) k_emit(const ImgDesc* __restrict__ descs, int B, int32_t n_total,
-                                               KParams kp, const Rec* __restrict__ recs,
-                                               const uint32_t* __restrict__ count,
+                                               KParams kp, const uint4* __restrict__ pkx,
                                                const uint32_t* __restrict__ order,
                                                const uint32_t* __restrict__ offs,
-                                               const uint32_t* __restrict__ off_id,
                                                const uint32_t* __restrict__ n_eff, uint32_t* __restrict__ keys,
                                                uint32_t* __restrict__ vals, uint32_t* __restrict__ eidx)
 {
@@ -88,18 +107,18 @@ __global__ void __launch_bounds__(256) k_emit(const ImgDesc* __restrict__ descs,
     const int32_t r = r0 + l;
     uint32_t c = 0, prim = 0, base = 0, tilesx = 1, wd = 1, e0 = 0, off = 0xffffffffu;
     if (r < n_total) {
+        const uint4 q = pkx[r];
         prim = order ? order[r] : (uint32_t)r;
-        c = count[prim];
+        c = q.x;
         off = offs[r];
         if (c) {
             const ImgDesc& d = descs[image_of_prim(descs, B, (int32_t)prim)];
-            const uint32_t b0 = recs[prim].box0, b1 = recs[prim].box1;
-            const int32_t tx0 = lo16(b0) >> kp.log2_tw, ty0 = hi16(b0) >> kp.log2_th;
-            const int32_t tx1 = lo16(b1) >> kp.log2_tw;
+            const int32_t tx0 = lo16(q.y) >> kp.log2_tw, ty0 = hi16(q.y) >> kp.log2_th;
+            const int32_t tx1 = lo16(q.z) >> kp.log2_tw;
             wd = (uint32_t)(tx1 - tx0 + 1);
             tilesx = (uint32_t)d.tiles_x;
             base = (uint32_t)(d.tile_begin + ty0 * d.tiles_x + tx0);
-            e0 = eidx ? off_id[prim] : 0u;
+            e0 = order ? q.w : off;
         }
     }
     const uint32_t first = (uint32_t)__builtin_amdgcn_readfirstlane((int)off);   // lane 0 is in range
@@ -174,21 +193,30 @@ __global__ void __launch_bounds__(256) k_fill_u32(uint32_t* __restrict__ p, uint
 static inline uint32_t blocks_of(uint32_t n) { return (n + 255u) / 256u; }
 
 hipError_t launch_bin_count(const ImgDesc* descs, int B, int32_t n_total, const KParams& kp, Rec* recs,
-                            const void* aux, uint32_t* count, uint32_t* dkey, uint32_t* dval, hipStream_t s)
+                            const void* aux, uint32_t* count, uint4* pk, uint32_t* dkey, uint32_t* dval, hipStream_t s)
 {
     if (n_total > 0)
         hipLaunchKernelGGL(k_bin_count, dim3(blocks_of((uint32_t)n_total)), dim3(256), 0, s, descs, B, n_total, kp,
-                           recs, (const Aux*)aux, count, dkey, dval);
+                           recs, (const Aux*)aux, count, pk, dkey, dval);
     return hipGetLastError();
 }
 
-hipError_t launch_emit(const ImgDesc* descs, int B, int32_t n_total, const KParams& kp, const Rec* recs,
-                       const uint32_t* count, const uint32_t* order, const uint32_t* offs, const uint32_t* off_id,
-                       const uint32_t* n_eff, uint32_t* keys, uint32_t* vals, uint32_t* eidx, hipStream_t s)
+hipError_t launch_rank_pack(int32_t n_total, const uint32_t* order, const uint4* pk, const uint32_t* off_id,
+                            uint4* pkr, uint32_t* cnt_r, hipStream_t s)
 {
     if (n_total > 0)
-        hipLaunchKernelGGL(k_emit, dim3(blocks_of((uint32_t)n_total)), dim3(256), 0, s, descs, B, n_total, kp, recs,
-                           count, order, offs, off_id, n_eff, keys, vals, eidx);
+        hipLaunchKernelGGL(k_rank_pack, dim3(blocks_of((uint32_t)n_total)), dim3(256), 0, s, n_total, order, pk,
+                           off_id, pkr, cnt_r);
+    return hipGetLastError();
+}
+
+hipError_t launch_emit(const ImgDesc* descs, int B, int32_t n_total, const KParams& kp, const uint4* pkx,
+                       const uint32_t* order, const uint32_t* offs, const uint32_t* n_eff, uint32_t* keys,
+                       uint32_t* vals, uint32_t* eidx, hipStream_t s)
+{
+    if (n_total > 0)
+        hipLaunchKernelGGL(k_emit, dim3(blocks_of((uint32_t)n_total)), dim3(256), 0, s, descs, B, n_total, kp, pkx,
+                           order, offs, n_eff, keys, vals, eidx);
     return hipGetLastError();
 }
 

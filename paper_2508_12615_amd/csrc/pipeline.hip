@@ -19,6 +19,8 @@ struct Views {
     Aux* aux;
     uint32_t *count, *off_id, *dkey_a, *dval_a, *dkey_b, *dval_b, *off_rank, *dhist, *ddtot, *bsum, *bsum2, *ctrl;
     ImgDesc* descs;
+    uint4 *pk, *pkr;
+    uint32_t* cnt_r;
     uint32_t *keys_a, *vals_a, *keys_b, *vals_b, *hist, *dtot, *order, *tbsum, *w_a, *w_b;
     uint2* ranges;
     float* slots;
@@ -35,12 +37,15 @@ static Views views(const Layout& L, const void* screen, const void* bins)
     v.aux = (Aux*)(s + L.s_aux);
     v.count = (uint32_t*)(s + L.s_count);
     v.off_id = (uint32_t*)(s + L.s_off_id);
+    v.pk = (uint4*)(s + L.s_pk);
     if (L.alpha) {
         v.dkey_a = (uint32_t*)(s + L.s_dkey_a);
         v.dval_a = (uint32_t*)(s + L.s_dval_a);
         v.dkey_b = (uint32_t*)(s + L.s_dkey_b);
         v.dval_b = (uint32_t*)(s + L.s_dval_b);
         v.off_rank = (uint32_t*)(s + L.s_off_rank);
+        v.pkr = (uint4*)(s + L.s_pkr);
+        v.cnt_r = (uint32_t*)(s + L.s_cnt_r);
         v.dhist = (uint32_t*)(s + L.s_dhist);
         v.ddtot = (uint32_t*)(s + L.s_ddtot);
     }
@@ -92,7 +97,8 @@ wipes_status bin_sort_core(wipes_ctx* ctx, const wipes_params* p, const wipes_ba
     const uint32_t n = (uint32_t)L.n;
     {
         StageScope sc(ctx, kStCount, s);
-        HIP_TRY(launch_bin_count(v.descs, L.B, (int32_t)n, kp, v.recs, v.aux, v.count, v.dkey_a, v.dval_a, s), "count");
+        HIP_TRY(launch_bin_count(v.descs, L.B, (int32_t)n, kp, v.recs, v.aux, v.count, v.pk, v.dkey_a, v.dval_a, s),
+                "count");
     }
     // K, capacity check -> n_eff, overflow flag
     {
@@ -113,7 +119,9 @@ wipes_status bin_sort_core(wipes_ctx* ctx, const wipes_params* p, const wipes_ba
         order = in_b ? v.dval_b : v.dval_a;
         {
             StageScope sc(ctx, kStRankScan, s);
-            HIP_TRY(scan_excl(v.count, order, n, nullptr, n, v.bsum2, v.off_rank, v.ctrl + 3, 0, nullptr, nullptr, s),
+            HIP_TRY(launch_rank_pack((int32_t)n, order, v.pk, v.off_id, v.pkr, v.cnt_r, s), "rank pack");
+            HIP_TRY(scan_excl(v.cnt_r, nullptr, n, nullptr, n, v.bsum2, v.off_rank, v.ctrl + 3, 0, nullptr, nullptr,
+                              s),
                     "rank scan");
         }
         offs = v.off_rank;
@@ -129,7 +137,7 @@ wipes_status bin_sort_core(wipes_ctx* ctx, const wipes_params* p, const wipes_ba
     }
     {
         StageScope sc(ctx, kStEmit, s);
-        HIP_TRY(launch_emit(v.descs, L.B, (int32_t)n, kp, v.recs, v.count, order, offs, v.off_id, v.ctrl + kCtrlNEff,
+        HIP_TRY(launch_emit(v.descs, L.B, (int32_t)n, kp, L.alpha ? v.pkr : v.pk, order, offs, v.ctrl + kCtrlNEff,
                             v.keys_a, v.vals_a, v.w_a, s),
                 "emit");
     }

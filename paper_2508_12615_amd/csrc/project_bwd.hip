@@ -14,12 +14,15 @@
 //                  dL/dSigma = M^T G M, dL/df = M^T dL/df', then J(t), mu'(t),
 //                  t = W mu + w and Sigma = V V^T with V = R(q) diag(s),
 //                  q normalised inside.
-// The arithmetic is FP64, like the forward projection.
+// The arithmetic is FP32: the inputs (screen record, slot sums, parameters)
+// are FP32 and the gradients are compared at 1e-3 relative, so FP64 would only
+// cost time (the forward projection is FP64 for the mean's sub-pixel phase).
 #include "common.hpp"
 
 namespace wipes {
 
 constexpr int kSlotB = 12;
+using real = float;
 
 __global__ void __launch_bounds__(256) k_project_bwd(const ImgDesc* __restrict__ descs, int B, int32_t n_total,
                                                       KParams kp, const Rec* __restrict__ recs,
@@ -94,108 +97,108 @@ __global__ void __launch_bounds__(256) k_project_bwd(const ImgDesc* __restrict__
     }
     // dL/dSigma' = -A GA A
     const Rec& R = recs[i];
-    const double a = R.ca, b = R.cb, cc = R.cc;
-    const double ga = acc[2], gb = 0.5 * (double)acc[3], gc = acc[4];
-    const double P00 = a * ga + b * gb, P01 = a * gb + b * gc, P10 = b * ga + cc * gb, P11 = b * gb + cc * gc;
-    const double G00 = -(P00 * a + P01 * b), G01 = -(P00 * b + P01 * cc), G11 = -(P10 * b + P11 * cc);
+    const real a = R.ca, b = R.cb, cc = R.cc;
+    const real ga = acc[2], gb = 0.5f * (real)acc[3], gc = acc[4];
+    const real P00 = a * ga + b * gb, P01 = a * gb + b * gc, P10 = b * ga + cc * gb, P11 = b * gb + cc * gc;
+    const real G00 = -(P00 * a + P01 * b), G01 = -(P00 * b + P01 * cc), G11 = -(P10 * b + P11 * cc);
 
     if (kp.mode == WIPES_2D_ADDITIVE) {
         if (d.g_mean) { d.g_mean[2 * j] = acc[0]; d.g_mean[2 * j + 1] = acc[1]; }
         if (d.g_freq) { d.g_freq[2 * j] = acc[5]; d.g_freq[2 * j + 1] = acc[6]; }
         if (!d.g_cov) return;
-        const double c0 = d.cov[3 * j], c1 = d.cov[3 * j + 1], c2 = d.cov[3 * j + 2];
+        const real c0 = d.cov[3 * j], c1 = d.cov[3 * j + 1], c2 = d.cov[3 * j + 2];
         if (kp.cov == WIPES_COV_CHOLESKY) {
-            d.g_cov[3 * j] = (float)(2.0 * (G00 * c0 + G01 * c1));
-            d.g_cov[3 * j + 1] = (float)(2.0 * (G01 * c0 + G11 * c1));
-            d.g_cov[3 * j + 2] = (float)(2.0 * G11 * c2);
+            d.g_cov[3 * j] = (float)(2.0f * (G00 * c0 + G01 * c1));
+            d.g_cov[3 * j + 1] = (float)(2.0f * (G01 * c0 + G11 * c1));
+            d.g_cov[3 * j + 2] = (float)(2.0f * G11 * c2);
         } else {
-            double sn, cs;
-            sincos(c2, &sn, &cs);
+            real sn, cs;
+            sincosf(c2, &sn, &cs);
             // r0 = (cs, sn), r1 = (-sn, cs)
-            const double q00 = cs * (G00 * cs + G01 * sn) + sn * (G01 * cs + G11 * sn);
-            const double q11 = -sn * (-G00 * sn + G01 * cs) + cs * (-G01 * sn + G11 * cs);
-            const double q01 = cs * (-G00 * sn + G01 * cs) + sn * (-G01 * sn + G11 * cs);
-            d.g_cov[3 * j] = (float)(2.0 * c0 * q00);
-            d.g_cov[3 * j + 1] = (float)(2.0 * c1 * q11);
-            d.g_cov[3 * j + 2] = (float)(2.0 * (c0 * c0 - c1 * c1) * q01);
+            const real q00 = cs * (G00 * cs + G01 * sn) + sn * (G01 * cs + G11 * sn);
+            const real q11 = -sn * (-G00 * sn + G01 * cs) + cs * (-G01 * sn + G11 * cs);
+            const real q01 = cs * (-G00 * sn + G01 * cs) + sn * (-G01 * sn + G11 * cs);
+            d.g_cov[3 * j] = (float)(2.0f * c0 * q00);
+            d.g_cov[3 * j + 1] = (float)(2.0f * c1 * q11);
+            d.g_cov[3 * j + 2] = (float)(2.0f * (c0 * c0 - c1 * c1) * q01);
         }
         return;
     }
 
     // ---- 3D: recompute the forward quantities
-    double m[3];
+    real m[3];
     for (int k = 0; k < 3; ++k)
-        m[k] = (double)d.mean[3 * j + k] + (d.vel ? (double)d.vel[3 * j + k] * (double)d.time : 0.0);
-    double t[3];
+        m[k] = (real)d.mean[3 * j + k] + (d.vel ? (real)d.vel[3 * j + k] * (real)d.time : 0.0f);
+    real t[3];
     for (int r = 0; r < 3; ++r)
-        t[r] = (double)d.view[4 * r] * m[0] + (double)d.view[4 * r + 1] * m[1] + (double)d.view[4 * r + 2] * m[2] +
-               (double)d.view[4 * r + 3];
-    const double tz = t[2], iz = 1.0 / tz;
-    const double ur = t[0] * iz, vr = t[1] * iz;
-    const double lx = d.limx, ly = d.limy;
+        t[r] = (real)d.view[4 * r] * m[0] + (real)d.view[4 * r + 1] * m[1] + (real)d.view[4 * r + 2] * m[2] +
+               (real)d.view[4 * r + 3];
+    const real tz = t[2], iz = 1.0f / tz;
+    const real ur = t[0] * iz, vr = t[1] * iz;
+    const real lx = d.limx, ly = d.limy;
     const bool clx = ur < -lx || ur > lx, cly = vr < -ly || vr > ly;
-    const double u = clx ? (ur < 0 ? -lx : lx) : ur;
-    const double v = cly ? (vr < 0 ? -ly : ly) : vr;
-    const double fxc = d.fx, fyc = d.fy;
-    const double J00 = fxc * iz, J02 = -fxc * u * iz, J11 = fyc * iz, J12 = -fyc * v * iz;
-    double Rw[3][3];
+    const real u = clx ? (ur < 0 ? -lx : lx) : ur;
+    const real v = cly ? (vr < 0 ? -ly : ly) : vr;
+    const real fxc = d.fx, fyc = d.fy;
+    const real J00 = fxc * iz, J02 = -fxc * u * iz, J11 = fyc * iz, J12 = -fyc * v * iz;
+    real Rw[3][3];
     for (int r = 0; r < 3; ++r)
         for (int k = 0; k < 3; ++k) Rw[r][k] = d.view[4 * r + k];
-    double M[2][3];
+    real M[2][3];
     for (int k = 0; k < 3; ++k) {
         M[0][k] = J00 * Rw[0][k] + J02 * Rw[2][k];
         M[1][k] = J11 * Rw[1][k] + J12 * Rw[2][k];
     }
-    const double q0r = d.quat[4 * j], q1r = d.quat[4 * j + 1], q2r = d.quat[4 * j + 2], q3r = d.quat[4 * j + 3];
-    const double qn = sqrt(q0r * q0r + q1r * q1r + q2r * q2r + q3r * q3r);
-    const double w = q0r / qn, x = q1r / qn, y = q2r / qn, z = q3r / qn;
-    const double Rq[3][3] = {{1.0 - 2.0 * (y * y + z * z), 2.0 * (x * y - w * z), 2.0 * (x * z + w * y)},
-                             {2.0 * (x * y + w * z), 1.0 - 2.0 * (x * x + z * z), 2.0 * (y * z - w * x)},
-                             {2.0 * (x * z - w * y), 2.0 * (y * z + w * x), 1.0 - 2.0 * (x * x + y * y)}};
-    const double s[3] = {d.scale[3 * j], d.scale[3 * j + 1], d.scale[3 * j + 2]};
-    double V[3][3];   // Rq diag(s)
+    const real q0r = d.quat[4 * j], q1r = d.quat[4 * j + 1], q2r = d.quat[4 * j + 2], q3r = d.quat[4 * j + 3];
+    const real qn = sqrtf(q0r * q0r + q1r * q1r + q2r * q2r + q3r * q3r);
+    const real w = q0r / qn, x = q1r / qn, y = q2r / qn, z = q3r / qn;
+    const real Rq[3][3] = {{1.0f - 2.0f * (y * y + z * z), 2.0f * (x * y - w * z), 2.0f * (x * z + w * y)},
+                             {2.0f * (x * y + w * z), 1.0f - 2.0f * (x * x + z * z), 2.0f * (y * z - w * x)},
+                             {2.0f * (x * z - w * y), 2.0f * (y * z + w * x), 1.0f - 2.0f * (x * x + y * y)}};
+    const real s[3] = {d.scale[3 * j], d.scale[3 * j + 1], d.scale[3 * j + 2]};
+    real V[3][3];   // Rq diag(s)
     for (int r = 0; r < 3; ++r)
         for (int k = 0; k < 3; ++k) V[r][k] = Rq[r][k] * s[k];
-    double T[2][3];   // M V
+    real T[2][3];   // M V
     for (int r = 0; r < 2; ++r)
         for (int k = 0; k < 3; ++k) T[r][k] = M[r][0] * V[0][k] + M[r][1] * V[1][k] + M[r][2] * V[2][k];
-    const double f3[3] = {d.freq[3 * j], d.freq[3 * j + 1], d.freq[3 * j + 2]};
-    const double dfp[2] = {acc[5], acc[6]};
-    const double G[2][2] = {{G00, G01}, {G01, G11}};
+    const real f3[3] = {d.freq[3 * j], d.freq[3 * j + 1], d.freq[3 * j + 2]};
+    const real dfp[2] = {acc[5], acc[6]};
+    const real G[2][2] = {{G00, G01}, {G01, G11}};
     // dM = 2 G (M Sigma) + dfp f^T,  M Sigma = T V^T
-    double MS[2][3];
+    real MS[2][3];
     for (int r = 0; r < 2; ++r)
         for (int k = 0; k < 3; ++k) MS[r][k] = T[r][0] * V[k][0] + T[r][1] * V[k][1] + T[r][2] * V[k][2];
-    double dM[2][3];
+    real dM[2][3];
     for (int r = 0; r < 2; ++r)
-        for (int k = 0; k < 3; ++k) dM[r][k] = 2.0 * (G[r][0] * MS[0][k] + G[r][1] * MS[1][k]) + dfp[r] * f3[k];
+        for (int k = 0; k < 3; ++k) dM[r][k] = 2.0f * (G[r][0] * MS[0][k] + G[r][1] * MS[1][k]) + dfp[r] * f3[k];
     // dSigma = M^T G M
-    double GM[2][3];
+    real GM[2][3];
     for (int r = 0; r < 2; ++r)
         for (int k = 0; k < 3; ++k) GM[r][k] = G[r][0] * M[0][k] + G[r][1] * M[1][k];
-    double dS[3][3];
+    real dS[3][3];
     for (int r = 0; r < 3; ++r)
         for (int k = 0; k < 3; ++k) dS[r][k] = M[0][r] * GM[0][k] + M[1][r] * GM[1][k];
     // Sigma = V V^T: dV = 2 dS V
-    double dV[3][3];
+    real dV[3][3];
     for (int r = 0; r < 3; ++r)
-        for (int k = 0; k < 3; ++k) dV[r][k] = 2.0 * (dS[r][0] * V[0][k] + dS[r][1] * V[1][k] + dS[r][2] * V[2][k]);
+        for (int k = 0; k < 3; ++k) dV[r][k] = 2.0f * (dS[r][0] * V[0][k] + dS[r][1] * V[1][k] + dS[r][2] * V[2][k]);
     if (d.g_scale)
         for (int k = 0; k < 3; ++k)
             d.g_scale[3 * j + k] = (float)(dV[0][k] * Rq[0][k] + dV[1][k] * Rq[1][k] + dV[2][k] * Rq[2][k]);
     if (d.g_quat) {
-        double dR[3][3];
+        real dR[3][3];
         for (int r = 0; r < 3; ++r)
             for (int k = 0; k < 3; ++k) dR[r][k] = dV[r][k] * s[k];
-        const double dw = 2.0 * (-z * dR[0][1] + y * dR[0][2] + z * dR[1][0] - x * dR[1][2] - y * dR[2][0] +
+        const real dw = 2.0f * (-z * dR[0][1] + y * dR[0][2] + z * dR[1][0] - x * dR[1][2] - y * dR[2][0] +
                                  x * dR[2][1]);
-        const double dx = 2.0 * (y * dR[0][1] + z * dR[0][2] + y * dR[1][0] - 2.0 * x * dR[1][1] - w * dR[1][2] +
-                                 z * dR[2][0] + w * dR[2][1] - 2.0 * x * dR[2][2]);
-        const double dy = 2.0 * (-2.0 * y * dR[0][0] + x * dR[0][1] + w * dR[0][2] + x * dR[1][0] + z * dR[1][2] -
-                                 w * dR[2][0] + z * dR[2][1] - 2.0 * y * dR[2][2]);
-        const double dz = 2.0 * (-2.0 * z * dR[0][0] - w * dR[0][1] + x * dR[0][2] + w * dR[1][0] -
-                                 2.0 * z * dR[1][1] + y * dR[1][2] + x * dR[2][0] + y * dR[2][1]);
-        const double dot = w * dw + x * dx + y * dy + z * dz;
+        const real dx = 2.0f * (y * dR[0][1] + z * dR[0][2] + y * dR[1][0] - 2.0f * x * dR[1][1] - w * dR[1][2] +
+                                 z * dR[2][0] + w * dR[2][1] - 2.0f * x * dR[2][2]);
+        const real dy = 2.0f * (-2.0f * y * dR[0][0] + x * dR[0][1] + w * dR[0][2] + x * dR[1][0] + z * dR[1][2] -
+                                 w * dR[2][0] + z * dR[2][1] - 2.0f * y * dR[2][2]);
+        const real dz = 2.0f * (-2.0f * z * dR[0][0] - w * dR[0][1] + x * dR[0][2] + w * dR[1][0] -
+                                 2.0f * z * dR[1][1] + y * dR[1][2] + x * dR[2][0] + y * dR[2][1]);
+        const real dot = w * dw + x * dx + y * dy + z * dz;
         d.g_quat[4 * j] = (float)((dw - w * dot) / qn);
         d.g_quat[4 * j + 1] = (float)((dx - x * dot) / qn);
         d.g_quat[4 * j + 2] = (float)((dy - y * dot) / qn);
@@ -204,33 +207,33 @@ __global__ void __launch_bounds__(256) k_project_bwd(const ImgDesc* __restrict__
     if (d.g_freq)
         for (int k = 0; k < 3; ++k) d.g_freq[3 * j + k] = (float)(M[0][k] * dfp[0] + M[1][k] * dfp[1]);
     // dJ = dM W^T
-    double dJ[2][3];
+    real dJ[2][3];
     for (int r = 0; r < 2; ++r)
         for (int k = 0; k < 3; ++k) dJ[r][k] = dM[r][0] * Rw[k][0] + dM[r][1] * Rw[k][1] + dM[r][2] * Rw[k][2];
-    double dt[3] = {0.0, 0.0, 0.0};
-    const double iz2 = iz * iz;
+    real dt[3] = {0.0f, 0.0f, 0.0f};
+    const real iz2 = iz * iz;
     dt[2] += -fxc * iz2 * dJ[0][0] - fyc * iz2 * dJ[1][1];
     if (!clx) {
         dt[0] += -fxc * iz2 * dJ[0][2];
-        dt[2] += 2.0 * fxc * t[0] * iz2 * iz * dJ[0][2];
+        dt[2] += 2.0f * fxc * t[0] * iz2 * iz * dJ[0][2];
     } else {
         dt[2] += fxc * u * iz2 * dJ[0][2];
     }
     if (!cly) {
         dt[1] += -fyc * iz2 * dJ[1][2];
-        dt[2] += 2.0 * fyc * t[1] * iz2 * iz * dJ[1][2];
+        dt[2] += 2.0f * fyc * t[1] * iz2 * iz * dJ[1][2];
     } else {
         dt[2] += fyc * v * iz2 * dJ[1][2];
     }
     dt[0] += fxc * iz * acc[0];
     dt[1] += fyc * iz * acc[1];
     dt[2] += -fxc * t[0] * iz2 * acc[0] - fyc * t[1] * iz2 * acc[1];
-    double dm[3];
+    real dm[3];
     for (int k = 0; k < 3; ++k) dm[k] = Rw[0][k] * dt[0] + Rw[1][k] * dt[1] + Rw[2][k] * dt[2];
     if (d.g_mean)
         for (int k = 0; k < 3; ++k) d.g_mean[3 * j + k] = (float)dm[k];
     if (d.g_vel)
-        for (int k = 0; k < 3; ++k) d.g_vel[3 * j + k] = d.vel ? (float)(dm[k] * (double)d.time) : 0.0f;
+        for (int k = 0; k < 3; ++k) d.g_vel[3 * j + k] = d.vel ? (float)(dm[k] * (real)d.time) : 0.0f;
 }
 
 hipError_t launch_project_bwd(const ImgDesc* descs, int B, int32_t n_total, const KParams& kp, const Rec* recs,
