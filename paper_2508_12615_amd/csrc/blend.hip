@@ -324,6 +324,10 @@ __device__ __forceinline__ void fwd_block(const ImgDesc* __restrict__ descs, int
             uint64_t contrib = 0;   // bit (pos & 63): the primitive at pos contributed to a pixel of the block
             for (int j = 0; j < nh; ++j) {
                 const Staged S = stage[j];
+                // the colour is read with the rest of the record, not inside the
+                // branch below, so its LDS latency overlaps the evaluation
+                float cr = S.r, cg = S.g, cb = S.b;
+                asm volatile("" : "+v"(cr), "+v"(cg), "+v"(cb));
                 const PairEval p = eval_at(S.mrx, S.mry, S.c0, S.c1, S.c2, S.f0, S.f1, lx, ly);
                 if constexpr (MODE == WIPES_2D_ADDITIVE) {
                     const bool in = p.e2 >= thr2;
@@ -340,9 +344,9 @@ __device__ __forceinline__ void fwd_block(const ImgDesc* __restrict__ descs, int
                 if (adds) {
                     const float al = fminf(a, kp.alpha_max);
                     const float wt = T * al;
-                    C0 = fmaf(wt, S.r, C0);
-                    C1 = fmaf(wt, S.g, C1);
-                    C2 = fmaf(wt, S.b, C2);
+                    C0 = fmaf(wt, cr, C0);
+                    C1 = fmaf(wt, cg, C1);
+                    C2 = fmaf(wt, cb, C2);
                     T = T * (1.0f - al);
                     lst = (int32_t)S.pos;
                     if (T < kp.T_min) {
@@ -614,45 +618,49 @@ __device__ __forceinline__ void bwd_tile(const ImgDesc* __restrict__ descs, int 
         for (int j = nh - 1; j >= 0; --j) {
             const Staged S = Sn;
             Sn = st[j > 0 ? j - 1 : 0];
+            // branch-free: a pair that takes no part gets zero weight, for which
+            // every update is an exact identity and every gradient term is zero
             float v[16];
 #pragma unroll
             for (int k = 0; k < 16; ++k) v[k] = 0.0f;
-            bool any = false;
-            if (on && (int32_t)S.pos <= lst) {
-                const PairEval p = eval_at(S.mrx, S.mry, S.c0 * kConicScale, S.c1 * (2.0f * kConicScale),
-                                           S.c2 * kConicScale, S.f0 * kInv2Pi, S.f1 * kInv2Pi, lx, ly);
-                const float a = S.op * p.W;
-                if constexpr (MODE == WIPES_2D_ADDITIVE) {
-                    if (p.e2 >= thr2) {
-                        const float cg = S.r * g0 + S.g * g1 + S.b * g2;
-                        v[8] = a * g0;
-                        v[9] = a * g1;
-                        v[10] = a * g2;
-                        v[7] = p.W * cg;
-                        any = true;
-                        pair_grads(v, p, S.op * cg, S.c0, S.c1, S.c2, S.f0, S.f1);
-                    }
-                } else if (a >= kp.alpha_min) {
-                    const float al = fminf(a, kp.alpha_max);
-                    // T before this pair; the hardware reciprocal (1 ulp) keeps the
-                    // recovery within a few ulp of the forward's T per step
-                    const float Tb = T * __builtin_amdgcn_rcpf(1.0f - al);
-                    const float cg = S.r * g0 + S.g * g1 + S.b * g2;
-                    const float dal = Tb * (cg - Sg);
-                    const float wt = Tb * al;
-                    v[8] = wt * g0;
-                    v[9] = wt * g1;
-                    v[10] = wt * g2;
-                    Sg = fmaf(al, cg - Sg, Sg);
-                    T = Tb;
-                    const float da = a <= kp.alpha_max ? dal : 0.0f;
-                    v[7] = p.W * da;
-                    any = true;
-                    pair_grads(v, p, S.op * da, S.c0, S.c1, S.c2, S.f0, S.f1);
-                }
+            const PairEval p = eval_at(S.mrx, S.mry, S.c0 * kConicScale, S.c1 * (2.0f * kConicScale),
+                                       S.c2 * kConicScale, S.f0 * kInv2Pi, S.f1 * kInv2Pi, lx, ly);
+            const float a = S.op * p.W;
+            const bool reach = on && (int32_t)S.pos <= lst;
+            bool takes;
+            float dW;
+            if constexpr (MODE == WIPES_2D_ADDITIVE) {
+                takes = reach && p.e2 >= thr2;
+                const float cg = S.r * g0 + S.g * g1 + S.b * g2;
+                const float ow = takes ? a : 0.0f;
+                v[8] = ow * g0;
+                v[9] = ow * g1;
+                v[10] = ow * g2;
+                v[7] = takes ? p.W * cg : 0.0f;
+                dW = takes ? S.op * cg : 0.0f;
+            } else {
+                takes = reach && a >= kp.alpha_min;
+                const float al = takes ? fminf(a, kp.alpha_max) : 0.0f;
+                // T before this pair; the hardware reciprocal (1 ulp) keeps the
+                // recovery within a few ulp of the forward's T.  A pair that takes
+                // no part keeps T exactly (selected, not divided by 1).
+                const float Tb = takes ? T * __builtin_amdgcn_rcpf(1.0f - al) : T;
+                const float cg = S.r * g0 + S.g * g1 + S.b * g2;
+                const float dal = Tb * (cg - Sg);
+                const float wt = Tb * al;
+                v[8] = wt * g0;
+                v[9] = wt * g1;
+                v[10] = wt * g2;
+                Sg = fmaf(al, cg - Sg, Sg);
+                T = Tb;
+                const float da = (takes && a <= kp.alpha_max) ? dal : 0.0f;
+                v[7] = p.W * da;
+                dW = S.op * da;
             }
+            pair_grads(v, p, dW, S.c0, S.c1, S.c2, S.f0, S.f1);
+            const bool any = __ballot(takes) != 0ull;
             float* o = mine + (S.pos & 63u) * kSlot;
-            if (__ballot(any)) {
+            if (any) {
                 wave_reduce16_valu(v);
                 const int id = l >> 2;
                 if ((l & 3) == 0 && id < kSlot) o[id] = v[0];
