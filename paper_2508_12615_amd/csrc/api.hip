@@ -188,7 +188,7 @@ Layout layout_of(const wipes_params* p, const wipes_batch* b, int64_t cap, int w
     L.tile_bits = std::max(bits, 1);
     L.tile_result_b = radix_passes(L.tile_bits) & 1;
     L.depth_result_b = radix_passes(32) & 1;
-    L.order_result_b = radix_passes(24) & 1;
+    L.order_result_b = radix_passes(8) & 1;
     return L;
 }
 

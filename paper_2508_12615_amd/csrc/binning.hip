@@ -167,17 +167,18 @@ __global__ void __launch_bounds__(256) k_ranges(const uint32_t* __restrict__ key
     if (s == K - 1 || keys[s + 1] != t) ranges[t].y = s + 1;
 }
 
-// Keys for a longest-list-first tile order: key = 2^24 - 1 - min(list length,
-// 2^24 - 1), value = tile; a stable ascending sort then lists long tiles first
-// (ties in tile order).
+// Keys for a longest-list-first tile order: key = 255 - q(list length) with
+// q = min(255, floor(16 log2(length + 1))) (16 steps per doubling), value =
+// tile; one stable 8-bit pass then lists long tiles first (ties and equal
+// quanta in tile order) -- an approximate order is all the queue needs.
 __global__ void __launch_bounds__(256) k_tile_lpt_keys(const uint2* __restrict__ ranges, uint32_t n_tiles,
                                                         uint32_t* __restrict__ keys, uint32_t* __restrict__ vals)
 {
     const uint32_t t = blockIdx.x * 256u + threadIdx.x;
     if (t >= n_tiles) return;
     const uint2 r = ranges[t];
-    const uint32_t len = min(r.y - r.x, 0xffffffu);
-    keys[t] = 0xffffffu - len;
+    const float q = 16.0f * __log2f((float)(r.y - r.x) + 1.0f);
+    keys[t] = 255u - min((uint32_t)q, 255u);
     vals[t] = t;
 }
 

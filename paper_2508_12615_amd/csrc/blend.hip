@@ -166,6 +166,17 @@ __device__ __forceinline__ uint32_t pull_tile(uint32_t* __restrict__ queue, uint
     return n_tiles;
 }
 
+// Issue priority of a wave by its tile's list length: the kernels' time is
+// set by the serial walk of the heaviest tiles, so their waves go first on a
+// shared SIMD and lighter waves fill the gaps.
+__device__ __forceinline__ void prioritise(uint32_t len)
+{
+    if (len >= 4096u) __builtin_amdgcn_s_setprio(3);
+    else if (len >= 1024u) __builtin_amdgcn_s_setprio(2);
+    else if (len >= 256u) __builtin_amdgcn_s_setprio(1);
+    else __builtin_amdgcn_s_setprio(0);
+}
+
 // ------------------------------------------------------------ block waves
 
 // One staged primitive (48 bytes).  The forward stages the conic and the
@@ -279,6 +290,7 @@ __device__ __forceinline__ void fwd_block(const ImgDesc* __restrict__ descs, int
                                           uint32_t cmask_words, Staged* __restrict__ stage)
 {
     const TileGeo G = tile_geo(descs, B, ranges, t, TW, TH);
+    prioritise(G.end - G.start);
     const ImgDesc& d = descs[G.b];
     const int l = lane_id();
     const int bx = G.ox + (blk % (TW / 8)) * 8, by = G.oy + (blk / (TW / 8)) * 8;
@@ -536,6 +548,7 @@ __device__ __forceinline__ void bwd_tile(const ImgDesc* __restrict__ descs, int 
     const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int l = lane_id(), tid = (int)threadIdx.x;
     const TileGeo G = tile_geo(descs, B, ranges, t, TW, TH);
+    prioritise(G.end - G.start);
     const ImgDesc& d = descs[G.b];
     const int bx = G.ox + (w % NBX) * 8, by = G.oy + (w / NBX) * 8;
     const int px = bx + (l & 7), py = by + (l >> 3);

@@ -159,7 +159,7 @@ wipes_status bin_sort_core(wipes_ctx* ctx, const wipes_params* p, const wipes_ba
         uint32_t* ov = v.order + nt;
         HIP_TRY(launch_tile_lpt_keys(v.ranges, nt, ok, ov, s), "lpt keys");
         int in_b2 = 0;
-        HIP_TRY(radix_sort(ok, ov, ov + nt, ov + 2 * (size_t)nt, nt, nullptr, nt, 24, v.hist, v.dtot, &in_b2, s),
+        HIP_TRY(radix_sort(ok, ov, ov + nt, ov + 2 * (size_t)nt, nt, nullptr, nt, 8, v.hist, v.dtot, &in_b2, s),
                 "lpt sort");
     }
     return WIPES_OK;
