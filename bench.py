@@ -44,7 +44,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--prims", type=int, default=1_000_000)
     ap.add_argument("--tile", type=str, default="16x16")
-    ap.add_argument("--persistent", type=int, default=0)
+    ap.add_argument("--persistent", type=int, default=2,
+                    help="blend launch form: 0 grid, 1 persistent tile queue, 2 queue with longest lists first")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--extras", type=str, default="serve,batched,fit",
                     help="comma list of secondary workloads to add to the JSON line (serve, batched, fit) or none")
@@ -296,7 +297,7 @@ def main():
                data="synthetic",
                config=dict(workload="3D static view synthesis: %d wavelet primitives, %dx%d, alpha blending, "
                                     "fwd+bwd" % (a.prims, W, H), tile="%dx%d" % (tw, th),
-                           persistent=bool(a.persistent), instances=K),
+                           launch=("grid", "tile queue", "tile queue, longest first")[a.persistent], instances=K),
                roofline=roof,
                stages_ms={k: round(v, 4) for k, v in stages.items()},
                roofline_blend={k: alu_roof(k, stages["blend_" + k]) for k in ("fwd", "bwd")

@@ -227,6 +227,28 @@ __device__ __forceinline__ bool box_meets(uint32_t b0, uint32_t b1, const PixBox
     return lo16(b0) <= q.x1 && lo16(b1) >= q.x0 && hi16(b0) <= q.y1 && hi16(b1) >= q.y0;
 }
 
+// Whether the support ellipse {q(x) <= Qs} of record R can reach a pixel
+// centre of the box q (image pixels): the minimum of the convex quadratic
+// q(x) = ca dx^2 + 2 cb dx dy + cc dy^2 over the centre rectangle is 0 if the
+// mean lies inside, else it lies on an edge, where it is a clamped 1-D
+// minimum.  Qs carries a margin over the blend's own threshold, so a pixel
+// the blend would accept is never dropped.
+__device__ __forceinline__ bool ellipse_meets(const Rec& R, const PixBox& q, float Qs)
+{
+    const float mx = R.mx + R.mxl, my = R.my + R.myl;
+    const float x0 = (float)q.x0 + 0.5f, x1 = (float)q.x1 + 0.5f;
+    const float y0 = (float)q.y0 + 0.5f, y1 = (float)q.y1 + 0.5f;
+    if (mx >= x0 && mx <= x1 && my >= y0 && my <= y1) return true;
+    const float sy = -R.cb * __builtin_amdgcn_rcpf(R.cc), sx = -R.cb * __builtin_amdgcn_rcpf(R.ca);
+    auto qv = [&](float dx, float dy) { return fmaf(R.ca * dx, dx, fmaf(2.0f * R.cb * dx, dy, R.cc * dy * dy)); };
+    const float dxa = x0 - mx, dxb = x1 - mx, dya = y0 - my, dyb = y1 - my;
+    float m = qv(dxa, fminf(fmaxf(sy * dxa, dya), dyb));
+    m = fminf(m, qv(dxb, fminf(fmaxf(sy * dxb, dya), dyb)));
+    m = fminf(m, qv(fminf(fmaxf(sx * dya, dxa), dxb), dya));
+    m = fminf(m, qv(fminf(fmaxf(sx * dyb, dxa), dxb), dyb));
+    return m <= Qs;
+}
+
 // box0 of a lane past the end of a chunk: x0 = y0 = 65535 lies beyond every
 // image (pixel coordinates stay below 2^15), so it meets no pixel box.
 constexpr uint32_t kNoBox = 0xffffffffu;
@@ -317,7 +339,11 @@ __device__ __forceinline__ void fwd_block(const ImgDesc* __restrict__ descs, int
         if (base + (uint32_t)l < G.start || base + (uint32_t)l > e1) cur.box0 = kNoBox;
         uint32_t pn = vals[min(base + (uint32_t)(kWave + l), e1)];
         for (;;) {
-            const bool hit = box_meets(cur.box0, cur.box1, live);
+            // support threshold with margin: additive q <= q_add; alpha
+            // o W' >= alpha_min needs q <= 2 ln(o / alpha_min) (W' <= G')
+            const float Qs = (MODE == WIPES_2D_ADDITIVE ? kp.q_add : 2.0f * __logf(cur.op / kp.alpha_min)) * 1.001f +
+                             1e-3f;
+            const bool hit = box_meets(cur.box0, cur.box1, live) && ellipse_meets(cur, live, Qs);
             const uint64_t m = __ballot(hit);
             if (hit)
                 stage[__popcll(m & below)] = MODE == WIPES_2D_ADDITIVE ? stage_add(cur, bx, by, base + (uint32_t)l)
