@@ -134,7 +134,7 @@ def lib():
         _lib.or_project_bwd.argtypes = [C.POINTER(_Params), C.POINTER(_Camera), C.c_int64] + [P] * 7 + [P] * 10
         _lib.or_support_counts.argtypes = [C.POINTER(_Params), C.c_int32, C.c_int32, C.c_int64, P, P, C.c_int64,
                                            P, P, P]
-        _lib.or_bin.argtypes = [C.c_int32] * 5 + [C.c_int64] + [P] * 5 + [P, P, P, P, P, P]
+        _lib.or_bin.argtypes = [C.c_int32] * 5 + [C.c_int64] + [P] * 9 + [P, P, P, P, P, P]
     return _lib
 
 
@@ -285,23 +285,25 @@ def project_bwd(params: Params, prims: dict, screen: np.ndarray, dscreen: np.nda
     return out
 
 
-def bin_tiles(W: int, H: int, tw: int, th: int, mode: int, mx, my, rx, ry, depth):
-    """O-bin (FP32 rule).  Returns dict(box [n,4], count [n], K, keys u64 [K], vals u32 [K], ranges [T,2])."""
-    mx, my, rx, ry, depth = (np.ascontiguousarray(np.asarray(a, dtype=np.float32)) for a in (mx, my, rx, ry, depth))
+def bin_tiles(W: int, H: int, tw: int, th: int, mode: int, mx, my, rx, ry, depth, ca, cb, cc, Qs):
+    """O-bin (FP32 rule: pixel box, then the tiles of its rectangle whose pixel-centre rectangle the
+    padded support ellipse q <= Qs reaches, conic (ca, cb, cc); rectangles of more than 64 tiles keep
+    every tile).  Returns dict(box [n,4], count [n], K, keys u64 [K], vals u32 [K], ranges [T,2])."""
+    mx, my, rx, ry, depth, ca, cb, cc, Qs = (np.ascontiguousarray(np.asarray(a, dtype=np.float32))
+                                             for a in (mx, my, rx, ry, depth, ca, cb, cc, Qs))
     n = mx.shape[0]
     box = np.zeros((n, 4), np.int32)
     count = np.zeros(n, np.int32)
     K = C.c_int64(0)
     L = lib()
-    L.or_bin(W, H, tw, th, mode, n, _p(mx), _p(my), _p(rx), _p(ry), _p(depth), _p(box), _p(count), C.byref(K),
-             None, None, None)
+    args = [_p(mx), _p(my), _p(rx), _p(ry), _p(depth), _p(ca), _p(cb), _p(cc), _p(Qs)]
+    L.or_bin(W, H, tw, th, mode, n, *args, _p(box), _p(count), C.byref(K), None, None, None)
     Kv = K.value
     tiles = ((W + tw - 1) // tw) * ((H + th - 1) // th)
     keys = np.zeros(max(Kv, 1), np.uint64)
     vals = np.zeros(max(Kv, 1), np.uint32)
     ranges = np.zeros((tiles, 2), np.uint32)
-    L.or_bin(W, H, tw, th, mode, n, _p(mx), _p(my), _p(rx), _p(ry), _p(depth), _p(box), _p(count), C.byref(K),
-             _p(keys), _p(vals), _p(ranges))
+    L.or_bin(W, H, tw, th, mode, n, *args, _p(box), _p(count), C.byref(K), _p(keys), _p(vals), _p(ranges))
     return dict(box=box, count=count, K=Kv, keys=keys[:Kv], vals=vals[:Kv], ranges=ranges)
 
 

@@ -1119,9 +1119,54 @@ static int cmp_bin(const void* a, const void* b)
     return x->seq < y->seq ? -1 : (x->seq > y->seq ? 1 : 0);
 }
 
+/*
+ * Ellipse part of the binning rule (a reading; Sec. 4.1 bins like 3DGS): a
+ * tile of a primitive's tile rectangle gets an instance only if the padded
+ * support ellipse q(x) <= Qs, q = ca dx^2 + 2 cb dx dy + cc dy^2, reaches the
+ * rectangle of pixel centres of (tile intersected with the pixel box).  The
+ * minimum of the convex q over that rectangle is 0 if the mean lies inside,
+ * else it lies on an edge, where it is a clamped one-dimensional minimum.
+ * FP32 in exactly this sequence (explicit fmaf, IEEE division).  Rectangles
+ * of more than 64 tiles keep every tile.
+ */
+static float or_q32(float ca, float cb, float cc, float dx, float dy)
+{
+    return fmaf(ca * dx, dx, fmaf(2.0f * cb * dx, dy, cc * dy * dy));
+}
+
+static float or_clamp32(float v, float lo, float hi) { return fminf(fmaxf(v, lo), hi); }
+
+static int or_ellipse_meets(float mx, float my, float ca, float cb, float cc, float Qs, int32_t x0, int32_t y0,
+                            int32_t x1, int32_t y1)
+{
+    const float fx0 = (float)x0 + 0.5f, fx1 = (float)x1 + 0.5f, fy0 = (float)y0 + 0.5f, fy1 = (float)y1 + 0.5f;
+    if (mx >= fx0 && mx <= fx1 && my >= fy0 && my <= fy1) return 1;
+    const float sy = -cb / cc, sx = -cb / ca;
+    const float dxa = fx0 - mx, dxb = fx1 - mx, dya = fy0 - my, dyb = fy1 - my;
+    float m = or_q32(ca, cb, cc, dxa, or_clamp32(sy * dxa, dya, dyb));
+    m = fminf(m, or_q32(ca, cb, cc, dxb, or_clamp32(sy * dxb, dya, dyb)));
+    m = fminf(m, or_q32(ca, cb, cc, or_clamp32(sx * dya, dxa, dxb), dya));
+    m = fminf(m, or_q32(ca, cb, cc, or_clamp32(sx * dyb, dxa, dxb), dyb));
+    return m <= Qs;
+}
+
+#define OR_BIN_CULL_MAX_TILES 64
+
+/* Whether tile (tx, ty) of primitive i's rectangle is kept. */
+static int or_bin_keep(const int32_t* b, int32_t tw, int32_t th, int32_t tx, int32_t ty, int32_t nt, float mx,
+                       float my, float ca, float cb, float cc, float Qs)
+{
+    if (nt > OR_BIN_CULL_MAX_TILES) return 1;
+    const int32_t x0 = tx * tw > b[0] ? tx * tw : b[0], y0 = ty * th > b[1] ? ty * th : b[1];
+    const int32_t x1 = tx * tw + tw - 1 < b[2] ? tx * tw + tw - 1 : b[2];
+    const int32_t y1 = ty * th + th - 1 < b[3] ? ty * th + th - 1 : b[3];
+    return or_ellipse_meets(mx, my, ca, cb, cc, Qs, x0, y0, x1, y1);
+}
+
 void or_bin(int32_t W, int32_t H, int32_t tw, int32_t th, int32_t mode, int64_t n, const float* mx, const float* my,
-            const float* rx, const float* ry, const float* depth, int32_t* box, int32_t* count, int64_t* K_out,
-            uint64_t* keys, uint32_t* vals, uint32_t* ranges)
+            const float* rx, const float* ry, const float* depth, const float* ca, const float* cb, const float* cc,
+            const float* Qs, int32_t* box, int32_t* count, int64_t* K_out, uint64_t* keys, uint32_t* vals,
+            uint32_t* ranges)
 {
     int32_t tiles_x = (W + tw - 1) / tw, tiles_y = (H + th - 1) / th;
     int64_t K = 0;
@@ -1140,7 +1185,12 @@ void or_bin(int32_t W, int32_t H, int32_t tw, int32_t th, int32_t mode, int64_t 
         if (!(x0 <= x1 && y0 <= y1)) continue;
         b[0] = (int32_t)x0; b[1] = (int32_t)y0; b[2] = (int32_t)x1; b[3] = (int32_t)y1;
         int32_t tx0 = b[0] / tw, tx1 = b[2] / tw, ty0 = b[1] / th, ty1 = b[3] / th;
-        count[i] = (tx1 - tx0 + 1) * (ty1 - ty0 + 1);
+        const int32_t nt = (tx1 - tx0 + 1) * (ty1 - ty0 + 1);
+        int32_t c = 0;
+        for (int32_t ty = ty0; ty <= ty1; ++ty)
+            for (int32_t tx = tx0; tx <= tx1; ++tx)
+                c += or_bin_keep(b, tw, th, tx, ty, nt, x, y, ca[i], cb[i], cc[i], Qs[i]);
+        count[i] = c;
         K += count[i];
     }
     *K_out = K;
@@ -1150,8 +1200,10 @@ void or_bin(int32_t W, int32_t H, int32_t tw, int32_t th, int32_t mode, int64_t 
     for (int64_t i = 0; i < n; ++i) {
         if (count[i] == 0) continue;
         const int32_t* b = box + 4 * i;
+        const int32_t nt = (b[2] / tw - b[0] / tw + 1) * (b[3] / th - b[1] / th + 1);
         for (int32_t ty = b[1] / th; ty <= b[3] / th; ++ty)
             for (int32_t tx = b[0] / tw; tx <= b[2] / tw; ++tx) {
+                if (!or_bin_keep(b, tw, th, tx, ty, nt, mx[i], my[i], ca[i], cb[i], cc[i], Qs[i])) continue;
                 uint64_t tile = (uint64_t)ty * (uint64_t)tiles_x + (uint64_t)tx;
                 e[k].key = mode == OR_MODE_ALPHA3D ? (tile << 32) | float_bits(depth[i]) : tile;
                 e[k].val = (uint32_t)i;

@@ -141,9 +141,9 @@ Layout layout_of(const wipes_params* p, const wipes_batch* b, int64_t cap, int w
     L.s_aux = take((size_t)n * 16);
     L.s_count = take((size_t)n * 4);
     L.s_off_id = take((size_t)n * 4);
-    L.s_pk = take((size_t)n * 16);
+    L.s_pk = take((size_t)n * sizeof(PrimPack));
     if (L.alpha) {
-        L.s_pkr = take((size_t)n * 16);
+        L.s_pkr = take((size_t)n * sizeof(PrimPack));
         L.s_cnt_r = take((size_t)n * 4);
         L.s_dkey_a = take((size_t)n * 4);
         L.s_dval_a = take((size_t)n * 4);

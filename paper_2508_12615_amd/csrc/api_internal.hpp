@@ -118,10 +118,11 @@ wipes_status render_stats_core(wipes_ctx* ctx, const wipes_params* p, const wipe
 hipError_t launch_project(const ImgDesc* descs, int B, int32_t n_total, const KParams& kp, Rec* recs, Aux* aux,
                           hipStream_t s);
 hipError_t launch_bin_count(const ImgDesc* descs, int B, int32_t n_total, const KParams& kp, Rec* recs,
-                            const void* aux, uint32_t* count, uint4* pk, uint32_t* dkey, uint32_t* dval, hipStream_t s);
-hipError_t launch_rank_pack(int32_t n_total, const uint32_t* order, const uint4* pk, const uint32_t* off_id,
-                            uint4* pkr, uint32_t* cnt_r, hipStream_t s);
-hipError_t launch_emit(const ImgDesc* descs, int B, int32_t n_total, const KParams& kp, const uint4* pkx,
+                            const void* aux, uint32_t* count, PrimPack* pk, uint32_t* dkey, uint32_t* dval,
+                            hipStream_t s);
+hipError_t launch_rank_pack(int32_t n_total, const uint32_t* order, const PrimPack* pk, const uint32_t* off_id,
+                            PrimPack* pkr, uint32_t* cnt_r, hipStream_t s);
+hipError_t launch_emit(const ImgDesc* descs, int B, int32_t n_total, const KParams& kp, const PrimPack* pkx,
                        const uint32_t* order, const uint32_t* offs, const uint32_t* n_eff, uint32_t* keys,
                        uint32_t* vals, uint32_t* eidx, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t n, uint32_t v, hipStream_t s);

@@ -21,14 +21,43 @@ namespace wipes {
 constexpr uint32_t kEmptyBox0 = 0x0000ffffu;   // x0 = 65535 > x1 = 0
 constexpr uint32_t kEmptyBox1 = 0u;
 
-// count[i] = tiles touched; writes the pixel box into the record and
-// {count, box0, box1, -} into pk[i] (read by the emission in one 16-byte
-// load).  Alpha mode also emits (depth key, index) pairs for the depth sort,
-// with culled or off-screen primitives keyed to the end.
+// Ellipse part of the binning rule: whether the padded support ellipse
+// q(x) <= Qs, q = ca dx^2 + 2 cb dx dy + cc dy^2, reaches the rectangle of
+// pixel centres [x0 + 1/2, x1 + 1/2] x [y0 + 1/2, y1 + 1/2].  The minimum of
+// the convex q over the rectangle is 0 if the mean lies inside, else it lies
+// on an edge, where it is a clamped one-dimensional minimum.  FP32 in exactly
+// this sequence (explicit fma, IEEE division).
+__device__ __forceinline__ float q32(float ca, float cb, float cc, float dx, float dy)
+{
+    return fmaf(ca * dx, dx, fmaf(2.0f * cb * dx, dy, cc * dy * dy));
+}
+
+__device__ __forceinline__ float clamp32(float v, float lo, float hi) { return fminf(fmaxf(v, lo), hi); }
+
+__device__ __forceinline__ bool ellipse_reaches(float mx, float my, float ca, float cb, float cc, float Qs, int32_t x0,
+                                                int32_t y0, int32_t x1, int32_t y1)
+{
+    const float fx0 = (float)x0 + 0.5f, fx1 = (float)x1 + 0.5f, fy0 = (float)y0 + 0.5f, fy1 = (float)y1 + 0.5f;
+    if (mx >= fx0 && mx <= fx1 && my >= fy0 && my <= fy1) return true;
+    const float sy = -cb / cc, sx = -cb / ca;
+    const float dxa = fx0 - mx, dxb = fx1 - mx, dya = fy0 - my, dyb = fy1 - my;
+    float m = q32(ca, cb, cc, dxa, clamp32(sy * dxa, dya, dyb));
+    m = fminf(m, q32(ca, cb, cc, dxb, clamp32(sy * dxb, dya, dyb)));
+    m = fminf(m, q32(ca, cb, cc, clamp32(sx * dya, dxa, dxb), dya));
+    m = fminf(m, q32(ca, cb, cc, clamp32(sx * dyb, dxa, dxb), dyb));
+    return m <= Qs;
+}
+
+constexpr int32_t kCullMaxTiles = 64;   // larger tile rectangles keep every tile
+
+// count[i] = tiles of the pixel box's tile rectangle that the support ellipse
+// reaches; writes the pixel box into the record and the PrimPack (count, box,
+// kept-tile mask) into pk[i].  Alpha mode also emits (depth key, index) pairs
+// for the depth sort, with culled or off-screen primitives keyed to the end.
 __global__ void __launch_bounds__(256) k_bin_count(const ImgDesc* __restrict__ descs, int B, int32_t n_total,
                                                     KParams kp, Rec* __restrict__ recs,
                                                     const Aux* __restrict__ aux, uint32_t* __restrict__ count,
-                                                    uint4* __restrict__ pk, uint32_t* __restrict__ dkey,
+                                                    PrimPack* __restrict__ pk, uint32_t* __restrict__ dkey,
                                                     uint32_t* __restrict__ dval)
 {
     const int32_t i = (int32_t)(blockIdx.x * 256u + threadIdx.x);
@@ -36,7 +65,8 @@ __global__ void __launch_bounds__(256) k_bin_count(const ImgDesc* __restrict__ d
     const ImgDesc& d = descs[image_of_prim(descs, B, i)];
     const Aux a = aux[i];
     const float mx = recs[i].mx, my = recs[i].my;
-    uint32_t c = 0, b0 = kEmptyBox0, b1 = kEmptyBox1;
+    uint32_t c = 0, b0 = kEmptyBox0, b1 = kEmptyBox1, full = 1;
+    uint64_t mask = 0;
     if (a.rx >= 0.0f && a.ry >= 0.0f && fabsf(mx) < 1e30f && fabsf(my) < 1e30f) {
         float x0 = ceilf((mx - a.rx) - 0.5f), x1 = floorf((mx + a.rx) - 0.5f);
         float y0 = ceilf((my - a.ry) - 0.5f), y1 = floorf((my + a.ry) - 0.5f);
@@ -48,35 +78,81 @@ __global__ void __launch_bounds__(256) k_bin_count(const ImgDesc* __restrict__ d
             const int32_t ix0 = (int32_t)x0, iy0 = (int32_t)y0, ix1 = (int32_t)x1, iy1 = (int32_t)y1;
             b0 = pack16(ix0, iy0);
             b1 = pack16(ix1, iy1);
-            c = (uint32_t)(((ix1 >> kp.log2_tw) - (ix0 >> kp.log2_tw) + 1) *
-                           ((iy1 >> kp.log2_th) - (iy0 >> kp.log2_th) + 1));
+            const int32_t tx0 = ix0 >> kp.log2_tw, ty0 = iy0 >> kp.log2_th;
+            const int32_t tx1 = ix1 >> kp.log2_tw, ty1 = iy1 >> kp.log2_th;
+            const int32_t nt = (tx1 - tx0 + 1) * (ty1 - ty0 + 1);
+            if (nt > kCullMaxTiles) {
+                c = (uint32_t)nt;
+            } else {
+                full = 0;
+                const float ca = recs[i].ca, cb = recs[i].cb, cc = recs[i].cc;
+                int k = 0;
+                for (int32_t ty = ty0; ty <= ty1; ++ty)
+                    for (int32_t tx = tx0; tx <= tx1; ++tx, ++k) {
+                        const int32_t rx0 = max(tx * kp.tile_w, ix0), ry0 = max(ty * kp.tile_h, iy0);
+                        const int32_t rx1 = min(tx * kp.tile_w + kp.tile_w - 1, ix1);
+                        const int32_t ry1 = min(ty * kp.tile_h + kp.tile_h - 1, iy1);
+                        if (ellipse_reaches(mx, my, ca, cb, cc, a.Qs, rx0, ry0, rx1, ry1)) mask |= 1ull << k;
+                    }
+                c = (uint32_t)__popcll(mask);
+            }
         }
     }
     recs[i].box0 = b0;
     recs[i].box1 = b1;
     count[i] = c;
-    pk[i] = make_uint4(c, b0, b1, 0u);
+    PrimPack q;
+    q.count = c;
+    q.box0 = b0;
+    q.box1 = b1;
+    q.base = 0;
+    q.mlo = (uint32_t)mask;
+    q.mhi = (uint32_t)(mask >> 32);
+    q.full = full;
+    q.pad = 0;
+    pk[i] = q;
     if (dkey) {
         dkey[i] = c ? __float_as_uint(a.depth) : 0xffffffffu;
         dval[i] = (uint32_t)i;
     }
 }
 
-// Depth-rank order of the packed per-primitive data: pkr[r] = {count, box0,
-// box1, slot base off_id} of primitive order[r], cnt_r[r] its count.  One
+// Position of the k-th (0-based) set bit of m (k < popcount(m)).
+__device__ __forceinline__ uint32_t nth_set_bit(uint64_t m, uint32_t k)
+{
+    uint32_t pos = 0, v = (uint32_t)m, c = (uint32_t)__popc(v);
+    if (k >= c) {
+        k -= c;
+        pos = 32;
+        v = (uint32_t)(m >> 32);
+    }
+#pragma unroll
+    for (int w = 16; w >= 1; w >>= 1) {
+        c = (uint32_t)__popc(v & ((1u << w) - 1u));
+        if (k >= c) {
+            k -= c;
+            pos += (uint32_t)w;
+            v >>= w;
+        }
+    }
+    return pos;
+}
+
+// Depth-rank order of the packed per-primitive data: pkr[r] = the PrimPack
+// of primitive order[r] with its slot base off_id, cnt_r[r] its count.  One
 // gather here lets the rank scan and the emission read coalesced.
 __global__ void __launch_bounds__(256) k_rank_pack(int32_t n_total, const uint32_t* __restrict__ order,
-                                                    const uint4* __restrict__ pk,
-                                                    const uint32_t* __restrict__ off_id, uint4* __restrict__ pkr,
-                                                    uint32_t* __restrict__ cnt_r)
+                                                    const PrimPack* __restrict__ pk,
+                                                    const uint32_t* __restrict__ off_id,
+                                                    PrimPack* __restrict__ pkr, uint32_t* __restrict__ cnt_r)
 {
     const int32_t r = (int32_t)(blockIdx.x * 256u + threadIdx.x);
     if (r >= n_total) return;
     const uint32_t prim = order[r];
-    uint4 q = pk[prim];
-    q.w = off_id[prim];
+    PrimPack q = pk[prim];
+    q.base = off_id[prim];
     pkr[r] = q;
-    cnt_r[r] = q.x;
+    cnt_r[r] = q.count;
 }
 
 // Writes the instances of the primitive of rank r at offs[r]..: key = global
@@ -93,32 +169,35 @@ __global__ void __launch_bounds__(256) k_rank_pack(int32_t n_total, const uint32
 // primitive by a binary search over the 64 start offsets in LDS, so every
 // store is coalesced however uneven the per-primitive counts are.
 __global__ void __launch_bounds__(256) k_emit(const ImgDesc* __restrict__ descs, int B, int32_t n_total,
-                                               KParams kp, const uint4* __restrict__ pkx,
+                                               KParams kp, const PrimPack* __restrict__ pkx,
                                                const uint32_t* __restrict__ order,
                                                const uint32_t* __restrict__ offs,
                                                const uint32_t* __restrict__ n_eff, uint32_t* __restrict__ keys,
                                                uint32_t* __restrict__ vals, uint32_t* __restrict__ eidx)
 {
     __shared__ uint32_t s_start[4][kWave], s_prim[4][kWave], s_base[4][kWave], s_tx[4][kWave], s_w[4][kWave],
-        s_e0[4][kWave];
+        s_e0[4][kWave], s_mlo[4][kWave], s_mhi[4][kWave], s_full[4][kWave];
     const int w = (int)(threadIdx.x >> 6), l = lane_id();
     const int32_t r0 = (int32_t)(blockIdx.x * 256u + (uint32_t)w * kWave);   // rank of lane 0
     if (r0 >= n_total || *n_eff == 0u) return;   // wave-uniform
     const int32_t r = r0 + l;
-    uint32_t c = 0, prim = 0, base = 0, tilesx = 1, wd = 1, e0 = 0, off = 0xffffffffu;
+    uint32_t c = 0, prim = 0, base = 0, tilesx = 1, wd = 1, e0 = 0, off = 0xffffffffu, mlo = 0, mhi = 0, full = 1;
     if (r < n_total) {
-        const uint4 q = pkx[r];
+        const PrimPack q = pkx[r];
         prim = order ? order[r] : (uint32_t)r;
-        c = q.x;
+        c = q.count;
         off = offs[r];
         if (c) {
             const ImgDesc& d = descs[image_of_prim(descs, B, (int32_t)prim)];
-            const int32_t tx0 = lo16(q.y) >> kp.log2_tw, ty0 = hi16(q.y) >> kp.log2_th;
-            const int32_t tx1 = lo16(q.z) >> kp.log2_tw;
+            const int32_t tx0 = lo16(q.box0) >> kp.log2_tw, ty0 = hi16(q.box0) >> kp.log2_th;
+            const int32_t tx1 = lo16(q.box1) >> kp.log2_tw;
             wd = (uint32_t)(tx1 - tx0 + 1);
             tilesx = (uint32_t)d.tiles_x;
             base = (uint32_t)(d.tile_begin + ty0 * d.tiles_x + tx0);
-            e0 = order ? q.w : off;
+            e0 = order ? q.base : off;
+            mlo = q.mlo;
+            mhi = q.mhi;
+            full = q.full;
         }
     }
     const uint32_t first = (uint32_t)__builtin_amdgcn_readfirstlane((int)off);   // lane 0 is in range
@@ -130,6 +209,9 @@ __global__ void __launch_bounds__(256) k_emit(const ImgDesc* __restrict__ descs,
     s_tx[w][l] = tilesx;
     s_w[w][l] = wd;
     s_e0[w][l] = e0;
+    s_mlo[w][l] = mlo;
+    s_mhi[w][l] = mhi;
+    s_full[w][l] = full;
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -144,10 +226,13 @@ __global__ void __launch_bounds__(256) k_emit(const ImgDesc* __restrict__ descs,
             if (s_start[w][j + step] <= k) j += step;
         const uint32_t local = k - s_start[w][j];
         const uint32_t wj = s_w[w][j];
-        uint32_t dy = (uint32_t)((float)local / (float)wj);   // corrected to the exact quotient below
-        if (dy * wj > local) --dy;
-        else if ((dy + 1u) * wj <= local) ++dy;
-        const uint32_t dx = local - dy * wj;
+        // position in the tile rectangle: the local-th kept tile
+        const uint32_t at = s_full[w][j] ? local
+                                         : nth_set_bit(((uint64_t)s_mhi[w][j] << 32) | s_mlo[w][j], local);
+        uint32_t dy = (uint32_t)((float)at / (float)wj);   // corrected to the exact quotient below
+        if (dy * wj > at) --dy;
+        else if ((dy + 1u) * wj <= at) ++dy;
+        const uint32_t dx = at - dy * wj;
         const uint32_t o = first + k;
         keys[o] = s_base[w][j] + dy * s_tx[w][j] + dx;
         vals[o] = s_prim[w][j];
@@ -194,7 +279,8 @@ __global__ void __launch_bounds__(256) k_fill_u32(uint32_t* __restrict__ p, uint
 static inline uint32_t blocks_of(uint32_t n) { return (n + 255u) / 256u; }
 
 hipError_t launch_bin_count(const ImgDesc* descs, int B, int32_t n_total, const KParams& kp, Rec* recs,
-                            const void* aux, uint32_t* count, uint4* pk, uint32_t* dkey, uint32_t* dval, hipStream_t s)
+                            const void* aux, uint32_t* count, PrimPack* pk, uint32_t* dkey, uint32_t* dval,
+                            hipStream_t s)
 {
     if (n_total > 0)
         hipLaunchKernelGGL(k_bin_count, dim3(blocks_of((uint32_t)n_total)), dim3(256), 0, s, descs, B, n_total, kp,
@@ -202,8 +288,8 @@ hipError_t launch_bin_count(const ImgDesc* descs, int B, int32_t n_total, const 
     return hipGetLastError();
 }
 
-hipError_t launch_rank_pack(int32_t n_total, const uint32_t* order, const uint4* pk, const uint32_t* off_id,
-                            uint4* pkr, uint32_t* cnt_r, hipStream_t s)
+hipError_t launch_rank_pack(int32_t n_total, const uint32_t* order, const PrimPack* pk, const uint32_t* off_id,
+                            PrimPack* pkr, uint32_t* cnt_r, hipStream_t s)
 {
     if (n_total > 0)
         hipLaunchKernelGGL(k_rank_pack, dim3(blocks_of((uint32_t)n_total)), dim3(256), 0, s, n_total, order, pk,
@@ -211,7 +297,7 @@ hipError_t launch_rank_pack(int32_t n_total, const uint32_t* order, const uint4*
     return hipGetLastError();
 }
 
-hipError_t launch_emit(const ImgDesc* descs, int B, int32_t n_total, const KParams& kp, const uint4* pkx,
+hipError_t launch_emit(const ImgDesc* descs, int B, int32_t n_total, const KParams& kp, const PrimPack* pkx,
                        const uint32_t* order, const uint32_t* offs, const uint32_t* n_eff, uint32_t* keys,
                        uint32_t* vals, uint32_t* eidx, hipStream_t s)
 {

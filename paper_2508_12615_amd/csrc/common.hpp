@@ -39,7 +39,16 @@ static_assert(sizeof(Rec) == 64, "screen record must be 64 bytes");
 struct Aux {
     float rx, ry;   // padded support half-extents (pixels); rx < 0 marks a culled primitive
     float depth;    // FP32 depth key (alpha mode)
-    float pad;
+    float Qs;       // padded support threshold: the ellipse q <= Qs holds every pixel the blend accepts
+};
+
+// Per-primitive binning result, read by the emission in two 16-byte loads:
+// instance count, pixel box, slot base (filled in depth order), and the
+// kept tiles of the box's tile rectangle (bit k = k-th tile row-major) when
+// the rectangle has at most 64 tiles (full = 1: every tile kept).
+struct __align__(16) PrimPack {
+    uint32_t count, box0, box1, base;
+    uint32_t mlo, mhi, full, pad;
 };
 
 // Per-image descriptor, uploaded once per call into the screen buffer.

@@ -19,7 +19,7 @@ struct Views {
     Aux* aux;
     uint32_t *count, *off_id, *dkey_a, *dval_a, *dkey_b, *dval_b, *off_rank, *dhist, *ddtot, *bsum, *bsum2, *ctrl;
     ImgDesc* descs;
-    uint4 *pk, *pkr;
+    PrimPack *pk, *pkr;
     uint32_t* cnt_r;
     uint32_t *keys_a, *vals_a, *keys_b, *vals_b, *hist, *dtot, *order, *tbsum, *w_a, *w_b;
     uint2* ranges;
@@ -37,14 +37,14 @@ static Views views(const Layout& L, const void* screen, const void* bins)
     v.aux = (Aux*)(s + L.s_aux);
     v.count = (uint32_t*)(s + L.s_count);
     v.off_id = (uint32_t*)(s + L.s_off_id);
-    v.pk = (uint4*)(s + L.s_pk);
+    v.pk = (PrimPack*)(s + L.s_pk);
     if (L.alpha) {
         v.dkey_a = (uint32_t*)(s + L.s_dkey_a);
         v.dval_a = (uint32_t*)(s + L.s_dval_a);
         v.dkey_b = (uint32_t*)(s + L.s_dkey_b);
         v.dval_b = (uint32_t*)(s + L.s_dval_b);
         v.off_rank = (uint32_t*)(s + L.s_off_rank);
-        v.pkr = (uint4*)(s + L.s_pkr);
+        v.pkr = (PrimPack*)(s + L.s_pkr);
         v.cnt_r = (uint32_t*)(s + L.s_cnt_r);
         v.dhist = (uint32_t*)(s + L.s_dhist);
         v.ddtot = (uint32_t*)(s + L.s_ddtot);

@@ -48,6 +48,10 @@ __device__ __forceinline__ void support_box(double sxx, double syy, double Q, fl
     *ry = (float)(sqrt(Q * syy) * 1.0001 + 1e-3);
 }
 
+// The same support, as a threshold on q for the binning's ellipse test, with
+// the same kind of margin (0.1 % + 1e-3).
+__device__ __forceinline__ float support_threshold(double Q) { return (float)(Q * 1.001 + 1e-3); }
+
 __global__ void __launch_bounds__(256) k_project_2d(const ImgDesc* __restrict__ descs, int B, int32_t n_total,
                                                      KParams kp, Rec* __restrict__ recs, Aux* __restrict__ aux)
 {
@@ -83,7 +87,7 @@ __global__ void __launch_bounds__(256) k_project_2d(const ImgDesc* __restrict__ 
                  d.color[3 * j + 1], d.color[3 * j + 2]);
     float rx, ry;
     support_box(sxx, syy, kp.q_add, &rx, &ry);
-    aux[i] = Aux{rx, ry, 0.0f, 0.0f};
+    aux[i] = Aux{rx, ry, 0.0f, support_threshold(kp.q_add)};
 }
 
 // FP32 depth key: z = fma(V20, m_x, fma(V21, m_y, fma(V22, m_z, V23))), m = fma(v, tau, mu).
@@ -163,8 +167,9 @@ __global__ void __launch_bounds__(256) k_project_3d(const ImgDesc* __restrict__ 
     store_record(recs, i, mx, my, syy * inv, -sxy * inv, sxx * inv, fx, fy, op, d.color[3 * j],
                  d.color[3 * j + 1], d.color[3 * j + 2]);
     float rx, ry;
-    support_box(sxx, syy, 2.0 * log((double)op / (double)kp.alpha_min), &rx, &ry);
-    aux[i] = Aux{rx, ry, zkey, 0.0f};
+    const double Q = 2.0 * log((double)op / (double)kp.alpha_min);
+    support_box(sxx, syy, Q, &rx, &ry);
+    aux[i] = Aux{rx, ry, zkey, support_threshold(Q)};
 }
 
 }  // namespace wipes

@@ -244,7 +244,8 @@ def screen_records(n: int, width: int, height: int, seed: int, dup_depth_frac: f
     Means U(-40, W+40) x U(-40, H+40); half-extents logU(0.05, 80) px, with
     2% marked culled (-1); depths U(0.5, 5) with a fraction copied from other
     records so that equal keys occur; some means placed exactly on tile and
-    pixel-centre boundaries.
+    pixel-centre boundaries; then a conic (ca, cb, cc) and padded support
+    threshold Qs whose support ellipse has exactly those half-extents.
     """
     g = rng(seed)
     mx = g.uniform(-40.0, width + 40.0, n)
@@ -260,5 +261,14 @@ def screen_records(n: int, width: int, height: int, seed: int, dup_depth_frac: f
     mx[snap] = np.round(mx[snap] / 8.0) * 8.0 + 0.5 * g.integers(0, 2, int(snap.sum()))
     my[snap] = np.round(my[snap] / 8.0) * 8.0
     rx[snap & ~cull] = np.round(rx[snap & ~cull]) + 0.5
+    # conic and padded support threshold consistent with the box: Q ~ U(8, 12),
+    # correlation ~ U(-0.95, 0.95), variances rx^2 / Q and ry^2 / Q
+    rho = g.uniform(-0.95, 0.95, n)
+    Q = g.uniform(8.0, 12.0, n)
+    sxx, syy = np.abs(rx) ** 2 / Q, np.abs(ry) ** 2 / Q
+    sxy = rho * np.sqrt(sxx * syy)
+    det = sxx * syy - sxy * sxy
     return dict(mx=mx.astype(np.float32), my=my.astype(np.float32), rx=rx.astype(np.float32),
-                ry=ry.astype(np.float32), depth=depth.astype(np.float32))
+                ry=ry.astype(np.float32), depth=depth.astype(np.float32), ca=(syy / det).astype(np.float32),
+                cb=(-sxy / det).astype(np.float32), cc=(sxx / det).astype(np.float32),
+                Qs=(Q * 1.001 + 1e-3).astype(np.float32))

@@ -110,13 +110,15 @@ def test_bin_sort_bit_exact(mode, tw, th, n, seed):
     if n:
         recs = np.zeros((n, 16), np.float32)
         recs[:, 0], recs[:, 1] = rec["mx"], rec["my"]
+        recs[:, 2], recs[:, 3], recs[:, 4] = rec["ca"], rec["cb"], rec["cc"]
         aux = np.zeros((n, 4), np.float32)
-        aux[:, 0], aux[:, 1], aux[:, 2] = rec["rx"], rec["ry"], rec["depth"]
+        aux[:, 0], aux[:, 1], aux[:, 2], aux[:, 3] = rec["rx"], rec["ry"], rec["depth"], rec["Qs"]
         off = (n * 64 + 255) // 256 * 256
         screen[: n * 64] = torch.from_numpy(recs.view(np.uint8).reshape(-1)).to(dev)
         screen[off: off + n * 16] = torch.from_numpy(aux.view(np.uint8).reshape(-1)).to(dev)
     omode = O.MODE_ALPHA3D if mode == B.WIPES_3D_ALPHA else O.MODE_ADD2D
-    ob = O.bin_tiles(W, H, tw, th, omode, rec["mx"], rec["my"], rec["rx"], rec["ry"], rec["depth"])
+    ob = O.bin_tiles(W, H, tw, th, omode, rec["mx"], rec["my"], rec["rx"], rec["ry"], rec["depth"], rec["ca"],
+                     rec["cb"], rec["cc"], rec["Qs"])
     cap = ob["K"] + 17
     _, bb = B.wipes_workspace_size(p, batch, cap, True)
     bins = torch.zeros(bb, dtype=torch.uint8, device=dev)

@@ -35,6 +35,11 @@ MUTATIONS = {
     "binning_rounding": ("float x0 = ceilf((x - ex) - 0.5f), x1 = floorf((x + ex) - 0.5f);",
                          "float x0 = floorf((x - ex) - 0.5f), x1 = floorf((x + ex) - 0.5f);",
                          "test_binning_brute_force"),
+    "binning_cross_term_sign": ("return fmaf(ca * dx, dx, fmaf(2.0f * cb * dx, dy, cc * dy * dy));",
+                                "return fmaf(ca * dx, dx, fmaf(-2.0f * cb * dx, dy, cc * dy * dy));",
+                                "test_binning_brute_force"),
+    "binning_edge_slope": ("const float sy = -cb / cc, sx = -cb / ca;", "const float sy = -cb / ca, sx = -cb / cc;",
+                           "test_binning_brute_force"),
 }
 
 

@@ -463,15 +463,26 @@ def test_fd_gradients_alpha_guard_band():
 
 @pytest.mark.parametrize("mode,tw,th", [(O.MODE_ALPHA3D, 16, 16), (O.MODE_ADD2D, 8, 8), (O.MODE_ALPHA3D, 32, 16)])
 def test_binning_brute_force(mode, tw, th):
+    """O-bin against brute force.  The pixel box: pixels whose centre lies within the FP32 half-extents
+    (enumerated).  The tiles kept: a tile of a rectangle of at most 64 tiles is kept iff the support
+    ellipse q <= Qs reaches its pixel-centre rectangle -- checked against the rectangle minimum of q
+    found by scipy's bounded L-BFGS-B in FP64 (decisions within 1e-3 of Qs are ties and accept either
+    outcome), and against pixel-centre enumeration (no tile holding a centre with q <= Qs is dropped).
+    Keys, values and ranges: numpy's stable argsort of the kept instances."""
+    from scipy.optimize import minimize
     from paper_2508_12615_amd import synth
     W, H = 150, 93
-    r = synth.screen_records(400, W, H, seed=77)
-    out = O.bin_tiles(W, H, tw, th, mode, r["mx"], r["my"], r["rx"], r["ry"], r["depth"])
+    n = 250
+    r = synth.screen_records(n, W, H, seed=77)
+    out = O.bin_tiles(W, H, tw, th, mode, r["mx"], r["my"], r["rx"], r["ry"], r["depth"], r["ca"], r["cb"], r["cc"],
+                      r["Qs"])
     tiles_x = -(-W // tw)
-    keys, vals = [], []
-    for i in range(400):
+    keys, vals, decided, dropped = [], [], 0, 0
+    kept_ref = {}
+    for i in range(n):
         mx, my, rx, ry = (np.float32(r[k][i]) for k in ("mx", "my", "rx", "ry"))
-        cover = set()
+        ca, cb, cc, Qs = (float(r[k][i]) for k in ("ca", "cb", "cc", "Qs"))
+        rect = set()
         if rx >= 0 and ry >= 0:
             lox, hix = (mx - rx) - np.float32(0.5), (mx + rx) - np.float32(0.5)
             loy, hiy = (my - ry) - np.float32(0.5), (my + ry) - np.float32(0.5)
@@ -479,11 +490,49 @@ def test_binning_brute_force(mode, tw, th):
             ys = [y for y in range(H) if loy <= y <= hiy]
             for y in ys:
                 for x in xs:
-                    cover.add((y // th) * tiles_x + x // tw)
+                    rect.add((y // th, x // tw))
             if xs and ys:
                 assert tuple(out["box"][i]) == (xs[0], ys[0], xs[-1], ys[-1])
-        assert out["count"][i] == len(cover)
-        for t in sorted(cover):
+        q = lambda p: ca * (p[0] - float(mx)) ** 2 + 2 * cb * (p[0] - float(mx)) * (p[1] - float(my)) + \
+            cc * (p[1] - float(my)) ** 2  # noqa: E731
+        mine = set()
+        for (ty, tx) in sorted(rect):
+            b = out["box"][i]
+            x0, x1 = max(tx * tw, b[0]) + 0.5, min(tx * tw + tw - 1, b[2]) + 0.5
+            y0, y1 = max(ty * th, b[1]) + 0.5, min(ty * th + th - 1, b[3]) + 0.5
+            if len(rect) > 64:
+                mine.add((ty, tx))
+                continue
+            res = minimize(q, [(x0 + x1) / 2, (y0 + y1) / 2], method="L-BFGS-B", bounds=[(x0, x1), (y0, y1)],
+                           options=dict(ftol=1e-15, gtol=1e-12))
+            centres = [q((x + 0.5, y + 0.5)) for x in range(int(x0), int(x1) + 1) for y in range(int(y0), int(y1) + 1)]
+            if min(centres) <= Qs * (1 - 1e-6):
+                mine.add((ty, tx))                 # holds a supported pixel centre: must be kept
+            elif res.fun > Qs * (1 + 1e-3):
+                dropped += 1                       # ellipse misses the rectangle: must be dropped
+            elif res.fun < Qs * (1 - 1e-3):
+                mine.add((ty, tx))                 # ellipse reaches the rectangle: kept
+            else:
+                mine.add(None)                     # tie: either outcome
+                continue
+            decided += 1
+        kept_ref[i] = mine
+    # the oracle's instances per primitive, from its sorted output
+    got = {}
+    tile_of = out["keys"] >> np.uint64(32) if mode == O.MODE_ALPHA3D else out["keys"]
+    for t, v in zip(tile_of.astype(np.int64), out["vals"]):
+        got.setdefault(int(v), set()).add((int(t) // tiles_x, int(t) % tiles_x))
+    for i in range(n):
+        ref = kept_ref[i]
+        have = got.get(i, set())
+        assert out["count"][i] == len(have)
+        assert {x for x in ref if x is not None} <= have, i
+        if None not in ref:
+            assert have == ref, i
+    assert decided > 200 and dropped > 20, (decided, dropped)
+    for i in sorted(got):
+        for (ty, tx) in sorted(got[i]):
+            t = ty * tiles_x + tx
             d = int(np.float32(r["depth"][i]).view(np.uint32))
             keys.append((t << 32) | d if mode == O.MODE_ALPHA3D else t)
             vals.append(i)
@@ -491,7 +540,6 @@ def test_binning_brute_force(mode, tw, th):
     order = np.argsort(keys, kind="stable")
     assert out["K"] == len(keys)
     assert np.array_equal(out["keys"], keys[order]) and np.array_equal(out["vals"], vals[order])
-    tile_of = out["keys"] >> np.uint64(32) if mode == O.MODE_ALPHA3D else out["keys"]
     for t in range(out["ranges"].shape[0]):
         lo = np.searchsorted(tile_of, t, "left"); hi = np.searchsorted(tile_of, t, "right")
         exp = (lo, hi) if hi > lo else (0, 0)
