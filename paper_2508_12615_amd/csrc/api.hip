@@ -150,8 +150,8 @@ Layout layout_of(const wipes_params* p, const wipes_batch* b, int64_t cap, int w
         L.s_dkey_b = take((size_t)n * 4);
         L.s_dval_b = take((size_t)n * 4);
         L.s_off_rank = take((size_t)n * 4);
-        L.s_dhist = take((size_t)256 * nb_n * 4);
-        L.s_ddtot = take(256 * 4);
+        L.s_dhist = take(((size_t)1 << radix_digit_bits(32)) * nb_n * 4);
+        L.s_ddtot = take(((size_t)1 << radix_digit_bits(32)) * 4);
     }
     L.s_bsum = take((size_t)(nb_n + 1) * 4);
     L.s_bsum2 = take((size_t)(nb_n + 1) * 4);
@@ -161,13 +161,22 @@ Layout layout_of(const wipes_params* p, const wipes_batch* b, int64_t cap, int w
 
     const int64_t nb_k = (cap + 4095) / 4096 + 1;
     const int64_t nb_t = (L.tiles + 4095) / 4096 + 1;
+    // tile sort bits and where its result lands
+    int bits = 0;
+    while (bits < 32 && (1ll << bits) < L.tiles) ++bits;
+    L.tile_bits = std::max(bits, 1);
+    L.tile_result_b = radix_passes(L.tile_bits) & 1;
+    L.depth_result_b = radix_passes(32) & 1;
+    L.order_result_b = radix_passes(8) & 1;
+    // digit histograms of the tile sort and of the 8-bit longest-first sort
+    const size_t nd_bins = (size_t)1 << std::max(radix_digit_bits(L.tile_bits), 8);
     o = 0;
     L.b_keys_a = take((size_t)cap * 4);
     L.b_vals_a = take((size_t)cap * 4);
     L.b_keys_b = take((size_t)cap * 4);
     L.b_vals_b = take((size_t)cap * 4);
-    L.b_hist = take((size_t)256 * std::max(nb_k, nb_t) * 4);
-    L.b_dtot = take(256 * 4);
+    L.b_hist = take(nd_bins * std::max(nb_k, nb_t) * 4);
+    L.b_dtot = take(nd_bins * 4);
     L.b_ranges = take((size_t)L.tiles * 8);
     L.b_order = take((size_t)L.tiles * 4 * 4);   // LPT order + sort scratch (4 arrays)
     L.b_tbsum = take((size_t)(nb_t + 1) * 4);
@@ -182,13 +191,6 @@ Layout layout_of(const wipes_params* p, const wipes_batch* b, int64_t cap, int w
     }
     L.bins_bytes = o;
     L.with_bwd = with_bwd;
-    // tile sort bits and where its result lands
-    int bits = 0;
-    while (bits < 32 && (1ll << bits) < L.tiles) ++bits;
-    L.tile_bits = std::max(bits, 1);
-    L.tile_result_b = radix_passes(L.tile_bits) & 1;
-    L.depth_result_b = radix_passes(32) & 1;
-    L.order_result_b = radix_passes(8) & 1;
     return L;
 }
 
@@ -339,6 +341,12 @@ wipes_status wipes_ctx_create(int32_t device, wipes_ctx** out)
         return hip_fail(nullptr, e, "hipGetDeviceProperties");
     }
     c->n_cu = prop.multiProcessorCount;
+    e = hipHostMalloc((void**)&c->k_host, 256, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->k_ev, hipEventDisableTiming);
+    if (e != hipSuccess) {
+        wipes_ctx_destroy(c);
+        return hip_fail(nullptr, e, "instance-count readback allocation");
+    }
     for (int i = 0; i < kRing; ++i) {
         e = hipHostMalloc(&c->ring[i].host, kStagingBytes, hipHostMallocDefault);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ring[i].ev, hipEventDisableTiming);
@@ -368,6 +376,11 @@ void wipes_ctx_destroy(wipes_ctx* ctx)
         }
         if (ctx->ring[i].host) hipHostFree(ctx->ring[i].host);
     }
+    if (ctx->k_ev) {
+        (void)hipEventSynchronize(ctx->k_ev);
+        (void)hipEventDestroy(ctx->k_ev);
+    }
+    if (ctx->k_host) hipHostFree(ctx->k_host);
     delete ctx;
 }
 

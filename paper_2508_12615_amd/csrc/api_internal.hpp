@@ -53,6 +53,8 @@ struct wipes_ctx {
     StagingSlot ring[kRing];
     int ring_next = 0;
     bool capturing = false;      // descriptor uploads are skipped while capturing a graph
+    uint32_t* k_host = nullptr;  // pinned word: instance count read back by bin_sort
+    hipEvent_t k_ev = nullptr;   // recorded after that copy
     Profiler prof;
 };
 
@@ -133,6 +135,7 @@ hipError_t scan_excl(const uint32_t* vals, const uint32_t* gather, uint32_t n_ho
                      uint32_t max_n, uint32_t* block_sums, uint32_t* out, uint32_t* total, uint32_t cap,
                      uint32_t* n_eff, uint32_t* overflow, hipStream_t s);
 int radix_passes(int nbits);
+int radix_digit_bits(int nbits);   // digit width of each pass of radix_sort
 // Stable LSD sort of (key, value[, w]) over the low nbits of the keys; ping-pongs
 // between the *0 and *1 arrays, *result_in_1 tells where the result is.
 hipError_t radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, uint32_t n_host,

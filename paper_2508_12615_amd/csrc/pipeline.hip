@@ -107,6 +107,12 @@ wipes_status bin_sort_core(wipes_ctx* ctx, const wipes_params* p, const wipes_ba
                           v.ctrl + kCtrlNEff, v.ctrl + kCtrlOverflow, s),
                 "scan");
     }
+    if (n_instances_out) {
+        // start the read-back of K now and wait for it only before the
+        // emission, so the host round trip overlaps the depth sort
+        HIP_TRY(hipMemcpyAsync(ctx->k_host, v.ctrl + kCtrlK, 4, hipMemcpyDeviceToHost, s), "read K");
+        HIP_TRY(hipEventRecord(ctx->k_ev, s), "read K event");
+    }
     const uint32_t* order = nullptr;
     const uint32_t* offs = v.off_id;
     if (L.alpha) {
@@ -128,9 +134,8 @@ wipes_status bin_sort_core(wipes_ctx* ctx, const wipes_params* p, const wipes_ba
     }
     uint32_t max_k = (uint32_t)L.cap;
     if (n_instances_out) {
-        uint32_t K = 0;
-        HIP_TRY(hipMemcpyAsync(&K, v.ctrl + kCtrlK, 4, hipMemcpyDeviceToHost, s), "read K");
-        HIP_TRY(hipStreamSynchronize(s), "sync K");
+        HIP_TRY(hipEventSynchronize(ctx->k_ev), "sync K");
+        const uint32_t K = *ctx->k_host;
         *n_instances_out = K;
         if ((int64_t)K > L.cap) return fail(ctx, WIPES_ERR_CAPACITY, "%u instances exceed capacity %lld", K, (long long)L.cap);
         max_k = K;
@@ -181,12 +186,12 @@ wipes_status render_fwd_core(wipes_ctx* ctx, const wipes_params* p, const wipes_
         HIP_TRY(launch_fill_u32(queue, kQueueLanes * kQueueStride, 0u, s), "queue reset");
         pblocks = (uint32_t)ctx->n_cu * 8u;
     }
-    StageScope sc(ctx, kStBlendFwd, s);
     if (v.cmask) {
         // the forward records which primitives contribute to each block, for the backward
         const size_t words = (size_t)(p->tile_w / 8) * (p->tile_h / 8) * L.cmask_words;
         HIP_TRY(launch_fill_u32((uint32_t*)v.cmask, (uint32_t)(2 * words), 0u, s), "mask clear");
     }
+    StageScope sc(ctx, kStBlendFwd, s);
     HIP_TRY(launch_blend_fwd(v.descs, L.B, kp, v.recs, svals, v.ranges, v.ctrl + kCtrlOverflow, (uint32_t)L.tiles,
                              order, queue, pblocks, image, T_final, last, v.cmask, L.cmask_words, s),
             "blend fwd");
@@ -209,10 +214,10 @@ wipes_status render_bwd_core(wipes_ctx* ctx, const wipes_params* p, const wipes_
         HIP_TRY(launch_fill_u32(queue, kQueueLanes * kQueueStride, 0u, s), "queue reset");
         pblocks = (uint32_t)ctx->n_cu * 8u;
     }
+    HIP_TRY(launch_fill_u32(v.svalid, (uint32_t)(L.cap / 32 + 2), 0u, s), "slot marks clear");
     {
         StageScope sc(ctx, kStBlendBwd, s);
         const uint32_t* seidx = L.tile_result_b ? v.w_b : v.w_a;
-        HIP_TRY(launch_fill_u32(v.svalid, (uint32_t)(L.cap / 32 + 2), 0u, s), "slot marks clear");
         HIP_TRY(launch_blend_bwd(v.descs, L.B, kp, v.recs, svals, seidx, v.ranges, v.ctrl + kCtrlOverflow,
                                  (uint32_t)L.tiles, order, queue, pblocks, T_final, last, dLdC, v.slots, v.svalid,
                                  v.cmask, L.cmask_words, s),

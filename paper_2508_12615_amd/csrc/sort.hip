@@ -197,6 +197,7 @@ __global__ void __launch_bounds__(kBlock) k_radix_scatter(const uint32_t* __rest
     __shared__ uint32_t s_wcnt[NW][ND];
     __shared__ uint32_t s_dbase[ND];
     __shared__ uint32_t s_gbase[ND];
+    __shared__ uint32_t s_part[2][NW];
 
     const uint32_t n = load_n(n_host, n_dev);
     const uint32_t base = blockIdx.x * kTile;
@@ -245,22 +246,41 @@ __global__ void __launch_bounds__(kBlock) k_radix_scatter(const uint32_t* __rest
         s_dbase[d] = run;   // tile total of digit d (scanned below)
     }
     __syncthreads();
-    if (threadIdx.x < kWave) {
-        // exclusive scan of the ND tile totals and of the ND global digit totals, 64 at a time
-        uint32_t carry_t = 0, carry_g = 0;
-        for (int c = 0; c < ND; c += kWave) {
-            const int d = c + l;
-            const uint32_t tt = d < ND ? s_dbase[d] : 0u;
-            const uint32_t gt = d < ND ? dtot[d] : 0u;
-            uint32_t wt, wg;
-            const uint32_t et = wave_excl_scan_u32(tt, &wt);
-            const uint32_t eg = wave_excl_scan_u32(gt, &wg);
+    {
+        // exclusive scans of the ND tile totals and of the ND global digit
+        // totals over the whole workgroup: thread t owns DPT consecutive
+        // digits (all loads issued up front), waves combine through LDS
+        constexpr int DPT = (ND + kBlock - 1) / kBlock;
+        const int d0 = threadIdx.x * DPT;
+        uint32_t tt[DPT], gt[DPT], hb[DPT], st = 0, sg = 0;
+        for (int i = 0; i < DPT; ++i) {
+            const int d = d0 + i;
+            tt[i] = d < ND ? s_dbase[d] : 0u;
+            gt[i] = d < ND ? dtot[d] : 0u;
+            hb[i] = d < ND ? hist[(uint32_t)d * nblocks + blockIdx.x] : 0u;
+            st += tt[i];
+            sg += gt[i];
+        }
+        uint32_t wt, wg;
+        uint32_t ot = wave_excl_scan_u32(st, &wt);
+        uint32_t og = wave_excl_scan_u32(sg, &wg);
+        if (l == 0) {
+            s_part[0][w] = wt;
+            s_part[1][w] = wg;
+        }
+        __syncthreads();
+        for (int x = 0; x < w; ++x) {
+            ot += s_part[0][x];
+            og += s_part[1][x];
+        }
+        for (int i = 0; i < DPT; ++i) {
+            const int d = d0 + i;
             if (d < ND) {
-                s_dbase[d] = carry_t + et;
-                s_gbase[d] = carry_g + eg + hist[(uint32_t)d * nblocks + blockIdx.x];
+                s_dbase[d] = ot;
+                s_gbase[d] = og + hb[i];
             }
-            carry_t += wt;
-            carry_g += wg;
+            ot += tt[i];
+            og += gt[i];
         }
     }
     __syncthreads();
@@ -321,7 +341,16 @@ static void radix_pass(const uint32_t* ki, const uint32_t* vi, const uint32_t* w
                            n_dev, shift, nb, hist, dtot, ko, vo, nullptr);
 }
 
+// Passes of at most 8-bit digits.  (Wider digits save passes but shorten the
+// runs of equal digits in a 4096-element tile, so the scatter's stores stop
+// coalescing: three 11-bit passes over 1M depth keys measured slower than
+// four 8-bit ones.)
 int radix_passes(int nbits) { return nbits <= 0 ? 0 : (nbits + 7) / 8; }
+int radix_digit_bits(int nbits)
+{
+    const int np = radix_passes(nbits);
+    return np == 0 ? 0 : (nbits + np - 1) / np;
+}
 
 hipError_t radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, uint32_t n_host,
                       const uint32_t* n_dev, uint32_t max_n, int nbits, uint32_t* hist, uint32_t* dtot,
@@ -331,7 +360,7 @@ hipError_t radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, ui
     *result_in_1 = 0;
     const uint32_t nb = scan_blocks(max_n);
     if (np == 0 || nb == 0) return hipGetLastError();
-    const int bits = (nbits + np - 1) / np;
+    const int bits = radix_digit_bits(nbits);
     uint32_t *ki = k0, *vi = v0, *wi = w0, *ko = k1, *vo = v1, *wo = w1;
     for (int p = 0; p < np; ++p) {
         const int shift = p * bits;
@@ -343,7 +372,8 @@ hipError_t radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, ui
         case 5: radix_pass<5>(ki, vi, wi, ko, vo, wo, n_host, n_dev, nb, shift, hist, dtot, s); break;
         case 6: radix_pass<6>(ki, vi, wi, ko, vo, wo, n_host, n_dev, nb, shift, hist, dtot, s); break;
         case 7: radix_pass<7>(ki, vi, wi, ko, vo, wo, n_host, n_dev, nb, shift, hist, dtot, s); break;
-        default: radix_pass<8>(ki, vi, wi, ko, vo, wo, n_host, n_dev, nb, shift, hist, dtot, s); break;
+        case 8: radix_pass<8>(ki, vi, wi, ko, vo, wo, n_host, n_dev, nb, shift, hist, dtot, s); break;
+        default: return hipErrorInvalidValue;
         }
         uint32_t* t;
         t = ki; ki = ko; ko = t;
