@@ -35,6 +35,13 @@
 // phase in revolutions ph = (f'/2pi).d, K = (1 + cos 2pi ph)/2, W' = K E.
 #include "common.hpp"
 
+// Multiply-adds within one expression fuse into FMAs here (the rest of the
+// library builds with contraction off).  Every include/stop decision goes
+// through eval_at, whose arithmetic is spelled out with fmaf, so the forward
+// and the backward still take identical decisions; only the rounding of the
+// colour and gradient sums changes.
+#pragma clang fp contract(on)
+
 namespace wipes {
 
 constexpr int kWpb = 4;   // waves (tiles) per workgroup of the work-counting kernel
@@ -481,51 +488,57 @@ __global__ void __launch_bounds__(TW * TH) k_blend_fwd_q(const ImgDesc* __restri
     }
 }
 
-// Sum 16 per-lane values over the wave with a halving butterfly on VALU
+// Sum 12 per-lane values over the wave with a halving butterfly on VALU
 // cross-lane paths only (no LDS round trips): each step pairs lanes, keeps
-// half the values and adds the partner's copy of that half.  gfx950's
+// part of the values and adds the partner's copy of that part.  gfx950's
 // permlane32/permlane16 swaps exchange the two halves / row pairs of two
-// registers in one instruction, and DPP row_mirror, row_half_mirror and
-// quad_perm pair lanes inside a 16-lane row.  Pairing lanes by a mirror flips
-// several low bits at once, which is still a valid butterfly as long as the
-// kept half is chosen by the bit the pairing flips last; the final layout is
-// lane l holds, in v[0], the wave total of value (l >> 2) & 15.
+// registers in one instruction (12 -> 6 -> 3 values per lane), and DPP
+// row_mirror, row_half_mirror and quad_perm pair lanes inside a 16-lane row.
+// Pairing lanes by a mirror flips several low bits at once, which is still a
+// valid butterfly as long as the lanes that keep a value are chosen by the
+// bit the pairing flips last.  The three values left in a row end in lanes
+// 0-3 (first), 4-7 (second) and 8-15 (third) of that row, so lane l returns
+// the wave total of value reduce12_index(l).
 template <int CTRL>
 __device__ __forceinline__ float dpp_mov(float v)
 {
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, false));
 }
 
-__device__ __forceinline__ void wave_reduce16_valu(float v[16])
+__device__ __forceinline__ float wave_reduce12_valu(const float v[12])
 {
     const int l = lane_id();
+    float u[6], w[3];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {   // lanes 0-31 keep v[j], lanes 32-63 keep v[j + 8]
-        const auto r = __builtin_amdgcn_permlane32_swap(__float_as_int(v[j]), __float_as_int(v[j + 8]), false, false);
-        v[j] = __int_as_float(r[0]) + __int_as_float(r[1]);
+    for (int j = 0; j < 6; ++j) {   // lanes 0-31 keep v[j], lanes 32-63 keep v[j + 6]
+        const auto r = __builtin_amdgcn_permlane32_swap(__float_as_int(v[j]), __float_as_int(v[j + 6]), false, false);
+        u[j] = __int_as_float(r[0]) + __int_as_float(r[1]);
     }
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {   // even rows keep v[j], odd rows keep v[j + 4]
-        const auto r = __builtin_amdgcn_permlane16_swap(__float_as_int(v[j]), __float_as_int(v[j + 4]), false, false);
-        v[j] = __int_as_float(r[0]) + __int_as_float(r[1]);
+    for (int j = 0; j < 3; ++j) {   // even rows keep u[j], odd rows keep u[j + 3]
+        const auto r = __builtin_amdgcn_permlane16_swap(__float_as_int(u[j]), __float_as_int(u[j + 3]), false, false);
+        w[j] = __int_as_float(r[0]) + __int_as_float(r[1]);
     }
-    {
-        const bool h = (l & 8) != 0;   // row_mirror pairs i with 15 - i
-#pragma unroll
-        for (int j = 0; j < 2; ++j) {
-            const float a = v[j] + dpp_mov<0x140>(v[j]);
-            const float b = v[j + 2] + dpp_mov<0x140>(v[j + 2]);
-            v[j] = h ? b : a;
-        }
-    }
-    {
-        const bool h = (l & 4) != 0;   // row_half_mirror pairs i with 7 - i inside each half row
-        const float a = v[0] + dpp_mov<0x141>(v[0]);
-        const float b = v[1] + dpp_mov<0x141>(v[1]);
-        v[0] = h ? b : a;
-    }
-    v[0] += dpp_mov<0x4e>(v[0]);      // quad_perm [2, 3, 0, 1]
-    v[0] += dpp_mov<0xb1>(v[0]);      // quad_perm [1, 0, 3, 2]
+    // row_mirror pairs i with 15 - i: lanes 0-7 go on with w[0] and w[1], lanes 8-15 with w[2]
+    const float a0 = w[0] + dpp_mov<0x140>(w[0]);
+    const float a1 = w[1] + dpp_mov<0x140>(w[1]);
+    const float a2 = w[2] + dpp_mov<0x140>(w[2]);
+    const float x = (l & 8) ? a2 : a0;
+    // row_half_mirror pairs i with 7 - i inside each half row: lanes 4-7 keep the second value
+    const float xs = x + dpp_mov<0x141>(x);
+    const float ys = a1 + dpp_mov<0x141>(a1);
+    float t = ((l & 12) == 4) ? ys : xs;
+    t += dpp_mov<0x4e>(t);   // quad_perm [2, 3, 0, 1]
+    t += dpp_mov<0xb1>(t);   // quad_perm [1, 0, 3, 2]
+    return t;
+}
+
+// Which of the 12 values wave_reduce12_valu leaves in lane l; lanes whose
+// (l & 15) is 0, 4 or 8 are the first of their group.
+__device__ __forceinline__ int reduce12_index(int l)
+{
+    const int i = l & 15;
+    return 6 * (l >> 5) + 3 * ((l >> 4) & 1) + (i < 4 ? 0 : i < 8 ? 1 : 2);
 }
 
 // ------------------------------------------------------------ backward
@@ -535,7 +548,7 @@ __device__ __forceinline__ void wave_reduce16_valu(float v[16])
 constexpr int kSlot = 12;
 
 // Per-pair gradient terms shared by both modes: dW = dL/dW' of the pair.
-__device__ __forceinline__ void pair_grads(float v[16], const PairEval& p, float dW, float ca, float cb, float cc,
+__device__ __forceinline__ void pair_grads(float v[12], const PairEval& p, float dW, float ca, float cb, float cc,
                                            float fx, float fy)
 {
     const float sn = __builtin_amdgcn_sinf(__builtin_amdgcn_fractf(p.ph));
@@ -628,8 +641,14 @@ __device__ __forceinline__ void bwd_tile(const ImgDesc* __restrict__ descs, int 
     uint64_t mn = c0 > G.start ? hits_of(n0, n1) : 0ull;
     uint32_t pn = 0;
     if ((mn >> l) & 1ull) pn = vals[(n0 & ~63u) + (uint32_t)l];
+    // the combine step gives thread tid list position b + (tid >> 2) of the
+    // chunk and three of its slot values
+    const uint32_t co = (uint32_t)tid >> 2, cc3 = ((uint32_t)tid & 3u) * 3u;
     for (;;) {
         const uint32_t b = c0 & ~63u;
+        // its slot index is loaded now and used after the replay
+        const bool cmine = NT >= 4 * kWave && b + co >= c0 && b + co < c1;
+        const uint32_t ce = cmine ? eidx[b + co] : 0u;
         if ((m >> l) & 1ull) {
             st[__popcll(m & below)] = stage_raw(cur, bx, by, b + (uint32_t)l);
         } else {
@@ -659,9 +678,9 @@ __device__ __forceinline__ void bwd_tile(const ImgDesc* __restrict__ descs, int 
             Sn = st[j > 0 ? j - 1 : 0];
             // branch-free: a pair that takes no part gets zero weight, for which
             // every update is an exact identity and every gradient term is zero
-            float v[16];
+            float v[12];
 #pragma unroll
-            for (int k = 0; k < 16; ++k) v[k] = 0.0f;
+            for (int k = 0; k < 12; ++k) v[k] = 0.0f;
             const PairEval p = eval_at(S.mrx, S.mry, S.c0 * kConicScale, S.c1 * (2.0f * kConicScale),
                                        S.c2 * kConicScale, S.f0 * kInv2Pi, S.f1 * kInv2Pi, lx, ly);
             const float a = S.op * p.W;
@@ -700,9 +719,8 @@ __device__ __forceinline__ void bwd_tile(const ImgDesc* __restrict__ descs, int 
             const bool any = __ballot(takes) != 0ull;
             float* o = mine + (S.pos & 63u) * kSlot;
             if (any) {
-                wave_reduce16_valu(v);
-                const int id = l >> 2;
-                if ((l & 3) == 0 && id < kSlot) o[id] = v[0];
+                const float tot = wave_reduce12_valu(v);
+                if ((l & 15) == 0 || (l & 15) == 4 || (l & 15) == 8) o[reduce12_index(l)] = tot;
             } else if (l < kSlot) {
                 o[l] = 0.0f;
             }
@@ -712,16 +730,35 @@ __device__ __forceinline__ void bwd_tile(const ImgDesc* __restrict__ descs, int 
         uint64_t anyhit = 0ull;
 #pragma unroll
         for (int k = 0; k < NB; ++k) anyhit |= hitm[k];
-        const uint32_t n = c1 - c0, r0 = (c0 & 63u) * kSlot;
-        for (uint32_t q = (uint32_t)tid; q < n * kSlot; q += NT) {
-            const uint32_t pp = q / kSlot, pos = c0 + pp;
-            if (!((anyhit >> (pos & 63u)) & 1ull)) continue;
-            float sum = part[r0 + q];
+        if constexpr (NT >= 4 * kWave) {
+            if (cmine && ((anyhit >> co) & 1ull)) {
+                const uint32_t r = co * kSlot + cc3;
+                float s3[3];
 #pragma unroll
-            for (int k = 1; k < NB; ++k) sum += part[(size_t)k * kWave * kSlot + r0 + q];
-            const uint32_t e = eidx[pos], comp = q - pp * kSlot;
-            slots[(size_t)e * kSlot + comp] = sum;
-            if (comp == 0) atomicOr(smark + (e >> 5), 1u << (e & 31u));
+                for (int c = 0; c < 3; ++c) {
+                    float sum = part[r + c];
+#pragma unroll
+                    for (int k = 1; k < NB; ++k) sum += part[(size_t)k * kWave * kSlot + r + c];
+                    s3[c] = sum;
+                }
+                float* dst = slots + (size_t)ce * kSlot + cc3;
+                dst[0] = s3[0];
+                dst[1] = s3[1];
+                dst[2] = s3[2];
+                if (cc3 == 0) atomicOr(smark + (ce >> 5), 1u << (ce & 31u));
+            }
+        } else {
+            const uint32_t n = c1 - c0, r0 = (c0 & 63u) * kSlot;
+            for (uint32_t q = (uint32_t)tid; q < n * kSlot; q += NT) {
+                const uint32_t pp = q / kSlot, pos = c0 + pp;
+                if (!((anyhit >> (pos & 63u)) & 1ull)) continue;
+                float sum = part[r0 + q];
+#pragma unroll
+                for (int k = 1; k < NB; ++k) sum += part[(size_t)k * kWave * kSlot + r0 + q];
+                const uint32_t e = eidx[pos], comp = q - pp * kSlot;
+                slots[(size_t)e * kSlot + comp] = sum;
+                if (comp == 0) atomicOr(smark + (e >> 5), 1u << (e & 31u));
+            }
         }
         __syncthreads();
         if (!more) break;

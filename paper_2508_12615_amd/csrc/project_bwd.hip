@@ -19,6 +19,11 @@
 // cost time (the forward projection is FP64 for the mean's sub-pixel phase).
 #include "common.hpp"
 
+// Multiply-adds within one expression fuse into FMAs here (the rest of the
+// library builds with contraction off): the chain rule is FP32 and compared
+// at a relative tolerance, so only its rounding changes.
+#pragma clang fp contract(on)
+
 namespace wipes {
 
 constexpr int kSlotB = 12;
