@@ -34,12 +34,13 @@ __device__ __forceinline__ float q32(float ca, float cb, float cc, float dx, flo
 
 __device__ __forceinline__ float clamp32(float v, float lo, float hi) { return fminf(fmaxf(v, lo), hi); }
 
-__device__ __forceinline__ bool ellipse_reaches(float mx, float my, float ca, float cb, float cc, float Qs, int32_t x0,
-                                                int32_t y0, int32_t x1, int32_t y1)
+// sy = -cb / cc and sx = -cb / ca (the slopes of the clamped minima) depend
+// on the primitive only and are passed in, divided once per primitive.
+__device__ __forceinline__ bool ellipse_reaches(float mx, float my, float ca, float cb, float cc, float sy, float sx,
+                                                float Qs, int32_t x0, int32_t y0, int32_t x1, int32_t y1)
 {
     const float fx0 = (float)x0 + 0.5f, fx1 = (float)x1 + 0.5f, fy0 = (float)y0 + 0.5f, fy1 = (float)y1 + 0.5f;
     if (mx >= fx0 && mx <= fx1 && my >= fy0 && my <= fy1) return true;
-    const float sy = -cb / cc, sx = -cb / ca;
     const float dxa = fx0 - mx, dxb = fx1 - mx, dya = fy0 - my, dyb = fy1 - my;
     float m = q32(ca, cb, cc, dxa, clamp32(sy * dxa, dya, dyb));
     m = fminf(m, q32(ca, cb, cc, dxb, clamp32(sy * dxb, dya, dyb)));
@@ -86,13 +87,14 @@ __global__ void __launch_bounds__(256) k_bin_count(const ImgDesc* __restrict__ d
             } else {
                 full = 0;
                 const float ca = recs[i].ca, cb = recs[i].cb, cc = recs[i].cc;
+                const float sy = -cb / cc, sx = -cb / ca;
                 int k = 0;
                 for (int32_t ty = ty0; ty <= ty1; ++ty)
                     for (int32_t tx = tx0; tx <= tx1; ++tx, ++k) {
                         const int32_t rx0 = max(tx * kp.tile_w, ix0), ry0 = max(ty * kp.tile_h, iy0);
                         const int32_t rx1 = min(tx * kp.tile_w + kp.tile_w - 1, ix1);
                         const int32_t ry1 = min(ty * kp.tile_h + kp.tile_h - 1, iy1);
-                        if (ellipse_reaches(mx, my, ca, cb, cc, a.Qs, rx0, ry0, rx1, ry1)) mask |= 1ull << k;
+                        if (ellipse_reaches(mx, my, ca, cb, cc, sy, sx, a.Qs, rx0, ry0, rx1, ry1)) mask |= 1ull << k;
                     }
                 c = (uint32_t)__popcll(mask);
             }
