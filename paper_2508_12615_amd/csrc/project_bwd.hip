@@ -48,6 +48,9 @@ __global__ void __launch_bounds__(256) k_project_bwd(const ImgDesc* __restrict__
     // numbered in primitive order).  The wave streams the run through LDS 64
     // slots at a time with coalesced loads, and each lane adds up its own
     // primitive's slots in ascending order (the same order at any batch size).
+    // The next 64 slots are loaded while the current ones are added; their
+    // written-bits come from a window of 64 words (2048 slots) that lane j
+    // holds word wbase + j of, refilled when a chunk runs past it.
     const uint32_t c = inr ? count[i] : 0u;
     const uint32_t base = inr ? off_id[i] : 0u;
     const uint32_t first = (uint32_t)__builtin_amdgcn_readfirstlane((int)base);   // lane 0 is in range
@@ -56,28 +59,48 @@ __global__ void __launch_bounds__(256) k_project_bwd(const ImgDesc* __restrict__
     float acc[11];
 #pragma unroll
     for (int k = 0; k < 11; ++k) acc[k] = 0.0f;
+    const uint32_t wlast = total ? (first + total - 1u) >> 5 : 0u;
+    uint32_t wbase = first >> 5;
+    uint32_t vword = (total && wbase + (uint32_t)l <= wlast) ? valid[wbase + (uint32_t)l] : 0u;
+    // a slot the backward did not write (no pixel of its tile reached it) is zero
+    auto fetch = [&](uint32_t k0, float4& s0, float4& s1, float4& s2) {
+        const uint32_t lastw = (first + min(k0 + (uint32_t)kWave, total) - 1u) >> 5;
+        if (lastw - wbase >= (uint32_t)kWave) {   // uniform: the window moves on
+            wbase = (first + k0) >> 5;
+            vword = wbase + (uint32_t)l <= wlast ? valid[wbase + (uint32_t)l] : 0u;
+        }
+        const uint32_t e = first + k0 + (uint32_t)l;
+        const uint32_t word = (uint32_t)__shfl((int)vword, (int)(((e >> 5) - wbase) & 63u), kWave);
+        s0 = s1 = s2 = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (k0 + (uint32_t)l < total && ((word >> (e & 31u)) & 1u)) {
+            const float4* sl = reinterpret_cast<const float4*>(slots + (size_t)e * kSlotB);
+            s0 = sl[0];
+            s1 = sl[1];
+            s2 = sl[2];
+        }
+    };
+    float4 a0, a1, a2;
+    if (total) fetch(0, a0, a1, a2);
     for (uint32_t k0 = 0; k0 < total; k0 += kWave) {
+        float4 b0, b1, b2;
+        if (k0 + kWave < total) fetch(k0 + kWave, b0, b1, b2);
         if (k0 + (uint32_t)l < total) {
-            // a slot the backward did not write (no pixel of its tile reached it) is zero
-            const uint32_t e = first + k0 + (uint32_t)l;
-            if ((valid[e >> 5] >> (e & 31u)) & 1u) {
-                const float4* sl = reinterpret_cast<const float4*>(slots + (size_t)e * kSlotB);
-                s_slot[wv][l][0] = sl[0];
-                s_slot[wv][l][1] = sl[1];
-                s_slot[wv][l][2] = sl[2];
-            } else {
-                s_slot[wv][l][0] = s_slot[wv][l][1] = s_slot[wv][l][2] = make_float4(0.f, 0.f, 0.f, 0.f);
-            }
+            s_slot[wv][l][0] = a0;
+            s_slot[wv][l][1] = a1;
+            s_slot[wv][l][2] = a2;
         }
         wave_lds_sync();
         const uint32_t e1 = min(my1, k0 + kWave);
         for (uint32_t e = max(my0, k0); e < e1; ++e) {
-            const float4 a0 = s_slot[wv][e - k0][0], a1 = s_slot[wv][e - k0][1], a2 = s_slot[wv][e - k0][2];
-            acc[0] += a0.x; acc[1] += a0.y; acc[2] += a0.z; acc[3] += a0.w;
-            acc[4] += a1.x; acc[5] += a1.y; acc[6] += a1.z; acc[7] += a1.w;
-            acc[8] += a2.x; acc[9] += a2.y; acc[10] += a2.z;
+            const float4 x0 = s_slot[wv][e - k0][0], x1 = s_slot[wv][e - k0][1], x2 = s_slot[wv][e - k0][2];
+            acc[0] += x0.x; acc[1] += x0.y; acc[2] += x0.z; acc[3] += x0.w;
+            acc[4] += x1.x; acc[5] += x1.y; acc[6] += x1.z; acc[7] += x1.w;
+            acc[8] += x2.x; acc[9] += x2.y; acc[10] += x2.z;
         }
         wave_lds_sync();   // the stage is rewritten next
+        a0 = b0;
+        a1 = b1;
+        a2 = b2;
     }
     if (!inr) return;
     const ImgDesc& d = descs[image_of_prim(descs, B, i)];
