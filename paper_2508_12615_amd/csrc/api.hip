@@ -167,9 +167,8 @@ Layout layout_of(const wipes_params* p, const wipes_batch* b, int64_t cap, int w
     L.tile_bits = std::max(bits, 1);
     L.tile_result_b = radix_passes(L.tile_bits) & 1;
     L.depth_result_b = radix_passes(32) & 1;
-    L.order_result_b = radix_passes(8) & 1;
-    // digit histograms of the tile sort and of the 8-bit longest-first sort
-    const size_t nd_bins = (size_t)1 << std::max(radix_digit_bits(L.tile_bits), 8);
+    // digit histograms of the tile sort
+    const size_t nd_bins = (size_t)1 << radix_digit_bits(L.tile_bits);
     o = 0;
     L.b_keys_a = take((size_t)cap * 4);
     L.b_vals_a = take((size_t)cap * 4);
@@ -178,7 +177,7 @@ Layout layout_of(const wipes_params* p, const wipes_batch* b, int64_t cap, int w
     L.b_hist = take(nd_bins * std::max(nb_k, nb_t) * 4);
     L.b_dtot = take(nd_bins * 4);
     L.b_ranges = take((size_t)L.tiles * 8);
-    L.b_order = take((size_t)L.tiles * 4 * 4);   // LPT order + sort scratch (4 arrays)
+    L.b_order = take((size_t)L.tiles * 4);   // longest-first tile order
     L.b_tbsum = take((size_t)(nb_t + 1) * 4);
     if (with_bwd) {
         L.b_w_a = take((size_t)cap * 4);

@@ -79,7 +79,6 @@ struct Layout {
     int tile_bits = 1;
     int tile_result_b = 0;    // tile sort result in the *_b arrays
     int depth_result_b = 0;   // depth sort result in the *_b arrays
-    int order_result_b = 0;   // longest-first tile order in the second half of b_order
 };
 
 wipes_status fail(wipes_ctx* ctx, wipes_status st, const char* fmt, ...);
@@ -128,7 +127,8 @@ hipError_t launch_emit(const ImgDesc* descs, int B, int32_t n_total, const KPara
                        const uint32_t* order, const uint32_t* offs, const uint32_t* n_eff, uint32_t* keys,
                        uint32_t* vals, uint32_t* eidx, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t n, uint32_t v, hipStream_t s);
-hipError_t launch_tile_lpt_keys(const uint2* ranges, uint32_t n_tiles, uint32_t* keys, uint32_t* vals, hipStream_t s);
+hipError_t launch_tile_lpt_order(const uint2* ranges, uint32_t n_tiles, uint32_t* order, hipStream_t s);
+hipError_t launch_fill2_u32(uint32_t* p, uint32_t n, uint32_t* q, uint32_t m, uint32_t v, hipStream_t s);
 hipError_t launch_ranges(const uint32_t* keys, const uint32_t* n_eff, uint32_t max_k, uint2* ranges, hipStream_t s);
 uint32_t scan_blocks(uint32_t max_n);
 hipError_t scan_excl(const uint32_t* vals, const uint32_t* gather, uint32_t n_host, const uint32_t* n_dev,

@@ -254,19 +254,42 @@ __global__ void __launch_bounds__(256) k_ranges(const uint32_t* __restrict__ key
     if (s == K - 1 || keys[s + 1] != t) ranges[t].y = s + 1;
 }
 
-// Keys for a longest-list-first tile order: key = 255 - q(list length) with
-// q = min(255, floor(16 log2(length + 1))) (16 steps per doubling), value =
-// tile; one stable 8-bit pass then lists long tiles first (ties and equal
-// quanta in tile order) -- an approximate order is all the queue needs.
-__global__ void __launch_bounds__(256) k_tile_lpt_keys(const uint2* __restrict__ ranges, uint32_t n_tiles,
-                                                        uint32_t* __restrict__ keys, uint32_t* __restrict__ vals)
+// Longest-first tile order for the persistent queue: a counting sort of the
+// tiles by a log-scale length key, 255 - min(255, floor(16 log2(len + 1))),
+// by one workgroup with LDS counters.  Within a key the order is whatever the
+// LDS atomics give: any order of the tiles renders the same images and
+// gradients, the order only brings the long tiles to the front.
+__device__ __forceinline__ uint32_t lpt_key(uint2 r)
 {
-    const uint32_t t = blockIdx.x * 256u + threadIdx.x;
-    if (t >= n_tiles) return;
-    const uint2 r = ranges[t];
     const float q = 16.0f * __log2f((float)(r.y - r.x) + 1.0f);
-    keys[t] = 255u - min((uint32_t)q, 255u);
-    vals[t] = t;
+    return 255u - min((uint32_t)q, 255u);
+}
+
+__global__ void __launch_bounds__(1024) k_tile_lpt_order(const uint2* __restrict__ ranges, uint32_t n_tiles,
+                                                         uint32_t* __restrict__ order)
+{
+    __shared__ uint32_t s_cnt[256];
+    if (threadIdx.x < 256) s_cnt[threadIdx.x] = 0u;
+    __syncthreads();
+    for (uint32_t t = threadIdx.x; t < n_tiles; t += 1024u) atomicAdd(&s_cnt[lpt_key(ranges[t])], 1u);
+    __syncthreads();
+    if (threadIdx.x < kWave) {   // exclusive scan of the 256 counts, four per lane
+        const uint32_t l = threadIdx.x;
+        uint32_t c[4], sum = 0u, tot;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            c[k] = s_cnt[4u * l + k];
+            sum += c[k];
+        }
+        uint32_t ex = wave_excl_scan_u32(sum, &tot);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            s_cnt[4u * l + k] = ex;
+            ex += c[k];
+        }
+    }
+    __syncthreads();
+    for (uint32_t t = threadIdx.x; t < n_tiles; t += 1024u) order[atomicAdd(&s_cnt[lpt_key(ranges[t])], 1u)] = t;
 }
 
 // Fill kernel (used instead of memset so the sequence can live in a graph).
@@ -274,6 +297,15 @@ __global__ void __launch_bounds__(256) k_fill_u32(uint32_t* __restrict__ p, uint
 {
     const uint32_t i = blockIdx.x * 256u + threadIdx.x;
     if (i < n) p[i] = v;
+}
+
+// Two fills in one launch: p[0..n) then q[0..m).
+__global__ void __launch_bounds__(256) k_fill2_u32(uint32_t* __restrict__ p, uint32_t n, uint32_t* __restrict__ q,
+                                                    uint32_t m, uint32_t v)
+{
+    const uint32_t i = blockIdx.x * 256u + threadIdx.x;
+    if (i < n) p[i] = v;
+    else if (i - n < m) q[i - n] = v;
 }
 
 // ------------------------------------------------------------- host side
@@ -309,16 +341,27 @@ hipError_t launch_emit(const ImgDesc* descs, int B, int32_t n_total, const KPara
     return hipGetLastError();
 }
 
-hipError_t launch_tile_lpt_keys(const uint2* ranges, uint32_t n_tiles, uint32_t* keys, uint32_t* vals, hipStream_t s)
+hipError_t launch_tile_lpt_order(const uint2* ranges, uint32_t n_tiles, uint32_t* order, hipStream_t s)
 {
-    if (n_tiles > 0)
-        hipLaunchKernelGGL(k_tile_lpt_keys, dim3(blocks_of(n_tiles)), dim3(256), 0, s, ranges, n_tiles, keys, vals);
+    if (n_tiles > 0) hipLaunchKernelGGL(k_tile_lpt_order, dim3(1), dim3(1024), 0, s, ranges, n_tiles, order);
     return hipGetLastError();
 }
 
 hipError_t launch_fill_u32(uint32_t* p, uint32_t n, uint32_t v, hipStream_t s)
 {
     if (n > 0) hipLaunchKernelGGL(k_fill_u32, dim3(blocks_of(n)), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill2_u32(uint32_t* p, uint32_t n, uint32_t* q, uint32_t m, uint32_t v, hipStream_t s)
+{
+    if (!q) m = 0;
+    if (!p) n = 0;
+    if ((uint64_t)n + m >= (1ull << 32)) {
+        const hipError_t e = launch_fill_u32(p, n, v, s);
+        return e != hipSuccess ? e : launch_fill_u32(q, m, v, s);
+    }
+    if (n + m > 0) hipLaunchKernelGGL(k_fill2_u32, dim3(blocks_of(n + m)), dim3(256), 0, s, p, n, q, m, v);
     return hipGetLastError();
 }
 

@@ -74,12 +74,11 @@ static Views views(const Layout& L, const void* screen, const void* bins)
     return v;
 }
 
-// Where the longest-first tile order lands: the sort ping-pongs between
-// order[nt..2nt) / order[2nt..3nt) (values) -- see bin_sort_core.
+// The longest-first tile order (persistent == 2), written by bin_sort_core.
 static const uint32_t* tile_order(const Layout& L, const Views& v)
 {
-    const size_t nt = (size_t)L.tiles;
-    return L.order_result_b ? v.order + 3 * nt : v.order + nt;
+    (void)L;
+    return v.order;
 }
 
 #define HIP_TRY(call, what)                                    \
@@ -157,16 +156,8 @@ wipes_status bin_sort_core(wipes_ctx* ctx, const wipes_params* p, const wipes_ba
     StageScope sc(ctx, kStRanges, s);
     HIP_TRY(launch_fill_u32((uint32_t*)v.ranges, (uint32_t)(2 * L.tiles), 0u, s), "ranges fill");
     HIP_TRY(launch_ranges(skeys, v.ctrl + kCtrlNEff, max_k, v.ranges, s), "ranges");
-    if (p->persistent == 2) {
-        // longest tile list first for the persistent queue
-        const uint32_t nt = (uint32_t)L.tiles;
-        uint32_t* ok = v.order;
-        uint32_t* ov = v.order + nt;
-        HIP_TRY(launch_tile_lpt_keys(v.ranges, nt, ok, ov, s), "lpt keys");
-        int in_b2 = 0;
-        HIP_TRY(radix_sort(ok, ov, ov + nt, ov + 2 * (size_t)nt, nt, nullptr, nt, 8, v.hist, v.dtot, &in_b2, s),
-                "lpt sort");
-    }
+    if (p->persistent == 2)   // longest tile list first for the persistent queue
+        HIP_TRY(launch_tile_lpt_order(v.ranges, (uint32_t)L.tiles, v.order, s), "lpt order");
     return WIPES_OK;
 }
 
@@ -183,14 +174,14 @@ wipes_status render_fwd_core(wipes_ctx* ctx, const wipes_params* p, const wipes_
     const uint32_t* order = p->persistent == 2 ? tile_order(L, v) : nullptr;
     if (p->persistent) {
         queue = v.ctrl + kCtrlQueueFwd;
-        HIP_TRY(launch_fill_u32(queue, kQueueLanes * kQueueStride, 0u, s), "queue reset");
         pblocks = (uint32_t)ctx->n_cu * 8u;
     }
-    if (v.cmask) {
-        // the forward records which primitives contribute to each block, for the backward
-        const size_t words = (size_t)(p->tile_w / 8) * (p->tile_h / 8) * L.cmask_words;
-        HIP_TRY(launch_fill_u32((uint32_t*)v.cmask, (uint32_t)(2 * words), 0u, s), "mask clear");
-    }
+    // queue counters, and the mask in which the forward records which
+    // primitives contribute to each block (for the backward), cleared in one launch
+    const size_t mwords = v.cmask ? (size_t)(p->tile_w / 8) * (p->tile_h / 8) * L.cmask_words * 2 : 0;
+    HIP_TRY(launch_fill2_u32(queue, queue ? kQueueLanes * kQueueStride : 0u, (uint32_t*)v.cmask, (uint32_t)mwords,
+                             0u, s),
+            "queue reset / mask clear");
     StageScope sc(ctx, kStBlendFwd, s);
     HIP_TRY(launch_blend_fwd(v.descs, L.B, kp, v.recs, svals, v.ranges, v.ctrl + kCtrlOverflow, (uint32_t)L.tiles,
                              order, queue, pblocks, image, T_final, last, v.cmask, L.cmask_words, s),
@@ -211,10 +202,11 @@ wipes_status render_bwd_core(wipes_ctx* ctx, const wipes_params* p, const wipes_
     const uint32_t* order = p->persistent == 2 ? tile_order(L, v) : nullptr;
     if (p->persistent) {
         queue = v.ctrl + kCtrlQueueBwd;
-        HIP_TRY(launch_fill_u32(queue, kQueueLanes * kQueueStride, 0u, s), "queue reset");
         pblocks = (uint32_t)ctx->n_cu * 8u;
     }
-    HIP_TRY(launch_fill_u32(v.svalid, (uint32_t)(L.cap / 32 + 2), 0u, s), "slot marks clear");
+    HIP_TRY(launch_fill2_u32(queue, queue ? kQueueLanes * kQueueStride : 0u, v.svalid, (uint32_t)(L.cap / 32 + 2), 0u,
+                             s),
+            "queue reset / slot marks clear");
     {
         StageScope sc(ctx, kStBlendBwd, s);
         const uint32_t* seidx = L.tile_result_b ? v.w_b : v.w_a;
