@@ -61,45 +61,97 @@ __global__ void __launch_bounds__(256) k_bin_count(const ImgDesc* __restrict__ d
                                                     PrimPack* __restrict__ pk, uint32_t* __restrict__ dkey,
                                                     uint32_t* __restrict__ dval)
 {
+    // per lane of each wave: the ellipse and rectangle its primitive's tile
+    // tests need, the offset of those tests in the wave's list, the kept mask
+    __shared__ float4 s_pa[4][kWave];             // mx, my, ca, cb
+    __shared__ float4 s_pb[4][kWave];             // cc, sy, sx, Qs
+    __shared__ uint4 s_pc[4][kWave];              // box0, box1, first tile (x | y << 16), tiles per row
+    __shared__ uint32_t s_off[4][kWave];
+    __shared__ unsigned long long s_mask[4][kWave];
+    const int w = (int)(threadIdx.x >> 6), l = lane_id();
+    if ((int32_t)(blockIdx.x * 256u + (uint32_t)w * kWave) >= n_total) return;   // wave-uniform
     const int32_t i = (int32_t)(blockIdx.x * 256u + threadIdx.x);
-    if (i >= n_total) return;
-    const ImgDesc& d = descs[image_of_prim(descs, B, i)];
-    const Aux a = aux[i];
-    const float mx = recs[i].mx, my = recs[i].my;
-    uint32_t c = 0, b0 = kEmptyBox0, b1 = kEmptyBox1, full = 1;
-    uint64_t mask = 0;
-    if (a.rx >= 0.0f && a.ry >= 0.0f && fabsf(mx) < 1e30f && fabsf(my) < 1e30f) {
-        float x0 = ceilf((mx - a.rx) - 0.5f), x1 = floorf((mx + a.rx) - 0.5f);
-        float y0 = ceilf((my - a.ry) - 0.5f), y1 = floorf((my + a.ry) - 0.5f);
-        x0 = fmaxf(x0, 0.0f);
-        y0 = fmaxf(y0, 0.0f);
-        x1 = fminf(x1, (float)(d.W - 1));
-        y1 = fminf(y1, (float)(d.H - 1));
-        if (x0 <= x1 && y0 <= y1) {
-            const int32_t ix0 = (int32_t)x0, iy0 = (int32_t)y0, ix1 = (int32_t)x1, iy1 = (int32_t)y1;
-            b0 = pack16(ix0, iy0);
-            b1 = pack16(ix1, iy1);
-            const int32_t tx0 = ix0 >> kp.log2_tw, ty0 = iy0 >> kp.log2_th;
-            const int32_t tx1 = ix1 >> kp.log2_tw, ty1 = iy1 >> kp.log2_th;
-            const int32_t nt = (tx1 - tx0 + 1) * (ty1 - ty0 + 1);
-            if (nt > kCullMaxTiles) {
-                c = (uint32_t)nt;
-            } else {
-                full = 0;
-                const float ca = recs[i].ca, cb = recs[i].cb, cc = recs[i].cc;
-                const float sy = -cb / cc, sx = -cb / ca;
-                int k = 0;
-                for (int32_t ty = ty0; ty <= ty1; ++ty)
-                    for (int32_t tx = tx0; tx <= tx1; ++tx, ++k) {
-                        const int32_t rx0 = max(tx * kp.tile_w, ix0), ry0 = max(ty * kp.tile_h, iy0);
-                        const int32_t rx1 = min(tx * kp.tile_w + kp.tile_w - 1, ix1);
-                        const int32_t ry1 = min(ty * kp.tile_h + kp.tile_h - 1, iy1);
-                        if (ellipse_reaches(mx, my, ca, cb, cc, sy, sx, a.Qs, rx0, ry0, rx1, ry1)) mask |= 1ull << k;
-                    }
-                c = (uint32_t)__popcll(mask);
+    const bool inr = i < n_total;
+    uint32_t c = 0, b0 = kEmptyBox0, b1 = kEmptyBox1, full = 1, ncull = 0;
+    Aux a{};
+    float mx = 0.0f, my = 0.0f, ca = 0.0f, cb = 0.0f, cc = 0.0f, sy = 0.0f, sx = 0.0f;
+    int32_t tx0 = 0, ty0 = 0, ntx = 1;
+    if (inr) {
+        const ImgDesc& d = descs[image_of_prim(descs, B, i)];
+        a = aux[i];
+        mx = recs[i].mx;
+        my = recs[i].my;
+        if (a.rx >= 0.0f && a.ry >= 0.0f && fabsf(mx) < 1e30f && fabsf(my) < 1e30f) {
+            float x0 = ceilf((mx - a.rx) - 0.5f), x1 = floorf((mx + a.rx) - 0.5f);
+            float y0 = ceilf((my - a.ry) - 0.5f), y1 = floorf((my + a.ry) - 0.5f);
+            x0 = fmaxf(x0, 0.0f);
+            y0 = fmaxf(y0, 0.0f);
+            x1 = fminf(x1, (float)(d.W - 1));
+            y1 = fminf(y1, (float)(d.H - 1));
+            if (x0 <= x1 && y0 <= y1) {
+                const int32_t ix0 = (int32_t)x0, iy0 = (int32_t)y0, ix1 = (int32_t)x1, iy1 = (int32_t)y1;
+                b0 = pack16(ix0, iy0);
+                b1 = pack16(ix1, iy1);
+                tx0 = ix0 >> kp.log2_tw;
+                ty0 = iy0 >> kp.log2_th;
+                const int32_t tx1 = ix1 >> kp.log2_tw, ty1 = iy1 >> kp.log2_th;
+                ntx = tx1 - tx0 + 1;
+                const int32_t nt = ntx * (ty1 - ty0 + 1);
+                if (nt > kCullMaxTiles) {
+                    c = (uint32_t)nt;
+                } else {
+                    full = 0;
+                    ncull = (uint32_t)nt;
+                    ca = recs[i].ca;
+                    cb = recs[i].cb;
+                    cc = recs[i].cc;
+                    sy = -cb / cc;
+                    sx = -cb / ca;
+                }
             }
         }
     }
+    // The wave shares the tile tests of its primitives' rectangles over its
+    // lanes (test k of a primitive is tile k of its rectangle, row-major), so
+    // it takes ceil(sum / 64) rounds instead of as many as its largest
+    // rectangle has tiles.  Each test is the same FP32 rule as per primitive.
+    uint32_t tot;
+    const uint32_t off = wave_excl_scan_u32(ncull, &tot);
+    uint64_t mask = 0;
+    if (tot) {   // wave-uniform
+        s_pa[w][l] = make_float4(mx, my, ca, cb);
+        s_pb[w][l] = make_float4(cc, sy, sx, a.Qs);
+        s_pc[w][l] = make_uint4(b0, b1, (uint32_t)tx0 | ((uint32_t)ty0 << 16), (uint32_t)ntx);
+        s_off[w][l] = off;
+        s_mask[w][l] = 0ull;
+        wave_lds_sync();
+        for (uint32_t j0 = 0; j0 < tot; j0 += kWave) {
+            const uint32_t j = j0 + (uint32_t)l;
+            if (j < tot) {
+                // owner: the last lane whose first test is at or before j
+                int o = 0;
+#pragma unroll
+                for (int step = kWave / 2; step > 0; step >>= 1)
+                    if (s_off[w][o + step] <= j) o += step;
+                const uint32_t k = j - s_off[w][o];
+                const float4 pa = s_pa[w][o], pb = s_pb[w][o];
+                const uint4 pc = s_pc[w][o];
+                // k < 64 and the row length <= 64: the float quotient of
+                // k + 1/2 is at least 1/128 from an integer, so its floor is exact
+                const uint32_t ky = (uint32_t)(((float)k + 0.5f) * __builtin_amdgcn_rcpf((float)pc.w));
+                const int32_t tx = (int32_t)lo16(pc.z) + (int32_t)(k - ky * pc.w), ty = (int32_t)hi16(pc.z) + (int32_t)ky;
+                const int32_t rx0 = max(tx * kp.tile_w, (int32_t)lo16(pc.x)), ry0 = max(ty * kp.tile_h, (int32_t)hi16(pc.x));
+                const int32_t rx1 = min(tx * kp.tile_w + kp.tile_w - 1, (int32_t)lo16(pc.y));
+                const int32_t ry1 = min(ty * kp.tile_h + kp.tile_h - 1, (int32_t)hi16(pc.y));
+                if (ellipse_reaches(pa.x, pa.y, pa.z, pa.w, pb.x, pb.y, pb.z, pb.w, rx0, ry0, rx1, ry1))
+                    atomicOr(&s_mask[w][o], 1ull << k);
+            }
+        }
+        wave_lds_sync();
+        mask = s_mask[w][l];
+        if (ncull) c = (uint32_t)__popcll(mask);
+    }
+    if (!inr) return;
     recs[i].box0 = b0;
     recs[i].box1 = b1;
     count[i] = c;
