@@ -240,10 +240,27 @@ void fill_descs(const wipes_params* p, const wipes_batch* b, std::vector<ImgDesc
     }
 }
 
-// Copy the descriptor table into the screen buffer (stream-ordered).  Uses a
-// ring of pinned staging slots; a slot is reused only after its previous copy
-// has completed.  Skipped while a graph is being captured (the table is
-// uploaded before capture and stays valid for the graph's lifetime).
+// Tables of up to kDescArgMax images travel as a kernel argument and one
+// wave writes them into the screen buffer: no copy from host memory, whose
+// blit and the wait after it cost more than the blend of a small image.
+constexpr int kDescArgMax = 8;
+struct DescArgs {
+    ImgDesc d[kDescArgMax];
+};
+
+__global__ void __launch_bounds__(64) k_put_descs(DescArgs a, int n, ImgDesc* __restrict__ out)
+{
+    const uint32_t* src = reinterpret_cast<const uint32_t*>(a.d);
+    uint32_t* dst = reinterpret_cast<uint32_t*>(out);
+    const uint32_t words = (uint32_t)n * (uint32_t)(sizeof(ImgDesc) / 4);
+    for (uint32_t k = threadIdx.x; k < words; k += 64u) dst[k] = src[k];
+}
+
+// Copy the descriptor table into the screen buffer (stream-ordered): small
+// tables as a kernel argument, larger ones through a ring of pinned staging
+// slots (a slot is reused only after its previous copy has completed).
+// Skipped while a graph is being captured (the table is uploaded before
+// capture and stays valid for the graph's lifetime).
 wipes_status upload_descs(wipes_ctx* ctx, const wipes_params* p, const wipes_batch* b, const Layout& L, void* screen,
                           hipStream_t s)
 {
@@ -251,6 +268,15 @@ wipes_status upload_descs(wipes_ctx* ctx, const wipes_params* p, const wipes_bat
     std::vector<ImgDesc> h;
     fill_descs(p, b, h);
     const size_t bytes = h.size() * sizeof(ImgDesc);
+    if (h.size() <= (size_t)kDescArgMax) {
+        DescArgs a;
+        memset(&a, 0, sizeof(a));
+        memcpy(a.d, h.data(), bytes);
+        hipLaunchKernelGGL(k_put_descs, dim3(1), dim3(64), 0, s, a, (int)h.size(),
+                           reinterpret_cast<ImgDesc*>((char*)screen + L.s_descs));
+        const hipError_t e = hipGetLastError();
+        return e == hipSuccess ? WIPES_OK : hip_fail(ctx, e, "descriptor upload");
+    }
     StagingSlot& slot = ctx->ring[ctx->ring_next];
     ctx->ring_next = (ctx->ring_next + 1) % kRing;
     hipError_t e;
