@@ -366,7 +366,8 @@ wipes_status wipes_ctx_create(int32_t device, wipes_ctx** out)
         return hip_fail(nullptr, e, "hipGetDeviceProperties");
     }
     c->n_cu = prop.multiProcessorCount;
-    e = hipHostMalloc((void**)&c->k_host, 256, hipHostMallocDefault);
+    e = hipHostMalloc((void**)&c->k_host, 256, hipHostMallocMapped);
+    if (e == hipSuccess) e = hipHostGetDevicePointer((void**)&c->k_host_dev, c->k_host, 0);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&c->k_ev, hipEventDisableTiming);
     if (e != hipSuccess) {
         wipes_ctx_destroy(c);

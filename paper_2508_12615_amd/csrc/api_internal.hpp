@@ -54,7 +54,8 @@ struct wipes_ctx {
     int ring_next = 0;
     bool capturing = false;      // descriptor uploads are skipped while capturing a graph
     uint32_t* k_host = nullptr;  // pinned word: instance count read back by bin_sort
-    hipEvent_t k_ev = nullptr;   // recorded after that copy
+    uint32_t* k_host_dev = nullptr;   // the same word as the device addresses it
+    hipEvent_t k_ev = nullptr;   // recorded after the kernel that writes it
     Profiler prof;
 };
 
@@ -133,7 +134,7 @@ hipError_t launch_ranges(const uint32_t* keys, const uint32_t* n_eff, uint32_t m
 uint32_t scan_blocks(uint32_t max_n);
 hipError_t scan_excl(const uint32_t* vals, const uint32_t* gather, uint32_t n_host, const uint32_t* n_dev,
                      uint32_t max_n, uint32_t* block_sums, uint32_t* out, uint32_t* total, uint32_t cap,
-                     uint32_t* n_eff, uint32_t* overflow, hipStream_t s);
+                     uint32_t* n_eff, uint32_t* overflow, hipStream_t s, uint32_t* total_host = nullptr);
 int radix_passes(int nbits);
 int radix_digit_bits(int nbits);   // digit width of each pass of radix_sort
 // Stable LSD sort of (key, value[, w]) over the low nbits of the keys; ping-pongs

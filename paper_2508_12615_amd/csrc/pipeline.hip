@@ -102,16 +102,14 @@ wipes_status bin_sort_core(wipes_ctx* ctx, const wipes_params* p, const wipes_ba
     // K, capacity check -> n_eff, overflow flag
     {
         StageScope sc(ctx, kStScan, s);
+        // the scan also stores K into the pinned host word when the caller
+        // wants it; the host waits for it only before the emission, so the
+        // round trip overlaps the depth sort
         HIP_TRY(scan_excl(v.count, nullptr, n, nullptr, n, v.bsum, v.off_id, v.ctrl + kCtrlK, (uint32_t)L.cap,
-                          v.ctrl + kCtrlNEff, v.ctrl + kCtrlOverflow, s),
+                          v.ctrl + kCtrlNEff, v.ctrl + kCtrlOverflow, s, n_instances_out ? ctx->k_host_dev : nullptr),
                 "scan");
     }
-    if (n_instances_out) {
-        // start the read-back of K now and wait for it only before the
-        // emission, so the host round trip overlaps the depth sort
-        HIP_TRY(hipMemcpyAsync(ctx->k_host, v.ctrl + kCtrlK, 4, hipMemcpyDeviceToHost, s), "read K");
-        HIP_TRY(hipEventRecord(ctx->k_ev, s), "read K event");
-    }
+    if (n_instances_out) HIP_TRY(hipEventRecord(ctx->k_ev, s), "read K event");
     const uint32_t* order = nullptr;
     const uint32_t* offs = v.off_id;
     if (L.alpha) {

@@ -56,7 +56,8 @@ __global__ void __launch_bounds__(kBlock) k_block_reduce(const uint32_t* __restr
 __global__ void __launch_bounds__(kBlock) k_scan_block_sums(uint32_t* __restrict__ block_sums, uint32_t nb,
                                                             uint32_t* __restrict__ total, uint32_t cap,
                                                             uint32_t* __restrict__ n_eff,
-                                                            uint32_t* __restrict__ overflow)
+                                                            uint32_t* __restrict__ overflow,
+                                                            uint32_t* __restrict__ total_host)
 {
     __shared__ uint32_t s_w[kBlock / kWave];
     __shared__ uint32_t s_carry;
@@ -83,6 +84,10 @@ __global__ void __launch_bounds__(kBlock) k_scan_block_sums(uint32_t* __restrict
     if (threadIdx.x == 0) {
         const uint32_t t = s_carry;
         *total = t;
+        if (total_host) {   // pinned host word: the host reads it once this kernel has completed
+            *total_host = t;
+            __threadfence_system();
+        }
         if (n_eff) {
             const bool over = cap != 0u && t > cap;
             *n_eff = over ? 0u : t;
@@ -312,13 +317,14 @@ uint32_t scan_blocks(uint32_t max_n) { return (max_n + kTile - 1) / kTile; }
 
 hipError_t scan_excl(const uint32_t* vals, const uint32_t* gather, uint32_t n_host, const uint32_t* n_dev,
                      uint32_t max_n, uint32_t* block_sums, uint32_t* out, uint32_t* total, uint32_t cap,
-                     uint32_t* n_eff, uint32_t* overflow, hipStream_t s)
+                     uint32_t* n_eff, uint32_t* overflow, hipStream_t s, uint32_t* total_host)
 {
     const uint32_t nb = scan_blocks(max_n);
     if (nb > 0) {
         hipLaunchKernelGGL(k_block_reduce, dim3(nb), dim3(kBlock), 0, s, vals, gather, n_host, n_dev, block_sums);
     }
-    hipLaunchKernelGGL(k_scan_block_sums, dim3(1), dim3(kBlock), 0, s, block_sums, nb, total, cap, n_eff, overflow);
+    hipLaunchKernelGGL(k_scan_block_sums, dim3(1), dim3(kBlock), 0, s, block_sums, nb, total, cap, n_eff, overflow,
+                       total_host);
     if (nb > 0) {
         hipLaunchKernelGGL(k_scan_apply, dim3(nb), dim3(kBlock), 0, s, vals, gather, n_host, n_dev, block_sums,
                            out);
