@@ -150,7 +150,7 @@ Layout layout_of(const wipes_params* p, const wipes_batch* b, int64_t cap, int w
         L.s_dkey_b = take((size_t)n * 4);
         L.s_dval_b = take((size_t)n * 4);
         L.s_off_rank = take((size_t)n * 4);
-        L.s_dhist = take(((size_t)1 << radix_digit_bits(32)) * nb_n * 4);
+        L.s_dhist = take(((size_t)1 << radix_digit_bits(32)) * ((size_t)radix_max_blocks((uint32_t)n) + 1) * 4);
         L.s_ddtot = take(((size_t)1 << radix_digit_bits(32)) * 4);
     }
     L.s_bsum = take((size_t)(nb_n + 1) * 4);
@@ -159,7 +159,6 @@ Layout layout_of(const wipes_params* p, const wipes_batch* b, int64_t cap, int w
     L.s_descs = take((size_t)L.B * sizeof(ImgDesc));
     L.screen_bytes = o;
 
-    const int64_t nb_k = (cap + 4095) / 4096 + 1;
     const int64_t nb_t = (L.tiles + 4095) / 4096 + 1;
     // tile sort bits and where its result lands
     int bits = 0;
@@ -174,7 +173,7 @@ Layout layout_of(const wipes_params* p, const wipes_batch* b, int64_t cap, int w
     L.b_vals_a = take((size_t)cap * 4);
     L.b_keys_b = take((size_t)cap * 4);
     L.b_vals_b = take((size_t)cap * 4);
-    L.b_hist = take(nd_bins * std::max(nb_k, nb_t) * 4);
+    L.b_hist = take(nd_bins * std::max((int64_t)radix_max_blocks((uint32_t)cap) + 1, nb_t) * 4);
     L.b_dtot = take(nd_bins * 4);
     L.b_ranges = take((size_t)L.tiles * 8);
     L.b_order = take((size_t)L.tiles * 4);   // longest-first tile order

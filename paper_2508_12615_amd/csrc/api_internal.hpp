@@ -137,6 +137,7 @@ hipError_t scan_excl(const uint32_t* vals, const uint32_t* gather, uint32_t n_ho
                      uint32_t* n_eff, uint32_t* overflow, hipStream_t s, uint32_t* total_host = nullptr);
 int radix_passes(int nbits);
 int radix_digit_bits(int nbits);   // digit width of each pass of radix_sort
+uint32_t radix_max_blocks(uint32_t cap);   // histogram columns a sort of up to cap keys needs
 // Stable LSD sort of (key, value[, w]) over the low nbits of the keys; ping-pongs
 // between the *0 and *1 arrays, *result_in_1 tells where the result is.
 hipError_t radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, uint32_t n_host,

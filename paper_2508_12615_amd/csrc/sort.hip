@@ -11,6 +11,8 @@
 // Element counts may live in device memory (instance counts produced on the
 // device are never read back inside a captured graph); grids are sized by an
 // upper bound and surplus workgroups exit.
+#include <algorithm>
+
 #include "common.hpp"
 
 namespace wipes {
@@ -133,7 +135,7 @@ __global__ void __launch_bounds__(kBlock) k_scan_apply(const uint32_t* __restric
 // ------------------------------------------------------------ radix sort
 
 // hist[d * nblocks + b] = number of elements of tile b with digit d.
-template <int BITS>
+template <int BITS, int ITEMS>
 __global__ void __launch_bounds__(kBlock) k_radix_hist(const uint32_t* __restrict__ keys, uint32_t n_host,
                                                        const uint32_t* __restrict__ n_dev, int shift,
                                                        uint32_t nblocks, uint32_t* __restrict__ hist)
@@ -143,8 +145,8 @@ __global__ void __launch_bounds__(kBlock) k_radix_hist(const uint32_t* __restric
     for (int d = threadIdx.x; d < ND; d += kBlock) s_h[d] = 0;
     __syncthreads();
     const uint32_t n = load_n(n_host, n_dev);
-    const uint32_t base = blockIdx.x * kTile;
-    for (int j = 0; j < kItems; ++j) {
+    const uint32_t base = blockIdx.x * (uint32_t)(ITEMS * kBlock);
+    for (int j = 0; j < ITEMS; ++j) {
         const uint32_t i = base + j * kBlock + threadIdx.x;
         if (i < n) atomicAdd(&s_h[(keys[i] >> shift) & (ND - 1)], 1u);
     }
@@ -183,7 +185,7 @@ __global__ void __launch_bounds__(kBlock) k_radix_rowscan(uint32_t* __restrict__
 }
 
 // W: a second payload (w_in/w_out) is permuted with the values.
-template <int BITS, bool W>
+template <int BITS, bool W, int ITEMS>
 __global__ void __launch_bounds__(kBlock) k_radix_scatter(const uint32_t* __restrict__ keys_in,
                                                           const uint32_t* __restrict__ vals_in,
                                                           const uint32_t* __restrict__ w_in, uint32_t n_host,
@@ -196,32 +198,33 @@ __global__ void __launch_bounds__(kBlock) k_radix_scatter(const uint32_t* __rest
 {
     constexpr int ND = 1 << BITS;
     constexpr int NW = kBlock / kWave;
-    __shared__ uint32_t s_keys[kTile];
-    __shared__ uint32_t s_vals[kTile];
-    __shared__ uint32_t s_w[W ? kTile : 1];
+    constexpr int TILE = ITEMS * kBlock;
+    __shared__ uint32_t s_keys[TILE];
+    __shared__ uint32_t s_vals[TILE];
+    __shared__ uint32_t s_w[W ? TILE : 1];
     __shared__ uint32_t s_wcnt[NW][ND];
     __shared__ uint32_t s_dbase[ND];
     __shared__ uint32_t s_gbase[ND];
     __shared__ uint32_t s_part[2][NW];
 
     const uint32_t n = load_n(n_host, n_dev);
-    const uint32_t base = blockIdx.x * kTile;
+    const uint32_t base = blockIdx.x * TILE;
     if (base >= n) return;
     const int w = threadIdx.x / kWave, l = lane_id();
     for (int d = threadIdx.x; d < NW * ND; d += kBlock) (&s_wcnt[0][0])[d] = 0;
     __syncthreads();
 
-    const uint32_t wbase = base + (uint32_t)w * (kTile / NW);
+    const uint32_t wbase = base + (uint32_t)w * (TILE / NW);
     const uint64_t lt_mask = (l == 0) ? 0ull : (~0ull >> (64 - l));
-    uint32_t k[kItems], v[kItems], ww[W ? kItems : 1], rk[kItems];
-    for (int j = 0; j < kItems; ++j) {
+    uint32_t k[ITEMS], v[ITEMS], ww[W ? ITEMS : 1], rk[ITEMS];
+    for (int j = 0; j < ITEMS; ++j) {
         const uint32_t i = wbase + j * kWave + l;
         const bool ok = i < n;
         k[j] = ok ? keys_in[i] : 0u;
         v[j] = ok ? vals_in[i] : 0u;
         if (W) ww[j] = ok ? w_in[i] : 0u;
     }
-    for (int j = 0; j < kItems; ++j) {
+    for (int j = 0; j < ITEMS; ++j) {
         const uint32_t i = wbase + j * kWave + l;
         const bool ok = i < n;
         const uint32_t dig = (k[j] >> shift) & (ND - 1);
@@ -289,7 +292,7 @@ __global__ void __launch_bounds__(kBlock) k_radix_scatter(const uint32_t* __rest
         }
     }
     __syncthreads();
-    for (int j = 0; j < kItems; ++j) {
+    for (int j = 0; j < ITEMS; ++j) {
         const uint32_t i = wbase + j * kWave + l;
         if (i < n) {
             const uint32_t dig = (k[j] >> shift) & (ND - 1);
@@ -300,7 +303,7 @@ __global__ void __launch_bounds__(kBlock) k_radix_scatter(const uint32_t* __rest
         }
     }
     __syncthreads();
-    const uint32_t cnt = min((uint32_t)kTile, n - base);
+    const uint32_t cnt = min((uint32_t)TILE, n - base);
     for (uint32_t p = threadIdx.x; p < cnt; p += kBlock) {
         const uint32_t key = s_keys[p];
         const uint32_t dig = (key >> shift) & (ND - 1);
@@ -332,19 +335,47 @@ hipError_t scan_excl(const uint32_t* vals, const uint32_t* gather, uint32_t n_ho
     return hipGetLastError();
 }
 
+template <int BITS, int ITEMS>
+static void radix_pass_t(const uint32_t* ki, const uint32_t* vi, const uint32_t* wi, uint32_t* ko, uint32_t* vo,
+                         uint32_t* wo, uint32_t n_host, const uint32_t* n_dev, uint32_t nb, int shift, uint32_t* hist,
+                         uint32_t* dtot, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_radix_hist<BITS, ITEMS>), dim3(nb), dim3(kBlock), 0, s, ki, n_host, n_dev, shift, nb, hist);
+    hipLaunchKernelGGL(k_radix_rowscan, dim3(1 << BITS), dim3(kBlock), 0, s, hist, nb, dtot);
+    if (wi)
+        hipLaunchKernelGGL((k_radix_scatter<BITS, true, ITEMS>), dim3(nb), dim3(kBlock), 0, s, ki, vi, wi, n_host,
+                           n_dev, shift, nb, hist, dtot, ko, vo, wo);
+    else
+        hipLaunchKernelGGL((k_radix_scatter<BITS, false, ITEMS>), dim3(nb), dim3(kBlock), 0, s, ki, vi, nullptr,
+                           n_host, n_dev, shift, nb, hist, dtot, ko, vo, nullptr);
+}
+
+// Sorts of up to kSmallSort keys use 2048-key workgroups (8 keys per
+// thread): twice the workgroups of 4096-key ones, which a sort of ~1 M keys
+// needs to occupy the chip; larger sorts keep 4096 for longer runs of equal
+// digits in the scatter's stores.
+constexpr uint32_t kSmallSort = 1u << 21;
+uint32_t radix_tile(uint32_t max_n) { return max_n <= kSmallSort ? 8u * kBlock : (uint32_t)kTile; }
+
+// Workgroups of a radix sort of at most max_n keys (what its histograms hold).
+uint32_t radix_blocks(uint32_t max_n) { return (max_n + radix_tile(max_n) - 1u) / radix_tile(max_n); }
+
+// The most workgroups any sort of up to cap keys uses (the block count is not
+// monotonic in the key count where the tile size changes).
+uint32_t radix_max_blocks(uint32_t cap)
+{
+    return std::max(radix_blocks(cap), radix_blocks(std::min(cap, kSmallSort)));
+}
+
 template <int BITS>
 static void radix_pass(const uint32_t* ki, const uint32_t* vi, const uint32_t* wi, uint32_t* ko, uint32_t* vo,
                        uint32_t* wo, uint32_t n_host, const uint32_t* n_dev, uint32_t nb, int shift, uint32_t* hist,
-                       uint32_t* dtot, hipStream_t s)
+                       uint32_t* dtot, bool small, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_radix_hist<BITS>, dim3(nb), dim3(kBlock), 0, s, ki, n_host, n_dev, shift, nb, hist);
-    hipLaunchKernelGGL(k_radix_rowscan, dim3(1 << BITS), dim3(kBlock), 0, s, hist, nb, dtot);
-    if (wi)
-        hipLaunchKernelGGL((k_radix_scatter<BITS, true>), dim3(nb), dim3(kBlock), 0, s, ki, vi, wi, n_host, n_dev,
-                           shift, nb, hist, dtot, ko, vo, wo);
+    if (small)
+        radix_pass_t<BITS, 8>(ki, vi, wi, ko, vo, wo, n_host, n_dev, nb, shift, hist, dtot, s);
     else
-        hipLaunchKernelGGL((k_radix_scatter<BITS, false>), dim3(nb), dim3(kBlock), 0, s, ki, vi, nullptr, n_host,
-                           n_dev, shift, nb, hist, dtot, ko, vo, nullptr);
+        radix_pass_t<BITS, kItems>(ki, vi, wi, ko, vo, wo, n_host, n_dev, nb, shift, hist, dtot, s);
 }
 
 // Passes of at most 8-bit digits.  (Wider digits save passes but shorten the
@@ -364,21 +395,22 @@ hipError_t radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, ui
 {
     const int np = radix_passes(nbits);
     *result_in_1 = 0;
-    const uint32_t nb = scan_blocks(max_n);
+    const bool small = radix_tile(max_n) != (uint32_t)kTile;
+    const uint32_t nb = radix_blocks(max_n);
     if (np == 0 || nb == 0) return hipGetLastError();
     const int bits = radix_digit_bits(nbits);
     uint32_t *ki = k0, *vi = v0, *wi = w0, *ko = k1, *vo = v1, *wo = w1;
     for (int p = 0; p < np; ++p) {
         const int shift = p * bits;
         switch (bits) {
-        case 1: radix_pass<1>(ki, vi, wi, ko, vo, wo, n_host, n_dev, nb, shift, hist, dtot, s); break;
-        case 2: radix_pass<2>(ki, vi, wi, ko, vo, wo, n_host, n_dev, nb, shift, hist, dtot, s); break;
-        case 3: radix_pass<3>(ki, vi, wi, ko, vo, wo, n_host, n_dev, nb, shift, hist, dtot, s); break;
-        case 4: radix_pass<4>(ki, vi, wi, ko, vo, wo, n_host, n_dev, nb, shift, hist, dtot, s); break;
-        case 5: radix_pass<5>(ki, vi, wi, ko, vo, wo, n_host, n_dev, nb, shift, hist, dtot, s); break;
-        case 6: radix_pass<6>(ki, vi, wi, ko, vo, wo, n_host, n_dev, nb, shift, hist, dtot, s); break;
-        case 7: radix_pass<7>(ki, vi, wi, ko, vo, wo, n_host, n_dev, nb, shift, hist, dtot, s); break;
-        case 8: radix_pass<8>(ki, vi, wi, ko, vo, wo, n_host, n_dev, nb, shift, hist, dtot, s); break;
+        case 1: radix_pass<1>(ki, vi, wi, ko, vo, wo, n_host, n_dev, nb, shift, hist, dtot, small, s); break;
+        case 2: radix_pass<2>(ki, vi, wi, ko, vo, wo, n_host, n_dev, nb, shift, hist, dtot, small, s); break;
+        case 3: radix_pass<3>(ki, vi, wi, ko, vo, wo, n_host, n_dev, nb, shift, hist, dtot, small, s); break;
+        case 4: radix_pass<4>(ki, vi, wi, ko, vo, wo, n_host, n_dev, nb, shift, hist, dtot, small, s); break;
+        case 5: radix_pass<5>(ki, vi, wi, ko, vo, wo, n_host, n_dev, nb, shift, hist, dtot, small, s); break;
+        case 6: radix_pass<6>(ki, vi, wi, ko, vo, wo, n_host, n_dev, nb, shift, hist, dtot, small, s); break;
+        case 7: radix_pass<7>(ki, vi, wi, ko, vo, wo, n_host, n_dev, nb, shift, hist, dtot, small, s); break;
+        case 8: radix_pass<8>(ki, vi, wi, ko, vo, wo, n_host, n_dev, nb, shift, hist, dtot, small, s); break;
         default: return hipErrorInvalidValue;
         }
         uint32_t* t;
