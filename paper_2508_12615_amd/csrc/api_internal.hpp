@@ -122,8 +122,8 @@ hipError_t launch_project(const ImgDesc* descs, int B, int32_t n_total, const KP
 hipError_t launch_bin_count(const ImgDesc* descs, int B, int32_t n_total, const KParams& kp, Rec* recs,
                             const void* aux, uint32_t* count, PrimPack* pk, uint32_t* dkey, uint32_t* dval,
                             hipStream_t s);
-hipError_t launch_rank_pack(int32_t n_total, const uint32_t* order, const PrimPack* pk, const uint32_t* off_id,
-                            PrimPack* pkr, uint32_t* cnt_r, hipStream_t s);
+hipError_t launch_rank_pack(int32_t n_total, const uint32_t* order, const PrimPack* pk, PrimPack* pkr,
+                            uint32_t* cnt_r, hipStream_t s);
 hipError_t launch_emit(const ImgDesc* descs, int B, int32_t n_total, const KParams& kp, const PrimPack* pkx,
                        const uint32_t* order, const uint32_t* offs, const uint32_t* n_eff, uint32_t* keys,
                        uint32_t* vals, uint32_t* eidx, hipStream_t s);
@@ -134,7 +134,8 @@ hipError_t launch_ranges(const uint32_t* keys, const uint32_t* n_eff, uint32_t m
 uint32_t scan_blocks(uint32_t max_n);
 hipError_t scan_excl(const uint32_t* vals, const uint32_t* gather, uint32_t n_host, const uint32_t* n_dev,
                      uint32_t max_n, uint32_t* block_sums, uint32_t* out, uint32_t* total, uint32_t cap,
-                     uint32_t* n_eff, uint32_t* overflow, hipStream_t s, uint32_t* total_host = nullptr);
+                     uint32_t* n_eff, uint32_t* overflow, hipStream_t s, uint32_t* total_host = nullptr,
+                     uint32_t* out2 = nullptr, uint32_t stride2 = 0);   // out2[i * stride2] = out[i] too
 int radix_passes(int nbits);
 int radix_digit_bits(int nbits);   // digit width of each pass of radix_sort
 uint32_t radix_max_blocks(uint32_t cap);   // histogram columns a sort of up to cap keys needs

@@ -197,14 +197,11 @@ __device__ __forceinline__ uint32_t nth_set_bit(uint64_t m, uint32_t k)
 // gather here lets the rank scan and the emission read coalesced.
 __global__ void __launch_bounds__(256) k_rank_pack(int32_t n_total, const uint32_t* __restrict__ order,
                                                     const PrimPack* __restrict__ pk,
-                                                    const uint32_t* __restrict__ off_id,
                                                     PrimPack* __restrict__ pkr, uint32_t* __restrict__ cnt_r)
 {
     const int32_t r = (int32_t)(blockIdx.x * 256u + threadIdx.x);
     if (r >= n_total) return;
-    const uint32_t prim = order[r];
-    PrimPack q = pk[prim];
-    q.base = off_id[prim];
+    const PrimPack q = pk[order[r]];   // its slot base was filled in by the count scan
     pkr[r] = q;
     cnt_r[r] = q.count;
 }
@@ -374,12 +371,12 @@ hipError_t launch_bin_count(const ImgDesc* descs, int B, int32_t n_total, const 
     return hipGetLastError();
 }
 
-hipError_t launch_rank_pack(int32_t n_total, const uint32_t* order, const PrimPack* pk, const uint32_t* off_id,
-                            PrimPack* pkr, uint32_t* cnt_r, hipStream_t s)
+hipError_t launch_rank_pack(int32_t n_total, const uint32_t* order, const PrimPack* pk, PrimPack* pkr,
+                            uint32_t* cnt_r, hipStream_t s)
 {
     if (n_total > 0)
         hipLaunchKernelGGL(k_rank_pack, dim3(blocks_of((uint32_t)n_total)), dim3(256), 0, s, n_total, order, pk,
-                           off_id, pkr, cnt_r);
+                           pkr, cnt_r);
     return hipGetLastError();
 }
 

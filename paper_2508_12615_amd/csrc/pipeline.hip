@@ -105,8 +105,11 @@ wipes_status bin_sort_core(wipes_ctx* ctx, const wipes_params* p, const wipes_ba
         // the scan also stores K into the pinned host word when the caller
         // wants it; the host waits for it only before the emission, so the
         // round trip overlaps the depth sort
+        // (alpha: the offsets also go into the packs' slot base, so the rank
+        // pack gathers one record per primitive, not two)
         HIP_TRY(scan_excl(v.count, nullptr, n, nullptr, n, v.bsum, v.off_id, v.ctrl + kCtrlK, (uint32_t)L.cap,
-                          v.ctrl + kCtrlNEff, v.ctrl + kCtrlOverflow, s, n_instances_out ? ctx->k_host_dev : nullptr),
+                          v.ctrl + kCtrlNEff, v.ctrl + kCtrlOverflow, s, n_instances_out ? ctx->k_host_dev : nullptr,
+                          L.alpha ? &v.pk->base : nullptr, (uint32_t)(sizeof(PrimPack) / 4)),
                 "scan");
     }
     if (n_instances_out) HIP_TRY(hipEventRecord(ctx->k_ev, s), "read K event");
@@ -122,7 +125,7 @@ wipes_status bin_sort_core(wipes_ctx* ctx, const wipes_params* p, const wipes_ba
         order = in_b ? v.dval_b : v.dval_a;
         {
             StageScope sc(ctx, kStRankScan, s);
-            HIP_TRY(launch_rank_pack((int32_t)n, order, v.pk, v.off_id, v.pkr, v.cnt_r, s), "rank pack");
+            HIP_TRY(launch_rank_pack((int32_t)n, order, v.pk, v.pkr, v.cnt_r, s), "rank pack");
             HIP_TRY(scan_excl(v.cnt_r, nullptr, n, nullptr, n, v.bsum2, v.off_rank, v.ctrl + 3, 0, nullptr, nullptr,
                               s),
                     "rank scan");

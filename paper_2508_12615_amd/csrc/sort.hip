@@ -103,7 +103,8 @@ __global__ void __launch_bounds__(kBlock) k_scan_apply(const uint32_t* __restric
                                                        const uint32_t* __restrict__ gather, uint32_t n_host,
                                                        const uint32_t* __restrict__ n_dev,
                                                        const uint32_t* __restrict__ block_sums,
-                                                       uint32_t* __restrict__ out)
+                                                       uint32_t* __restrict__ out, uint32_t* __restrict__ out2,
+                                                       uint32_t stride2)
 {
     __shared__ uint32_t s_w[kBlock / kWave];
     const uint32_t n = load_n(n_host, n_dev);
@@ -127,7 +128,10 @@ __global__ void __launch_bounds__(kBlock) k_scan_apply(const uint32_t* __restric
         uint32_t t;
         const uint32_t ex = wave_excl_scan_u32(v[j], &t);
         const uint32_t i = wbase + j * kWave + l;
-        if (i < n) out[i] = run + ex;
+        if (i < n) {
+            out[i] = run + ex;
+            if (out2) out2[(size_t)i * stride2] = run + ex;
+        }
         run += t;
     }
 }
@@ -320,7 +324,8 @@ uint32_t scan_blocks(uint32_t max_n) { return (max_n + kTile - 1) / kTile; }
 
 hipError_t scan_excl(const uint32_t* vals, const uint32_t* gather, uint32_t n_host, const uint32_t* n_dev,
                      uint32_t max_n, uint32_t* block_sums, uint32_t* out, uint32_t* total, uint32_t cap,
-                     uint32_t* n_eff, uint32_t* overflow, hipStream_t s, uint32_t* total_host)
+                     uint32_t* n_eff, uint32_t* overflow, hipStream_t s, uint32_t* total_host, uint32_t* out2,
+                     uint32_t stride2)
 {
     const uint32_t nb = scan_blocks(max_n);
     if (nb > 0) {
@@ -330,7 +335,7 @@ hipError_t scan_excl(const uint32_t* vals, const uint32_t* gather, uint32_t n_ho
                        total_host);
     if (nb > 0) {
         hipLaunchKernelGGL(k_scan_apply, dim3(nb), dim3(kBlock), 0, s, vals, gather, n_host, n_dev, block_sums,
-                           out);
+                           out, out2, stride2);
     }
     return hipGetLastError();
 }
