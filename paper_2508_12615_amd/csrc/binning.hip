@@ -320,7 +320,18 @@ __global__ void __launch_bounds__(1024) k_tile_lpt_order(const uint2* __restrict
     __shared__ uint32_t s_cnt[256];
     if (threadIdx.x < 256) s_cnt[threadIdx.x] = 0u;
     __syncthreads();
-    for (uint32_t t = threadIdx.x; t < n_tiles; t += 1024u) atomicAdd(&s_cnt[lpt_key(ranges[t])], 1u);
+    // The key of empty tiles (255; half the tiles of a typical frame) is
+    // counted and placed once per wave rather than once per lane: per-lane
+    // LDS atomics on one address serialise.
+    const int l = lane_id();
+    const uint64_t lt = (l == 0) ? 0ull : (~0ull >> (64 - l));
+    const uint32_t n_pad = (n_tiles + 1023u) & ~1023u;   // every lane of a wave runs each round
+    for (uint32_t t = threadIdx.x; t < n_pad; t += 1024u) {
+        const uint32_t key = t < n_tiles ? lpt_key(ranges[t]) : 0u;
+        const uint64_t low = __ballot(t < n_tiles && key == 255u);
+        if (t < n_tiles && key != 255u) atomicAdd(&s_cnt[key], 1u);
+        if (low && l == 0) atomicAdd(&s_cnt[255], (uint32_t)__popcll(low));
+    }
     __syncthreads();
     if (threadIdx.x < kWave) {   // exclusive scan of the 256 counts, four per lane
         const uint32_t l = threadIdx.x;
@@ -338,7 +349,14 @@ __global__ void __launch_bounds__(1024) k_tile_lpt_order(const uint2* __restrict
         }
     }
     __syncthreads();
-    for (uint32_t t = threadIdx.x; t < n_tiles; t += 1024u) order[atomicAdd(&s_cnt[lpt_key(ranges[t])], 1u)] = t;
+    for (uint32_t t = threadIdx.x; t < n_pad; t += 1024u) {
+        const uint32_t key = t < n_tiles ? lpt_key(ranges[t]) : 0u;
+        const uint64_t low = __ballot(t < n_tiles && key == 255u);
+        uint32_t at = 0u;
+        if (low && l == 0) at = atomicAdd(&s_cnt[255], (uint32_t)__popcll(low));
+        at = (uint32_t)__shfl((int)at, 0, kWave);
+        if (t < n_tiles) order[key == 255u ? at + (uint32_t)__popcll(low & lt) : atomicAdd(&s_cnt[key], 1u)] = t;
+    }
 }
 
 // Fill kernel (used instead of memset so the sequence can live in a graph).
