@@ -280,7 +280,9 @@ __global__ void __launch_bounds__(256) k_emit(const ImgDesc* __restrict__ descs,
         // position in the tile rectangle: the local-th kept tile
         const uint32_t at = s_full[w][j] ? local
                                          : nth_set_bit(((uint64_t)s_mhi[w][j] << 32) | s_mlo[w][j], local);
-        uint32_t dy = (uint32_t)((float)at / (float)wj);   // corrected to the exact quotient below
+        // approximate quotient (off by at most one while it is below 2^22),
+        // corrected to the exact one below
+        uint32_t dy = (uint32_t)((float)at * __builtin_amdgcn_rcpf((float)wj));
         if (dy * wj > at) --dy;
         else if ((dy + 1u) * wj <= at) ++dy;
         const uint32_t dx = at - dy * wj;
@@ -317,45 +319,64 @@ __device__ __forceinline__ uint32_t lpt_key(uint2 r)
 __global__ void __launch_bounds__(1024) k_tile_lpt_order(const uint2* __restrict__ ranges, uint32_t n_tiles,
                                                          uint32_t* __restrict__ order)
 {
+    // Each thread takes kLptPer tiles a round, their range loads issued
+    // together, so a round costs one memory latency for 8192 tiles.  The key
+    // of empty tiles (255; half the tiles of a typical frame) is counted and
+    // placed once per wave rather than once per lane: per-lane LDS atomics on
+    // one address serialise.
+    constexpr uint32_t kLptPer = 8, kRound = 1024u * kLptPer;
     __shared__ uint32_t s_cnt[256];
     if (threadIdx.x < 256) s_cnt[threadIdx.x] = 0u;
     __syncthreads();
-    // The key of empty tiles (255; half the tiles of a typical frame) is
-    // counted and placed once per wave rather than once per lane: per-lane
-    // LDS atomics on one address serialise.
     const int l = lane_id();
     const uint64_t lt = (l == 0) ? 0ull : (~0ull >> (64 - l));
-    const uint32_t n_pad = (n_tiles + 1023u) & ~1023u;   // every lane of a wave runs each round
-    for (uint32_t t = threadIdx.x; t < n_pad; t += 1024u) {
-        const uint32_t key = t < n_tiles ? lpt_key(ranges[t]) : 0u;
-        const uint64_t low = __ballot(t < n_tiles && key == 255u);
-        if (t < n_tiles && key != 255u) atomicAdd(&s_cnt[key], 1u);
-        if (low && l == 0) atomicAdd(&s_cnt[255], (uint32_t)__popcll(low));
+    auto keys_of = [&](uint32_t t0, uint32_t* key) {
+#pragma unroll
+        for (uint32_t k = 0; k < kLptPer; ++k) {
+            const uint32_t t = t0 + k * 1024u + threadIdx.x;
+            key[k] = t < n_tiles ? lpt_key(ranges[t]) : 0u;
+        }
+    };
+    for (uint32_t t0 = 0; t0 < n_tiles; t0 += kRound) {
+        uint32_t key[kLptPer];
+        keys_of(t0, key);
+#pragma unroll
+        for (uint32_t k = 0; k < kLptPer; ++k) {
+            const bool in = t0 + k * 1024u + threadIdx.x < n_tiles;
+            const uint64_t low = __ballot(in && key[k] == 255u);
+            if (in && key[k] != 255u) atomicAdd(&s_cnt[key[k]], 1u);
+            if (low && l == 0) atomicAdd(&s_cnt[255], (uint32_t)__popcll(low));
+        }
     }
     __syncthreads();
     if (threadIdx.x < kWave) {   // exclusive scan of the 256 counts, four per lane
-        const uint32_t l = threadIdx.x;
         uint32_t c[4], sum = 0u, tot;
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            c[k] = s_cnt[4u * l + k];
+            c[k] = s_cnt[4u * (uint32_t)l + k];
             sum += c[k];
         }
         uint32_t ex = wave_excl_scan_u32(sum, &tot);
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            s_cnt[4u * l + k] = ex;
+            s_cnt[4u * (uint32_t)l + k] = ex;
             ex += c[k];
         }
     }
     __syncthreads();
-    for (uint32_t t = threadIdx.x; t < n_pad; t += 1024u) {
-        const uint32_t key = t < n_tiles ? lpt_key(ranges[t]) : 0u;
-        const uint64_t low = __ballot(t < n_tiles && key == 255u);
-        uint32_t at = 0u;
-        if (low && l == 0) at = atomicAdd(&s_cnt[255], (uint32_t)__popcll(low));
-        at = (uint32_t)__shfl((int)at, 0, kWave);
-        if (t < n_tiles) order[key == 255u ? at + (uint32_t)__popcll(low & lt) : atomicAdd(&s_cnt[key], 1u)] = t;
+    for (uint32_t t0 = 0; t0 < n_tiles; t0 += kRound) {
+        uint32_t key[kLptPer];
+        keys_of(t0, key);
+#pragma unroll
+        for (uint32_t k = 0; k < kLptPer; ++k) {
+            const uint32_t t = t0 + k * 1024u + threadIdx.x;
+            const bool in = t < n_tiles;
+            const uint64_t low = __ballot(in && key[k] == 255u);
+            uint32_t at = 0u;
+            if (low && l == 0) at = atomicAdd(&s_cnt[255], (uint32_t)__popcll(low));
+            at = (uint32_t)__shfl((int)at, 0, kWave);
+            if (in) order[key[k] == 255u ? at + (uint32_t)__popcll(low & lt) : atomicAdd(&s_cnt[key[k]], 1u)] = t;
+        }
     }
 }
 
