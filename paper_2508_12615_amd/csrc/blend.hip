@@ -543,25 +543,31 @@ __device__ __forceinline__ int reduce12_index(int l)
 
 // ------------------------------------------------------------ backward
 
-// Gradient slot layout per instance: 12 floats, the first 11 used, in the
-// order d/d(mu'x, mu'y, ca, cb, cc, f'x, f'y, opacity, r, g, b).
+// Gradient slot layout per instance: 12 floats, sums over the pixels of the
+// tile of (dq dx, dq dy, dq dx^2, dq dx dy, dq dy^2, dphi dx, dphi dy,
+// dL/do, dL/dr, dL/dg, dL/db, dphi), with dq = dL/dq, dphi = dL/dphi and
+// (dx, dy) the pixel's offset from the mean.  The gradients with respect to
+// mu', the conic and f' are linear in these sums with the primitive's own
+// conic and f' as coefficients (dL/dmu'x = -2 (ca S_qx + cb S_qy) - f'x S_phi,
+// dL/dcb = 2 S_qxy, ...), so the projection backward applies them once per
+// primitive instead of every pair paying for them.
 constexpr int kSlot = 12;
 
 // Per-pair gradient terms shared by both modes: dW = dL/dW' of the pair.
-__device__ __forceinline__ void pair_grads(float v[12], const PairEval& p, float dW, float ca, float cb, float cc,
-                                           float fx, float fy)
+__device__ __forceinline__ void pair_grads(float v[12], const PairEval& p, float dW)
 {
     const float sn = __builtin_amdgcn_sinf(__builtin_amdgcn_fractf(p.ph));
     const float dq = dW * (-0.5f * p.W);             // dL/dq
     const float dph = dW * (-0.5f * p.E * sn);       // dL/dphi (radians)
-    const float Adx = fmaf(ca, p.dx, cb * p.dy), Ady = fmaf(cb, p.dx, cc * p.dy);
-    v[0] = fmaf(-2.0f * dq, Adx, fmaf(-dph, fx, v[0]));
-    v[1] = fmaf(-2.0f * dq, Ady, fmaf(-dph, fy, v[1]));
-    v[2] = fmaf(dq * p.dx, p.dx, v[2]);
-    v[3] = fmaf(2.0f * dq * p.dx, p.dy, v[3]);
-    v[4] = fmaf(dq * p.dy, p.dy, v[4]);
-    v[5] = fmaf(dph, p.dx, v[5]);
-    v[6] = fmaf(dph, p.dy, v[6]);
+    const float qx = dq * p.dx, qy = dq * p.dy;
+    v[0] = qx;
+    v[1] = qy;
+    v[2] = qx * p.dx;
+    v[3] = qx * p.dy;
+    v[4] = qy * p.dy;
+    v[5] = dph * p.dx;
+    v[6] = dph * p.dy;
+    v[11] = dph;
 }
 
 // Backward of tile t by the whole workgroup (wave w = block w).  The waves
@@ -715,7 +721,7 @@ __device__ __forceinline__ void bwd_tile(const ImgDesc* __restrict__ descs, int 
                 v[7] = p.W * da;
                 dW = S.op * da;
             }
-            pair_grads(v, p, dW, S.c0, S.c1, S.c2, S.f0, S.f1);
+            pair_grads(v, p, dW);
             const bool any = __ballot(takes) != 0ull;
             float* o = mine + (S.pos & 63u) * kSlot;
             if (any) {

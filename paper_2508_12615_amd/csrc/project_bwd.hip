@@ -56,9 +56,9 @@ __global__ void __launch_bounds__(256) k_project_bwd(const ImgDesc* __restrict__
     const uint32_t first = (uint32_t)__builtin_amdgcn_readfirstlane((int)base);   // lane 0 is in range
     const uint32_t total = wave_sum_u32(c);
     const uint32_t my0 = base - first, my1 = my0 + c;
-    float acc[11];
+    float acc[12];
 #pragma unroll
-    for (int k = 0; k < 11; ++k) acc[k] = 0.0f;
+    for (int k = 0; k < 12; ++k) acc[k] = 0.0f;
     const uint32_t wlast = total ? (first + total - 1u) >> 5 : 0u;
     uint32_t wbase = first >> 5;
     uint32_t vword = (total && wbase + (uint32_t)l <= wlast) ? valid[wbase + (uint32_t)l] : 0u;
@@ -95,7 +95,7 @@ __global__ void __launch_bounds__(256) k_project_bwd(const ImgDesc* __restrict__
             const float4 x0 = s_slot[wv][e - k0][0], x1 = s_slot[wv][e - k0][1], x2 = s_slot[wv][e - k0][2];
             acc[0] += x0.x; acc[1] += x0.y; acc[2] += x0.z; acc[3] += x0.w;
             acc[4] += x1.x; acc[5] += x1.y; acc[6] += x1.z; acc[7] += x1.w;
-            acc[8] += x2.x; acc[9] += x2.y; acc[10] += x2.z;
+            acc[8] += x2.x; acc[9] += x2.y; acc[10] += x2.z; acc[11] += x2.w;
         }
         wave_lds_sync();   // the stage is rewritten next
         a0 = b0;
@@ -103,6 +103,18 @@ __global__ void __launch_bounds__(256) k_project_bwd(const ImgDesc* __restrict__
         a2 = b2;
     }
     if (!inr) return;
+    // The slots hold sums of (dq dx, dq dy, dq dx^2, dq dx dy, dq dy^2,
+    // dphi dx, dphi dy, opacity, colour, dphi) over the primitive's pixels:
+    // with its conic and f' they give d/d(mu', conic, f') (q = ca dx^2 +
+    // 2 cb dx dy + cc dy^2 and phi = f' . (x - mu')).  A primitive with no
+    // instance keeps all-zero sums (its record need not be finite).
+    if (c) {
+        const Rec& R0 = recs[i];
+        const float sqx = acc[0], sqy = acc[1], sph = acc[11];
+        acc[0] = -2.0f * (R0.ca * sqx + R0.cb * sqy) - R0.fx * sph;
+        acc[1] = -2.0f * (R0.cb * sqx + R0.cc * sqy) - R0.fy * sph;
+        acc[3] = 2.0f * acc[3];
+    }
     const ImgDesc& d = descs[image_of_prim(descs, B, i)];
     const int32_t j = i - d.prim_begin;
     if (dscreen) {
