@@ -28,7 +28,7 @@ METRIC = "fwd+bwd frames/s @1080p,1M prims; served p50/p99 ms vs plain rasterize
 
 # Algorithmic FP32 VALU operations per support pair, from the per-pixel rule
 # ("Roofline accounting"); transcendentals counted separately.
-ALU_PER_PAIR = {("alpha", "fwd"): 22, ("alpha", "bwd"): 52, ("add", "fwd"): 16, ("add", "bwd"): 44}
+ALU_PER_PAIR = {("alpha", "fwd"): 22, ("alpha", "bwd"): 43, ("add", "fwd"): 16, ("add", "bwd"): 35}
 TRANS_PER_PAIR = {("alpha", "fwd"): 2, ("alpha", "bwd"): 4, ("add", "fwd"): 2, ("add", "bwd"): 3}
 # MI355X: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz = 39.3e12 FP32 lane-ops/s (packed FP32 is not used);
 # a transcendental occupies TRANS_SLOTS issue slots (quarter rate on CDNA).
