@@ -678,10 +678,7 @@ __device__ __forceinline__ void bwd_tile(const ImgDesc* __restrict__ descs, int 
         if (l == 0) hitm[w] = m;
         wave_lds_sync();
         const int nh = __popcll(m);
-        Staged Sn = st[nh > 0 ? nh - 1 : 0];   // the next staged primitive is read while the current one replays
-        for (int j = nh - 1; j >= 0; --j) {
-            const Staged S = Sn;
-            Sn = st[j > 0 ? j - 1 : 0];
+        auto replay = [&](const Staged& S) {
             // branch-free: a pair that takes no part gets zero weight, for which
             // every update is an exact identity and every gradient term is zero
             float v[12];
@@ -730,6 +727,16 @@ __device__ __forceinline__ void bwd_tile(const ImgDesc* __restrict__ descs, int 
             } else if (l < kSlot) {
                 o[l] = 0.0f;
             }
+        };
+        // back to front, two records a round in alternating registers: each
+        // is read from the stage one replay ahead, without register copies
+        Staged Sa = st[nh > 0 ? nh - 1 : 0];
+        for (int j = nh - 1; j >= 0; j -= 2) {
+            const Staged Sb = st[j > 0 ? j - 1 : 0];
+            replay(Sa);
+            if (j == 0) break;
+            Sa = st[j > 1 ? j - 2 : 0];
+            replay(Sb);
         }
         __syncthreads();
         // positions some block staged get their slot written and marked
