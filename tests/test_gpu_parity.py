@@ -88,6 +88,8 @@ def test_project_3d():
     (B.WIPES_2D_ADDITIVE, 32, 16, 7000, 4),
     (B.WIPES_3D_ALPHA, 16, 8, 1, 5),
     (B.WIPES_2D_ADDITIVE, 8, 16, 0, 6),
+    # more than 2^21 primitives: the depth sort switches to 4096-key workgroups
+    (B.WIPES_3D_ALPHA, 16, 16, 2_200_000, 7),
 ])
 def test_bin_sort_bit_exact(mode, tw, th, n, seed):
     """Given the same FP32 records, boxes, instance keys, sorted order and ranges match O-bin."""
@@ -335,6 +337,45 @@ def test_batched_equals_single(mode, launch):
         assert torch.equal(f1.image, fb.image[o:o + npx[i]]), i
         if mode == B.WIPES_3D_ALPHA:
             assert torch.equal(f1.T_final, fb.T_final[o:o + npx[i]]), i
+        for k in g1:
+            assert torch.equal(g1[k], gb[i][k]), (i, k)
+        o += npx[i]
+
+
+def test_longest_first_order_over_many_tiles():
+    """16000 tiles (more than one round of the one-workgroup longest-first ordering): the
+    longest-first queue gives the grid launch's images and gradients bit for bit."""
+    W, H = 1280, 800
+    prims = to_torch(synth.prims_2d(20000, W, H, 81))
+    g = torch.from_numpy(np.random.default_rng(11).normal(0, 1, (W * H, 3)).astype(np.float32)).cuda()
+    outs = []
+    for persistent in (0, 2):
+        r = Rasterizer(B.WIPES_2D_ADDITIVE, tile_w=8, tile_h=8, persistent=persistent)
+        f = r.forward([dict(camera=(W, H), prims=prims)], with_backward=True)
+        gr = r.backward([dict(camera=(W, H), prims=prims)], f, g)[0]
+        outs.append((f.image.cpu(), {k: v.cpu() for k, v in gr.items()}))
+    assert torch.equal(outs[0][0], outs[1][0])
+    for k in outs[0][1]:
+        assert torch.equal(outs[0][1][k], outs[1][1][k]), k
+
+
+def test_batched_more_than_eight_images():
+    """Ten images in one call (the descriptor table then goes through the pinned staging ring,
+    not a kernel argument) give, bit for bit, the images and gradients of each alone."""
+    imgs, npx = [], []
+    for i in range(10):
+        W, H = 40 + 7 * i, 30 + 5 * i
+        imgs.append(dict(camera=(W, H), prims=to_torch(synth.prims_2d(150 + 20 * i, W, H, 90 + i))))
+        npx.append(W * H)
+    g = torch.from_numpy(np.random.default_rng(12).normal(0, 1, (sum(npx), 3)).astype(np.float32)).cuda()
+    r = Rasterizer(B.WIPES_2D_ADDITIVE, persistent=2)
+    fb = r.forward(imgs, with_backward=True)
+    gb = r.backward(imgs, fb, g)
+    o = 0
+    for i, im in enumerate(imgs):
+        f1 = r.forward([im], with_backward=True)
+        g1 = r.backward([im], f1, g[o:o + npx[i]].contiguous())[0]
+        assert torch.equal(f1.image, fb.image[o:o + npx[i]]), i
         for k in g1:
             assert torch.equal(g1[k], gb[i][k]), (i, k)
         o += npx[i]
