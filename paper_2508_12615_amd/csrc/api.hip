@@ -179,8 +179,6 @@ Layout layout_of(const wipes_params* p, const wipes_batch* b, int64_t cap, int w
     L.b_order = take((size_t)L.tiles * 4);   // longest-first tile order
     L.b_tbsum = take((size_t)(nb_t + 1) * 4);
     if (with_bwd) {
-        L.b_w_a = take((size_t)cap * 4);
-        L.b_w_b = take((size_t)cap * 4);
         L.b_slots = take((size_t)cap * 48);
         // contribution mask: (tile_w/8)(tile_h/8) block rows of cap/64 + 2 words
         L.cmask_words = (uint32_t)(cap / 64 + 2);

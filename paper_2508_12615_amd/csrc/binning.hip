@@ -209,11 +209,9 @@ __global__ void __launch_bounds__(256) k_rank_pack(int32_t n_total, const uint32
 // Writes the instances of the primitive of rank r at offs[r]..: key = global
 // tile, value = primitive, tiles of the pixel box row-major.  Ranks are
 // primitive indices (order == NULL; pkx = per-primitive pack, offs = off_id)
-// or depth ranks (pkx = per-rank pack, prim = order[r]).  With eidx set, also
-// each instance's index in primitive-index emission order, slot base +
-// (position in the tile rectangle): the slot the backward writes that
-// instance's gradients to, so the projection backward reads each primitive's
-// slots contiguously.
+// or depth ranks (pkx = per-rank pack, prim = order[r]).  (An instance's
+// gradient slot is its primitive's slot base plus the rank of its tile among
+// the primitive's kept tiles; the backward derives it from the pack.)
 //
 // A wave owns 64 consecutive ranks, whose instances form one contiguous run;
 // it walks that run 64 entries at a time and each lane finds its entry's
@@ -224,15 +222,15 @@ __global__ void __launch_bounds__(256) k_emit(const ImgDesc* __restrict__ descs,
                                                const uint32_t* __restrict__ order,
                                                const uint32_t* __restrict__ offs,
                                                const uint32_t* __restrict__ n_eff, uint32_t* __restrict__ keys,
-                                               uint32_t* __restrict__ vals, uint32_t* __restrict__ eidx)
+                                               uint32_t* __restrict__ vals)
 {
     __shared__ uint32_t s_start[4][kWave], s_prim[4][kWave], s_base[4][kWave], s_tx[4][kWave], s_w[4][kWave],
-        s_e0[4][kWave], s_mlo[4][kWave], s_mhi[4][kWave], s_full[4][kWave];
+        s_mlo[4][kWave], s_mhi[4][kWave], s_full[4][kWave];
     const int w = (int)(threadIdx.x >> 6), l = lane_id();
     const int32_t r0 = (int32_t)(blockIdx.x * 256u + (uint32_t)w * kWave);   // rank of lane 0
     if (r0 >= n_total || *n_eff == 0u) return;   // wave-uniform
     const int32_t r = r0 + l;
-    uint32_t c = 0, prim = 0, base = 0, tilesx = 1, wd = 1, e0 = 0, off = 0xffffffffu, mlo = 0, mhi = 0, full = 1;
+    uint32_t c = 0, prim = 0, base = 0, tilesx = 1, wd = 1, off = 0xffffffffu, mlo = 0, mhi = 0, full = 1;
     if (r < n_total) {
         const PrimPack q = pkx[r];
         prim = order ? order[r] : (uint32_t)r;
@@ -245,7 +243,6 @@ __global__ void __launch_bounds__(256) k_emit(const ImgDesc* __restrict__ descs,
             wd = (uint32_t)(tx1 - tx0 + 1);
             tilesx = (uint32_t)d.tiles_x;
             base = (uint32_t)(d.tile_begin + ty0 * d.tiles_x + tx0);
-            e0 = order ? q.base : off;
             mlo = q.mlo;
             mhi = q.mhi;
             full = q.full;
@@ -259,7 +256,6 @@ __global__ void __launch_bounds__(256) k_emit(const ImgDesc* __restrict__ descs,
     s_base[w][l] = base;
     s_tx[w][l] = tilesx;
     s_w[w][l] = wd;
-    s_e0[w][l] = e0;
     s_mlo[w][l] = mlo;
     s_mhi[w][l] = mhi;
     s_full[w][l] = full;
@@ -289,7 +285,6 @@ __global__ void __launch_bounds__(256) k_emit(const ImgDesc* __restrict__ descs,
         const uint32_t o = first + k;
         keys[o] = s_base[w][j] + dy * s_tx[w][j] + dx;
         vals[o] = s_prim[w][j];
-        if (eidx) eidx[o] = s_e0[w][j] + local;
     }
 }
 
@@ -421,11 +416,11 @@ hipError_t launch_rank_pack(int32_t n_total, const uint32_t* order, const PrimPa
 
 hipError_t launch_emit(const ImgDesc* descs, int B, int32_t n_total, const KParams& kp, const PrimPack* pkx,
                        const uint32_t* order, const uint32_t* offs, const uint32_t* n_eff, uint32_t* keys,
-                       uint32_t* vals, uint32_t* eidx, hipStream_t s)
+                       uint32_t* vals, hipStream_t s)
 {
     if (n_total > 0)
         hipLaunchKernelGGL(k_emit, dim3(blocks_of((uint32_t)n_total)), dim3(256), 0, s, descs, B, n_total, kp, pkx,
-                           order, offs, n_eff, keys, vals, eidx);
+                           order, offs, n_eff, keys, vals);
     return hipGetLastError();
 }
 

@@ -570,6 +570,20 @@ __device__ __forceinline__ void pair_grads(float v[12], const PairEval& p, float
     v[11] = dph;
 }
 
+// Gradient slot of an instance -- primitive with pack q on tile (tx, ty) of
+// its image: the primitive's slot base plus the rank of the tile among the
+// primitive's kept tiles, row-major over its tile rectangle, which is the
+// order the emission numbers them in.
+template <int TW, int TH>
+__device__ __forceinline__ uint32_t slot_of(const PrimPack& q, int tx, int ty)
+{
+    const int tx0 = lo16(q.box0) / TW, ty0 = hi16(q.box0) / TH, tx1 = lo16(q.box1) / TW;
+    const uint32_t k = (uint32_t)((ty - ty0) * (tx1 - tx0 + 1) + (tx - tx0));
+    if (q.full) return q.base + k;
+    const uint64_t mask = ((uint64_t)q.mhi << 32) | q.mlo;
+    return q.base + (uint32_t)__popcll(mask & ((1ull << k) - 1ull));   // k < 64 for a culled rectangle
+}
+
 // Backward of tile t by the whole workgroup (wave w = block w).  The waves
 // walk the tile's list in the same chunks of 64 positions, top down from the
 // tile's last contributing position (alpha; the list end for additive); each
@@ -581,7 +595,7 @@ __device__ __forceinline__ void pair_grads(float v[12], const PairEval& p, float
 template <int MODE, int TW, int TH>
 __device__ __forceinline__ void bwd_tile(const ImgDesc* __restrict__ descs, int B, const KParams& kp,
                                                const Rec* __restrict__ recs, const uint32_t* __restrict__ vals,
-                                               const uint32_t* __restrict__ eidx, const uint2* __restrict__ ranges,
+                                               const PrimPack* __restrict__ pk, const uint2* __restrict__ ranges,
                                                uint32_t t, const float* __restrict__ T_final,
                                                const int32_t* __restrict__ last, const float* __restrict__ dLdC,
                                                float* __restrict__ slots, uint32_t* __restrict__ smark,
@@ -647,14 +661,26 @@ __device__ __forceinline__ void bwd_tile(const ImgDesc* __restrict__ descs, int 
     uint64_t mn = c0 > G.start ? hits_of(n0, n1) : 0ull;
     uint32_t pn = 0;
     if ((mn >> l) & 1ull) pn = vals[(n0 & ~63u) + (uint32_t)l];
-    // the combine step gives thread tid list position b + (tid >> 2) of the
-    // chunk and three of its slot values
-    const uint32_t co = (uint32_t)tid >> 2, cc3 = ((uint32_t)tid & 3u) * 3u;
+    // The combine step gives four threads to each list position of the chunk
+    // (three slot values each), in CR rounds of NT / 4 positions; the
+    // positions' primitives (and, in one round, their packs) are loaded at
+    // the chunk's start and used after the replay.
+    constexpr int CR = NT >= 4 * kWave ? 1 : (4 * kWave) / NT;
+    constexpr uint32_t CP = (uint32_t)NT / 4u;
+    const uint32_t co0 = (uint32_t)tid >> 2, cc3 = ((uint32_t)tid & 3u) * 3u;
+    const int tcx = G.ox / TW, tcy = G.oy / TH;   // this tile in its image
     for (;;) {
         const uint32_t b = c0 & ~63u;
-        // its slot index is loaded now and used after the replay
-        const bool cmine = NT >= 4 * kWave && b + co >= c0 && b + co < c1;
-        const uint32_t ce = cmine ? eidx[b + co] : 0u;
+        bool cmine[CR];
+        uint32_t cprim[CR];
+#pragma unroll
+        for (int r = 0; r < CR; ++r) {
+            const uint32_t co = co0 + (uint32_t)r * CP;
+            cmine[r] = co < (uint32_t)kWave && b + co >= c0 && b + co < c1;
+            cprim[r] = cmine[r] ? vals[b + co] : 0u;
+        }
+        PrimPack cq{};
+        if (CR == 1 && cmine[0]) cq = pk[cprim[0]];
         if ((m >> l) & 1ull) {
             st[__popcll(m & below)] = stage_raw(cur, bx, by, b + (uint32_t)l);
         } else {
@@ -743,15 +769,18 @@ __device__ __forceinline__ void bwd_tile(const ImgDesc* __restrict__ descs, int 
         uint64_t anyhit = 0ull;
 #pragma unroll
         for (int k = 0; k < NB; ++k) anyhit |= hitm[k];
-        if constexpr (NT >= 4 * kWave) {
-            if (cmine && ((anyhit >> co) & 1ull)) {
-                const uint32_t r = co * kSlot + cc3;
+#pragma unroll
+        for (int r = 0; r < CR; ++r) {
+            const uint32_t co = co0 + (uint32_t)r * CP;
+            if (cmine[r] && ((anyhit >> co) & 1ull)) {
+                const uint32_t ce = slot_of<TW, TH>(CR == 1 ? cq : pk[cprim[r]], tcx, tcy);
+                const uint32_t rr = co * kSlot + cc3;
                 float s3[3];
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
-                    float sum = part[r + c];
+                    float sum = part[rr + c];
 #pragma unroll
-                    for (int k = 1; k < NB; ++k) sum += part[(size_t)k * kWave * kSlot + r + c];
+                    for (int k = 1; k < NB; ++k) sum += part[(size_t)k * kWave * kSlot + rr + c];
                     s3[c] = sum;
                 }
                 float* dst = slots + (size_t)ce * kSlot + cc3;
@@ -759,18 +788,6 @@ __device__ __forceinline__ void bwd_tile(const ImgDesc* __restrict__ descs, int 
                 dst[1] = s3[1];
                 dst[2] = s3[2];
                 if (cc3 == 0) atomicOr(smark + (ce >> 5), 1u << (ce & 31u));
-            }
-        } else {
-            const uint32_t n = c1 - c0, r0 = (c0 & 63u) * kSlot;
-            for (uint32_t q = (uint32_t)tid; q < n * kSlot; q += NT) {
-                const uint32_t pp = q / kSlot, pos = c0 + pp;
-                if (!((anyhit >> (pos & 63u)) & 1ull)) continue;
-                float sum = part[r0 + q];
-#pragma unroll
-                for (int k = 1; k < NB; ++k) sum += part[(size_t)k * kWave * kSlot + r0 + q];
-                const uint32_t e = eidx[pos], comp = q - pp * kSlot;
-                slots[(size_t)e * kSlot + comp] = sum;
-                if (comp == 0) atomicOr(smark + (e >> 5), 1u << (e & 31u));
             }
         }
         __syncthreads();
@@ -790,7 +807,7 @@ template <int MODE, int TW, int TH>
 __global__ void __launch_bounds__(TW * TH) k_blend_bwd(const ImgDesc* __restrict__ descs, int B, KParams kp,
                                                              const Rec* __restrict__ recs,
                                                              const uint32_t* __restrict__ vals,
-                                                             const uint32_t* __restrict__ eidx,
+                                                             const PrimPack* __restrict__ pk,
                                                              const uint2* __restrict__ ranges,
                                                              const uint32_t* __restrict__ ovf, uint32_t n_tiles,
                                                              const float* __restrict__ T_final,
@@ -809,7 +826,7 @@ __global__ void __launch_bounds__(TW * TH) k_blend_bwd(const ImgDesc* __restrict
     if (*ovf) return;
     const uint32_t t = blockIdx.x;
     if (t >= n_tiles) return;
-    bwd_tile<MODE, TW, TH>(descs, B, kp, recs, vals, eidx, ranges, t, T_final, last, dLdC, slots, valid, cmask,
+    bwd_tile<MODE, TW, TH>(descs, B, kp, recs, vals, pk, ranges, t, T_final, last, dLdC, slots, valid, cmask,
                            cmask_words, stage, part, top, hitm);
 }
 
@@ -818,7 +835,7 @@ template <int MODE, int TW, int TH>
 __global__ void __launch_bounds__(TW * TH) k_blend_bwd_q(const ImgDesc* __restrict__ descs, int B, KParams kp,
                                                                const Rec* __restrict__ recs,
                                                                const uint32_t* __restrict__ vals,
-                                                               const uint32_t* __restrict__ eidx,
+                                                               const PrimPack* __restrict__ pk,
                                                                const uint2* __restrict__ ranges,
                                                                const uint32_t* __restrict__ ovf, uint32_t n_tiles,
                                                                const uint32_t* __restrict__ order,
@@ -845,7 +862,7 @@ __global__ void __launch_bounds__(TW * TH) k_blend_bwd_q(const ImgDesc* __restri
         const uint32_t t = qtile;
         __syncthreads();   // every wave has read `qtile` before it is rewritten
         if (t >= n_tiles) break;
-        bwd_tile<MODE, TW, TH>(descs, B, kp, recs, vals, eidx, ranges, t, T_final, last, dLdC, slots, valid, cmask,
+        bwd_tile<MODE, TW, TH>(descs, B, kp, recs, vals, pk, ranges, t, T_final, last, dLdC, slots, valid, cmask,
                                cmask_words, stage, part, top, hitm);
     }
 }
@@ -944,7 +961,7 @@ static void launch_fwd_t(const ImgDesc* descs, int B, const KParams& kp, const R
 
 template <int MODE, int TW, int TH>
 static void launch_bwd_t(const ImgDesc* descs, int B, const KParams& kp, const Rec* recs, const uint32_t* vals,
-                         const uint32_t* eidx, const uint2* ranges, const uint32_t* ovf, uint32_t n_tiles,
+                         const PrimPack* pk, const uint2* ranges, const uint32_t* ovf, uint32_t n_tiles,
                          const uint32_t* order, uint32_t* queue, uint32_t persistent_blocks, const float* T_final,
                          const int32_t* last, const float* dLdC, float* slots, uint32_t* valid,
                          const unsigned long long* cmask, uint32_t cmask_words, hipStream_t s)
@@ -953,13 +970,13 @@ static void launch_bwd_t(const ImgDesc* descs, int B, const KParams& kp, const R
     if (queue) {
         const uint32_t nb = max(1u, persistent_blocks * kWpb / NB);
         hipLaunchKernelGGL((k_blend_bwd_q<MODE, TW, TH>), dim3(nb), dim3(TW * TH), 0, s, descs, B, kp, recs, vals,
-                           eidx, ranges, ovf, n_tiles, order, queue, T_final, last, dLdC, slots, valid, cmask,
+                           pk, ranges, ovf, n_tiles, order, queue, T_final, last, dLdC, slots, valid, cmask,
                            cmask_words);
         return;
     }
     if (n_tiles == 0) return;
     hipLaunchKernelGGL((k_blend_bwd<MODE, TW, TH>), dim3(n_tiles), dim3(TW * TH), 0, s, descs, B, kp, recs, vals,
-                       eidx, ranges, ovf, n_tiles, T_final, last, dLdC, slots, valid, cmask, cmask_words);
+                       pk, ranges, ovf, n_tiles, T_final, last, dLdC, slots, valid, cmask, cmask_words);
 }
 
 #define WIPES_TILE_DISPATCH(FN, MODE, ...)                                          \
@@ -1011,16 +1028,16 @@ hipError_t launch_blend_fwd(const ImgDesc* descs, int B, const KParams& kp, cons
 }
 
 hipError_t launch_blend_bwd(const ImgDesc* descs, int B, const KParams& kp, const Rec* recs, const uint32_t* vals,
-                            const uint32_t* eidx, const uint2* ranges, const uint32_t* ovf, uint32_t n_tiles,
+                            const PrimPack* pk, const uint2* ranges, const uint32_t* ovf, uint32_t n_tiles,
                             const uint32_t* order, uint32_t* queue, uint32_t persistent_blocks, const float* T_final,
                             const int32_t* last, const float* dLdC, float* slots, uint32_t* valid,
                             const unsigned long long* cmask, uint32_t cmask_words, hipStream_t s)
 {
     if (kp.mode == WIPES_2D_ADDITIVE)
-        WIPES_TILE_DISPATCH(launch_bwd_t, WIPES_2D_ADDITIVE, descs, B, kp, recs, vals, eidx, ranges, ovf, n_tiles,
+        WIPES_TILE_DISPATCH(launch_bwd_t, WIPES_2D_ADDITIVE, descs, B, kp, recs, vals, pk, ranges, ovf, n_tiles,
                             order, queue, persistent_blocks, T_final, last, dLdC, slots, valid, cmask, cmask_words, s);
     else
-        WIPES_TILE_DISPATCH(launch_bwd_t, WIPES_3D_ALPHA, descs, B, kp, recs, vals, eidx, ranges, ovf, n_tiles, order,
+        WIPES_TILE_DISPATCH(launch_bwd_t, WIPES_3D_ALPHA, descs, B, kp, recs, vals, pk, ranges, ovf, n_tiles, order,
                             queue, persistent_blocks, T_final, last, dLdC, slots, valid, cmask, cmask_words, s);
     return hipGetLastError();
 }

@@ -21,7 +21,7 @@ struct Views {
     ImgDesc* descs;
     PrimPack *pk, *pkr;
     uint32_t* cnt_r;
-    uint32_t *keys_a, *vals_a, *keys_b, *vals_b, *hist, *dtot, *order, *tbsum, *w_a, *w_b;
+    uint32_t *keys_a, *vals_a, *keys_b, *vals_b, *hist, *dtot, *order, *tbsum;
     uint2* ranges;
     float* slots;
     unsigned long long* cmask;
@@ -64,8 +64,6 @@ static Views views(const Layout& L, const void* screen, const void* bins)
         v.order = (uint32_t*)(b + L.b_order);
         v.tbsum = (uint32_t*)(b + L.b_tbsum);
         if (L.with_bwd) {
-            v.w_a = (uint32_t*)(b + L.b_w_a);
-            v.w_b = (uint32_t*)(b + L.b_w_b);
             v.slots = (float*)(b + L.b_slots);
             v.cmask = (unsigned long long*)(b + L.b_cmask);
             v.svalid = (uint32_t*)(b + L.b_svalid);
@@ -105,11 +103,12 @@ wipes_status bin_sort_core(wipes_ctx* ctx, const wipes_params* p, const wipes_ba
         // the scan also stores K into the pinned host word when the caller
         // wants it; the host waits for it only before the emission, so the
         // round trip overlaps the depth sort
-        // (alpha: the offsets also go into the packs' slot base, so the rank
-        // pack gathers one record per primitive, not two)
+        // (the offsets also go into the packs' slot base: the rank pack then
+        // gathers one record per primitive, and the backward finds each
+        // instance's gradient slot from its primitive's pack)
         HIP_TRY(scan_excl(v.count, nullptr, n, nullptr, n, v.bsum, v.off_id, v.ctrl + kCtrlK, (uint32_t)L.cap,
                           v.ctrl + kCtrlNEff, v.ctrl + kCtrlOverflow, s, n_instances_out ? ctx->k_host_dev : nullptr,
-                          L.alpha ? &v.pk->base : nullptr, (uint32_t)(sizeof(PrimPack) / 4)),
+                          &v.pk->base, (uint32_t)(sizeof(PrimPack) / 4)),
                 "scan");
     }
     if (n_instances_out) HIP_TRY(hipEventRecord(ctx->k_ev, s), "read K event");
@@ -143,14 +142,14 @@ wipes_status bin_sort_core(wipes_ctx* ctx, const wipes_params* p, const wipes_ba
     {
         StageScope sc(ctx, kStEmit, s);
         HIP_TRY(launch_emit(v.descs, L.B, (int32_t)n, kp, L.alpha ? v.pkr : v.pk, order, offs, v.ctrl + kCtrlNEff,
-                            v.keys_a, v.vals_a, v.w_a, s),
+                            v.keys_a, v.vals_a, s),
                 "emit");
     }
     int in_b = 0;
     {
         StageScope sc(ctx, kStTileSort, s);
         HIP_TRY(radix_sort(v.keys_a, v.vals_a, v.keys_b, v.vals_b, 0, v.ctrl + kCtrlNEff, max_k, L.tile_bits, v.hist,
-                           v.dtot, &in_b, s, v.w_a, v.w_b),
+                           v.dtot, &in_b, s),
                 "tile sort");
     }
     const uint32_t* skeys = in_b ? v.keys_b : v.keys_a;
@@ -210,8 +209,7 @@ wipes_status render_bwd_core(wipes_ctx* ctx, const wipes_params* p, const wipes_
             "queue reset / slot marks clear");
     {
         StageScope sc(ctx, kStBlendBwd, s);
-        const uint32_t* seidx = L.tile_result_b ? v.w_b : v.w_a;
-        HIP_TRY(launch_blend_bwd(v.descs, L.B, kp, v.recs, svals, seidx, v.ranges, v.ctrl + kCtrlOverflow,
+        HIP_TRY(launch_blend_bwd(v.descs, L.B, kp, v.recs, svals, v.pk, v.ranges, v.ctrl + kCtrlOverflow,
                                  (uint32_t)L.tiles, order, queue, pblocks, T_final, last, dLdC, v.slots, v.svalid,
                                  v.cmask, L.cmask_words, s),
                 "blend bwd");
