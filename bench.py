@@ -40,8 +40,8 @@ HBM_PEAK = 8.0e12
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--prims", type=int, default=1_000_000)
     ap.add_argument("--tile", type=str, default="16x16")
     ap.add_argument("--persistent", type=int, default=2,
