@@ -289,6 +289,36 @@ wipes_status wipes_graph_capture(wipes_ctx* ctx, const wipes_params* p, const wi
 wipes_status wipes_graph_launch(wipes_graph* g, void* stream);
 void wipes_graph_destroy(wipes_graph* g);
 
+/* One Adam step (the optimiser of the 2D fitting experiments, Sec. 5.1) over
+ * up to WIPES_ADAM_MAX_GROUPS parameter groups, in one launch.  Per element,
+ * with t = *step + 1:
+ *   m = m + (1 - beta1)(g - m),  v = beta2 v + (1 - beta2) g^2,
+ *   param = param - (lr / (1 - beta1^t)) m / (sqrt(v) / sqrt(1 - beta2^t) + eps),
+ * then *step = t.  Each group: device float32 param, grad, m and v of n
+ * elements (m and v start at zero and belong to the caller) and its learning
+ * rate.  step: device uint32 count of applied steps (the bias corrections are
+ * formed on the device from it, so a captured sequence can replay this call).
+ * When screen is given (p and batch describing it), the step is skipped on the
+ * device -- nothing written, *step unchanged -- if the last bin_sort on that
+ * screen buffer overflowed its capacity, so a replayed render + Adam sequence
+ * never applies the gradients of a truncated render; the caller learns of a
+ * skipped step from *step.  Asynchronous.  WIPES_ERR_INVALID for n_groups
+ * outside [1, WIPES_ADAM_MAX_GROUPS], a NULL array with n > 0, or more than
+ * 2^31 elements in all. */
+#define WIPES_ADAM_MAX_GROUPS 8
+typedef struct {
+    float* param;
+    const float* grad;
+    float* m;
+    float* v;
+    int64_t n;
+    double lr;
+} wipes_adam_group;
+
+wipes_status wipes_adam(wipes_ctx* ctx, int32_t n_groups, const wipes_adam_group* groups, double beta1, double beta2,
+                        double eps, uint32_t* step, const wipes_params* p, const wipes_batch* batch,
+                        const wipes_buffer* screen, void* stream);
+
 /* ------------------------------------------------------------ autotuning */
 
 /* Candidates the autotuner tries, in the order of its times_ms output:

@@ -220,6 +220,30 @@ def wipes_l2_grad(ctx, params, batch, screen, image: int, target: int, dL_dimage
                               stream), ctx)
 
 
+def wipes_adam(ctx, groups, beta1: float, beta2: float, eps: float, step: int, params=None, batch=None,
+               screen=None, stream: int = 0) -> None:
+    """One Adam step over groups = [(param, grad, m, v, lr)] of float32 CUDA tensors (see wipes.h);
+    step: device address of the uint32 step counter.  With (params, batch, screen) the step is
+    skipped on the device when the last bin_sort on that screen buffer overflowed."""
+    from .binding_ext import wipes_adam_group
+    arr = (wipes_adam_group * len(groups))()
+    for i, (p, g, m, v, lr) in enumerate(groups):
+        for t in (p, g, m, v):
+            if t.dtype != torch_float32() or not t.is_cuda or not t.is_contiguous() or t.numel() != p.numel():
+                raise ValueError("Adam group %d: param, grad, m, v must be contiguous float32 CUDA tensors "
+                                 "of equal size" % i)
+        arr[i] = wipes_adam_group(p.data_ptr(), g.data_ptr(), m.data_ptr(), v.data_ptr(), p.numel(), float(lr))
+    check(lib().wipes_adam(ctx, len(groups), arr, float(beta1), float(beta2), float(eps), step,
+                           C.byref(params) if params is not None else None,
+                           C.byref(batch) if batch is not None else None,
+                           C.byref(screen) if screen is not None else None, stream), ctx)
+
+
+def torch_float32():
+    import torch
+    return torch.float32
+
+
 def wipes_graph_capture(ctx, params, batch, screen, bins, image: int, T_final, last, target, dL_dimage,
                         backward: bool):
     g = C.c_void_p()

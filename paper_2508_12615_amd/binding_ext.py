@@ -15,6 +15,14 @@ class wipes_serve_report(C.Structure):
                 ("arena_peak_bytes", C.c_int64)]
 
 
+class wipes_adam_group(C.Structure):
+    _fields_ = [("param", C.c_void_p), ("grad", C.c_void_p), ("m", C.c_void_p), ("v", C.c_void_p),
+                ("n", C.c_int64), ("lr", C.c_double)]
+
+
+WIPES_ADAM_MAX_GROUPS = 8
+
+
 def declare(L) -> None:
     from .binding import wipes_batch, wipes_buffer, wipes_camera, wipes_params, wipes_prims
     P, PP = C.c_void_p, C.POINTER
@@ -38,6 +46,8 @@ def declare(L) -> None:
                                           P, P, P, P, P, C.c_int32, PP(C.c_void_p)]),
         "wipes_graph_launch": (C.c_int, [P, P]),
         "wipes_graph_destroy": (None, [P]),
+        "wipes_adam": (C.c_int, [P, C.c_int32, PP(wipes_adam_group), C.c_double, C.c_double, C.c_double, P,
+                                 PP(wipes_params), PP(wipes_batch), PP(wipes_buffer), P]),
     }
     for name, (res, args) in table.items():
         if hasattr(L, name):

@@ -6,12 +6,15 @@ Two drivers over the same rasterizer:
                       backward -> Adam; the plain per-image rasterizer with one
                       host synchronisation per step (instance count readback).
 * ``fit_graph``    -- one image, one step = one hipGraph replay of the whole
-                      render step + Adam (a BatchedFit of one image).
+                      render step + the library's Adam (a BatchedFit of one
+                      image), with no host synchronisation per step.
 * ``BatchedFit``   -- many images of uneven size fitted together; one step is a
                       single replay of a hipGraph holding projection, binning,
                       sorting, forward blend, L2 gradient, backward blend and
                       projection backward for every image, followed by one
-                      Adam update over the concatenated parameters.
+                      Adam launch (``wipes_adam``) over the concatenated
+                      parameters, skipped on the device if the replay
+                      overflowed the instance capacity.
 
 Optimiser settings (a reading; the paper keeps GaussianImage's values, which
 it does not list): Adam(beta = (0.9, 0.999), eps = 1e-8), learning rate 1e-3
@@ -60,19 +63,24 @@ def fit_graph(prims: dict, target: torch.Tensor, steps: int, tile=(16, 16), cov:
     grown = 0
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    it = 0
+    it = 0   # steps applied
     while it < steps:
-        fit.render_grads()
-        st, K = B.wipes_check_overflow(fit.rast.ctx, fit.rast.params, fit.batch, fit.sbuf,
-                                       torch.cuda.current_stream(fit.device).cuda_stream)
-        if st != B.WIPES_OK:
+        # launch up to 32 steps without waiting; a replay that overflows makes
+        # its Adam step (and every later one, whose inputs are then the same)
+        # a no-op on the device, which the step counter shows afterwards
+        chunk = min(32, steps - it)
+        for j in range(chunk):
+            fit.step()
+            if log_every and ((it + j) % log_every == 0 or it + j == steps - 1):
+                hist.append((it + j, fit.loss()))
+        done = fit.steps_applied()
+        if done < it + chunk:
+            st, K = B.wipes_check_overflow(fit.rast.ctx, fit.rast.params, fit.batch, fit.sbuf,
+                                           torch.cuda.current_stream(fit.device).cuda_stream)
             fit.grow(K)
             grown += 1
-            continue
-        fit.opt.step()
-        if log_every and (it % log_every == 0 or it == steps - 1):
-            hist.append((it, fit.loss()))
-        it += 1
+            hist = [h for h in hist if h[0] < done]   # losses of skipped steps are redone
+        it = done
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     with torch.no_grad():
@@ -138,7 +146,11 @@ class BatchedFit:
         npx = self.target.shape[0]
         self.image = torch.empty((npx, 3), dtype=torch.float32, device=self.device)
         self.dL = torch.empty((npx, 3), dtype=torch.float32, device=self.device)
-        self.opt = _adam(self.params)
+        # state of the library's Adam (one launch per step for all groups)
+        self.adam_m = {k: torch.zeros_like(self.params[k]) for k in KEYS_2D}
+        self.adam_v = {k: torch.zeros_like(self.params[k]) for k in KEYS_2D}
+        self.adam_lr = {k: (LR_FREQ if k == "freq" else LR_DEFAULT) for k in KEYS_2D}
+        self.adam_step = torch.zeros(1, dtype=torch.int32, device=self.device)
         self._views = self._image_views()
         # size the instance capacity from one plain pass
         f = self.rast.forward(self._views)
@@ -184,8 +196,19 @@ class BatchedFit:
         B.wipes_graph_launch(self.graph, torch.cuda.current_stream(self.device).cuda_stream)
 
     def step(self) -> None:
+        """One replay and one Adam step (skipped on the device if the replay overflowed)."""
         self.render_grads()
-        self.opt.step()
+        self.adam()
+
+    def adam(self) -> None:
+        groups = [(self.params[k].detach(), self.params[k].grad, self.adam_m[k], self.adam_v[k], self.adam_lr[k])
+                  for k in KEYS_2D]
+        B.wipes_adam(self.rast.ctx, groups, 0.9, 0.999, 1e-8, self.adam_step.data_ptr(), self.rast.params,
+                     self.batch, self.sbuf, torch.cuda.current_stream(self.device).cuda_stream)
+
+    def steps_applied(self) -> int:
+        """Adam steps applied so far (synchronises)."""
+        return int(self.adam_step.item())
 
     def check_capacity(self) -> int:
         """Synchronises; raises if the last replay overflowed the instance capacity."""

@@ -118,3 +118,58 @@ def test_batched_step_equals_plain_steps():
         for k in pr:
             assert torch.allclose(fit.params[k].detach()[a:z], pr[k], rtol=1e-6, atol=1e-7), (b, k)
     fit.close()
+
+
+def test_library_adam_matches_torch():
+    """wipes_adam over several groups (two learning rates) follows torch.optim.Adam step for step
+    (same update, constants formed the same way) and counts its steps on the device."""
+    g = torch.Generator(device="cuda").manual_seed(5)
+    sizes, lrs = [1000, 37, 4096], [1e-3, 2.5e-3, 1e-3]
+    ps = [torch.randn(n, device="cuda", generator=g) for n in sizes]
+    ref = [p.clone().requires_grad_(True) for p in ps]
+    opt = torch.optim.Adam([dict(params=[r], lr=lr) for r, lr in zip(ref, lrs)], betas=(0.9, 0.999), eps=1e-8)
+    ms = [torch.zeros_like(p) for p in ps]
+    vs = [torch.zeros_like(p) for p in ps]
+    step = torch.zeros(1, dtype=torch.int32, device="cuda")
+    ctx = B.wipes_ctx_create(0)
+    try:
+        for it in range(6):
+            grads = [torch.randn(n, device="cuda", generator=g) * (0.1 + it) for n in sizes]
+            for r, gr in zip(ref, grads):
+                r.grad = gr.clone()
+            opt.step()
+            B.wipes_adam(ctx, [(p, gr, m, v, lr) for p, gr, m, v, lr in zip(ps, grads, ms, vs, lrs)], 0.9, 0.999,
+                         1e-8, step.data_ptr(), stream=torch.cuda.current_stream().cuda_stream)
+            for p, r in zip(ps, ref):
+                assert torch.allclose(p, r.detach(), rtol=1e-6, atol=1e-7), it
+        assert int(step.item()) == 6
+    finally:
+        B.wipes_ctx_destroy(ctx)
+
+
+def test_adam_skipped_after_overflow():
+    """A replay that overflows the instance capacity leaves parameters, optimiser state and the step
+    count unchanged; after growing the capacity the next step applies."""
+    ims = uneven_images(2, 4)
+    fit = BatchedFit(ims, capacity_margin=1.0)
+    fit.step()
+    assert fit.steps_applied() == 1
+    with torch.no_grad():
+        fit.params["cov"].mul_(3.0)                            # larger footprints: more instances
+    before = {k: v.detach().clone() for k, v in fit.params.items()}
+    m_before = {k: v.clone() for k, v in fit.adam_m.items()}
+    fit.step()
+    assert fit.steps_applied() == 1
+    for k in before:
+        assert torch.equal(before[k], fit.params[k].detach()), k
+        assert torch.equal(m_before[k], fit.adam_m[k]), k
+    with pytest.raises(B.WipesError):
+        fit.check_capacity()
+    st, K = B.wipes_check_overflow(fit.rast.ctx, fit.rast.params, fit.batch, fit.sbuf,
+                                   torch.cuda.current_stream().cuda_stream)
+    fit.grow(K)
+    fit.step()
+    assert fit.steps_applied() == 2
+    fit.check_capacity()
+    assert not torch.equal(before["mean"], fit.params["mean"].detach())
+    fit.close()
