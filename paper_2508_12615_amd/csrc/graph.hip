@@ -14,14 +14,19 @@
 namespace wipes {
 
 // dL/dC of L = sum over images of mean over that image's 3 W H values of
-// (C - target)^2:  2 (C - target) / (3 W H).
+// (C - target)^2:  2 (C - target) / (3 W H).  One thread per pixel; the
+// image is looked up once per wave (for the wave's first pixel, with
+// wave-uniform loads), and a lane past that image's end searches on its own.
 __global__ void __launch_bounds__(256) k_l2_grad(const ImgDesc* __restrict__ descs, int B, int32_t npix,
                                                   const float* __restrict__ image, const float* __restrict__ target,
                                                   float* __restrict__ grad)
 {
+    const int32_t p0 = __builtin_amdgcn_readfirstlane((int32_t)(blockIdx.x * 256u + (threadIdx.x & ~63u)));
+    if (p0 >= npix) return;   // wave-uniform
+    int b = find_owner(B, p0, [&](int k) { return descs[k].pix_begin; });
     const int32_t p = (int32_t)(blockIdx.x * 256u + threadIdx.x);
     if (p >= npix) return;
-    const int b = find_owner(B, p, [&](int k) { return descs[k].pix_begin; });
+    if (b + 1 < B && p >= descs[b + 1].pix_begin) b = find_owner(B, p, [&](int k) { return descs[k].pix_begin; });
     const float scale = 2.0f / (3.0f * (float)descs[b].W * (float)descs[b].H);
     for (int c = 0; c < 3; ++c) grad[3 * p + c] = scale * (image[3 * p + c] - target[3 * p + c]);
 }
