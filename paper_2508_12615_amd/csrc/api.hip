@@ -177,6 +177,7 @@ Layout layout_of(const wipes_params* p, const wipes_batch* b, int64_t cap, int w
     L.b_dtot = take(nd_bins * 4);
     L.b_ranges = take((size_t)L.tiles * 8);
     L.b_order = take((size_t)L.tiles * 4);   // longest-first tile order
+    L.b_lpt = take((size_t)(lpt_slices((uint32_t)L.tiles) + 1) * 256 * 4);   // its per-slice key counts
     L.b_tbsum = take((size_t)(nb_t + 1) * 4);
     if (with_bwd) {
         L.b_slots = take((size_t)cap * 48);

@@ -72,7 +72,7 @@ struct Layout {
     size_t s_pk, s_pkr, s_cnt_r;   // packed {count, box0, box1, slot base} per primitive / per depth rank
     size_t s_bsum, s_bsum2, s_ctrl, s_descs, screen_bytes;
     // bins buffer
-    size_t b_keys_a, b_vals_a, b_keys_b, b_vals_b, b_hist, b_dtot, b_ranges, b_order, b_tbsum, b_slots;
+    size_t b_keys_a, b_vals_a, b_keys_b, b_vals_b, b_hist, b_dtot, b_ranges, b_order, b_lpt, b_tbsum, b_slots;
     size_t b_cmask;           // per 8x8 block of a tile, one bit per list position (backward only)
     size_t b_svalid;          // one bit per gradient slot: written by this backward (backward only)
     uint32_t cmask_words;     // 64-bit words per block row of the mask
@@ -128,7 +128,9 @@ hipError_t launch_emit(const ImgDesc* descs, int B, int32_t n_total, const KPara
                        const uint32_t* order, const uint32_t* offs, const uint32_t* n_eff, uint32_t* keys,
                        uint32_t* vals, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t n, uint32_t v, hipStream_t s);
-hipError_t launch_tile_lpt_order(const uint2* ranges, uint32_t n_tiles, uint32_t* order, hipStream_t s);
+uint32_t lpt_slices(uint32_t n_tiles);   // workgroups of the two-pass longest-first order (256 counts each)
+hipError_t launch_tile_lpt_order(const uint2* ranges, uint32_t n_tiles, uint32_t* counts, uint32_t* order,
+                                 hipStream_t s);
 hipError_t launch_fill2_u32(uint32_t* p, uint32_t n, uint32_t* q, uint32_t m, uint32_t v, hipStream_t s);
 hipError_t launch_ranges(const uint32_t* keys, const uint32_t* n_eff, uint32_t max_k, uint2* ranges, hipStream_t s);
 uint32_t scan_blocks(uint32_t max_n);

@@ -311,68 +311,126 @@ __device__ __forceinline__ uint32_t lpt_key(uint2 r)
     return 255u - min((uint32_t)q, 255u);
 }
 
+// Tiles per thread per round (their range loads issued together, so a
+// round costs one memory latency for kLptRound tiles), and tiles per
+// workgroup of the two-pass form.
+constexpr uint32_t kLptPer = 8, kLptRound = 1024u * kLptPer, kLptSlice = 2u * kLptRound;
+
+template <typename Fn>
+__device__ __forceinline__ void lpt_rounds(const uint2* __restrict__ ranges, uint32_t t_begin, uint32_t t_end, Fn fn)
+{
+    for (uint32_t t0 = t_begin; t0 < t_end; t0 += kLptRound) {
+        uint32_t key[kLptPer];
+#pragma unroll
+        for (uint32_t k = 0; k < kLptPer; ++k) {
+            const uint32_t t = t0 + k * 1024u + threadIdx.x;
+            key[k] = t < t_end ? lpt_key(ranges[t]) : 0u;
+        }
+#pragma unroll
+        for (uint32_t k = 0; k < kLptPer; ++k) fn(t0 + k * 1024u + threadIdx.x, key[k]);
+    }
+}
+
+// The key of empty tiles (255; half the tiles of a typical frame) is counted
+// and placed once per wave rather than once per lane: per-lane LDS atomics on
+// one address serialise.
+__device__ __forceinline__ void lpt_count(const uint2* __restrict__ ranges, uint32_t t_begin, uint32_t t_end,
+                                          uint32_t* s_cnt)
+{
+    const int l = lane_id();
+    lpt_rounds(ranges, t_begin, t_end, [&](uint32_t t, uint32_t key) {
+        const bool in = t < t_end;
+        const uint64_t low = __ballot(in && key == 255u);
+        if (in && key != 255u) atomicAdd(&s_cnt[key], 1u);
+        if (low && l == 0) atomicAdd(&s_cnt[255], (uint32_t)__popcll(low));
+    });
+}
+
+__device__ __forceinline__ void lpt_place(const uint2* __restrict__ ranges, uint32_t t_begin, uint32_t t_end,
+                                          uint32_t* s_cnt, uint32_t* __restrict__ order)
+{
+    const int l = lane_id();
+    const uint64_t lt = (l == 0) ? 0ull : (~0ull >> (64 - l));
+    lpt_rounds(ranges, t_begin, t_end, [&](uint32_t t, uint32_t key) {
+        const bool in = t < t_end;
+        const uint64_t low = __ballot(in && key == 255u);
+        uint32_t at = 0u;
+        if (low && l == 0) at = atomicAdd(&s_cnt[255], (uint32_t)__popcll(low));
+        at = (uint32_t)__shfl((int)at, 0, kWave);
+        if (in) order[key == 255u ? at + (uint32_t)__popcll(low & lt) : atomicAdd(&s_cnt[key], 1u)] = t;
+    });
+}
+
+// Exclusive scan of the 256 counts in place, by the first wave (four per lane).
+__device__ __forceinline__ void lpt_scan(uint32_t* s_cnt)
+{
+    if (threadIdx.x >= kWave) return;
+    const uint32_t l = threadIdx.x;
+    uint32_t c[4], sum = 0u, tot;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        c[k] = s_cnt[4u * l + k];
+        sum += c[k];
+    }
+    uint32_t ex = wave_excl_scan_u32(sum, &tot);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        s_cnt[4u * l + k] = ex;
+        ex += c[k];
+    }
+}
+
+// Up to kLptSlice tiles: one workgroup counts, scans and places.
 __global__ void __launch_bounds__(1024) k_tile_lpt_order(const uint2* __restrict__ ranges, uint32_t n_tiles,
                                                          uint32_t* __restrict__ order)
 {
-    // Each thread takes kLptPer tiles a round, their range loads issued
-    // together, so a round costs one memory latency for 8192 tiles.  The key
-    // of empty tiles (255; half the tiles of a typical frame) is counted and
-    // placed once per wave rather than once per lane: per-lane LDS atomics on
-    // one address serialise.
-    constexpr uint32_t kLptPer = 8, kRound = 1024u * kLptPer;
     __shared__ uint32_t s_cnt[256];
     if (threadIdx.x < 256) s_cnt[threadIdx.x] = 0u;
     __syncthreads();
-    const int l = lane_id();
-    const uint64_t lt = (l == 0) ? 0ull : (~0ull >> (64 - l));
-    auto keys_of = [&](uint32_t t0, uint32_t* key) {
-#pragma unroll
-        for (uint32_t k = 0; k < kLptPer; ++k) {
-            const uint32_t t = t0 + k * 1024u + threadIdx.x;
-            key[k] = t < n_tiles ? lpt_key(ranges[t]) : 0u;
+    lpt_count(ranges, 0u, n_tiles, s_cnt);
+    __syncthreads();
+    lpt_scan(s_cnt);
+    __syncthreads();
+    lpt_place(ranges, 0u, n_tiles, s_cnt, order);
+}
+
+// More tiles: workgroup g counts the keys of slice g into counts[g][256] ...
+__global__ void __launch_bounds__(1024) k_tile_lpt_count(const uint2* __restrict__ ranges, uint32_t n_tiles,
+                                                         uint32_t* __restrict__ counts)
+{
+    __shared__ uint32_t s_cnt[256];
+    if (threadIdx.x < 256) s_cnt[threadIdx.x] = 0u;
+    __syncthreads();
+    const uint32_t b = blockIdx.x * kLptSlice;
+    lpt_count(ranges, b, min(n_tiles, b + kLptSlice), s_cnt);
+    __syncthreads();
+    if (threadIdx.x < 256) counts[blockIdx.x * 256u + threadIdx.x] = s_cnt[threadIdx.x];
+}
+
+// ... then places slice g: a key's tiles start after every smaller key's and
+// after those of slices before g.
+__global__ void __launch_bounds__(1024) k_tile_lpt_place(const uint2* __restrict__ ranges, uint32_t n_tiles,
+                                                         const uint32_t* __restrict__ counts, uint32_t n_slices,
+                                                         uint32_t* __restrict__ order)
+{
+    __shared__ uint32_t s_cnt[256], s_pre[256];
+    if (threadIdx.x < 256) {
+        uint32_t tot = 0u, pre = 0u;
+        for (uint32_t g = 0; g < n_slices; ++g) {
+            const uint32_t c = counts[g * 256u + threadIdx.x];
+            tot += c;
+            pre += g < blockIdx.x ? c : 0u;
         }
-    };
-    for (uint32_t t0 = 0; t0 < n_tiles; t0 += kRound) {
-        uint32_t key[kLptPer];
-        keys_of(t0, key);
-#pragma unroll
-        for (uint32_t k = 0; k < kLptPer; ++k) {
-            const bool in = t0 + k * 1024u + threadIdx.x < n_tiles;
-            const uint64_t low = __ballot(in && key[k] == 255u);
-            if (in && key[k] != 255u) atomicAdd(&s_cnt[key[k]], 1u);
-            if (low && l == 0) atomicAdd(&s_cnt[255], (uint32_t)__popcll(low));
-        }
+        s_cnt[threadIdx.x] = tot;
+        s_pre[threadIdx.x] = pre;
     }
     __syncthreads();
-    if (threadIdx.x < kWave) {   // exclusive scan of the 256 counts, four per lane
-        uint32_t c[4], sum = 0u, tot;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            c[k] = s_cnt[4u * (uint32_t)l + k];
-            sum += c[k];
-        }
-        uint32_t ex = wave_excl_scan_u32(sum, &tot);
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            s_cnt[4u * (uint32_t)l + k] = ex;
-            ex += c[k];
-        }
-    }
+    lpt_scan(s_cnt);
     __syncthreads();
-    for (uint32_t t0 = 0; t0 < n_tiles; t0 += kRound) {
-        uint32_t key[kLptPer];
-        keys_of(t0, key);
-#pragma unroll
-        for (uint32_t k = 0; k < kLptPer; ++k) {
-            const uint32_t t = t0 + k * 1024u + threadIdx.x;
-            const bool in = t < n_tiles;
-            const uint64_t low = __ballot(in && key[k] == 255u);
-            uint32_t at = 0u;
-            if (low && l == 0) at = atomicAdd(&s_cnt[255], (uint32_t)__popcll(low));
-            at = (uint32_t)__shfl((int)at, 0, kWave);
-            if (in) order[key[k] == 255u ? at + (uint32_t)__popcll(low & lt) : atomicAdd(&s_cnt[key[k]], 1u)] = t;
-        }
-    }
+    if (threadIdx.x < 256) s_cnt[threadIdx.x] += s_pre[threadIdx.x];
+    __syncthreads();
+    const uint32_t b = blockIdx.x * kLptSlice;
+    lpt_place(ranges, b, min(n_tiles, b + kLptSlice), s_cnt, order);
 }
 
 // Fill kernel (used instead of memset so the sequence can live in a graph).
@@ -424,9 +482,19 @@ hipError_t launch_emit(const ImgDesc* descs, int B, int32_t n_total, const KPara
     return hipGetLastError();
 }
 
-hipError_t launch_tile_lpt_order(const uint2* ranges, uint32_t n_tiles, uint32_t* order, hipStream_t s)
+uint32_t lpt_slices(uint32_t n_tiles) { return (n_tiles + kLptSlice - 1u) / kLptSlice; }
+
+hipError_t launch_tile_lpt_order(const uint2* ranges, uint32_t n_tiles, uint32_t* counts, uint32_t* order,
+                                 hipStream_t s)
 {
-    if (n_tiles > 0) hipLaunchKernelGGL(k_tile_lpt_order, dim3(1), dim3(1024), 0, s, ranges, n_tiles, order);
+    if (n_tiles == 0) return hipGetLastError();
+    const uint32_t g = lpt_slices(n_tiles);
+    if (g <= 1) {
+        hipLaunchKernelGGL(k_tile_lpt_order, dim3(1), dim3(1024), 0, s, ranges, n_tiles, order);
+    } else {
+        hipLaunchKernelGGL(k_tile_lpt_count, dim3(g), dim3(1024), 0, s, ranges, n_tiles, counts);
+        hipLaunchKernelGGL(k_tile_lpt_place, dim3(g), dim3(1024), 0, s, ranges, n_tiles, counts, g, order);
+    }
     return hipGetLastError();
 }
 

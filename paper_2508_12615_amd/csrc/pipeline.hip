@@ -157,7 +157,8 @@ wipes_status bin_sort_core(wipes_ctx* ctx, const wipes_params* p, const wipes_ba
     HIP_TRY(launch_fill_u32((uint32_t*)v.ranges, (uint32_t)(2 * L.tiles), 0u, s), "ranges fill");
     HIP_TRY(launch_ranges(skeys, v.ctrl + kCtrlNEff, max_k, v.ranges, s), "ranges");
     if (p->persistent == 2)   // longest tile list first for the persistent queue
-        HIP_TRY(launch_tile_lpt_order(v.ranges, (uint32_t)L.tiles, v.order, s), "lpt order");
+        HIP_TRY(launch_tile_lpt_order(v.ranges, (uint32_t)L.tiles, (uint32_t*)((char*)bins + L.b_lpt), v.order, s),
+                "lpt order");
     return WIPES_OK;
 }
 

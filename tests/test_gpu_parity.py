@@ -343,10 +343,10 @@ def test_batched_equals_single(mode, launch):
 
 
 def test_longest_first_order_over_many_tiles():
-    """16000 tiles (more than one round of the one-workgroup longest-first ordering): the
+    """30000 tiles (the two-pass longest-first ordering, two slices of workgroups): the
     longest-first queue gives the grid launch's images and gradients bit for bit."""
-    W, H = 1280, 800
-    prims = to_torch(synth.prims_2d(20000, W, H, 81))
+    W, H = 1600, 1200
+    prims = to_torch(synth.prims_2d(30000, W, H, 81))
     g = torch.from_numpy(np.random.default_rng(11).normal(0, 1, (W * H, 3)).astype(np.float32)).cuda()
     outs = []
     for persistent in (0, 2):
