@@ -84,8 +84,8 @@ typedef struct {
     int32_t freq_xform;   /* wipes_freq_xform */
     int32_t tile_w;       /* tile width in pixels: 8, 16 or 32 */
     int32_t tile_h;       /* tile height in pixels: 8 or 16; tile_w * tile_h in {64, 128, 256, 512} */
-    int32_t persistent;   /* 0: one wave per tile, grid launch; 1: persistent tile queue in tile
-                             order; 2: persistent queue, longest tile list first */
+    int32_t persistent;   /* 0: grid launch, a workgroup per tile; 1: persistent tile queue in
+                             tile order; 2: persistent queue, longest tile list first (default) */
     float alpha_min;      /* 1/255: pairs with o W' below it are skipped (alpha) */
     float alpha_max;      /* 0.99: clamp of o W' (alpha) */
     float T_min;          /* 1e-4: termination threshold on transmittance (alpha) */
@@ -345,7 +345,7 @@ typedef struct {
     int32_t max_slots;         /* requests in flight at once */
     int32_t max_pending;       /* waiting requests before submit returns WIPES_ERR_BUSY */
     int32_t max_batch;         /* requests per launch */
-    int32_t persistent;        /* persistent tile-queue blend across the batch (1) or grid launch (0) */
+    int32_t persistent;        /* blend launch form across the batch, as wipes_params.persistent */
     int64_t hbm_budget_bytes;  /* arena for per-request workspaces, allocated at create */
 } wipes_serve_config;
 

@@ -335,7 +335,7 @@ void wipes_params_default(int32_t mode, wipes_params* p)
     p->freq_xform = WIPES_FREQ_VECTOR;
     p->tile_w = 16;
     p->tile_h = 16;
-    p->persistent = 0;
+    p->persistent = 2;
     p->alpha_min = 1.0f / 255.0f;
     p->alpha_max = 0.99f;
     p->T_min = 1e-4f;

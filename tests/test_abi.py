@@ -39,7 +39,7 @@ def test_every_declared_symbol_is_exported(B):
 
 def test_params_default(B):
     p = B.wipes_params_default(B.WIPES_3D_ALPHA)
-    assert (p.tile_w, p.tile_h, p.cov) == (16, 16, B.WIPES_COV_QUAT_SCALE)
+    assert (p.tile_w, p.tile_h, p.cov, p.persistent) == (16, 16, B.WIPES_COV_QUAT_SCALE, 2)
     assert abs(p.alpha_min - 1 / 255) < 1e-9 and abs(p.alpha_max - 0.99) < 1e-7 and abs(p.T_min - 1e-4) < 1e-10
     assert abs(p.blur_eps - 0.3) < 1e-7 and p.q_add == 9.0
     q = B.wipes_params_default(B.WIPES_2D_ADDITIVE)
