@@ -4,7 +4,9 @@
 // The binning rule (a reading of the 3DGS-style pipeline the paper follows,
 // Sec. 4.1), in FP32 with exactly these operations so that it is reproducible:
 //   x0 = max(ceil((mx - rx) - 1/2), 0), x1 = min(floor((mx + rx) - 1/2), W - 1)
-//   (same for y); empty unless x0 <= x1 and y0 <= y1; tile rect = box / tile size.
+//   (same for y); empty unless x0 <= x1 and y0 <= y1; tile rect = box / tile size;
+//   a rectangle of at most 64 tiles keeps only the tiles whose part of the box
+//   the padded support ellipse reaches (ellipse_reaches below).
 // (mx, rx) are the FP32 record mean and padded support half-extent, so the box
 // holds every pixel whose centre can pass the per-pixel test.
 //

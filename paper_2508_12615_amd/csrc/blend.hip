@@ -11,8 +11,9 @@
 //  * the wave walks the tile's list in chunks of 64 entries: each lane
 //    gathers one entry's record (vector loads; the next chunk's entries and
 //    records are in flight while the current chunk blends), tests its pixel
-//    box against the bounding box of the block pixels still in play, and the
-//    hits are packed (ballot + prefix count) into a per-wave LDS stage holding
+//    box and padded support ellipse against the bounding box of the block
+//    pixels still in play, and the hits are packed (ballot + prefix count)
+//    into a per-wave LDS stage holding
 //    their block-relative, pre-scaled values.  The wave then blends the staged
 //    primitives in list order; all lanes read the same LDS address, which the
 //    LDS broadcasts.  A primitive that misses the block costs one lane of one
@@ -20,15 +21,19 @@
 //  * alpha mode shrinks the box as pixels terminate and leaves when none is
 //    left (lists are long and skewed in clustered scenes, and pixels stop
 //    early); additive mode keeps the box of the block's pixels;
-//  * the backward walks the same chunks top down (alpha: from the tile's last
-//    contributing position) with all block waves in step, each wave reducing
-//    a primitive's eleven gradients over its block into LDS, and the
-//    workgroup sums the blocks in a fixed order into the instance's slot.
+//  * the forward records, per block and list position, whether the
+//    primitive contributed to a pixel of the block; the backward walks the
+//    same chunks top down (alpha: from the tile's last contributing position)
+//    with all block waves in step, replays only the recorded contributors,
+//    each wave reducing a primitive's twelve per-pair basis sums over its
+//    block into LDS, and the workgroup sums the blocks in a fixed order into
+//    the instance's slot.
 //
-// Gradient slots are numbered in primitive order (the sort carries each
-// instance's slot index), so the projection backward sums a primitive's slots
-// from one contiguous run in a fixed order: gradients are deterministic,
-// atomic-free and independent of the batch a primitive is rendered in.
+// Gradient slots are numbered in primitive order (an instance's slot is its
+// primitive's slot base plus the rank of its tile among the primitive's kept
+// tiles), so the projection backward sums a primitive's slots from one
+// contiguous run in a fixed order: gradients are deterministic, atomic-free
+// and independent of the batch a primitive is rendered in.
 //
 // Per-pair rule (shared by forward and backward so their FP32 decisions agree
 // bit for bit): e2 = -q/2 log2(e) from the pre-scaled conic, E = exp2(e2),

@@ -3,7 +3,7 @@
 // bin_sort (one stream, no allocation):
 //   count  -> scan (index order, capacity check)   -> [alpha: depth sort of all
 //   primitives by FP32 key, then scan in depth order] -> emit -> tile sort ->
-//   ranges (+ instance -> sorted-position map for the backward).
+//   ranges [-> longest-first tile order for the persistent queue].
 // The tile sort's key is the global tile index only; depth order comes from
 // emitting instances in depth order into a stable sort (see binning.hip), so
 // the 45-bit (tile, depth) sort of the 3DGS pipeline becomes a 32-bit sort over

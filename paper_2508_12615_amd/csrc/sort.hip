@@ -1,8 +1,10 @@
 // Device-wide exclusive scan and stable LSD radix sort of (uint32 key, uint32 value).
 //
 // Both are written for 64-lane waves: a workgroup of 256 threads owns a tile
-// of 4096 elements, each wave a contiguous quarter of it, so loads are fully
-// coalesced and the in-tile order (wave, round, lane) is the element order.
+// of elements (4096; 2048 for radix sorts of up to 2^21 keys, which need the
+// extra workgroups to fill the chip), each wave a contiguous quarter of it,
+// so loads are fully coalesced and the in-tile order (wave, round, lane) is
+// the element order.
 // The radix pass ranks a wave's 64 elements per round with ballot-based digit
 // matching (one ballot per digit bit), accumulates per-wave digit counters in
 // LDS, then stages the tile in LDS in sorted order and writes it out so that
