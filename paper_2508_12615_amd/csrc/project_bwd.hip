@@ -38,17 +38,22 @@ __global__ void __launch_bounds__(256) k_project_bwd(const ImgDesc* __restrict__
                                                       const uint32_t* __restrict__ overflow,
                                                       float* __restrict__ dscreen)
 {
-    __shared__ float4 s_slot[4][kWave][3];
+    // slots per lane staged per chunk: a chunk of 128 slots lets a lane add
+    // more of its primitive's slots per pass (the wave pays, per chunk, for
+    // the lane with the most slots in it)
+    constexpr int SPL = 2;
+    constexpr uint32_t CH = (uint32_t)kWave * SPL;
+    __shared__ float4 s_slot[4][CH][3];
     const int wv = (int)(threadIdx.x >> 6), l = lane_id();
     const int32_t i0 = (int32_t)(blockIdx.x * 256u + (uint32_t)wv * kWave);
     if (i0 >= n_total || *overflow) return;   // wave-uniform
     const int32_t i = i0 + l;
     const bool inr = i < n_total;
     // The slots of the wave's 64 primitives form one contiguous run (they are
-    // numbered in primitive order).  The wave streams the run through LDS 64
+    // numbered in primitive order).  The wave streams the run through LDS CH
     // slots at a time with coalesced loads, and each lane adds up its own
     // primitive's slots in ascending order (the same order at any batch size).
-    // The next 64 slots are loaded while the current ones are added; their
+    // The next chunk is loaded while the current one is added; the slots'
     // written-bits come from a window of 64 words (2048 slots) that lane j
     // holds word wbase + j of, refilled when a chunk runs past it.
     const uint32_t c = inr ? count[i] : 0u;
@@ -63,34 +68,40 @@ __global__ void __launch_bounds__(256) k_project_bwd(const ImgDesc* __restrict__
     uint32_t wbase = first >> 5;
     uint32_t vword = (total && wbase + (uint32_t)l <= wlast) ? valid[wbase + (uint32_t)l] : 0u;
     // a slot the backward did not write (no pixel of its tile reached it) is zero
-    auto fetch = [&](uint32_t k0, float4& s0, float4& s1, float4& s2) {
-        const uint32_t lastw = (first + min(k0 + (uint32_t)kWave, total) - 1u) >> 5;
+    auto fetch = [&](uint32_t k0, float4 (&sl)[SPL][3]) {
+        const uint32_t lastw = (first + min(k0 + CH, total) - 1u) >> 5;
         if (lastw - wbase >= (uint32_t)kWave) {   // uniform: the window moves on
             wbase = (first + k0) >> 5;
             vword = wbase + (uint32_t)l <= wlast ? valid[wbase + (uint32_t)l] : 0u;
         }
-        const uint32_t e = first + k0 + (uint32_t)l;
-        const uint32_t word = (uint32_t)__shfl((int)vword, (int)(((e >> 5) - wbase) & 63u), kWave);
-        s0 = s1 = s2 = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (k0 + (uint32_t)l < total && ((word >> (e & 31u)) & 1u)) {
-            const float4* sl = reinterpret_cast<const float4*>(slots + (size_t)e * kSlotB);
-            s0 = sl[0];
-            s1 = sl[1];
-            s2 = sl[2];
+#pragma unroll
+        for (int q = 0; q < SPL; ++q) {
+            const uint32_t kk = k0 + (uint32_t)(q * kWave + l), e = first + kk;
+            const uint32_t word = (uint32_t)__shfl((int)vword, (int)(((e >> 5) - wbase) & 63u), kWave);
+            sl[q][0] = sl[q][1] = sl[q][2] = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (kk < total && ((word >> (e & 31u)) & 1u)) {
+                const float4* src = reinterpret_cast<const float4*>(slots + (size_t)e * kSlotB);
+                sl[q][0] = src[0];
+                sl[q][1] = src[1];
+                sl[q][2] = src[2];
+            }
         }
     };
-    float4 a0, a1, a2;
-    if (total) fetch(0, a0, a1, a2);
-    for (uint32_t k0 = 0; k0 < total; k0 += kWave) {
-        float4 b0, b1, b2;
-        if (k0 + kWave < total) fetch(k0 + kWave, b0, b1, b2);
-        if (k0 + (uint32_t)l < total) {
-            s_slot[wv][l][0] = a0;
-            s_slot[wv][l][1] = a1;
-            s_slot[wv][l][2] = a2;
+    float4 cur[SPL][3];
+    if (total) fetch(0, cur);
+    for (uint32_t k0 = 0; k0 < total; k0 += CH) {
+        float4 b[SPL][3];
+        if (k0 + CH < total) fetch(k0 + CH, b);
+#pragma unroll
+        for (int q = 0; q < SPL; ++q) {
+            if (k0 + (uint32_t)(q * kWave + l) < total) {
+                s_slot[wv][q * kWave + l][0] = cur[q][0];
+                s_slot[wv][q * kWave + l][1] = cur[q][1];
+                s_slot[wv][q * kWave + l][2] = cur[q][2];
+            }
         }
         wave_lds_sync();
-        const uint32_t e1 = min(my1, k0 + kWave);
+        const uint32_t e1 = min(my1, k0 + CH);
         for (uint32_t e = max(my0, k0); e < e1; ++e) {
             const float4 x0 = s_slot[wv][e - k0][0], x1 = s_slot[wv][e - k0][1], x2 = s_slot[wv][e - k0][2];
             acc[0] += x0.x; acc[1] += x0.y; acc[2] += x0.z; acc[3] += x0.w;
@@ -98,9 +109,12 @@ __global__ void __launch_bounds__(256) k_project_bwd(const ImgDesc* __restrict__
             acc[8] += x2.x; acc[9] += x2.y; acc[10] += x2.z; acc[11] += x2.w;
         }
         wave_lds_sync();   // the stage is rewritten next
-        a0 = b0;
-        a1 = b1;
-        a2 = b2;
+#pragma unroll
+        for (int q = 0; q < SPL; ++q) {
+            cur[q][0] = b[q][0];
+            cur[q][1] = b[q][1];
+            cur[q][2] = b[q][2];
+        }
     }
     if (!inr) return;
     // The slots hold sums of (dq dx, dq dy, dq dx^2, dq dx dy, dq dy^2,
