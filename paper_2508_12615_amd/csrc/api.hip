@@ -130,7 +130,6 @@ Layout layout_of(const wipes_params* p, const wipes_batch* b, int64_t cap, int w
     }
     L.cap = cap;
     const int64_t n = L.n;
-    const int64_t nb_n = (n + 4095) / 4096 + 1;
     size_t o = 0;
     auto take = [&](size_t bytes) {
         size_t at = o;
@@ -153,8 +152,8 @@ Layout layout_of(const wipes_params* p, const wipes_batch* b, int64_t cap, int w
         L.s_dhist = take(((size_t)1 << radix_digit_bits(32)) * ((size_t)radix_max_blocks((uint32_t)n) + 1) * 4);
         L.s_ddtot = take(((size_t)1 << radix_digit_bits(32)) * 4);
     }
-    L.s_bsum = take((size_t)(nb_n + 1) * 4);
-    L.s_bsum2 = take((size_t)(nb_n + 1) * 4);
+    L.s_bsum = take((size_t)(scan_blocks((uint32_t)n) + 1) * 4);
+    L.s_bsum2 = take((size_t)(scan_blocks((uint32_t)n) + 1) * 4);
     L.s_ctrl = take(kCtrlWords * 4);
     L.s_descs = take((size_t)L.B * sizeof(ImgDesc));
     L.screen_bytes = o;

@@ -31,6 +31,7 @@ __device__ __forceinline__ uint32_t load_n(uint32_t n_host, const uint32_t* __re
 // ------------------------------------------------------------------ scan
 
 // block_sums[b] = sum of vals[gather ? gather[i] : i] over the tile of block b.
+template <int ITEMS>
 __global__ void __launch_bounds__(kBlock) k_block_reduce(const uint32_t* __restrict__ vals,
                                                          const uint32_t* __restrict__ gather, uint32_t n_host,
                                                          const uint32_t* __restrict__ n_dev,
@@ -38,9 +39,9 @@ __global__ void __launch_bounds__(kBlock) k_block_reduce(const uint32_t* __restr
 {
     __shared__ uint32_t s_w[kBlock / kWave];
     const uint32_t n = load_n(n_host, n_dev);
-    const uint32_t base = blockIdx.x * kTile;
+    const uint32_t base = blockIdx.x * (uint32_t)(ITEMS * kBlock);
     uint32_t acc = 0;
-    for (int j = 0; j < kItems; ++j) {
+    for (int j = 0; j < ITEMS; ++j) {
         const uint32_t i = base + j * kBlock + threadIdx.x;
         if (i < n) acc += vals[gather ? gather[i] : i];
     }
@@ -101,6 +102,7 @@ __global__ void __launch_bounds__(kBlock) k_scan_block_sums(uint32_t* __restrict
 }
 
 // out[i] = exclusive prefix of vals (through gather) + scanned block sum.
+template <int ITEMS>
 __global__ void __launch_bounds__(kBlock) k_scan_apply(const uint32_t* __restrict__ vals,
                                                        const uint32_t* __restrict__ gather, uint32_t n_host,
                                                        const uint32_t* __restrict__ n_dev,
@@ -110,13 +112,13 @@ __global__ void __launch_bounds__(kBlock) k_scan_apply(const uint32_t* __restric
 {
     __shared__ uint32_t s_w[kBlock / kWave];
     const uint32_t n = load_n(n_host, n_dev);
-    const uint32_t base = blockIdx.x * kTile;
+    const uint32_t base = blockIdx.x * (uint32_t)(ITEMS * kBlock);
     // each wave owns a contiguous quarter of the tile: 16 rounds of 64
     const int w = threadIdx.x / kWave, l = lane_id();
-    const uint32_t wbase = base + (uint32_t)w * (kTile / 4);
-    uint32_t v[kItems];
+    const uint32_t wbase = base + (uint32_t)w * (uint32_t)(ITEMS * kBlock / 4);
+    uint32_t v[ITEMS];
     uint32_t wsum = 0;
-    for (int j = 0; j < kItems; ++j) {
+    for (int j = 0; j < ITEMS; ++j) {
         const uint32_t i = wbase + j * kWave + l;
         v[j] = i < n ? vals[gather ? gather[i] : i] : 0u;
         wsum += v[j];
@@ -126,7 +128,7 @@ __global__ void __launch_bounds__(kBlock) k_scan_apply(const uint32_t* __restric
     __syncthreads();
     uint32_t run = block_sums[blockIdx.x];
     for (int k = 0; k < w; ++k) run += s_w[k];
-    for (int j = 0; j < kItems; ++j) {
+    for (int j = 0; j < ITEMS; ++j) {
         uint32_t t;
         const uint32_t ex = wave_excl_scan_u32(v[j], &t);
         const uint32_t i = wbase + j * kWave + l;
@@ -322,7 +324,10 @@ __global__ void __launch_bounds__(kBlock) k_radix_scatter(const uint32_t* __rest
 
 // ------------------------------------------------------------- host side
 
-uint32_t scan_blocks(uint32_t max_n) { return (max_n + kTile - 1) / kTile; }
+// Scans of up to 2^21 values use 2048-value workgroups (8 per thread), which
+// a scan of ~1 M values needs to fill the chip; larger ones 4096.
+static uint32_t scan_tile(uint32_t max_n) { return max_n <= (1u << 21) ? 8u * kBlock : (uint32_t)kTile; }
+uint32_t scan_blocks(uint32_t max_n) { return (max_n + scan_tile(max_n) - 1) / scan_tile(max_n); }
 
 hipError_t scan_excl(const uint32_t* vals, const uint32_t* gather, uint32_t n_host, const uint32_t* n_dev,
                      uint32_t max_n, uint32_t* block_sums, uint32_t* out, uint32_t* total, uint32_t cap,
@@ -330,14 +335,24 @@ hipError_t scan_excl(const uint32_t* vals, const uint32_t* gather, uint32_t n_ho
                      uint32_t stride2)
 {
     const uint32_t nb = scan_blocks(max_n);
+    const bool small = scan_tile(max_n) != (uint32_t)kTile;
     if (nb > 0) {
-        hipLaunchKernelGGL(k_block_reduce, dim3(nb), dim3(kBlock), 0, s, vals, gather, n_host, n_dev, block_sums);
+        if (small)
+            hipLaunchKernelGGL(k_block_reduce<8>, dim3(nb), dim3(kBlock), 0, s, vals, gather, n_host, n_dev,
+                               block_sums);
+        else
+            hipLaunchKernelGGL(k_block_reduce<kItems>, dim3(nb), dim3(kBlock), 0, s, vals, gather, n_host, n_dev,
+                               block_sums);
     }
     hipLaunchKernelGGL(k_scan_block_sums, dim3(1), dim3(kBlock), 0, s, block_sums, nb, total, cap, n_eff, overflow,
                        total_host);
     if (nb > 0) {
-        hipLaunchKernelGGL(k_scan_apply, dim3(nb), dim3(kBlock), 0, s, vals, gather, n_host, n_dev, block_sums,
-                           out, out2, stride2);
+        if (small)
+            hipLaunchKernelGGL(k_scan_apply<8>, dim3(nb), dim3(kBlock), 0, s, vals, gather, n_host, n_dev,
+                               block_sums, out, out2, stride2);
+        else
+            hipLaunchKernelGGL(k_scan_apply<kItems>, dim3(nb), dim3(kBlock), 0, s, vals, gather, n_host, n_dev,
+                               block_sums, out, out2, stride2);
     }
     return hipGetLastError();
 }
