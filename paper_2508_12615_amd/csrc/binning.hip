@@ -291,15 +291,36 @@ __global__ void __launch_bounds__(256) k_emit(const ImgDesc* __restrict__ descs,
 }
 
 // ranges[t] = [first, last + 1) of tile t in the sorted keys (pre-zeroed).
+// Four consecutive positions per thread (one 16-byte load; the keys array is
+// 256-byte aligned), with the neighbours of the first and last from memory.
 __global__ void __launch_bounds__(256) k_ranges(const uint32_t* __restrict__ keys,
                                                  const uint32_t* __restrict__ n_eff, uint2* __restrict__ ranges)
 {
-    const uint32_t s = blockIdx.x * 256u + threadIdx.x;
+    const uint32_t s0 = (blockIdx.x * 256u + threadIdx.x) * 4u;
     const uint32_t K = *n_eff;
-    if (s >= K) return;
-    const uint32_t t = keys[s];
-    if (s == 0 || keys[s - 1] != t) ranges[t].x = s;
-    if (s == K - 1 || keys[s + 1] != t) ranges[t].y = s + 1;
+    if (s0 >= K) return;
+    uint32_t k[4];
+    if (s0 + 3u < K) {
+        const uint4 q = *reinterpret_cast<const uint4*>(keys + s0);
+        k[0] = q.x;
+        k[1] = q.y;
+        k[2] = q.z;
+        k[3] = q.w;
+    } else {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) k[j] = s0 + (uint32_t)j < K ? keys[s0 + j] : 0u;
+    }
+    const bool first_starts = s0 == 0u || keys[s0 - 1u] != k[0];
+    const bool last_ends = s0 + 4u >= K || keys[s0 + 4u] != k[3];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const uint32_t s = s0 + (uint32_t)j;
+        if (s >= K) break;
+        const bool starts = j == 0 ? first_starts : k[j - 1] != k[j];
+        const bool ends = s == K - 1u || (j == 3 ? last_ends : k[j + 1] != k[j]);
+        if (starts) ranges[k[j]].x = s;
+        if (ends) ranges[k[j]].y = s + 1u;
+    }
 }
 
 // Longest-first tile order for the persistent queue: a counting sort of the
@@ -520,7 +541,8 @@ hipError_t launch_fill2_u32(uint32_t* p, uint32_t n, uint32_t* q, uint32_t m, ui
 
 hipError_t launch_ranges(const uint32_t* keys, const uint32_t* n_eff, uint32_t max_k, uint2* ranges, hipStream_t s)
 {
-    if (max_k > 0) hipLaunchKernelGGL(k_ranges, dim3(blocks_of(max_k)), dim3(256), 0, s, keys, n_eff, ranges);
+    if (max_k > 0)
+        hipLaunchKernelGGL(k_ranges, dim3(blocks_of((max_k + 3u) / 4u)), dim3(256), 0, s, keys, n_eff, ranges);
     return hipGetLastError();
 }
 
