@@ -643,7 +643,11 @@ __device__ __forceinline__ void bwd_tile(const ImgDesc* __restrict__ descs, int 
     // `smark` and the projection backward reads them as zero
     if (hi <= G.start) return;   // uniform over the workgroup
     const uint64_t below = (1ull << l) - 1ull;
-    float* mine = part + (size_t)w * kWave * kSlot;
+    // The block partials and hit masks alternate between two buffers from
+    // chunk to chunk, so one workgroup barrier per chunk suffices: the barrier
+    // after the next chunk's replay also orders every thread's combine of
+    // this chunk before its buffer is written again.
+    uint32_t pbuf = 0;
     Staged* st = stage[w];
     const unsigned long long* cm_row = cmask + (size_t)w * cmask_words;
     // Chunks are the 64-position words of the global list clipped to [start,
@@ -676,6 +680,9 @@ __device__ __forceinline__ void bwd_tile(const ImgDesc* __restrict__ descs, int 
     const int tcx = G.ox / TW, tcy = G.oy / TH;   // this tile in its image
     for (;;) {
         const uint32_t b = c0 & ~63u;
+        float* pcur = part + (size_t)pbuf * (NB * kWave * kSlot);
+        uint64_t* hcur = hitm + pbuf * NB;
+        float* mine = pcur + (size_t)w * kWave * kSlot;
         bool cmine[CR];
         uint32_t cprim[CR];
 #pragma unroll
@@ -706,7 +713,7 @@ __device__ __forceinline__ void bwd_tile(const ImgDesc* __restrict__ descs, int 
                 if ((mnn >> l) & 1ull) pnn = vals[(nn0 & ~63u) + (uint32_t)l];
             }
         }
-        if (l == 0) hitm[w] = m;
+        if (l == 0) hcur[w] = m;
         wave_lds_sync();
         const int nh = __popcll(m);
         auto replay = [&](const Staged& S) {
@@ -773,7 +780,7 @@ __device__ __forceinline__ void bwd_tile(const ImgDesc* __restrict__ descs, int 
         // positions some block staged get their slot written and marked
         uint64_t anyhit = 0ull;
 #pragma unroll
-        for (int k = 0; k < NB; ++k) anyhit |= hitm[k];
+        for (int k = 0; k < NB; ++k) anyhit |= hcur[k];
 #pragma unroll
         for (int r = 0; r < CR; ++r) {
             const uint32_t co = co0 + (uint32_t)r * CP;
@@ -783,9 +790,9 @@ __device__ __forceinline__ void bwd_tile(const ImgDesc* __restrict__ descs, int 
                 float s3[3];
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
-                    float sum = part[rr + c];
+                    float sum = pcur[rr + c];
 #pragma unroll
-                    for (int k = 1; k < NB; ++k) sum += part[(size_t)k * kWave * kSlot + rr + c];
+                    for (int k = 1; k < NB; ++k) sum += pcur[(size_t)k * kWave * kSlot + rr + c];
                     s3[c] = sum;
                 }
                 float* dst = slots + (size_t)ce * kSlot + cc3;
@@ -795,7 +802,7 @@ __device__ __forceinline__ void bwd_tile(const ImgDesc* __restrict__ descs, int 
                 if (cc3 == 0) atomicOr(smark + (ce >> 5), 1u << (ce & 31u));
             }
         }
-        __syncthreads();
+        pbuf ^= 1u;
         if (!more) break;
         cur = nx;
         m = mn;
@@ -825,9 +832,9 @@ __global__ void __launch_bounds__(TW * TH) k_blend_bwd(const ImgDesc* __restrict
 {
     constexpr int NB = (TW / 8) * (TH / 8);
     __shared__ Staged stage[NB][kWave];
-    __shared__ __attribute__((aligned(16))) float part[NB * kWave * kSlot];
+    __shared__ __attribute__((aligned(16))) float part[2 * NB * kWave * kSlot];
     __shared__ uint32_t top[NB];
-    __shared__ uint64_t hitm[NB];
+    __shared__ uint64_t hitm[2 * NB];
     if (*ovf) return;
     const uint32_t t = blockIdx.x;
     if (t >= n_tiles) return;
@@ -855,9 +862,9 @@ __global__ void __launch_bounds__(TW * TH) k_blend_bwd_q(const ImgDesc* __restri
 {
     constexpr int NB = (TW / 8) * (TH / 8);
     __shared__ Staged stage[NB][kWave];
-    __shared__ __attribute__((aligned(16))) float part[NB * kWave * kSlot];
+    __shared__ __attribute__((aligned(16))) float part[2 * NB * kWave * kSlot];
     __shared__ uint32_t top[NB];
-    __shared__ uint64_t hitm[NB];
+    __shared__ uint64_t hitm[2 * NB];
     __shared__ uint32_t qtile;
     if (*ovf) return;
     uint32_t lane = blockIdx.x % kQueueLanes;
