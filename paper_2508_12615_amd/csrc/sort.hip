@@ -143,53 +143,99 @@ __global__ void __launch_bounds__(kBlock) k_scan_apply(const uint32_t* __restric
 // ------------------------------------------------------------ radix sort
 
 // hist[d * nblocks + b] = number of elements of tile b with digit d.
+// Each thread counts ITEMS consecutive keys and adds a run of equal digits
+// with one LDS atomic: after a pass over the low digits the next digit comes
+// in long runs, and lanes adding to one counter at once are serialised.
 template <int BITS, int ITEMS>
 __global__ void __launch_bounds__(kBlock) k_radix_hist(const uint32_t* __restrict__ keys, uint32_t n_host,
                                                        const uint32_t* __restrict__ n_dev, int shift,
                                                        uint32_t nblocks, uint32_t* __restrict__ hist)
 {
+    static_assert(ITEMS % 4 == 0, "keys are read four at a time");
     constexpr int ND = 1 << BITS;
     __shared__ uint32_t s_h[ND];
     for (int d = threadIdx.x; d < ND; d += kBlock) s_h[d] = 0;
     __syncthreads();
     const uint32_t n = load_n(n_host, n_dev);
-    const uint32_t base = blockIdx.x * (uint32_t)(ITEMS * kBlock);
-    for (int j = 0; j < ITEMS; ++j) {
-        const uint32_t i = base + j * kBlock + threadIdx.x;
-        if (i < n) atomicAdd(&s_h[(keys[i] >> shift) & (ND - 1)], 1u);
+    const uint32_t i0 = blockIdx.x * (uint32_t)(ITEMS * kBlock) + threadIdx.x * (uint32_t)ITEMS;
+    if (i0 < n) {
+        uint32_t k[ITEMS];
+        if (i0 + ITEMS <= n) {
+            const uint4* q = reinterpret_cast<const uint4*>(keys + i0);
+#pragma unroll
+            for (int j = 0; j < ITEMS / 4; ++j) {
+                const uint4 x = q[j];
+                k[4 * j] = x.x;
+                k[4 * j + 1] = x.y;
+                k[4 * j + 2] = x.z;
+                k[4 * j + 3] = x.w;
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < ITEMS; ++j) k[j] = i0 + j < n ? keys[i0 + j] : 0u;
+        }
+        const uint32_t m = min((uint32_t)ITEMS, n - i0);   // valid keys of this thread, >= 1
+        uint32_t prev = (k[0] >> shift) & (ND - 1), run = 1;
+#pragma unroll
+        for (int j = 1; j < ITEMS; ++j) {
+            if ((uint32_t)j < m) {
+                const uint32_t d = (k[j] >> shift) & (ND - 1);
+                if (d == prev) {
+                    ++run;
+                } else {
+                    atomicAdd(&s_h[prev], run);
+                    prev = d;
+                    run = 1;
+                }
+            }
+        }
+        atomicAdd(&s_h[prev], run);
     }
     __syncthreads();
     for (int d = threadIdx.x; d < ND; d += kBlock) hist[(uint32_t)d * nblocks + blockIdx.x] = s_h[d];
 }
 
-// Exclusive scan of each digit's row of hist across blocks; row totals to dtot.
+// Exclusive scan of each digit's row of hist across blocks; row totals to
+// dtot.  A thread scans IPT consecutive entries in registers, so a row of up
+// to IPT * kBlock blocks takes one block-wide combine (two barriers).
+template <int IPT>
 __global__ void __launch_bounds__(kBlock) k_radix_rowscan(uint32_t* __restrict__ hist, uint32_t nblocks,
                                                           uint32_t* __restrict__ dtot)
 {
-    __shared__ uint32_t s_w[kBlock / kWave];
-    __shared__ uint32_t s_carry;
+    constexpr int NW = kBlock / kWave;
+    __shared__ uint32_t s_w[NW];
     uint32_t* row = hist + (uint32_t)blockIdx.x * nblocks;
-    if (threadIdx.x == 0) s_carry = 0;
-    __syncthreads();
-    for (uint32_t c = 0; c < nblocks; c += kBlock) {
-        const uint32_t i = c + threadIdx.x;
-        const uint32_t v = i < nblocks ? row[i] : 0u;
-        uint32_t wt;
-        const uint32_t ex = wave_excl_scan_u32(v, &wt);
-        if (lane_id() == 0) s_w[threadIdx.x / kWave] = wt;
-        __syncthreads();
-        uint32_t off = s_carry;
-        for (int w = 0; w < (int)(threadIdx.x / kWave); ++w) off += s_w[w];
-        if (i < nblocks) row[i] = off + ex;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            uint32_t t = 0;
-            for (int w = 0; w < kBlock / kWave; ++w) t += s_w[w];
-            s_carry += t;
+    const int w = threadIdx.x / kWave;
+    uint32_t carry = 0;
+    for (uint32_t c = 0; c < nblocks; c += IPT * kBlock) {
+        const uint32_t i0 = c + threadIdx.x * (uint32_t)IPT;
+        uint32_t v[IPT], sum = 0;
+#pragma unroll
+        for (int j = 0; j < IPT; ++j) {
+            v[j] = i0 + j < nblocks ? row[i0 + j] : 0u;
+            sum += v[j];
         }
+        uint32_t wt;
+        uint32_t ex = wave_excl_scan_u32(sum, &wt);
+        if (lane_id() == 0) s_w[w] = wt;
         __syncthreads();
+        uint32_t tot = 0;
+#pragma unroll
+        for (int x = 0; x < NW; ++x) {
+            const uint32_t t = s_w[x];
+            if (x < w) ex += t;
+            tot += t;
+        }
+        ex += carry;
+#pragma unroll
+        for (int j = 0; j < IPT; ++j) {
+            if (i0 + j < nblocks) row[i0 + j] = ex;
+            ex += v[j];
+        }
+        carry += tot;
+        __syncthreads();   // s_w is rewritten by the next chunk
     }
-    if (threadIdx.x == 0) dtot[blockIdx.x] = s_carry;
+    if (threadIdx.x == 0) dtot[blockIdx.x] = carry;
 }
 
 // W: a second payload (w_in/w_out) is permuted with the values.
@@ -363,7 +409,7 @@ static void radix_pass_t(const uint32_t* ki, const uint32_t* vi, const uint32_t*
                          uint32_t* dtot, hipStream_t s)
 {
     hipLaunchKernelGGL((k_radix_hist<BITS, ITEMS>), dim3(nb), dim3(kBlock), 0, s, ki, n_host, n_dev, shift, nb, hist);
-    hipLaunchKernelGGL(k_radix_rowscan, dim3(1 << BITS), dim3(kBlock), 0, s, hist, nb, dtot);
+    hipLaunchKernelGGL(k_radix_rowscan<8>, dim3(1 << BITS), dim3(kBlock), 0, s, hist, nb, dtot);
     if (wi)
         hipLaunchKernelGGL((k_radix_scatter<BITS, true, ITEMS>), dim3(nb), dim3(kBlock), 0, s, ki, vi, wi, n_host,
                            n_dev, shift, nb, hist, dtot, ko, vo, wo);
