@@ -258,19 +258,39 @@ __global__ void __launch_bounds__(64) k_put_descs(DescArgs a, int n, ImgDesc* __
 // slots (a slot is reused only after its previous copy has completed).
 // Skipped while a graph is being captured (the table is uploaded before
 // capture and stays valid for the graph's lifetime).
+static wipes_status put_descs(wipes_ctx* ctx, const std::vector<ImgDesc>& h, char* dst, hipStream_t s);
+
 wipes_status upload_descs(wipes_ctx* ctx, const wipes_params* p, const wipes_batch* b, const Layout& L, void* screen,
-                          hipStream_t s)
+                          hipStream_t s, bool reuse)
 {
     if (ctx->capturing) return WIPES_OK;
     std::vector<ImgDesc> h;
     fill_descs(p, b, h);
     const size_t bytes = h.size() * sizeof(ImgDesc);
+    char* dst = (char*)screen + L.s_descs;
+    // the table this context wrote last is still in place for the later
+    // stages of the same frame (they read the screen buffer that the
+    // projection filled, so it cannot have been overwritten meanwhile)
+    if (reuse && ctx->desc_dst == dst && ctx->desc_last.size() == h.size() &&
+        memcmp(ctx->desc_last.data(), h.data(), bytes) == 0)
+        return WIPES_OK;
+    ctx->desc_dst = nullptr;
+    wipes_status st = put_descs(ctx, h, dst, s);
+    if (st == WIPES_OK) {
+        ctx->desc_dst = dst;
+        ctx->desc_last.swap(h);
+    }
+    return st;
+}
+
+static wipes_status put_descs(wipes_ctx* ctx, const std::vector<ImgDesc>& h, char* dst, hipStream_t s)
+{
+    const size_t bytes = h.size() * sizeof(ImgDesc);
     if (h.size() <= (size_t)kDescArgMax) {
         DescArgs a;
         memset(&a, 0, sizeof(a));
         memcpy(a.d, h.data(), bytes);
-        hipLaunchKernelGGL(k_put_descs, dim3(1), dim3(64), 0, s, a, (int)h.size(),
-                           reinterpret_cast<ImgDesc*>((char*)screen + L.s_descs));
+        hipLaunchKernelGGL(k_put_descs, dim3(1), dim3(64), 0, s, a, (int)h.size(), reinterpret_cast<ImgDesc*>(dst));
         const hipError_t e = hipGetLastError();
         return e == hipSuccess ? WIPES_OK : hip_fail(ctx, e, "descriptor upload");
     }
@@ -282,7 +302,7 @@ wipes_status upload_descs(wipes_ctx* ctx, const wipes_params* p, const wipes_bat
         if (e != hipSuccess) return hip_fail(ctx, e, "staging event");
     }
     memcpy(slot.host, h.data(), bytes);
-    e = hipMemcpyAsync((char*)screen + L.s_descs, slot.host, bytes, hipMemcpyHostToDevice, s);
+    e = hipMemcpyAsync(dst, slot.host, bytes, hipMemcpyHostToDevice, s);
     if (e != hipSuccess) return hip_fail(ctx, e, "descriptor upload");
     e = hipEventRecord(slot.ev, s);
     if (e != hipSuccess) return hip_fail(ctx, e, "staging event record");
@@ -478,7 +498,7 @@ wipes_status wipes_bin_sort(wipes_ctx* ctx, const wipes_params* p, const wipes_b
     wipes_status st = prologue(ctx, p, b, screen, bins, false, false, &L);
     if (st != WIPES_OK) return st;
     hipStream_t s = (hipStream_t)stream;
-    if ((st = upload_descs(ctx, p, b, L, screen->base, s)) != WIPES_OK) return st;
+    if ((st = upload_descs(ctx, p, b, L, screen->base, s, true)) != WIPES_OK) return st;
     return bin_sort_core(ctx, p, b, L, screen->base, bins->base, n_instances_out, s);
 }
 
@@ -493,7 +513,7 @@ wipes_status wipes_render_fwd(wipes_ctx* ctx, const wipes_params* p, const wipes
     if (p->mode == WIPES_3D_ALPHA && (!T_final || !last))
         return fail(ctx, WIPES_ERR_INVALID, "alpha mode needs T_final and last");
     hipStream_t s = (hipStream_t)stream;
-    if ((st = upload_descs(ctx, p, b, L, screen->base, s)) != WIPES_OK) return st;
+    if ((st = upload_descs(ctx, p, b, L, screen->base, s, true)) != WIPES_OK) return st;
     return render_fwd_core(ctx, p, b, L, screen->base, bins->base, image, T_final, last, s);
 }
 
@@ -509,7 +529,7 @@ wipes_status wipes_render_bwd(wipes_ctx* ctx, const wipes_params* p, const wipes
     if (p->mode == WIPES_3D_ALPHA && (!T_final || !last))
         return fail(ctx, WIPES_ERR_INVALID, "alpha mode needs T_final and last");
     hipStream_t s = (hipStream_t)stream;
-    if ((st = upload_descs(ctx, p, b, L, screen->base, s)) != WIPES_OK) return st;
+    if ((st = upload_descs(ctx, p, b, L, screen->base, s, true)) != WIPES_OK) return st;
     return render_bwd_core(ctx, p, b, L, screen->base, bins->base, T_final, last, dL_dimage, dscreen, s);
 }
 
@@ -593,7 +613,7 @@ wipes_status wipes_render_stats(wipes_ctx* ctx, const wipes_params* p, const wip
     if (p->mode == WIPES_3D_ALPHA && (!T_final || !last))
         return fail(ctx, WIPES_ERR_INVALID, "alpha mode needs T_final and last");
     hipStream_t s = (hipStream_t)stream;
-    if ((st = upload_descs(ctx, p, b, L, screen->base, s)) != WIPES_OK) return st;
+    if ((st = upload_descs(ctx, p, b, L, screen->base, s, true)) != WIPES_OK) return st;
     return render_stats_core(ctx, p, b, L, screen->base, bins->base, T_final, last, out, s);
 }
 

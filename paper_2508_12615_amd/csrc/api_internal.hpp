@@ -56,6 +56,8 @@ struct wipes_ctx {
     uint32_t* k_host = nullptr;  // pinned word: instance count read back by bin_sort
     uint32_t* k_host_dev = nullptr;   // the same word as the device addresses it
     hipEvent_t k_ev = nullptr;   // recorded after the kernel that writes it
+    const void* desc_dst = nullptr;          // where the last descriptor table went
+    std::vector<wipes::ImgDesc> desc_last;   // and what it held
     Profiler prof;
 };
 
@@ -89,8 +91,10 @@ bool tile_ok(int tw, int th);
 KParams kparams(const wipes_params* p);
 Layout layout_of(const wipes_params* p, const wipes_batch* b, int64_t cap, int with_bwd);
 void fill_descs(const wipes_params* p, const wipes_batch* b, std::vector<ImgDesc>& out);
+// reuse: skip the upload when this context's last upload put the same table
+// at the same place (for the stages after the projection of one frame)
 wipes_status upload_descs(wipes_ctx* ctx, const wipes_params* p, const wipes_batch* b, const Layout& L, void* screen,
-                          hipStream_t s);
+                          hipStream_t s, bool reuse = false);
 
 // Brackets one stage with events when profiling is on (never while capturing).
 struct StageScope {
@@ -119,9 +123,11 @@ wipes_status render_stats_core(wipes_ctx* ctx, const wipes_params* p, const wipe
 // kernel launchers
 hipError_t launch_project(const ImgDesc* descs, int B, int32_t n_total, const KParams& kp, Rec* recs, Aux* aux,
                           hipStream_t s);
+// clr: two word ranges that the count kernel zeroes on its way (the tile
+// ranges of this bin_sort)
 hipError_t launch_bin_count(const ImgDesc* descs, int B, int32_t n_total, const KParams& kp, Rec* recs,
                             const void* aux, uint32_t* count, PrimPack* pk, uint32_t* dkey, uint32_t* dval,
-                            hipStream_t s);
+                            const Clear2& clr, hipStream_t s);
 hipError_t launch_rank_pack(int32_t n_total, const uint32_t* order, const PrimPack* pk, PrimPack* pkr,
                             uint32_t* cnt_r, hipStream_t s);
 hipError_t launch_emit(const ImgDesc* descs, int B, int32_t n_total, const KParams& kp, const PrimPack* pkx,

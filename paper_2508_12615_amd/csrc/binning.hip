@@ -61,8 +61,14 @@ __global__ void __launch_bounds__(256) k_bin_count(const ImgDesc* __restrict__ d
                                                     KParams kp, Rec* __restrict__ recs,
                                                     const Aux* __restrict__ aux, uint32_t* __restrict__ count,
                                                     PrimPack* __restrict__ pk, uint32_t* __restrict__ dkey,
-                                                    uint32_t* __restrict__ dval)
+                                                    uint32_t* __restrict__ dval, Clear2 clr)
 {
+    // zero what the later stages of this bin_sort expect cleared
+    {
+        const uint32_t g = blockIdx.x * 256u + threadIdx.x, gs = gridDim.x * 256u;
+        for (uint32_t k = g; k < clr.n0; k += gs) clr.p0[k] = 0u;
+        for (uint32_t k = g; k < clr.n1; k += gs) clr.p1[k] = 0u;
+    }
     // per lane of each wave: the ellipse and rectangle its primitive's tile
     // tests need, the offset of those tests in the wave's list, the kept mask
     __shared__ float4 s_pa[4][kWave];             // mx, my, ca, cb
@@ -476,13 +482,17 @@ __global__ void __launch_bounds__(256) k_fill2_u32(uint32_t* __restrict__ p, uin
 
 static inline uint32_t blocks_of(uint32_t n) { return (n + 255u) / 256u; }
 
+hipError_t launch_fill2_u32(uint32_t* p, uint32_t n, uint32_t* q, uint32_t m, uint32_t v, hipStream_t s);
+
 hipError_t launch_bin_count(const ImgDesc* descs, int B, int32_t n_total, const KParams& kp, Rec* recs,
                             const void* aux, uint32_t* count, PrimPack* pk, uint32_t* dkey, uint32_t* dval,
-                            hipStream_t s)
+                            const Clear2& clr, hipStream_t s)
 {
     if (n_total > 0)
         hipLaunchKernelGGL(k_bin_count, dim3(blocks_of((uint32_t)n_total)), dim3(256), 0, s, descs, B, n_total, kp,
-                           recs, (const Aux*)aux, count, pk, dkey, dval);
+                           recs, (const Aux*)aux, count, pk, dkey, dval, clr);
+    else
+        return launch_fill2_u32(clr.p0, clr.n0, clr.p1, clr.n1, 0u, s);
     return hipGetLastError();
 }
 

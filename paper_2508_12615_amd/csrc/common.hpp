@@ -82,6 +82,14 @@ struct __align__(16) ImgDesc {
     int32_t pad_;
 };
 
+// Two word ranges a kernel zeroes on its way (p0/p1 may be null with n 0).
+struct Clear2 {
+    uint32_t* p0;
+    uint32_t n0;
+    uint32_t* p1;
+    uint32_t n1;
+};
+
 // Rasterizer constants as the kernels see them.
 struct KParams {
     int32_t mode, cov, tile_w, tile_h, log2_tw, log2_th;

@@ -94,7 +94,10 @@ wipes_status bin_sort_core(wipes_ctx* ctx, const wipes_params* p, const wipes_ba
     const uint32_t n = (uint32_t)L.n;
     {
         StageScope sc(ctx, kStCount, s);
-        HIP_TRY(launch_bin_count(v.descs, L.B, (int32_t)n, kp, v.recs, v.aux, v.count, v.pk, v.dkey_a, v.dval_a, s),
+        // (the count kernel also zeroes the tile ranges for the end of this call)
+        const Clear2 clr{nullptr, 0u, (uint32_t*)v.ranges, (uint32_t)(2 * L.tiles)};
+        HIP_TRY(launch_bin_count(v.descs, L.B, (int32_t)n, kp, v.recs, v.aux, v.count, v.pk, v.dkey_a, v.dval_a, clr,
+                                 s),
                 "count");
     }
     // K, capacity check -> n_eff, overflow flag
@@ -154,7 +157,6 @@ wipes_status bin_sort_core(wipes_ctx* ctx, const wipes_params* p, const wipes_ba
     }
     const uint32_t* skeys = in_b ? v.keys_b : v.keys_a;
     StageScope sc(ctx, kStRanges, s);
-    HIP_TRY(launch_fill_u32((uint32_t*)v.ranges, (uint32_t)(2 * L.tiles), 0u, s), "ranges fill");
     HIP_TRY(launch_ranges(skeys, v.ctrl + kCtrlNEff, max_k, v.ranges, s), "ranges");
     if (p->persistent == 2)   // longest tile list first for the persistent queue
         HIP_TRY(launch_tile_lpt_order(v.ranges, (uint32_t)L.tiles, (uint32_t*)((char*)bins + L.b_lpt), v.order, s),

@@ -64,30 +64,42 @@ __global__ void __launch_bounds__(kBlock) k_scan_block_sums(uint32_t* __restrict
                                                             uint32_t* __restrict__ overflow,
                                                             uint32_t* __restrict__ total_host)
 {
-    __shared__ uint32_t s_w[kBlock / kWave];
-    __shared__ uint32_t s_carry;
-    if (threadIdx.x == 0) s_carry = 0;
-    __syncthreads();
-    for (uint32_t c = 0; c < nb; c += kBlock) {
-        const uint32_t i = c + threadIdx.x;
-        const uint32_t v = i < nb ? block_sums[i] : 0u;
-        uint32_t wt;
-        const uint32_t ex = wave_excl_scan_u32(v, &wt);
-        if (lane_id() == 0) s_w[threadIdx.x / kWave] = wt;
-        __syncthreads();
-        uint32_t off = s_carry;
-        for (int w = 0; w < (int)(threadIdx.x / kWave); ++w) off += s_w[w];
-        if (i < nb) block_sums[i] = off + ex;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            uint32_t t = 0;
-            for (int w = 0; w < kBlock / kWave; ++w) t += s_w[w];
-            s_carry += t;
+    // a thread scans 8 consecutive sums in registers: one block-wide combine
+    // per 2048 sums
+    constexpr int IPT = 8, NW = kBlock / kWave;
+    __shared__ uint32_t s_w[NW];
+    const int w = threadIdx.x / kWave;
+    uint32_t carry = 0;
+    for (uint32_t c = 0; c < nb; c += IPT * kBlock) {
+        const uint32_t i0 = c + threadIdx.x * (uint32_t)IPT;
+        uint32_t v[IPT], sum = 0;
+#pragma unroll
+        for (int j = 0; j < IPT; ++j) {
+            v[j] = i0 + j < nb ? block_sums[i0 + j] : 0u;
+            sum += v[j];
         }
+        uint32_t wt;
+        uint32_t ex = wave_excl_scan_u32(sum, &wt);
+        if (lane_id() == 0) s_w[w] = wt;
         __syncthreads();
+        uint32_t tot = 0;
+#pragma unroll
+        for (int x = 0; x < NW; ++x) {
+            const uint32_t t = s_w[x];
+            if (x < w) ex += t;
+            tot += t;
+        }
+        ex += carry;
+#pragma unroll
+        for (int j = 0; j < IPT; ++j) {
+            if (i0 + j < nb) block_sums[i0 + j] = ex;
+            ex += v[j];
+        }
+        carry += tot;
+        __syncthreads();   // s_w is rewritten by the next chunk
     }
     if (threadIdx.x == 0) {
-        const uint32_t t = s_carry;
+        const uint32_t t = carry;
         *total = t;
         if (total_host) {   // pinned host word: the host reads it once this kernel has completed
             *total_host = t;
