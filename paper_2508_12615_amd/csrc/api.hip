@@ -143,17 +143,15 @@ Layout layout_of(const wipes_params* p, const wipes_batch* b, int64_t cap, int w
     L.s_pk = take((size_t)n * sizeof(PrimPack));
     if (L.alpha) {
         L.s_pkr = take((size_t)n * sizeof(PrimPack));
-        L.s_cnt_r = take((size_t)n * 4);
         L.s_dkey_a = take((size_t)n * 4);
         L.s_dval_a = take((size_t)n * 4);
         L.s_dkey_b = take((size_t)n * 4);
         L.s_dval_b = take((size_t)n * 4);
-        L.s_off_rank = take((size_t)n * 4);
         L.s_dhist = take(((size_t)1 << radix_digit_bits(32)) * ((size_t)radix_max_blocks((uint32_t)n) + 1) * 4);
         L.s_ddtot = take(((size_t)1 << radix_digit_bits(32)) * 4);
     }
-    L.s_bsum = take((size_t)(scan_blocks((uint32_t)n) + 1) * 4);
-    L.s_bsum2 = take((size_t)(scan_blocks((uint32_t)n) + 1) * 4);
+    L.s_bsum = take((size_t)((n + 63) / 64 + 1) * 4);
+    L.s_bsum2 = take((size_t)((n + 63) / 64 + 1) * 4);
     L.s_ctrl = take(kCtrlWords * 4);
     L.s_descs = take((size_t)L.B * sizeof(ImgDesc));
     L.screen_bytes = o;

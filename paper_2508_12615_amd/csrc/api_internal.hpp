@@ -70,9 +70,10 @@ struct Layout {
     int with_bwd = 0;
     int64_t n = 0, pixels = 0, tiles = 0, cap = 0;
     // screen buffer
-    size_t s_recs, s_aux, s_count, s_off_id, s_dkey_a, s_dval_a, s_dkey_b, s_dval_b, s_off_rank, s_dhist, s_ddtot;
-    size_t s_pk, s_pkr, s_cnt_r;   // packed {count, box0, box1, slot base} per primitive / per depth rank
-    size_t s_bsum, s_bsum2, s_ctrl, s_descs, screen_bytes;
+    size_t s_recs, s_aux, s_count, s_off_id, s_dkey_a, s_dval_a, s_dkey_b, s_dval_b, s_dhist, s_ddtot;
+    size_t s_pk, s_pkr;   // packed {count, box0, box1, slot base, ...} per primitive / per depth rank
+    size_t s_bsum, s_bsum2;   // count sums per 64 primitives / per 64 depth ranks, scanned in place
+    size_t s_ctrl, s_descs, screen_bytes;
     // bins buffer
     size_t b_keys_a, b_vals_a, b_keys_b, b_vals_b, b_hist, b_dtot, b_ranges, b_order, b_lpt, b_tbsum, b_slots;
     size_t b_cmask;           // per 8x8 block of a tile, one bit per list position (backward only)
@@ -123,15 +124,20 @@ wipes_status render_stats_core(wipes_ctx* ctx, const wipes_params* p, const wipe
 // kernel launchers
 hipError_t launch_project(const ImgDesc* descs, int B, int32_t n_total, const KParams& kp, Rec* recs, Aux* aux,
                           hipStream_t s);
-// clr: two word ranges that the count kernel zeroes on its way (the tile
-// ranges of this bin_sort)
+// Counting: per primitive its kept tile count (count, pk), depth keys; per 64
+// primitives the count sum (wsum); clr: two word ranges that the kernel
+// zeroes on its way (the tile ranges of this bin_sort).
 hipError_t launch_bin_count(const ImgDesc* descs, int B, int32_t n_total, const KParams& kp, Rec* recs,
                             const void* aux, uint32_t* count, PrimPack* pk, uint32_t* dkey, uint32_t* dval,
-                            const Clear2& clr, hipStream_t s);
-hipError_t launch_rank_pack(int32_t n_total, const uint32_t* order, const PrimPack* pk, PrimPack* pkr,
-                            uint32_t* cnt_r, hipStream_t s);
+                            uint32_t* wsum, const Clear2& clr, hipStream_t s);
+// off_id[i] = pk[i].base = exclusive prefix of count (woff: scanned wave sums)
+hipError_t launch_count_apply(int32_t n_total, const uint32_t* count, const uint32_t* woff, uint32_t* off_id,
+                              PrimPack* pk, hipStream_t s);
+// pkr[r] = pk[order[r]], wsum_r: count sums of 64 ranks; and count_apply
+hipError_t launch_rank_pack(int32_t n_total, const uint32_t* order, PrimPack* pk, PrimPack* pkr, uint32_t* wsum_r,
+                            const uint32_t* count, const uint32_t* woff_c, uint32_t* off_id, hipStream_t s);
 hipError_t launch_emit(const ImgDesc* descs, int B, int32_t n_total, const KParams& kp, const PrimPack* pkx,
-                       const uint32_t* order, const uint32_t* offs, const uint32_t* n_eff, uint32_t* keys,
+                       const uint32_t* order, const uint32_t* woff, const uint32_t* n_eff, uint32_t* keys,
                        uint32_t* vals, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t n, uint32_t v, hipStream_t s);
 uint32_t lpt_slices(uint32_t n_tiles);   // workgroups of the two-pass longest-first order (256 counts each)
@@ -139,11 +145,12 @@ hipError_t launch_tile_lpt_order(const uint2* ranges, uint32_t n_tiles, uint32_t
                                  hipStream_t s);
 hipError_t launch_fill2_u32(uint32_t* p, uint32_t n, uint32_t* q, uint32_t m, uint32_t v, hipStream_t s);
 hipError_t launch_ranges(const uint32_t* keys, const uint32_t* n_eff, uint32_t max_k, uint2* ranges, hipStream_t s);
-uint32_t scan_blocks(uint32_t max_n);
-hipError_t scan_excl(const uint32_t* vals, const uint32_t* gather, uint32_t n_host, const uint32_t* n_dev,
-                     uint32_t max_n, uint32_t* block_sums, uint32_t* out, uint32_t* total, uint32_t cap,
-                     uint32_t* n_eff, uint32_t* overflow, hipStream_t s, uint32_t* total_host = nullptr,
-                     uint32_t* out2 = nullptr, uint32_t stride2 = 0);   // out2[i * stride2] = out[i] too
+// Exclusive scan of sums[0..n) in place by one workgroup; *total = sum, and
+// with n_eff set: *n_eff = total, or 0 with *overflow = 1 when cap != 0 and
+// total > cap; total_host (pinned) also gets the total when set.
+hipError_t scan_sums(uint32_t* sums, uint32_t n, uint32_t* total, uint32_t cap, uint32_t* n_eff, uint32_t* overflow,
+                     uint32_t* total_host, hipStream_t s);
+   // out2[i * stride2] = out[i] too
 int radix_passes(int nbits);
 int radix_digit_bits(int nbits);   // digit width of each pass of radix_sort
 uint32_t radix_max_blocks(uint32_t cap);   // histogram columns a sort of up to cap keys needs

@@ -61,7 +61,8 @@ __global__ void __launch_bounds__(256) k_bin_count(const ImgDesc* __restrict__ d
                                                     KParams kp, Rec* __restrict__ recs,
                                                     const Aux* __restrict__ aux, uint32_t* __restrict__ count,
                                                     PrimPack* __restrict__ pk, uint32_t* __restrict__ dkey,
-                                                    uint32_t* __restrict__ dval, Clear2 clr)
+                                                    uint32_t* __restrict__ dval, uint32_t* __restrict__ wsum,
+                                                    Clear2 clr)
 {
     // zero what the later stages of this bin_sort expect cleared
     {
@@ -159,6 +160,10 @@ __global__ void __launch_bounds__(256) k_bin_count(const ImgDesc* __restrict__ d
         mask = s_mask[w][l];
         if (ncull) c = (uint32_t)__popcll(mask);
     }
+    {   // the wave's count sum, for the offset scan
+        const uint32_t ws = wave_sum_u32(c);
+        if (l == 0) wsum[(blockIdx.x * 256u + (uint32_t)w * kWave) >> 6] = ws;
+    }
     if (!inr) return;
     recs[i].box0 = b0;
     recs[i].box1 = b1;
@@ -200,24 +205,62 @@ __device__ __forceinline__ uint32_t nth_set_bit(uint64_t m, uint32_t k)
     return pos;
 }
 
-// Depth-rank order of the packed per-primitive data: pkr[r] = the PrimPack
-// of primitive order[r] with its slot base off_id, cnt_r[r] its count.  One
-// gather here lets the rank scan and the emission read coalesced.
-__global__ void __launch_bounds__(256) k_rank_pack(int32_t n_total, const uint32_t* __restrict__ order,
-                                                    const PrimPack* __restrict__ pk,
-                                                    PrimPack* __restrict__ pkr, uint32_t* __restrict__ cnt_r)
+// Instance offsets by primitive: off_id[i] = pk[i].base = exclusive prefix
+// of count, from the scanned wave sums woff (one per 64 primitives) and the
+// prefix within the wave.
+__device__ __forceinline__ void count_apply(int32_t i, int32_t i0, int32_t n_total,
+                                            const uint32_t* __restrict__ count, const uint32_t* __restrict__ woff,
+                                            uint32_t* __restrict__ off_id, PrimPack* pk)
 {
-    const int32_t r = (int32_t)(blockIdx.x * 256u + threadIdx.x);
-    if (r >= n_total) return;
-    const PrimPack q = pk[order[r]];   // its slot base was filled in by the count scan
-    pkr[r] = q;
-    cnt_r[r] = q.count;
+    const bool ok = i < n_total;
+    uint32_t t;
+    const uint32_t ex = wave_excl_scan_u32(ok ? count[i] : 0u, &t);
+    if (ok) {
+        const uint32_t o = woff[i0 >> 6] + ex;
+        off_id[i] = o;
+        pk[i].base = o;
+    }
 }
 
-// Writes the instances of the primitive of rank r at offs[r]..: key = global
-// tile, value = primitive, tiles of the pixel box row-major.  Ranks are
-// primitive indices (order == NULL; pkx = per-primitive pack, offs = off_id)
-// or depth ranks (pkx = per-rank pack, prim = order[r]).  (An instance's
+__global__ void __launch_bounds__(256) k_count_apply(int32_t n_total, const uint32_t* __restrict__ count,
+                                                     const uint32_t* __restrict__ woff, uint32_t* __restrict__ off_id,
+                                                     PrimPack* __restrict__ pk)
+{
+    const int32_t i0 = (int32_t)(blockIdx.x * 256u + (threadIdx.x & ~63u));   // lane 0 of the wave
+    if (i0 >= n_total) return;   // wave-uniform
+    count_apply(i0 + lane_id(), i0, n_total, count, woff, off_id, pk);
+}
+
+// Depth-rank order of the packed per-primitive data: pkr[r] = the PrimPack
+// of primitive order[r] (its base field is not read from pkr), and the
+// count sum of each 64 ranks into wsum_r for the emission's offsets.  One
+// gather here lets the emission read coalesced.  The same threads also
+// apply the count offsets by primitive index (count_apply), which only the
+// backward and this kernel's successors read.
+__global__ void __launch_bounds__(256) k_rank_pack(int32_t n_total, const uint32_t* __restrict__ order, PrimPack* pk,
+                                                   PrimPack* __restrict__ pkr, uint32_t* __restrict__ wsum_r,
+                                                   const uint32_t* __restrict__ count,
+                                                   const uint32_t* __restrict__ woff_c, uint32_t* __restrict__ off_id)
+{
+    const int32_t r0 = (int32_t)(blockIdx.x * 256u + (threadIdx.x & ~63u));   // lane 0 of the wave
+    if (r0 >= n_total) return;   // wave-uniform
+    const int32_t r = r0 + lane_id();
+    uint32_t c = 0;
+    if (r < n_total) {
+        const PrimPack q = pk[order[r]];
+        pkr[r] = q;
+        c = q.count;
+    }
+    const uint32_t ws = wave_sum_u32(c);
+    if (lane_id() == 0) wsum_r[r0 >> 6] = ws;
+    count_apply(r, r0, n_total, count, woff_c, off_id, pk);
+}
+
+// Writes the instances of the primitive of rank r at its offset (woff[r /
+// 64], the scanned count sum of the ranks before its wave, plus the counts of
+// the lanes before it): key = global tile, value = primitive, tiles of the
+// pixel box row-major.  Ranks are primitive indices (order == NULL; pkx =
+// per-primitive pack) or depth ranks (pkx = per-rank pack, prim = order[r]).  (An instance's
 // gradient slot is its primitive's slot base plus the rank of its tile among
 // the primitive's kept tiles; the backward derives it from the pack.)
 //
@@ -228,7 +271,7 @@ __global__ void __launch_bounds__(256) k_rank_pack(int32_t n_total, const uint32
 __global__ void __launch_bounds__(256) k_emit(const ImgDesc* __restrict__ descs, int B, int32_t n_total,
                                                KParams kp, const PrimPack* __restrict__ pkx,
                                                const uint32_t* __restrict__ order,
-                                               const uint32_t* __restrict__ offs,
+                                               const uint32_t* __restrict__ woff,
                                                const uint32_t* __restrict__ n_eff, uint32_t* __restrict__ keys,
                                                uint32_t* __restrict__ vals)
 {
@@ -238,12 +281,11 @@ __global__ void __launch_bounds__(256) k_emit(const ImgDesc* __restrict__ descs,
     const int32_t r0 = (int32_t)(blockIdx.x * 256u + (uint32_t)w * kWave);   // rank of lane 0
     if (r0 >= n_total || *n_eff == 0u) return;   // wave-uniform
     const int32_t r = r0 + l;
-    uint32_t c = 0, prim = 0, base = 0, tilesx = 1, wd = 1, off = 0xffffffffu, mlo = 0, mhi = 0, full = 1;
+    uint32_t c = 0, prim = 0, base = 0, tilesx = 1, wd = 1, mlo = 0, mhi = 0, full = 1;
     if (r < n_total) {
         const PrimPack q = pkx[r];
         prim = order ? order[r] : (uint32_t)r;
         c = q.count;
-        off = offs[r];
         if (c) {
             const ImgDesc& d = descs[image_of_prim(descs, B, (int32_t)prim)];
             const int32_t tx0 = lo16(q.box0) >> kp.log2_tw, ty0 = hi16(q.box0) >> kp.log2_th;
@@ -256,10 +298,11 @@ __global__ void __launch_bounds__(256) k_emit(const ImgDesc* __restrict__ descs,
             full = q.full;
         }
     }
-    const uint32_t first = (uint32_t)__builtin_amdgcn_readfirstlane((int)off);   // lane 0 is in range
-    const uint32_t total = wave_sum_u32(c);
+    const uint32_t first = woff[r0 >> 6];   // offset of lane 0
+    uint32_t total;
+    const uint32_t ex = wave_excl_scan_u32(c, &total);
     // ranks past the end never match (start beyond every entry)
-    s_start[w][l] = r < n_total ? off - first : 0xffffffffu;
+    s_start[w][l] = r < n_total ? ex : 0xffffffffu;
     s_prim[w][l] = prim;
     s_base[w][l] = base;
     s_tx[w][l] = tilesx;
@@ -486,32 +529,41 @@ hipError_t launch_fill2_u32(uint32_t* p, uint32_t n, uint32_t* q, uint32_t m, ui
 
 hipError_t launch_bin_count(const ImgDesc* descs, int B, int32_t n_total, const KParams& kp, Rec* recs,
                             const void* aux, uint32_t* count, PrimPack* pk, uint32_t* dkey, uint32_t* dval,
-                            const Clear2& clr, hipStream_t s)
+                            uint32_t* wsum, const Clear2& clr, hipStream_t s)
 {
     if (n_total > 0)
         hipLaunchKernelGGL(k_bin_count, dim3(blocks_of((uint32_t)n_total)), dim3(256), 0, s, descs, B, n_total, kp,
-                           recs, (const Aux*)aux, count, pk, dkey, dval, clr);
+                           recs, (const Aux*)aux, count, pk, dkey, dval, wsum, clr);
     else
         return launch_fill2_u32(clr.p0, clr.n0, clr.p1, clr.n1, 0u, s);
     return hipGetLastError();
 }
 
-hipError_t launch_rank_pack(int32_t n_total, const uint32_t* order, const PrimPack* pk, PrimPack* pkr,
-                            uint32_t* cnt_r, hipStream_t s)
+hipError_t launch_count_apply(int32_t n_total, const uint32_t* count, const uint32_t* woff, uint32_t* off_id,
+                              PrimPack* pk, hipStream_t s)
+{
+    if (n_total > 0)
+        hipLaunchKernelGGL(k_count_apply, dim3(blocks_of((uint32_t)n_total)), dim3(256), 0, s, n_total, count, woff,
+                           off_id, pk);
+    return hipGetLastError();
+}
+
+hipError_t launch_rank_pack(int32_t n_total, const uint32_t* order, PrimPack* pk, PrimPack* pkr, uint32_t* wsum_r,
+                            const uint32_t* count, const uint32_t* woff_c, uint32_t* off_id, hipStream_t s)
 {
     if (n_total > 0)
         hipLaunchKernelGGL(k_rank_pack, dim3(blocks_of((uint32_t)n_total)), dim3(256), 0, s, n_total, order, pk,
-                           pkr, cnt_r);
+                           pkr, wsum_r, count, woff_c, off_id);
     return hipGetLastError();
 }
 
 hipError_t launch_emit(const ImgDesc* descs, int B, int32_t n_total, const KParams& kp, const PrimPack* pkx,
-                       const uint32_t* order, const uint32_t* offs, const uint32_t* n_eff, uint32_t* keys,
+                       const uint32_t* order, const uint32_t* woff, const uint32_t* n_eff, uint32_t* keys,
                        uint32_t* vals, hipStream_t s)
 {
     if (n_total > 0)
         hipLaunchKernelGGL(k_emit, dim3(blocks_of((uint32_t)n_total)), dim3(256), 0, s, descs, B, n_total, kp, pkx,
-                           order, offs, n_eff, keys, vals);
+                           order, woff, n_eff, keys, vals);
     return hipGetLastError();
 }
 

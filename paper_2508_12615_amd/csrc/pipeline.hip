@@ -17,10 +17,9 @@ namespace wipes {
 struct Views {
     Rec* recs;
     Aux* aux;
-    uint32_t *count, *off_id, *dkey_a, *dval_a, *dkey_b, *dval_b, *off_rank, *dhist, *ddtot, *bsum, *bsum2, *ctrl;
+    uint32_t *count, *off_id, *dkey_a, *dval_a, *dkey_b, *dval_b, *dhist, *ddtot, *bsum, *bsum2, *ctrl;
     ImgDesc* descs;
     PrimPack *pk, *pkr;
-    uint32_t* cnt_r;
     uint32_t *keys_a, *vals_a, *keys_b, *vals_b, *hist, *dtot, *order, *tbsum;
     uint2* ranges;
     float* slots;
@@ -43,9 +42,7 @@ static Views views(const Layout& L, const void* screen, const void* bins)
         v.dval_a = (uint32_t*)(s + L.s_dval_a);
         v.dkey_b = (uint32_t*)(s + L.s_dkey_b);
         v.dval_b = (uint32_t*)(s + L.s_dval_b);
-        v.off_rank = (uint32_t*)(s + L.s_off_rank);
         v.pkr = (PrimPack*)(s + L.s_pkr);
-        v.cnt_r = (uint32_t*)(s + L.s_cnt_r);
         v.dhist = (uint32_t*)(s + L.s_dhist);
         v.ddtot = (uint32_t*)(s + L.s_ddtot);
     }
@@ -92,12 +89,13 @@ wipes_status bin_sort_core(wipes_ctx* ctx, const wipes_params* p, const wipes_ba
     const Views v = views(L, screen, bins);
     const KParams kp = kparams(p);
     const uint32_t n = (uint32_t)L.n;
+    const uint32_t nw = (n + 63u) / 64u;   // count sums, one per 64 primitives (or depth ranks)
     {
         StageScope sc(ctx, kStCount, s);
         // (the count kernel also zeroes the tile ranges for the end of this call)
         const Clear2 clr{nullptr, 0u, (uint32_t*)v.ranges, (uint32_t)(2 * L.tiles)};
-        HIP_TRY(launch_bin_count(v.descs, L.B, (int32_t)n, kp, v.recs, v.aux, v.count, v.pk, v.dkey_a, v.dval_a, clr,
-                                 s),
+        HIP_TRY(launch_bin_count(v.descs, L.B, (int32_t)n, kp, v.recs, v.aux, v.count, v.pk, v.dkey_a, v.dval_a,
+                                 v.bsum, clr, s),
                 "count");
     }
     // K, capacity check -> n_eff, overflow flag
@@ -106,17 +104,13 @@ wipes_status bin_sort_core(wipes_ctx* ctx, const wipes_params* p, const wipes_ba
         // the scan also stores K into the pinned host word when the caller
         // wants it; the host waits for it only before the emission, so the
         // round trip overlaps the depth sort
-        // (the offsets also go into the packs' slot base: the rank pack then
-        // gathers one record per primitive, and the backward finds each
-        // instance's gradient slot from its primitive's pack)
-        HIP_TRY(scan_excl(v.count, nullptr, n, nullptr, n, v.bsum, v.off_id, v.ctrl + kCtrlK, (uint32_t)L.cap,
-                          v.ctrl + kCtrlNEff, v.ctrl + kCtrlOverflow, s, n_instances_out ? ctx->k_host_dev : nullptr,
-                          &v.pk->base, (uint32_t)(sizeof(PrimPack) / 4)),
+        HIP_TRY(scan_sums(v.bsum, nw, v.ctrl + kCtrlK, (uint32_t)L.cap, v.ctrl + kCtrlNEff, v.ctrl + kCtrlOverflow,
+                          n_instances_out ? ctx->k_host_dev : nullptr, s),
                 "scan");
     }
     if (n_instances_out) HIP_TRY(hipEventRecord(ctx->k_ev, s), "read K event");
     const uint32_t* order = nullptr;
-    const uint32_t* offs = v.off_id;
+    const uint32_t* woff = v.bsum;
     if (L.alpha) {
         int in_b = 0;
         {
@@ -127,12 +121,18 @@ wipes_status bin_sort_core(wipes_ctx* ctx, const wipes_params* p, const wipes_ba
         order = in_b ? v.dval_b : v.dval_a;
         {
             StageScope sc(ctx, kStRankScan, s);
-            HIP_TRY(launch_rank_pack((int32_t)n, order, v.pk, v.pkr, v.cnt_r, s), "rank pack");
-            HIP_TRY(scan_excl(v.cnt_r, nullptr, n, nullptr, n, v.bsum2, v.off_rank, v.ctrl + 3, 0, nullptr, nullptr,
-                              s),
-                    "rank scan");
+            // the packs in depth order with the count sums of each 64 ranks;
+            // the same launch numbers each primitive's gradient slots (its
+            // instance offset: the backward finds an instance's slot from its
+            // primitive's pack)
+            HIP_TRY(launch_rank_pack((int32_t)n, order, v.pk, v.pkr, v.bsum2, v.count, v.bsum, v.off_id, s),
+                    "rank pack");
+            HIP_TRY(scan_sums(v.bsum2, nw, v.ctrl + 3, 0u, nullptr, nullptr, nullptr, s), "rank scan");
         }
-        offs = v.off_rank;
+        woff = v.bsum2;
+    } else {
+        StageScope sc(ctx, kStRankScan, s);
+        HIP_TRY(launch_count_apply((int32_t)n, v.count, v.bsum, v.off_id, v.pk, s), "count offsets");
     }
     uint32_t max_k = (uint32_t)L.cap;
     if (n_instances_out) {
@@ -144,7 +144,7 @@ wipes_status bin_sort_core(wipes_ctx* ctx, const wipes_params* p, const wipes_ba
     }
     {
         StageScope sc(ctx, kStEmit, s);
-        HIP_TRY(launch_emit(v.descs, L.B, (int32_t)n, kp, L.alpha ? v.pkr : v.pk, order, offs, v.ctrl + kCtrlNEff,
+        HIP_TRY(launch_emit(v.descs, L.B, (int32_t)n, kp, L.alpha ? v.pkr : v.pk, order, woff, v.ctrl + kCtrlNEff,
                             v.keys_a, v.vals_a, s),
                 "emit");
     }

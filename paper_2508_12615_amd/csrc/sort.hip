@@ -1,14 +1,20 @@
-// Device-wide exclusive scan and stable LSD radix sort of (uint32 key, uint32 value).
+// Scan of partial sums and stable LSD radix sort of (uint32 key, uint32 value).
 //
-// Both are written for 64-lane waves: a workgroup of 256 threads owns a tile
-// of elements (4096; 2048 for radix sorts of up to 2^21 keys, which need the
-// extra workgroups to fill the chip), each wave a contiguous quarter of it,
-// so loads are fully coalesced and the in-tile order (wave, round, lane) is
-// the element order.
-// The radix pass ranks a wave's 64 elements per round with ballot-based digit
-// matching (one ballot per digit bit), accumulates per-wave digit counters in
-// LDS, then stages the tile in LDS in sorted order and writes it out so that
-// runs of equal digits go to HBM as contiguous stores.
+// The scan is the middle step of an exclusive prefix: the kernels that
+// produce the values also write one sum per 64 of them, one workgroup scans
+// those sums here, and the kernels that need the per-element offsets add the
+// prefix within their wave themselves -- two launches fewer per prefix, which
+// on this chip costs more than the work they did.
+//
+// The radix sort is written for 64-lane waves: a workgroup of 256 threads
+// owns a tile of elements (4096; 2048 for sorts of up to 2^21 keys, which
+// need the extra workgroups to fill the chip), each wave a contiguous quarter
+// of it, so loads are fully coalesced and the in-tile order (wave, round,
+// lane) is the element order.  A pass ranks a wave's 64 elements per round
+// with ballot-based digit matching (one ballot per digit bit), accumulates
+// per-wave digit counters in LDS, then stages the tile in LDS in sorted order
+// and writes it out so that runs of equal digits go to HBM as contiguous
+// stores.
 //
 // Element counts may live in device memory (instance counts produced on the
 // device are never read back inside a captured graph); grids are sized by an
@@ -30,56 +36,35 @@ __device__ __forceinline__ uint32_t load_n(uint32_t n_host, const uint32_t* __re
 
 // ------------------------------------------------------------------ scan
 
-// block_sums[b] = sum of vals[gather ? gather[i] : i] over the tile of block b.
-template <int ITEMS>
-__global__ void __launch_bounds__(kBlock) k_block_reduce(const uint32_t* __restrict__ vals,
-                                                         const uint32_t* __restrict__ gather, uint32_t n_host,
-                                                         const uint32_t* __restrict__ n_dev,
-                                                         uint32_t* __restrict__ block_sums)
+// Exclusive scan of block_sums[0..nb) in place (one workgroup of 1024
+// threads); *total = sum.  If cap != 0 and the total exceeds it, *n_eff = 0
+// and *overflow = 1, else *n_eff = total (n_eff/overflow may be NULL).
+// A round covers 4096 sums: each thread reads four consecutive ones with one
+// 16-byte load (the wave's loads are one contiguous kilobyte), and the
+// workgroup combines the threads' sums once per round.
+constexpr int kSumsBlock = 1024;
+__global__ void __launch_bounds__(kSumsBlock) k_scan_block_sums(uint32_t* __restrict__ block_sums, uint32_t nb,
+                                                                uint32_t* __restrict__ total, uint32_t cap,
+                                                                uint32_t* __restrict__ n_eff,
+                                                                uint32_t* __restrict__ overflow,
+                                                                uint32_t* __restrict__ total_host)
 {
-    __shared__ uint32_t s_w[kBlock / kWave];
-    const uint32_t n = load_n(n_host, n_dev);
-    const uint32_t base = blockIdx.x * (uint32_t)(ITEMS * kBlock);
-    uint32_t acc = 0;
-    for (int j = 0; j < ITEMS; ++j) {
-        const uint32_t i = base + j * kBlock + threadIdx.x;
-        if (i < n) acc += vals[gather ? gather[i] : i];
-    }
-    acc = wave_sum_u32(acc);
-    if (lane_id() == 0) s_w[threadIdx.x / kWave] = acc;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        uint32_t t = 0;
-        for (int w = 0; w < kBlock / kWave; ++w) t += s_w[w];
-        block_sums[blockIdx.x] = t;
-    }
-}
-
-// Exclusive scan of block_sums[0..nb) in place (one workgroup); *total = sum.
-// If cap != 0 and the total exceeds it, *n_eff = 0 and *overflow = 1, else
-// *n_eff = total (n_eff/overflow may be NULL).
-__global__ void __launch_bounds__(kBlock) k_scan_block_sums(uint32_t* __restrict__ block_sums, uint32_t nb,
-                                                            uint32_t* __restrict__ total, uint32_t cap,
-                                                            uint32_t* __restrict__ n_eff,
-                                                            uint32_t* __restrict__ overflow,
-                                                            uint32_t* __restrict__ total_host)
-{
-    // a thread scans 8 consecutive sums in registers: one block-wide combine
-    // per 2048 sums
-    constexpr int IPT = 8, NW = kBlock / kWave;
+    constexpr int NW = kSumsBlock / kWave;
     __shared__ uint32_t s_w[NW];
     const int w = threadIdx.x / kWave;
     uint32_t carry = 0;
-    for (uint32_t c = 0; c < nb; c += IPT * kBlock) {
-        const uint32_t i0 = c + threadIdx.x * (uint32_t)IPT;
-        uint32_t v[IPT], sum = 0;
-#pragma unroll
-        for (int j = 0; j < IPT; ++j) {
-            v[j] = i0 + j < nb ? block_sums[i0 + j] : 0u;
-            sum += v[j];
+    for (uint32_t c = 0; c < nb; c += 4u * kSumsBlock) {
+        const uint32_t i0 = c + threadIdx.x * 4u;
+        uint4 v = make_uint4(0u, 0u, 0u, 0u);
+        if (i0 + 4u <= nb) {
+            v = *reinterpret_cast<const uint4*>(block_sums + i0);
+        } else if (i0 < nb) {
+            v.x = block_sums[i0];
+            if (i0 + 1u < nb) v.y = block_sums[i0 + 1u];
+            if (i0 + 2u < nb) v.z = block_sums[i0 + 2u];
         }
         uint32_t wt;
-        uint32_t ex = wave_excl_scan_u32(sum, &wt);
+        uint32_t ex = wave_excl_scan_u32(v.x + v.y + v.z + v.w, &wt);
         if (lane_id() == 0) s_w[w] = wt;
         __syncthreads();
         uint32_t tot = 0;
@@ -90,13 +75,16 @@ __global__ void __launch_bounds__(kBlock) k_scan_block_sums(uint32_t* __restrict
             tot += t;
         }
         ex += carry;
-#pragma unroll
-        for (int j = 0; j < IPT; ++j) {
-            if (i0 + j < nb) block_sums[i0 + j] = ex;
-            ex += v[j];
+        const uint4 o = make_uint4(ex, ex + v.x, ex + v.x + v.y, ex + v.x + v.y + v.z);
+        if (i0 + 4u <= nb) {
+            *reinterpret_cast<uint4*>(block_sums + i0) = o;
+        } else if (i0 < nb) {
+            block_sums[i0] = o.x;
+            if (i0 + 1u < nb) block_sums[i0 + 1u] = o.y;
+            if (i0 + 2u < nb) block_sums[i0 + 2u] = o.z;
         }
         carry += tot;
-        __syncthreads();   // s_w is rewritten by the next chunk
+        __syncthreads();   // s_w is rewritten by the next round
     }
     if (threadIdx.x == 0) {
         const uint32_t t = carry;
@@ -110,45 +98,6 @@ __global__ void __launch_bounds__(kBlock) k_scan_block_sums(uint32_t* __restrict
             *n_eff = over ? 0u : t;
             if (overflow) *overflow = over ? 1u : 0u;
         }
-    }
-}
-
-// out[i] = exclusive prefix of vals (through gather) + scanned block sum.
-template <int ITEMS>
-__global__ void __launch_bounds__(kBlock) k_scan_apply(const uint32_t* __restrict__ vals,
-                                                       const uint32_t* __restrict__ gather, uint32_t n_host,
-                                                       const uint32_t* __restrict__ n_dev,
-                                                       const uint32_t* __restrict__ block_sums,
-                                                       uint32_t* __restrict__ out, uint32_t* __restrict__ out2,
-                                                       uint32_t stride2)
-{
-    __shared__ uint32_t s_w[kBlock / kWave];
-    const uint32_t n = load_n(n_host, n_dev);
-    const uint32_t base = blockIdx.x * (uint32_t)(ITEMS * kBlock);
-    // each wave owns a contiguous quarter of the tile: 16 rounds of 64
-    const int w = threadIdx.x / kWave, l = lane_id();
-    const uint32_t wbase = base + (uint32_t)w * (uint32_t)(ITEMS * kBlock / 4);
-    uint32_t v[ITEMS];
-    uint32_t wsum = 0;
-    for (int j = 0; j < ITEMS; ++j) {
-        const uint32_t i = wbase + j * kWave + l;
-        v[j] = i < n ? vals[gather ? gather[i] : i] : 0u;
-        wsum += v[j];
-    }
-    wsum = wave_sum_u32(wsum);
-    if (l == 0) s_w[w] = wsum;
-    __syncthreads();
-    uint32_t run = block_sums[blockIdx.x];
-    for (int k = 0; k < w; ++k) run += s_w[k];
-    for (int j = 0; j < ITEMS; ++j) {
-        uint32_t t;
-        const uint32_t ex = wave_excl_scan_u32(v[j], &t);
-        const uint32_t i = wbase + j * kWave + l;
-        if (i < n) {
-            out[i] = run + ex;
-            if (out2) out2[(size_t)i * stride2] = run + ex;
-        }
-        run += t;
     }
 }
 
@@ -382,36 +331,11 @@ __global__ void __launch_bounds__(kBlock) k_radix_scatter(const uint32_t* __rest
 
 // ------------------------------------------------------------- host side
 
-// Scans of up to 2^21 values use 2048-value workgroups (8 per thread), which
-// a scan of ~1 M values needs to fill the chip; larger ones 4096.
-static uint32_t scan_tile(uint32_t max_n) { return max_n <= (1u << 21) ? 8u * kBlock : (uint32_t)kTile; }
-uint32_t scan_blocks(uint32_t max_n) { return (max_n + scan_tile(max_n) - 1) / scan_tile(max_n); }
-
-hipError_t scan_excl(const uint32_t* vals, const uint32_t* gather, uint32_t n_host, const uint32_t* n_dev,
-                     uint32_t max_n, uint32_t* block_sums, uint32_t* out, uint32_t* total, uint32_t cap,
-                     uint32_t* n_eff, uint32_t* overflow, hipStream_t s, uint32_t* total_host, uint32_t* out2,
-                     uint32_t stride2)
+hipError_t scan_sums(uint32_t* sums, uint32_t n, uint32_t* total, uint32_t cap, uint32_t* n_eff, uint32_t* overflow,
+                     uint32_t* total_host, hipStream_t s)
 {
-    const uint32_t nb = scan_blocks(max_n);
-    const bool small = scan_tile(max_n) != (uint32_t)kTile;
-    if (nb > 0) {
-        if (small)
-            hipLaunchKernelGGL(k_block_reduce<8>, dim3(nb), dim3(kBlock), 0, s, vals, gather, n_host, n_dev,
-                               block_sums);
-        else
-            hipLaunchKernelGGL(k_block_reduce<kItems>, dim3(nb), dim3(kBlock), 0, s, vals, gather, n_host, n_dev,
-                               block_sums);
-    }
-    hipLaunchKernelGGL(k_scan_block_sums, dim3(1), dim3(kBlock), 0, s, block_sums, nb, total, cap, n_eff, overflow,
+    hipLaunchKernelGGL(k_scan_block_sums, dim3(1), dim3(kSumsBlock), 0, s, sums, n, total, cap, n_eff, overflow,
                        total_host);
-    if (nb > 0) {
-        if (small)
-            hipLaunchKernelGGL(k_scan_apply<8>, dim3(nb), dim3(kBlock), 0, s, vals, gather, n_host, n_dev,
-                               block_sums, out, out2, stride2);
-        else
-            hipLaunchKernelGGL(k_scan_apply<kItems>, dim3(nb), dim3(kBlock), 0, s, vals, gather, n_host, n_dev,
-                               block_sums, out, out2, stride2);
-    }
     return hipGetLastError();
 }
 
