@@ -154,11 +154,12 @@ hipError_t scan_sums(uint32_t* sums, uint32_t n, uint32_t* total, uint32_t cap, 
 int radix_passes(int nbits);
 int radix_digit_bits(int nbits);   // digit width of each pass of radix_sort
 uint32_t radix_max_blocks(uint32_t cap);   // histogram columns a sort of up to cap keys needs
-// Stable LSD sort of (key, value[, w]) over the low nbits of the keys; ping-pongs
-// between the *0 and *1 arrays, *result_in_1 tells where the result is.
+// Stable LSD sort of (key, value) over the low nbits of the keys; ping-pongs
+// between the *0 and *1 arrays, *result_in_1 tells where the result is.  With
+// nbits <= 16 the keys must be below 2^16 (they are staged in 16 bits).
 hipError_t radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, uint32_t n_host,
                       const uint32_t* n_dev, uint32_t max_n, int nbits, uint32_t* hist, uint32_t* dtot,
-                      int* result_in_1, hipStream_t s, uint32_t* w0 = nullptr, uint32_t* w1 = nullptr);
+                      int* result_in_1, hipStream_t s);
 hipError_t launch_blend_fwd(const ImgDesc* descs, int B, const KParams& kp, const Rec* recs, const uint32_t* vals,
                             const uint2* ranges, const uint32_t* ovf, uint32_t n_tiles, const uint32_t* order,
                             uint32_t* queue, uint32_t persistent_blocks, float* image, float* T_final, int32_t* last,

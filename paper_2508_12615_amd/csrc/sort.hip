@@ -20,6 +20,7 @@
 // device are never read back inside a captured graph); grids are sized by an
 // upper bound and surplus workgroups exit.
 #include <algorithm>
+#include <type_traits>
 
 #include "common.hpp"
 
@@ -199,25 +200,28 @@ __global__ void __launch_bounds__(kBlock) k_radix_rowscan(uint32_t* __restrict__
     if (threadIdx.x == 0) dtot[blockIdx.x] = carry;
 }
 
-// W: a second payload (w_in/w_out) is permuted with the values.
-template <int BITS, bool W, int ITEMS>
+// K16: the keys fit in 16 bits and are staged in LDS as such (6 bytes per
+// element instead of 8), with 16-bit per-wave digit counters: six workgroups
+// per CU instead of four, so a 6.3 M-key sort runs in one round of
+// workgroups rather than one and a half.
+template <int BITS, bool K16, int ITEMS>
 __global__ void __launch_bounds__(kBlock) k_radix_scatter(const uint32_t* __restrict__ keys_in,
-                                                          const uint32_t* __restrict__ vals_in,
-                                                          const uint32_t* __restrict__ w_in, uint32_t n_host,
+                                                          const uint32_t* __restrict__ vals_in, uint32_t n_host,
                                                           const uint32_t* __restrict__ n_dev, int shift,
                                                           uint32_t nblocks, const uint32_t* __restrict__ hist,
                                                           const uint32_t* __restrict__ dtot,
                                                           uint32_t* __restrict__ keys_out,
-                                                          uint32_t* __restrict__ vals_out,
-                                                          uint32_t* __restrict__ w_out)
+                                                          uint32_t* __restrict__ vals_out)
 {
     constexpr int ND = 1 << BITS;
     constexpr int NW = kBlock / kWave;
     constexpr int TILE = ITEMS * kBlock;
-    __shared__ uint32_t s_keys[TILE];
+    using KeyT = typename std::conditional<K16, uint16_t, uint32_t>::type;
+    using CntT = KeyT;   // per-wave digit counts and their prefixes (at most a tile)
+    static_assert(!K16 || TILE <= 65535, "16-bit counters");
+    __shared__ KeyT s_keys[TILE];
     __shared__ uint32_t s_vals[TILE];
-    __shared__ uint32_t s_w[W ? TILE : 1];
-    __shared__ uint32_t s_wcnt[NW][ND];
+    __shared__ CntT s_wcnt[NW][ND];
     __shared__ uint32_t s_dbase[ND];
     __shared__ uint32_t s_gbase[ND];
     __shared__ uint32_t s_part[2][NW];
@@ -231,13 +235,12 @@ __global__ void __launch_bounds__(kBlock) k_radix_scatter(const uint32_t* __rest
 
     const uint32_t wbase = base + (uint32_t)w * (TILE / NW);
     const uint64_t lt_mask = (l == 0) ? 0ull : (~0ull >> (64 - l));
-    uint32_t k[ITEMS], v[ITEMS], ww[W ? ITEMS : 1], rk[ITEMS];
+    uint32_t k[ITEMS], v[ITEMS], rk[ITEMS];
     for (int j = 0; j < ITEMS; ++j) {
         const uint32_t i = wbase + j * kWave + l;
         const bool ok = i < n;
         k[j] = ok ? keys_in[i] : 0u;
         v[j] = ok ? vals_in[i] : 0u;
-        if (W) ww[j] = ok ? w_in[i] : 0u;
     }
     for (int j = 0; j < ITEMS; ++j) {
         const uint32_t i = wbase + j * kWave + l;
@@ -255,7 +258,7 @@ __global__ void __launch_bounds__(kBlock) k_radix_scatter(const uint32_t* __rest
         rk[j] = old + before;
         // the lowest lane of each digit group publishes the new count; every
         // lane of the wave has read the old value above (in-order LDS per wave)
-        if (ok && before == 0) s_wcnt[w][dig] = old + (uint32_t)__popcll(peers);
+        if (ok && before == 0) s_wcnt[w][dig] = (CntT)(old + (uint32_t)__popcll(peers));
     }
     __syncthreads();
     // per digit: exclusive prefix over waves, then over digits within the tile
@@ -263,7 +266,7 @@ __global__ void __launch_bounds__(kBlock) k_radix_scatter(const uint32_t* __rest
         uint32_t run = 0;
         for (int ww = 0; ww < NW; ++ww) {
             const uint32_t c = s_wcnt[ww][d];
-            s_wcnt[ww][d] = run;
+            s_wcnt[ww][d] = (CntT)run;
             run += c;
         }
         s_dbase[d] = run;   // tile total of digit d (scanned below)
@@ -312,20 +315,18 @@ __global__ void __launch_bounds__(kBlock) k_radix_scatter(const uint32_t* __rest
         if (i < n) {
             const uint32_t dig = (k[j] >> shift) & (ND - 1);
             const uint32_t pos = s_dbase[dig] + s_wcnt[w][dig] + rk[j];
-            s_keys[pos] = k[j];
+            s_keys[pos] = (KeyT)k[j];
             s_vals[pos] = v[j];
-            if (W) s_w[pos] = ww[j];
         }
     }
     __syncthreads();
     const uint32_t cnt = min((uint32_t)TILE, n - base);
     for (uint32_t p = threadIdx.x; p < cnt; p += kBlock) {
-        const uint32_t key = s_keys[p];
+        const uint32_t key = (uint32_t)s_keys[p];
         const uint32_t dig = (key >> shift) & (ND - 1);
         const uint32_t g = s_gbase[dig] + (p - s_dbase[dig]);
         keys_out[g] = key;
         vals_out[g] = s_vals[p];
-        if (W) w_out[g] = s_w[p];
     }
 }
 
@@ -339,19 +340,14 @@ hipError_t scan_sums(uint32_t* sums, uint32_t n, uint32_t* total, uint32_t cap, 
     return hipGetLastError();
 }
 
-template <int BITS, int ITEMS>
-static void radix_pass_t(const uint32_t* ki, const uint32_t* vi, const uint32_t* wi, uint32_t* ko, uint32_t* vo,
-                         uint32_t* wo, uint32_t n_host, const uint32_t* n_dev, uint32_t nb, int shift, uint32_t* hist,
-                         uint32_t* dtot, hipStream_t s)
+template <int BITS, bool K16, int ITEMS>
+static void radix_pass_t(const uint32_t* ki, const uint32_t* vi, uint32_t* ko, uint32_t* vo, uint32_t n_host,
+                         const uint32_t* n_dev, uint32_t nb, int shift, uint32_t* hist, uint32_t* dtot, hipStream_t s)
 {
     hipLaunchKernelGGL((k_radix_hist<BITS, ITEMS>), dim3(nb), dim3(kBlock), 0, s, ki, n_host, n_dev, shift, nb, hist);
     hipLaunchKernelGGL(k_radix_rowscan<8>, dim3(1 << BITS), dim3(kBlock), 0, s, hist, nb, dtot);
-    if (wi)
-        hipLaunchKernelGGL((k_radix_scatter<BITS, true, ITEMS>), dim3(nb), dim3(kBlock), 0, s, ki, vi, wi, n_host,
-                           n_dev, shift, nb, hist, dtot, ko, vo, wo);
-    else
-        hipLaunchKernelGGL((k_radix_scatter<BITS, false, ITEMS>), dim3(nb), dim3(kBlock), 0, s, ki, vi, nullptr,
-                           n_host, n_dev, shift, nb, hist, dtot, ko, vo, nullptr);
+    hipLaunchKernelGGL((k_radix_scatter<BITS, K16, ITEMS>), dim3(nb), dim3(kBlock), 0, s, ki, vi, n_host, n_dev,
+                       shift, nb, hist, dtot, ko, vo);
 }
 
 // Sorts of up to kSmallSort keys use 2048-key workgroups (8 keys per
@@ -372,14 +368,16 @@ uint32_t radix_max_blocks(uint32_t cap)
 }
 
 template <int BITS>
-static void radix_pass(const uint32_t* ki, const uint32_t* vi, const uint32_t* wi, uint32_t* ko, uint32_t* vo,
-                       uint32_t* wo, uint32_t n_host, const uint32_t* n_dev, uint32_t nb, int shift, uint32_t* hist,
-                       uint32_t* dtot, bool small, hipStream_t s)
+static void radix_pass(const uint32_t* ki, const uint32_t* vi, uint32_t* ko, uint32_t* vo, uint32_t n_host,
+                       const uint32_t* n_dev, uint32_t nb, int shift, uint32_t* hist, uint32_t* dtot, bool small,
+                       bool k16, hipStream_t s)
 {
     if (small)
-        radix_pass_t<BITS, 8>(ki, vi, wi, ko, vo, wo, n_host, n_dev, nb, shift, hist, dtot, s);
+        radix_pass_t<BITS, false, 8>(ki, vi, ko, vo, n_host, n_dev, nb, shift, hist, dtot, s);
+    else if (k16)
+        radix_pass_t<BITS, true, kItems>(ki, vi, ko, vo, n_host, n_dev, nb, shift, hist, dtot, s);
     else
-        radix_pass_t<BITS, kItems>(ki, vi, wi, ko, vo, wo, n_host, n_dev, nb, shift, hist, dtot, s);
+        radix_pass_t<BITS, false, kItems>(ki, vi, ko, vo, n_host, n_dev, nb, shift, hist, dtot, s);
 }
 
 // Passes of at most 8-bit digits.  (Wider digits save passes but shorten the
@@ -395,32 +393,31 @@ int radix_digit_bits(int nbits)
 
 hipError_t radix_sort(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, uint32_t n_host,
                       const uint32_t* n_dev, uint32_t max_n, int nbits, uint32_t* hist, uint32_t* dtot,
-                      int* result_in_1, hipStream_t s, uint32_t* w0, uint32_t* w1)
+                      int* result_in_1, hipStream_t s)
 {
     const int np = radix_passes(nbits);
     *result_in_1 = 0;
     const bool small = radix_tile(max_n) != (uint32_t)kTile;
+    const bool k16 = nbits <= 16;   // (the keys then fit in 16 bits)
     const uint32_t nb = radix_blocks(max_n);
     if (np == 0 || nb == 0) return hipGetLastError();
     const int bits = radix_digit_bits(nbits);
-    uint32_t *ki = k0, *vi = v0, *wi = w0, *ko = k1, *vo = v1, *wo = w1;
+    uint32_t *ki = k0, *vi = v0, *ko = k1, *vo = v1;
     for (int p = 0; p < np; ++p) {
         const int shift = p * bits;
         switch (bits) {
-        case 1: radix_pass<1>(ki, vi, wi, ko, vo, wo, n_host, n_dev, nb, shift, hist, dtot, small, s); break;
-        case 2: radix_pass<2>(ki, vi, wi, ko, vo, wo, n_host, n_dev, nb, shift, hist, dtot, small, s); break;
-        case 3: radix_pass<3>(ki, vi, wi, ko, vo, wo, n_host, n_dev, nb, shift, hist, dtot, small, s); break;
-        case 4: radix_pass<4>(ki, vi, wi, ko, vo, wo, n_host, n_dev, nb, shift, hist, dtot, small, s); break;
-        case 5: radix_pass<5>(ki, vi, wi, ko, vo, wo, n_host, n_dev, nb, shift, hist, dtot, small, s); break;
-        case 6: radix_pass<6>(ki, vi, wi, ko, vo, wo, n_host, n_dev, nb, shift, hist, dtot, small, s); break;
-        case 7: radix_pass<7>(ki, vi, wi, ko, vo, wo, n_host, n_dev, nb, shift, hist, dtot, small, s); break;
-        case 8: radix_pass<8>(ki, vi, wi, ko, vo, wo, n_host, n_dev, nb, shift, hist, dtot, small, s); break;
+        case 1: radix_pass<1>(ki, vi, ko, vo, n_host, n_dev, nb, shift, hist, dtot, small, k16, s); break;
+        case 2: radix_pass<2>(ki, vi, ko, vo, n_host, n_dev, nb, shift, hist, dtot, small, k16, s); break;
+        case 3: radix_pass<3>(ki, vi, ko, vo, n_host, n_dev, nb, shift, hist, dtot, small, k16, s); break;
+        case 4: radix_pass<4>(ki, vi, ko, vo, n_host, n_dev, nb, shift, hist, dtot, small, k16, s); break;
+        case 5: radix_pass<5>(ki, vi, ko, vo, n_host, n_dev, nb, shift, hist, dtot, small, k16, s); break;
+        case 6: radix_pass<6>(ki, vi, ko, vo, n_host, n_dev, nb, shift, hist, dtot, small, k16, s); break;
+        case 7: radix_pass<7>(ki, vi, ko, vo, n_host, n_dev, nb, shift, hist, dtot, small, k16, s); break;
+        case 8: radix_pass<8>(ki, vi, ko, vo, n_host, n_dev, nb, shift, hist, dtot, small, k16, s); break;
         default: return hipErrorInvalidValue;
         }
-        uint32_t* t;
-        t = ki; ki = ko; ko = t;
-        t = vi; vi = vo; vo = t;
-        t = wi; wi = wo; wo = t;
+        std::swap(ki, ko);
+        std::swap(vi, vo);
     }
     *result_in_1 = (np & 1);
     return hipGetLastError();
