@@ -91,9 +91,20 @@ def test_project_3d():
     # more than 2^21 primitives: the depth sort switches to 4096-key workgroups
     (B.WIPES_3D_ALPHA, 16, 16, 2_200_000, 7),
 ])
-def test_bin_sort_bit_exact(mode, tw, th, n, seed):
+@pytest.mark.parametrize("W,H", [(333, 257)])
+def test_bin_sort_bit_exact(mode, tw, th, n, seed, W, H):
     """Given the same FP32 records, boxes, instance keys, sorted order and ranges match O-bin."""
-    W, H = 333, 257
+    _bin_sort_case(mode, tw, th, n, seed, W, H)
+
+
+@pytest.mark.parametrize("mode", [B.WIPES_3D_ALPHA, B.WIPES_2D_ADDITIVE])
+def test_bin_sort_more_than_65536_tiles(mode):
+    """2200 x 2048 pixels in 8 x 8 tiles (70400 tiles, 17-bit tile keys): the tile sort
+    takes three passes and stages 32-bit keys; the result still matches O-bin bit for bit."""
+    _bin_sort_case(mode, 8, 8, 20000, 8, 2200, 2048)
+
+
+def _bin_sort_case(mode, tw, th, n, seed, W, H):
     rec = synth.screen_records(max(n, 1), W, H, seed)
     rec = {k: v[:n] for k, v in rec.items()}
     p = B.wipes_params_default(mode)
