@@ -238,10 +238,6 @@ void fill_descs(const wipes_params* p, const wipes_batch* b, std::vector<ImgDesc
 // Tables of up to kDescArgMax images travel as a kernel argument and one
 // wave writes them into the screen buffer: no copy from host memory, whose
 // blit and the wait after it cost more than the blend of a small image.
-constexpr int kDescArgMax = 8;
-struct DescArgs {
-    ImgDesc d[kDescArgMax];
-};
 
 __global__ void __launch_bounds__(64) k_put_descs(DescArgs a, int n, ImgDesc* __restrict__ out)
 {
@@ -259,8 +255,9 @@ __global__ void __launch_bounds__(64) k_put_descs(DescArgs a, int n, ImgDesc* __
 static wipes_status put_descs(wipes_ctx* ctx, const std::vector<ImgDesc>& h, char* dst, hipStream_t s);
 
 wipes_status upload_descs(wipes_ctx* ctx, const wipes_params* p, const wipes_batch* b, const Layout& L, void* screen,
-                          hipStream_t s, bool reuse)
+                          hipStream_t s, bool reuse, bool defer)
 {
+    ctx->desc_pend = false;
     if (ctx->capturing) return WIPES_OK;
     std::vector<ImgDesc> h;
     fill_descs(p, b, h);
@@ -273,12 +270,57 @@ wipes_status upload_descs(wipes_ctx* ctx, const wipes_params* p, const wipes_bat
         memcmp(ctx->desc_last.data(), h.data(), bytes) == 0)
         return WIPES_OK;
     ctx->desc_dst = nullptr;
+    if (defer && h.size() <= (size_t)kDescArgMax) {
+        // the caller's first launch (launch_fill2_put) writes the table
+        memset(&ctx->desc_pend_args, 0, sizeof(DescArgs));
+        memcpy(ctx->desc_pend_args.d, h.data(), bytes);
+        ctx->desc_pend_n = (int)h.size();
+        ctx->desc_pend_dst = dst;
+        ctx->desc_pend = true;
+        ctx->desc_last.swap(h);
+        return WIPES_OK;
+    }
     wipes_status st = put_descs(ctx, h, dst, s);
     if (st == WIPES_OK) {
         ctx->desc_dst = dst;
         ctx->desc_last.swap(h);
     }
     return st;
+}
+
+// Two fills (p[0..n), q[0..m)) and, when a table is pending, its copy
+// (words 32-bit words) into the screen buffer, in one launch.
+__global__ void __launch_bounds__(256) k_fill2_put(uint32_t* __restrict__ p, uint32_t n, uint32_t* __restrict__ q,
+                                                   uint32_t m, uint32_t v, DescArgs a, uint32_t words,
+                                                   uint32_t* __restrict__ out)
+{
+    const uint32_t i = blockIdx.x * 256u + threadIdx.x;
+    if (i < n) p[i] = v;
+    else if (i - n < m) q[i - n] = v;
+    if (i < words) out[i] = reinterpret_cast<const uint32_t*>(a.d)[i];
+}
+
+hipError_t launch_fill2_put(wipes_ctx* ctx, uint32_t* p, uint32_t n, uint32_t* q, uint32_t m, uint32_t v,
+                            hipStream_t s)
+{
+    if (!ctx->desc_pend) return launch_fill2_u32(p, n, q, m, v, s);
+    if (!q) m = 0;
+    if (!p) n = 0;
+    const uint32_t words = (uint32_t)ctx->desc_pend_n * (uint32_t)(sizeof(ImgDesc) / 4);
+    hipError_t e = hipSuccess;
+    if ((uint64_t)n + m >= (1ull << 32)) {   // (not in one launch)
+        e = launch_fill2_u32(p, n, q, m, v, s);
+        n = m = 0;
+    }
+    if (e == hipSuccess) {
+        const uint32_t cnt = std::max(n + m, words);
+        hipLaunchKernelGGL(k_fill2_put, dim3((cnt + 255u) / 256u), dim3(256), 0, s, p, n, q, m, v,
+                           ctx->desc_pend_args, words, reinterpret_cast<uint32_t*>(ctx->desc_pend_dst));
+        e = hipGetLastError();
+    }
+    ctx->desc_pend = false;
+    if (e == hipSuccess) ctx->desc_dst = ctx->desc_pend_dst;
+    return e;
 }
 
 static wipes_status put_descs(wipes_ctx* ctx, const std::vector<ImgDesc>& h, char* dst, hipStream_t s)
@@ -511,7 +553,7 @@ wipes_status wipes_render_fwd(wipes_ctx* ctx, const wipes_params* p, const wipes
     if (p->mode == WIPES_3D_ALPHA && (!T_final || !last))
         return fail(ctx, WIPES_ERR_INVALID, "alpha mode needs T_final and last");
     hipStream_t s = (hipStream_t)stream;
-    if ((st = upload_descs(ctx, p, b, L, screen->base, s, true)) != WIPES_OK) return st;
+    if ((st = upload_descs(ctx, p, b, L, screen->base, s, true, true)) != WIPES_OK) return st;
     return render_fwd_core(ctx, p, b, L, screen->base, bins->base, image, T_final, last, s);
 }
 
@@ -527,7 +569,7 @@ wipes_status wipes_render_bwd(wipes_ctx* ctx, const wipes_params* p, const wipes
     if (p->mode == WIPES_3D_ALPHA && (!T_final || !last))
         return fail(ctx, WIPES_ERR_INVALID, "alpha mode needs T_final and last");
     hipStream_t s = (hipStream_t)stream;
-    if ((st = upload_descs(ctx, p, b, L, screen->base, s, true)) != WIPES_OK) return st;
+    if ((st = upload_descs(ctx, p, b, L, screen->base, s, true, true)) != WIPES_OK) return st;
     return render_bwd_core(ctx, p, b, L, screen->base, bins->base, T_final, last, dL_dimage, dscreen, s);
 }
 

@@ -28,6 +28,12 @@ enum {
     kCtrlWords = kCtrlQueueBwd + wipes::kQueueLanes * wipes::kQueueStride
 };
 
+// A descriptor table small enough to travel as a kernel argument.
+constexpr int kDescArgMax = 8;
+struct DescArgs {
+    wipes::ImgDesc d[kDescArgMax];
+};
+
 struct StagingSlot {
     void* host = nullptr;
     hipEvent_t ev = nullptr;
@@ -58,6 +64,10 @@ struct wipes_ctx {
     hipEvent_t k_ev = nullptr;   // recorded after the kernel that writes it
     const void* desc_dst = nullptr;          // where the last descriptor table went
     std::vector<wipes::ImgDesc> desc_last;   // and what it held
+    bool desc_pend = false;                  // a table waits for launch_fill2_put
+    int desc_pend_n = 0;
+    char* desc_pend_dst = nullptr;
+    DescArgs desc_pend_args;
     Profiler prof;
 };
 
@@ -93,9 +103,14 @@ KParams kparams(const wipes_params* p);
 Layout layout_of(const wipes_params* p, const wipes_batch* b, int64_t cap, int with_bwd);
 void fill_descs(const wipes_params* p, const wipes_batch* b, std::vector<ImgDesc>& out);
 // reuse: skip the upload when this context's last upload put the same table
-// at the same place (for the stages after the projection of one frame)
+// at the same place (for the stages after the projection of one frame).
+// defer: a small table is left pending for the caller's first launch, which
+// must be launch_fill2_put.
 wipes_status upload_descs(wipes_ctx* ctx, const wipes_params* p, const wipes_batch* b, const Layout& L, void* screen,
-                          hipStream_t s, bool reuse = false);
+                          hipStream_t s, bool reuse = false, bool defer = false);
+// launch_fill2_u32 that also writes a pending descriptor table
+hipError_t launch_fill2_put(wipes_ctx* ctx, uint32_t* p, uint32_t n, uint32_t* q, uint32_t m, uint32_t v,
+                            hipStream_t s);
 
 // Brackets one stage with events when profiling is on (never while capturing).
 struct StageScope {

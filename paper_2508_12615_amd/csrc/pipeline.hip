@@ -182,7 +182,7 @@ wipes_status render_fwd_core(wipes_ctx* ctx, const wipes_params* p, const wipes_
     // queue counters, and the mask in which the forward records which
     // primitives contribute to each block (for the backward), cleared in one launch
     const size_t mwords = v.cmask ? (size_t)(p->tile_w / 8) * (p->tile_h / 8) * L.cmask_words * 2 : 0;
-    HIP_TRY(launch_fill2_u32(queue, queue ? kQueueLanes * kQueueStride : 0u, (uint32_t*)v.cmask, (uint32_t)mwords,
+    HIP_TRY(launch_fill2_put(ctx, queue, queue ? kQueueLanes * kQueueStride : 0u, (uint32_t*)v.cmask, (uint32_t)mwords,
                              0u, s),
             "queue reset / mask clear");
     StageScope sc(ctx, kStBlendFwd, s);
@@ -207,8 +207,8 @@ wipes_status render_bwd_core(wipes_ctx* ctx, const wipes_params* p, const wipes_
         queue = v.ctrl + kCtrlQueueBwd;
         pblocks = (uint32_t)ctx->n_cu * 8u;
     }
-    HIP_TRY(launch_fill2_u32(queue, queue ? kQueueLanes * kQueueStride : 0u, v.svalid, (uint32_t)(L.cap / 32 + 2), 0u,
-                             s),
+    HIP_TRY(launch_fill2_put(ctx, queue, queue ? kQueueLanes * kQueueStride : 0u, v.svalid, (uint32_t)(L.cap / 32 + 2),
+                             0u, s),
             "queue reset / slot marks clear");
     {
         StageScope sc(ctx, kStBlendBwd, s);
