@@ -521,12 +521,20 @@ wipes_status wipes_project(wipes_ctx* ctx, const wipes_params* p, const wipes_ba
     wipes_status st = prologue(ctx, p, b, screen, nullptr, false, false, &L);
     if (st != WIPES_OK) return st;
     hipStream_t s = (hipStream_t)stream;
-    if ((st = upload_descs(ctx, p, b, L, screen->base, s)) != WIPES_OK) return st;
+    // the projection always writes the table (a new frame may follow a
+    // different one in this screen buffer); a small one travels with the
+    // projection's own launch
+    const bool defer = L.n > 0;
+    if ((st = upload_descs(ctx, p, b, L, screen->base, s, false, defer)) != WIPES_OK) return st;
     char* base = (char*)screen->base;
     StageScope sc(ctx, kStProject, s);
+    const bool pend = ctx->desc_pend;
+    ctx->desc_pend = false;
     hipError_t e = launch_project((const ImgDesc*)(base + L.s_descs), L.B, (int32_t)L.n, kparams(p),
-                                  (Rec*)(base + L.s_recs), (Aux*)(base + L.s_aux), s);
+                                  (Rec*)(base + L.s_recs), (Aux*)(base + L.s_aux), s,
+                                  pend ? &ctx->desc_pend_args : nullptr, pend ? ctx->desc_pend_n : 0);
     if (e != hipSuccess) return hip_fail(ctx, e, "project");
+    if (pend) ctx->desc_dst = ctx->desc_pend_dst;
     return WIPES_OK;
 }
 

@@ -28,12 +28,6 @@ enum {
     kCtrlWords = kCtrlQueueBwd + wipes::kQueueLanes * wipes::kQueueStride
 };
 
-// A descriptor table small enough to travel as a kernel argument.
-constexpr int kDescArgMax = 8;
-struct DescArgs {
-    wipes::ImgDesc d[kDescArgMax];
-};
-
 struct StagingSlot {
     void* host = nullptr;
     hipEvent_t ev = nullptr;
@@ -67,7 +61,7 @@ struct wipes_ctx {
     bool desc_pend = false;                  // a table waits for launch_fill2_put
     int desc_pend_n = 0;
     char* desc_pend_dst = nullptr;
-    DescArgs desc_pend_args;
+    wipes::DescArgs desc_pend_args;
     Profiler prof;
 };
 
@@ -137,8 +131,10 @@ wipes_status render_stats_core(wipes_ctx* ctx, const wipes_params* p, const wipe
                                uint64_t* out, hipStream_t s);
 
 // kernel launchers
+// da/nda: a descriptor table passed as the argument (nda images), which the
+// kernel reads from there and stores at descs (nda = 0: read descs)
 hipError_t launch_project(const ImgDesc* descs, int B, int32_t n_total, const KParams& kp, Rec* recs, Aux* aux,
-                          hipStream_t s);
+                          hipStream_t s, const DescArgs* da = nullptr, int nda = 0);
 // Counting: per primitive its kept tile count (count, pk), depth keys; per 64
 // primitives the count sum (wsum); clr: two word ranges that the kernel
 // zeroes on its way (the tile ranges of this bin_sort).

@@ -82,6 +82,14 @@ struct __align__(16) ImgDesc {
     int32_t pad_;
 };
 
+// A descriptor table small enough to travel as a kernel argument (the
+// kernel that receives it may read it from there and store it for the
+// kernels after it).
+constexpr int kDescArgMax = 8;
+struct DescArgs {
+    ImgDesc d[kDescArgMax];
+};
+
 // Two word ranges a kernel zeroes on its way (p0/p1 may be null with n 0).
 struct Clear2 {
     uint32_t* p0;

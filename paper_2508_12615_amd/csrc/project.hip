@@ -15,6 +15,8 @@
 // The depth key is the one exception: it is defined as an FP32 evaluation
 // (fused multiply-adds in a fixed order) so that the compositing order is
 // reproducible bit for bit.
+#include <cstring>
+
 #include "common.hpp"
 
 namespace wipes {
@@ -52,9 +54,17 @@ __device__ __forceinline__ void support_box(double sxx, double syy, double Q, fl
 // the same kind of margin (0.1 % + 1e-3).
 __device__ __forceinline__ float support_threshold(double Q) { return (float)(Q * 1.001 + 1e-3); }
 
-__global__ void __launch_bounds__(256) k_project_2d(const ImgDesc* __restrict__ descs, int B, int32_t n_total,
-                                                     KParams kp, Rec* __restrict__ recs, Aux* __restrict__ aux)
+__global__ void __launch_bounds__(256) k_project_2d(const ImgDesc* __restrict__ descs_mem, int B, int32_t n_total,
+                                                     KParams kp, Rec* __restrict__ recs, Aux* __restrict__ aux, DescArgs da, int nda, ImgDesc* __restrict__ tab)
 {
+    // a table that came as the argument is read from there, and stored for
+    // the kernels after this one
+    const ImgDesc* __restrict__ descs = nda ? da.d : descs_mem;
+    if (nda && blockIdx.x == 0) {
+        const uint32_t words = (uint32_t)nda * (uint32_t)(sizeof(ImgDesc) / 4);
+        for (uint32_t k = threadIdx.x; k < words; k += 256u)
+            reinterpret_cast<uint32_t*>(tab)[k] = reinterpret_cast<const uint32_t*>(da.d)[k];
+    }
     const int32_t i = (int32_t)(blockIdx.x * 256u + threadIdx.x);
     if (i >= n_total) return;
     const ImgDesc& d = descs[image_of_prim(descs, B, i)];
@@ -96,9 +106,17 @@ __device__ __forceinline__ float depth_key(const float* __restrict__ V, float mx
     return fmaf(V[8], mx, fmaf(V[9], my, fmaf(V[10], mz, V[11])));
 }
 
-__global__ void __launch_bounds__(256) k_project_3d(const ImgDesc* __restrict__ descs, int B, int32_t n_total,
-                                                     KParams kp, Rec* __restrict__ recs, Aux* __restrict__ aux)
+__global__ void __launch_bounds__(256) k_project_3d(const ImgDesc* __restrict__ descs_mem, int B, int32_t n_total,
+                                                     KParams kp, Rec* __restrict__ recs, Aux* __restrict__ aux, DescArgs da, int nda, ImgDesc* __restrict__ tab)
 {
+    // a table that came as the argument is read from there, and stored for
+    // the kernels after this one
+    const ImgDesc* __restrict__ descs = nda ? da.d : descs_mem;
+    if (nda && blockIdx.x == 0) {
+        const uint32_t words = (uint32_t)nda * (uint32_t)(sizeof(ImgDesc) / 4);
+        for (uint32_t k = threadIdx.x; k < words; k += 256u)
+            reinterpret_cast<uint32_t*>(tab)[k] = reinterpret_cast<const uint32_t*>(da.d)[k];
+    }
     const int32_t i = (int32_t)(blockIdx.x * 256u + threadIdx.x);
     if (i >= n_total) return;
     const ImgDesc& d = descs[image_of_prim(descs, B, i)];
@@ -177,14 +195,19 @@ __global__ void __launch_bounds__(256) k_project_3d(const ImgDesc* __restrict__ 
 namespace wipes {
 
 hipError_t launch_project(const ImgDesc* descs, int B, int32_t n_total, const KParams& kp, Rec* recs, Aux* aux,
-                          hipStream_t s)
+                          hipStream_t s, const DescArgs* da, int nda)
 {
     if (n_total <= 0) return hipGetLastError();
     const dim3 grid(((uint32_t)n_total + 255u) / 256u);
+    DescArgs a;
+    if (da) a = *da;
+    else memset(&a, 0, sizeof(a));
+    if (!da) nda = 0;
+    ImgDesc* tab = const_cast<ImgDesc*>(descs);
     if (kp.mode == WIPES_2D_ADDITIVE)
-        hipLaunchKernelGGL(k_project_2d, grid, dim3(256), 0, s, descs, B, n_total, kp, recs, aux);
+        hipLaunchKernelGGL(k_project_2d, grid, dim3(256), 0, s, descs, B, n_total, kp, recs, aux, a, nda, tab);
     else
-        hipLaunchKernelGGL(k_project_3d, grid, dim3(256), 0, s, descs, B, n_total, kp, recs, aux);
+        hipLaunchKernelGGL(k_project_3d, grid, dim3(256), 0, s, descs, B, n_total, kp, recs, aux, a, nda, tab);
     return hipGetLastError();
 }
 
