@@ -269,9 +269,19 @@ wipes_status upload_descs(wipes_ctx* ctx, const wipes_params* p, const wipes_bat
     if (reuse && ctx->desc_dst == dst && ctx->desc_last.size() == h.size() &&
         memcmp(ctx->desc_last.data(), h.data(), bytes) == 0)
         return WIPES_OK;
+    // does the new table differ from the stored one in gradient pointers only?
+    bool grads_only = ctx->desc_dst == dst && ctx->desc_last.size() == h.size();
+    for (size_t k = 0; grads_only && k < h.size(); ++k) {
+        ImgDesc x = ctx->desc_last[k], y = h[k];
+        x.g_mean = x.g_cov = x.g_quat = x.g_scale = x.g_freq = x.g_color = x.g_opac = x.g_vel = nullptr;
+        y.g_mean = y.g_cov = y.g_quat = y.g_scale = y.g_freq = y.g_color = y.g_opac = y.g_vel = nullptr;
+        grads_only = memcmp(&x, &y, sizeof(ImgDesc)) == 0;
+    }
     ctx->desc_dst = nullptr;
     if (defer && h.size() <= (size_t)kDescArgMax) {
-        // the caller's first launch (launch_fill2_put) writes the table
+        // the caller's first launch (launch_fill2_put, or the projection
+        // backward after a fresh bin_sort) writes the table
+        ctx->desc_pend_grads_only = grads_only;
         memset(&ctx->desc_pend_args, 0, sizeof(DescArgs));
         memcpy(ctx->desc_pend_args.d, h.data(), bytes);
         ctx->desc_pend_n = (int)h.size();

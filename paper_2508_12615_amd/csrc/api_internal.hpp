@@ -59,6 +59,12 @@ struct wipes_ctx {
     const void* desc_dst = nullptr;          // where the last descriptor table went
     std::vector<wipes::ImgDesc> desc_last;   // and what it held
     bool desc_pend = false;                  // a table waits for launch_fill2_put
+    bool desc_pend_grads_only = false;       // it differs from the stored one in gradient pointers only
+    // bin_sort zeroed the queue counters, contribution mask and slot marks of
+    // this (screen, bins) pair: the next forward / backward render need not
+    const void* fresh_screen = nullptr;
+    const void* fresh_bins = nullptr;
+    bool fresh_fwd = false, fresh_bwd = false;
     int desc_pend_n = 0;
     char* desc_pend_dst = nullptr;
     wipes::DescArgs desc_pend_args;
@@ -159,8 +165,9 @@ hipError_t launch_ranges(const uint32_t* keys, const uint32_t* n_eff, uint32_t m
 // Exclusive scan of sums[0..n) in place by one workgroup; *total = sum, and
 // with n_eff set: *n_eff = total, or 0 with *overflow = 1 when cap != 0 and
 // total > cap; total_host (pinned) also gets the total when set.
+// clr[0..nclr) is zeroed on the way.
 hipError_t scan_sums(uint32_t* sums, uint32_t n, uint32_t* total, uint32_t cap, uint32_t* n_eff, uint32_t* overflow,
-                     uint32_t* total_host, hipStream_t s);
+                     uint32_t* total_host, hipStream_t s, uint32_t* clr = nullptr, uint32_t nclr = 0);
    // out2[i * stride2] = out[i] too
 int radix_passes(int nbits);
 int radix_digit_bits(int nbits);   // digit width of each pass of radix_sort
@@ -185,8 +192,10 @@ hipError_t launch_l2_grad(const ImgDesc* descs, int B, int32_t npix, const float
 hipError_t launch_pair_stats(const ImgDesc* descs, int B, const KParams& kp, const Rec* recs, const uint32_t* vals,
                              const uint2* ranges, const uint32_t* ovf, uint32_t n_tiles, const float* T_final,
                              const int32_t* last, unsigned long long* out, hipStream_t s);
+// da/nda: as launch_project (the table with this call's gradient pointers)
 hipError_t launch_project_bwd(const ImgDesc* descs, int B, int32_t n_total, const KParams& kp, const Rec* recs,
                               const uint32_t* count, const uint32_t* off_id, const float* slots,
-                              const uint32_t* valid, const uint32_t* overflow, float* dscreen, hipStream_t s);
+                              const uint32_t* valid, const uint32_t* overflow, float* dscreen, hipStream_t s,
+                              const DescArgs* da = nullptr, int nda = 0);
 
 }  // namespace wipes

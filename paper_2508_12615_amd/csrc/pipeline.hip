@@ -92,8 +92,12 @@ wipes_status bin_sort_core(wipes_ctx* ctx, const wipes_params* p, const wipes_ba
     const uint32_t nw = (n + 63u) / 64u;   // count sums, one per 64 primitives (or depth ranks)
     {
         StageScope sc(ctx, kStCount, s);
-        // (the count kernel also zeroes the tile ranges for the end of this call)
-        const Clear2 clr{nullptr, 0u, (uint32_t*)v.ranges, (uint32_t)(2 * L.tiles)};
+        // (the count kernel also zeroes the tile ranges for the end of this
+        // call, and with backward bins the contribution mask and slot marks
+        // of the renders that follow)
+        uint32_t* cm = v.cmask ? (uint32_t*)v.cmask : nullptr;
+        const uint32_t ncm = v.cmask ? (uint32_t)((L.b_svalid + (size_t)(L.cap / 32 + 2) * 4 - L.b_cmask) / 4) : 0u;
+        const Clear2 clr{cm, ncm, (uint32_t*)v.ranges, (uint32_t)(2 * L.tiles)};
         HIP_TRY(launch_bin_count(v.descs, L.B, (int32_t)n, kp, v.recs, v.aux, v.count, v.pk, v.dkey_a, v.dval_a,
                                  v.bsum, clr, s),
                 "count");
@@ -104,9 +108,16 @@ wipes_status bin_sort_core(wipes_ctx* ctx, const wipes_params* p, const wipes_ba
         // the scan also stores K into the pinned host word when the caller
         // wants it; the host waits for it only before the emission, so the
         // round trip overlaps the depth sort
+        // (and zeroes both persistent-queue counter sets)
         HIP_TRY(scan_sums(v.bsum, nw, v.ctrl + kCtrlK, (uint32_t)L.cap, v.ctrl + kCtrlNEff, v.ctrl + kCtrlOverflow,
-                          n_instances_out ? ctx->k_host_dev : nullptr, s),
+                          n_instances_out ? ctx->k_host_dev : nullptr, s, v.ctrl + kCtrlQueueFwd,
+                          (uint32_t)(kCtrlWords - kCtrlQueueFwd)),
                 "scan");
+    }
+    if (!ctx->capturing) {   // the first forward and backward render after this need not clear again
+        ctx->fresh_screen = screen;
+        ctx->fresh_bins = bins;
+        ctx->fresh_fwd = ctx->fresh_bwd = true;
     }
     if (n_instances_out) HIP_TRY(hipEventRecord(ctx->k_ev, s), "read K event");
     const uint32_t* order = nullptr;
@@ -180,11 +191,15 @@ wipes_status render_fwd_core(wipes_ctx* ctx, const wipes_params* p, const wipes_
         pblocks = (uint32_t)ctx->n_cu * 8u;
     }
     // queue counters, and the mask in which the forward records which
-    // primitives contribute to each block (for the backward), cleared in one launch
-    const size_t mwords = v.cmask ? (size_t)(p->tile_w / 8) * (p->tile_h / 8) * L.cmask_words * 2 : 0;
-    HIP_TRY(launch_fill2_put(ctx, queue, queue ? kQueueLanes * kQueueStride : 0u, (uint32_t*)v.cmask, (uint32_t)mwords,
-                             0u, s),
-            "queue reset / mask clear");
+    // primitives contribute to each block (for the backward), cleared in one
+    // launch -- unless bin_sort has just cleared them
+    const bool fresh = !ctx->capturing && ctx->fresh_fwd && ctx->fresh_screen == screen && ctx->fresh_bins == bins;
+    ctx->fresh_fwd = false;
+    const size_t mwords = v.cmask && !fresh ? (size_t)(p->tile_w / 8) * (p->tile_h / 8) * L.cmask_words * 2 : 0;
+    if (!fresh || ctx->desc_pend)
+        HIP_TRY(launch_fill2_put(ctx, fresh ? nullptr : queue, queue && !fresh ? kQueueLanes * kQueueStride : 0u,
+                                 (uint32_t*)v.cmask, (uint32_t)mwords, 0u, s),
+                "queue reset / mask clear");
     StageScope sc(ctx, kStBlendFwd, s);
     HIP_TRY(launch_blend_fwd(v.descs, L.B, kp, v.recs, svals, v.ranges, v.ctrl + kCtrlOverflow, (uint32_t)L.tiles,
                              order, queue, pblocks, image, T_final, last, v.cmask, L.cmask_words, s),
@@ -207,9 +222,19 @@ wipes_status render_bwd_core(wipes_ctx* ctx, const wipes_params* p, const wipes_
         queue = v.ctrl + kCtrlQueueBwd;
         pblocks = (uint32_t)ctx->n_cu * 8u;
     }
-    HIP_TRY(launch_fill2_put(ctx, queue, queue ? kQueueLanes * kQueueStride : 0u, v.svalid, (uint32_t)(L.cap / 32 + 2),
-                             0u, s),
-            "queue reset / slot marks clear");
+    // queue counters and slot marks cleared -- unless bin_sort has just
+    // cleared them; then a pending descriptor table that differs from the
+    // stored one only in gradient pointers (the blend reads none) travels
+    // with the projection backward, the only kernel that uses them
+    const bool fresh = !ctx->capturing && ctx->fresh_bwd && ctx->fresh_screen == screen &&
+                       ctx->fresh_bins == bins && (!ctx->desc_pend || ctx->desc_pend_grads_only);
+    ctx->fresh_bwd = false;
+    const bool pend_pbwd = fresh && ctx->desc_pend;
+    if (!fresh)
+        HIP_TRY(launch_fill2_put(ctx, queue, queue ? kQueueLanes * kQueueStride : 0u, v.svalid,
+                                 (uint32_t)(L.cap / 32 + 2), 0u, s),
+                "queue reset / slot marks clear");
+    if (pend_pbwd) ctx->desc_pend = false;
     {
         StageScope sc(ctx, kStBlendBwd, s);
         HIP_TRY(launch_blend_bwd(v.descs, L.B, kp, v.recs, svals, v.pk, v.ranges, v.ctrl + kCtrlOverflow,
@@ -219,8 +244,10 @@ wipes_status render_bwd_core(wipes_ctx* ctx, const wipes_params* p, const wipes_
     }
     StageScope sc(ctx, kStProjectBwd, s);
     HIP_TRY(launch_project_bwd(v.descs, L.B, (int32_t)L.n, kp, v.recs, v.count, v.off_id, v.slots, v.svalid,
-                               v.ctrl + kCtrlOverflow, dscreen, s),
+                               v.ctrl + kCtrlOverflow, dscreen, s, pend_pbwd ? &ctx->desc_pend_args : nullptr,
+                               pend_pbwd ? ctx->desc_pend_n : 0),
             "project bwd");
+    if (pend_pbwd && L.n > 0) ctx->desc_dst = ctx->desc_pend_dst;
     return WIPES_OK;
 }
 

@@ -17,6 +17,8 @@
 // The arithmetic is FP32: the inputs (screen record, slot sums, parameters)
 // are FP32 and the gradients are compared at 1e-3 relative, so FP64 would only
 // cost time (the forward projection is FP64 for the mean's sub-pixel phase).
+#include <cstring>
+
 #include "common.hpp"
 
 // Multiply-adds within one expression fuse into FMAs here (the rest of the
@@ -29,15 +31,23 @@ namespace wipes {
 constexpr int kSlotB = 12;
 using real = float;
 
-__global__ void __launch_bounds__(256) k_project_bwd(const ImgDesc* __restrict__ descs, int B, int32_t n_total,
+__global__ void __launch_bounds__(256) k_project_bwd(const ImgDesc* __restrict__ descs_mem, int B, int32_t n_total,
                                                       KParams kp, const Rec* __restrict__ recs,
                                                       const uint32_t* __restrict__ count,
                                                       const uint32_t* __restrict__ off_id,
                                                       const float* __restrict__ slots,
                                                       const uint32_t* __restrict__ valid,
                                                       const uint32_t* __restrict__ overflow,
-                                                      float* __restrict__ dscreen)
+                                                      float* __restrict__ dscreen, DescArgs da, int nda)
 {
+    // a table that came as the argument (the gradient pointers of this call)
+    // is read from there, and stored for later calls
+    const ImgDesc* __restrict__ descs = nda ? da.d : descs_mem;
+    if (nda && blockIdx.x == 0) {
+        const uint32_t words = (uint32_t)nda * (uint32_t)(sizeof(ImgDesc) / 4);
+        for (uint32_t k = threadIdx.x; k < words; k += 256u)
+            reinterpret_cast<uint32_t*>(const_cast<ImgDesc*>(descs_mem))[k] = reinterpret_cast<const uint32_t*>(da.d)[k];
+    }
     // slots per lane staged per chunk: a chunk of 128 slots lets a lane add
     // more of its primitive's slots per pass (the wave pays, per chunk, for
     // the lane with the most slots in it)
@@ -292,11 +302,16 @@ __global__ void __launch_bounds__(256) k_project_bwd(const ImgDesc* __restrict__
 
 hipError_t launch_project_bwd(const ImgDesc* descs, int B, int32_t n_total, const KParams& kp, const Rec* recs,
                               const uint32_t* count, const uint32_t* off_id, const float* slots,
-                              const uint32_t* valid, const uint32_t* overflow, float* dscreen, hipStream_t s)
+                              const uint32_t* valid, const uint32_t* overflow, float* dscreen, hipStream_t s,
+                              const DescArgs* da, int nda)
 {
+    DescArgs a;
+    if (da) a = *da;
+    else memset(&a, 0, sizeof(a));
+    if (!da) nda = 0;
     if (n_total > 0)
         hipLaunchKernelGGL(k_project_bwd, dim3(((uint32_t)n_total + 255u) / 256u), dim3(256), 0, s, descs, B, n_total,
-                           kp, recs, count, off_id, slots, valid, overflow, dscreen);
+                           kp, recs, count, off_id, slots, valid, overflow, dscreen, a, nda);
     return hipGetLastError();
 }
 

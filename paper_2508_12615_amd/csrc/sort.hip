@@ -48,8 +48,10 @@ __global__ void __launch_bounds__(kSumsBlock) k_scan_block_sums(uint32_t* __rest
                                                                 uint32_t* __restrict__ total, uint32_t cap,
                                                                 uint32_t* __restrict__ n_eff,
                                                                 uint32_t* __restrict__ overflow,
-                                                                uint32_t* __restrict__ total_host)
+                                                                uint32_t* __restrict__ total_host,
+                                                                uint32_t* __restrict__ clr, uint32_t nclr)
 {
+    for (uint32_t k = threadIdx.x; k < nclr; k += kSumsBlock) clr[k] = 0u;
     constexpr int NW = kSumsBlock / kWave;
     __shared__ uint32_t s_w[NW];
     const int w = threadIdx.x / kWave;
@@ -333,10 +335,10 @@ __global__ void __launch_bounds__(kBlock) k_radix_scatter(const uint32_t* __rest
 // ------------------------------------------------------------- host side
 
 hipError_t scan_sums(uint32_t* sums, uint32_t n, uint32_t* total, uint32_t cap, uint32_t* n_eff, uint32_t* overflow,
-                     uint32_t* total_host, hipStream_t s)
+                     uint32_t* total_host, hipStream_t s, uint32_t* clr, uint32_t nclr)
 {
     hipLaunchKernelGGL(k_scan_block_sums, dim3(1), dim3(kSumsBlock), 0, s, sums, n, total, cap, n_eff, overflow,
-                       total_host);
+                       total_host, clr, nclr);
     return hipGetLastError();
 }
 
