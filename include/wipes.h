@@ -220,7 +220,15 @@ wipes_status wipes_project(wipes_ctx* ctx, const wipes_params* p, const wipes_ba
  * (with *n_instances_out = K) if K exceeds the bins buffer's capacity.
  * n_instances_out == NULL: no host synchronisation (graph capture); an
  * overflow sets a device flag that turns the later stages into no-ops and is
- * reported by wipes_check_overflow. */
+ * reported by wipes_check_overflow.
+ * It also clears the persistent-queue counters, contribution mask and slot
+ * marks of the renders that follow, so the first wipes_render_fwd and the
+ * first wipes_render_bwd on the same context and buffers skip their own
+ * clearing; later renders of the same bins clear again.  Rendering these
+ * buffers through another context in between is not supported.
+ * wipes_project stores the batch's descriptor table in the screen buffer;
+ * the later stages of the frame reuse it when the batch is unchanged, so the
+ * screen buffer must still hold what wipes_project wrote (as it must anyway). */
 wipes_status wipes_bin_sort(wipes_ctx* ctx, const wipes_params* p, const wipes_batch* batch, wipes_buffer* screen,
                             wipes_buffer* bins, int64_t* n_instances_out, void* stream);
 
