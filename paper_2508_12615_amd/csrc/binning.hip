@@ -340,33 +340,38 @@ __global__ void __launch_bounds__(256) k_emit(const ImgDesc* __restrict__ descs,
 }
 
 // ranges[t] = [first, last + 1) of tile t in the sorted keys (pre-zeroed).
-// Four consecutive positions per thread (one 16-byte load; the keys array is
-// 256-byte aligned), with the neighbours of the first and last from memory.
+// Eight consecutive positions per thread (two 16-byte loads; the keys array
+// is 256-byte aligned), with the neighbours of the first and last from memory.
+constexpr uint32_t kRangePer = 8;
 __global__ void __launch_bounds__(256) k_ranges(const uint32_t* __restrict__ keys,
                                                  const uint32_t* __restrict__ n_eff, uint2* __restrict__ ranges)
 {
-    const uint32_t s0 = (blockIdx.x * 256u + threadIdx.x) * 4u;
+    const uint32_t s0 = (blockIdx.x * 256u + threadIdx.x) * kRangePer;
     const uint32_t K = *n_eff;
     if (s0 >= K) return;
-    uint32_t k[4];
-    if (s0 + 3u < K) {
-        const uint4 q = *reinterpret_cast<const uint4*>(keys + s0);
-        k[0] = q.x;
-        k[1] = q.y;
-        k[2] = q.z;
-        k[3] = q.w;
+    uint32_t k[kRangePer];
+    if (s0 + kRangePer - 1u < K) {
+        const uint4* q = reinterpret_cast<const uint4*>(keys + s0);
+#pragma unroll
+        for (uint32_t j = 0; j < kRangePer / 4u; ++j) {
+            const uint4 x = q[j];
+            k[4 * j] = x.x;
+            k[4 * j + 1] = x.y;
+            k[4 * j + 2] = x.z;
+            k[4 * j + 3] = x.w;
+        }
     } else {
 #pragma unroll
-        for (int j = 0; j < 4; ++j) k[j] = s0 + (uint32_t)j < K ? keys[s0 + j] : 0u;
+        for (uint32_t j = 0; j < kRangePer; ++j) k[j] = s0 + j < K ? keys[s0 + j] : 0u;
     }
     const bool first_starts = s0 == 0u || keys[s0 - 1u] != k[0];
-    const bool last_ends = s0 + 4u >= K || keys[s0 + 4u] != k[3];
+    const bool last_ends = s0 + kRangePer >= K || keys[s0 + kRangePer] != k[kRangePer - 1u];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        const uint32_t s = s0 + (uint32_t)j;
+    for (uint32_t j = 0; j < kRangePer; ++j) {
+        const uint32_t s = s0 + j;
         if (s >= K) break;
         const bool starts = j == 0 ? first_starts : k[j - 1] != k[j];
-        const bool ends = s == K - 1u || (j == 3 ? last_ends : k[j + 1] != k[j]);
+        const bool ends = s == K - 1u || (j == kRangePer - 1u ? last_ends : k[j + 1] != k[j]);
         if (starts) ranges[k[j]].x = s;
         if (ends) ranges[k[j]].y = s + 1u;
     }
@@ -405,32 +410,38 @@ __device__ __forceinline__ void lpt_rounds(const uint2* __restrict__ ranges, uin
 
 // The key of empty tiles (255; half the tiles of a typical frame) is counted
 // and placed once per wave rather than once per lane: per-lane LDS atomics on
-// one address serialise.
+// one address serialise.  (Called by whole waves: t_end bounds the tiles.)
+__device__ __forceinline__ void lpt_count1(uint32_t t, uint32_t key, uint32_t t_end, uint32_t* s_cnt)
+{
+    const bool in = t < t_end;
+    const uint64_t low = __ballot(in && key == 255u);
+    if (in && key != 255u) atomicAdd(&s_cnt[key], 1u);
+    if (low && lane_id() == 0) atomicAdd(&s_cnt[255], (uint32_t)__popcll(low));
+}
+
+__device__ __forceinline__ void lpt_place1(uint32_t t, uint32_t key, uint32_t t_end, uint32_t* s_cnt,
+                                           uint32_t* __restrict__ order)
+{
+    const int l = lane_id();
+    const uint64_t lt = (l == 0) ? 0ull : (~0ull >> (64 - l));
+    const bool in = t < t_end;
+    const uint64_t low = __ballot(in && key == 255u);
+    uint32_t at = 0u;
+    if (low && l == 0) at = atomicAdd(&s_cnt[255], (uint32_t)__popcll(low));
+    at = (uint32_t)__shfl((int)at, 0, kWave);
+    if (in) order[key == 255u ? at + (uint32_t)__popcll(low & lt) : atomicAdd(&s_cnt[key], 1u)] = t;
+}
+
 __device__ __forceinline__ void lpt_count(const uint2* __restrict__ ranges, uint32_t t_begin, uint32_t t_end,
                                           uint32_t* s_cnt)
 {
-    const int l = lane_id();
-    lpt_rounds(ranges, t_begin, t_end, [&](uint32_t t, uint32_t key) {
-        const bool in = t < t_end;
-        const uint64_t low = __ballot(in && key == 255u);
-        if (in && key != 255u) atomicAdd(&s_cnt[key], 1u);
-        if (low && l == 0) atomicAdd(&s_cnt[255], (uint32_t)__popcll(low));
-    });
+    lpt_rounds(ranges, t_begin, t_end, [&](uint32_t t, uint32_t key) { lpt_count1(t, key, t_end, s_cnt); });
 }
 
 __device__ __forceinline__ void lpt_place(const uint2* __restrict__ ranges, uint32_t t_begin, uint32_t t_end,
                                           uint32_t* s_cnt, uint32_t* __restrict__ order)
 {
-    const int l = lane_id();
-    const uint64_t lt = (l == 0) ? 0ull : (~0ull >> (64 - l));
-    lpt_rounds(ranges, t_begin, t_end, [&](uint32_t t, uint32_t key) {
-        const bool in = t < t_end;
-        const uint64_t low = __ballot(in && key == 255u);
-        uint32_t at = 0u;
-        if (low && l == 0) at = atomicAdd(&s_cnt[255], (uint32_t)__popcll(low));
-        at = (uint32_t)__shfl((int)at, 0, kWave);
-        if (in) order[key == 255u ? at + (uint32_t)__popcll(low & lt) : atomicAdd(&s_cnt[key], 1u)] = t;
-    });
+    lpt_rounds(ranges, t_begin, t_end, [&](uint32_t t, uint32_t key) { lpt_place1(t, key, t_end, s_cnt, order); });
 }
 
 // Exclusive scan of the 256 counts in place, by the first wave (four per lane).
@@ -458,12 +469,30 @@ __global__ void __launch_bounds__(1024) k_tile_lpt_order(const uint2* __restrict
 {
     __shared__ uint32_t s_cnt[256];
     if (threadIdx.x < 256) s_cnt[threadIdx.x] = 0u;
+    // the keys of all (at most kLptSlice) tiles, read once for both phases
+    constexpr uint32_t R = kLptSlice / kLptRound;
+    uint32_t key[R][kLptPer];
+#pragma unroll
+    for (uint32_t r = 0; r < R; ++r)
+#pragma unroll
+        for (uint32_t k = 0; k < kLptPer; ++k) {
+            const uint32_t t = r * kLptRound + k * 1024u + threadIdx.x;
+            key[r][k] = t < n_tiles ? lpt_key(ranges[t]) : 0u;
+        }
     __syncthreads();
-    lpt_count(ranges, 0u, n_tiles, s_cnt);
+#pragma unroll
+    for (uint32_t r = 0; r < R; ++r)
+#pragma unroll
+        for (uint32_t k = 0; k < kLptPer; ++k)
+            lpt_count1(r * kLptRound + k * 1024u + threadIdx.x, key[r][k], n_tiles, s_cnt);
     __syncthreads();
     lpt_scan(s_cnt);
     __syncthreads();
-    lpt_place(ranges, 0u, n_tiles, s_cnt, order);
+#pragma unroll
+    for (uint32_t r = 0; r < R; ++r)
+#pragma unroll
+        for (uint32_t k = 0; k < kLptPer; ++k)
+            lpt_place1(r * kLptRound + k * 1024u + threadIdx.x, key[r][k], n_tiles, s_cnt, order);
 }
 
 // More tiles: workgroup g counts the keys of slice g into counts[g][256] ...
@@ -604,7 +633,8 @@ hipError_t launch_fill2_u32(uint32_t* p, uint32_t n, uint32_t* q, uint32_t m, ui
 hipError_t launch_ranges(const uint32_t* keys, const uint32_t* n_eff, uint32_t max_k, uint2* ranges, hipStream_t s)
 {
     if (max_k > 0)
-        hipLaunchKernelGGL(k_ranges, dim3(blocks_of((max_k + 3u) / 4u)), dim3(256), 0, s, keys, n_eff, ranges);
+        hipLaunchKernelGGL(k_ranges, dim3(blocks_of((max_k + kRangePer - 1u) / kRangePer)), dim3(256), 0, s, keys,
+                           n_eff, ranges);
     return hipGetLastError();
 }
 
