@@ -77,8 +77,9 @@ __global__ void __launch_bounds__(256) k_project_bwd(const ImgDesc* __restrict__
     const uint32_t wlast = total ? (first + total - 1u) >> 5 : 0u;
     uint32_t wbase = first >> 5;
     uint32_t vword = (total && wbase + (uint32_t)l <= wlast) ? valid[wbase + (uint32_t)l] : 0u;
-    // a slot the backward did not write (no pixel of its tile reached it) is zero
-    auto fetch = [&](uint32_t k0, float4 (&sl)[SPL][3]) {
+    // a slot the backward did not write (no pixel of its tile reached it) is
+    // zero: it is neither loaded nor added (vm: the written slots of the chunk)
+    auto fetch = [&](uint32_t k0, float4 (&sl)[SPL][3], uint64_t (&vm)[SPL]) {
         const uint32_t lastw = (first + min(k0 + CH, total) - 1u) >> 5;
         if (lastw - wbase >= (uint32_t)kWave) {   // uniform: the window moves on
             wbase = (first + k0) >> 5;
@@ -89,7 +90,9 @@ __global__ void __launch_bounds__(256) k_project_bwd(const ImgDesc* __restrict__
             const uint32_t kk = k0 + (uint32_t)(q * kWave + l), e = first + kk;
             const uint32_t word = (uint32_t)__shfl((int)vword, (int)(((e >> 5) - wbase) & 63u), kWave);
             sl[q][0] = sl[q][1] = sl[q][2] = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (kk < total && ((word >> (e & 31u)) & 1u)) {
+            const bool w = kk < total && ((word >> (e & 31u)) & 1u);
+            vm[q] = __ballot(w);
+            if (w) {
                 const float4* src = reinterpret_cast<const float4*>(slots + (size_t)e * kSlotB);
                 sl[q][0] = src[0];
                 sl[q][1] = src[1];
@@ -98,10 +101,12 @@ __global__ void __launch_bounds__(256) k_project_bwd(const ImgDesc* __restrict__
         }
     };
     float4 cur[SPL][3];
-    if (total) fetch(0, cur);
+    uint64_t cm[SPL] = {};
+    if (total) fetch(0, cur, cm);
     for (uint32_t k0 = 0; k0 < total; k0 += CH) {
         float4 b[SPL][3];
-        if (k0 + CH < total) fetch(k0 + CH, b);
+        uint64_t bm[SPL] = {};
+        if (k0 + CH < total) fetch(k0 + CH, b, bm);
 #pragma unroll
         for (int q = 0; q < SPL; ++q) {
             if (k0 + (uint32_t)(q * kWave + l) < total) {
@@ -111,12 +116,26 @@ __global__ void __launch_bounds__(256) k_project_bwd(const ImgDesc* __restrict__
             }
         }
         wave_lds_sync();
-        const uint32_t e1 = min(my1, k0 + CH);
-        for (uint32_t e = max(my0, k0); e < e1; ++e) {
-            const float4 x0 = s_slot[wv][e - k0][0], x1 = s_slot[wv][e - k0][1], x2 = s_slot[wv][e - k0][2];
-            acc[0] += x0.x; acc[1] += x0.y; acc[2] += x0.z; acc[3] += x0.w;
-            acc[4] += x1.x; acc[5] += x1.y; acc[6] += x1.z; acc[7] += x1.w;
-            acc[8] += x2.x; acc[9] += x2.y; acc[10] += x2.z; acc[11] += x2.w;
+        // this lane's written slots of the chunk, in ascending order
+        const uint32_t lo = max(my0, k0), hi = min(my1, k0 + CH);
+        const uint32_t r0 = lo < hi ? lo - k0 : 0u, r1 = lo < hi ? hi - k0 : 0u;   // chunk-relative [r0, r1)
+#pragma unroll
+        for (int q = 0; q < SPL; ++q) {
+            const uint32_t a = max(r0, (uint32_t)(q * kWave)), z = min(r1, (uint32_t)(q * kWave + kWave));
+            uint64_t m = 0ull;
+            if (a < z) {
+                const uint32_t a1 = a - (uint32_t)(q * kWave), z1 = z - (uint32_t)(q * kWave);
+                const uint64_t upto = z1 >= 64u ? ~0ull : ((1ull << z1) - 1ull);
+                m = cm[q] & upto & ~((1ull << a1) - 1ull);
+            }
+            while (m) {
+                const uint32_t t = (uint32_t)__builtin_ctzll(m) + (uint32_t)(q * kWave);
+                m &= m - 1ull;
+                const float4 x0 = s_slot[wv][t][0], x1 = s_slot[wv][t][1], x2 = s_slot[wv][t][2];
+                acc[0] += x0.x; acc[1] += x0.y; acc[2] += x0.z; acc[3] += x0.w;
+                acc[4] += x1.x; acc[5] += x1.y; acc[6] += x1.z; acc[7] += x1.w;
+                acc[8] += x2.x; acc[9] += x2.y; acc[10] += x2.z; acc[11] += x2.w;
+            }
         }
         wave_lds_sync();   // the stage is rewritten next
 #pragma unroll
@@ -124,6 +143,7 @@ __global__ void __launch_bounds__(256) k_project_bwd(const ImgDesc* __restrict__
             cur[q][0] = b[q][0];
             cur[q][1] = b[q][1];
             cur[q][2] = b[q][2];
+            cm[q] = bm[q];
         }
     }
     if (!inr) return;
