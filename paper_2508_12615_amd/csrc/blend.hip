@@ -389,21 +389,18 @@ __device__ __forceinline__ void fwd_block(const ImgDesc* __restrict__ descs, int
                     continue;
                 }
                 const float a = S.op * p.W;
-                bool died = false;
                 const bool adds = alive && a >= kp.alpha_min;
-                if (adds) {
-                    const float al = fminf(a, kp.alpha_max);
-                    const float wt = T * al;
-                    C0 = fmaf(wt, cr, C0);
-                    C1 = fmaf(wt, cg, C1);
-                    C2 = fmaf(wt, cb, C2);
-                    T = T * (1.0f - al);
-                    lst = (int32_t)S.pos;
-                    if (T < kp.T_min) {
-                        alive = false;
-                        died = true;
-                    }
-                }
+                // branch-free: a pair that does not add gets alpha 0, for which
+                // the colour, T and `last` updates are exact identities
+                const float al = adds ? fminf(a, kp.alpha_max) : 0.0f;
+                const float wt = T * al;
+                C0 = fmaf(wt, cr, C0);
+                C1 = fmaf(wt, cg, C1);
+                C2 = fmaf(wt, cb, C2);
+                T = T * (1.0f - al);
+                lst = adds ? (int32_t)S.pos : lst;
+                const bool died = adds && T < kp.T_min;
+                alive = alive && !died;
                 if (__ballot(adds)) contrib |= 1ull << (S.pos & 63u);
                 if (__ballot(died)) {
                     const uint64_t am = __ballot(alive);
