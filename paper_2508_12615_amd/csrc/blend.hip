@@ -250,7 +250,8 @@ __device__ __forceinline__ bool ellipse_meets(const Rec& R, const PixBox& q, flo
     const float mx = R.mx + R.mxl, my = R.my + R.myl;
     const float x0 = (float)q.x0 + 0.5f, x1 = (float)q.x1 + 0.5f;
     const float y0 = (float)q.y0 + 0.5f, y1 = (float)q.y1 + 0.5f;
-    if (mx >= x0 && mx <= x1 && my >= y0 && my <= y1) return true;
+    // (branch-free: every lane evaluates the whole test)
+    const bool inside = (mx >= x0) & (mx <= x1) & (my >= y0) & (my <= y1);
     const float sy = -R.cb * __builtin_amdgcn_rcpf(R.cc), sx = -R.cb * __builtin_amdgcn_rcpf(R.ca);
     auto qv = [&](float dx, float dy) { return fmaf(R.ca * dx, dx, fmaf(2.0f * R.cb * dx, dy, R.cc * dy * dy)); };
     const float dxa = x0 - mx, dxb = x1 - mx, dya = y0 - my, dyb = y1 - my;
@@ -258,7 +259,7 @@ __device__ __forceinline__ bool ellipse_meets(const Rec& R, const PixBox& q, flo
     m = fminf(m, qv(dxb, fminf(fmaxf(sy * dxb, dya), dyb)));
     m = fminf(m, qv(fminf(fmaxf(sx * dya, dxa), dxb), dya));
     m = fminf(m, qv(fminf(fmaxf(sx * dyb, dxa), dxb), dyb));
-    return m <= Qs;
+    return inside | (m <= Qs);
 }
 
 // box0 of a lane past the end of a chunk: x0 = y0 = 65535 lies beyond every
@@ -355,7 +356,7 @@ __device__ __forceinline__ void fwd_block(const ImgDesc* __restrict__ descs, int
             // o W' >= alpha_min needs q <= 2 ln(o / alpha_min) (W' <= G')
             const float Qs = (MODE == WIPES_2D_ADDITIVE ? kp.q_add : 2.0f * __logf(cur.op / kp.alpha_min)) * 1.001f +
                              1e-3f;
-            const bool hit = box_meets(cur.box0, cur.box1, live) && ellipse_meets(cur, live, Qs);
+            const bool hit = box_meets(cur.box0, cur.box1, live) & ellipse_meets(cur, live, Qs);
             const uint64_t m = __ballot(hit);
             if (hit)
                 stage[__popcll(m & below)] = MODE == WIPES_2D_ADDITIVE ? stage_add(cur, bx, by, base + (uint32_t)l)
