@@ -14,7 +14,8 @@ The readings the paper leaves open (support, clamp, termination, pixel
 centres, key layout) are documented in wipes_oracle.c where they are used.
 
 Functions: project, depth_keys, render_o1, render_bwd_o1, render_o2,
-render_bwd_o2, project_bwd, bin_tiles.  All are pinned by tests/test_oracle_*.
+render_bwd_o2, project_bwd, bin_tiles, support_counts, sh_basis.  All are
+pinned by tests/test_oracle_*.
 """
 from __future__ import annotations
 
@@ -34,9 +35,12 @@ COV_CHOLESKY, COV_RS, COV_QUAT_SCALE = 0, 1, 2
 FREQ_VECTOR, FREQ_COVECTOR = 0, 1
 
 # screen record columns (FP64)
-SR = dict(mx=0, my=1, ca=2, cb=3, cc=4, fx=5, fy=6, op=7, r=8, g=9, b=10, depth=11, rx=12, ry=13, Q=14, valid=15)
+SR = dict(mx=0, my=1, ca=2, cb=3, cc=4, fx=5, fy=6, op=7, r=8, g=9, b=10, depth=11, rx=12, ry=13, Q=14, valid=15,
+          phase=16)
+SR_N = 17
 # screen-space gradient columns
-SG = dict(mx=0, my=1, ca=2, cb=3, cc=4, fx=5, fy=6, op=7, r=8, g=9, b=10)
+SG = dict(mx=0, my=1, ca=2, cb=3, cc=4, fx=5, fy=6, op=7, r=8, g=9, b=10, phase=11)
+SG_N = 12
 
 TIE_SUPPORT, TIE_SKIP, TIE_STOP, TIE_CLAMP, TIE_CULL = 1, 2, 4, 8, 16
 
@@ -53,7 +57,7 @@ def build(force: bool = False) -> str:
 
 
 class _Params(C.Structure):
-    _fields_ = [("mode", C.c_int32), ("cov", C.c_int32), ("freq_xform", C.c_int32), ("reserved", C.c_int32),
+    _fields_ = [("mode", C.c_int32), ("cov", C.c_int32), ("freq_xform", C.c_int32), ("sh_degree", C.c_int32),
                 ("alpha_min", C.c_double), ("alpha_max", C.c_double), ("T_min", C.c_double),
                 ("q_add", C.c_double), ("blur_eps", C.c_double), ("near_plane", C.c_double),
                 ("fov_guard", C.c_double), ("bg", C.c_double * 3)]
@@ -70,6 +74,7 @@ class Params:
     mode: int = MODE_ADD2D
     cov: int = COV_RS
     freq_xform: int = FREQ_VECTOR
+    sh_degree: int = -1          # < 0: direct RGB colour; 0..3: spherical-harmonic colour
     alpha_min: float = 1.0 / 255.0
     alpha_max: float = 0.99
     T_min: float = 1e-4
@@ -81,7 +86,7 @@ class Params:
 
     def c(self) -> _Params:
         p = _Params()
-        p.mode, p.cov, p.freq_xform, p.reserved = self.mode, self.cov, self.freq_xform, 0
+        p.mode, p.cov, p.freq_xform, p.sh_degree = self.mode, self.cov, self.freq_xform, self.sh_degree
         p.alpha_min, p.alpha_max, p.T_min = self.alpha_min, self.alpha_max, self.T_min
         p.q_add, p.blur_eps, p.near_plane, p.fov_guard = self.q_add, self.blur_eps, self.near_plane, self.fov_guard
         for k in range(3):
@@ -122,16 +127,17 @@ def lib():
         alt = os.environ.get("WIPES_ORACLE_LIB")
         _lib = C.CDLL(alt if alt else build())
         P = C.c_void_p
-        _lib.or_project.argtypes = [C.POINTER(_Params), C.POINTER(_Camera), C.c_int64] + [P] * 8 + [P]
+        _lib.or_project.argtypes = [C.POINTER(_Params), C.POINTER(_Camera), C.c_int64] + [P] * 10 + [P]
         _lib.or_depth_keys.argtypes = [C.c_int64, P, P, C.c_float, P, P]
         _lib.or_render_o1.argtypes = [C.POINTER(_Params), C.c_int32, C.c_int32, C.c_int64, P, P, C.c_int64,
-                                      P, P, P, P, P]
+                                      P, P, P, P, P, P]
         _lib.or_render_bwd_o1.argtypes = [C.POINTER(_Params), C.c_int32, C.c_int32, C.c_int64, P, P, C.c_int64,
                                           P, P, P, C.c_int32]
-        _lib.or_render_o2.argtypes = [C.POINTER(_Params), C.c_int32, C.c_int32, C.c_int64, P, P, P, P, P, P]
+        _lib.or_render_o2.argtypes = [C.POINTER(_Params), C.c_int32, C.c_int32, C.c_int64, P, P, P, P, P, P, P]
         _lib.or_render_bwd_o2.argtypes = [C.POINTER(_Params), C.c_int32, C.c_int32, C.c_int64, P, P, P, P, P, P,
                                           C.c_int32]
-        _lib.or_project_bwd.argtypes = [C.POINTER(_Params), C.POINTER(_Camera), C.c_int64] + [P] * 7 + [P] * 10
+        _lib.or_project_bwd.argtypes = [C.POINTER(_Params), C.POINTER(_Camera), C.c_int64] + [P] * 8 + [P] * 12
+        _lib.or_sh_basis.argtypes = [C.c_int32, C.c_int64, P, P, P]
         _lib.or_support_counts.argtypes = [C.POINTER(_Params), C.c_int32, C.c_int32, C.c_int64, P, P, C.c_int64,
                                            P, P, P]
         _lib.or_bin.argtypes = [C.c_int32] * 5 + [C.c_int64] + [P] * 9 + [P, P, P, P, P, P]
@@ -163,7 +169,10 @@ def _f64(a, shape=None):
 def _prims(prims: dict, n: int, three_d: bool):
     """Parameters as FP64 arrays (exact widening of the FP32 inputs)."""
     d = 3 if three_d else 2
+    sh = prims.get("sh")
     return dict(
+        phase=_f64(prims.get("phase"), (n,)) if prims.get("phase") is not None else None,
+        sh=_f64(sh) if sh is not None and three_d else None,
         mean=_f64(prims["mean"], (n, d)),
         cov=_f64(prims.get("cov"), (n, 3)) if not three_d else None,
         quat=_f64(prims.get("quat"), (n, 4)) if three_d else None,
@@ -176,17 +185,38 @@ def _prims(prims: dict, n: int, three_d: bool):
 
 
 def project(params: Params, prims: dict, cam: Camera | None = None) -> np.ndarray:
-    """FP64 screen records [n, 16] (columns in SR)."""
+    """FP64 screen records [n, SR_N] (columns in SR)."""
     n = int(np.asarray(prims["opacity"]).shape[0])
     three_d = params.mode == MODE_ALPHA3D
     q = _prims(prims, n, three_d)
-    out = np.zeros((n, 16), dtype=np.float64)
+    _check_sh(params, q, n)
+    out = np.zeros((n, SR_N), dtype=np.float64)
     cp = params.c()
     cc = cam.c() if cam is not None else None
     lib().or_project(C.byref(cp), C.byref(cc) if cc is not None else None, n, _p(q["mean"]), _p(q["cov"]),
                      _p(q["quat"]), _p(q["scale"]), _p(q["freq"]), _p(q["color"]), _p(q["opacity"]),
-                     _p(q["velocity"]), _p(out))
+                     _p(q["velocity"]), _p(q["phase"]), _p(q["sh"]), _p(out))
     return out
+
+
+def _check_sh(params: Params, q: dict, n: int):
+    if params.sh_degree >= 0:
+        if params.mode != MODE_ALPHA3D:
+            raise ValueError("spherical-harmonic colour is defined for 3D primitives")
+        K = (params.sh_degree + 1) ** 2
+        if q["sh"] is None or q["sh"].shape != (n, K, 3):
+            raise ValueError("sh must be [n, %d, 3] for degree %d" % (K, params.sh_degree))
+
+
+def sh_basis(degree: int, dirs) -> np.ndarray:
+    """Real spherical harmonics (Condon-Shortley phase) of unit directions [n, 3]: [n, (degree+1)^2],
+    and their polynomial gradients [n, (degree+1)^2, 3]."""
+    d = _f64(dirs, (-1, 3))
+    n = d.shape[0]
+    K = (degree + 1) ** 2
+    Y = np.zeros((n, K)); G = np.zeros((n, K, 3))
+    lib().or_sh_basis(degree, n, _p(d), _p(Y), _p(G))
+    return Y, G
 
 
 def depth_keys(prims: dict, cam: Camera) -> np.ndarray:
@@ -206,17 +236,20 @@ def _keys_or_none(params, keys):
     return np.ascontiguousarray(np.asarray(keys, dtype=np.uint32))
 
 
-def render_o1(params: Params, W: int, H: int, screen: np.ndarray, keys=None, pix=None):
-    """O1 brute force.  Returns (image [npix,3], T_final [npix], n_contrib [npix], tie [npix])."""
+def render_o1(params: Params, W: int, H: int, screen: np.ndarray, keys=None, pix=None, jump: bool = False):
+    """O1 brute force.  Returns (image [npix,3], T_final [npix], n_contrib [npix], tie [npix]) and, with
+    jump=True, the tie jump bounds [npix, 2] (image value, final T) as a fifth item."""
     screen = np.ascontiguousarray(screen, dtype=np.float64)
     n = screen.shape[0]
     pix = None if pix is None else np.ascontiguousarray(np.asarray(pix, dtype=np.int64))
     npix = W * H if pix is None else pix.shape[0]
     img = np.zeros((npix, 3)); T = np.zeros(npix); nc = np.zeros(npix, np.int32); tie = np.zeros(npix, np.uint8)
+    jb = np.zeros((npix, 2))
     k = _keys_or_none(params, keys)
     cp = params.c()
-    lib().or_render_o1(C.byref(cp), W, H, n, _p(screen), _p(k), npix, _p(pix), _p(img), _p(T), _p(nc), _p(tie))
-    return img, T, nc, tie
+    lib().or_render_o1(C.byref(cp), W, H, n, _p(screen), _p(k), npix, _p(pix), _p(img), _p(T), _p(nc), _p(tie),
+                       _p(jb))
+    return (img, T, nc, tie, jb) if jump else (img, T, nc, tie)
 
 
 def render_bwd_o1(params: Params, W: int, H: int, screen: np.ndarray, dLdC, keys=None, pix=None, max_threads=0):
@@ -226,23 +259,25 @@ def render_bwd_o1(params: Params, W: int, H: int, screen: np.ndarray, dLdC, keys
     pix = None if pix is None else np.ascontiguousarray(np.asarray(pix, dtype=np.int64))
     npix = W * H if pix is None else pix.shape[0]
     g = np.ascontiguousarray(np.asarray(dLdC, dtype=np.float64).reshape(npix, 3))
-    out = np.zeros((n, 11))
+    out = np.zeros((n, SG_N))
     k = _keys_or_none(params, keys)
     cp = params.c()
     lib().or_render_bwd_o1(C.byref(cp), W, H, n, _p(screen), _p(k), npix, _p(pix), _p(g), _p(out), max_threads)
     return out
 
 
-def render_o2(params: Params, W: int, H: int, screen: np.ndarray, keys=None):
-    """O2 support scatter over the full image.  Returns (image [H,W,3], T [H,W], last_id [H,W], tie [H,W])."""
+def render_o2(params: Params, W: int, H: int, screen: np.ndarray, keys=None, jump: bool = False):
+    """O2 support scatter over the full image.  Returns (image [H,W,3], T [H,W], last_id [H,W], tie [H,W])
+    and, with jump=True, the tie jump bounds [H,W,2] as a fifth item."""
     screen = np.ascontiguousarray(screen, dtype=np.float64)
     n = screen.shape[0]
     img = np.zeros((H, W, 3)); T = np.zeros((H, W)); last = np.zeros((H, W), np.int32)
     tie = np.zeros((H, W), np.uint8)
+    jb = np.zeros((H, W, 2))
     k = _keys_or_none(params, keys)
     cp = params.c()
-    lib().or_render_o2(C.byref(cp), W, H, n, _p(screen), _p(k), _p(img), _p(T), _p(last), _p(tie))
-    return img, T, last, tie
+    lib().or_render_o2(C.byref(cp), W, H, n, _p(screen), _p(k), _p(img), _p(T), _p(last), _p(tie), _p(jb))
+    return (img, T, last, tie, jb) if jump else (img, T, last, tie)
 
 
 def render_bwd_o2(params: Params, W: int, H: int, screen: np.ndarray, T_final, last_id, dLdC, keys=None,
@@ -253,7 +288,7 @@ def render_bwd_o2(params: Params, W: int, H: int, screen: np.ndarray, T_final, l
     T = np.ascontiguousarray(np.asarray(T_final, dtype=np.float64).reshape(H * W))
     last = np.ascontiguousarray(np.asarray(last_id, dtype=np.int32).reshape(H * W))
     g = np.ascontiguousarray(np.asarray(dLdC, dtype=np.float64).reshape(H * W, 3))
-    out = np.zeros((n, 11))
+    out = np.zeros((n, SG_N))
     k = _keys_or_none(params, keys)
     cp = params.c()
     lib().or_render_bwd_o2(C.byref(cp), W, H, n, _p(screen), _p(k), _p(T), _p(last), _p(g), _p(out), max_threads)
@@ -266,7 +301,11 @@ def project_bwd(params: Params, prims: dict, screen: np.ndarray, dscreen: np.nda
     three_d = params.mode == MODE_ALPHA3D
     q = _prims(prims, n, three_d)
     d = 3 if three_d else 2
-    out = dict(mean=np.zeros((n, d)), freq=np.zeros((n, d)), color=np.zeros((n, 3)), opacity=np.zeros(n))
+    _check_sh(params, q, n)
+    out = dict(mean=np.zeros((n, d)), freq=np.zeros((n, d)), color=np.zeros((n, 3)), opacity=np.zeros(n),
+               phase=np.zeros(n))
+    if q["sh"] is not None and params.sh_degree >= 0:
+        out["sh"] = np.zeros_like(q["sh"])
     if three_d:
         out.update(quat=np.zeros((n, 4)), scale=np.zeros((n, 3)))
         if q["velocity"] is not None:
@@ -275,13 +314,17 @@ def project_bwd(params: Params, prims: dict, screen: np.ndarray, dscreen: np.nda
         out["cov"] = np.zeros((n, 3))
     screen = np.ascontiguousarray(screen, dtype=np.float64)
     dscreen = np.ascontiguousarray(dscreen, dtype=np.float64)
+    if dscreen.shape[1] < SG_N:   # screen gradients without the phase column
+        dscreen = np.ascontiguousarray(np.concatenate([dscreen, np.zeros((n, SG_N - dscreen.shape[1]))], 1))
     cp = params.c()
     cc = cam.c() if cam is not None else None
     lib().or_project_bwd(C.byref(cp), C.byref(cc) if cc is not None else None, n, _p(q["mean"]), _p(q["cov"]),
                          _p(q["quat"]), _p(q["scale"]), _p(q["freq"]), _p(q["opacity"]), _p(q["velocity"]),
-                         _p(screen), _p(dscreen), _p(out["mean"]), _p(out.get("cov")), _p(out.get("quat")),
-                         _p(out.get("scale")), _p(out["freq"]), _p(out["color"]), _p(out["opacity"]),
-                         _p(out.get("velocity")))
+                         _p(q["sh"]), _p(screen), _p(dscreen), _p(out["mean"]), _p(out.get("cov")),
+                         _p(out.get("quat")), _p(out.get("scale")), _p(out["freq"]), _p(out["color"]),
+                         _p(out["opacity"]), _p(out.get("velocity")), _p(out["phase"]), _p(out.get("sh")))
+    if "sh" in out:
+        out["sh"] = out["sh"].reshape(np.asarray(prims["sh"]).shape)
     return out
 
 

@@ -29,9 +29,17 @@
  * silent paper; each reading is named where it is used below.
  *
  * Parity pins live in tests/test_oracle_*.py (closed forms, finite
- * differences, library routines, brute force).  Functions without a pin:
- * none at the time of writing; the FREQ_COVECTOR variant is pinned only by
- * its closed form on the optical axis.
+ * differences, library routines, brute force, quadrature).  Every function
+ * has one: projection (closed form on the axis, numerical Jacobian off it),
+ * W' and both blends (Poisson-summation sums, pointwise identities, scipy's
+ * Gaussian, compositing closed forms), the backward (central differences,
+ * closed-form sum gradients), the covector transform (closed forms, phase
+ * invariance, finite differences), the carrier phase (closed forms, finite
+ * differences), SH colour (scipy's spherical harmonics, quadrature,
+ * degree-0 reduction, finite differences), O-bin (pixel enumeration, scipy
+ * minimisation, numpy's stable sort) and the support counts (a numpy brute
+ * force).  tests/test_oracle_mutations.py plants plausible mistakes and
+ * checks that these pins fail.
  */
 #include <math.h>
 #include <stdint.h>
@@ -53,7 +61,7 @@ typedef struct {
     int32_t mode;        /* OR_MODE_* */
     int32_t cov;         /* OR_COV_* */
     int32_t freq_xform;  /* OR_FREQ_* */
-    int32_t reserved;
+    int32_t sh_degree;   /* < 0: colour is the direct RGB input; 0..3: spherical-harmonic colour */
     double alpha_min;    /* skip a pair whose o*W' is below this (alpha mode) */
     double alpha_max;    /* clamp of o*W' (alpha mode) */
     double T_min;        /* stop once transmittance falls below this */
@@ -74,12 +82,23 @@ typedef struct {
 /* FP64 screen record, one row of 16 doubles per primitive. */
 enum {
     SR_MX = 0, SR_MY, SR_CA, SR_CB, SR_CC, SR_FX, SR_FY, SR_OP,
-    SR_R, SR_G, SR_B, SR_DEPTH, SR_RX, SR_RY, SR_Q, SR_VALID, SR_N
+    SR_R, SR_G, SR_B, SR_DEPTH, SR_RX, SR_RY, SR_Q, SR_VALID, SR_PH, SR_N
 };
-/* Screen-space gradient row: d/d(mu'x, mu'y, a, b, c, f'x, f'y, o, r, g, b). */
-enum { SG_MX = 0, SG_MY, SG_CA, SG_CB, SG_CC, SG_FX, SG_FY, SG_OP, SG_R, SG_G, SG_B, SG_N };
+/* Screen-space gradient row: d/d(mu'x, mu'y, a, b, c, f'x, f'y, o, r, g, b, phase). */
+enum { SG_MX = 0, SG_MY, SG_CA, SG_CB, SG_CC, SG_FX, SG_FY, SG_OP, SG_R, SG_G, SG_B, SG_PH, SG_N };
 
-/* Per-pixel tie flags (decisions within a stated margin of their threshold). */
+/* Per-pixel tie flags (decisions within a stated margin of their threshold).
+ * With every flag the renders also accumulate a bound on how far the pixel's
+ * value (jump[0], max over channels) and final transmittance (jump[1]) move
+ * if that decision goes the other way, with cmax = the largest |colour| or
+ * |bg| of the scene:
+ *   support (additive)  o W' max|c|            -- the pair's whole contribution
+ *   skip / cull (alpha) 2 cmax (T a + T_min)   -- the pair's contribution, plus
+ *                                                  the tail a moved stop decision drops
+ *   stop                2 cmax T               -- the tail after the stopping pair
+ *   clamp               0                      -- the value is continuous there
+ *   near-plane cull     2 cmax                 -- anything
+ */
 enum {
     TIE_SUPPORT = 1,   /* |q - q_add| < 1e-5 q_add           (additive support) */
     TIE_SKIP = 2,      /* |o W' - alpha_min| < 1e-5 alpha_min (alpha skip)      */
@@ -127,6 +146,84 @@ static void quat_rot_deriv(const double q[4], int k, double D[9])
         D[6] = 2 * x;    D[7] = 2 * y;   D[8] = 0;
         break;
     }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Spherical-harmonic colour                                                */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * 3DGS stores view-dependent colour as spherical-harmonic coefficients
+ * (Sec. 3.1).  Reading: the real spherical harmonics with the Condon-Shortley
+ * phase, Y_{l,m} = sqrt(2) Re Y_l^m (m > 0), sqrt(2) Im Y_l^|m| (m < 0),
+ * Y_l^0 (m = 0), where Y_l^m is the complex harmonic, of degree l <= 3,
+ * indexed k = l^2 + l + m, evaluated at the unit direction from the camera
+ * centre to the (time-shifted) mean; colour_c = sum_k Y_k sh[k][c], with no
+ * offset and no clamp.  The degree-<=3 harmonics are written out as their
+ * Cartesian polynomials in (x, y, z) on the unit sphere; G (may be NULL)
+ * receives the gradient of each polynomial in R^3 (3 values per k).
+ */
+static int sh_count(int deg) { return (deg + 1) * (deg + 1); }
+
+static void sh_basis(int deg, double x, double y, double z, double* Y, double* G)
+{
+    const double pi = 3.14159265358979323846;
+    const double c0 = 0.5 * sqrt(1.0 / pi), c1 = sqrt(3.0 / (4.0 * pi));
+    const double c2a = 0.5 * sqrt(15.0 / pi), c2b = 0.25 * sqrt(5.0 / pi), c2c = 0.25 * sqrt(15.0 / pi);
+    const double c3a = 0.25 * sqrt(35.0 / (2.0 * pi)), c3b = 0.5 * sqrt(105.0 / pi);
+    const double c3c = 0.25 * sqrt(21.0 / (2.0 * pi)), c3d = 0.25 * sqrt(7.0 / pi), c3e = 0.25 * sqrt(105.0 / pi);
+    double g[16][3];
+    double v[16];
+    memset(g, 0, sizeof(g));
+    v[0] = c0;
+    if (deg >= 1) {
+        v[1] = -c1 * y;  g[1][1] = -c1;
+        v[2] = c1 * z;   g[2][2] = c1;
+        v[3] = -c1 * x;  g[3][0] = -c1;
+    }
+    if (deg >= 2) {
+        v[4] = c2a * x * y;                        g[4][0] = c2a * y;  g[4][1] = c2a * x;
+        v[5] = -c2a * y * z;                       g[5][1] = -c2a * z; g[5][2] = -c2a * y;
+        v[6] = c2b * (2 * z * z - x * x - y * y);  g[6][0] = -2 * c2b * x; g[6][1] = -2 * c2b * y; g[6][2] = 4 * c2b * z;
+        v[7] = -c2a * x * z;                       g[7][0] = -c2a * z; g[7][2] = -c2a * x;
+        v[8] = c2c * (x * x - y * y);              g[8][0] = 2 * c2c * x; g[8][1] = -2 * c2c * y;
+    }
+    if (deg >= 3) {
+        v[9] = -c3a * y * (3 * x * x - y * y);
+        g[9][0] = -c3a * 6 * x * y; g[9][1] = -c3a * (3 * x * x - 3 * y * y);
+        v[10] = c3b * x * y * z;
+        g[10][0] = c3b * y * z; g[10][1] = c3b * x * z; g[10][2] = c3b * x * y;
+        v[11] = -c3c * y * (4 * z * z - x * x - y * y);
+        g[11][0] = c3c * 2 * x * y; g[11][1] = -c3c * (4 * z * z - x * x - 3 * y * y); g[11][2] = -c3c * 8 * y * z;
+        v[12] = c3d * z * (2 * z * z - 3 * x * x - 3 * y * y);
+        g[12][0] = -c3d * 6 * x * z; g[12][1] = -c3d * 6 * y * z; g[12][2] = c3d * (6 * z * z - 3 * x * x - 3 * y * y);
+        v[13] = -c3c * x * (4 * z * z - x * x - y * y);
+        g[13][0] = -c3c * (4 * z * z - 3 * x * x - y * y); g[13][1] = c3c * 2 * x * y; g[13][2] = -c3c * 8 * x * z;
+        v[14] = c3e * z * (x * x - y * y);
+        g[14][0] = c3e * 2 * x * z; g[14][1] = -c3e * 2 * y * z; g[14][2] = c3e * (x * x - y * y);
+        v[15] = -c3a * x * (x * x - 3 * y * y);
+        g[15][0] = -c3a * (3 * x * x - 3 * y * y); g[15][1] = c3a * 6 * x * y;
+    }
+    int K = sh_count(deg);
+    for (int k = 0; k < K; ++k) {
+        Y[k] = v[k];
+        if (G) for (int a = 0; a < 3; ++a) G[3 * k + a] = g[k][a];
+    }
+}
+
+/* Real SH basis of n unit directions (for the pins): Y[n][(deg+1)^2]. */
+void or_sh_basis(int32_t deg, int64_t n, const double* dirs, double* Y, double* G)
+{
+    for (int64_t i = 0; i < n; ++i)
+        sh_basis(deg, dirs[3 * i], dirs[3 * i + 1], dirs[3 * i + 2], Y + (size_t)sh_count(deg) * i,
+                 G ? G + (size_t)3 * sh_count(deg) * i : NULL);
+}
+
+/* World position of the camera centre: -W^T w for the world->camera map [W | w]. */
+static void camera_centre(const or_camera* cam, double C[3])
+{
+    const double* V = cam->viewmat;
+    for (int k = 0; k < 3; ++k) C[k] = -(V[k] * V[3] + V[4 + k] * V[7] + V[8 + k] * V[11]);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -179,7 +276,7 @@ void or_depth_keys(int64_t n, const float* mean, const float* vel, float tau, co
  * sqrt(q_add Sigma'_xx), sqrt(q_add Sigma'_yy).
  */
 static void project_2d(const or_params* P, int64_t i, const double* mean, const double* covp,
-                       const double* freq, const double* color, const double* opac, double* s)
+                       const double* freq, const double* color, const double* opac, const double* phase, double* s)
 {
     double Sxx, Sxy, Syy;
     if (P->cov == OR_COV_CHOLESKY) {
@@ -206,6 +303,7 @@ static void project_2d(const or_params* P, int64_t i, const double* mean, const 
     s[SR_G] = color[3 * i + 1];
     s[SR_B] = color[3 * i + 2];
     s[SR_DEPTH] = 0.0;
+    s[SR_PH] = phase ? phase[i] : 0.0;
     if (!(det > 0.0)) {
         s[SR_VALID] = 0.0;
         return;
@@ -327,16 +425,33 @@ static int inv3(const double A[9], double B[9])
 
 static void project_3d(const or_params* P, const or_camera* cam, int64_t i, const double* mean,
                        const double* quat, const double* scale, const double* freq, const double* color,
-                       const double* opac, const double* vel, double* s)
+                       const double* opac, const double* vel, const double* phase, const double* sh, double* s)
 {
     proj3 pj;
     s[SR_OP] = opac[i];
-    s[SR_R] = color[3 * i];
-    s[SR_G] = color[3 * i + 1];
-    s[SR_B] = color[3 * i + 2];
+    if (P->sh_degree < 0) {
+        s[SR_R] = color[3 * i];
+        s[SR_G] = color[3 * i + 1];
+        s[SR_B] = color[3 * i + 2];
+    }
+    s[SR_PH] = phase ? phase[i] : 0.0;
     s[SR_VALID] = 0.0;
     double o = opac[i];
     if (!project_3d_core(P, cam, i, mean, quat, scale, freq, vel, &pj)) return;
+    if (P->sh_degree >= 0) {
+        /* view-dependent colour from the direction camera centre -> mean */
+        double Cc[3], d[3], Y[16];
+        camera_centre(cam, Cc);
+        for (int k = 0; k < 3; ++k) d[k] = pj.m[k] - Cc[k];
+        double dl = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+        sh_basis(P->sh_degree, d[0] / dl, d[1] / dl, d[2] / dl, Y, NULL);
+        int K = sh_count(P->sh_degree);
+        for (int c = 0; c < 3; ++c) {
+            double acc = 0.0;
+            for (int k = 0; k < K; ++k) acc += Y[k] * sh[((size_t)i * K + k) * 3 + c];
+            s[SR_R + c] = acc;
+        }
+    }
     double tz = pj.t[2];
     s[SR_DEPTH] = tz;
     if (!(tz > P->near_plane)) return;
@@ -372,16 +487,16 @@ static void project_3d(const or_params* P, const or_camera* cam, int64_t i, cons
 
 void or_project(const or_params* P, const or_camera* cam, int64_t n, const double* mean, const double* covp,
                 const double* quat, const double* scale, const double* freq, const double* color,
-                const double* opac, const double* vel, double* screen)
+                const double* opac, const double* vel, const double* phase, const double* sh, double* screen)
 {
 #pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < n; ++i) {
         double* s = screen + SR_N * i;
         memset(s, 0, sizeof(double) * SR_N);
         if (P->mode == OR_MODE_ADD2D)
-            project_2d(P, i, mean, covp, freq, color, opac, s);
+            project_2d(P, i, mean, covp, freq, color, opac, phase, s);
         else
-            project_3d(P, cam, i, mean, quat, scale, freq, color, opac, vel, s);
+            project_3d(P, cam, i, mean, quat, scale, freq, color, opac, vel, phase, sh, s);
     }
 }
 
@@ -392,8 +507,10 @@ void or_project(const or_params* P, const or_camera* cam, int64_t n, const doubl
 /*
  * Evaluation of one (pixel, primitive) pair.  Reading: the centre of pixel
  * (x, y) is (x + 1/2, y + 1/2).  Then d = p - mu', q = d^T A d,
- * phi = f'.d (radians), e = exp(-q/2), kappa = (1 + cos phi)/2 and
- * W' = kappa e (Eq. 6-7).
+ * phi = f'.d + phi0 (radians), e = exp(-q/2), kappa = (1 + cos phi)/2 and
+ * W' = kappa e (Eq. 6-7).  phi0 is an optional per-primitive carrier phase
+ * (Eq. 6 has none, so phi0 = 0 gives the paper's primitive; a phase is the
+ * primitive variant in which the carrier is cos(f.(x - mu) + phi0)).
  */
 typedef struct {
     double dx, dy, q, phi, e, kappa, w;
@@ -404,7 +521,7 @@ static void eval_pair(const double* s, double px, double py, pair_eval* pe)
     pe->dx = px - s[SR_MX];
     pe->dy = py - s[SR_MY];
     pe->q = s[SR_CA] * pe->dx * pe->dx + 2.0 * s[SR_CB] * pe->dx * pe->dy + s[SR_CC] * pe->dy * pe->dy;
-    pe->phi = s[SR_FX] * pe->dx + s[SR_FY] * pe->dy;
+    pe->phi = s[SR_FX] * pe->dx + s[SR_FY] * pe->dy + s[SR_PH];
     pe->e = exp(-0.5 * pe->q);
     pe->kappa = 0.5 * (1.0 + cos(pe->phi));
     pe->w = pe->kappa * pe->e;
@@ -437,6 +554,7 @@ static void pair_grad_w(const double* s, const pair_eval* pe, double dLdw, doubl
     g[SG_CC] += dq * pe->dy * pe->dy;
     g[SG_FX] += dphi * pe->dx;
     g[SG_FY] += dphi * pe->dy;
+    g[SG_PH] += dphi;
 }
 
 typedef struct {
@@ -469,7 +587,8 @@ typedef struct {
  * Returns the number of contributing pairs written to out[] (may be NULL).
  */
 static int64_t composite_pixel(const or_params* P, const double* screen, const order_ent* cand, int64_t ncand,
-                               double px, double py, double C[3], double* T_out, int* tie, contrib* out)
+                               double px, double py, double C[3], double* T_out, int* tie, contrib* out,
+                               double cmax, double* jump)
 {
     double T = 1.0;
     int64_t nc = 0;
@@ -479,7 +598,10 @@ static int64_t composite_pixel(const or_params* P, const double* screen, const o
         pair_eval pe;
         eval_pair(s, px, py, &pe);
         double a = s[SR_OP] * pe.w;
-        if (fabs(a - P->alpha_min) < 1e-5 * P->alpha_min) *tie |= TIE_SKIP;
+        if (fabs(a - P->alpha_min) < 1e-5 * P->alpha_min) {
+            *tie |= TIE_SKIP;
+            if (jump) { jump[0] += 2.0 * cmax * (T * a + P->T_min); jump[1] += T * a + P->T_min; }
+        }
         if (a < P->alpha_min) continue;
         if (fabs(a - P->alpha_max) < 1e-5 * P->alpha_max) *tie |= TIE_CLAMP;
         int clamped = a > P->alpha_max;
@@ -497,7 +619,10 @@ static int64_t composite_pixel(const or_params* P, const double* screen, const o
         C[1] += T * alpha * s[SR_G];
         C[2] += T * alpha * s[SR_B];
         T *= (1.0 - alpha);
-        if (fabs(T - P->T_min) < 1e-4 * P->T_min) *tie |= TIE_STOP;
+        if (fabs(T - P->T_min) < 1e-4 * P->T_min) {
+            *tie |= TIE_STOP;
+            if (jump) { jump[0] += 2.0 * cmax * T; jump[1] += T; }
+        }
         if (T < P->T_min) break;
     }
     C[0] += T * P->bg[0];
@@ -509,10 +634,32 @@ static int64_t composite_pixel(const or_params* P, const double* screen, const o
 
 static int cull_tie(const or_params* P, const double* s)
 {
-    /* a primitive whose cull decision (near plane, opacity floor) sits on its threshold */
+    /* a primitive whose cull decision (near plane, opacity floor) sits on its
+     * threshold: 2 = near plane (any jump), 1 = opacity floor */
     if (P->mode != OR_MODE_ALPHA3D) return 0;
-    return fabs(s[SR_DEPTH] - P->near_plane) < 1e-6 * (1.0 + P->near_plane) ||
-           fabs(s[SR_OP] - P->alpha_min) < 1e-5 * P->alpha_min;
+    if (fabs(s[SR_DEPTH] - P->near_plane) < 1e-6 * (1.0 + P->near_plane)) return 2;
+    return fabs(s[SR_OP] - P->alpha_min) < 1e-5 * P->alpha_min ? 1 : 0;
+}
+
+/* Jump bound of a cull tie of kind k (cull_tie) at transmittance T. */
+static void cull_jump(const or_params* P, int k, double T, double cmax, double* jump)
+{
+    if (!jump) return;
+    if (k == 2) { jump[0] += 2.0 * cmax; jump[1] += 1.0; }
+    else { jump[0] += 2.0 * cmax * (T * P->alpha_min + P->T_min); jump[1] += T * P->alpha_min + P->T_min; }
+}
+
+/* Largest |colour| of the valid primitives and |bg| (the scale of every jump bound). */
+static double colour_max(const or_params* P, const double* screen, int64_t n)
+{
+    double m = 0.0;
+    for (int k = 0; k < 3; ++k) m = fmax(m, fabs(P->bg[k]));
+    for (int64_t i = 0; i < n; ++i) {
+        const double* s = screen + SR_N * i;
+        if (s[SR_VALID] == 0.0) continue;
+        for (int k = 0; k < 3; ++k) m = fmax(m, fabs(s[SR_R + k]));
+    }
+    return m;
 }
 
 /*
@@ -547,13 +694,14 @@ static int64_t pix_of(const int64_t* pix, int64_t k) { return pix ? pix[k] : k; 
  */
 void or_render_o1(const or_params* P, int32_t W, int32_t H, int64_t n, const double* screen,
                   const uint32_t* depth_key, int64_t npix, const int64_t* pix, double* image, double* T_final,
-                  int32_t* n_contrib, uint8_t* tie)
+                  int32_t* n_contrib, uint8_t* tie, double* jump)
 {
     (void)H;
     int64_t nvalid = 0;
     order_ent* ord = make_order(screen, n, P->mode == OR_MODE_ALPHA3D ? depth_key : NULL, &nvalid);
     uint8_t* ptie = (uint8_t*)calloc((size_t)(n > 0 ? n : 1), 1);
-    for (int64_t i = 0; i < n; ++i) ptie[i] = (uint8_t)(cull_tie(P, screen + SR_N * i) ? 1 : 0);
+    for (int64_t i = 0; i < n; ++i) ptie[i] = (uint8_t)cull_tie(P, screen + SR_N * i);
+    const double cmax = colour_max(P, screen, n);
 #pragma omp parallel
     {
         order_ent* cand = (order_ent*)malloc(sizeof(order_ent) * (size_t)(nvalid > 0 ? nvalid : 1));
@@ -563,11 +711,15 @@ void or_render_o1(const or_params* P, int32_t W, int32_t H, int64_t n, const dou
             double px = (double)(p % W) + 0.5, py = (double)(p / W) + 0.5;
             int t = 0;
             int64_t nc = 0;
+            double jb[2] = {0.0, 0.0};
             for (int64_t j = 0; j < nvalid; ++j) {
                 const double* s = screen + SR_N * ord[j].id;
                 if (in_padded_box(s, px, py)) {
                     cand[nc++] = ord[j];
-                    if (ptie[ord[j].id]) t |= TIE_CULL;
+                    if (ptie[ord[j].id]) {
+                        t |= TIE_CULL;
+                        cull_jump(P, ptie[ord[j].id], 1.0, cmax, jb);
+                    }
                 }
             }
             double* C = image + 3 * k;
@@ -578,7 +730,11 @@ void or_render_o1(const or_params* P, int32_t W, int32_t H, int64_t n, const dou
                     const double* s = screen + SR_N * cand[j].id;
                     pair_eval pe;
                     eval_pair(s, px, py, &pe);
-                    if (fabs(pe.q - s[SR_Q]) < 1e-5 * s[SR_Q]) t |= TIE_SUPPORT;
+                    if (fabs(pe.q - s[SR_Q]) < 1e-5 * s[SR_Q]) {
+                        t |= TIE_SUPPORT;
+                        jb[0] += fabs(s[SR_OP] * pe.w) *
+                                 fmax(fabs(s[SR_R]), fmax(fabs(s[SR_G]), fabs(s[SR_B])));
+                    }
                     if (!(pe.q <= s[SR_Q])) continue;
                     double cw = s[SR_OP] * pe.w;
                     C[0] += s[SR_R] * cw;
@@ -590,11 +746,12 @@ void or_render_o1(const or_params* P, int32_t W, int32_t H, int64_t n, const dou
                 if (n_contrib) n_contrib[k] = cnt;
             } else {
                 double T;
-                int64_t cnt = composite_pixel(P, screen, cand, nc, px, py, C, &T, &t, NULL);
+                int64_t cnt = composite_pixel(P, screen, cand, nc, px, py, C, &T, &t, NULL, cmax, jb);
                 if (T_final) T_final[k] = T;
                 if (n_contrib) n_contrib[k] = (int32_t)cnt;
             }
             if (tie) tie[k] = (uint8_t)t;
+            if (jump) { jump[2 * k] = jb[0]; jump[2 * k + 1] = jb[1]; }
         }
         free(cand);
     }
@@ -668,7 +825,7 @@ void or_render_bwd_o1(const or_params* P, int32_t W, int32_t H, int64_t n, const
             } else {
                 double C[3], T;
                 int t = 0;
-                int64_t m = composite_pixel(P, screen, cand, nc, px, py, C, &T, &t, list);
+                int64_t m = composite_pixel(P, screen, cand, nc, px, py, C, &T, &t, list, 0.0, NULL);
                 double S[3] = {P->bg[0], P->bg[1], P->bg[2]};
                 for (int64_t j = m - 1; j >= 0; --j) {
                     const contrib* cb = &list[j];
@@ -711,10 +868,12 @@ void or_render_bwd_o1(const or_params* P, int32_t W, int32_t H, int64_t n, const
  * shared.  Outputs cover all W*H pixels, row-major.
  */
 void or_render_o2(const or_params* P, int32_t W, int32_t H, int64_t n, const double* screen,
-                  const uint32_t* depth_key, double* image, double* T_final, int32_t* last_id, uint8_t* tie)
+                  const uint32_t* depth_key, double* image, double* T_final, int32_t* last_id, uint8_t* tie,
+                  double* jump)
 {
     int64_t nvalid = 0;
     order_ent* ord = make_order(screen, n, P->mode == OR_MODE_ALPHA3D ? depth_key : NULL, &nvalid);
+    const double cmax = colour_max(P, screen, n);
     int64_t npx = (int64_t)W * H;
     double* T = (double*)malloc(sizeof(double) * (size_t)(npx > 0 ? npx : 1));
     uint8_t* done = (uint8_t*)calloc((size_t)(npx > 0 ? npx : 1), 1);
@@ -722,6 +881,7 @@ void or_render_o2(const or_params* P, int32_t W, int32_t H, int64_t n, const dou
         T[p] = 1.0;
         image[3 * p] = image[3 * p + 1] = image[3 * p + 2] = 0.0;
         if (tie) tie[p] = 0;
+        if (jump) jump[2 * p] = jump[2 * p + 1] = 0.0;
         if (last_id) last_id[p] = -1;
     }
 #pragma omp parallel for schedule(static, 1)
@@ -743,12 +903,21 @@ void or_render_o2(const or_params* P, int32_t W, int32_t H, int64_t n, const dou
                     int64_t p = (int64_t)y * W + x;
                     double px = x + 0.5, py = y + 0.5;
                     if (!in_padded_box(s, px, py)) continue;
-                    if (ct && tie) tie[p] |= TIE_CULL;
+                    double* jb = jump ? jump + 2 * p : NULL;
+                    if (ct && tie && !done[p]) {
+                        tie[p] |= TIE_CULL;
+                        cull_jump(P, ct, T[p], cmax, jb);
+                    }
                     pair_eval pe;
                     eval_pair(s, px, py, &pe);
                     double* C = image + 3 * p;
                     if (P->mode == OR_MODE_ADD2D) {
-                        if (tie && fabs(pe.q - s[SR_Q]) < 1e-5 * s[SR_Q]) tie[p] |= TIE_SUPPORT;
+                        if (tie && fabs(pe.q - s[SR_Q]) < 1e-5 * s[SR_Q]) {
+                            tie[p] |= TIE_SUPPORT;
+                            if (jb)
+                                jb[0] += fabs(s[SR_OP] * pe.w) *
+                                         fmax(fabs(s[SR_R]), fmax(fabs(s[SR_G]), fabs(s[SR_B])));
+                        }
                         if (!(pe.q <= s[SR_Q])) continue;
                         double cw = s[SR_OP] * pe.w;
                         C[0] += s[SR_R] * cw;
@@ -758,7 +927,10 @@ void or_render_o2(const or_params* P, int32_t W, int32_t H, int64_t n, const dou
                     } else {
                         if (done[p]) continue;
                         double a = s[SR_OP] * pe.w;
-                        if (tie && fabs(a - P->alpha_min) < 1e-5 * P->alpha_min) tie[p] |= TIE_SKIP;
+                        if (tie && fabs(a - P->alpha_min) < 1e-5 * P->alpha_min) {
+                            tie[p] |= TIE_SKIP;
+                            if (jb) { jb[0] += 2.0 * cmax * (T[p] * a + P->T_min); jb[1] += T[p] * a + P->T_min; }
+                        }
                         if (a < P->alpha_min) continue;
                         if (tie && fabs(a - P->alpha_max) < 1e-5 * P->alpha_max) tie[p] |= TIE_CLAMP;
                         double alpha = a > P->alpha_max ? P->alpha_max : a;
@@ -767,7 +939,10 @@ void or_render_o2(const or_params* P, int32_t W, int32_t H, int64_t n, const dou
                         C[2] += T[p] * alpha * s[SR_B];
                         T[p] *= (1.0 - alpha);
                         if (last_id) last_id[p] = (int32_t)ord[j].id;
-                        if (tie && fabs(T[p] - P->T_min) < 1e-4 * P->T_min) tie[p] |= TIE_STOP;
+                        if (tie && fabs(T[p] - P->T_min) < 1e-4 * P->T_min) {
+                            tie[p] |= TIE_STOP;
+                            if (jb) { jb[0] += 2.0 * cmax * T[p]; jb[1] += T[p]; }
+                        }
                         if (T[p] < P->T_min) done[p] = 1;
                     }
                 }
@@ -906,14 +1081,22 @@ void or_render_bwd_o2(const or_params* P, int32_t W, int32_t H, int64_t n, const
  * From screen-space gradients (dscreen[n][SG_N]) to parameter gradients.
  * Conic: A = Sigma'^-1, so dL/dSigma' = -A (dL/dA) A with the symmetric
  * dL/dA = [[ga, gb/2], [gb/2, gc]].
+ * Covector frequency transform: f3' = A3^-T f with A3 = Jfull W (3x3) and
+ * f' its first two entries, so dL/df = A3^-1 g3 (g3 = (dL/df', 0)) and
+ * dL/dA3 = -f3' (dL/df)^T, which reaches t through the two rows of J and the
+ * third row t/|t| (derivative (I - t t^T/|t|^2)/|t|).
+ * SH colour: dL/dsh[k] = Y_k dL/dc, and the view direction carries
+ * dL/dmean += (I - u u^T)/|d| sum_k grad Y_k (sh[k] . dL/dc), u = d/|d|.
  * Output arrays (any may be NULL): dmean[n*D], dcov[n*3] (2D), dquat[n*4],
- * dscale[n*3], dfreq[n*D], dcolor[n*3], dopac[n], dvel[n*3].
+ * dscale[n*3], dfreq[n*D], dcolor[n*3] (direct RGB only), dopac[n], dvel[n*3],
+ * dphase[n], dsh[n*(deg+1)^2*3].
  * Invalid (culled) primitives get zero gradients.
  */
 void or_project_bwd(const or_params* P, const or_camera* cam, int64_t n, const double* mean, const double* covp,
                     const double* quat, const double* scale, const double* freq, const double* opac, const double* vel,
-                    const double* screen, const double* dscreen, double* dmean, double* dcov, double* dquat,
-                    double* dscale, double* dfreq, double* dcolor, double* dopac, double* dvel)
+                    const double* sh, const double* screen, const double* dscreen, double* dmean, double* dcov,
+                    double* dquat, double* dscale, double* dfreq, double* dcolor, double* dopac, double* dvel,
+                    double* dphase, double* dsh)
 {
     int D = P->mode == OR_MODE_ADD2D ? 2 : 3;
     (void)opac;
@@ -929,9 +1112,13 @@ void or_project_bwd(const or_params* P, const or_camera* cam, int64_t n, const d
         if (dvel) for (int k = 0; k < 3; ++k) dvel[3 * i + k] = 0.0;
         if (dcolor) for (int k = 0; k < 3; ++k) dcolor[3 * i + k] = 0.0;
         if (dopac) dopac[i] = 0.0;
+        if (dphase) dphase[i] = 0.0;
+        const int KSH = P->sh_degree >= 0 ? sh_count(P->sh_degree) : 0;
+        if (dsh) for (int k = 0; k < 3 * KSH; ++k) dsh[(size_t)3 * KSH * i + k] = 0.0;
         if (s[SR_VALID] == 0.0) continue;
-        if (dcolor) for (int k = 0; k < 3; ++k) dcolor[3 * i + k] = g[SG_R + k];
+        if (dcolor && KSH == 0) for (int k = 0; k < 3; ++k) dcolor[3 * i + k] = g[SG_R + k];
         if (dopac) dopac[i] = g[SG_OP];
+        if (dphase) dphase[i] = g[SG_PH];
         /* dL/dSigma' (symmetric 2x2) */
         double a = s[SR_CA], b = s[SR_CB], c = s[SR_CC];
         double GA[4] = {g[SG_CA], 0.5 * g[SG_CB], 0.5 * g[SG_CB], g[SG_CC]};
@@ -997,12 +1184,31 @@ void or_project_bwd(const or_params* P, const or_camera* cam, int64_t n, const d
                 dM[3 * r + cc] = 2.0 * acc;
             }
         double dfw[3] = {0, 0, 0};
+        double dJ3[3] = {0, 0, 0};   /* dL/d(third row of Jfull) (covector only) */
+        double dJc[6] = {0, 0, 0, 0, 0, 0};   /* dL/d(rows 0-1 of Jfull) from the covector */
         if (P->freq_xform == OR_FREQ_VECTOR) {
             for (int cc = 0; cc < 3; ++cc) {
                 dM[cc] += g[SG_FX] * pj.f3[cc];
                 dM[3 + cc] += g[SG_FY] * pj.f3[cc];
                 dfw[cc] = M[cc] * g[SG_FX] + M[3 + cc] * g[SG_FY];
             }
+        } else {
+            double A3[9], Ai[9];
+            for (int r = 0; r < 3; ++r)
+                for (int cc = 0; cc < 3; ++cc)
+                    A3[3 * r + cc] = pj.Jfull[3 * r] * pj.Rw[cc] + pj.Jfull[3 * r + 1] * pj.Rw[3 + cc] +
+                                     pj.Jfull[3 * r + 2] * pj.Rw[6 + cc];
+            inv3(A3, Ai);
+            double f3p[3], g3[3] = {g[SG_FX], g[SG_FY], 0.0};
+            for (int r = 0; r < 3; ++r) f3p[r] = Ai[r] * pj.f3[0] + Ai[3 + r] * pj.f3[1] + Ai[6 + r] * pj.f3[2];
+            for (int r = 0; r < 3; ++r) dfw[r] = Ai[3 * r] * g3[0] + Ai[3 * r + 1] * g3[1] + Ai[3 * r + 2] * g3[2];
+            /* dL/dA3 = -f3' dfw^T, then dL/dJfull = dL/dA3 W^T */
+            for (int r = 0; r < 3; ++r)
+                for (int cc = 0; cc < 3; ++cc) {
+                    double acc = 0.0;
+                    for (int k = 0; k < 3; ++k) acc += -f3p[r] * dfw[k] * pj.Rw[3 * cc + k];
+                    if (r < 2) dJc[3 * r + cc] = acc; else dJ3[cc] = acc;
+                }
         }
         /* dL/dSigma3 = M^T G M */
         double dS3[9];
@@ -1013,11 +1219,11 @@ void or_project_bwd(const or_params* P, const or_camera* cam, int64_t n, const d
                     for (int l = 0; l < 2; ++l) acc += M[3 * k + r] * GS[2 * k + l] * M[3 * l + cc];
                 dS3[3 * r + cc] = acc;
             }
-        /* dL/dJ = dM Rw^T */
+        /* dL/dJ = dM Rw^T (+ the covector's direct term) */
         double dJ[6];
         for (int r = 0; r < 2; ++r)
             for (int cc = 0; cc < 3; ++cc) {
-                double acc = 0.0;
+                double acc = dJc[3 * r + cc];
                 for (int k = 0; k < 3; ++k) acc += dM[3 * r + k] * pj.Rw[3 * cc + k];
                 dJ[3 * r + cc] = acc;
             }
@@ -1039,6 +1245,12 @@ void or_project_bwd(const or_params* P, const or_camera* cam, int64_t n, const d
             double vc = -pj.J[5] * tz / fyc;
             dt[2] += dJ[5] * (fyc * vc / (tz * tz));
         }
+        /* third row of Jfull = t / |t| (covector only) */
+        {
+            double tl = sqrt(tx * tx + ty * ty + tz * tz), th[3] = {tx / tl, ty / tl, tz / tl};
+            double dot = th[0] * dJ3[0] + th[1] * dJ3[1] + th[2] * dJ3[2];
+            for (int k = 0; k < 3; ++k) dt[k] += (dJ3[k] - th[k] * dot) / tl;
+        }
         /* mu' = (fx tx/tz + cx, fy ty/tz + cy) */
         dt[0] += g[SG_MX] * fxc / tz;
         dt[1] += g[SG_MY] * fyc / tz;
@@ -1046,6 +1258,25 @@ void or_project_bwd(const or_params* P, const or_camera* cam, int64_t n, const d
         /* t = Rw m + w  ->  dL/dm = Rw^T dL/dt */
         double dm[3];
         for (int k = 0; k < 3; ++k) dm[k] = pj.Rw[k] * dt[0] + pj.Rw[3 + k] * dt[1] + pj.Rw[6 + k] * dt[2];
+        if (KSH > 0) {
+            /* colour = sum_k Y_k(u) sh[k], u = (m - C)/|m - C| */
+            double Cc[3], d[3], Y[16], G[48];
+            camera_centre(cam, Cc);
+            for (int k = 0; k < 3; ++k) d[k] = pj.m[k] - Cc[k];
+            double dl = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+            double u[3] = {d[0] / dl, d[1] / dl, d[2] / dl};
+            sh_basis(P->sh_degree, u[0], u[1], u[2], Y, G);
+            double du[3] = {0, 0, 0};
+            for (int k = 0; k < KSH; ++k) {
+                const double* c = sh + ((size_t)i * KSH + k) * 3;
+                double w = c[0] * g[SG_R] + c[1] * g[SG_G] + c[2] * g[SG_B];
+                for (int a = 0; a < 3; ++a) du[a] += G[3 * k + a] * w;
+                if (dsh)
+                    for (int cc = 0; cc < 3; ++cc) dsh[((size_t)i * KSH + k) * 3 + cc] = Y[k] * g[SG_R + cc];
+            }
+            double dot = u[0] * du[0] + u[1] * du[1] + u[2] * du[2];
+            for (int a = 0; a < 3; ++a) dm[a] += (du[a] - u[a] * dot) / dl;
+        }
         if (dmean) for (int k = 0; k < 3; ++k) dmean[3 * i + k] = dm[k];
         if (dvel && vel) for (int k = 0; k < 3; ++k) dvel[3 * i + k] = dm[k] * cam->time;
         if (dfreq) for (int k = 0; k < 3; ++k) dfreq[3 * i + k] = dfw[k];

@@ -34,18 +34,31 @@ def to_torch(prims: dict, device="cuda"):
     return {k: torch.from_numpy(np.ascontiguousarray(v, dtype=np.float32)).to(device) for k, v in prims.items()}
 
 
-def compare_image(gpu, ref, tie, tol=1e-4, max_tie_frac=5e-3, min_tie_allow=8):
-    """Max-abs error over non-tie pixels <= tol; tie pixels (a decision within
-    its stated margin, see the oracle) are counted and their number bounded."""
+def compare_image(gpu, ref, tie, jump, tol=1e-4, max_tie_frac=1e-3, min_tie_allow=2, T_gpu=None, T_ref=None):
+    """Tie protocol.  A pixel is a tie pixel when one of its decisions (support, skip, stop, clamp,
+    cull) lies within the stated margin of its threshold; the oracle flags it and bounds how far the
+    pixel can move if that decision goes the other way (jump[:, 0] for the colour, jump[:, 1] for the
+    final transmittance).  Non-tie pixels: max-abs error over the channels <= tol.  Tie pixels: error
+    <= jump + tol.  The number of tie pixels is at most max_tie_frac of the pixels (at least
+    min_tie_allow are allowed).  With T_gpu/T_ref the final transmittance is held to the same rule.
+    Returns (worst non-tie error, tie pixel count)."""
     gpu = np.asarray(gpu, np.float64).reshape(-1, 3)
     ref = np.asarray(ref, np.float64).reshape(-1, 3)
     tie = np.asarray(tie).reshape(-1)
+    jump = np.asarray(jump, np.float64).reshape(-1, 2)
     err = np.abs(gpu - ref).max(axis=1)
     ok = tie == 0
     worst = float(err[ok].max()) if ok.any() else 0.0
     n_tie = int((~ok).sum())
     assert worst <= tol, "max-abs error %.3g > %.3g at pixel %d" % (worst, tol, int(np.argmax(np.where(ok, err, 0))))
-    assert n_tie <= max(min_tie_allow, max_tie_frac * tie.size), "too many tie pixels: %d" % n_tie
+    over = np.flatnonzero(~ok & (err > jump[:, 0] + tol))
+    assert over.size == 0, "tie pixel %d: error %.3g above its jump bound %.3g + %.3g" % (
+        over[0], err[over[0]], jump[over[0], 0], tol)
+    assert n_tie <= max(min_tie_allow, max_tie_frac * tie.size), "too many tie pixels: %d of %d" % (n_tie, tie.size)
+    if T_gpu is not None:
+        eT = np.abs(np.asarray(T_gpu, np.float64).reshape(-1) - np.asarray(T_ref, np.float64).reshape(-1))
+        assert float(eT[ok].max(initial=0.0)) <= tol, "T_final error %.3g" % float(eT[ok].max())
+        assert np.all(eT[~ok] <= jump[~ok, 1] + tol), "T_final error above the jump bound on a tie pixel"
     return worst, n_tie
 
 

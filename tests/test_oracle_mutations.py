@@ -16,8 +16,9 @@ SRC = os.path.join(ROOT, "oracle", "wipes_oracle.c")
 MUTATIONS = {
     "dropped_half_of_carrier": ("pe->kappa = 0.5 * (1.0 + cos(pe->phi));", "pe->kappa = (1.0 + cos(pe->phi));",
                                 "test_pixel_sum_matches_poisson_closed_form"),
-    "phase_sign": ("pe->phi = s[SR_FX] * pe->dx + s[SR_FY] * pe->dy;", "pe->phi = s[SR_FX] * pe->dx - s[SR_FY] * pe->dy;",
-                   "test_pixel_sum_matches_poisson_closed_form or test_pixel_sum_gradient_closed_form"),
+    "frequency_sign": ("pe->phi = s[SR_FX] * pe->dx + s[SR_FY] * pe->dy + s[SR_PH];",
+                       "pe->phi = s[SR_FX] * pe->dx - s[SR_FY] * pe->dy + s[SR_PH];",
+                       "test_pixel_sum_matches_poisson_closed_form or test_pixel_sum_gradient_closed_form"),
     "transposed_conic": ("s[SR_CA] = Syy / det;\n    s[SR_CB] = -Sxy / det;\n    s[SR_CC] = Sxx / det;",
                          "s[SR_CA] = Sxx / det;\n    s[SR_CB] = -Sxy / det;\n    s[SR_CC] = Syy / det;",
                          "test_pixel_sum_matches_poisson_closed_form or test_zero_frequency_is_gaussian_image"),
@@ -40,6 +41,28 @@ MUTATIONS = {
                                 "test_binning_brute_force"),
     "binning_edge_slope": ("const float sy = -cb / cc, sx = -cb / ca;", "const float sy = -cb / ca, sx = -cb / cc;",
                            "test_binning_brute_force"),
+    "covector_third_row_dropped": ("for (int k = 0; k < 3; ++k) dt[k] += (dJ3[k] - th[k] * dot) / tl;",
+                                   "for (int k = 0; k < 3; ++k) dt[k] += 0.0 * (dJ3[k] - th[k] * dot) / tl;",
+                                   "test_fd_gradients_covector"),
+    "covector_inverse_transposed": (
+        "for (int r = 0; r < 3; ++r) dfw[r] = Ai[3 * r] * g3[0] + Ai[3 * r + 1] * g3[1] + Ai[3 * r + 2] * g3[2];",
+        "for (int r = 0; r < 3; ++r) dfw[r] = Ai[r] * g3[0] + Ai[3 + r] * g3[1] + Ai[6 + r] * g3[2];",
+        "test_fd_gradients_covector or test_covector_frequency_gradient_closed_form"),
+    "phase_sign": ("pe->phi = s[SR_FX] * pe->dx + s[SR_FY] * pe->dy + s[SR_PH];",
+                   "pe->phi = s[SR_FX] * pe->dx + s[SR_FY] * pe->dy - s[SR_PH];",
+                   "test_phase_pixel_sum_closed_form or test_phase_pointwise"),
+    "phase_gradient_dropped": ("    g[SG_PH] += dphi;\n}", "    g[SG_PH] += 0.5 * dphi;\n}",
+                               "test_phase_pixel_sum_closed_form or test_fd_gradients_phase"),
+    "sh_basis_sign": ("v[1] = -c1 * y;", "v[1] = c1 * y;", "test_sh_basis_matches_scipy"),
+    "sh_view_direction_gradient": ("for (int a = 0; a < 3; ++a) dm[a] += (du[a] - u[a] * dot) / dl;",
+                                   "for (int a = 0; a < 3; ++a) dm[a] += du[a] / dl;",
+                                   "test_fd_gradients_sh"),
+    "support_counts_past_stop": ("T *= (1.0 - alpha);\n                if (T < P->T_min) break;",
+                                 "T *= (1.0 - alpha);",
+                                 "test_support_counts_brute_force"),
+    "support_jump_bound_shrunk": ("jb[0] += fabs(s[SR_OP] * pe.w) *\n                                 fmax(",
+                                  "jb[0] += 0.01 * fabs(s[SR_OP] * pe.w) *\n                                 fmax(",
+                                  "test_tie_protocol"),
 }
 
 
@@ -55,7 +78,8 @@ def test_pins_catch_planted_mistake(name, tmp_path):
                            str(lib), str(mutated), "-lm"])
     env = dict(os.environ, WIPES_ORACLE_LIB=str(lib), OMP_NUM_THREADS="4")
     r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-p", "no:cacheprovider",
-                        os.path.join(ROOT, "tests", "test_oracle_pins.py"), "-k", selector],
+                        os.path.join(ROOT, "tests", "test_oracle_pins.py"), os.path.join(ROOT, "tests", "test_oracle_variants.py"),
+                        "-k", selector],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
     assert r.returncode == 1, "pins did not catch %s:\n%s" % (name, r.stdout[-2000:])
     assert "failed" in r.stdout

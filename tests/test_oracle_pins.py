@@ -544,3 +544,149 @@ def test_binning_brute_force(mode, tw, th):
         lo = np.searchsorted(tile_of, t, "left"); hi = np.searchsorted(tile_of, t, "right")
         exp = (lo, hi) if hi > lo else (0, 0)
         assert tuple(out["ranges"][t]) == exp
+
+
+# ----------------------------------------------------------------------------
+# Work counts against a numpy brute force
+# ----------------------------------------------------------------------------
+
+def _support_counts_numpy(P, W, H, scr, keys):
+    """Support pairs per pixel, written out from the definitions: a pair is in the support when
+    q <= Q (Q = q_add, or 2 ln(o / alpha_min) in alpha mode); pairs are visited in compositing order
+    ((depth key, index) in alpha mode, index order in additive mode); the forward count runs up to and
+    including the stopping pair (the pair after which T < T_min), the backward count up to and
+    including the last pair with o W' >= alpha_min before that stop."""
+    valid = np.flatnonzero(scr[:, 15] != 0)
+    if P.mode == O.MODE_ALPHA3D:
+        valid = valid[np.lexsort((valid, np.asarray(keys)[valid]))]
+    fwd = np.zeros(W * H, np.int64)
+    bwd = np.zeros(W * H, np.int64)
+    ys, xs = np.divmod(np.arange(W * H), W)
+    px, py = xs + 0.5, ys + 0.5
+    q = np.zeros((valid.size, W * H))
+    a = np.zeros_like(q)
+    for j, i in enumerate(valid):
+        s = scr[i]
+        dx, dy = px - s[0], py - s[1]
+        q[j] = s[2] * dx * dx + 2 * s[3] * dx * dy + s[4] * dy * dy
+        a[j] = s[7] * 0.5 * (1 + np.cos(s[5] * dx + s[6] * dy + s[16])) * np.exp(-0.5 * q[j])
+    insup = q <= scr[valid, 14][:, None]
+    for p in range(W * H):
+        if P.mode == O.MODE_ADD2D:
+            fwd[p] = bwd[p] = insup[:, p].sum()
+            continue
+        T, stop, last = 1.0, valid.size - 1, -1
+        for j in range(valid.size):
+            if a[j, p] < P.alpha_min:
+                continue
+            last = j
+            T *= 1.0 - min(a[j, p], P.alpha_max)
+            if T < P.T_min:
+                stop = j
+                break
+        fwd[p] = insup[: stop + 1, p].sum()
+        bwd[p] = insup[: last + 1, p].sum()
+    return fwd, bwd
+
+
+@pytest.mark.parametrize("mode", [O.MODE_ADD2D, O.MODE_ALPHA3D])
+def test_support_counts_brute_force(mode):
+    """The oracle's support-pair counts (the roofline numerator) against the numpy brute force above,
+    on scenes where pixels stop, pairs are skipped, and supports overlap; catches an off-by-one in
+    the stop or last rule."""
+    if mode == O.MODE_ADD2D:
+        prims = scene2d(40, 36, 30, 5, O.COV_RS)
+        P = O.Params(mode=O.MODE_ADD2D, cov=O.COV_RS)
+        W, H, cam, keys = 36, 30, None, None
+    else:
+        prims, cam = scene3d(900, 6)
+        cam = O.Camera(width=40, height=30, fx=40.0, fy=40.0, cx=20.0, cy=15.0, viewmat=cam.viewmat)
+        prims["opacity"] = np.clip(prims["opacity"] * 1.2, 0, 0.995)
+        P = O.Params(mode=O.MODE_ALPHA3D, cov=O.COV_QUAT_SCALE, blur_eps=0.3)
+        W, H = cam.width, cam.height
+        keys = O.depth_keys(prims, cam)
+    scr = O.project(P, prims, cam)
+    cf, cb = O.support_counts(P, W, H, scr, keys)
+    nf, nb = _support_counts_numpy(P, W, H, scr, keys)
+    assert np.array_equal(cf, nf) and np.array_equal(cb, nb)
+    if mode == O.MODE_ALPHA3D:
+        _, T, _, _ = O.render_o1(P, W, H, scr, keys)
+        assert (T < P.T_min).sum() > 20 and (cb < cf).sum() > 20      # stops and skipped tails occur
+
+
+# ----------------------------------------------------------------------------
+# O-bin kept tiles against pixel-centre enumeration (no tile-count rule)
+# ----------------------------------------------------------------------------
+
+@pytest.mark.parametrize("tw,th", [(8, 8), (16, 16)])
+def test_binning_keeps_every_supported_tile(tw, th):
+    """Large, anisotropic supports (tile rectangles of up to several hundred tiles, so both sides of
+    the binning's 64-tile rule occur): every tile holding a pixel centre with q <= Qs is kept, no kept
+    tile lies outside the tile rectangle of the enumerated pixel box, and count is the number kept.
+    Checked by enumerating every pixel centre of the image; nothing here depends on the tile-count
+    rule, so it pins the rule's large-rectangle branch as well as the culled one."""
+    g = np.random.default_rng(123)
+    W, H, n = 240, 200, 60
+    sig = np.exp(g.uniform(np.log(2.0), np.log(70.0), (n, 2)))
+    th_ = g.uniform(0, math.pi, n)
+    c, s_ = np.cos(th_), np.sin(th_)
+    Sxx = c * c * sig[:, 0] ** 2 + s_ * s_ * sig[:, 1] ** 2
+    Syy = s_ * s_ * sig[:, 0] ** 2 + c * c * sig[:, 1] ** 2
+    Sxy = c * s_ * (sig[:, 0] ** 2 - sig[:, 1] ** 2)
+    det = Sxx * Syy - Sxy ** 2
+    Qs = np.full(n, 9.0 * 1.001 + 1e-3)
+    r = dict(mx=g.uniform(-20, W + 20, n), my=g.uniform(-20, H + 20, n), ca=Syy / det, cb=-Sxy / det, cc=Sxx / det,
+             rx=np.sqrt(Qs * Sxx) * 1.0002, ry=np.sqrt(Qs * Syy) * 1.0002, depth=g.uniform(1, 2, n), Qs=Qs)
+    r = {k: np.asarray(v, np.float32) for k, v in r.items()}
+    out = O.bin_tiles(W, H, tw, th, O.MODE_ALPHA3D, r["mx"], r["my"], r["rx"], r["ry"], r["depth"], r["ca"], r["cb"],
+                      r["cc"], r["Qs"])
+    tiles_x = -(-W // tw)
+    got = {}
+    for t, v in zip((out["keys"] >> np.uint64(32)).astype(np.int64), out["vals"]):
+        got.setdefault(int(v), set()).add((int(t) // tiles_x, int(t) % tiles_x))
+    ys, xs = np.mgrid[0:H, 0:W]
+    big = 0
+    for i in range(n):
+        mx, my, rx, ry = (np.float32(r[k][i]) for k in ("mx", "my", "rx", "ry"))
+        dx, dy = xs + 0.5 - float(mx), ys + 0.5 - float(my)
+        q = float(r["ca"][i]) * dx * dx + 2 * float(r["cb"][i]) * dx * dy + float(r["cc"][i]) * dy * dy
+        inbox = ((mx - rx) - np.float32(0.5) <= xs) & (xs <= (mx + rx) - np.float32(0.5)) & \
+                ((my - ry) - np.float32(0.5) <= ys) & (ys <= (my + ry) - np.float32(0.5))
+        need = {(int(y) // th, int(x) // tw) for y, x in zip(*np.nonzero(inbox & (q <= float(r["Qs"][i]) * (1 - 1e-6))))}
+        rect = {(int(y) // th, int(x) // tw) for y, x in zip(*np.nonzero(inbox))}
+        have = got.get(i, set())
+        assert need <= have, i
+        assert have <= rect, i
+        assert out["count"][i] == len(have)
+        big += len(rect) > 64
+    assert big >= 5
+
+
+# ----------------------------------------------------------------------------
+# The tie protocol itself (tests/helpers.compare_image)
+# ----------------------------------------------------------------------------
+
+def test_tie_protocol_accepts_flipped_ties_and_catches_wrong_decisions():
+    """Renders whose support threshold moves by 3e-6 relative flip only decisions the oracle flags as
+    ties: compare_image accepts them (each flip stays within its jump bound).  A threshold moved by
+    1e-3 flips decisions that are not ties: compare_image rejects it.  A tie pixel moved beyond its
+    jump bound is rejected too."""
+    from helpers import compare_image
+    W, H = 150, 118
+    prims = scene2d(900, W, H, 8, O.COV_RS)
+    P = O.Params(mode=O.MODE_ADD2D, cov=O.COV_RS)
+    scr = O.project(P, prims)
+    ref, _, _, tie, jb = O.render_o1(P, W, H, scr, jump=True)
+    assert tie.sum() > 0
+    flipped = scr.copy(); flipped[:, 14] *= 1 + 3e-6
+    img2, _, _, _ = O.render_o1(P, W, H, flipped)
+    assert np.abs(img2 - ref).max() > 1e-4            # some tie pixel really moved
+    compare_image(img2, ref, tie, jb, max_tie_frac=1e-2)
+    wrong = scr.copy(); wrong[:, 14] *= 1 + 1e-3
+    img3, _, _, _ = O.render_o1(P, W, H, wrong)
+    with pytest.raises(AssertionError):
+        compare_image(img3, ref, tie, jb, max_tie_frac=1e-2)
+    k = int(np.flatnonzero(tie)[0])
+    bad = ref.copy(); bad[k, 0] += jb[k, 0] + 3e-4
+    with pytest.raises(AssertionError):
+        compare_image(bad, ref, tie, jb, max_tie_frac=1e-2)
