@@ -100,12 +100,31 @@ enum { SG_MX = 0, SG_MY, SG_CA, SG_CB, SG_CC, SG_FX, SG_FY, SG_OP, SG_R, SG_G, S
  *   near-plane cull     2 cmax                 -- anything
  */
 enum {
-    TIE_SUPPORT = 1,   /* |q - q_add| < 1e-5 q_add           (additive support) */
-    TIE_SKIP = 2,      /* |o W' - alpha_min| < 1e-5 alpha_min (alpha skip)      */
-    TIE_STOP = 4,      /* |T_after - T_min| < 1e-4 T_min      (termination)     */
-    TIE_CLAMP = 8,     /* |o W' - alpha_max| < 1e-5 alpha_max (clamp kink)      */
-    TIE_CULL = 16      /* primitive-level cull decision near its threshold       */
+    TIE_SUPPORT = 1,   /* |q - q_add| < 1e-5 q_add                      (additive support) */
+    TIE_SKIP = 2,      /* |o W' - alpha_min| < 1e-5 alpha_min + da      (alpha skip)       */
+    TIE_STOP = 4,      /* |T_after - T_min| < (1e-4 + dT) T_min         (termination)      */
+    TIE_CLAMP = 8,     /* |o W' - alpha_max| < 1e-5 alpha_max + da      (clamp kink)       */
+    TIE_CULL = 16      /* primitive-level cull decision near its threshold                  */
 };
+
+/*
+ * Reading of the tie bands: a decision counts as a tie when the rendered
+ * quantity lies within the error with which an FP32 evaluation (the
+ * renderer's arithmetic, with hardware exp2 and cos) can place it.  For
+ * o W' = o kappa e that error is absolute in the carrier kappa, not relative
+ * to alpha_min: a pair near the skip threshold with a small kappa (close to a
+ * trough of the cosine) and a large phase can be decided differently by any
+ * FP32 evaluation.  Bound used, per pair (phi in radians):
+ *   phase error     dphi  = 4e-7 |phi| + 4e-6 |f'| + 1e-6
+ *                           (rounding of the phase sum, of the mean to ~1e-6 px
+ *                            times |f'|, and of the argument reduction)
+ *   carrier error   dkap  = |sin phi| dphi / 2 + 2e-6   (cos approximation)
+ *   envelope error  de/e  = 1e-6 + 2e-7 q               (exp2 and the quadratic)
+ *   da = o (e dkap + kappa e de/e)
+ * and the transmittance carries the accumulated relative error
+ * dT = sum of da / (1 - alpha) over the pixel's contributing pairs
+ * (a_err below).
+ */
 
 /* ------------------------------------------------------------------------ */
 /* Small FP64 linear algebra                                                */
@@ -527,6 +546,15 @@ static void eval_pair(const double* s, double px, double py, pair_eval* pe)
     pe->w = pe->kappa * pe->e;
 }
 
+/* FP32 evaluation error bound da of a = o W' (the tie bands above). */
+static double a_err(const double* s, const pair_eval* pe)
+{
+    const double fn = sqrt(s[SR_FX] * s[SR_FX] + s[SR_FY] * s[SR_FY]);
+    const double dphi = 4e-7 * fabs(pe->phi) + 4e-6 * fn + 1e-6;
+    const double dkap = 0.5 * fabs(sin(pe->phi)) * dphi + 2e-6;
+    return s[SR_OP] * (pe->e * dkap + pe->w * (1e-6 + 2e-7 * pe->q));
+}
+
 /* Candidate test: a padded box around the exact support box.  Outside the
  * exact box the rule rejects the pair in exact arithmetic, so the padding only
  * widens the set in which ties are looked for. */
@@ -590,7 +618,7 @@ static int64_t composite_pixel(const or_params* P, const double* screen, const o
                                double px, double py, double C[3], double* T_out, int* tie, contrib* out,
                                double cmax, double* jump)
 {
-    double T = 1.0;
+    double T = 1.0, dT = 0.0;
     int64_t nc = 0;
     C[0] = C[1] = C[2] = 0.0;
     for (int64_t k = 0; k < ncand; ++k) {
@@ -598,12 +626,13 @@ static int64_t composite_pixel(const or_params* P, const double* screen, const o
         pair_eval pe;
         eval_pair(s, px, py, &pe);
         double a = s[SR_OP] * pe.w;
-        if (fabs(a - P->alpha_min) < 1e-5 * P->alpha_min) {
+        const double da = a_err(s, &pe);
+        if (fabs(a - P->alpha_min) < 1e-5 * P->alpha_min + da) {
             *tie |= TIE_SKIP;
             if (jump) { jump[0] += 2.0 * cmax * (T * a + P->T_min); jump[1] += T * a + P->T_min; }
         }
         if (a < P->alpha_min) continue;
-        if (fabs(a - P->alpha_max) < 1e-5 * P->alpha_max) *tie |= TIE_CLAMP;
+        if (fabs(a - P->alpha_max) < 1e-5 * P->alpha_max + da) *tie |= TIE_CLAMP;
         int clamped = a > P->alpha_max;
         double alpha = clamped ? P->alpha_max : a;
         if (out) {
@@ -619,7 +648,8 @@ static int64_t composite_pixel(const or_params* P, const double* screen, const o
         C[1] += T * alpha * s[SR_G];
         C[2] += T * alpha * s[SR_B];
         T *= (1.0 - alpha);
-        if (fabs(T - P->T_min) < 1e-4 * P->T_min) {
+        dT += da / (1.0 - alpha);
+        if (fabs(T - P->T_min) < (1e-4 + dT) * P->T_min) {
             *tie |= TIE_STOP;
             if (jump) { jump[0] += 2.0 * cmax * T; jump[1] += T; }
         }
@@ -876,6 +906,7 @@ void or_render_o2(const or_params* P, int32_t W, int32_t H, int64_t n, const dou
     const double cmax = colour_max(P, screen, n);
     int64_t npx = (int64_t)W * H;
     double* T = (double*)malloc(sizeof(double) * (size_t)(npx > 0 ? npx : 1));
+    double* dT = (double*)calloc((size_t)(npx > 0 ? npx : 1), sizeof(double));
     uint8_t* done = (uint8_t*)calloc((size_t)(npx > 0 ? npx : 1), 1);
     for (int64_t p = 0; p < npx; ++p) {
         T[p] = 1.0;
@@ -927,19 +958,21 @@ void or_render_o2(const or_params* P, int32_t W, int32_t H, int64_t n, const dou
                     } else {
                         if (done[p]) continue;
                         double a = s[SR_OP] * pe.w;
-                        if (tie && fabs(a - P->alpha_min) < 1e-5 * P->alpha_min) {
+                        const double da = tie ? a_err(s, &pe) : 0.0;
+                        if (tie && fabs(a - P->alpha_min) < 1e-5 * P->alpha_min + da) {
                             tie[p] |= TIE_SKIP;
                             if (jb) { jb[0] += 2.0 * cmax * (T[p] * a + P->T_min); jb[1] += T[p] * a + P->T_min; }
                         }
                         if (a < P->alpha_min) continue;
-                        if (tie && fabs(a - P->alpha_max) < 1e-5 * P->alpha_max) tie[p] |= TIE_CLAMP;
+                        if (tie && fabs(a - P->alpha_max) < 1e-5 * P->alpha_max + da) tie[p] |= TIE_CLAMP;
                         double alpha = a > P->alpha_max ? P->alpha_max : a;
                         C[0] += T[p] * alpha * s[SR_R];
                         C[1] += T[p] * alpha * s[SR_G];
                         C[2] += T[p] * alpha * s[SR_B];
                         T[p] *= (1.0 - alpha);
+                        dT[p] += da / (1.0 - alpha);
                         if (last_id) last_id[p] = (int32_t)ord[j].id;
-                        if (tie && fabs(T[p] - P->T_min) < 1e-4 * P->T_min) {
+                        if (tie && fabs(T[p] - P->T_min) < (1e-4 + dT[p]) * P->T_min) {
                             tie[p] |= TIE_STOP;
                             if (jb) { jb[0] += 2.0 * cmax * T[p]; jb[1] += T[p]; }
                         }
@@ -959,6 +992,7 @@ void or_render_o2(const or_params* P, int32_t W, int32_t H, int64_t n, const dou
         }
     }
     free(T);
+    free(dT);
     free(done);
     free(ord);
 }

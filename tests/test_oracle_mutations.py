@@ -26,7 +26,7 @@ MUTATIONS = {
                              "test_projection_off_axis_matches_linearised_pinhole"),
     "quaternion_order": ("R[1] = 2.0 * (x * y - w * z);", "R[1] = 2.0 * (x * y + w * z);",
                          "test_projection_off_axis_matches_linearised_pinhole"),
-    "transmittance_update": ("T *= (1.0 - alpha);\n        if (fabs(T - P->T_min)", "T *= alpha;\n        if (fabs(T - P->T_min)",
+    "transmittance_update": ("T *= (1.0 - alpha);\n        dT += da", "T *= alpha;\n        dT += da",
                              "test_alpha_two_primitives_order_and_ties or test_alpha_termination_count"),
     "gradient_sign_of_mean": ("g[SG_MX] += dq * (-2.0 * Adx) + dphi * (-s[SR_FX]);",
                               "g[SG_MX] += dq * (2.0 * Adx) + dphi * (-s[SR_FX]);",
