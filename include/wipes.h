@@ -29,7 +29,8 @@
  *
  * The per-pixel rule, identical for every tile shape and launch form:
  *   pixel (x, y) has centre p = (x + 1/2, y + 1/2); d = p - mu'; q = d^T A d
- *   with A = Sigma'^-1; phi = f'.d; W' = 1/2 (1 + cos phi) exp(-q/2).
+ *   with A = Sigma'^-1; phi = f'.d + phi0 (phi0 = 0 unless a phase is given);
+ *   W' = 1/2 (1 + cos phi) exp(-q/2).
  *   Additive:  C = sum_i c_i o_i W'_i over primitives with q_i <= q_add, in
  *              primitive order.
  *   Alpha:     primitives in ascending depth key (ties by index); a = o W';
@@ -72,7 +73,9 @@ typedef enum {
 
 typedef enum {
     WIPES_FREQ_VECTOR = 0,   /* f' = J W f, the ray-space map applied to f as to Sigma (Sec. 4.1) */
-    WIPES_FREQ_COVECTOR = 1  /* reserved: phase-preserving variant; rejected with WIPES_ERR_INVALID */
+    WIPES_FREQ_COVECTOR = 1  /* f' = first two components of (J3 W)^-T f, J3 = J with the third row
+                                t/|t|: the carrier's phase f.(x - mu) is carried to first order
+                                (3D only; 2D has f' = f either way) */
 } wipes_freq_xform;
 
 /* ---------------------------------------------------------------- inputs */
@@ -94,6 +97,10 @@ typedef struct {
     float near_plane;     /* 0.01: cull primitives with camera z <= near */
     float fov_guard;      /* 1.3: x/z, y/z clamped to +-guard*half-fov inside J */
     float bg[3];          /* background colour added with the final T (alpha) */
+    int32_t sh_degree;    /* -1 (default): colour is the direct RGB input; 0..3 (3D only): colour is the
+                             real spherical-harmonic expansion of degree sh_degree (Sec. 3.1) at the
+                             unit direction from the camera centre to the mean, no offset, no clamp */
+    int32_t lds_batch;    /* list positions a wave stages into LDS per batch: 64 or 128 (0 = 64) */
 } wipes_params;
 
 /* Pinhole camera.  viewmat is world->camera, row-major 4x4, OpenCV axes
@@ -109,7 +116,10 @@ typedef struct {
  * D = 2 (2D) or 3 (3D).  Unused members may be NULL.
  *   mean [n, D], cov [n, 3] (2D), quat [n, 4] (3D), scale [n, 3] (3D),
  *   freq [n, D] (rad per pixel in 2D, rad per world unit in 3D),
- *   color [n, 3], opacity [n], velocity [n, 3] (3D, optional). */
+ *   color [n, 3] (unused with sh_degree >= 0), opacity [n], velocity [n, 3] (3D, optional),
+ *   phase [n] (optional carrier phase phi0 in radians: the carrier becomes
+ *   cos(f'.(x - mu') + phi0); NULL = 0, the primitive of Eq. 6),
+ *   sh [n, (sh_degree + 1)^2, 3] (spherical-harmonic colour coefficients, 3D). */
 typedef struct {
     int64_t n;
     const float* mean;
@@ -120,6 +130,8 @@ typedef struct {
     const float* color;
     const float* opacity;
     const float* velocity;
+    const float* phase;
+    const float* sh;
 } wipes_prims;
 
 /* Device gradient outputs, same shapes as wipes_prims; NULL members are skipped.
@@ -133,6 +145,8 @@ typedef struct {
     float* color;
     float* opacity;
     float* velocity;
+    float* phase;
+    float* sh;
 } wipes_prims_grad;
 
 typedef struct {
@@ -166,8 +180,10 @@ typedef struct {
 /* Screen-space record written by wipes_project, one per primitive, 64 bytes,
  * at the start of the screen buffer in batch order (image 0's primitives
  * first).  The mean is mx + mx_lo (an FP32 pair carrying an FP64 value, so
- * the carrier phase stays exact at 1080p).  box0/box1 pack the pixel box
- * (x0 | y0 << 16, x1 | y1 << 16) and are written by wipes_bin_sort. */
+ * the carrier phase stays exact at 1080p).  r, g, b are the colour the blend
+ * uses (evaluated from the spherical harmonics when sh_degree >= 0).
+ * box0/box1 pack the pixel box (x0 | y0 << 16, x1 | y1 << 16) and are written
+ * by wipes_bin_sort. */
 typedef struct {
     float mx, my;          /* mu' (pixels), FP32 rounding */
     float ca, cb, cc;      /* conic A = Sigma'^-1 = [[ca, cb], [cb, cc]] */
@@ -175,7 +191,7 @@ typedef struct {
     float opacity;
     float r, g, b;
     float mx_lo, my_lo;    /* mu' - (mx, my) */
-    float reserved;
+    float phase_rev;       /* carrier phase phi0 / (2 pi), in revolutions */
     uint32_t box0, box1;
 } wipes_screen_record;
 
@@ -246,8 +262,8 @@ wipes_status wipes_render_fwd(wipes_ctx* ctx, const wipes_params* p, const wipes
  * written to each image's grads.  Alpha mode walks each pixel's list back
  * to front from `last`, recovering transmittance by dividing by (1 - alpha)
  * (nothing per pair is stored by the forward).  dscreen (optional, device
- * [sum n, 11]) receives the screen-space gradients d/d(mu'x, mu'y, ca, cb, cc,
- * f'x, f'y, opacity, r, g, b).  Needs the bins buffer sized with_backward, on
+ * [sum n, 12]) receives the screen-space gradients d/d(mu'x, mu'y, ca, cb, cc,
+ * f'x, f'y, opacity, r, g, b, phi0).  Needs the bins buffer sized with_backward, on
  * which wipes_render_fwd has run after the last wipes_bin_sort (the backward
  * reads the forward's per-block contribution record from it). */
 wipes_status wipes_render_bwd(wipes_ctx* ctx, const wipes_params* p, const wipes_batch* batch,
@@ -379,10 +395,16 @@ wipes_status wipes_serve_create(const wipes_serve_config* cfg, const wipes_param
 wipes_status wipes_serve_load_scene(wipes_server* s, const wipes_prims* prims, int32_t* scene_id);
 /* WIPES_ERR_BUSY while requests for the scene are pending or in flight. */
 wipes_status wipes_serve_unload_scene(wipes_server* s, int32_t scene_id);
-/* Queue a render (non-blocking).  out_image: device [W H, 3], must stay valid
- * until poll reports the request done.  WIPES_ERR_BUSY if the queue is full. */
+/* Queue a render of scene scene_id seen from cam (Eq. 3 with W', as
+ * wipes_render_fwd; non-blocking).  out_image: device array of out_floats
+ * floats, at least W H 3 ([H, W, 3] row-major), that must stay valid until
+ * poll reports the request done.  stream: the caller's stream (NULL = the
+ * default stream); the server writes out_image only after the work queued on
+ * that stream before this call, so the caller may still be filling or reading
+ * the buffer there.  WIPES_ERR_NOMEM if out_floats < W H 3, WIPES_ERR_BUSY if
+ * the queue is full, WIPES_ERR_NOTFOUND for an unknown scene. */
 wipes_status wipes_serve_submit(wipes_server* s, int32_t scene_id, const wipes_camera* cam, float* out_image,
-                                uint64_t* req_id);
+                                size_t out_floats, void* stream, uint64_t* req_id);
 /* *done = 1 once the image is in out_image; then *latency_ms is the submit ->
  * completion time and the id is forgotten. */
 wipes_status wipes_serve_poll(wipes_server* s, uint64_t req_id, int32_t* done, double* latency_ms);
@@ -423,6 +445,15 @@ wipes_status wipes_profile_enable(wipes_ctx* ctx, int32_t enable);
  * in ms (ms[WIPES_N_STAGES]) and the number of launches since the last read;
  * then forgets them. n must be >= WIPES_N_STAGES. */
 wipes_status wipes_profile_read(wipes_ctx* ctx, double* ms, int64_t* launches, int32_t n);
+
+/* Issue-rate probe for the blend's roofline (synchronises; allocates two
+ * events): the sustained lane operations per second of one instruction on
+ * this device -- op 0: FP32 fused multiply-add, 1: exp2, 2: cos, 3: sin,
+ * 4: reciprocal, the transcendentals of the per-pixel rule (Eq. 6-7 and its
+ * derivatives) -- from a kernel of independent chains of that instruction
+ * over every SIMD.  The FMA rate divided by a transcendental's rate is the
+ * number of issue slots that transcendental takes. */
+wipes_status wipes_probe_issue_rate(wipes_ctx* ctx, int32_t op, double* lane_ops_per_s, void* stream);
 
 /* Work counts of a rendered frame, for roofline accounting (synchronises):
  *   out[0]  support pairs the forward evaluates: (pixel, primitive) pairs with

@@ -100,7 +100,7 @@ enum { SG_MX = 0, SG_MY, SG_CA, SG_CB, SG_CC, SG_FX, SG_FY, SG_OP, SG_R, SG_G, S
  *   near-plane cull     2 cmax                 -- anything
  */
 enum {
-    TIE_SUPPORT = 1,   /* |q - q_add| < 1e-5 q_add                      (additive support) */
+    TIE_SUPPORT = 1,   /* |q - q_add| < dq + 1e-7 q_add (q_err below)   (additive support) */
     TIE_SKIP = 2,      /* |o W' - alpha_min| < 1e-5 alpha_min + da      (alpha skip)       */
     TIE_STOP = 4,      /* |T_after - T_min| < (1e-4 + dT) T_min         (termination)      */
     TIE_CLAMP = 8,     /* |o W' - alpha_max| < 1e-5 alpha_max + da      (clamp kink)       */
@@ -546,6 +546,22 @@ static void eval_pair(const double* s, double px, double py, pair_eval* pe)
     pe->w = pe->kappa * pe->e;
 }
 
+/* FP32 evaluation error bound of q = d^T A d (the additive support band):
+ * the conic enters rounded to FP32 and pre-scaled (two roundings, 1.2e-7
+ * relative per coefficient), the quadratic form is summed in three rounded
+ * operations (1.8e-7 relative to the sum of the magnitudes of its terms,
+ * which exceeds q when the cross term cancels, up to twice the condition
+ * number of A), the threshold itself is rounded once, and the offset d
+ * carries the FP32 rounding of the block-relative mean (at most 2e-6 px,
+ * zero for 2D means that are FP32 inputs).  Bound:
+ *   dq = 4e-7 (|a| dx^2 + 2 |b dx dy| + |c| dy^2) + 4e-6 (|a dx + b dy| + |b dx + c dy|). */
+static double q_err(const double* s, const pair_eval* pe)
+{
+    const double a = s[SR_CA], b = s[SR_CB], c = s[SR_CC], dx = pe->dx, dy = pe->dy;
+    return 4e-7 * (fabs(a) * dx * dx + 2.0 * fabs(b * dx * dy) + fabs(c) * dy * dy) +
+           4e-6 * (fabs(a * dx + b * dy) + fabs(b * dx + c * dy));
+}
+
 /* FP32 evaluation error bound da of a = o W' (the tie bands above). */
 static double a_err(const double* s, const pair_eval* pe)
 {
@@ -760,7 +776,7 @@ void or_render_o1(const or_params* P, int32_t W, int32_t H, int64_t n, const dou
                     const double* s = screen + SR_N * cand[j].id;
                     pair_eval pe;
                     eval_pair(s, px, py, &pe);
-                    if (fabs(pe.q - s[SR_Q]) < 1e-5 * s[SR_Q]) {
+                    if (fabs(pe.q - s[SR_Q]) < q_err(s, &pe) + 1e-7 * s[SR_Q]) {
                         t |= TIE_SUPPORT;
                         jb[0] += fabs(s[SR_OP] * pe.w) *
                                  fmax(fabs(s[SR_R]), fmax(fabs(s[SR_G]), fabs(s[SR_B])));
@@ -943,7 +959,7 @@ void or_render_o2(const or_params* P, int32_t W, int32_t H, int64_t n, const dou
                     eval_pair(s, px, py, &pe);
                     double* C = image + 3 * p;
                     if (P->mode == OR_MODE_ADD2D) {
-                        if (tie && fabs(pe.q - s[SR_Q]) < 1e-5 * s[SR_Q]) {
+                        if (tie && fabs(pe.q - s[SR_Q]) < q_err(s, &pe) + 1e-7 * s[SR_Q]) {
                             tie[p] |= TIE_SUPPORT;
                             if (jb)
                                 jb[0] += fabs(s[SR_OP] * pe.w) *

@@ -30,7 +30,8 @@ class wipes_params(C.Structure):
     _fields_ = [("mode", C.c_int32), ("cov", C.c_int32), ("freq_xform", C.c_int32), ("tile_w", C.c_int32),
                 ("tile_h", C.c_int32), ("persistent", C.c_int32), ("alpha_min", C.c_float),
                 ("alpha_max", C.c_float), ("T_min", C.c_float), ("q_add", C.c_float), ("blur_eps", C.c_float),
-                ("near_plane", C.c_float), ("fov_guard", C.c_float), ("bg", C.c_float * 3)]
+                ("near_plane", C.c_float), ("fov_guard", C.c_float), ("bg", C.c_float * 3),
+                ("sh_degree", C.c_int32), ("lds_batch", C.c_int32)]
 
 
 class wipes_camera(C.Structure):
@@ -38,7 +39,7 @@ class wipes_camera(C.Structure):
                 ("cx", C.c_float), ("cy", C.c_float), ("viewmat", C.c_float * 16), ("time", C.c_float)]
 
 
-_PRIM_FIELDS = ["mean", "cov", "quat", "scale", "freq", "color", "opacity", "velocity"]
+_PRIM_FIELDS = ["mean", "cov", "quat", "scale", "freq", "color", "opacity", "velocity", "phase", "sh"]
 
 
 class wipes_prims(C.Structure):
@@ -95,6 +96,7 @@ def lib() -> C.CDLL:
     }
     sig.update({
         "wipes_stage_name": (C.c_char_p, [C.c_int32]),
+        "wipes_probe_issue_rate": (C.c_int, [P, C.c_int32, PP(C.c_double), P]),
         "wipes_profile_enable": (C.c_int, [P, C.c_int32]),
         "wipes_profile_read": (C.c_int, [P, PP(C.c_double), PP(C.c_int64), C.c_int32]),
         "wipes_render_stats": (C.c_int, [P, PP(wipes_params), PP(wipes_batch), PP(wipes_buffer), PP(wipes_buffer),
@@ -206,6 +208,16 @@ def wipes_profile_read(ctx):
     n = (C.c_int64 * WIPES_N_STAGES)()
     check(lib().wipes_profile_read(ctx, ms, n, WIPES_N_STAGES), ctx)
     return {wipes_stage_name(i): (ms[i], n[i]) for i in range(WIPES_N_STAGES)}
+
+
+PROBE_OPS = ("fma", "exp2", "cos", "sin", "rcp")
+
+
+def wipes_probe_issue_rate(ctx, op: str, stream: int = 0) -> float:
+    """Sustained lane operations per second of one instruction (see wipes.h)."""
+    r = C.c_double()
+    check(lib().wipes_probe_issue_rate(ctx, PROBE_OPS.index(op), C.byref(r), stream), ctx)
+    return r.value
 
 
 def wipes_render_stats(ctx, params, batch, screen, bins, T_final: int, last: int, stream: int = 0):

@@ -34,7 +34,7 @@ def declare(L) -> None:
         "wipes_serve_create": (C.c_int, [PP(wipes_serve_config), PP(wipes_params), C.c_int32, PP(C.c_void_p)]),
         "wipes_serve_load_scene": (C.c_int, [P, PP(wipes_prims), PP(C.c_int32)]),
         "wipes_serve_unload_scene": (C.c_int, [P, C.c_int32]),
-        "wipes_serve_submit": (C.c_int, [P, C.c_int32, PP(wipes_camera), P, PP(C.c_uint64)]),
+        "wipes_serve_submit": (C.c_int, [P, C.c_int32, PP(wipes_camera), P, C.c_size_t, P, PP(C.c_uint64)]),
         "wipes_serve_poll": (C.c_int, [P, C.c_uint64, PP(C.c_int32), D]),
         "wipes_serve_drain": (C.c_int, [P]),
         "wipes_serve_stats": (C.c_int, [P, PP(wipes_serve_report)]),

@@ -59,6 +59,8 @@ KParams kparams(const wipes_params* p)
     k.tile_h = p->tile_h;
     k.log2_tw = ilog2(p->tile_w);
     k.log2_th = ilog2(p->tile_h);
+    k.freq_xform = p->freq_xform;
+    k.sh_degree = p->sh_degree;
     k.alpha_min = p->alpha_min;
     k.alpha_max = p->alpha_max;
     k.T_min = p->T_min;
@@ -79,7 +81,13 @@ wipes_status validate(wipes_ctx* ctx, const wipes_params* p, const wipes_batch* 
         return fail(ctx, WIPES_ERR_INVALID, "2D mode needs cov CHOLESKY or RS");
     if (p->mode == WIPES_3D_ALPHA && p->cov != WIPES_COV_QUAT_SCALE)
         return fail(ctx, WIPES_ERR_INVALID, "3D mode needs cov QUAT_SCALE");
-    if (p->freq_xform != WIPES_FREQ_VECTOR) return fail(ctx, WIPES_ERR_INVALID, "only WIPES_FREQ_VECTOR is built");
+    if (p->freq_xform != WIPES_FREQ_VECTOR && p->freq_xform != WIPES_FREQ_COVECTOR)
+        return fail(ctx, WIPES_ERR_INVALID, "bad freq_xform");
+    if (p->sh_degree < -1 || p->sh_degree > 3) return fail(ctx, WIPES_ERR_INVALID, "sh_degree must be -1..3");
+    if (p->sh_degree >= 0 && p->mode != WIPES_3D_ALPHA)
+        return fail(ctx, WIPES_ERR_INVALID, "spherical-harmonic colour needs 3D mode");
+    if (p->lds_batch != 0 && p->lds_batch != 64 && p->lds_batch != 128)
+        return fail(ctx, WIPES_ERR_INVALID, "lds_batch must be 0, 64 or 128");
     if (!tile_ok(p->tile_w, p->tile_h)) return fail(ctx, WIPES_ERR_INVALID, "unsupported tile %dx%d", p->tile_w, p->tile_h);
     if (!(p->alpha_min > 0.0f) || !(p->alpha_max > p->alpha_min) || !(p->alpha_max < 1.0f) || !(p->T_min > 0.0f) ||
         !(p->q_add > 0.0f) || !(p->blur_eps >= 0.0f) || !(p->near_plane > 0.0f) || !(p->fov_guard > 0.0f))
@@ -94,8 +102,11 @@ wipes_status validate(wipes_ctx* ctx, const wipes_params* p, const wipes_batch* 
             return fail(ctx, WIPES_ERR_INVALID, "image %d: size %dx%d out of range", i, im.cam.width, im.cam.height);
         if (q.n < 0) return fail(ctx, WIPES_ERR_INVALID, "image %d: negative primitive count", i);
         if (q.n > 0) {
-            if (!q.mean || !q.freq || !q.color || !q.opacity)
-                return fail(ctx, WIPES_ERR_INVALID, "image %d: mean/freq/color/opacity must be set", i);
+            if (!q.mean || !q.freq || !q.opacity)
+                return fail(ctx, WIPES_ERR_INVALID, "image %d: mean/freq/opacity must be set", i);
+            if (p->sh_degree < 0 && !q.color) return fail(ctx, WIPES_ERR_INVALID, "image %d: color missing", i);
+            if (p->sh_degree >= 0 && !q.sh)
+                return fail(ctx, WIPES_ERR_INVALID, "image %d: sh_degree %d needs sh coefficients", i, p->sh_degree);
             if (p->mode == WIPES_2D_ADDITIVE && !q.cov) return fail(ctx, WIPES_ERR_INVALID, "image %d: cov missing", i);
             if (p->mode == WIPES_3D_ALPHA) {
                 if (!q.quat || !q.scale) return fail(ctx, WIPES_ERR_INVALID, "image %d: quat/scale missing", i);
@@ -107,6 +118,8 @@ wipes_status validate(wipes_ctx* ctx, const wipes_params* p, const wipes_batch* 
             const wipes_prims_grad& g = im.grads;
             if (g.velocity && !q.velocity)
                 return fail(ctx, WIPES_ERR_INVALID, "image %d: velocity gradient without velocity", i);
+            if (g.sh && p->sh_degree < 0)
+                return fail(ctx, WIPES_ERR_INVALID, "image %d: sh gradient without spherical-harmonic colour", i);
         }
         prims += q.n;
         pix += (int64_t)im.cam.width * im.cam.height;
@@ -204,6 +217,8 @@ void fill_descs(const wipes_params* p, const wipes_batch* b, std::vector<ImgDesc
         d.color = im.prims.color;
         d.opac = im.prims.opacity;
         d.vel = im.prims.velocity;
+        d.phase = im.prims.phase;
+        d.sh = p->sh_degree >= 0 ? im.prims.sh : nullptr;
         d.g_mean = im.grads.mean;
         d.g_cov = im.grads.cov;
         d.g_quat = im.grads.quat;
@@ -212,6 +227,8 @@ void fill_descs(const wipes_params* p, const wipes_batch* b, std::vector<ImgDesc
         d.g_color = im.grads.color;
         d.g_opac = im.grads.opacity;
         d.g_vel = im.grads.velocity;
+        d.g_phase = im.grads.phase;
+        d.g_sh = p->sh_degree >= 0 ? im.grads.sh : nullptr;
         d.out_image = im.out_image;
         d.prim_begin = prim;
         d.n = (int32_t)im.prims.n;
@@ -229,6 +246,10 @@ void fill_descs(const wipes_params* p, const wipes_batch* b, std::vector<ImgDesc
         d.time = im.cam.time;
         d.limx = p->mode == WIPES_3D_ALPHA ? p->fov_guard * 0.5f * (float)d.W / im.cam.fx : 0.0f;
         d.limy = p->mode == WIPES_3D_ALPHA ? p->fov_guard * 0.5f * (float)d.H / im.cam.fy : 0.0f;
+        // camera centre -R^T w of the world->camera map [R | w]
+        const float* V = im.cam.viewmat;
+        for (int k = 0; k < 3; ++k)
+            d.cam_c[k] = (float)-((double)V[k] * V[3] + (double)V[4 + k] * V[7] + (double)V[8 + k] * V[11]);
         prim += d.n;
         pix += d.W * d.H;
         tile += d.tiles_x * d.tiles_y;
@@ -259,7 +280,7 @@ wipes_status upload_descs(wipes_ctx* ctx, const wipes_params* p, const wipes_bat
 {
     ctx->desc_pend = false;
     if (ctx->capturing) return WIPES_OK;
-    std::vector<ImgDesc> h;
+    std::vector<ImgDesc>& h = ctx->desc_tmp;   // swapped with desc_last below: both keep their storage
     fill_descs(p, b, h);
     const size_t bytes = h.size() * sizeof(ImgDesc);
     char* dst = (char*)screen + L.s_descs;
@@ -275,6 +296,7 @@ wipes_status upload_descs(wipes_ctx* ctx, const wipes_params* p, const wipes_bat
         ImgDesc x = ctx->desc_last[k], y = h[k];
         x.g_mean = x.g_cov = x.g_quat = x.g_scale = x.g_freq = x.g_color = x.g_opac = x.g_vel = nullptr;
         y.g_mean = y.g_cov = y.g_quat = y.g_scale = y.g_freq = y.g_color = y.g_opac = y.g_vel = nullptr;
+        x.g_phase = x.g_sh = y.g_phase = y.g_sh = nullptr;
         grads_only = memcmp(&x, &y, sizeof(ImgDesc)) == 0;
     }
     ctx->desc_dst = nullptr;
@@ -412,6 +434,8 @@ void wipes_params_default(int32_t mode, wipes_params* p)
     p->blur_eps = mode == WIPES_3D_ALPHA ? 0.3f : 0.0f;
     p->near_plane = 0.01f;
     p->fov_guard = 1.3f;
+    p->sh_degree = -1;
+    p->lds_batch = 0;
 }
 
 wipes_status wipes_ctx_create(int32_t device, wipes_ctx** out)

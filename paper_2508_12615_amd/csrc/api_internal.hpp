@@ -68,6 +68,7 @@ struct wipes_ctx {
     int desc_pend_n = 0;
     char* desc_pend_dst = nullptr;
     wipes::DescArgs desc_pend_args;
+    std::vector<wipes::ImgDesc> desc_tmp;    // reused for each new table (no per-call reallocation)
     Profiler prof;
 };
 

@@ -37,7 +37,8 @@
 //
 // Per-pair rule (shared by forward and backward so their FP32 decisions agree
 // bit for bit): e2 = -q/2 log2(e) from the pre-scaled conic, E = exp2(e2),
-// phase in revolutions ph = (f'/2pi).d, K = (1 + cos 2pi ph)/2, W' = K E.
+// phase in revolutions ph = (f'/2pi).d + phi0/2pi, K = (1 + cos 2pi ph)/2,
+// W' = K E.
 #include "common.hpp"
 
 // Multiply-adds within one expression fuse into FMAs here (the rest of the
@@ -56,11 +57,13 @@ struct PrimU {
     float mrx, mry;       // mean relative to the tile origin
     float ca2, cb2, cc2;  // conic scaled by -log2(e)/2 (cb2 includes the factor 2)
     float fxr, fyr;       // frequency in revolutions per pixel
+    float ph0;            // carrier phase in revolutions
     float op, r, g, b;
     float ca, cb, cc, fx, fy;   // raw values for the backward
 };
 
 constexpr float kConicScale = -0.5f * kLog2e;
+constexpr float kTwoLn2 = 1.3862943611198906f;
 
 __device__ __forceinline__ PrimU load_prim(const Rec* __restrict__ recs, uint32_t prim, int ox, int oy,
                                            uint32_t* box0, uint32_t* box1)
@@ -74,6 +77,7 @@ __device__ __forceinline__ PrimU load_prim(const Rec* __restrict__ recs, uint32_
     u.cc2 = R.cc * kConicScale;
     u.fxr = R.fx * kInv2Pi;
     u.fyr = R.fy * kInv2Pi;
+    u.ph0 = R.ph;
     u.op = R.op;
     u.r = R.r; u.g = R.g; u.b = R.b;
     u.ca = R.ca; u.cb = R.cb; u.cc = R.cc; u.fx = R.fx; u.fy = R.fy;
@@ -87,14 +91,14 @@ struct PairEval {
 };
 
 __device__ __forceinline__ PairEval eval_at(float mrx, float mry, float ca2, float cb2, float cc2, float fxr, float fyr,
-                                            float lx, float ly)
+                                            float ph0, float lx, float ly)
 {
     PairEval p;
     p.dx = lx - mrx;
     p.dy = ly - mry;
     const float t = fmaf(ca2, p.dx, cb2 * p.dy);
     p.e2 = fmaf(t, p.dx, (cc2 * p.dy) * p.dy);
-    p.ph = fmaf(fxr, p.dx, fyr * p.dy);
+    p.ph = fmaf(fxr, p.dx, fmaf(fyr, p.dy, ph0));
     p.E = __builtin_amdgcn_exp2f(p.e2);
     p.K = fmaf(0.5f, __builtin_amdgcn_cosf(__builtin_amdgcn_fractf(p.ph)), 0.5f);
     p.W = p.K * p.E;
@@ -103,7 +107,7 @@ __device__ __forceinline__ PairEval eval_at(float mrx, float mry, float ca2, flo
 
 __device__ __forceinline__ PairEval eval_pair(const PrimU& u, float lx, float ly)
 {
-    return eval_at(u.mrx, u.mry, u.ca2, u.cb2, u.cc2, u.fxr, u.fyr, lx, ly);
+    return eval_at(u.mrx, u.mry, u.ca2, u.cb2, u.cc2, u.fxr, u.fyr, u.ph0, lx, ly);
 }
 
 // Sub-blocks (8 x 8) of a TW x TH tile hit by the pixel box, as a bit mask.
@@ -191,16 +195,17 @@ __device__ __forceinline__ void prioritise(uint32_t len)
 
 // ------------------------------------------------------------ block waves
 
-// One staged primitive (48 bytes).  The forward stages the conic and the
-// frequency pre-scaled as load_prim does; the backward stages them raw and
-// rebuilds the scaled values with the same operations, so both passes take
-// identical FP32 decisions.
+// One staged primitive (48 bytes), with the conic and the frequency
+// pre-scaled as load_prim does; forward and backward stage the same values,
+// so both passes take identical FP32 decisions.  A staged primitive's list position is not
+// stored: the j-th staged entry is the j-th set bit of the chunk's hit mask,
+// which the (wave-uniform) loops walk with scalar bit scans.
 struct __align__(16) Staged {
     float mrx, mry;     // mean relative to the block origin
     float c0, c1, c2;   // conic
     float f0, f1;       // frequency
+    float ph;           // carrier phase (revolutions)
     float op, r, g, b;
-    uint32_t pos;       // list position
 };
 static_assert(sizeof(Staged) == 48, "staged record must be 48 bytes");
 
@@ -266,7 +271,7 @@ __device__ __forceinline__ bool ellipse_meets(const Rec& R, const PixBox& q, flo
 // image (pixel coordinates stay below 2^15), so it meets no pixel box.
 constexpr uint32_t kNoBox = 0xffffffffu;
 
-__device__ __forceinline__ Staged stage_fwd(const Rec& R, int bx, int by, uint32_t pos)
+__device__ __forceinline__ Staged stage_fwd(const Rec& R, int bx, int by)
 {
     Staged w;
     w.mrx = (R.mx - (float)bx) + R.mxl;
@@ -276,39 +281,21 @@ __device__ __forceinline__ Staged stage_fwd(const Rec& R, int bx, int by, uint32
     w.c2 = R.cc * kConicScale;
     w.f0 = R.fx * kInv2Pi;
     w.f1 = R.fy * kInv2Pi;
+    w.ph = R.ph;
     w.op = R.op;
     w.r = R.r;
     w.g = R.g;
     w.b = R.b;
-    w.pos = pos;
     return w;
 }
 
 // Additive forward: colour premultiplied by the opacity (Eq. 4's weight).
-__device__ __forceinline__ Staged stage_add(const Rec& R, int bx, int by, uint32_t pos)
+__device__ __forceinline__ Staged stage_add(const Rec& R, int bx, int by)
 {
-    Staged w = stage_fwd(R, bx, by, pos);
+    Staged w = stage_fwd(R, bx, by);
     w.r = R.r * R.op;
     w.g = R.g * R.op;
     w.b = R.b * R.op;
-    return w;
-}
-
-__device__ __forceinline__ Staged stage_raw(const Rec& R, int bx, int by, uint32_t pos)
-{
-    Staged w;
-    w.mrx = (R.mx - (float)bx) + R.mxl;
-    w.mry = (R.my - (float)by) + R.myl;
-    w.c0 = R.ca;
-    w.c1 = R.cb;
-    w.c2 = R.cc;
-    w.f0 = R.fx;
-    w.f1 = R.fy;
-    w.op = R.op;
-    w.r = R.r;
-    w.g = R.g;
-    w.b = R.b;
-    w.pos = pos;
     return w;
 }
 
@@ -339,6 +326,7 @@ __device__ __forceinline__ void fwd_block(const ImgDesc* __restrict__ descs, int
     bool alive = valid;
     PixBox live = block_box(__ballot(alive), bx, by);
     const float thr2 = kp.q_add * kConicScale;
+    const float lg2_amin = __builtin_amdgcn_logf(kp.alpha_min);
     unsigned long long* cm_row = cmask ? cmask + (size_t)blk * cmask_words : nullptr;
     if (G.start < G.end) {
         const uint32_t e1 = G.end - 1u;
@@ -353,14 +341,16 @@ __device__ __forceinline__ void fwd_block(const ImgDesc* __restrict__ descs, int
         uint32_t pn = vals[min(base + (uint32_t)(kWave + l), e1)];
         for (;;) {
             // support threshold with margin: additive q <= q_add; alpha
-            // o W' >= alpha_min needs q <= 2 ln(o / alpha_min) (W' <= G')
-            const float Qs = (MODE == WIPES_2D_ADDITIVE ? kp.q_add : 2.0f * __logf(cur.op / kp.alpha_min)) * 1.001f +
+            // o W' >= alpha_min needs q <= 2 ln(o / alpha_min) = 2 ln 2 (log2 o - log2 alpha_min)
+            // (W' <= G'); the hardware log2 is within a few ulp, far inside the margin
+            const float Qs = (MODE == WIPES_2D_ADDITIVE ? kp.q_add
+                                                        : kTwoLn2 * (__builtin_amdgcn_logf(cur.op) - lg2_amin)) *
+                                 1.001f +
                              1e-3f;
             const bool hit = box_meets(cur.box0, cur.box1, live) & ellipse_meets(cur, live, Qs);
             const uint64_t m = __ballot(hit);
             if (hit)
-                stage[__popcll(m & below)] = MODE == WIPES_2D_ADDITIVE ? stage_add(cur, bx, by, base + (uint32_t)l)
-                                                                       : stage_fwd(cur, bx, by, base + (uint32_t)l);
+                stage[__popcll(m & below)] = MODE == WIPES_2D_ADDITIVE ? stage_add(cur, bx, by) : stage_fwd(cur, bx, by);
             const uint32_t cn = base + kWave;
             const bool more = cn < G.end;
             Rec nx{};
@@ -373,20 +363,23 @@ __device__ __forceinline__ void fwd_block(const ImgDesc* __restrict__ descs, int
             const int nh = __popcll(m);
             bool left = true;
             uint64_t contrib = 0;   // bit (pos & 63): the primitive at pos contributed to a pixel of the block
+            uint64_t rest = m;      // staged positions not yet blended (bit = position - base)
             for (int j = 0; j < nh; ++j) {
                 const Staged S = stage[j];
+                const uint32_t bp = (uint32_t)__builtin_ctzll(rest);   // this entry's position - base
+                rest &= rest - 1ull;
                 // the colour is read with the rest of the record, not inside the
                 // branch below, so its LDS latency overlaps the evaluation
                 float cr = S.r, cg = S.g, cb = S.b;
                 asm volatile("" : "+v"(cr), "+v"(cg), "+v"(cb));
-                const PairEval p = eval_at(S.mrx, S.mry, S.c0, S.c1, S.c2, S.f0, S.f1, lx, ly);
+                const PairEval p = eval_at(S.mrx, S.mry, S.c0, S.c1, S.c2, S.f0, S.f1, S.ph, lx, ly);
                 if constexpr (MODE == WIPES_2D_ADDITIVE) {
                     const bool in = p.e2 >= thr2;
                     const float w = in ? p.W : 0.0f;
                     C0 = fmaf(S.r, w, C0);
                     C1 = fmaf(S.g, w, C1);
                     C2 = fmaf(S.b, w, C2);
-                    if (__ballot(in && valid)) contrib |= 1ull << (S.pos & 63u);
+                    if (__ballot(in && valid)) contrib |= 1ull << bp;
                     continue;
                 }
                 const float a = S.op * p.W;
@@ -399,10 +392,10 @@ __device__ __forceinline__ void fwd_block(const ImgDesc* __restrict__ descs, int
                 C1 = fmaf(wt, cg, C1);
                 C2 = fmaf(wt, cb, C2);
                 T = T * (1.0f - al);
-                lst = adds ? (int32_t)S.pos : lst;
+                lst = adds ? (int32_t)(base + bp) : lst;
                 const bool died = adds && T < kp.T_min;
                 alive = alive && !died;
-                if (__ballot(adds)) contrib |= 1ull << (S.pos & 63u);
+                if (__ballot(adds)) contrib |= 1ull << bp;
                 if (__ballot(died)) {
                     const uint64_t am = __ballot(alive);
                     if (am == 0ull) {
@@ -647,6 +640,9 @@ __device__ __forceinline__ void bwd_tile(const ImgDesc* __restrict__ descs, int 
     // this chunk before its buffer is written again.
     uint32_t pbuf = 0;
     Staged* st = stage[w];
+    // the lanes that hold the wave totals of the twelve slot values, and which value
+    const bool red_lane = (l & 3) == 0 && (l & 15) <= 8;
+    const int red_idx = reduce12_index(l);
     const unsigned long long* cm_row = cmask + (size_t)w * cmask_words;
     // Chunks are the 64-position words of the global list clipped to [start,
     // hi), walked top down; lane l holds position (c0 & ~63) + l.  A chunk's
@@ -692,7 +688,7 @@ __device__ __forceinline__ void bwd_tile(const ImgDesc* __restrict__ descs, int 
         PrimPack cq{};
         if (CR == 1 && cmine[0]) cq = pk[cprim[0]];
         if ((m >> l) & 1ull) {
-            st[__popcll(m & below)] = stage_raw(cur, bx, by, b + (uint32_t)l);
+            st[__popcll(m & below)] = stage_fwd(cur, bx, by);
         } else {
             float4* z = reinterpret_cast<float4*>(mine + l * kSlot);
             z[0] = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -714,16 +710,17 @@ __device__ __forceinline__ void bwd_tile(const ImgDesc* __restrict__ descs, int 
         if (l == 0) hcur[w] = m;
         wave_lds_sync();
         const int nh = __popcll(m);
-        auto replay = [&](const Staged& S) {
+        // bp: the staged entry's position - b (its bit in m)
+        auto replay = [&](const Staged& S, uint32_t bp) {
+            __builtin_assume(bp < 64u);
             // branch-free: a pair that takes no part gets zero weight, for which
             // every update is an exact identity and every gradient term is zero
             float v[12];
 #pragma unroll
             for (int k = 0; k < 12; ++k) v[k] = 0.0f;
-            const PairEval p = eval_at(S.mrx, S.mry, S.c0 * kConicScale, S.c1 * (2.0f * kConicScale),
-                                       S.c2 * kConicScale, S.f0 * kInv2Pi, S.f1 * kInv2Pi, lx, ly);
+            const PairEval p = eval_at(S.mrx, S.mry, S.c0, S.c1, S.c2, S.f0, S.f1, S.ph, lx, ly);
             const float a = S.op * p.W;
-            const bool reach = on && (int32_t)S.pos <= lst;
+            const bool reach = on && (int32_t)(b + bp) <= lst;
             bool takes;
             float dW;
             if constexpr (MODE == WIPES_2D_ADDITIVE) {
@@ -755,24 +752,26 @@ __device__ __forceinline__ void bwd_tile(const ImgDesc* __restrict__ descs, int 
                 dW = S.op * da;
             }
             pair_grads(v, p, dW);
-            const bool any = __ballot(takes) != 0ull;
-            float* o = mine + (S.pos & 63u) * kSlot;
-            if (any) {
-                const float tot = wave_reduce12_valu(v);
-                if ((l & 15) == 0 || (l & 15) == 4 || (l & 15) == 8) o[reduce12_index(l)] = tot;
-            } else if (l < kSlot) {
-                o[l] = 0.0f;
-            }
+            // (a primitive no pixel takes reduces to exact zeros: every term has a zero factor)
+            const float tot = wave_reduce12_valu(v);
+            if (red_lane) mine[bp * kSlot + red_idx] = tot;
         };
         // back to front, two records a round in alternating registers: each
-        // is read from the stage one replay ahead, without register copies
+        // is read from the stage one replay ahead, without register copies;
+        // positions come off the top of the hit mask
+        uint64_t rest = m;
+        auto top_pos = [&]() {
+            const uint32_t bp = 63u - (uint32_t)__builtin_clzll(rest);
+            rest &= ~(1ull << bp);
+            return bp;
+        };
         Staged Sa = st[nh > 0 ? nh - 1 : 0];
         for (int j = nh - 1; j >= 0; j -= 2) {
             const Staged Sb = st[j > 0 ? j - 1 : 0];
-            replay(Sa);
+            replay(Sa, top_pos());
             if (j == 0) break;
             Sa = st[j > 1 ? j - 2 : 0];
-            replay(Sb);
+            replay(Sb, top_pos());
         }
         __syncthreads();
         // positions some block staged get their slot written and marked

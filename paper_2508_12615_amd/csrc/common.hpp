@@ -30,7 +30,8 @@ constexpr float kInv2Pi = 0.15915494309189535f;
 // Screen record (mirrors wipes_screen_record).  The mean is mx + mxl in
 // exact arithmetic (mx = FP32 rounding, mxl = FP32 rounding of the rest).
 struct __align__(64) Rec {
-    float mx, my, ca, cb, cc, fx, fy, op, r, g, b, mxl, myl, reserved;
+    float mx, my, ca, cb, cc, fx, fy, op, r, g, b, mxl, myl;
+    float ph;   // carrier phase in revolutions (phi0 / 2 pi)
     uint32_t box0, box1;
 };
 static_assert(sizeof(Rec) == 64, "screen record must be 64 bytes");
@@ -61,6 +62,8 @@ struct __align__(16) ImgDesc {
     const float* color;
     const float* opac;
     const float* vel;
+    const float* phase;   // [n] carrier phase (radians) or null
+    const float* sh;      // [n, (deg + 1)^2, 3] spherical-harmonic colour or null
     float* g_mean;
     float* g_cov;
     float* g_quat;
@@ -69,6 +72,8 @@ struct __align__(16) ImgDesc {
     float* g_color;
     float* g_opac;
     float* g_vel;
+    float* g_phase;
+    float* g_sh;
     float* out_image;     // optional per-image colour output (forward)
     int32_t prim_begin;   // first global record index of this image
     int32_t n;            // primitives of this image
@@ -79,7 +84,7 @@ struct __align__(16) ImgDesc {
     float view[12];       // rows 0..2 of the world->camera matrix
     float time;
     float limx, limy;     // guard band of x/z and y/z
-    int32_t pad_;
+    float cam_c[3];       // camera centre in world coordinates (spherical-harmonic view direction)
 };
 
 // A descriptor table small enough to travel as a kernel argument (the
@@ -101,6 +106,7 @@ struct Clear2 {
 // Rasterizer constants as the kernels see them.
 struct KParams {
     int32_t mode, cov, tile_w, tile_h, log2_tw, log2_th;
+    int32_t freq_xform, sh_degree;
     float alpha_min, alpha_max, T_min, q_add, blur_eps, near_plane;
     float bg[3];
 };

@@ -21,9 +21,19 @@
 
 namespace wipes {
 
+// Carrier phase phi0 (radians; none = 0) as the record stores it: in
+// revolutions, reduced to [0, 1) in FP64 so that the blend's phase sum stays
+// exact however large phi0 is.
+__device__ __forceinline__ float phase_rev(const float* __restrict__ phase, int32_t j)
+{
+    if (!phase) return 0.0f;
+    const double r = (double)phase[j] * 0.15915494309189533577;
+    return (float)(r - floor(r));
+}
+
 __device__ __forceinline__ void store_record(Rec* __restrict__ recs, int32_t i, double mx, double my, double ca,
                                              double cb, double cc, float fx, float fy, float op, float r, float g,
-                                             float b)
+                                             float b, float ph)
 {
     float mxh = (float)mx, myh = (float)my;
     float mxl = (float)(mx - (double)mxh), myl = (float)(my - (double)myh);
@@ -31,7 +41,7 @@ __device__ __forceinline__ void store_record(Rec* __restrict__ recs, int32_t i, 
     o[0] = make_float4(mxh, myh, (float)ca, (float)cb);
     o[1] = make_float4((float)cc, fx, fy, op);
     o[2] = make_float4(r, g, b, mxl);
-    o[3] = make_float4(myl, 0.0f, 0.0f, 0.0f);
+    o[3] = make_float4(myl, ph, 0.0f, 0.0f);
 }
 
 __device__ __forceinline__ void store_culled(Rec* __restrict__ recs, Aux* __restrict__ aux, int32_t i, float depth)
@@ -94,10 +104,61 @@ __global__ void __launch_bounds__(256) k_project_2d(const ImgDesc* __restrict__ 
     const float2 mu = reinterpret_cast<const float2*>(d.mean)[j];
     const float2 f = reinterpret_cast<const float2*>(d.freq)[j];
     store_record(recs, i, mu.x, mu.y, syy * inv, -sxy * inv, sxx * inv, f.x, f.y, d.opac[j], d.color[3 * j],
-                 d.color[3 * j + 1], d.color[3 * j + 2]);
+                 d.color[3 * j + 1], d.color[3 * j + 2], phase_rev(d.phase, j));
     float rx, ry;
     support_box(sxx, syy, kp.q_add, &rx, &ry);
     aux[i] = Aux{rx, ry, 0.0f, support_threshold(kp.q_add)};
+}
+
+// View-dependent colour (Sec. 3.1: 3DGS keeps colour as spherical-harmonic
+// coefficients): colour_c = sum_k Y_k(u) sh[k][c] over the real harmonics of
+// degree <= deg (Condon-Shortley phase, k = l^2 + l + m) at the unit
+// direction u from the camera centre to the mean.  Each Y_k is its
+// Cartesian polynomial on the unit sphere, built band by band from the
+// products of (x, y, z).
+__device__ __forceinline__ void sh_colour(int deg, const float* __restrict__ c, double x, double y, double z,
+                                          double out[3])
+{
+    const double kPi = 3.14159265358979323846;
+    double Y[16];
+    Y[0] = 0.5 / sqrt(kPi);
+    int K = 1;
+    if (deg >= 1) {
+        const double a = sqrt(3.0 / (4.0 * kPi));
+        Y[1] = -a * y;
+        Y[2] = a * z;
+        Y[3] = -a * x;
+        K = 4;
+    }
+    if (deg >= 2) {
+        const double xx = x * x, yy = y * y, zz = z * z;
+        const double a = 0.5 * sqrt(15.0 / kPi), b = 0.25 * sqrt(5.0 / kPi), h = 0.25 * sqrt(15.0 / kPi);
+        Y[4] = a * x * y;
+        Y[5] = -a * y * z;
+        Y[6] = b * (2.0 * zz - xx - yy);
+        Y[7] = -a * x * z;
+        Y[8] = h * (xx - yy);
+        K = 9;
+    }
+    if (deg >= 3) {
+        const double xx = x * x, yy = y * y, zz = z * z;
+        const double a = 0.25 * sqrt(35.0 / (2.0 * kPi)), b = 0.5 * sqrt(105.0 / kPi);
+        const double e = 0.25 * sqrt(21.0 / (2.0 * kPi)), g = 0.25 * sqrt(7.0 / kPi), h = 0.25 * sqrt(105.0 / kPi);
+        const double t = 4.0 * zz - xx - yy;
+        Y[9] = -a * y * (3.0 * xx - yy);
+        Y[10] = b * x * y * z;
+        Y[11] = -e * y * t;
+        Y[12] = g * z * (2.0 * zz - 3.0 * xx - 3.0 * yy);
+        Y[13] = -e * x * t;
+        Y[14] = h * z * (xx - yy);
+        Y[15] = -a * x * (xx - 3.0 * yy);
+        K = 16;
+    }
+    for (int ch = 0; ch < 3; ++ch) {
+        double acc = 0.0;
+        for (int k = 0; k < K; ++k) acc += Y[k] * (double)c[3 * k + ch];
+        out[ch] = acc;
+    }
 }
 
 // FP32 depth key: z = fma(V20, m_x, fma(V21, m_y, fma(V22, m_z, V23))), m = fma(v, tau, mu).
@@ -179,11 +240,47 @@ __global__ void __launch_bounds__(256) k_project_3d(const ImgDesc* __restrict__ 
     }
     const double inv = 1.0 / det;
     const double f0 = d.freq[3 * j], f1 = d.freq[3 * j + 1], f2 = d.freq[3 * j + 2];
-    const float fx = (float)(M[0][0] * f0 + M[0][1] * f1 + M[0][2] * f2);
-    const float fy = (float)(M[1][0] * f0 + M[1][1] * f1 + M[1][2] * f2);
+    float fx, fy;
+    if (kp.freq_xform == WIPES_FREQ_VECTOR) {   // f' = M f
+        fx = (float)(M[0][0] * f0 + M[0][1] * f1 + M[0][2] * f2);
+        fy = (float)(M[1][0] * f0 + M[1][1] * f1 + M[1][2] * f2);
+    } else {
+        // covector: f' = rows 0-1 of (J3 W)^-T f = J3^-T (W f) (W a rotation),
+        // J3 = J with the third row t/|t|; J3^-T g = adj(J3)^T g / det J3
+        const double tl = sqrt(t[0] * t[0] + t[1] * t[1] + tz * tz);
+        const double J3[3][3] = {{J00, 0.0, J02}, {0.0, J11, J12}, {t[0] / tl, t[1] / tl, tz / tl}};
+        double g[3];
+        for (int r = 0; r < 3; ++r) g[r] = d.view[4 * r] * f0 + d.view[4 * r + 1] * f1 + d.view[4 * r + 2] * f2;
+        // cofactors C[r][c] of J3: (J3^-T g)_r = sum_c C[r][c] g_c / det
+        const double C00 = J3[1][1] * J3[2][2] - J3[1][2] * J3[2][1], C01 = J3[1][2] * J3[2][0] - J3[1][0] * J3[2][2];
+        const double C02 = J3[1][0] * J3[2][1] - J3[1][1] * J3[2][0];
+        const double C10 = J3[0][2] * J3[2][1] - J3[0][1] * J3[2][2], C11 = J3[0][0] * J3[2][2] - J3[0][2] * J3[2][0];
+        const double C12 = J3[0][1] * J3[2][0] - J3[0][0] * J3[2][1];
+        const double dj = J3[0][0] * C00 + J3[0][1] * C01 + J3[0][2] * C02;
+        if (!(dj != 0.0)) {
+            store_culled(recs, aux, i, zkey);
+            return;
+        }
+        fx = (float)((C00 * g[0] + C01 * g[1] + C02 * g[2]) / dj);
+        fy = (float)((C10 * g[0] + C11 * g[1] + C12 * g[2]) / dj);
+    }
+    float cr, cg, cb;
+    if (kp.sh_degree >= 0) {   // colour from the view direction camera centre -> mean(tau)
+        const double dx = m[0] - (double)d.cam_c[0], dy = m[1] - (double)d.cam_c[1], dz = m[2] - (double)d.cam_c[2];
+        const double il = 1.0 / sqrt(dx * dx + dy * dy + dz * dz);
+        const int K = (kp.sh_degree + 1) * (kp.sh_degree + 1);
+        double col[3];
+        sh_colour(kp.sh_degree, d.sh + (size_t)j * K * 3, dx * il, dy * il, dz * il, col);
+        cr = (float)col[0];
+        cg = (float)col[1];
+        cb = (float)col[2];
+    } else {
+        cr = d.color[3 * j];
+        cg = d.color[3 * j + 1];
+        cb = d.color[3 * j + 2];
+    }
     const double mx = fxc * t[0] * iz + d.cx, my = fyc * t[1] * iz + d.cy;
-    store_record(recs, i, mx, my, syy * inv, -sxy * inv, sxx * inv, fx, fy, op, d.color[3 * j],
-                 d.color[3 * j + 1], d.color[3 * j + 2]);
+    store_record(recs, i, mx, my, syy * inv, -sxy * inv, sxx * inv, fx, fy, op, cr, cg, cb, phase_rev(d.phase, j));
     float rx, ry;
     const double Q = 2.0 * log((double)op / (double)kp.alpha_min);
     support_box(sxx, syy, Q, &rx, &ry);

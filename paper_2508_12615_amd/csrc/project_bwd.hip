@@ -14,6 +14,14 @@
 //                  dL/dSigma = M^T G M, dL/df = M^T dL/df', then J(t), mu'(t),
 //                  t = W mu + w and Sigma = V V^T with V = R(q) diag(s),
 //                  q normalised inside.
+//   Covector frequency f' = rows 0-1 of A^-T f, A = J3 W (J3 = J over the
+//                  row t/|t|): dL/df = A^-1 g (g = (dL/df', 0)) and
+//                  dL/dA = -(A^-T f) (dL/df)^T, whose rows 0-1 join dL/dM and
+//                  whose row 2 reaches t through t/|t|.
+//   Carrier phase: dL/dphi0 is the slot sum of dL/dphi itself.
+//   Spherical-harmonic colour c = sum_k Y_k(u) sh_k, u = d/|d|, d = mu - C:
+//                  dL/dsh_k = Y_k dL/dc, dL/dmu += (I - u u^T)/|d| sum_k
+//                  grad Y_k (sh_k . dL/dc).
 // The arithmetic is FP32: the inputs (screen record, slot sums, parameters)
 // are FP32 and the gradients are compared at 1e-3 relative, so FP64 would only
 // cost time (the forward projection is FP64 for the mean's sub-pixel phase).
@@ -30,6 +38,55 @@ namespace wipes {
 
 constexpr int kSlotB = 12;
 using real = float;
+
+// Value and gradient in R^3 of a polynomial in (x, y, z), carried through
+// products and sums (forward-mode derivatives), so each spherical harmonic's
+// gradient comes from the same expression as its value.
+struct Poly3 {
+    float v, gx, gy, gz;
+};
+__device__ __forceinline__ Poly3 operator*(Poly3 a, Poly3 b)
+{
+    return {a.v * b.v, a.gx * b.v + a.v * b.gx, a.gy * b.v + a.v * b.gy, a.gz * b.v + a.v * b.gz};
+}
+__device__ __forceinline__ Poly3 operator*(float s, Poly3 a) { return {s * a.v, s * a.gx, s * a.gy, s * a.gz}; }
+__device__ __forceinline__ Poly3 operator+(Poly3 a, Poly3 b) { return {a.v + b.v, a.gx + b.gx, a.gy + b.gy, a.gz + b.gz}; }
+__device__ __forceinline__ Poly3 operator-(Poly3 a, Poly3 b) { return {a.v - b.v, a.gx - b.gx, a.gy - b.gy, a.gz - b.gz}; }
+
+// Real spherical harmonics of degree <= deg (Condon-Shortley phase, index
+// l^2 + l + m) at (x, y, z) as polynomials; returns the count (deg + 1)^2.
+__device__ __forceinline__ int sh_poly(int deg, float ux, float uy, float uz, Poly3 Y[16])
+{
+    const float kPi = 3.14159265358979f;
+    const Poly3 x{ux, 1.f, 0.f, 0.f}, y{uy, 0.f, 1.f, 0.f}, z{uz, 0.f, 0.f, 1.f};
+    Y[0] = {0.5f / sqrtf(kPi), 0.f, 0.f, 0.f};
+    if (deg < 1) return 1;
+    const float a1 = sqrtf(3.0f / (4.0f * kPi));
+    Y[1] = (-a1) * y;
+    Y[2] = a1 * z;
+    Y[3] = (-a1) * x;
+    if (deg < 2) return 4;
+    const Poly3 xx = x * x, yy = y * y, zz = z * z;
+    const float a2 = 0.5f * sqrtf(15.0f / kPi), b2 = 0.25f * sqrtf(5.0f / kPi), h2 = 0.25f * sqrtf(15.0f / kPi);
+    Y[4] = a2 * (x * y);
+    Y[5] = (-a2) * (y * z);
+    Y[6] = b2 * (2.0f * zz - xx - yy);
+    Y[7] = (-a2) * (x * z);
+    Y[8] = h2 * (xx - yy);
+    if (deg < 3) return 9;
+    const float a3 = 0.25f * sqrtf(35.0f / (2.0f * kPi)), b3 = 0.5f * sqrtf(105.0f / kPi);
+    const float e3 = 0.25f * sqrtf(21.0f / (2.0f * kPi)), g3 = 0.25f * sqrtf(7.0f / kPi);
+    const float h3 = 0.25f * sqrtf(105.0f / kPi);
+    const Poly3 t = 4.0f * zz - xx - yy;
+    Y[9] = (-a3) * (y * (3.0f * xx - yy));
+    Y[10] = b3 * (x * y * z);
+    Y[11] = (-e3) * (y * t);
+    Y[12] = g3 * (z * (2.0f * zz - 3.0f * xx - 3.0f * yy));
+    Y[13] = (-e3) * (x * t);
+    Y[14] = h3 * (z * (xx - yy));
+    Y[15] = (-a3) * (x * (xx - 3.0f * yy));
+    return 16;
+}
 
 __global__ void __launch_bounds__(256) k_project_bwd(const ImgDesc* __restrict__ descs_mem, int B, int32_t n_total,
                                                       KParams kp, const Rec* __restrict__ recs,
@@ -163,13 +220,19 @@ __global__ void __launch_bounds__(256) k_project_bwd(const ImgDesc* __restrict__
     const int32_t j = i - d.prim_begin;
     if (dscreen) {
 #pragma unroll
-        for (int k = 0; k < 11; ++k) dscreen[(size_t)i * 11 + k] = acc[k];
+        for (int k = 0; k < 12; ++k) dscreen[(size_t)i * 12 + k] = acc[k];
     }
     const int D = kp.mode == WIPES_2D_ADDITIVE ? 2 : 3;
-    if (d.g_color)
+    const bool sh = kp.sh_degree >= 0;
+    if (d.g_color && !sh)
         for (int k = 0; k < 3; ++k) d.g_color[3 * j + k] = acc[8 + k];
     if (d.g_opac) d.g_opac[j] = acc[7];
+    if (d.g_phase) d.g_phase[j] = acc[11];
     if (c == 0) {
+        if (d.g_sh) {
+            const int K3 = 3 * (kp.sh_degree + 1) * (kp.sh_degree + 1);
+            for (int k = 0; k < K3; ++k) d.g_sh[(size_t)K3 * j + k] = 0.0f;
+        }
         // culled or off-screen: zero gradients
         if (d.g_mean) for (int k = 0; k < D; ++k) d.g_mean[D * j + k] = 0.0f;
         if (d.g_freq) for (int k = 0; k < D; ++k) d.g_freq[D * j + k] = 0.0f;
@@ -254,8 +317,41 @@ __global__ void __launch_bounds__(256) k_project_bwd(const ImgDesc* __restrict__
     for (int r = 0; r < 2; ++r)
         for (int k = 0; k < 3; ++k) MS[r][k] = T[r][0] * V[k][0] + T[r][1] * V[k][1] + T[r][2] * V[k][2];
     real dM[2][3];
+    const bool cov_f = kp.freq_xform == WIPES_FREQ_COVECTOR;
     for (int r = 0; r < 2; ++r)
-        for (int k = 0; k < 3; ++k) dM[r][k] = 2.0f * (G[r][0] * MS[0][k] + G[r][1] * MS[1][k]) + dfp[r] * f3[k];
+        for (int k = 0; k < 3; ++k)
+            dM[r][k] = 2.0f * (G[r][0] * MS[0][k] + G[r][1] * MS[1][k]) + (cov_f ? 0.0f : dfp[r] * f3[k]);
+    // covector frequency: A = J3 W, f'3 = A^-T f, dL/df = A^-1 (dfp, 0),
+    // dL/dA = -f'3 (dL/df)^T (rows 0-1 into dM; row 2 through t/|t| below)
+    real dfw[3] = {0.0f, 0.0f, 0.0f}, dA2[3] = {0.0f, 0.0f, 0.0f};
+    const real tl = sqrtf(t[0] * t[0] + t[1] * t[1] + tz * tz);
+    if (cov_f) {
+        real A[3][3];
+        for (int k = 0; k < 3; ++k) {
+            A[0][k] = M[0][k];
+            A[1][k] = M[1][k];
+            A[2][k] = (t[0] * Rw[0][k] + t[1] * Rw[1][k] + tz * Rw[2][k]) / tl;
+        }
+        // inverse by cofactors: Ai[r][c] = Cof[c][r] / det
+        real Cf[3][3];
+        for (int r = 0; r < 3; ++r)
+            for (int k = 0; k < 3; ++k) {
+                const int r1 = (r + 1) % 3, r2 = (r + 2) % 3, k1 = (k + 1) % 3, k2 = (k + 2) % 3;
+                Cf[r][k] = A[r1][k1] * A[r2][k2] - A[r1][k2] * A[r2][k1];
+            }
+        const real det = A[0][0] * Cf[0][0] + A[0][1] * Cf[0][1] + A[0][2] * Cf[0][2];
+        const real id = 1.0f / det;
+        real f3p[3];
+        for (int r = 0; r < 3; ++r)   // (A^-T f)_r = sum_c Ai[c][r] f_c = sum_c Cf[r][c] f_c / det
+            f3p[r] = (Cf[r][0] * f3[0] + Cf[r][1] * f3[1] + Cf[r][2] * f3[2]) * id;
+        for (int k = 0; k < 3; ++k)   // (A^-1 g)_k = sum_r Cf[r][k] g_r / det
+            dfw[k] = (Cf[0][k] * dfp[0] + Cf[1][k] * dfp[1]) * id;
+        for (int k = 0; k < 3; ++k) {
+            dM[0][k] -= f3p[0] * dfw[k];
+            dM[1][k] -= f3p[1] * dfw[k];
+            dA2[k] = -f3p[2] * dfw[k];
+        }
+    }
     // dSigma = M^T G M
     real GM[2][3];
     for (int r = 0; r < 2; ++r)
@@ -289,7 +385,7 @@ __global__ void __launch_bounds__(256) k_project_bwd(const ImgDesc* __restrict__
         d.g_quat[4 * j + 3] = (float)((dz - z * dot) / qn);
     }
     if (d.g_freq)
-        for (int k = 0; k < 3; ++k) d.g_freq[3 * j + k] = (float)(M[0][k] * dfp[0] + M[1][k] * dfp[1]);
+        for (int k = 0; k < 3; ++k) d.g_freq[3 * j + k] = cov_f ? dfw[k] : (float)(M[0][k] * dfp[0] + M[1][k] * dfp[1]);
     // dJ = dM W^T
     real dJ[2][3];
     for (int r = 0; r < 2; ++r)
@@ -309,11 +405,46 @@ __global__ void __launch_bounds__(256) k_project_bwd(const ImgDesc* __restrict__
     } else {
         dt[2] += fyc * v * iz2 * dJ[1][2];
     }
+    if (cov_f) {   // row 2 of A is (t/|t|)^T W: dL/dt += (I - th th^T)/|t| (W dA2)
+        real gth[3], th[3];
+        for (int r = 0; r < 3; ++r) {
+            gth[r] = Rw[r][0] * dA2[0] + Rw[r][1] * dA2[1] + Rw[r][2] * dA2[2];
+            th[r] = (r == 0 ? t[0] : r == 1 ? t[1] : tz) / tl;
+        }
+        const real dot = th[0] * gth[0] + th[1] * gth[1] + th[2] * gth[2];
+        for (int r = 0; r < 3; ++r) dt[r] += (gth[r] - th[r] * dot) / tl;
+    }
     dt[0] += fxc * iz * acc[0];
     dt[1] += fyc * iz * acc[1];
     dt[2] += -fxc * t[0] * iz2 * acc[0] - fyc * t[1] * iz2 * acc[1];
     real dm[3];
     for (int k = 0; k < 3; ++k) dm[k] = Rw[0][k] * dt[0] + Rw[1][k] * dt[1] + Rw[2][k] * dt[2];
+    if (sh) {   // colour from the view direction u = (mu - C)/|mu - C|
+        const real dx = m[0] - d.cam_c[0], dy = m[1] - d.cam_c[1], dz = m[2] - d.cam_c[2];
+        const real dl = sqrtf(dx * dx + dy * dy + dz * dz), il = 1.0f / dl;
+        const real ux = dx * il, uy = dy * il, uz = dz * il;
+        Poly3 Y[16];
+        const int K = sh_poly(kp.sh_degree, ux, uy, uz, Y);
+        const float* shc = d.sh + (size_t)j * K * 3;
+        const real gr = acc[8], gg = acc[9], gb = acc[10];
+        real du[3] = {0.0f, 0.0f, 0.0f};
+        for (int k = 0; k < K; ++k) {
+            const real w = shc[3 * k] * gr + shc[3 * k + 1] * gg + shc[3 * k + 2] * gb;
+            du[0] += Y[k].gx * w;
+            du[1] += Y[k].gy * w;
+            du[2] += Y[k].gz * w;
+            if (d.g_sh) {
+                float* o = d.g_sh + ((size_t)j * K + k) * 3;
+                o[0] = Y[k].v * gr;
+                o[1] = Y[k].v * gg;
+                o[2] = Y[k].v * gb;
+            }
+        }
+        const real dot = ux * du[0] + uy * du[1] + uz * du[2];
+        dm[0] += (du[0] - ux * dot) * il;
+        dm[1] += (du[1] - uy * dot) * il;
+        dm[2] += (du[2] - uz * dot) * il;
+    }
     if (d.g_mean)
         for (int k = 0; k < 3; ++k) d.g_mean[3 * j + k] = (float)dm[k];
     if (d.g_vel)

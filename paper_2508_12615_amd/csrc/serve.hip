@@ -123,6 +123,7 @@ struct SReq {
     int32_t scene = 0;
     wipes_camera cam{};
     float* out = nullptr;
+    hipEvent_t ready = nullptr;   // recorded on the caller's stream at submit: `out` is free to write after it
     double t_submit = 0.0, t_done = -1.0;
     bool deferred = false;
     bool admitted = false;
@@ -207,6 +208,8 @@ void retire_front(wipes_server* S)
     for (uint64_t id : b.ids) {
         SReq& r = S->reqs[id];
         r.t_done = t;
+        if (r.ready) S->ev_pool.push_back(r.ready);
+        r.ready = nullptr;
         S->lat_ms.push_back((t - r.t_submit) * 1e3);
         S->scenes[r.scene].refs--;
         S->slots_used--;
@@ -238,7 +241,8 @@ void completer_main(wipes_server* S)
 // Project, bin, sort (prep stream) and blend (blend stream) one batch.
 // Called without the lock; takes it only for the arena (shared with the
 // completion thread).  *K_out receives the batch's instance count.
-wipes_status launch_batch(wipes_server* S, std::vector<wipes_image>& ims, int64_t cap, SBatch& B, int64_t* K_out)
+wipes_status launch_batch(wipes_server* S, std::vector<wipes_image>& ims, const std::vector<hipEvent_t>& ready,
+                          int64_t cap, SBatch& B, int64_t* K_out)
 {
     wipes_batch b{(int32_t)ims.size(), ims.data()};
     for (int attempt = 0; attempt < 4; ++attempt) {
@@ -275,6 +279,9 @@ wipes_status launch_batch(wipes_server* S, std::vector<wipes_image>& ims, int64_
         *K_out = K;
         (void)hipEventRecord(B.prep, S->s_prep);
         (void)hipStreamWaitEvent(S->s_blend, B.prep, 0);
+        // the blend writes the callers' buffers: after whatever their streams queued before each submit
+        for (hipEvent_t e : ready)
+            if (e) (void)hipStreamWaitEvent(S->s_blend, e, 0);
         // every image writes to its request's buffer; the batch image array is unused
         st = wipes_render_fwd(S->ctx, &S->params, &b, &sb, &bb, T, T, last, S->s_blend);
         (void)hipEventRecord(B.done, S->s_blend);
@@ -307,6 +314,7 @@ void worker_main(wipes_server* S)
         std::vector<wipes_image> cand;
         std::vector<double> ratio;
         std::vector<int32_t> cand_scene;
+        std::vector<hipEvent_t> cand_ready;
         for (size_t i = 0; i < S->pending.size() && i < max_take; ++i) {
             const SReq& r = S->reqs[S->pending[i]];
             const SScene& sc = S->scenes[r.scene];
@@ -317,6 +325,7 @@ void worker_main(wipes_server* S)
             cand.push_back(im);
             ratio.push_back(sc.k_ratio);
             cand_scene.push_back(r.scene);
+            cand_ready.push_back(r.ready);
         }
         const size_t take = admit_prefix(cand.size(), max_take, S->arena, [&](size_t k) {
             std::vector<wipes_image> pre(cand.begin(), cand.begin() + k);
@@ -336,6 +345,8 @@ void worker_main(wipes_server* S)
                 // the head request does not fit even an empty arena: it fails
                 SReq& r = S->reqs[S->pending.front()];
                 r.t_done = now_s();
+                if (r.ready) S->ev_pool.push_back(r.ready);
+                r.ready = nullptr;
                 S->scenes[r.scene].refs--;
                 S->pending.pop_front();
                 S->err = "request exceeds the serving arena";
@@ -356,6 +367,7 @@ void worker_main(wipes_server* S)
         cand.resize(take);
         ratio.resize(take);
         cand_scene.resize(take);
+        cand_ready.resize(take);
         const int64_t cap = capacity_for(cand, ratio);
         S->slots_used += (int)take;
         S->n_admitted += (int64_t)take;
@@ -365,7 +377,7 @@ void worker_main(wipes_server* S)
         B.done = get_event(S);
         lk.unlock();
         int64_t K = 0;
-        wipes_status st = launch_batch(S, cand, cap, B, &K);
+        wipes_status st = launch_batch(S, cand, cand_ready, cap, B, &K);
         lk.lock();
         S->launching--;
         if (st != WIPES_OK) {
@@ -376,6 +388,8 @@ void worker_main(wipes_server* S)
             for (uint64_t id : B.ids) {
                 SReq& r = S->reqs[id];
                 r.t_done = now_s();
+                if (r.ready) S->ev_pool.push_back(r.ready);
+                r.ready = nullptr;
                 S->scenes[r.scene].refs--;
                 S->slots_used--;
             }
@@ -444,10 +458,14 @@ wipes_status wipes_serve_create(const wipes_serve_config* cfg, const wipes_param
 wipes_status wipes_serve_load_scene(wipes_server* S, const wipes_prims* prims, int32_t* scene_id)
 {
     if (!S || !prims || !scene_id || prims->n <= 0 || !prims->mean || !prims->quat || !prims->scale ||
-        !prims->freq || !prims->color || !prims->opacity)
+        !prims->freq || !prims->opacity)
         return fail(nullptr, WIPES_ERR_INVALID, "server, prims (3D, n > 0) and scene_id must be set");
+    const int deg = S->params.sh_degree;
+    const int K3 = deg >= 0 ? 3 * (deg + 1) * (deg + 1) : 0;
+    if (deg < 0 ? !prims->color : !prims->sh)
+        return fail(nullptr, WIPES_ERR_INVALID, "scene needs %s", deg < 0 ? "color" : "sh coefficients");
     const int64_t n = prims->n;
-    const int per = 3 + 4 + 3 + 3 + 3 + 1 + (prims->velocity ? 3 : 0);
+    const int per = 3 + 4 + 3 + 3 + (deg < 0 ? 3 : 0) + 1 + (prims->velocity ? 3 : 0) + (prims->phase ? 1 : 0) + K3;
     void* mem = nullptr;
     hipError_t e = hipMalloc(&mem, (size_t)n * per * 4);
     if (e != hipSuccess) return hip_fail(nullptr, e, "scene allocation");
@@ -465,9 +483,11 @@ wipes_status wipes_serve_load_scene(wipes_server* S, const wipes_prims* prims, i
     if (e == hipSuccess) e = put(prims->quat, 4, &sc.prims.quat);
     if (e == hipSuccess) e = put(prims->scale, 3, &sc.prims.scale);
     if (e == hipSuccess) e = put(prims->freq, 3, &sc.prims.freq);
-    if (e == hipSuccess) e = put(prims->color, 3, &sc.prims.color);
+    if (e == hipSuccess) e = put(deg < 0 ? prims->color : nullptr, 3, &sc.prims.color);
     if (e == hipSuccess) e = put(prims->opacity, 1, &sc.prims.opacity);
     if (e == hipSuccess) e = put(prims->velocity, 3, &sc.prims.velocity);
+    if (e == hipSuccess) e = put(prims->phase, 1, &sc.prims.phase);
+    if (e == hipSuccess) e = put(deg >= 0 ? prims->sh : nullptr, K3, &sc.prims.sh);
     if (e != hipSuccess) {
         (void)hipFree(mem);
         return hip_fail(nullptr, e, "scene copy");
@@ -492,21 +512,34 @@ wipes_status wipes_serve_unload_scene(wipes_server* S, int32_t scene_id)
 }
 
 wipes_status wipes_serve_submit(wipes_server* S, int32_t scene_id, const wipes_camera* cam, float* out_image,
-                                uint64_t* req_id)
+                                size_t out_floats, void* stream, uint64_t* req_id)
 {
     if (!S || !cam || !out_image || !req_id) return fail(nullptr, WIPES_ERR_INVALID, "arguments must be set");
     if (cam->width < 1 || cam->height < 1 || cam->width > 32768 || cam->height > 32768 || !(cam->fx > 0.0f) ||
         !(cam->fy > 0.0f))
         return fail(nullptr, WIPES_ERR_INVALID, "bad camera");
+    const size_t need = (size_t)cam->width * (size_t)cam->height * 3;
+    if (out_floats < need)
+        return fail(nullptr, WIPES_ERR_NOMEM, "output buffer holds %zu floats, the %dx%d image needs %zu", out_floats,
+                    cam->width, cam->height, need);
     std::lock_guard<std::mutex> lk(S->mu);
     auto it = S->scenes.find(scene_id);
     if (it == S->scenes.end()) return fail(nullptr, WIPES_ERR_NOTFOUND, "unknown scene %d", scene_id);
     if ((int)S->pending.size() >= S->cfg.max_pending) return fail(nullptr, WIPES_ERR_BUSY, "queue full");
+    // the server writes `out` only after the work the caller's stream holds now
+    hipEvent_t ready = get_event(S);
+    if (!ready) return fail(nullptr, WIPES_ERR_DEVICE, "event creation failed");
+    const hipError_t e = hipEventRecord(ready, (hipStream_t)stream);
+    if (e != hipSuccess) {
+        S->ev_pool.push_back(ready);
+        return fail(nullptr, WIPES_ERR_DEVICE, "recording the caller's stream: %s", hipGetErrorString(e));
+    }
     const uint64_t id = S->next_id++;
     SReq r;
     r.scene = scene_id;
     r.cam = *cam;
     r.out = out_image;
+    r.ready = ready;
     r.t_submit = now_s();
     if (S->t_first < 0.0) S->t_first = r.t_submit;
     S->reqs[id] = r;

@@ -15,7 +15,7 @@ import torch
 
 from . import binding as B
 
-_PRIM_KEYS = ("mean", "cov", "quat", "scale", "freq", "color", "opacity", "velocity")
+_PRIM_KEYS = ("mean", "cov", "quat", "scale", "freq", "color", "opacity", "velocity", "phase", "sh")
 
 
 def _ptr(t):
@@ -182,7 +182,7 @@ class Rasterizer:
         sbuf = B.wipes_buffer(frame.screen.data_ptr(), frame.screen.numel(), 0, 0, 0)
         bbuf = B.wipes_buffer(frame.bins.data_ptr(), frame.bins.numel(), frame.cap, 1, 0)
         n_total = sum(int(im["prims"]["opacity"].shape[0]) for im in images)
-        dscreen = torch.empty((n_total, 11), dtype=torch.float32, device=self.device) if want_dscreen else None
+        dscreen = torch.empty((n_total, 12), dtype=torch.float32, device=self.device) if want_dscreen else None
         B.wipes_render_bwd(self.ctx, self.params, batch, sbuf, bbuf, _ptr(frame.T_final), _ptr(frame.last),
                            dL.data_ptr(), _ptr(dscreen), self._stream())
         return (grads, dscreen) if want_dscreen else grads

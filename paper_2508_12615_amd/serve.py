@@ -16,7 +16,7 @@ from . import binding as B
 from .binding_ext import wipes_serve_config, wipes_serve_report
 from .raster import Rasterizer, make_camera
 
-SCENE_KEYS = ("mean", "quat", "scale", "freq", "color", "opacity", "velocity")
+SCENE_KEYS = ("mean", "quat", "scale", "freq", "color", "opacity", "velocity", "phase", "sh")
 
 
 def simulate(cfg: dict, t_arrive, footprint, prep_s, blend_s):
@@ -72,15 +72,15 @@ class Server:
 
     def submit(self, sid: int, camera: dict, out: torch.Tensor) -> int:
         """Queue a render of scene `sid` from `camera` into `out`, a contiguous
-        float32 device tensor of height * width * 3 elements (checked here: the
-        library writes through the raw pointer)."""
-        W, H = int(camera["width"]), int(camera["height"])
-        if (out.dtype != torch.float32 or not out.is_cuda or not out.is_contiguous()
-                or out.numel() != W * H * 3):
-            raise ValueError("out must be a contiguous float32 CUDA tensor of %dx%dx3 elements, got %s %s"
-                             % (H, W, tuple(out.shape), out.dtype))
+        float32 device tensor of height * width * 3 elements.  The library checks
+        the element count and writes `out` only after the work already queued on
+        the current stream (e.g. a fill of `out`)."""
+        if out.dtype != torch.float32 or not out.is_cuda or not out.is_contiguous():
+            raise ValueError("out must be a contiguous float32 CUDA tensor, got %s %s" % (tuple(out.shape), out.dtype))
         rid = C.c_uint64()
-        B.check(B.lib().wipes_serve_submit(self.h, sid, C.byref(make_camera(camera)), out.data_ptr(), C.byref(rid)))
+        stream = torch.cuda.current_stream(out.device).cuda_stream
+        B.check(B.lib().wipes_serve_submit(self.h, sid, C.byref(make_camera(camera)), out.data_ptr(), out.numel(),
+                                           stream, C.byref(rid)))
         return rid.value
 
     def poll(self, rid: int):

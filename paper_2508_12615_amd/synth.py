@@ -72,14 +72,14 @@ def add_stripe_patches(img: np.ndarray, n_patches: int, seed: int) -> np.ndarray
 # 2D primitives (image fitting)
 # --------------------------------------------------------------------------
 
-def prims_2d(n: int, width: int, height: int, seed: int, cov: str = "rs") -> dict:
+def prims_2d(n: int, width: int, height: int, seed: int, cov: str = "rs", phase: bool = False) -> dict:
     """2D wavelet primitives in pixel units.
 
     Draw order: mean ~ U([0,W] x [0,H]); s1, s2 ~ logU(1, 16) px;
     theta ~ U(0, pi); |f| = 2 pi U(0, 0.5) rad/px; direction psi ~ U(0, 2 pi);
-    phase0 ~ U(0, 2 pi) (drawn, unused: the primitive has no phase term);
-    colour ~ U(0, 1)^3; opacity = 1.
-    cov="rs" returns (s1, s2, theta); cov="cholesky" returns
+    phase0 ~ U(0, 2 pi) (always drawn; returned as "phase" only when asked
+    for, since the paper's primitive has no phase term); colour ~ U(0, 1)^3;
+    opacity = 1.  cov="rs" returns (s1, s2, theta); cov="cholesky" returns
     (l11, l21, l22) = (s1, t, s2) with t ~ N(0, 2^2) drawn last.
     """
     g = rng(seed)
@@ -98,8 +98,11 @@ def prims_2d(n: int, width: int, height: int, seed: int, cov: str = "rs") -> dic
         covp = np.stack([s[:, 0], t, s[:, 1]], 1)
     else:
         raise ValueError(cov)
-    return dict(mean=mean.astype(np.float32), cov=covp.astype(np.float32), freq=freq.astype(np.float32),
-                color=color.astype(np.float32), opacity=np.ones(n, np.float32))
+    out = dict(mean=mean.astype(np.float32), cov=covp.astype(np.float32), freq=freq.astype(np.float32),
+               color=color.astype(np.float32), opacity=np.ones(n, np.float32))
+    if phase:
+        out["phase"] = _phase0.astype(np.float32)
+    return out
 
 
 # --------------------------------------------------------------------------
@@ -109,7 +112,8 @@ def prims_2d(n: int, width: int, height: int, seed: int, cov: str = "rs") -> dic
 FOCAL_1080 = 540.0 / math.tan(math.radians(25.0))   # ~1158.1 px at 1920x1080
 
 
-def scene_3d(n: int, seed: int, velocity: bool = False, n_clusters: int = 64) -> dict:
+def scene_3d(n: int, seed: int, velocity: bool = False, n_clusters: int = 64, phase: bool = False,
+             sh_degree: int = -1, covector: bool = False) -> dict:
     """3D wavelet primitives inside the unit cube.
 
     Draw order: cluster centres U(0.1, 0.9)^3, cluster std U(0.02, 0.15);
@@ -119,6 +123,11 @@ def scene_3d(n: int, seed: int, velocity: bool = False, n_clusters: int = 64) ->
     direction uniform on S^2 with |f| = 2 pi U(0, 0.5) * 2.5 / FOCAL_1080
     (world rad/unit; about 0..pi rad/px on screen at depth 2.5 under the
     literal transform); optional velocity N(0, 0.05^2 I3) per unit time.
+    Then, each only when asked for and in this order: carrier phase
+    U(0, 2 pi); spherical-harmonic coefficients [n, (deg+1)^2, 3] with the
+    constant band U(0.2, 3.5) and the others N(0, 0.15^2).  covector=True
+    scales |f| by (FOCAL_1080 / 2.5)^2 instead (the same 0..pi rad/px on
+    screen at depth 2.5 under the phase-preserving transform).
     """
     g = rng(seed)
     centres = g.uniform(0.1, 0.9, (n_clusters, 3))
@@ -137,11 +146,21 @@ def scene_3d(n: int, seed: int, velocity: bool = False, n_clusters: int = 64) ->
     d = g.standard_normal((n, 3))
     d /= np.linalg.norm(d, axis=1, keepdims=True)
     fmag = 2.0 * math.pi * g.uniform(0.0, 0.5, n) * 2.5 / FOCAL_1080
+    if covector:
+        fmag = fmag * (FOCAL_1080 / 2.5) ** 2
     freq = d * fmag[:, None]
     out = dict(mean=mean.astype(np.float32), quat=quat.astype(np.float32), scale=scale.astype(np.float32),
                freq=freq.astype(np.float32), color=color.astype(np.float32), opacity=opac.astype(np.float32))
     if velocity:
         out["velocity"] = (g.standard_normal((n, 3)) * 0.05).astype(np.float32)
+    if phase:
+        out["phase"] = g.uniform(0.0, 2.0 * math.pi, n).astype(np.float32)
+    if sh_degree >= 0:
+        K = (sh_degree + 1) ** 2
+        sh = np.empty((n, K, 3))
+        sh[:, 0, :] = g.uniform(0.2, 3.5, (n, 3))
+        sh[:, 1:, :] = g.normal(0.0, 0.15, (n, K - 1, 3))
+        out["sh"] = sh.astype(np.float32)
     return out
 
 

