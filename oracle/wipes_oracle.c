@@ -357,7 +357,7 @@ typedef struct {
  *   J   = [[fx/t_z, 0, -fx u/t_z], [0, fy/t_z, -fy v/t_z]], u, v = t_x/t_z, t_y/t_z
  *         clamped to +-guard * half-fov (reading, gsplat lineage)
  *   Sigma' = (J W) Sigma (J W)^T + eps I,   Sigma = R(q) diag(s^2) R(q)^T
- *   f'  = (J W) f     (the text: "identical ray-space transformation")
+ *   f'  = (J W) f     (f goes through the same ray-space map as Sigma)
  * Reading for alpha mode: cull if o < alpha_min, support bound
  * q <= 2 ln(o / alpha_min) (W' <= G' makes o W' < alpha_min outside it).
  */
@@ -1370,7 +1370,7 @@ void or_project_bwd(const or_params* P, const or_camera* cam, int64_t n, const d
 /* ------------------------------------------------------------------------ */
 
 /*
- * Reading of "a similar pipeline as in 3D GS" (Sec. 4.1): every primitive is
+ * Reading of the 3DGS-like pipeline of Sec. 4.1: every primitive is
  * duplicated once per screen tile its support box touches; the duplicates are
  * keyed by (tile, depth) and stably sorted, and each tile's run of the sorted
  * list is its range.  The rule, in FP32 with exactly these operations:

@@ -379,6 +379,27 @@ void worker_main(wipes_server* S)
         int64_t K = 0;
         wipes_status st = launch_batch(S, cand, cand_ready, cap, B, &K);
         lk.lock();
+        // a batch whose instances outgrew its estimate may not fit even an
+        // empty arena: the second half goes back to the head of the queue (in
+        // order) and the first half is launched again, down to one request
+        while (st == WIPES_ERR_NOMEM && B.ids.size() > 1) {
+            const size_t keep = B.ids.size() / 2;
+            for (size_t i = B.ids.size(); i-- > keep;) {
+                S->reqs[B.ids[i]].admitted = false;
+                S->pending.push_front(B.ids[i]);
+            }
+            S->slots_used -= (int)(B.ids.size() - keep);
+            S->n_admitted -= (int64_t)(B.ids.size() - keep);
+            B.ids.resize(keep);
+            cand.resize(keep);
+            ratio.resize(keep);
+            cand_scene.resize(keep);
+            cand_ready.resize(keep);
+            const int64_t cap2 = capacity_for(cand, ratio);
+            lk.unlock();
+            st = launch_batch(S, cand, cand_ready, cap2, B, &K);
+            lk.lock();
+        }
         S->launching--;
         if (st != WIPES_OK) {
             // the batch failed: its requests complete without an image; the error is kept
@@ -407,7 +428,7 @@ void worker_main(wipes_server* S)
             }
         }
         S->n_batches++;
-        S->n_batched += (int64_t)take;
+        S->n_batched += (int64_t)B.ids.size();
         S->inflight.push_back(std::move(B));
         S->cv.notify_all();
     }

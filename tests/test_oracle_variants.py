@@ -7,8 +7,8 @@ forward.
     undergo the same ray-space transformation", Sec. 4.1 after Eq. 7);
   * per-primitive carrier phase phi0 (Eq. 6 carries none; phi0 = 0 is the
     paper's primitive);
-  * spherical-harmonic colour of degree <= 3 (Sec. 3.1: colour "encoded by
-    spherical harmonic coefficients").
+  * spherical-harmonic colour of degree <= 3 (Sec. 3.1: 3DGS keeps colour as
+    spherical-harmonic coefficients).
 """
 import math
 
