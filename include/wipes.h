@@ -282,6 +282,37 @@ wipes_status wipes_bins_view(const wipes_params* p, const wipes_batch* batch, co
                              const wipes_buffer* bins, const uint32_t** keys, const uint32_t** vals,
                              const uint32_t** ranges, int64_t* n_tiles);
 
+/* ------------------------------------------------ allocation-free form */
+
+/* Size of the static device workspace of wipes_render_fwd_noalloc. */
+#define WIPES_NOALLOC_WORKSPACE_BYTES ((size_t)128 << 20)
+
+/* For callers that cannot allocate device memory -- code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc: one forward
+ * frame, i.e. wipes_project + wipes_bin_sort + wipes_render_fwd with the same
+ * kernels and the same outputs, whose screen and bins workspaces are carved
+ * from a static device array of WIPES_NOALLOC_WORKSPACE_BYTES (the screen
+ * part first, then bins of the largest instance capacity that fits).  Each
+ * device the library runs on holds its own array until the process ends.
+ * The call allocates nothing: no hipMalloc, hipFree, event creation or other
+ * allocating routine, on any path.
+ *   image, T_final, last: the caller's device arrays, as wipes_render_fwd.
+ *   n_instances_out != NULL: the stream is synchronised once to read the
+ *     instance count K (as wipes_bin_sort does); if K exceeds the capacity
+ *     that fits, nothing is rendered and WIPES_ERR_CAPACITY is returned with
+ *     *n_instances_out = K.  NULL: no host synchronisation; a frame that
+ *     overflows leaves image, T_final and last unwritten.
+ * Errors: WIPES_ERR_INVALID as wipes_render_fwd; WIPES_ERR_CAPACITY, before
+ * any work is queued, when the batch's projection workspace (about 200 bytes
+ * per primitive) leaves no room for bins; wipes_last_error names the sizes.
+ * Every call on a device uses that device's one array and leaves its
+ * contents behind (nothing needs to start zeroed: the stages clear what they
+ * use): calls that overlap on one device -- from two host threads, or on two
+ * streams not ordered with each other -- race and give wrong images.
+ * Asynchronous on the stream unless n_instances_out is set. */
+wipes_status wipes_render_fwd_noalloc(wipes_ctx* ctx, const wipes_params* p, const wipes_batch* batch, float* image,
+                                      float* T_final, int32_t* last, int64_t* n_instances_out, void* stream);
+
 /* ------------------------------------------------------- fitting, graphs */
 
 /* Gradient of the L2 fitting loss L = sum over images of the mean over that

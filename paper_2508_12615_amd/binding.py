@@ -95,6 +95,7 @@ def lib() -> C.CDLL:
                                       PP(C.c_void_p), PP(C.c_void_p), PP(C.c_void_p), PP(C.c_int64)]),
     }
     sig.update({
+        "wipes_render_fwd_noalloc": (C.c_int, [P, PP(wipes_params), PP(wipes_batch), P, P, P, PP(C.c_int64), P]),
         "wipes_stage_name": (C.c_char_p, [C.c_int32]),
         "wipes_probe_issue_rate": (C.c_int, [P, C.c_int32, PP(C.c_double), P]),
         "wipes_profile_enable": (C.c_int, [P, C.c_int32]),
@@ -175,6 +176,17 @@ def wipes_render_bwd(ctx, params, batch, screen, bins, T_final: int, last: int, 
                      stream: int = 0) -> None:
     check(lib().wipes_render_bwd(ctx, C.byref(params), C.byref(batch), C.byref(screen), C.byref(bins), T_final,
                                  last, dL_dimage, dscreen, stream), ctx)
+
+
+def wipes_render_fwd_noalloc(ctx, params, batch, image: int, T_final: int, last: int, stream: int = 0,
+                             sync: bool = True):
+    """Returns (status, K): status is WIPES_OK or WIPES_ERR_CAPACITY (K = required instances; -1 when
+    sync is False, i.e. no host synchronisation)."""
+    k = C.c_int64(-1)
+    st = lib().wipes_render_fwd_noalloc(ctx, C.byref(params), C.byref(batch), image, T_final, last,
+                                        C.byref(k) if sync else None, stream)
+    check(st, ctx, allow=(WIPES_ERR_CAPACITY,))
+    return st, k.value
 
 
 def wipes_check_overflow(ctx, params, batch, screen, stream: int = 0):

@@ -413,6 +413,16 @@ StageScope::~StageScope()
 
 }  // namespace wipes
 
+// --------------------------------------------------------------- static workspace
+
+// Device workspace of wipes_render_fwd_noalloc, for callers that cannot
+// allocate: every device the library runs on holds its own copy until the
+// process ends.  In host code `scratch` names a host-side stand-in, not the
+// device array: host code only ever uses the device address that
+// hipGetSymbolAddress gives for the current device at context creation
+// (wipes_ctx::scratch).
+static __device__ __align__(256) unsigned char scratch[WIPES_NOALLOC_WORKSPACE_BYTES];
+
 // --------------------------------------------------------------- C ABI
 
 extern "C" {
@@ -463,6 +473,13 @@ wipes_status wipes_ctx_create(int32_t device, wipes_ctx** out)
     if (e != hipSuccess) {
         wipes_ctx_destroy(c);
         return hip_fail(nullptr, e, "instance-count readback allocation");
+    }
+    // this device's copy of the static workspace (the device is current)
+    e = hipGetSymbolAddress((void**)&c->scratch, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) {
+        c->scratch = nullptr;
+        wipes_ctx_destroy(c);
+        return hip_fail(nullptr, e, "static workspace address");
     }
     for (int i = 0; i < kRing; ++i) {
         e = hipHostMalloc(&c->ring[i].host, kStagingBytes, hipHostMallocDefault);
@@ -613,6 +630,46 @@ wipes_status wipes_render_bwd(wipes_ctx* ctx, const wipes_params* p, const wipes
     hipStream_t s = (hipStream_t)stream;
     if ((st = upload_descs(ctx, p, b, L, screen->base, s, true, true)) != WIPES_OK) return st;
     return render_bwd_core(ctx, p, b, L, screen->base, bins->base, T_final, last, dL_dimage, dscreen, s);
+}
+
+wipes_status wipes_render_fwd_noalloc(wipes_ctx* ctx, const wipes_params* p, const wipes_batch* b, float* image,
+                                      float* T_final, int32_t* last, int64_t* n_instances_out, void* stream)
+{
+    if (!ctx) return fail(nullptr, WIPES_ERR_INVALID, "ctx must not be NULL");
+    wipes_status st = validate(ctx, p, b, false);
+    if (st != WIPES_OK) return st;
+    if (!image) return fail(ctx, WIPES_ERR_INVALID, "image must not be NULL");
+    if (p->mode == WIPES_3D_ALPHA && (!T_final || !last))
+        return fail(ctx, WIPES_ERR_INVALID, "alpha mode needs T_final and last");
+    if (!ctx->scratch) return fail(ctx, WIPES_ERR_DEVICE, "static workspace unavailable on this device");
+    // the screen workspace first, the bins after it with the largest
+    // instance capacity that fits (host arithmetic only)
+    const size_t total = (size_t)WIPES_NOALLOC_WORKSPACE_BYTES;
+    const size_t sbytes = align_up(layout_of(p, b, 0, 0).screen_bytes, 256);
+    const size_t bmin = layout_of(p, b, 1, 0).bins_bytes;
+    if (sbytes > total || total - sbytes < bmin)
+        return fail(ctx, WIPES_ERR_CAPACITY,
+                    "batch needs %zu bytes of projection workspace plus %zu of bins; the static workspace holds %zu",
+                    sbytes, bmin, total);
+    const size_t rest = total - sbytes;
+    int64_t lo = 1, hi = std::min<int64_t>((int64_t)(rest / 16) + 1, (1ll << 31) - 1);   // bins > 16 B/instance
+    while (lo < hi) {   // largest capacity whose bins fit in `rest`
+        const int64_t mid = lo + (hi - lo + 1) / 2;
+        if (layout_of(p, b, mid, 0).bins_bytes <= rest) lo = mid; else hi = mid - 1;
+    }
+    wipes_buffer screen{ctx->scratch, sbytes, 0, 0, 0};
+    wipes_buffer bins{ctx->scratch + sbytes, rest, lo, 0, 0};
+    // no profiling events here: creating one may allocate
+    const bool prof = ctx->prof.on;
+    ctx->prof.on = false;
+    st = wipes_project(ctx, p, b, &screen, stream);
+    if (st == WIPES_OK) st = wipes_bin_sort(ctx, p, b, &screen, &bins, n_instances_out, stream);
+    if (st == WIPES_ERR_CAPACITY)
+        (void)fail(ctx, st, "frame needs %lld instances; the static workspace holds %lld for this batch",
+                   n_instances_out ? (long long)*n_instances_out : -1ll, (long long)lo);
+    if (st == WIPES_OK) st = wipes_render_fwd(ctx, p, b, &screen, &bins, image, T_final, last, stream);
+    ctx->prof.on = prof;
+    return st;
 }
 
 wipes_status wipes_check_overflow(wipes_ctx* ctx, const wipes_params* p, const wipes_batch* b,

@@ -70,6 +70,7 @@ struct wipes_ctx {
     wipes::DescArgs desc_pend_args;
     std::vector<wipes::ImgDesc> desc_tmp;    // reused for each new table (no per-call reallocation)
     Profiler prof;
+    unsigned char* scratch = nullptr;        // this device's copy of the static workspace (device address)
 };
 
 namespace wipes {
