@@ -3,8 +3,8 @@ the oracle itself: closed forms, scipy's spherical harmonics, quadrature,
 reductions to the base primitive, and central finite differences of the FP64
 forward.
 
-  * covector frequency transform (the phase-preserving reading of "Sigma and f
-    undergo the same ray-space transformation", Sec. 4.1 after Eq. 7);
+  * covector frequency transform (the phase-preserving reading of Sec. 4.1
+    after Eq. 7, where f goes through the same ray-space map as Sigma);
   * per-primitive carrier phase phi0 (Eq. 6 carries none; phi0 = 0 is the
     paper's primitive);
   * spherical-harmonic colour of degree <= 3 (Sec. 3.1: 3DGS keeps colour as
