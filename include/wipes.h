@@ -10,7 +10,7 @@
  *   - blending:    additive weighted sum (2D images)                      Sec. 3.2, Eq. 4
  *                  front-to-back alpha compositing (3D scenes)           Sec. 3.1, Eq. 3
  *   - rasterizer:  tile binning + depth-keyed sort + per-tile blending,
- *                  "a similar pipeline as in 3D GS"                        Sec. 4.1
+ *                  as in 3D Gaussian splatting                             Sec. 4.1
  *   - backward:    explicit gradients for every parameter                 Sec. 1 (contributions)
  *
  * Conventions for every call:
@@ -312,6 +312,56 @@ wipes_status wipes_bins_view(const wipes_params* p, const wipes_batch* batch, co
  * Asynchronous on the stream unless n_instances_out is set. */
 wipes_status wipes_render_fwd_noalloc(wipes_ctx* ctx, const wipes_params* p, const wipes_batch* batch, float* image,
                                       float* T_final, int32_t* last, int64_t* n_instances_out, void* stream);
+
+/* ---------------------------------------------------- deformation network */
+
+/* The network F of Sec. 4.3, Eq. 8, that maps the positional encodings of a
+ * primitive's position and of the time to offsets of its position, frequency
+ * and covariance, in the D-3DGS configuration the paper keeps for its other
+ * settings (Sec. 3.2, Sec. 5.3):
+ *   e = (gamma(x), gamma(t)), gamma(p) = (p, sin(2^k pi p), cos(2^k pi p) for
+ *   k < L), the components of p kept together inside each block; L = 10 for
+ *   the position, 6 for the time: 63 + 13 = 76 inputs;
+ *   8 ReLU layers of 256 units; e joins the fifth layer's output (the sixth
+ *   layer reads 256 + 76 inputs); a linear output layer of 13 values
+ *   (dx[3], df[3], dq[4], ds[3]): the offsets added to mean, freq, quat (before
+ *   normalisation) and the linear scales of a 3D primitive.
+ * Parameters: one flat FP32 device array, per layer W [out][in] row-major
+ * then b [out]: W0 [256][76], b0, W1..W4 [256][256], b1..b4, W5 [256][332],
+ * b5, W6, W7 [256][256], b6, b7, Wo [13][256], bo -- wipes_deform_param_count()
+ * values (503053).
+ *
+ * The products run on the matrix cores.  WIPES_DEFORM_BF16X3 splits every
+ * operand into two bf16 parts and keeps three of the four partial products
+ * (FP32 accumulation; about 2^-16 relative per product, FP32-class);
+ * WIPES_DEFORM_BF16 keeps the leading one (about 2^-8 relative). */
+enum { WIPES_DEFORM_BF16X3 = 0, WIPES_DEFORM_BF16 = 1 };
+
+/* Number of FP32 values in the flat parameter array. */
+int64_t wipes_deform_param_count(void);
+
+/* Device workspace bytes for n primitives; with_backward != 0 adds the stored
+ * layer inputs and the backward's scratch (about 17 KB per primitive). */
+wipes_status wipes_deform_workspace_size(int64_t n, int32_t with_backward, size_t* bytes);
+
+/* offsets[n][13] = F(e(mean[i], time)) for mean[n][3] (device, FP32).  The
+ * workspace (device, caller-owned, >= wipes_deform_workspace_size(n,
+ * keep_for_backward)) receives the split weights and, when keep_for_backward
+ * != 0, the layer inputs wipes_deform_bwd reads; it must then be left as is
+ * until that call.  Asynchronous on `stream`.  INVALID for a bad precision,
+ * n < 0 or missing pointers; NOMEM when workspace_bytes is too small. */
+wipes_status wipes_deform_fwd(wipes_ctx* ctx, int32_t precision, const float* params, int64_t n, const float* mean,
+                              float time, float* offsets, void* workspace, size_t workspace_bytes,
+                              int32_t keep_for_backward, void* stream);
+
+/* Gradients for the upstream d_offsets[n][13]: d_params (overwritten, laid
+ * out like params) and d_mean[n][3] (overwritten; the encoding's derivative).
+ * Needs the workspace of a wipes_deform_fwd call with keep_for_backward != 0
+ * on the same params, mean, time and precision.  Deterministic: the row sums
+ * are taken in a fixed order.  Asynchronous on `stream`; errors as above. */
+wipes_status wipes_deform_bwd(wipes_ctx* ctx, int32_t precision, const float* params, int64_t n, const float* mean,
+                              float time, const float* d_offsets, void* workspace, size_t workspace_bytes,
+                              float* d_params, float* d_mean, void* stream);
 
 /* ------------------------------------------------------- fitting, graphs */
 

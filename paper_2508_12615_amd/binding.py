@@ -98,6 +98,10 @@ def lib() -> C.CDLL:
         "wipes_render_fwd_noalloc": (C.c_int, [P, PP(wipes_params), PP(wipes_batch), P, P, P, PP(C.c_int64), P]),
         "wipes_stage_name": (C.c_char_p, [C.c_int32]),
         "wipes_probe_issue_rate": (C.c_int, [P, C.c_int32, PP(C.c_double), P]),
+        "wipes_deform_param_count": (C.c_int64, []),
+        "wipes_deform_workspace_size": (C.c_int, [C.c_int64, C.c_int32, PP(C.c_size_t)]),
+        "wipes_deform_fwd": (C.c_int, [P, C.c_int32, P, C.c_int64, P, C.c_float, P, P, C.c_size_t, C.c_int32, P]),
+        "wipes_deform_bwd": (C.c_int, [P, C.c_int32, P, C.c_int64, P, C.c_float, P, P, C.c_size_t, P, P, P]),
         "wipes_profile_enable": (C.c_int, [P, C.c_int32]),
         "wipes_profile_read": (C.c_int, [P, PP(C.c_double), PP(C.c_int64), C.c_int32]),
         "wipes_render_stats": (C.c_int, [P, PP(wipes_params), PP(wipes_batch), PP(wipes_buffer), PP(wipes_buffer),
@@ -230,6 +234,31 @@ def wipes_probe_issue_rate(ctx, op: str, stream: int = 0) -> float:
     r = C.c_double()
     check(lib().wipes_probe_issue_rate(ctx, PROBE_OPS.index(op), C.byref(r), stream), ctx)
     return r.value
+
+
+WIPES_DEFORM_BF16X3, WIPES_DEFORM_BF16 = 0, 1
+
+
+def wipes_deform_param_count() -> int:
+    return int(lib().wipes_deform_param_count())
+
+
+def wipes_deform_workspace_size(n: int, with_backward: bool) -> int:
+    b = C.c_size_t()
+    check(lib().wipes_deform_workspace_size(n, int(with_backward), C.byref(b)))
+    return b.value
+
+
+def wipes_deform_fwd(ctx, precision: int, params: int, n: int, mean: int, time: float, offsets: int,
+                     workspace: int, workspace_bytes: int, keep_for_backward: bool, stream: int = 0) -> None:
+    check(lib().wipes_deform_fwd(ctx, precision, params, n, mean, time, offsets, workspace, workspace_bytes,
+                                 int(keep_for_backward), stream), ctx)
+
+
+def wipes_deform_bwd(ctx, precision: int, params: int, n: int, mean: int, time: float, d_offsets: int,
+                     workspace: int, workspace_bytes: int, d_params: int, d_mean: int, stream: int = 0) -> None:
+    check(lib().wipes_deform_bwd(ctx, precision, params, n, mean, time, d_offsets, workspace, workspace_bytes,
+                                 d_params, d_mean, stream), ctx)
 
 
 def wipes_render_stats(ctx, params, batch, screen, bins, T_final: int, last: int, stream: int = 0):

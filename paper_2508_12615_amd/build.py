@@ -19,7 +19,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libwipes.so")
 OBJDIR = os.path.join(HERE, "_build")
 SOURCES = ["api.hip", "pipeline.hip", "project.hip", "binning.hip", "sort.hip", "blend.hip", "project_bwd.hip",
-           "graph.hip", "autotune.hip", "serve.hip", "adam.hip", "probe.hip"]
+           "graph.hip", "autotune.hip", "serve.hip", "adam.hip", "probe.hip", "deform.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-ffp-contract=off",

@@ -164,6 +164,20 @@ def scene_3d(n: int, seed: int, velocity: bool = False, n_clusters: int = 64, ph
     return out
 
 
+def deform_params(shapes, seed: int, head: float = 0.05) -> np.ndarray:
+    """Random weights of a fully connected network, flat FP32: for each layer
+    (out, in) in `shapes`, W [out, in] row-major then b [out], both
+    U(-1/sqrt(in), 1/sqrt(in)) (the usual default initialisation of a linear
+    layer), the last layer's scaled by `head` (small initial offsets)."""
+    g = rng(seed)
+    parts = []
+    for l, (m, k) in enumerate(shapes):
+        s = 1.0 / math.sqrt(k) * (head if l == len(shapes) - 1 else 1.0)
+        parts.append(g.uniform(-s, s, m * k))
+        parts.append(g.uniform(-s, s, m))
+    return np.concatenate(parts).astype(np.float32)
+
+
 def look_at(eye, target, up=(0.0, 0.0, 1.0)) -> np.ndarray:
     """World->camera 4x4 matrix with OpenCV axes (x right, y down, z forward)."""
     eye = np.asarray(eye, np.float64)
