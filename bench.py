@@ -60,8 +60,8 @@ def parse():
     ap.add_argument("--persistent", type=int, default=2,
                     help="blend launch form: 0 grid, 1 persistent tile queue, 2 queue with longest lists first")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--extras", type=str, default="plain2d,batched,fit,serve",
-                    help="comma list of secondary workloads (plain2d, batched, fit, serve) or none")
+    ap.add_argument("--extras", type=str, default="plain2d,batched,fit,serve,deform",
+                    help="comma list of secondary workloads (plain2d, batched, fit, serve, deform) or none")
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-warmup", type=int, default=200)
     ap.add_argument("--fit-steps", type=int, default=1000)
@@ -295,6 +295,55 @@ def bench_fit(steps, log):
                 graph=dict(steps_per_s=steps / graph["seconds"], ms_per_step=graph["seconds"] * 1e3 / steps,
                            psnr_db=graph["psnr"], loss=[(i, round(v, 6)) for i, v in graph["history"]],
                            recaptures=graph["recaptures"]))
+
+
+# multiply-adds per primitive of the deformation network (Eq. 8): 76 -> 256, four 256 -> 256, 332 -> 256,
+# two 256 -> 256, 256 -> 13; the backward does twice as many (input and weight gradients)
+DEFORM_MACS = 76 * 256 + 6 * 256 * 256 + 332 * 256 + 256 * 13
+MFMA_BF16_PEAK = 2.5e15
+
+
+def bench_deform(log, n=1_000_000, reps=10):
+    """Eq. 8 deformation network over the 3D scene's primitives at one time: forward alone, and
+    forward (keeping the layer inputs) + backward, in both precisions; matrix-core roofline."""
+    import torch
+    from paper_2508_12615_amd import binding as B
+    from paper_2508_12615_amd import synth
+    from paper_2508_12615_amd.deform import Deformation
+    dev = torch.device("cuda", 0)
+    shapes = [(256, 76)] + [(256, 256)] * 4 + [(256, 332)] + [(256, 256)] * 2 + [(13, 256)]
+    params = torch.from_numpy(synth.deform_params(shapes, 2024)).to(dev)
+    mean = torch.from_numpy(synth.scene_3d(n, 2025)["mean"]).to(dev)
+    dout = torch.randn((n, 13), device=dev)
+    res = {}
+    for prec, name, products in ((B.WIPES_DEFORM_BF16X3, "bf16x3", 3), (B.WIPES_DEFORM_BF16, "bf16", 1)):
+        net = Deformation(device=dev, precision=prec)
+        ws = net.new_workspace(n)
+        for keep in (False, True):
+            def step():
+                net.forward(params, mean, 0.625, keep_for_backward=keep, workspace=ws)
+                if keep:
+                    net.backward(params, mean, 0.625, dout, workspace=ws)
+            step()
+            torch.cuda.synchronize()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            for _ in range(reps):
+                step()
+            b.record()
+            b.synchronize()
+            ms = a.elapsed_time(b) / reps
+            flops = 2.0 * DEFORM_MACS * n * (3 if keep else 1)
+            key = "%s_%s" % (name, "fwd_bwd" if keep else "fwd")
+            res[key] = dict(ms=ms, prims_per_s=n / (ms * 1e-3), alg_tflops=flops / (ms * 1e-3) / 1e12,
+                            mfma_frac=products * flops / (ms * 1e-3) / MFMA_BF16_PEAK)
+            log("deform %s: %.3f ms, %.1f TFLOP/s algorithmic, %.3f of the bf16 MFMA peak"
+                % (key, ms, res[key]["alg_tflops"], res[key]["mfma_frac"]))
+        net.close()
+        del ws
+    torch.cuda.empty_cache()
+    return dict(workload="Eq. 8 deformation network, %d primitives, one time" % n,
+                macs_per_primitive=DEFORM_MACS, mfma_peak_tflops=MFMA_BF16_PEAK / 1e12, **res)
 
 
 def bench_serving(n_req, n_warm, log, budget=3 << 29):
@@ -588,6 +637,8 @@ def main():
         out["fit_loop"] = bench_fit(a.fit_steps, log)
     if "serve" in extras:
         out["serving"] = bench_serving(a.serve_requests, a.serve_warmup, log)
+    if "deform" in extras:
+        out["deform"] = bench_deform(log)
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(log)
     print(json.dumps(out), flush=True)

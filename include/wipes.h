@@ -100,7 +100,8 @@ typedef struct {
     int32_t sh_degree;    /* -1 (default): colour is the direct RGB input; 0..3 (3D only): colour is the
                              real spherical-harmonic expansion of degree sh_degree (Sec. 3.1) at the
                              unit direction from the camera centre to the mean, no offset, no clamp */
-    int32_t lds_batch;    /* list positions a wave stages into LDS per batch: 64 or 128 (0 = 64) */
+    int32_t lds_batch;    /* list positions a wave stages into LDS per batch: 64 (0 = 64); fixed at
+                           * one 64-bit contribution-mask word, one position per lane */
 } wipes_params;
 
 /* Pinhole camera.  viewmat is world->camera, row-major 4x4, OpenCV axes
@@ -229,8 +230,11 @@ wipes_status wipes_workspace_size(const wipes_params* p, const wipes_batch* batc
 wipes_status wipes_project(wipes_ctx* ctx, const wipes_params* p, const wipes_batch* batch, wipes_buffer* screen,
                            void* stream);
 
-/* Tile binning and sort: pixel boxes, per-primitive tile counts, instance
- * emission, stable sort by (tile, depth key, index), per-tile ranges.
+/* Tile binning and sort (Sec. 4.1: the tile pipeline of 3D Gaussian
+ * splatting with W' in place of the projected Gaussian; Sec. 1: primitives
+ * sorted with a GPU sort, depth-ordered per tile for Eq. 3): pixel boxes,
+ * per-primitive tile counts, instance emission, stable sort by (tile, depth
+ * key, index), per-tile ranges.
  * n_instances_out != NULL: the call synchronises the stream once to read the
  * instance count K into *n_instances_out, and returns WIPES_ERR_CAPACITY
  * (with *n_instances_out = K) if K exceeds the bins buffer's capacity.
@@ -258,7 +262,9 @@ wipes_status wipes_render_fwd(wipes_ctx* ctx, const wipes_params* p, const wipes
                               const wipes_buffer* screen, const wipes_buffer* bins, float* image, float* T_final,
                               int32_t* last, void* stream);
 
-/* Backward pass: dL/dimage (device [sum W H, 3]) -> parameter gradients
+/* Backward pass (Sec. 1: explicit gradients of Eq. 3 / Eq. 4 with W' of
+ * Eq. 6-7 for every primitive parameter, in place of automatic
+ * differentiation): dL/dimage (device [sum W H, 3]) -> parameter gradients
  * written to each image's grads.  Alpha mode walks each pixel's list back
  * to front from `last`, recovering transmittance by dividing by (1 - alpha)
  * (nothing per pair is stored by the forward).  dscreen (optional, device
@@ -443,6 +449,11 @@ wipes_status wipes_autotune(wipes_ctx* ctx, const wipes_params* p, const wipes_b
                             int32_t reps, wipes_params* best, double* times_ms, void* stream);
 
 /* --------------------------------------------------------------- serving */
+
+/* Rendering of resident 3D scenes on request: each request is one novel view
+ * of a scene (Sec. 3.1 projection and Eq. 3 compositing with W', Sec. 4.1),
+ * optionally at a time t for the scenes with a linear-in-time mean (the
+ * dynamic setting of Sec. 4.3 with its deformation reduced to a velocity). */
 
 typedef struct wipes_server wipes_server;
 

@@ -86,8 +86,8 @@ wipes_status validate(wipes_ctx* ctx, const wipes_params* p, const wipes_batch* 
     if (p->sh_degree < -1 || p->sh_degree > 3) return fail(ctx, WIPES_ERR_INVALID, "sh_degree must be -1..3");
     if (p->sh_degree >= 0 && p->mode != WIPES_3D_ALPHA)
         return fail(ctx, WIPES_ERR_INVALID, "spherical-harmonic colour needs 3D mode");
-    if (p->lds_batch != 0 && p->lds_batch != 64 && p->lds_batch != 128)
-        return fail(ctx, WIPES_ERR_INVALID, "lds_batch must be 0, 64 or 128");
+    if (p->lds_batch != 0 && p->lds_batch != 64)
+        return fail(ctx, WIPES_ERR_INVALID, "lds_batch must be 0 or 64 (the blend stages one 64-position word)");
     if (!tile_ok(p->tile_w, p->tile_h)) return fail(ctx, WIPES_ERR_INVALID, "unsupported tile %dx%d", p->tile_w, p->tile_h);
     if (!(p->alpha_min > 0.0f) || !(p->alpha_max > p->alpha_min) || !(p->alpha_max < 1.0f) || !(p->T_min > 0.0f) ||
         !(p->q_add > 0.0f) || !(p->blur_eps >= 0.0f) || !(p->near_plane > 0.0f) || !(p->fov_guard > 0.0f))

@@ -89,7 +89,7 @@ def test_validation_rejects_bad_arguments(B, bad):
     elif bad == "sh_2d":
         p.sh_degree = 0
     elif bad == "lds_batch":
-        p.lds_batch = 96
+        p.lds_batch = 128
     sb, bb = C.c_size_t(), C.c_size_t()
     st = B.lib().wipes_workspace_size(C.byref(p), C.byref(b), 100, 0, C.byref(sb), C.byref(bb))
     assert st == B.WIPES_ERR_INVALID
