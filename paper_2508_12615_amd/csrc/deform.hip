@@ -11,17 +11,24 @@
 // and the split residuals are below 2^-16 relative).  WIPES_DEFORM_BF16 keeps
 // hi*hi only (three times fewer matrix instructions, ~2^-8 relative).
 //
-// Forward kernel: one workgroup (4 waves) per 32 primitives.  The 32 rows of
-// activations live in LDS as bf16 hi/lo pairs, one row = [256 hidden | 76
-// encoding | 4 zero], so the first layer reads the encoding block and the
-// skip layer reads hidden + encoding in one contiguous K range.  Each wave
-// computes 64 of the 256 output columns (two 32x32 tiles of
-// v_mfma_f32_32x32x16_bf16), streaming its weight fragments from the
-// pre-split weight copy (L2-resident: every workgroup reads the same 2 MB).
-// Bias, ReLU and the hi/lo split happen in the epilogue, written back into
-// the same LDS rows after a barrier.  For the backward the kernel can store
-// every layer input per tile, column-major over the 32 rows (the layout the
-// weight-gradient products read as contiguous K runs).
+// Row kernels (forward, and the backward through the layers): one workgroup
+// of 4 waves per block of 128 primitives, one workgroup per CU (the block's
+// activations fill 132 KB of LDS: 128 rows x 256 hidden units as bf16 hi/lo
+// pairs).  Each wave computes 64 output units for all 128 rows -- 8 tiles of
+// v_mfma_f32_32x32x16_bf16 -- so every weight fragment it streams from L2
+// feeds four row tiles and every activation fragment it reads from LDS feeds
+// two unit tiles.  The encoding (76 values per row) is not kept in LDS: the
+// first and the sixth layer compute their encoding fragments in registers
+// (exact range reduction, hardware sine and cosine in revolutions).  Bias,
+// ReLU and the hi/lo split happen in the epilogue, written back into the same
+// LDS rows after a barrier.
+//
+// For the backward the forward stores every layer input per block, column
+// major over groups of 32 rows (each lane holds four consecutive rows of one
+// unit after the matrix product: one 8-byte store per plane), the layout in
+// which the weight-gradient products read their K runs (the rows) as
+// contiguous 32-row steps.  The weight copies are stored in matrix-core
+// fragment order, so a wave's operand fragment is one contiguous kilobyte.
 #include <hip/hip_runtime.h>
 
 #include "api_internal.hpp"
@@ -37,30 +44,31 @@ constexpr int kDepth = 8;
 constexpr int kSkip = 5;
 constexpr int kOut = 13;
 constexpr int kOutPad = 32;
-constexpr int kRows = 32;                  // primitives per workgroup
-constexpr int kRowLen = kW + kInPad;       // 336: [hidden | encoding | zero]
-constexpr int kRowStride = kRowLen + 8;    // LDS row stride (bf16 elements)
-constexpr int kSaveCols = kInPad + kDepth * kW;   // layer inputs stored per tile: e and h1..h8
+constexpr int kRB = 128;                          // primitives per block (workgroup of the row kernels)
+constexpr int kAS = kW + 8;                       // LDS row stride of the activations (bf16 elements)
+constexpr int kSaveCols = kInPad + kDepth * kW;   // stored layer inputs per row: e, then h_1..h_8
+constexpr int kZS = 32 + 8;                       // LDS row stride of the weight-gradient stage
+constexpr int kES = 16 + 8;                       // LDS row stride of the forward's encoding stage
 }  // namespace dmlp
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
-// Layer l: K range [k0, k0 + klen) of an activation row, output columns n.
+// Layer l of the split weight copy: K length (padded inputs) and output units (padded).
 struct DLayer {
-    int k0, klen, n;
+    int klen, n;
 };
 
 __host__ __device__ constexpr DLayer dlayer(int l)
 {
     using namespace dmlp;
-    return l == 0 ? DLayer{kW, kInPad, kW}
-                  : l == kSkip ? DLayer{0, kRowLen, kW} : l == kDepth ? DLayer{0, kW, kOutPad} : DLayer{0, kW, kW};
+    return l == 0 ? DLayer{kInPad, kW}
+                  : l == kSkip ? DLayer{kW + kInPad, kW} : l == kDepth ? DLayer{kW, kOutPad} : DLayer{kW, kW};
 }
 
-// Offsets (elements) of layer l's weights [n][klen] and bias in the split
-// weight copy; the caller's FP32 parameters are [out][in] row-major per layer
-// (W0 [256, 76], b0, ..., W5 [256, 332], b5, ..., Wo [13, 256], bo).
+// Offsets (elements) of layer l's weights [n][klen] in the split weight copy;
+// the caller's FP32 parameters are [out][in] row-major per layer (W0 [256,
+// 76], b0, ..., W5 [256, 332], b5, ..., Wo [13, 256], bo).
 __host__ __device__ inline size_t dw_off(int l)
 {
     size_t o = 0;
@@ -68,220 +76,6 @@ __host__ __device__ inline size_t dw_off(int l)
     return o;
 }
 __host__ __device__ inline size_t dw_total() { return dw_off(dmlp::kDepth + 1); }
-
-__device__ __forceinline__ void split_bf16(float x, __bf16& hi, __bf16& lo)
-{
-    hi = (__bf16)x;
-    lo = (__bf16)(x - (float)hi);
-}
-
-// Pre-split copy of the weights: hi/lo bf16 arrays [n][klen] per layer, K
-// padded with zeros (layer 0: 76 -> 80 in the encoding block; the skip layer:
-// hidden 256 then encoding 76 then 4 zeros) and the output layer's rows
-// padded 13 -> 32.  Source index of (layer, row r, padded column c).
-__global__ void __launch_bounds__(256) k_deform_split(const float* __restrict__ params, __bf16* __restrict__ whi,
-                                                      __bf16* __restrict__ wlo, float* __restrict__ bias)
-{
-    using namespace dmlp;
-    const size_t i = (size_t)blockIdx.x * 256u + threadIdx.x;
-    const size_t total = dw_total();
-    // source offsets of each layer in the caller's flat array
-    if (i < total) {
-        int l = 0;
-        while (l < kDepth && i >= dw_off(l + 1)) ++l;
-        const DLayer L = dlayer(l);
-        const size_t j = i - dw_off(l);
-        const int r = (int)(j / (size_t)L.klen), c = (int)(j % (size_t)L.klen);
-        size_t src = 0;
-        int fan_in = 0, nout = 0;
-        for (int q = 0; q <= l; ++q) {
-            fan_in = q == 0 ? kIn : q == kSkip ? kW + kIn : kW;
-            nout = q == kDepth ? kOut : kW;
-            if (q < l) src += (size_t)nout * fan_in + nout;
-        }
-        int sc = -1;   // source column
-        if (l == 0) sc = c < kIn ? c : -1;
-        else if (l == kSkip) sc = c < kW + kIn ? c : -1;
-        else sc = c;
-        const float v = (r < nout && sc >= 0) ? params[src + (size_t)r * fan_in + sc] : 0.0f;
-        split_bf16(v, whi[i], wlo[i]);
-    }
-    // biases: [layer][256] (the output layer's 13 then zeros)
-    if (i < (size_t)(kDepth + 1) * kW) {
-        const int l = (int)(i / kW), r = (int)(i % kW);
-        size_t src = 0;
-        for (int q = 0; q < l; ++q) {
-            const int fi = q == 0 ? kIn : q == kSkip ? kW + kIn : kW;
-            const int no = q == kDepth ? kOut : kW;
-            src += (size_t)no * fi + no;
-        }
-        const int fi = l == 0 ? kIn : l == kSkip ? kW + kIn : kW;
-        const int no = l == kDepth ? kOut : kW;
-        bias[i] = r < no ? params[src + (size_t)no * fi + r] : 0.0f;
-    }
-}
-
-// Encoding entry j (0..75) of position x and time t, FP32 with exact range
-// reduction: sin(2^k pi p) = sin(2 pi r), r = fract(2^(k-1) p), and the power
-// of two scaling is exact.
-__device__ __forceinline__ float encode_entry(int j, const float x[3], float t)
-{
-    using namespace dmlp;
-    float p;
-    int k, kind;   // kind 0: the value itself, 1: sin, 2: cos
-    if (j < 3 * (1 + 2 * kLX)) {
-        const int blk = j / 3;
-        p = x[j % 3];
-        kind = blk == 0 ? 0 : ((blk - 1) & 1) + 1;
-        k = blk == 0 ? 0 : (blk - 1) >> 1;
-    } else {
-        const int blk = j - 3 * (1 + 2 * kLX);
-        p = t;
-        kind = blk == 0 ? 0 : ((blk - 1) & 1) + 1;
-        k = blk == 0 ? 0 : (blk - 1) >> 1;
-    }
-    if (kind == 0) return p;
-    const float r = __builtin_amdgcn_fractf(ldexpf(p, k - 1));
-    return kind == 1 ? __builtin_amdgcn_sinf(r) : __builtin_amdgcn_cosf(r);
-}
-
-template <bool SPLIT>
-__global__ void __launch_bounds__(256) k_deform_fwd(int32_t n, const float* __restrict__ mean, float t,
-                                                    const __bf16* __restrict__ whi, const __bf16* __restrict__ wlo,
-                                                    const float* __restrict__ bias, float* __restrict__ delta,
-                                                    __bf16* __restrict__ save)
-{
-    using namespace dmlp;
-    __shared__ __attribute__((aligned(16))) __bf16 ahi[kRows * kRowStride];
-    __shared__ __attribute__((aligned(16))) __bf16 alo[kRows * kRowStride];
-    const int tid = (int)threadIdx.x, w = tid >> 6, l = tid & 63;
-    const int32_t row0 = (int32_t)blockIdx.x * kRows;
-    // encoding block (columns 256..335) of every row; zero the padding
-    for (int q = tid; q < kRows * kInPad; q += 256) {
-        const int r = q / kInPad, j = q % kInPad;
-        const int32_t p = row0 + r;
-        float v = 0.0f;
-        if (j < kIn && p < n) {
-            const float x[3] = {mean[3 * (size_t)p], mean[3 * (size_t)p + 1], mean[3 * (size_t)p + 2]};
-            v = encode_entry(j, x, t);
-        }
-        split_bf16(v, ahi[r * kRowStride + kW + j], alo[r * kRowStride + kW + j]);
-    }
-    __syncthreads();
-    const size_t tile = blockIdx.x;
-    // lane roles in v_mfma_f32_32x32x16_bf16: A row / B column = l % 32, K sub-block 8 (l / 32)
-    const int lr = l & 31, lk = (l >> 5) * 8;
-    for (int layer = 0; layer <= kDepth; ++layer) {
-        const DLayer L = dlayer(layer);
-        const bool out_layer = layer == kDepth;
-        if (save && layer >= 1) {   // layer input (hidden block), column-major over the 32 rows
-            __bf16* sh = save + ((tile * kSaveCols * 2) + (size_t)(kInPad + (layer - 1) * kW) * 2) * kRows;
-            for (int q = tid; q < kW * kRows; q += 256) {
-                const int c = q / kRows, r = q % kRows;
-                sh[(size_t)c * kRows + r] = ahi[r * kRowStride + c];
-                sh[(size_t)kW * kRows + (size_t)c * kRows + r] = alo[r * kRowStride + c];
-            }
-        } else if (save && layer == 0) {   // the encoding
-            __bf16* sh = save + tile * kSaveCols * 2 * kRows;
-            for (int q = tid; q < kInPad * kRows; q += 256) {
-                const int c = q / kRows, r = q % kRows;
-                sh[(size_t)c * kRows + r] = ahi[r * kRowStride + kW + c];
-                sh[(size_t)kInPad * kRows + (size_t)c * kRows + r] = alo[r * kRowStride + kW + c];
-            }
-        }
-        const int ntile = out_layer ? (w == 0 ? 1 : 0) : 2;   // 32-column tiles of this wave
-        f32x16 acc[2];
-        for (int q = 0; q < 2; ++q)
-            for (int e = 0; e < 16; ++e) acc[q][e] = 0.0f;
-        if (ntile > 0) {
-            const __bf16* wh = whi + dw_off(layer);
-            const __bf16* wl = wlo + dw_off(layer);
-            const int c0 = out_layer ? 0 : 64 * w;
-            for (int k = 0; k < L.klen; k += 16) {
-                const bf16x8 a_h = *reinterpret_cast<const bf16x8*>(ahi + lr * kRowStride + L.k0 + k + lk);
-                const bf16x8 a_l = *reinterpret_cast<const bf16x8*>(alo + lr * kRowStride + L.k0 + k + lk);
-#pragma unroll
-                for (int q = 0; q < 2; ++q) {
-                    if (q >= ntile) break;
-                    const size_t wo = (size_t)(c0 + 32 * q + lr) * L.klen + k + lk;
-                    const bf16x8 b_h = *reinterpret_cast<const bf16x8*>(wh + wo);
-                    acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a_h, b_h, acc[q], 0, 0, 0);
-                    if (SPLIT) {
-                        const bf16x8 b_l = *reinterpret_cast<const bf16x8*>(wl + wo);
-                        acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a_h, b_l, acc[q], 0, 0, 0);
-                        acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a_l, b_h, acc[q], 0, 0, 0);
-                    }
-                }
-            }
-        }
-        __syncthreads();   // every wave has read this layer's input rows
-        // epilogue: D layout of a 32x32 tile -- lane l holds column l % 32,
-        // element e holds row 8 (e / 4) + 4 (l / 32) + e % 4
-        for (int q = 0; q < ntile; ++q) {
-            const int col = (out_layer ? 0 : 64 * w) + 32 * q + lr;
-            const float bcol = bias[(size_t)layer * kW + col];
-#pragma unroll
-            for (int e = 0; e < 16; ++e) {
-                const int r = 8 * (e >> 2) + 4 * (l >> 5) + (e & 3);
-                const float z = acc[q][e] + bcol;
-                if (out_layer) {
-                    const int32_t p = row0 + r;
-                    if (col < kOut && p < n) delta[(size_t)p * kOut + col] = z;
-                } else {
-                    split_bf16(fmaxf(z, 0.0f), ahi[r * kRowStride + col], alo[r * kRowStride + col]);
-                }
-            }
-        }
-        __syncthreads();   // the next layer reads the rows just written
-    }
-}
-
-hipError_t launch_deform_fwd(int32_t n, const float* mean, float t, const float* params, void* ws, int split,
-                             float* delta, void* save, hipStream_t s)
-{
-    using namespace dmlp;
-    __bf16* whi = (__bf16*)ws;
-    __bf16* wlo = whi + dw_total();
-    float* bias = (float*)(wlo + dw_total());
-    const size_t total = dw_total();
-    hipLaunchKernelGGL(k_deform_split, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, params, whi, wlo,
-                       bias);
-    if (n > 0) {
-        const dim3 grid((unsigned)((n + kRows - 1) / kRows));
-        if (split)
-            hipLaunchKernelGGL(k_deform_fwd<true>, grid, dim3(256), 0, s, n, mean, t, whi, wlo, bias, delta,
-                               (__bf16*)save);
-        else
-            hipLaunchKernelGGL(k_deform_fwd<false>, grid, dim3(256), 0, s, n, mean, t, whi, wlo, bias, delta,
-                               (__bf16*)save);
-    }
-    return hipGetLastError();
-}
-
-// ------------------------------------------------------------------ backward
-//
-// dIn_j = dZ_j W_j for layer j (dZ_8 = dL/d offsets; dZ_{j-1} = dIn_j masked by
-// the ReLU of the layer input h_j, read from the stored forward activations),
-// the encoding's gradient collected from layer 0 and the skip layer, then
-// dL/dmean through the encoding's derivative -- one workgroup per 32 rows,
-// the same matrix-core tiling as the forward, with the transposed split
-// weights as the B operand.  Each dZ_j is also stored per tile, column-major
-// over the rows, with its column sums (the bias gradients); a second kernel
-// forms the weight gradients dW_j = sum over rows of dZ_j^T a_j as split-K
-// matrix products over chunks of tiles, and a third adds the chunks in a
-// fixed order (deterministic) into the caller's parameter layout.
-
-// Backward GEMM of layer j: K = out width Kb, output columns nT (the layer's
-// input width padded to 32).
-__host__ __device__ constexpr int dkb(int j) { return dlayer(j).n; }
-__host__ __device__ constexpr int dnt(int j) { return j == 0 ? 96 : j == dmlp::kSkip ? 352 : dmlp::kW; }
-__host__ __device__ inline size_t dwt_off(int j)
-{
-    size_t o = 0;
-    for (int i = 0; i < j; ++i) o += (size_t)dnt(i) * dkb(i);
-    return o;
-}
-__host__ __device__ inline size_t dwt_total() { return dwt_off(dmlp::kDepth + 1); }
 
 // Caller-layout geometry of layer j: fan-in, outputs and offset of W_j in the flat array.
 __host__ __device__ inline int dfan(int j) { return j == 0 ? dmlp::kIn : j == dmlp::kSkip ? dmlp::kW + dmlp::kIn : dmlp::kW; }
@@ -293,8 +87,386 @@ __host__ __device__ inline size_t dsrc_off(int j)
     return o;
 }
 
-// Transposed split weights WT_j [nT][Kb]: WT_j[in][out] = W_j[out][in], zero
-// outside the layer's real inputs and outputs.
+__device__ __forceinline__ void split_bf16(float x, __bf16& hi, __bf16& lo)
+{
+    hi = (__bf16)x;
+    lo = (__bf16)(x - (float)hi);
+}
+
+// Four bf16 values as one 8-byte word (element 0 in the low half of .x), and back.
+__device__ __forceinline__ uint2 pack4(const __bf16 v[4])
+{
+    uint32_t b[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) b[i] = __builtin_bit_cast(uint16_t, v[i]);
+    return make_uint2(b[0] | (b[1] << 16), b[2] | (b[3] << 16));
+}
+__device__ __forceinline__ float unpack4(uint2 v, int i)
+{
+    const uint32_t w = i < 2 ? v.x : v.y;
+    return __uint_as_float((i & 1) ? (w & 0xffff0000u) : (w << 16));
+}
+
+__device__ __forceinline__ f32x16 mfma(const bf16x8& a, const bf16x8& b, const f32x16& c)
+{
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+}
+
+// The weight copies are in matrix-core fragment order: for each tile of 32
+// units and K step of 16 the 64 lanes' 8-element runs are contiguous (one
+// operand fragment is 1 KB), lane l holding unit 32 tile + l % 32 and K
+// 16 step + 8 (l / 32) .. + 7; nks = K steps of the matrix.
+__host__ __device__ inline size_t frag_index(int unit, int k, int nks)
+{
+    const int lane = (unit & 31) + 32 * ((k >> 3) & 1);
+    return (((size_t)(unit >> 5) * nks + (k >> 4)) * 64 + lane) * 8 + (k & 7);
+}
+// Offset (elements) of the fragment of (unit tile, K step) in such a copy.
+__host__ __device__ inline size_t frag_at(int tile, int ks, int nks) { return ((size_t)tile * nks + ks) * 512; }
+
+// Per-block stored arrays of ncols columns x 128 rows are kept in groups of 32
+// rows, (row / 32, column, row % 32), so that one 32-row step of the weight
+// gradients reads contiguous runs and a lane's four consecutive rows of one
+// column are one 8-byte word.
+__host__ __device__ inline size_t cm(int c, int r, int ncols) { return ((size_t)(r >> 5) * ncols + c) * 32 + (r & 31); }
+
+// Pre-split copy of the weights: hi/lo bf16 arrays [n][klen] per layer (in
+// fragment order), K
+// padded with zeros (layer 0: 76 -> 80; the skip layer: hidden 256 then
+// encoding 76 then 4 zeros) and the output layer's rows padded 13 -> 32; and
+// the biases [layer][256] (the output layer's 13 then zeros).
+__global__ void __launch_bounds__(256) k_deform_split(const float* __restrict__ params, __bf16* __restrict__ whi,
+                                                      __bf16* __restrict__ wlo, float* __restrict__ bias)
+{
+    using namespace dmlp;
+    const size_t i = (size_t)blockIdx.x * 256u + threadIdx.x;
+    if (i < dw_total()) {
+        int l = 0;
+        while (l < kDepth && i >= dw_off(l + 1)) ++l;
+        const DLayer L = dlayer(l);
+        const size_t q = i - dw_off(l);
+        const int r = (int)(q / (size_t)L.klen), c = (int)(q % (size_t)L.klen);
+        const float v = (r < dnout(l) && c < dfan(l)) ? params[dsrc_off(l) + (size_t)r * dfan(l) + c] : 0.0f;
+        const size_t o = dw_off(l) + frag_index(r, c, L.klen / 16);
+        split_bf16(v, whi[o], wlo[o]);
+    }
+    if (i < (size_t)(kDepth + 1) * kW) {
+        const int l = (int)(i / kW), r = (int)(i % kW);
+        bias[i] = r < dnout(l) ? params[dsrc_off(l) + (size_t)dnout(l) * dfan(l) + r] : 0.0f;
+    }
+}
+
+// Encoding entry j (0..75) of position x and time t, FP32 with exact range
+// reduction: sin(2^k pi p) = sin(2 pi r), r = fract(2^(k-1) p), and the power
+// of two scaling is exact.
+__device__ __forceinline__ float encode_entry(int j, const float x[3], float t)
+{
+    using namespace dmlp;
+    float p;
+    int blk;
+    if (j < 3 * (1 + 2 * kLX)) {
+        blk = j / 3;
+        p = x[j % 3];
+    } else {
+        blk = j - 3 * (1 + 2 * kLX);
+        p = t;
+    }
+    if (blk == 0) return p;
+    const int k = (blk - 1) >> 1;
+    const float r = __builtin_amdgcn_fractf(ldexpf(p, k - 1));
+    return (blk & 1) ? __builtin_amdgcn_sinf(r) : __builtin_amdgcn_cosf(r);
+}
+
+// Stored layer inputs of block b: plane 0 (hi) then plane 1 (lo), each
+// kSaveCols columns x 128 rows in the row-group order of cm(); column c < 80
+// is encoding entry c, column 80 + 256 (j - 1) + u is unit u of h_j (the
+// input of layer j).
+__host__ __device__ inline size_t save_block(size_t b) { return b * dmlp::kSaveCols * 2 * dmlp::kRB; }
+__host__ __device__ constexpr size_t save_col_h(int j) { return (size_t)dmlp::kInPad + (size_t)(j - 1) * dmlp::kW; }
+// ReLU masks of h_1..h_8 per block, stored after the layer inputs of all blocks: [layer][unit] of four
+// 32-bit words, bit r % 32 of word r / 32 set when row r's pre-activation of the unit is positive (32 KB
+// per block; the backward reads these instead of the 64 KB hi plane of each h_j).
+__host__ __device__ constexpr size_t mask_words_per_block() { return (size_t)dmlp::kDepth * dmlp::kW * 4; }
+
+template <bool SPLIT, bool KEEP>
+__global__ void __launch_bounds__(256, 1) k_deform_fwd(int32_t n, const float* __restrict__ mean, float t,
+                                                       const __bf16* __restrict__ whi,
+                                                       const __bf16* __restrict__ wlo,
+                                                       const float* __restrict__ bias, float* __restrict__ delta,
+                                                       __bf16* __restrict__ save, uint32_t* __restrict__ mask)
+{
+    using namespace dmlp;
+    __shared__ __attribute__((aligned(16))) __bf16 ahi[kRB * kAS];
+    __shared__ __attribute__((aligned(16))) __bf16 alo[kRB * kAS];
+    // encoding columns 16 s .. 16 s + 15 of every row, two stages; the block's positions
+    __shared__ __attribute__((aligned(16))) __bf16 ehi[2][kRB * kES];
+    __shared__ __attribute__((aligned(16))) __bf16 elo[2][kRB * kES];
+    __shared__ float xs[kRB * 3];
+    const int tid = (int)threadIdx.x, w = tid >> 6, l = tid & 63;
+    // lane roles in v_mfma_f32_32x32x16_bf16: A row / B column = l % 32, K run 8 (l / 32) .. + 7;
+    // result element e of a lane: column l % 32, row 8 (e / 4) + 4 (l / 32) + e % 4
+    const int lr = l & 31, lk = (l >> 5) * 8, hs = l >> 5;
+    const int32_t row0 = (int32_t)blockIdx.x * kRB;
+    __bf16* sv = KEEP ? save + save_block(blockIdx.x) : nullptr;
+    for (int q = tid; q < kRB * 3; q += 256)
+        xs[q] = row0 + q / 3 < n ? mean[3 * (size_t)row0 + q] : 0.0f;
+    __syncthreads();
+    // Encoding columns 16 s .. + 15 into stage b, computed once for the workgroup: thread t takes
+    // column 16 s + t / 16 (uniform over 16 lanes) for rows 8 (t % 16) .. + 7; in layer 0 it also
+    // stores them for the backward (eight consecutive rows of one column: 16 bytes per plane).
+    auto enc_stage = [&](int st, int b, bool store) __attribute__((always_inline)) {
+        const int jj = tid >> 4, r0 = 8 * (tid & 15), j = 16 * st + jj;
+        __bf16 eh[8], el[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const float x3[3] = {xs[3 * (r0 + i)], xs[3 * (r0 + i) + 1], xs[3 * (r0 + i) + 2]};
+            const float v = j < kIn ? encode_entry(j, x3, t) : 0.0f;
+            split_bf16(v, eh[i], el[i]);
+            ehi[b][(r0 + i) * kES + jj] = eh[i];
+            elo[b][(r0 + i) * kES + jj] = el[i];
+        }
+        if (store) {
+            const uint4 hv = make_uint4(pack4(eh).x, pack4(eh).y, pack4(eh + 4).x, pack4(eh + 4).y);
+            const uint4 lv = make_uint4(pack4(el).x, pack4(el).y, pack4(el + 4).x, pack4(el + 4).y);
+            *reinterpret_cast<uint4*>(sv + cm(j, r0, kSaveCols)) = hv;
+            *reinterpret_cast<uint4*>(sv + (size_t)kSaveCols * kRB + cm(j, r0, kSaveCols)) = lv;
+        }
+    };
+    // hidden layers: this wave's units 64 w .. 64 w + 63 (two tiles) for the four row tiles
+    for (int layer = 0; layer < kDepth; ++layer) {
+        const int klen = dlayer(layer).klen;
+        const int nks = klen / 16;
+        const __bf16* wh = whi + dw_off(layer) + 8 * l;
+        const __bf16* wl = wlo + dw_off(layer) + 8 * l;
+        f32x16 acc[2][4];
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+#pragma unroll
+            for (int bt = 0; bt < 4; ++bt)
+#pragma unroll
+                for (int e = 0; e < 16; ++e) acc[q][bt][e] = 0.0f;
+        // weight fragments of K step k (weight column k) are loaded one step ahead of their products
+        auto load_b = [&](int k, bf16x8(&bh)[2], bf16x8(&bl)[2]) __attribute__((always_inline)) {
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                const size_t o = frag_at(2 * w + q, k >> 4, nks);
+                bh[q] = *reinterpret_cast<const bf16x8*>(wh + o);
+                if (SPLIT) bl[q] = *reinterpret_cast<const bf16x8*>(wl + o);
+            }
+        };
+        auto mma = [&](int bt, const bf16x8& ah, const bf16x8& al, const bf16x8(&bh)[2], const bf16x8(&bl)[2])
+            __attribute__((always_inline)) {
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                acc[q][bt] = mfma(ah, bh[q], acc[q][bt]);
+                if (SPLIT) {
+                    acc[q][bt] = mfma(ah, bl[q], acc[q][bt]);
+                    acc[q][bt] = mfma(al, bh[q], acc[q][bt]);
+                }
+            }
+        };
+        // activation fragments of K step k (LDS), and one K step's products
+        auto load_a = [&](int k, bf16x8(&ah)[4], bf16x8(&al)[4]) __attribute__((always_inline)) {
+#pragma unroll
+            for (int bt = 0; bt < 4; ++bt) {
+                const int ao = (32 * bt + lr) * kAS + k + lk;
+                ah[bt] = *reinterpret_cast<const bf16x8*>(ahi + ao);
+                if (SPLIT) al[bt] = *reinterpret_cast<const bf16x8*>(alo + ao);
+            }
+        };
+        auto step_h = [&](const bf16x8(&ah)[4], const bf16x8(&al)[4], const bf16x8(&bh)[2], const bf16x8(&bl)[2])
+            __attribute__((always_inline)) {
+#pragma unroll
+            for (int bt = 0; bt < 4; ++bt) mma(bt, ah[bt], al[bt], bh, bl);
+        };
+        // one K step over the encoding (fragments from stage b)
+        auto step_e = [&](int b, const bf16x8(&bh)[2], const bf16x8(&bl)[2]) __attribute__((always_inline)) {
+#pragma unroll
+            for (int bt = 0; bt < 4; ++bt) {
+                const int eo2 = (32 * bt + lr) * kES + lk;
+                mma(bt, *reinterpret_cast<const bf16x8*>(&ehi[b][eo2]), *reinterpret_cast<const bf16x8*>(&elo[b][eo2]),
+                    bh, bl);
+            }
+        };
+        bf16x8 bh0[2], bl0[2], bh1[2], bl1[2];
+        if (layer >= 1) {   // K over the hidden units: weight columns 0 .. 255
+            // software pipeline: the fragments of step k + 1 are in flight during step k's
+            // products (the scheduling barriers keep the compiler from sinking them)
+            bf16x8 ah0[4], al0[4], ah1[4], al1[4];
+            load_b(0, bh0, bl0);
+            load_a(0, ah0, al0);
+#pragma unroll 1
+            for (int k = 0; k < kW; k += 32) {
+                load_b(k + 16, bh1, bl1);
+                load_a(k + 16, ah1, al1);
+                __builtin_amdgcn_sched_barrier(0);
+                step_h(ah0, al0, bh0, bl0);
+                __builtin_amdgcn_sched_barrier(0);
+                if (k + 32 < kW) {
+                    load_b(k + 32, bh0, bl0);
+                    load_a(k + 32, ah0, al0);
+                }
+                __builtin_amdgcn_sched_barrier(0);
+                step_h(ah1, al1, bh1, bl1);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        }
+        if (layer == 0 || layer == kSkip) {   // K over the encoding: weight columns eo .. eo + 79
+            const int eo = layer == 0 ? 0 : kW;
+            const bool store = KEEP && layer == 0;
+            load_b(eo, bh0, bl0);
+            enc_stage(0, 0, store);
+            __syncthreads();
+            // step st reads stage st % 2 while stage (st + 1) % 2 -- last read in step st - 1, before
+            // the barrier that ended it -- is computed; weights one step ahead as above
+#pragma unroll 1
+            for (int k = 0; k < kInPad; k += 32) {
+                const int st = k / 16;
+                if (k + 16 < kInPad) {
+                    load_b(eo + k + 16, bh1, bl1);
+                    enc_stage(st + 1, 1, store);
+                }
+                step_e(0, bh0, bl0);
+                __syncthreads();
+                if (k + 16 >= kInPad) break;
+                if (k + 32 < kInPad) {
+                    load_b(eo + k + 32, bh0, bl0);
+                    enc_stage(st + 2, 0, store);
+                }
+                step_e(1, bh1, bl1);
+                __syncthreads();
+            }
+        }
+        __syncthreads();   // every wave has read this layer's input rows
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const int col = 64 * w + 32 * q + lr;
+            const float bcol = bias[(size_t)layer * kW + col];
+            uint32_t mw[4];   // ReLU mask words of unit col (rows 32 bt .. + 31)
+#pragma unroll
+            for (int bt = 0; bt < 4; ++bt) {
+                mw[bt] = 0u;
+#pragma unroll
+                for (int g = 0; g < 4; ++g) {
+                    const int r = 32 * bt + 8 * g + 4 * hs;   // this lane's rows r .. r + 3
+                    __bf16 hh[4], hl[4];
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const float z = acc[q][bt][4 * g + i] + bcol;
+                        if (KEEP) mw[bt] |= z > 0.0f ? 1u << (8 * g + 4 * hs + i) : 0u;
+                        split_bf16(fmaxf(z, 0.0f), hh[i], hl[i]);
+                        ahi[(r + i) * kAS + col] = hh[i];
+                        alo[(r + i) * kAS + col] = hl[i];
+                    }
+                    if (KEEP) {   // h_{layer+1}, four rows of unit col per plane
+                        const size_t so = cm((int)save_col_h(layer + 1) + col, r, kSaveCols);
+                        *reinterpret_cast<uint2*>(sv + so) = pack4(hh);
+                        *reinterpret_cast<uint2*>(sv + (size_t)kSaveCols * kRB + so) = pack4(hl);
+                    }
+                }
+                if (KEEP) mw[bt] |= (uint32_t)__shfl_xor((int)mw[bt], 32, kWave);   // the other four of each eight rows
+            }
+            if (KEEP && hs == 0)
+                *reinterpret_cast<uint4*>(mask + mask_words_per_block() * blockIdx.x + ((size_t)layer * kW + col) * 4) =
+                    make_uint4(mw[0], mw[1], mw[2], mw[3]);
+        }
+        __syncthreads();   // the next layer reads the rows just written
+    }
+    // output layer: units 0..31 (13 real) of row tile w, K over the 256 hidden units
+    {
+        const __bf16* wh = whi + dw_off(kDepth) + 8 * l;
+        const __bf16* wl = wlo + dw_off(kDepth) + 8 * l;
+        f32x16 acc;
+#pragma unroll
+        for (int e = 0; e < 16; ++e) acc[e] = 0.0f;
+#pragma unroll 4
+        for (int k = 0; k < kW; k += 16) {
+            const int ao = (32 * w + lr) * kAS + k + lk;
+            const bf16x8 ah = *reinterpret_cast<const bf16x8*>(ahi + ao);
+            const bf16x8 bh = *reinterpret_cast<const bf16x8*>(wh + frag_at(0, k >> 4, kW / 16));
+            acc = mfma(ah, bh, acc);
+            if (SPLIT) {
+                const bf16x8 al = *reinterpret_cast<const bf16x8*>(alo + ao);
+                const bf16x8 bl = *reinterpret_cast<const bf16x8*>(wl + frag_at(0, k >> 4, kW / 16));
+                acc = mfma(ah, bl, acc);
+                acc = mfma(al, bh, acc);
+            }
+        }
+        const float bcol = bias[(size_t)kDepth * kW + lr];
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            const int32_t p = row0 + 32 * w + 8 * (e >> 2) + 4 * hs + (e & 3);
+            if (lr < kOut && p < n) delta[(size_t)p * kOut + lr] = acc[e] + bcol;
+        }
+    }
+}
+
+// The mask words of a stored forward (after the layer inputs of every block).
+static uint32_t* save_masks(__bf16* save, int64_t n)
+{
+    const int64_t blocks = (n + dmlp::kRB - 1) / dmlp::kRB;
+    return reinterpret_cast<uint32_t*>(save + save_block((size_t)blocks));
+}
+
+hipError_t launch_deform_fwd(int32_t n, const float* mean, float t, const float* params, void* ws, int split,
+                             float* delta, void* save, hipStream_t s)
+{
+    using namespace dmlp;
+    __bf16* whi = (__bf16*)ws;
+    __bf16* wlo = whi + dw_total();
+    float* bias = (float*)(wlo + dw_total());
+    hipLaunchKernelGGL(k_deform_split, dim3((unsigned)((dw_total() + 255) / 256)), dim3(256), 0, s, params, whi,
+                       wlo, bias);
+    if (n > 0) {
+        const dim3 grid((unsigned)((n + kRB - 1) / kRB));
+        __bf16* sv = (__bf16*)save;
+        uint32_t* mk = save ? save_masks(sv, n) : nullptr;
+        if (split && save)
+            hipLaunchKernelGGL((k_deform_fwd<true, true>), grid, dim3(256), 0, s, n, mean, t, whi, wlo, bias, delta, sv,
+                               mk);
+        else if (split)
+            hipLaunchKernelGGL((k_deform_fwd<true, false>), grid, dim3(256), 0, s, n, mean, t, whi, wlo, bias, delta,
+                               sv, mk);
+        else if (save)
+            hipLaunchKernelGGL((k_deform_fwd<false, true>), grid, dim3(256), 0, s, n, mean, t, whi, wlo, bias, delta,
+                               sv, mk);
+        else
+            hipLaunchKernelGGL((k_deform_fwd<false, false>), grid, dim3(256), 0, s, n, mean, t, whi, wlo, bias, delta,
+                               sv, mk);
+    }
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ backward
+//
+// Rows kernel, per block of 128 rows, the forward's tiling with the
+// transposed split weights as the B operand: dIn_j = dZ_j W_j for j = 8 .. 0
+// (dZ_8 = dL/d offsets; dZ_{j-1} = dIn_j where the stored h_j > 0), the
+// encoding's gradient collected from layer 0 and from the skip layer's
+// encoding inputs, then dL/dmean through the encoding's derivative.  Each
+// dZ_j is also stored per block column major over the rows, with its column
+// sums (the bias gradients).
+//
+// Weight gradients dW_j = sum over rows of dZ_j^T a_j: one workgroup of 8
+// waves per (chunk of blocks, layer part) stages 32 rows of dZ_j and a_j at a
+// time in LDS and accumulates its layer's whole 256 x 256 (at most) product;
+// a last kernel adds the chunks' partial sums in a fixed order (deterministic)
+// into the caller's parameter layout.
+
+// Backward product of layer j: K = output width Kb, output columns nT (the
+// layer's input width padded to 32).
+__host__ __device__ constexpr int dkb(int j) { return dlayer(j).n; }
+__host__ __device__ constexpr int dnt(int j) { return j == 0 ? 96 : j == dmlp::kSkip ? 352 : dmlp::kW; }
+__host__ __device__ inline size_t dwt_off(int j)
+{
+    size_t o = 0;
+    for (int i = 0; i < j; ++i) o += (size_t)dnt(i) * dkb(i);
+    return o;
+}
+__host__ __device__ inline size_t dwt_total() { return dwt_off(dmlp::kDepth + 1); }
+
+// Transposed split weights WT_j [nT][Kb] (fragment order): WT_j[in][out] =
+// W_j[out][in], zero outside the layer's real inputs and outputs.
 __global__ void __launch_bounds__(256) k_deform_splitT(const float* __restrict__ params, __bf16* __restrict__ thi,
                                                        __bf16* __restrict__ tlo)
 {
@@ -306,224 +478,368 @@ __global__ void __launch_bounds__(256) k_deform_splitT(const float* __restrict__
     const size_t q = i - dwt_off(j);
     const int in = (int)(q / (size_t)dkb(j)), out = (int)(q % (size_t)dkb(j));
     const float v = (in < dfan(j) && out < dnout(j)) ? params[dsrc_off(j) + (size_t)out * dfan(j) + in] : 0.0f;
-    split_bf16(v, thi[i], tlo[i]);
+    const size_t o = dwt_off(j) + frag_index(in, out, dkb(j) / 16);
+    split_bf16(v, thi[o], tlo[o]);
 }
 
-// Stored forward activation a_j (j >= 1: h_j; hi part) at column c, row r of a tile.
-__device__ __forceinline__ const __bf16* saved_block(const __bf16* save, size_t tile, int j)
-{
-    using namespace dmlp;
-    // block start of a_j: e (j = 0) at 0, h_j at kInPad + (j - 1) kW columns; each block is hi then lo
-    const size_t col0 = j == 0 ? 0 : (size_t)kInPad + (size_t)(j - 1) * kW;
-    return save + (tile * kSaveCols * 2 + col0 * 2) * kRows;
-}
-
-// Per-tile dZ storage: layers 0..7 256 columns, layer 8 32 columns, each hi then lo, column-major over the rows.
+// Per-block dZ storage: dZ_0..dZ_7 256 units, dZ_8 32 units, each plane 0
+// (hi) then plane 1 (lo), units x 128 rows in the row-group order of cm().
 __host__ __device__ constexpr size_t dz_cols_total() { return (size_t)dmlp::kDepth * dmlp::kW + dmlp::kOutPad; }
-__host__ __device__ inline size_t dz_block(int j) { return (size_t)j * dmlp::kW * 2 * dmlp::kRows; }
+__host__ __device__ inline size_t dz_region(int j) { return (size_t)j * dmlp::kW * 2 * dmlp::kRB; }
+__host__ __device__ constexpr int dz_units(int j) { return j == dmlp::kDepth ? dmlp::kOutPad : dmlp::kW; }
 
 template <bool SPLIT>
-__global__ void __launch_bounds__(256) k_deform_bwd_rows(int32_t n, const float* __restrict__ mean, float t,
-                                                         const float* __restrict__ ddelta,
-                                                         const __bf16* __restrict__ thi,
-                                                         const __bf16* __restrict__ tlo,
-                                                         const __bf16* __restrict__ save, __bf16* __restrict__ dz,
-                                                         float* __restrict__ dbp, float* __restrict__ dmean)
+__global__ void __launch_bounds__(256, 1) k_deform_bwd_rows(int32_t n, const float* __restrict__ mean,
+                                                            const float* __restrict__ ddelta,
+                                                            const __bf16* __restrict__ thi,
+                                                            const __bf16* __restrict__ tlo,
+                                                            __bf16* __restrict__ dz, float* __restrict__ dbp,
+                                                            float* __restrict__ de_scr, float* __restrict__ dmean,
+                                                            const uint32_t* __restrict__ mask)
 {
     using namespace dmlp;
-    constexpr int kGs = kW + 8;   // LDS row stride of the dZ operand
-    __shared__ __attribute__((aligned(16))) __bf16 ghi[kRows * kGs];
-    __shared__ __attribute__((aligned(16))) __bf16 glo[kRows * kGs];
-    __shared__ float de[kRows * kInPad];
-    __shared__ float dbs[kW];
+    __shared__ __attribute__((aligned(16))) __bf16 ghi[kRB * kAS];
+    __shared__ __attribute__((aligned(16))) __bf16 glo[kRB * kAS];
     const int tid = (int)threadIdx.x, w = tid >> 6, l = tid & 63;
-    const size_t tile = blockIdx.x;
-    const int32_t row0 = (int32_t)blockIdx.x * kRows;
-    const int lr = l & 31, lk = (l >> 5) * 8;
-    __bf16* dzt = dz + tile * dz_cols_total() * 2 * kRows;
-    // dZ_8 = dL/d offsets (13 columns of 32), rows past n are zero
-    for (int q = tid; q < kRows * kOutPad; q += 256) {
-        const int r = q / kOutPad, c = q % kOutPad;
+    const int lr = l & 31, lk = (l >> 5) * 8, hs = l >> 5;
+    const size_t blk = blockIdx.x;
+    const int32_t row0 = (int32_t)blk * kRB;
+    __bf16* dzb = dz + blk * dz_cols_total() * 2 * kRB;
+    float* dbb = dbp + blk * (kDepth + 1) * kW;
+    // dZ_8 = dL/d offsets (13 of 32 units; rows past n are zero), in LDS and stored
+    for (int q = tid; q < kRB * kOutPad; q += 256) {
+        const int r = q % kRB, c = q / kRB;
         const int32_t p = row0 + r;
         const float v = (c < kOut && p < n) ? ddelta[(size_t)p * kOut + c] : 0.0f;
-        split_bf16(v, ghi[r * kGs + c], glo[r * kGs + c]);
-        __bf16* b8 = dzt + dz_block(kDepth);
-        b8[(size_t)c * kRows + r] = ghi[r * kGs + c];
-        b8[(size_t)kOutPad * kRows + (size_t)c * kRows + r] = glo[r * kGs + c];
+        __bf16 h, o;
+        split_bf16(v, h, o);
+        ghi[r * kAS + c] = h;
+        glo[r * kAS + c] = o;
+        dzb[dz_region(kDepth) + cm(c, r, kOutPad)] = h;
+        dzb[dz_region(kDepth) + (size_t)kOutPad * kRB + cm(c, r, kOutPad)] = o;
     }
-    for (int q = tid; q < kRows * kInPad; q += 256) de[q] = 0.0f;
-    if (tid < kOutPad) {   // bias gradient of the output layer: column sums of dZ_8
-        float sacc = 0.0f;
-        for (int r = 0; r < kRows; ++r) {
+    if (tid < kOutPad) {   // bias gradient of the output layer: column sums of dZ_8, row order
+        float s = 0.0f;
+        for (int r = 0; r < kRB; ++r) {
             const int32_t p = row0 + r;
-            sacc += (tid < kOut && p < n) ? ddelta[(size_t)p * kOut + tid] : 0.0f;
+            s += (tid < kOut && p < n) ? ddelta[(size_t)p * kOut + tid] : 0.0f;
         }
-        dbp[(tile * (kDepth + 1) + kDepth) * kW + tid] = sacc;
+        dbb[(size_t)kDepth * kW + tid] = s;
     }
     __syncthreads();
     for (int j = kDepth; j >= 0; --j) {
-        const int Kb = dkb(j), NT = dnt(j);
-        const int ntiles = NT / 32;
+        const int Kb = dkb(j);
         const __bf16* th = thi + dwt_off(j);
         const __bf16* tl = tlo + dwt_off(j);
-        f32x16 acc[3];
-        for (int q = 0; q < 3; ++q)
-            for (int e = 0; e < 16; ++e) acc[q][e] = 0.0f;
-        // this wave's 32-column tiles: w, w + 4, w + 8 (< ntiles)
-        for (int k = 0; k < Kb; k += 16) {
-            const bf16x8 a_h = *reinterpret_cast<const bf16x8*>(ghi + lr * kGs + k + lk);
-            const bf16x8 a_l = *reinterpret_cast<const bf16x8*>(glo + lr * kGs + k + lk);
+        const bool hpass = j >= 1;                            // input units 0..255 are hidden units
+        const bool epass = (j == 0 || j == kSkip) && w < 3;   // encoding inputs: 3 tiles of 32
+        const int eo = j == 0 ? 0 : kW;                       // their first row in WT_j
+        // the ReLU mask words of h_j for this lane's two units, in flight during the products
+        uint4 mk[2];
+        if (hpass) {
 #pragma unroll
-            for (int q = 0; q < 3; ++q) {
-                const int ct = w + 4 * q;
-                if (ct >= ntiles) break;
-                const size_t wo = (size_t)(32 * ct + lr) * Kb + k + lk;
-                const bf16x8 b_h = *reinterpret_cast<const bf16x8*>(th + wo);
-                acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a_h, b_h, acc[q], 0, 0, 0);
-                if (SPLIT) {
-                    const bf16x8 b_l = *reinterpret_cast<const bf16x8*>(tl + wo);
-                    acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a_h, b_l, acc[q], 0, 0, 0);
-                    acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a_l, b_h, acc[q], 0, 0, 0);
+            for (int q = 0; q < 2; ++q)
+                mk[q] = *reinterpret_cast<const uint4*>(mask + mask_words_per_block() * blk +
+                                                        ((size_t)(j - 1) * kW + 64 * w + 32 * q + lr) * 4);
+        }
+        // encoding inputs first: the skip layer's part goes to scratch, and layer 0's is added to
+        // it by the same lanes (same elements); the position gradient reads the sum
+        f32x16 acce[4];
+#pragma unroll
+        for (int bt = 0; bt < 4; ++bt)
+#pragma unroll
+            for (int e = 0; e < 16; ++e) acce[bt][e] = 0.0f;
+        if (epass) {
+            auto load_e = [&](int k, bf16x8& bh, bf16x8& bl) __attribute__((always_inline)) {
+                const size_t wo = frag_at(eo / 32 + w, k >> 4, Kb / 16) + 8 * l;
+                bh = *reinterpret_cast<const bf16x8*>(th + wo);
+                if (SPLIT) bl = *reinterpret_cast<const bf16x8*>(tl + wo);
+            };
+            auto step_e = [&](int k, const bf16x8& bh, const bf16x8& bl) __attribute__((always_inline)) {
+#pragma unroll
+                for (int bt = 0; bt < 4; ++bt) {
+                    const int ao = (32 * bt + lr) * kAS + k + lk;
+                    const bf16x8 ah = *reinterpret_cast<const bf16x8*>(ghi + ao);
+                    acce[bt] = mfma(ah, bh, acce[bt]);
+                    if (SPLIT) {
+                        const bf16x8 al = *reinterpret_cast<const bf16x8*>(glo + ao);
+                        acce[bt] = mfma(ah, bl, acce[bt]);
+                        acce[bt] = mfma(al, bh, acce[bt]);
+                    }
                 }
+            };
+            bf16x8 eh0, el0, eh1, el1;
+            load_e(0, eh0, el0);
+            for (int k = 0; k < Kb; k += 32) {
+                load_e(k + 16, eh1, el1);
+                step_e(k, eh0, el0);
+                if (k + 32 < Kb) load_e(k + 32, eh0, el0);
+                step_e(k + 16, eh1, el1);
+            }
+            const int u = 32 * w + lr;
+#pragma unroll
+            for (int bt = 0; bt < 4; ++bt)
+#pragma unroll
+                for (int e = 0; e < 16; ++e) {
+                    const int r = 32 * bt + 8 * (e >> 2) + 4 * hs + (e & 3);
+                    float* sc = de_scr + (size_t)(row0 + r) * kInPad + u;
+                    if (u < kInPad) *sc = j == kSkip ? acce[bt][e] : acce[bt][e] + *sc;
+                }
+        }
+        f32x16 acc[2][4];
+#pragma unroll
+        for (int bt = 0; bt < 4; ++bt)
+#pragma unroll
+            for (int e = 0; e < 16; ++e) acc[0][bt][e] = acc[1][bt][e] = 0.0f;
+        if (hpass) {
+            auto load_h = [&](int k, bf16x8(&bh)[2], bf16x8(&bl)[2]) __attribute__((always_inline)) {
+#pragma unroll
+                for (int q = 0; q < 2; ++q) {
+                    const size_t wo = frag_at(2 * w + q, k >> 4, Kb / 16) + 8 * l;
+                    bh[q] = *reinterpret_cast<const bf16x8*>(th + wo);
+                    if (SPLIT) bl[q] = *reinterpret_cast<const bf16x8*>(tl + wo);
+                }
+            };
+            auto load_a = [&](int k, bf16x8(&ah)[4], bf16x8(&al)[4]) __attribute__((always_inline)) {
+#pragma unroll
+                for (int bt = 0; bt < 4; ++bt) {
+                    const int ao = (32 * bt + lr) * kAS + k + lk;
+                    ah[bt] = *reinterpret_cast<const bf16x8*>(ghi + ao);
+                    if (SPLIT) al[bt] = *reinterpret_cast<const bf16x8*>(glo + ao);
+                }
+            };
+            auto step_h = [&](const bf16x8(&ah)[4], const bf16x8(&al)[4], const bf16x8(&bh)[2],
+                              const bf16x8(&bl)[2]) __attribute__((always_inline)) {
+#pragma unroll
+                for (int bt = 0; bt < 4; ++bt) {
+#pragma unroll
+                    for (int q = 0; q < 2; ++q) {
+                        acc[q][bt] = mfma(ah[bt], bh[q], acc[q][bt]);
+                        if (SPLIT) {
+                            acc[q][bt] = mfma(ah[bt], bl[q], acc[q][bt]);
+                            acc[q][bt] = mfma(al[bt], bh[q], acc[q][bt]);
+                        }
+                    }
+                }
+            };
+            // software pipeline as in the forward
+            bf16x8 bh0[2], bl0[2], bh1[2], bl1[2], ah0[4], al0[4], ah1[4], al1[4];
+            load_h(0, bh0, bl0);
+            load_a(0, ah0, al0);
+#pragma unroll 1
+            for (int k = 0; k < Kb; k += 32) {
+                load_h(k + 16, bh1, bl1);
+                load_a(k + 16, ah1, al1);
+                __builtin_amdgcn_sched_barrier(0);
+                step_h(ah0, al0, bh0, bl0);
+                __builtin_amdgcn_sched_barrier(0);
+                if (k + 32 < Kb) {
+                    load_h(k + 32, bh0, bl0);
+                    load_a(k + 32, ah0, al0);
+                }
+                __builtin_amdgcn_sched_barrier(0);
+                step_h(ah1, al1, bh1, bl1);
+                __builtin_amdgcn_sched_barrier(0);
             }
         }
         __syncthreads();   // every wave has read dZ_j
-        if (tid < kW) dbs[tid] = 0.0f;
-        __syncthreads();
-        // epilogue: lane l holds column 32 ct + l % 32 and rows 8 (e / 4) + 4 (l / 32) + e % 4
-        const __bf16* hs = j >= 1 ? saved_block(save, tile, j) : nullptr;   // a_j = h_j (its first 256 columns)
-        for (int q = 0; q < 3; ++q) {
-            const int ct = w + 4 * q;
-            if (ct >= ntiles) break;
-            const int col = 32 * ct + lr;
-            float csum = 0.0f;
+        if (hpass) {
+            // dZ_{j-1} = dIn_j where the pre-activation of h_j was positive, into LDS, with its column sums
 #pragma unroll
-            for (int e = 0; e < 16; ++e) {
-                const int r = 8 * (e >> 2) + 4 * (l >> 5) + (e & 3);
-                const float v = acc[q][e];
-                if (j >= 1 && col < kW) {
-                    // dZ_{j-1} = dIn_j where h_j > 0
-                    const float h = (float)hs[(size_t)col * kRows + r];
-                    const float d = h > 0.0f ? v : 0.0f;
-                    split_bf16(d, ghi[r * kGs + col], glo[r * kGs + col]);
-                    csum += d;
-                } else {
-                    // encoding block: layer 0 (columns 0..79) or the skip layer (256..335)
-                    const int ec = j == 0 ? col : col - kW;
-                    if (ec < kInPad) de[r * kInPad + ec] += v;
+            for (int q = 0; q < 2; ++q) {
+                const int u = 64 * w + 32 * q + lr;
+                float cs = 0.0f;
+#pragma unroll
+                for (int bt = 0; bt < 4; ++bt) {
+                    const uint32_t mw = bt == 0 ? mk[q].x : bt == 1 ? mk[q].y : bt == 2 ? mk[q].z : mk[q].w;
+#pragma unroll
+                    for (int g = 0; g < 4; ++g) {
+                        const int r = 32 * bt + 8 * g + 4 * hs;
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) {
+                            const float d = (mw >> (8 * g + 4 * hs + i)) & 1u ? acc[q][bt][4 * g + i] : 0.0f;
+                            split_bf16(d, ghi[(r + i) * kAS + u], glo[(r + i) * kAS + u]);
+                            cs += d;
+                        }
+                    }
                 }
-            }
-            if (j >= 1 && col < kW) {   // column sum over the 32 rows (two lane halves)
-                csum += __shfl_xor(csum, 32, kWave);
-                if (l < 32) dbs[col] = csum;
+                cs += __shfl_xor(cs, 32, kWave);   // the other half of the rows
+                if (hs == 0) dbb[(size_t)(j - 1) * kW + u] = cs;
             }
         }
         __syncthreads();
-        if (j >= 1) {
-            // store dZ_{j-1} column-major with its bias gradient
-            __bf16* bz = dzt + dz_block(j - 1);
-            for (int q = tid; q < kW * kRows; q += 256) {
-                const int c = q / kRows, r = q % kRows;
-                bz[(size_t)c * kRows + r] = ghi[r * kGs + c];
-                bz[(size_t)kW * kRows + (size_t)c * kRows + r] = glo[r * kGs + c];
+        if (hpass) {
+            // dZ_{j-1} from LDS to its stored copy: 16-byte chunks (8 rows of one unit), consecutive
+            // threads on consecutive chunks; the stores overlap the next layer's products
+            __bf16* zo = dzb + dz_region(j - 1);
+            for (int c = tid; c < 2 * kRB * kW / 8; c += 256) {
+                const int r8 = c & 3, u = (c >> 2) & (kW - 1), g = (c >> 10) & 3, p = c >> 12;
+                const int r0 = 32 * g + 8 * r8;
+                const __bf16* src = p ? glo : ghi;
+                __bf16 v[8];
+#pragma unroll
+                for (int i = 0; i < 8; ++i) v[i] = src[(r0 + i) * kAS + u];
+                const uint2 a = pack4(v), b = pack4(v + 4);
+                *reinterpret_cast<uint4*>(zo + (size_t)p * kW * kRB + cm(u, r0, kW)) = make_uint4(a.x, a.y, b.x, b.y);
             }
-            if (tid < kW) dbp[(tile * (kDepth + 1) + (j - 1)) * kW + tid] = dbs[tid];
-            __syncthreads();
         }
     }
-    __syncthreads();   // the encoding gradient is complete
     // dL/dmean: the encoding's derivative, FP32 with the forward's range reduction
-    if (tid < kRows * 3) {
-        const int r = tid / 3, c = tid % 3;
+    const float* des = de_scr + (size_t)row0 * kInPad;   // written by this workgroup before the last barrier
+    for (int q = tid; q < kRB * 3; q += 256) {
+        const int r = q / 3, c = q % 3;
         const int32_t p = row0 + r;
-        if (p < n) {
-            const float x = mean[3 * (size_t)p + c];
-            float g = de[r * kInPad + c];
-            for (int k = 0; k < kLX; ++k) {
-                const float rr = __builtin_amdgcn_fractf(ldexpf(x, k - 1));
-                const float wgt = ldexpf(3.14159265358979f, k);   // 2^k pi
-                g += de[r * kInPad + 3 + 6 * k + c] * wgt * __builtin_amdgcn_cosf(rr);
-                g -= de[r * kInPad + 6 + 6 * k + c] * wgt * __builtin_amdgcn_sinf(rr);
-            }
-            dmean[3 * (size_t)p + c] = g;
+        if (p >= n) continue;
+        const float x = mean[3 * (size_t)p + c];
+        float g = des[r * kInPad + c];
+        for (int k = 0; k < kLX; ++k) {
+            const float rr = __builtin_amdgcn_fractf(ldexpf(x, k - 1));
+            const float wgt = ldexpf(3.14159265358979f, k);   // 2^k pi
+            g += des[r * kInPad + 3 + 6 * k + c] * wgt * __builtin_amdgcn_cosf(rr);
+            g -= des[r * kInPad + 6 + 6 * k + c] * wgt * __builtin_amdgcn_sinf(rr);
         }
+        dmean[3 * (size_t)p + c] = g;
     }
 }
 
-// Weight gradients of layer j, split over chunks of tiles: each wave owns one
-// 32 x 32 tile of C = sum over rows of dZ_j^T a_j (rows out, columns in, the
-// padded layout of the split weights) and writes its chunk's partial sum.
+// Parts of the weight-gradient products: layer, output units and inputs in
+// tiles of 32, the stored input columns that feed them (zero beyond), and the
+// first column of the part in layer j's padded [n][klen] product.
+struct WPart {
+    int j, mt, nt;
+    int acol, avalid;
+    int ccol;
+};
+constexpr int kWParts = 10;
+
+__host__ __device__ constexpr WPart wpart(int v)
+{
+    using namespace dmlp;
+    return v == 0   ? WPart{0, 8, 3, 0, kInPad, 0}
+           : v <= 4 ? WPart{v, 8, 8, (int)save_col_h(v), kW, 0}
+           : v == 5 ? WPart{kSkip, 8, 8, (int)save_col_h(kSkip), kW, 0}
+           : v == 6 ? WPart{kSkip, 8, 3, 0, kInPad, kW}
+           : v <= 8 ? WPart{v - 1, 8, 8, (int)save_col_h(v - 1), kW, 0}
+                    : WPart{kDepth, 1, 8, (int)save_col_h(kDepth), kW, 0};
+}
+
 template <bool SPLIT>
-__global__ void __launch_bounds__(256) k_deform_wgrad(int j, int32_t n_tiles, int tiles_per_chunk,
+__global__ void __launch_bounds__(512) k_deform_wgrad(int32_t n_blocks, int blocks_per_chunk,
                                                       const __bf16* __restrict__ dz, const __bf16* __restrict__ save,
                                                       float* __restrict__ part)
 {
     using namespace dmlp;
-    const DLayer L = dlayer(j);
-    const int mt = L.n / 32, nt = (L.klen + 31) / 32;
-    const int w = (int)(threadIdx.x >> 6), l = (int)(threadIdx.x & 63);
-    const int ctile = (int)blockIdx.x * 4 + w;
-    if (ctile >= mt * nt) return;   // whole wave
-    const int mi = ctile / nt, ni = ctile % nt;
-    const int chunk = (int)blockIdx.y;
-    const int32_t t0 = chunk * tiles_per_chunk, t1 = min(n_tiles, t0 + tiles_per_chunk);
-    const int lr = l & 31, lk = (l >> 5) * 8;
-    const int m = 32 * mi + lr;    // output unit (A row)
-    const int c = 32 * ni + lr;    // input column (B column) in the layer's padded input
-    // where input column c lives in the stored activations: block, column, valid
-    int blk, bc;
-    bool cvalid = c < L.klen;
-    if (j == 0) { blk = 0; bc = c; cvalid = c < kInPad; }
-    else if (j == kSkip) { blk = c < kW ? j : 0; bc = c < kW ? c : c - kW; cvalid = bc < (c < kW ? kW : kInPad); }
-    else { blk = j; bc = c; }
-    const int bcols = blk == 0 ? kInPad : kW;   // columns of that block (hi plane size)
-    const int zcols = j == kDepth ? kOutPad : kW;
-    f32x16 acc;
-    for (int e = 0; e < 16; ++e) acc[e] = 0.0f;
-    for (int32_t tt = t0; tt < t1; ++tt) {
-        const __bf16* zb = dz + (size_t)tt * dz_cols_total() * 2 * kRows + dz_block(j);
-        const __bf16* sb = saved_block(save, (size_t)tt, blk);
+    // two stages (the next one fills while the current one feeds the products):
+    // dZ_j [unit][32 rows] and a_j [input][32 rows], hi and lo planes each
+    __shared__ __attribute__((aligned(16))) __bf16 zs[2][2][kW * kZS];
+    __shared__ __attribute__((aligned(16))) __bf16 as[2][2][kW * kZS];
+    const WPart P = wpart((int)blockIdx.y);
+    const int tid = (int)threadIdx.x, w = tid >> 6, l = tid & 63;
+    const int lr = l & 31, lk = (l >> 5) * 8, hs = l >> 5;
+    const int M = 32 * P.mt, N = 32 * P.nt, T = P.mt * P.nt;
+    const int zu = dz_units(P.j);
+    const int32_t b0 = (int32_t)blockIdx.x * blocks_per_chunk, b1 = min(n_blocks, b0 + blocks_per_chunk);
+    const int steps = (b1 - b0) * (kRB / 32);
+    f32x16 acc[8];
 #pragma unroll
-        for (int k = 0; k < kRows; k += 16) {
-            const bf16x8 a_h = *reinterpret_cast<const bf16x8*>(zb + (size_t)m * kRows + k + lk);
-            bf16x8 b_h, b_l;
-            if (cvalid) {
-                b_h = *reinterpret_cast<const bf16x8*>(sb + (size_t)bc * kRows + k + lk);
-                b_l = *reinterpret_cast<const bf16x8*>(sb + (size_t)bcols * kRows + (size_t)bc * kRows + k + lk);
-            } else {
-                for (int e = 0; e < 8; ++e) b_h[e] = b_l[e] = (__bf16)0.0f;
-            }
-            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a_h, b_h, acc, 0, 0, 0);
-            if (SPLIT) {
-                const bf16x8 a_l = *reinterpret_cast<const bf16x8*>(zb + (size_t)zcols * kRows + (size_t)m * kRows + k + lk);
-                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a_h, b_l, acc, 0, 0, 0);
-                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a_l, b_h, acc, 0, 0, 0);
+    for (int i = 0; i < 8; ++i)
+#pragma unroll
+        for (int e = 0; e < 16; ++e) acc[i][e] = 0.0f;
+    // this thread's 16-byte pieces of a stage: piece q = tid + 512 i (i < 4) is unit q / 8,
+    // plane (q / 4) % 2, rows 8 (q % 4) .. + 7 of the step
+    uint4 rz0, rz1, rz2, rz3, ra0, ra1, ra2, ra3;
+    auto gpiece = [&](int st, int i, uint4& z, uint4& a) __attribute__((always_inline)) {
+        const int32_t b = b0 + st / (kRB / 32);
+        const int ks = (st % (kRB / 32)) * 32;
+        const int q = tid + 512 * i;
+        const int u = q >> 3, p = (q >> 2) & 1, c = q & 3;
+        const __bf16* zb = dz + (size_t)b * dz_cols_total() * 2 * kRB + dz_region(P.j);
+        const __bf16* sb = save + save_block((size_t)b);
+        z = make_uint4(0u, 0u, 0u, 0u);
+        a = make_uint4(0u, 0u, 0u, 0u);
+        if (q < M * 8) z = *reinterpret_cast<const uint4*>(zb + (size_t)p * zu * kRB + cm(u, ks, zu) + 8 * c);
+        if (q < N * 8 && u < P.avalid)
+            a = *reinterpret_cast<const uint4*>(sb + (size_t)p * kSaveCols * kRB + cm(P.acol + u, ks, kSaveCols) +
+                                                8 * c);
+    };
+    auto spiece = [&](int buf, int i, const uint4& z, const uint4& a) __attribute__((always_inline)) {
+        const int q = tid + 512 * i;
+        const int u = q >> 3, p = (q >> 2) & 1, c = q & 3;
+        if (q < M * 8) *reinterpret_cast<uint4*>(&zs[buf][p][u * kZS + 8 * c]) = z;
+        if (q < N * 8) *reinterpret_cast<uint4*>(&as[buf][p][u * kZS + 8 * c]) = a;
+    };
+    auto gload = [&](int st) __attribute__((always_inline)) {
+        gpiece(st, 0, rz0, ra0);
+        gpiece(st, 1, rz1, ra1);
+        gpiece(st, 2, rz2, ra2);
+        gpiece(st, 3, rz3, ra3);
+    };
+    auto sstore = [&](int buf) __attribute__((always_inline)) {
+        spiece(buf, 0, rz0, ra0);
+        spiece(buf, 1, rz1, ra1);
+        spiece(buf, 2, rz2, ra2);
+        spiece(buf, 3, rz3, ra3);
+    };
+    if (steps > 0) {
+        gload(0);
+        sstore(0);
+    }
+    __syncthreads();
+    for (int st = 0; st < steps; ++st) {
+        const int cur = st & 1;
+        if (st + 1 < steps) gload(st + 1);   // in flight during this step's products
+#pragma unroll
+        for (int kk = 0; kk < 32; kk += 16) {
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const int ti = w + 8 * i;
+                if (ti >= T) break;
+                const int mi = ti / P.nt, ni = ti - mi * P.nt;
+                const int ao = (32 * mi + lr) * kZS + kk + lk, bo = (32 * ni + lr) * kZS + kk + lk;
+                const bf16x8 a_h = *reinterpret_cast<const bf16x8*>(&zs[cur][0][ao]);
+                const bf16x8 b_h = *reinterpret_cast<const bf16x8*>(&as[cur][0][bo]);
+                acc[i] = mfma(a_h, b_h, acc[i]);
+                if (SPLIT) {
+                    const bf16x8 a_l = *reinterpret_cast<const bf16x8*>(&zs[cur][1][ao]);
+                    const bf16x8 b_l = *reinterpret_cast<const bf16x8*>(&as[cur][1][bo]);
+                    acc[i] = mfma(a_h, b_l, acc[i]);
+                    acc[i] = mfma(a_l, b_h, acc[i]);
+                }
             }
         }
+        // the other stage was last read in the previous step, before the barrier that ended it
+        if (st + 1 < steps) sstore(cur ^ 1);
+        __syncthreads();
     }
-    // D: lane l holds C column 32 ni + l % 32, rows 32 mi + 8 (e / 4) + 4 (l / 32) + e % 4
-    float* pc = part + (size_t)chunk * dw_total() + dw_off(j);
+    // result element e of tile (mi, ni): unit 32 mi + 8 (e / 4) + 4 (l / 32) + e % 4, input 32 ni + l % 32
+    const DLayer L = dlayer(P.j);
+    float* pc = part + (size_t)blockIdx.x * dw_total() + dw_off(P.j);
 #pragma unroll
-    for (int e = 0; e < 16; ++e) {
-        const int row = 32 * mi + 8 * (e >> 2) + 4 * (l >> 5) + (e & 3);
+    for (int i = 0; i < 8; ++i) {
+        const int ti = w + 8 * i;
+        if (ti >= T) break;
+        const int mi = ti / P.nt, ni = ti - mi * P.nt;
         const int col = 32 * ni + lr;
-        if (col < L.klen) pc[(size_t)row * L.klen + col] = acc[e];
+        if (col >= P.avalid) continue;
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            const int row = 32 * mi + 8 * (e >> 2) + 4 * hs + (e & 3);
+            pc[(size_t)row * L.klen + P.ccol + col] = acc[i][e];
+        }
     }
 }
 
-// Bias gradients per chunk of tiles: thread r of chunk k sums unit r of every
-// layer over the chunk's tiles, in tile order.
-__global__ void __launch_bounds__(256) k_deform_bias_part(int32_t n_tiles, int tiles_per_chunk,
+// Bias gradients per chunk: thread r of (chunk k, layer j) sums unit r of
+// layer j over the chunk's blocks, in block order.
+__global__ void __launch_bounds__(256) k_deform_bias_part(int32_t n_blocks, int blocks_per_chunk,
                                                           const float* __restrict__ dbp, float* __restrict__ bpart)
 {
     using namespace dmlp;
-    const int r = (int)threadIdx.x, chunk = (int)blockIdx.x;
-    const int32_t t0 = chunk * tiles_per_chunk, t1 = min(n_tiles, t0 + tiles_per_chunk);
-    for (int j = 0; j <= kDepth; ++j) {
-        float acc = 0.0f;
-        for (int32_t tt = t0; tt < t1; ++tt) acc += dbp[((size_t)tt * (kDepth + 1) + j) * kW + r];
-        bpart[((size_t)chunk * (kDepth + 1) + j) * kW + r] = acc;
-    }
+    const int r = (int)threadIdx.x, chunk = (int)blockIdx.x, j = (int)blockIdx.y;
+    const int32_t b0 = chunk * blocks_per_chunk, b1 = min(n_blocks, b0 + blocks_per_chunk);
+    float acc = 0.0f;
+    for (int32_t b = b0; b < b1; ++b) acc += dbp[((size_t)b * (kDepth + 1) + j) * kW + r];
+    bpart[((size_t)chunk * (kDepth + 1) + j) * kW + r] = acc;
 }
 
 // Sum the chunks' partial weight and bias gradients in a fixed order into the
@@ -533,14 +849,13 @@ __global__ void __launch_bounds__(256) k_deform_reduce(int chunks, const float* 
 {
     using namespace dmlp;
     const size_t i = (size_t)blockIdx.x * 256u + threadIdx.x;
-    const size_t total = dsrc_off(kDepth + 1);
-    if (i >= total) return;
+    if (i >= dsrc_off(kDepth + 1)) return;
     int j = 0;
     while (j < kDepth && i >= dsrc_off(j + 1)) ++j;
     const size_t q = i - dsrc_off(j);
     const int fan = dfan(j), no = dnout(j);
     float acc = 0.0f;
-    if (q < (size_t)no * fan) {   // weight (out r, in c) -> padded column c (same index: padding comes after)
+    if (q < (size_t)no * fan) {   // weight (out r, in c): padded column c (the padding follows the inputs)
         const int r = (int)(q / (size_t)fan), c = (int)(q % (size_t)fan);
         const size_t pi = dw_off(j) + (size_t)r * dlayer(j).klen + c;
         for (int k = 0; k < chunks; ++k) acc += part[(size_t)k * dw_total() + pi];
@@ -551,76 +866,87 @@ __global__ void __launch_bounds__(256) k_deform_reduce(int chunks, const float* 
     dparams[i] = acc;
 }
 
-constexpr int kTilesPerChunk = 128;
+// Chunks of blocks of the weight-gradient products: about 100 per layer part
+// (a thousand workgroups in all), at least one block each.
+static int wgrad_blocks_per_chunk(int32_t n_blocks) { return std::max<int32_t>(1, (n_blocks + 99) / 100); }
 
-hipError_t launch_deform_bwd(int32_t n, const float* mean, float t, const float* params, void* ws, int split,
-                             const float* ddelta, float* dparams, float* dmean, hipStream_t s)
-{
-    using namespace dmlp;
-    const int32_t n_tiles = (n + kRows - 1) / kRows;
-    const int chunks = (n_tiles + kTilesPerChunk - 1) / kTilesPerChunk;
-    char* base = (char*)ws;
-    const size_t wbytes = (dw_total() * 2 * sizeof(__bf16) + (size_t)(kDepth + 1) * kW * sizeof(float) + 255) / 256 * 256;
-    const __bf16* save = (const __bf16*)(base + wbytes);
-    const size_t sbytes = ((size_t)n_tiles * kSaveCols * 2 * kRows * sizeof(__bf16) + 255) / 256 * 256;
-    char* scr = base + wbytes + sbytes;
-    __bf16* thi = (__bf16*)scr;
-    __bf16* tlo = thi + dwt_total();
-    char* after_t = scr + (dwt_total() * 2 * sizeof(__bf16) + 255) / 256 * 256;
-    __bf16* dz = (__bf16*)after_t;
-    float* dbp = (float*)(after_t + ((size_t)n_tiles * dz_cols_total() * 2 * kRows * sizeof(__bf16) + 255) / 256 * 256);
-    float* bpart = dbp + ((size_t)n_tiles * (kDepth + 1) * kW + 63) / 64 * 64;
-    float* part = bpart + (size_t)std::max(chunks, 1) * (kDepth + 1) * kW;
-    hipLaunchKernelGGL(k_deform_splitT, dim3((unsigned)((dwt_total() + 255) / 256)), dim3(256), 0, s, params, thi,
-                       tlo);
-    if (n_tiles > 0) {
-        if (split)
-            hipLaunchKernelGGL(k_deform_bwd_rows<true>, dim3((unsigned)n_tiles), dim3(256), 0, s, n, mean, t, ddelta,
-                               thi, tlo, save, dz, dbp, dmean);
-        else
-            hipLaunchKernelGGL(k_deform_bwd_rows<false>, dim3((unsigned)n_tiles), dim3(256), 0, s, n, mean, t,
-                               ddelta, thi, tlo, save, dz, dbp, dmean);
-        for (int j = 0; j <= kDepth; ++j) {
-            const DLayer L = dlayer(j);
-            const int ct = (L.n / 32) * ((L.klen + 31) / 32);
-            const dim3 grid((unsigned)((ct + 3) / 4), (unsigned)chunks);
-            if (split)
-                hipLaunchKernelGGL(k_deform_wgrad<true>, grid, dim3(256), 0, s, j, n_tiles, kTilesPerChunk, dz, save,
-                                   part);
-            else
-                hipLaunchKernelGGL(k_deform_wgrad<false>, grid, dim3(256), 0, s, j, n_tiles, kTilesPerChunk, dz, save,
-                                   part);
-        }
-    }
-    if (n_tiles > 0)
-        hipLaunchKernelGGL(k_deform_bias_part, dim3((unsigned)chunks), dim3(256), 0, s, n_tiles, kTilesPerChunk, dbp,
-                           bpart);
-    const size_t total = dsrc_off(kDepth + 1);
-    hipLaunchKernelGGL(k_deform_reduce, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s,
-                       n_tiles > 0 ? chunks : 0, part, bpart, dparams);
-    return hipGetLastError();
-}
+static size_t up256(size_t b) { return (b + 255) / 256 * 256; }
 
 size_t deform_weight_bytes()
 {
-    return (dw_total() * 2 * sizeof(__bf16) + (size_t)(dmlp::kDepth + 1) * dmlp::kW * sizeof(float) + 255) / 256 * 256;
+    return up256(dw_total() * 2 * sizeof(__bf16) + (size_t)(dmlp::kDepth + 1) * dmlp::kW * sizeof(float));
 }
 
 size_t deform_save_bytes(int64_t n)
 {
-    const int64_t tiles = (n + dmlp::kRows - 1) / dmlp::kRows;
-    return ((size_t)tiles * dmlp::kSaveCols * 2 * dmlp::kRows * sizeof(__bf16) + 255) / 256 * 256;
+    const int64_t blocks = (n + dmlp::kRB - 1) / dmlp::kRB;
+    return up256(save_block((size_t)blocks) * sizeof(__bf16) + (size_t)blocks * mask_words_per_block() * 4);
 }
 
-size_t deform_bwd_scratch_bytes(int64_t n)
+// Backward scratch: WT | dZ per block | bias partials per block | encoding
+// gradient of the skip layer | bias partials per chunk | weight partials per chunk.
+struct BwdScratch {
+    size_t wt, dz, dbp, de, bpart, part, total;
+};
+
+static BwdScratch bwd_scratch(int64_t n)
 {
     using namespace dmlp;
-    const int64_t tiles = (n + kRows - 1) / kRows;
-    const int64_t chunks = (tiles + kTilesPerChunk - 1) / kTilesPerChunk;
-    return (dwt_total() * 2 * sizeof(__bf16) + 255) / 256 * 256 +
-           ((size_t)tiles * dz_cols_total() * 2 * kRows * sizeof(__bf16) + 255) / 256 * 256 +
-           ((size_t)tiles * (kDepth + 1) * kW + 63) / 64 * 64 * sizeof(float) +
-           (size_t)std::max<int64_t>(chunks, 1) * ((kDepth + 1) * kW + dw_total()) * sizeof(float);
+    const int32_t blocks = (int32_t)((n + kRB - 1) / kRB);
+    const int bpc = wgrad_blocks_per_chunk(blocks);
+    const int32_t chunks = std::max<int32_t>(1, (blocks + bpc - 1) / bpc);
+    BwdScratch s;
+    s.wt = 0;
+    s.dz = s.wt + up256(dwt_total() * 2 * sizeof(__bf16));
+    s.dbp = s.dz + up256((size_t)blocks * dz_cols_total() * 2 * kRB * sizeof(__bf16));
+    s.de = s.dbp + up256((size_t)blocks * (kDepth + 1) * kW * sizeof(float));
+    s.bpart = s.de + up256((size_t)blocks * kRB * kInPad * sizeof(float));
+    s.part = s.bpart + up256((size_t)chunks * (kDepth + 1) * kW * sizeof(float));
+    s.total = s.part + up256((size_t)chunks * dw_total() * sizeof(float));
+    return s;
+}
+
+size_t deform_bwd_scratch_bytes(int64_t n) { return bwd_scratch(n).total; }
+
+hipError_t launch_deform_bwd(int32_t n, const float* mean, const float* params, void* ws, int split,
+                             const float* ddelta, float* dparams, float* dmean, hipStream_t s)
+{
+    using namespace dmlp;
+    const int32_t blocks = (n + kRB - 1) / kRB;
+    const int bpc = wgrad_blocks_per_chunk(blocks);
+    const int chunks = (blocks + bpc - 1) / bpc;
+    char* base = (char*)ws;
+    const __bf16* save = (const __bf16*)(base + deform_weight_bytes());
+    char* scr = base + deform_weight_bytes() + deform_save_bytes(n);
+    const BwdScratch L = bwd_scratch(n);
+    __bf16* thi = (__bf16*)(scr + L.wt);
+    __bf16* tlo = thi + dwt_total();
+    __bf16* dz = (__bf16*)(scr + L.dz);
+    float* dbp = (float*)(scr + L.dbp);
+    float* de = (float*)(scr + L.de);
+    float* bpart = (float*)(scr + L.bpart);
+    float* part = (float*)(scr + L.part);
+    hipLaunchKernelGGL(k_deform_splitT, dim3((unsigned)((dwt_total() + 255) / 256)), dim3(256), 0, s, params, thi,
+                       tlo);
+    if (blocks > 0) {
+        if (split)
+            hipLaunchKernelGGL(k_deform_bwd_rows<true>, dim3((unsigned)blocks), dim3(256), 0, s, n, mean, ddelta,
+                               thi, tlo, dz, dbp, de, dmean, save_masks((__bf16*)save, n));
+        else
+            hipLaunchKernelGGL(k_deform_bwd_rows<false>, dim3((unsigned)blocks), dim3(256), 0, s, n, mean, ddelta,
+                               thi, tlo, dz, dbp, de, dmean, save_masks((__bf16*)save, n));
+        const dim3 grid((unsigned)chunks, (unsigned)kWParts);
+        if (split)
+            hipLaunchKernelGGL(k_deform_wgrad<true>, grid, dim3(512), 0, s, blocks, bpc, dz, save, part);
+        else
+            hipLaunchKernelGGL(k_deform_wgrad<false>, grid, dim3(512), 0, s, blocks, bpc, dz, save, part);
+        hipLaunchKernelGGL(k_deform_bias_part, dim3((unsigned)chunks, (unsigned)(kDepth + 1)), dim3(256), 0, s,
+                           blocks, bpc, dbp, bpart);
+    }
+    const size_t total = dsrc_off(kDepth + 1);
+    hipLaunchKernelGGL(k_deform_reduce, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s,
+                       blocks > 0 ? chunks : 0, part, bpart, dparams);
+    return hipGetLastError();
 }
 
 }  // namespace wipes
@@ -676,13 +1002,13 @@ wipes_status wipes_deform_bwd(wipes_ctx* ctx, int32_t precision, const float* pa
                               float time, const float* d_offsets, void* workspace, size_t workspace_bytes,
                               float* d_params, float* d_mean, void* stream)
 {
+    (void)time;   // the stored layer inputs carry it
     wipes_status st = deform_check(ctx, precision, params, n, mean, workspace, workspace_bytes, 1);
     if (st != WIPES_OK) return st;
     if (!d_params || (n > 0 && (!d_offsets || !d_mean)))
         return fail(ctx, WIPES_ERR_INVALID, "d_offsets, d_params and d_mean must be set");
-    const hipError_t e = launch_deform_bwd((int32_t)n, mean, time, params, workspace,
-                                           precision == WIPES_DEFORM_BF16X3, d_offsets, d_params, d_mean,
-                                           (hipStream_t)stream);
+    const hipError_t e = launch_deform_bwd((int32_t)n, mean, params, workspace, precision == WIPES_DEFORM_BF16X3,
+                                           d_offsets, d_params, d_mean, (hipStream_t)stream);
     return e == hipSuccess ? WIPES_OK : hip_fail(ctx, e, "deform bwd");
 }
 
