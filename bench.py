@@ -304,8 +304,11 @@ MFMA_BF16_PEAK = 2.5e15
 
 
 def bench_deform(log, n=1_000_000, reps=10):
-    """Eq. 8 deformation network over the 3D scene's primitives at one time: forward alone, and
-    forward (keeping the layer inputs) + backward, in both precisions; matrix-core roofline."""
+    """Eq. 8 deformation network over the 3D scene's primitives at one time: forward alone (the
+    per-frame cost of a dynamic scene) and forward keeping the layer inputs + backward (a training
+    step's cost), in both precisions.  Roofline of the forward: the bf16 matrix-core work the
+    precision executes (three products per FP32-class product for BF16X3) over the event-timed call,
+    against the dense bf16 peak; the FP32-equivalent algorithmic rate beside it."""
     import torch
     from paper_2508_12615_amd import binding as B
     from paper_2508_12615_amd import synth
@@ -342,8 +345,13 @@ def bench_deform(log, n=1_000_000, reps=10):
         net.close()
         del ws
     torch.cuda.empty_cache()
+    f = res["bf16x3_fwd"]
+    ach = 3 * 2.0 * DEFORM_MACS * n / (f["ms"] * 1e-3)
+    roof = dict(bound="mfma", achieved=ach / 1e12, peak=MFMA_BF16_PEAK / 1e12, unit="TFLOP/s",
+                frac=ach / MFMA_BF16_PEAK, traffic=None, kernel="k_deform_fwd (BF16X3)",
+                fp32_equivalent_tflops=f["alg_tflops"], fp32_vector_peak_tflops=157.3)
     return dict(workload="Eq. 8 deformation network, %d primitives, one time" % n,
-                macs_per_primitive=DEFORM_MACS, mfma_peak_tflops=MFMA_BF16_PEAK / 1e12, **res)
+                macs_per_primitive=DEFORM_MACS, roofline=roof, **res)
 
 
 def bench_serving(n_req, n_warm, log, budget=3 << 29):
