@@ -344,13 +344,53 @@ def bench_deform(log, n=1_000_000, reps=10):
                 % (key, ms, res[key]["alg_tflops"], res[key]["mfma_frac"]))
         net.close()
         del ws
+    # a dynamic-scene frame (Sec. 4.3, 6D): the network at time t, the offsets applied, the 1080p view
+    # rendered; and the training step through all three (render and network backward)
+    from paper_2508_12615_amd.deform import apply_offsets
+    from paper_2508_12615_amd.raster import Rasterizer
+    c = synth.config3(n)
+    prims = {k: torch.from_numpy(v).to(dev) for k, v in c["prims"].items()}
+    net = Deformation(device=dev)
+    r = Rasterizer(B.WIPES_3D_ALPHA, device=dev)
+    W, H = c["camera"]["width"], c["camera"]["height"]
+    dL = torch.randn((W * H, 3), device=dev) / (3 * W * H)
+
+    def frame(train):
+        if train:
+            p = params.detach().requires_grad_(True)
+            off = net(p, prims["mean"], 0.625)
+            dyn = apply_offsets(net, prims, off)
+            f = r.forward([dict(camera=c["camera"], prims=dyn)], with_backward=True)
+            grads = r.backward([dict(camera=c["camera"], prims=dyn)], f, dL)[0]
+            torch.autograd.backward([dyn[k] for k in ("mean", "freq", "quat", "scale")],
+                                    [grads[k] for k in ("mean", "freq", "quat", "scale")])
+            return p.grad
+        off = net.forward(params, prims["mean"], 0.625)
+        dyn = apply_offsets(net, prims, off)
+        return r.forward([dict(camera=c["camera"], prims=dyn)]).image
+
+    for train in (False, True):
+        frame(train)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            frame(train)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / reps
+        key = "dynamic_frame_train" if train else "dynamic_frame"
+        res[key] = dict(ms=ms, frames_per_s=1e3 / ms)
+        log("deform %s: %.3f ms (%.1f frames/s)" % (key, ms, 1e3 / ms))
+    net.close()
+    del prims, r
     torch.cuda.empty_cache()
     f = res["bf16x3_fwd"]
     ach = 3 * 2.0 * DEFORM_MACS * n / (f["ms"] * 1e-3)
     roof = dict(bound="mfma", achieved=ach / 1e12, peak=MFMA_BF16_PEAK / 1e12, unit="TFLOP/s",
                 frac=ach / MFMA_BF16_PEAK, traffic=None, kernel="k_deform_fwd (BF16X3)",
                 fp32_equivalent_tflops=f["alg_tflops"], fp32_vector_peak_tflops=157.3)
-    return dict(workload="Eq. 8 deformation network, %d primitives, one time" % n,
+    return dict(workload="Eq. 8 deformation network, %d primitives, one time; dynamic frame = network + "
+                         "applied offsets + 1920x1080 alpha render of the same scene (train: + render and "
+                         "network backward)" % n,
                 macs_per_primitive=DEFORM_MACS, roofline=roof, **res)
 
 

@@ -369,6 +369,18 @@ wipes_status wipes_deform_bwd(wipes_ctx* ctx, int32_t precision, const float* pa
                               float time, const float* d_offsets, void* workspace, size_t workspace_bytes,
                               float* d_params, float* d_mean, void* stream);
 
+/* The deformed primitive set of Sec. 4.3 (the offsets of Eq. 8 added to a 3D
+ * primitive's parameters): out_mean = mean + dx, out_freq = freq + df,
+ * out_quat = quat + dq, out_scale = scale + ds, for offsets[n][13] from
+ * wipes_deform_fwd and device arrays mean/freq/scale [n][3], quat [n][4];
+ * the outputs may alias the inputs.  Its backward is the identity: the
+ * rasterizer's gradients for the deformed mean, freq, quat and scale are the
+ * columns 0-2, 3-5, 6-9 and 10-12 of d_offsets.  Asynchronous on `stream`;
+ * INVALID for n < 0 or a missing array. */
+wipes_status wipes_deform_apply(wipes_ctx* ctx, int64_t n, const float* offsets, const float* mean,
+                                const float* freq, const float* quat, const float* scale, float* out_mean,
+                                float* out_freq, float* out_quat, float* out_scale, void* stream);
+
 /* ------------------------------------------------------- fitting, graphs */
 
 /* Gradient of the L2 fitting loss L = sum over images of the mean over that

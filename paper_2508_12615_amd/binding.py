@@ -102,6 +102,7 @@ def lib() -> C.CDLL:
         "wipes_deform_workspace_size": (C.c_int, [C.c_int64, C.c_int32, PP(C.c_size_t)]),
         "wipes_deform_fwd": (C.c_int, [P, C.c_int32, P, C.c_int64, P, C.c_float, P, P, C.c_size_t, C.c_int32, P]),
         "wipes_deform_bwd": (C.c_int, [P, C.c_int32, P, C.c_int64, P, C.c_float, P, P, C.c_size_t, P, P, P]),
+        "wipes_deform_apply": (C.c_int, [P, C.c_int64, P, P, P, P, P, P, P, P, P, P]),
         "wipes_profile_enable": (C.c_int, [P, C.c_int32]),
         "wipes_profile_read": (C.c_int, [P, PP(C.c_double), PP(C.c_int64), C.c_int32]),
         "wipes_render_stats": (C.c_int, [P, PP(wipes_params), PP(wipes_batch), PP(wipes_buffer), PP(wipes_buffer),
@@ -259,6 +260,12 @@ def wipes_deform_bwd(ctx, precision: int, params: int, n: int, mean: int, time: 
                      workspace: int, workspace_bytes: int, d_params: int, d_mean: int, stream: int = 0) -> None:
     check(lib().wipes_deform_bwd(ctx, precision, params, n, mean, time, d_offsets, workspace, workspace_bytes,
                                  d_params, d_mean, stream), ctx)
+
+
+def wipes_deform_apply(ctx, n: int, offsets: int, mean: int, freq: int, quat: int, scale: int, out_mean: int,
+                       out_freq: int, out_quat: int, out_scale: int, stream: int = 0) -> None:
+    check(lib().wipes_deform_apply(ctx, n, offsets, mean, freq, quat, scale, out_mean, out_freq, out_quat, out_scale,
+                                   stream), ctx)
 
 
 def wipes_render_stats(ctx, params, batch, screen, bins, T_final: int, last: int, stream: int = 0):

@@ -949,6 +949,26 @@ hipError_t launch_deform_bwd(int32_t n, const float* mean, const float* params, 
     return hipGetLastError();
 }
 
+// The deformed primitive set: mean + dx, freq + df, quat + dq, scale + ds, one
+// thread per primitive (13 offsets in, 13 values out).
+// (no __restrict__: the outputs may alias the inputs)
+__global__ void __launch_bounds__(256) k_deform_apply(int32_t n, const float* off, const float* mean, const float* freq,
+                                                      const float* quat, const float* scale, float* omean,
+                                                      float* ofreq, float* oquat, float* oscale)
+{
+    const int32_t i = (int32_t)(blockIdx.x * 256u + threadIdx.x);
+    if (i >= n) return;
+    const float* d = off + (size_t)i * dmlp::kOut;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        omean[3 * (size_t)i + c] = mean[3 * (size_t)i + c] + d[c];
+        ofreq[3 * (size_t)i + c] = freq[3 * (size_t)i + c] + d[3 + c];
+        oscale[3 * (size_t)i + c] = scale[3 * (size_t)i + c] + d[10 + c];
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) oquat[4 * (size_t)i + c] = quat[4 * (size_t)i + c] + d[6 + c];
+}
+
 }  // namespace wipes
 
 using namespace wipes;
@@ -1010,6 +1030,21 @@ wipes_status wipes_deform_bwd(wipes_ctx* ctx, int32_t precision, const float* pa
     const hipError_t e = launch_deform_bwd((int32_t)n, mean, params, workspace, precision == WIPES_DEFORM_BF16X3,
                                            d_offsets, d_params, d_mean, (hipStream_t)stream);
     return e == hipSuccess ? WIPES_OK : hip_fail(ctx, e, "deform bwd");
+}
+
+wipes_status wipes_deform_apply(wipes_ctx* ctx, int64_t n, const float* offsets, const float* mean,
+                                const float* freq, const float* quat, const float* scale, float* out_mean,
+                                float* out_freq, float* out_quat, float* out_scale, void* stream)
+{
+    if (!ctx) return fail(nullptr, WIPES_ERR_INVALID, "ctx must not be NULL");
+    if (n < 0 || n >= (1ll << 31)) return fail(ctx, WIPES_ERR_INVALID, "n out of range");
+    if (n > 0 && (!offsets || !mean || !freq || !quat || !scale || !out_mean || !out_freq || !out_quat || !out_scale))
+        return fail(ctx, WIPES_ERR_INVALID, "every array must be set");
+    if (n > 0)
+        hipLaunchKernelGGL(k_deform_apply, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, (hipStream_t)stream,
+                           (int32_t)n, offsets, mean, freq, quat, scale, out_mean, out_freq, out_quat, out_scale);
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? WIPES_OK : hip_fail(ctx, e, "deform apply");
 }
 
 }  // extern "C"

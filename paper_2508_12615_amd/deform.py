@@ -20,14 +20,41 @@ def param_count() -> int:
     return B.wipes_deform_param_count()
 
 
-def apply_offsets(prims: dict, offsets: torch.Tensor) -> dict:
-    """Deformed primitive set: mean + dx, freq + df, quat + dq, scale + ds (differentiable in torch)."""
+_APPLY_KEYS = ("mean", "freq", "quat", "scale")
+
+
+def apply_offsets(net: "Deformation", prims: dict, offsets: torch.Tensor) -> dict:
+    """Deformed primitive set (wipes_deform_apply): mean + dx, freq + df, quat + dq, scale + ds; the other keys
+    are passed through.  Differentiable: the gradients of the deformed values flow to the offsets and to the
+    original values unchanged."""
     out = dict(prims)
-    out["mean"] = (prims["mean"] + offsets[:, 0:3]).contiguous()
-    out["freq"] = (prims["freq"] + offsets[:, 3:6]).contiguous()
-    out["quat"] = (prims["quat"] + offsets[:, 6:10]).contiguous()
-    out["scale"] = (prims["scale"] + offsets[:, 10:13]).contiguous()
+    vals = _ApplyFn.apply(net, offsets, *[prims[k] for k in _APPLY_KEYS])
+    for k, v in zip(_APPLY_KEYS, vals):
+        out[k] = v
     return out
+
+
+class _ApplyFn(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, net, offsets, mean, freq, quat, scale):
+        ins = [t.detach().to(torch.float32).contiguous() for t in (offsets, mean, freq, quat, scale)]
+        n = ins[1].shape[0]
+        if ins[0].shape != (n, N_OUT):
+            raise ValueError("offsets must be [n, 13]")
+        outs = [torch.empty_like(t) for t in ins[1:]]
+        B.wipes_deform_apply(net.ctx, n, *[t.data_ptr() for t in ins], *[t.data_ptr() for t in outs],
+                             torch.cuda.current_stream(net.device).cuda_stream)
+        return tuple(outs)
+
+    @staticmethod
+    def backward(ctx, gm, gf, gq, gs):
+        # the identity: the offsets' gradient is the four gradients side by side
+        parts = [g if g is not None else torch.zeros(0) for g in (gm, gf, gq, gs)]
+        n = next(g.shape[0] for g in parts if g.numel())
+        widths = (3, 3, 4, 3)
+        dev = next(g.device for g in parts if g.numel())
+        cols = [g if g.numel() else torch.zeros((n, w), device=dev) for g, w in zip(parts, widths)]
+        return (None, torch.cat(cols, dim=1), gm, gf, gq, gs)
 
 
 class Deformation:

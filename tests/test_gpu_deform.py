@@ -262,3 +262,27 @@ def test_full_size_sampled():
     _check_grads(dp, dm[rows], ref_dp, ref_dm, 1e-3, "full")
     others = np.setdiff1d(np.arange(n), rows)
     assert float(np.abs(dm[others]).max()) == 0.0
+
+
+def test_apply_exact_and_gradients_pass_through():
+    """wipes_deform_apply (Sec. 4.3: the offsets added to the primitive's parameters) against the oracle's
+    FP64 sums rounded to FP32 (exact: one FP32 addition), and its autograd passing gradients through."""
+    n = 777
+    prims = synth.scene_3d(n, 41)
+    off = np.random.default_rng(42).normal(0.0, 0.05, (n, D.N_OUT)).astype(np.float32)
+    ref = D.apply({k: prims[k] for k in ("mean", "freq", "quat", "scale")}, off)
+    net = GD.Deformation()
+    tp = {k: torch.from_numpy(prims[k]).cuda().requires_grad_(True) for k in ("mean", "freq", "quat", "scale")}
+    toff = torch.from_numpy(off).cuda().requires_grad_(True)
+    out = GD.apply_offsets(net, tp, toff)
+    for k in ("mean", "freq", "quat", "scale"):
+        assert np.array_equal(out[k].detach().cpu().numpy(), ref[k].astype(np.float32)), k
+    g = {k: torch.randn_like(out[k]) for k in ("mean", "freq", "quat", "scale")}
+    sum((out[k] * g[k]).sum() for k in g).backward()
+    for k in g:
+        assert torch.equal(tp[k].grad, g[k]), k
+    assert torch.equal(toff.grad, torch.cat([g["mean"], g["freq"], g["quat"], g["scale"]], dim=1))
+    # n = 0 and a missing array
+    B.wipes_deform_apply(net.ctx, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0)
+    with pytest.raises(RuntimeError, match="every array"):
+        B.wipes_deform_apply(net.ctx, 3, 0, 0, 0, 0, 0, 0, 0, 0, 0)
