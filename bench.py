@@ -394,7 +394,7 @@ def bench_deform(log, n=1_000_000, reps=10):
                 macs_per_primitive=DEFORM_MACS, roofline=roof, **res)
 
 
-def bench_serving(n_req, n_warm, log, budget=3 << 29):
+def bench_serving(n_req, n_warm, log, rates, budget=3 << 29):
     """8 resident scenes (0.1-2M primitives, linear motion), Poisson requests at 540p-1080p
     with seeded poses and times.  The plain rasterizer's capacity (one request at a time,
     synchronous) sets the arrival rate; at each offered load rho the library's continuously
@@ -416,6 +416,12 @@ def bench_serving(n_req, n_warm, log, budget=3 << 29):
     run_plain(rast, scenes, probe[:8], outs[:8])                     # warm-up
     lat, span = run_plain(rast, scenes, probe, outs)
     service_ms = span * 1e3 / len(probe)
+    # work per request (forward support pairs, wipes_render_stats) over 16 of the probe requests
+    pairs = []
+    for r in probe[:16]:
+        views = [dict(camera=r["camera"], prims=scenes[r["scene"]])]
+        pairs.append(rast.stats(views, rast.forward(views))["support_fwd"])
+    pairs_per_request = float(np.mean(pairs))
     srv = Server(max_slots=16, max_batch=8, persistent=2, hbm_budget_bytes=budget)
     ids = [srv.load_scene(sc) for sc in scenes]
     pct = lambda v, q: float(np.percentile(v, q))  # noqa: E731
@@ -447,10 +453,17 @@ def bench_serving(n_req, n_warm, log, budget=3 << 29):
                             runs[-1]["plain"]["p50_ms"], runs[-1]["plain"]["p99_ms"], runs[-1]["plain"]["frames_per_s"]))
     srv.close()
     sat = runs[-1]
+    # the saturated service against the blend forward's VALU roofline: the requests' support pairs at
+    # the per-pair cost, over the whole service time per request (projection, sort and admission
+    # included, so a lower bound on the blend kernel's own fraction)
+    roof = blend_roofline("alpha", "fwd", pairs_per_request, 1e3 / sat["served"]["frames_per_s"], rates,
+                          "served frames (whole service time)")
+    roof["support_pairs_per_request"] = pairs_per_request
+    roof["traffic"] = None   # the committed counters are the headline frame's, not the served batches
     return dict(workload="8 resident scenes of 0.1-2M wavelet primitives with linear motion, Poisson requests at "
                          "960x540-1920x1080; %d warm-up + %d measured requests per load; arena %d MiB" % (
                              n_warm, n_req, budget >> 20),
-                plain_service_ms=service_ms, loads=runs,
+                plain_service_ms=service_ms, loads=runs, roofline=roof,
                 saturated_served_over_plain=sat["served"]["frames_per_s"] / sat["plain"]["frames_per_s"])
 
 
@@ -684,7 +697,7 @@ def main():
     if "fit" in extras:
         out["fit_loop"] = bench_fit(a.fit_steps, log)
     if "serve" in extras:
-        out["serving"] = bench_serving(a.serve_requests, a.serve_warmup, log)
+        out["serving"] = bench_serving(a.serve_requests, a.serve_warmup, log, rates)
     if "deform" in extras:
         out["deform"] = bench_deform(log)
     if not a.no_cpu_baseline:
