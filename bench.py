@@ -558,6 +558,19 @@ def cpu_worker(kind):
             O.render_o2(P, r["camera"]["width"], r["camera"]["height"], scr, O.depth_keys(prims, ocam))
             t += time.perf_counter() - t0
         out = dict(seconds=t, requests=len(reqs))
+    elif kind == "deform":
+        import deform as D   # oracle/deform.py
+        rows = 20_000
+        params = synth.deform_params(D.layer_shapes(), 2024)
+        x = synth.scene_3d(rows, 2025)["mean"]
+        dout = np.random.default_rng(7).normal(0.0, 1.0, (rows, D.N_OUT))
+        D.backward(params, x, 0.625, dout)   # thread pool start and first-touch pages outside the timing
+        t0 = time.perf_counter()
+        D.forward(params, x, 0.625)
+        t1 = time.perf_counter()
+        D.backward(params, x, 0.625, dout)
+        t2 = time.perf_counter()
+        out = dict(fwd=t1 - t0, fwd_bwd=t2 - t1, rows=rows)
     print(json.dumps(out), flush=True)
 
 
@@ -588,6 +601,9 @@ def cpu_baseline(log):
     c4, _ = med("c4", nthreads, lambda d: d["seconds"] * d["pixels_all"] / d["pixels"])
     c5, _ = med("c5", nthreads, lambda d: d["seconds"] / d["requests"])
     log("cpu: c1 %.2f s, c2 %.2f s/step, c4 %.1f s, c5 %.2f s/request" % (c1, c2, c4, c5))
+    dfw, _ = med("deform", nthreads, lambda d: d["fwd"] / d["rows"])
+    dfb, _ = med("deform", nthreads, lambda d: d["fwd_bwd"] / d["rows"])
+    log("cpu: deform %.3g s/row forward, %.3g s/row forward + backward" % (dfw, dfb))
     return dict(value=1.0 / full, unit="frames/s", cores=nthreads, kind="oracle",
                 sample="full 1920x1080 frame, 1M primitives: FP64 projection, forward and backward "
                        "(support-scatter organisation of the oracle), median of 3 (%s s)" % ", ".join(
@@ -605,7 +621,10 @@ def cpu_baseline(log):
                              "70k-primitive fit (without the optimiser update)"),
                     batched=dict(value=64.0 / c4, unit="images/s", sample="8 of the 64 images fwd+L2+bwd, "
                                  "extrapolated by pixel count"),
-                    serving=dict(value=1.0 / c5, unit="frames/s", sample="forward of 4 served requests")))
+                    serving=dict(value=1.0 / c5, unit="frames/s", sample="forward of 4 served requests"),
+                    deform=dict(value=1.0 / dfw, unit="primitives/s (forward)", fwd_bwd=1.0 / dfb,
+                                sample="the FP64 network on 20k of the scene's primitives (numpy matrix products), "
+                                       "forward, and forward + backward")))
 
 
 # ---------------------------------------------------------------------- main
