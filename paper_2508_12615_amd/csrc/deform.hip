@@ -188,6 +188,32 @@ __host__ __device__ constexpr size_t save_col_h(int j) { return (size_t)dmlp::kI
 // per block; the backward reads these instead of the 64 KB hi plane of each h_j).
 __host__ __device__ constexpr size_t mask_words_per_block() { return (size_t)dmlp::kDepth * dmlp::kW * 4; }
 
+// Copy-out of a layer's 128 x 256 activations (or gradients) from LDS (row major, hi and lo arrays) to a
+// stored per-block array in the row-group order of cm(): chunk c (0 .. 8191) is 8 rows of one unit of one
+// plane -- r8 = c % 4, unit (c / 4) % 256, row group (c / 1024) % 4, plane c / 4096 -- read as 8 LDS
+// values and written as one 16-byte store, consecutive chunks contiguous in memory.  With mbytes the hi
+// plane's chunks also store their ReLU mask byte (bit i: row 8 r8 + i of the group is positive).
+constexpr int kCopyChunks = 2 * dmlp::kRB * dmlp::kW / 8;
+__device__ __forceinline__ void copy_chunk(int c, const __bf16* shi, const __bf16* slo, __bf16* dst,
+                                           size_t plane_stride, int ncols, int col0, uint8_t* mbytes)
+{
+    using namespace dmlp;
+    const int r8 = c & 3, u = (c >> 2) & (kW - 1), g = (c >> 10) & 3, p = c >> 12;
+    const int r0 = 32 * g + 8 * r8;
+    const __bf16* src = p ? slo : shi;
+    __bf16 v[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) v[i] = src[(r0 + i) * kAS + u];
+    const uint2 a = pack4(v), b = pack4(v + 4);
+    *reinterpret_cast<uint4*>(dst + (size_t)p * plane_stride + cm(col0 + u, r0, ncols)) = make_uint4(a.x, a.y, b.x, b.y);
+    if (mbytes && p == 0) {
+        uint32_t m = 0;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) m |= (float)v[i] > 0.0f ? 1u << i : 0u;
+        mbytes[u * 16 + g * 4 + r8] = (uint8_t)m;
+    }
+}
+
 template <bool SPLIT, bool KEEP>
 __global__ void __launch_bounds__(256, 1) k_deform_fwd(int32_t n, const float* __restrict__ mean, float t,
                                                        const __bf16* __restrict__ whi,
@@ -291,14 +317,25 @@ __global__ void __launch_bounds__(256, 1) k_deform_fwd(int32_t n, const float* _
         bf16x8 bh0[2], bl0[2], bh1[2], bl1[2];
         if (layer >= 1) {   // K over the hidden units: weight columns 0 .. 255
             // software pipeline: the fragments of step k + 1 are in flight during step k's
-            // products (the scheduling barriers keep the compiler from sinking them)
+            // products (the scheduling barriers keep the compiler from sinking them); the stored
+            // copy of this layer's input h_layer (and its ReLU mask bytes) goes out a few chunks per
+            // step, its stores overlapping the products
             bf16x8 ah0[4], al0[4], ah1[4], al1[4];
+            uint8_t* mb = KEEP ? reinterpret_cast<uint8_t*>(mask + mask_words_per_block() * blockIdx.x) +
+                                     (size_t)(layer - 1) * kW * 16
+                               : nullptr;
             load_b(0, bh0, bl0);
             load_a(0, ah0, al0);
 #pragma unroll 1
             for (int k = 0; k < kW; k += 32) {
                 load_b(k + 16, bh1, bl1);
                 load_a(k + 16, ah1, al1);
+                if (KEEP) {
+#pragma unroll
+                    for (int i = 0; i < kCopyChunks / 256 / (kW / 32); ++i)
+                        copy_chunk(tid + 256 * ((k / 32) * (kCopyChunks / 256 / (kW / 32)) + i), ahi, alo, sv,
+                                   (size_t)kSaveCols * kRB, kSaveCols, (int)save_col_h(layer), mb);
+                }
                 __builtin_amdgcn_sched_barrier(0);
                 step_h(ah0, al0, bh0, bl0);
                 __builtin_amdgcn_sched_barrier(0);
@@ -342,33 +379,20 @@ __global__ void __launch_bounds__(256, 1) k_deform_fwd(int32_t n, const float* _
         for (int q = 0; q < 2; ++q) {
             const int col = 64 * w + 32 * q + lr;
             const float bcol = bias[(size_t)layer * kW + col];
-            uint32_t mw[4];   // ReLU mask words of unit col (rows 32 bt .. + 31)
 #pragma unroll
             for (int bt = 0; bt < 4; ++bt) {
-                mw[bt] = 0u;
 #pragma unroll
                 for (int g = 0; g < 4; ++g) {
                     const int r = 32 * bt + 8 * g + 4 * hs;   // this lane's rows r .. r + 3
                     __bf16 hh[4], hl[4];
 #pragma unroll
                     for (int i = 0; i < 4; ++i) {
-                        const float z = acc[q][bt][4 * g + i] + bcol;
-                        if (KEEP) mw[bt] |= z > 0.0f ? 1u << (8 * g + 4 * hs + i) : 0u;
-                        split_bf16(fmaxf(z, 0.0f), hh[i], hl[i]);
+                        split_bf16(fmaxf(acc[q][bt][4 * g + i] + bcol, 0.0f), hh[i], hl[i]);
                         ahi[(r + i) * kAS + col] = hh[i];
                         alo[(r + i) * kAS + col] = hl[i];
                     }
-                    if (KEEP) {   // h_{layer+1}, four rows of unit col per plane
-                        const size_t so = cm((int)save_col_h(layer + 1) + col, r, kSaveCols);
-                        *reinterpret_cast<uint2*>(sv + so) = pack4(hh);
-                        *reinterpret_cast<uint2*>(sv + (size_t)kSaveCols * kRB + so) = pack4(hl);
-                    }
                 }
-                if (KEEP) mw[bt] |= (uint32_t)__shfl_xor((int)mw[bt], 32, kWave);   // the other four of each eight rows
             }
-            if (KEEP && hs == 0)
-                *reinterpret_cast<uint4*>(mask + mask_words_per_block() * blockIdx.x + ((size_t)layer * kW + col) * 4) =
-                    make_uint4(mw[0], mw[1], mw[2], mw[3]);
         }
         __syncthreads();   // the next layer reads the rows just written
     }
@@ -379,8 +403,17 @@ __global__ void __launch_bounds__(256, 1) k_deform_fwd(int32_t n, const float* _
         f32x16 acc;
 #pragma unroll
         for (int e = 0; e < 16; ++e) acc[e] = 0.0f;
+        uint8_t* mb = KEEP ? reinterpret_cast<uint8_t*>(mask + mask_words_per_block() * blockIdx.x) +
+                                 (size_t)(kDepth - 1) * kW * 16
+                           : nullptr;
 #pragma unroll 4
         for (int k = 0; k < kW; k += 16) {
+            if (KEEP) {   // the stored copy of h_8, two chunks per step
+#pragma unroll
+                for (int i = 0; i < kCopyChunks / 256 / (kW / 16); ++i)
+                    copy_chunk(tid + 256 * ((k / 16) * (kCopyChunks / 256 / (kW / 16)) + i), ahi, alo, sv,
+                               (size_t)kSaveCols * kRB, kSaveCols, (int)save_col_h(kDepth), mb);
+            }
             const int ao = (32 * w + lr) * kAS + k + lk;
             const bf16x8 ah = *reinterpret_cast<const bf16x8*>(ahi + ao);
             const bf16x8 bh = *reinterpret_cast<const bf16x8*>(wh + frag_at(0, k >> 4, kW / 16));
@@ -668,20 +701,9 @@ __global__ void __launch_bounds__(256, 1) k_deform_bwd_rows(int32_t n, const flo
             }
         }
         __syncthreads();
-        if (hpass) {
-            // dZ_{j-1} from LDS to its stored copy: 16-byte chunks (8 rows of one unit), consecutive
-            // threads on consecutive chunks; the stores overlap the next layer's products
-            __bf16* zo = dzb + dz_region(j - 1);
-            for (int c = tid; c < 2 * kRB * kW / 8; c += 256) {
-                const int r8 = c & 3, u = (c >> 2) & (kW - 1), g = (c >> 10) & 3, p = c >> 12;
-                const int r0 = 32 * g + 8 * r8;
-                const __bf16* src = p ? glo : ghi;
-                __bf16 v[8];
-#pragma unroll
-                for (int i = 0; i < 8; ++i) v[i] = src[(r0 + i) * kAS + u];
-                const uint2 a = pack4(v), b = pack4(v + 4);
-                *reinterpret_cast<uint4*>(zo + (size_t)p * kW * kRB + cm(u, r0, kW)) = make_uint4(a.x, a.y, b.x, b.y);
-            }
+        if (hpass) {   // dZ_{j-1} from LDS to its stored copy (16-byte chunks, contiguous over the workgroup)
+            for (int c = tid; c < kCopyChunks; c += 256)
+                copy_chunk(c, ghi, glo, dzb + dz_region(j - 1), (size_t)kW * kRB, kW, 0, nullptr);
         }
     }
     // dL/dmean: the encoding's derivative, FP32 with the forward's range reduction
