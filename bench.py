@@ -138,6 +138,47 @@ def blend_roofline(mode, kind, pairs, ms, rates, kernel):
                 frac_of_measured_fma_rate=ach / fma)
 
 
+def graph_step(r, images, dL, K, ref_image, steps, warmup):
+    """The same fwd + bwd step captured once as a hipGraph (wipes_graph_capture: project, bin/sort with
+    the instance count kept on the device, forward and backward blend, projection backward) and
+    replayed: no host synchronisation per step.  Capacity from the warm-up frame's instance count; the
+    replays must not overflow it and must render the plain step's image bit for bit."""
+    import torch
+    from paper_2508_12615_amd import binding as B
+    grads = [{k: torch.empty_like(v) for k, v in images[0]["prims"].items()}]
+    batch, keep, _ = r.make_batch(images, grads)
+    cap = int(K * 1.1) + 4096
+    sb, bb = B.wipes_workspace_size(r.params, batch, cap, True)
+    screen = torch.empty(sb, dtype=torch.uint8, device=r.device)
+    bins = torch.empty(bb, dtype=torch.uint8, device=r.device)
+    sbuf = B.wipes_buffer(screen.data_ptr(), sb, 0, 0, 0)
+    bbuf = B.wipes_buffer(bins.data_ptr(), bb, cap, 1, 0)
+    npx = ref_image.shape[0]
+    image = torch.empty((npx, 3), dtype=torch.float32, device=r.device)
+    T = torch.empty(npx, dtype=torch.float32, device=r.device)
+    last = torch.empty(npx, dtype=torch.int32, device=r.device)
+    g = B.wipes_graph_capture(r.ctx, r.params, batch, sbuf, bbuf, image.data_ptr(), T.data_ptr(), last.data_ptr(),
+                              None, dL.data_ptr(), True)
+    stream = torch.cuda.current_stream(r.device).cuda_stream
+    try:
+        for _ in range(warmup):
+            B.wipes_graph_launch(g, stream)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            B.wipes_graph_launch(g, stream)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        st, k2 = B.wipes_check_overflow(r.ctx, r.params, batch, sbuf)
+        if st != B.WIPES_OK or k2 != K:
+            raise RuntimeError("graph replay: instance count %d against %d (capacity %d)" % (k2, K, cap))
+        if not torch.equal(image, ref_image):
+            raise RuntimeError("graph replay renders a different image")
+    finally:
+        B.wipes_graph_destroy(g)
+    return ms
+
+
 def stage_profile(r, step, steps):
     """Mean ms per launch of every stage over `steps` calls of step(), from HIP events the library
     records around each stage on its stream."""
@@ -678,6 +719,8 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms_step = (t1 - t0) * 1e3 / a.steps
+    ms_graph = graph_step(r, images, dL, K, f.image, a.steps, a.warmup)
+    log("gpu: %.3f ms/step plain, %.3f ms/step as one graph replay" % (ms_step, ms_graph))
     # per-stage times from a second, separately run set of steps: the stage
     # events themselves cost a few microseconds of idle GPU each, so they stay
     # out of the timed steps above
@@ -704,7 +747,10 @@ def main():
                roofline=roof,
                step_roofline=dict(t_roof_ms=t_roof * 1e3, frac=t_roof * 1e3 / ms_step),
                stages_ms={k: round(v, 4) for k, v in stages.items()},
-               roofline_blend=roof_blend, measured_peaks=rates, work=stats)
+               roofline_blend=roof_blend, measured_peaks=rates, work=stats,
+               graph_replay=dict(ms_per_step=ms_graph, frames_per_s=1e3 / ms_graph,
+                                 note="the same step captured once as a hipGraph and replayed (no host "
+                                      "synchronisation per step); same image bit for bit"))
     log("gpu: %.3f ms/step, stages %s" % (ms_step, out["stages_ms"]))
     del prims, r
     torch.cuda.empty_cache()
