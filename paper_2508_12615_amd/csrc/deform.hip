@@ -971,24 +971,28 @@ hipError_t launch_deform_bwd(int32_t n, const float* mean, const float* params, 
     return hipGetLastError();
 }
 
-// The deformed primitive set: mean + dx, freq + df, quat + dq, scale + ds, one
-// thread per primitive (13 offsets in, 13 values out).
+// The deformed primitive set: mean + dx, freq + df, quat + dq, scale + ds.  One
+// thread per output value, over [mean 3n | freq 3n | quat 4n | scale 3n], so the
+// parameter arrays are read and written coalesced (the offsets' rows of 13 are
+// gathered, consecutive threads on neighbouring rows).
 // (no __restrict__: the outputs may alias the inputs)
 __global__ void __launch_bounds__(256) k_deform_apply(int32_t n, const float* off, const float* mean, const float* freq,
                                                       const float* quat, const float* scale, float* omean,
                                                       float* ofreq, float* oquat, float* oscale)
 {
-    const int32_t i = (int32_t)(blockIdx.x * 256u + threadIdx.x);
-    if (i >= n) return;
-    const float* d = off + (size_t)i * dmlp::kOut;
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        omean[3 * (size_t)i + c] = mean[3 * (size_t)i + c] + d[c];
-        ofreq[3 * (size_t)i + c] = freq[3 * (size_t)i + c] + d[3 + c];
-        oscale[3 * (size_t)i + c] = scale[3 * (size_t)i + c] + d[10 + c];
-    }
-#pragma unroll
-    for (int c = 0; c < 4; ++c) oquat[4 * (size_t)i + c] = quat[4 * (size_t)i + c] + d[6 + c];
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t n3 = 3 * (int64_t)n;
+    if (e >= 13 * (int64_t)n) return;
+    const float* src;
+    float* dst;
+    int64_t k;   // element within the array
+    int width, col0;
+    if (e < n3) { src = mean; dst = omean; k = e; width = 3; col0 = 0; }
+    else if (e < 2 * n3) { src = freq; dst = ofreq; k = e - n3; width = 3; col0 = 3; }
+    else if (e < 2 * n3 + 4 * (int64_t)n) { src = quat; dst = oquat; k = e - 2 * n3; width = 4; col0 = 6; }
+    else { src = scale; dst = oscale; k = e - 2 * n3 - 4 * (int64_t)n; width = 3; col0 = 10; }
+    const int64_t row = k / width;
+    dst[k] = src[k] + off[row * dmlp::kOut + col0 + (k - row * width)];
 }
 
 }  // namespace wipes
@@ -1063,7 +1067,7 @@ wipes_status wipes_deform_apply(wipes_ctx* ctx, int64_t n, const float* offsets,
     if (n > 0 && (!offsets || !mean || !freq || !quat || !scale || !out_mean || !out_freq || !out_quat || !out_scale))
         return fail(ctx, WIPES_ERR_INVALID, "every array must be set");
     if (n > 0)
-        hipLaunchKernelGGL(k_deform_apply, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, (hipStream_t)stream,
+        hipLaunchKernelGGL(k_deform_apply, dim3((unsigned)((13 * n + 255) / 256)), dim3(256), 0, (hipStream_t)stream,
                            (int32_t)n, offsets, mean, freq, quat, scale, out_mean, out_freq, out_quat, out_scale);
     const hipError_t e = hipGetLastError();
     return e == hipSuccess ? WIPES_OK : hip_fail(ctx, e, "deform apply");
