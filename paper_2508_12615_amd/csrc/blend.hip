@@ -323,8 +323,10 @@ __device__ __forceinline__ void fwd_block(const ImgDesc* __restrict__ descs, int
     const uint64_t below = (1ull << l) - 1ull;
     float C0 = 0.0f, C1 = 0.0f, C2 = 0.0f, T = 1.0f;
     int32_t lst = -1;
-    bool alive = valid;
-    PixBox live = block_box(__ballot(alive), bx, by);
+    // the block's pixels still transmitting, as a wave mask (scalar registers)
+    const uint64_t vm = __builtin_amdgcn_ballot_w64(valid);
+    uint64_t am = vm;
+    PixBox live = block_box(am, bx, by);
     const float thr2 = kp.q_add * kConicScale;
     const float lg2_amin = __builtin_amdgcn_logf(kp.alpha_min);
     unsigned long long* cm_row = cmask ? cmask + (size_t)blk * cmask_words : nullptr;
@@ -368,10 +370,7 @@ __device__ __forceinline__ void fwd_block(const ImgDesc* __restrict__ descs, int
                 const Staged S = stage[j];
                 const uint32_t bp = (uint32_t)__builtin_ctzll(rest);   // this entry's position - base
                 rest &= rest - 1ull;
-                // the colour is read with the rest of the record, not inside the
-                // branch below, so its LDS latency overlaps the evaluation
-                float cr = S.r, cg = S.g, cb = S.b;
-                asm volatile("" : "+v"(cr), "+v"(cg), "+v"(cb));
+                const float cr = S.r, cg = S.g, cb = S.b;
                 const PairEval p = eval_at(S.mrx, S.mry, S.c0, S.c1, S.c2, S.f0, S.f1, S.ph, lx, ly);
                 if constexpr (MODE == WIPES_2D_ADDITIVE) {
                     const bool in = p.e2 >= thr2;
@@ -379,25 +378,28 @@ __device__ __forceinline__ void fwd_block(const ImgDesc* __restrict__ descs, int
                     C0 = fmaf(S.r, w, C0);
                     C1 = fmaf(S.g, w, C1);
                     C2 = fmaf(S.b, w, C2);
-                    if (__ballot(in && valid)) contrib |= 1ull << bp;
+                    if (__builtin_amdgcn_ballot_w64(in) & vm) contrib |= 1ull << bp;
                     continue;
                 }
                 const float a = S.op * p.W;
-                const bool adds = alive && a >= kp.alpha_min;
+                // the pixels the pair adds to and the pixels it ends, as wave
+                // masks: lane conditions combined with AND stay in scalar
+                // registers instead of round trips through vector booleans
+                const uint64_t addm = am & __builtin_amdgcn_ballot_w64(a >= kp.alpha_min);
+                const bool adds = __builtin_amdgcn_inverse_ballot_w64(addm);
                 // branch-free: a pair that does not add gets alpha 0, for which
                 // the colour, T and `last` updates are exact identities
-                const float al = adds ? fminf(a, kp.alpha_max) : 0.0f;
+                const float al = adds ? __builtin_amdgcn_fmed3f(a, 0.0f, kp.alpha_max) : 0.0f;
                 const float wt = T * al;
                 C0 = fmaf(wt, cr, C0);
                 C1 = fmaf(wt, cg, C1);
                 C2 = fmaf(wt, cb, C2);
                 T = T * (1.0f - al);
                 lst = adds ? (int32_t)(base + bp) : lst;
-                const bool died = adds && T < kp.T_min;
-                alive = alive && !died;
-                if (__ballot(adds)) contrib |= 1ull << bp;
-                if (__ballot(died)) {
-                    const uint64_t am = __ballot(alive);
+                if (addm) contrib |= 1ull << bp;
+                const uint64_t diedm = addm & __builtin_amdgcn_ballot_w64(T < kp.T_min);
+                if (diedm) {
+                    am &= ~diedm;
                     if (am == 0ull) {
                         left = false;
                         break;
@@ -546,15 +548,21 @@ __device__ __forceinline__ int reduce12_index(int l)
 // mu', the conic and f' are linear in these sums with the primitive's own
 // conic and f' as coefficients (dL/dmu'x = -2 (ca S_qx + cb S_qy) - f'x S_phi,
 // dL/dcb = 2 S_qxy, ...), so the projection backward applies them once per
-// primitive instead of every pair paying for them.
+// primitive instead of every pair paying for them.  The same holds for the
+// factor -o/2 that dq and dphi share: with d = dL/d(o W') of the pair,
+// dL/dq = -o/2 W' d and dL/dphi = -o/2 E sin(phi) d (E the Gaussian factor,
+// W' = E (1 + cos phi) / 2), so the slots hold the sums without it (the
+// first seven values and the last) and the projection backward multiplies
+// them by -o/2.
 constexpr int kSlot = 12;
 
-// Per-pair gradient terms shared by both modes: dW = dL/dW' of the pair.
-__device__ __forceinline__ void pair_grads(float v[12], const PairEval& p, float dW)
+// Per-pair gradient terms shared by both modes: d = dL/d(o W') of the pair,
+// v[7] = W' d already set (the opacity term, which is also dq / (-o/2)).
+__device__ __forceinline__ void pair_grads(float v[12], const PairEval& p, float d)
 {
     const float sn = __builtin_amdgcn_sinf(__builtin_amdgcn_fractf(p.ph));
-    const float dq = dW * (-0.5f * p.W);             // dL/dq
-    const float dph = dW * (-0.5f * p.E * sn);       // dL/dphi (radians)
+    const float dq = v[7];                 // dL/dq / (-o/2)
+    const float dph = (p.E * sn) * d;      // dL/dphi (radians) / (-o/2)
     const float qx = dq * p.dx, qy = dq * p.dy;
     v[0] = qx;
     v[1] = qy;
@@ -722,7 +730,7 @@ __device__ __forceinline__ void bwd_tile(const ImgDesc* __restrict__ descs, int 
             const float a = S.op * p.W;
             const bool reach = on && (int32_t)(b + bp) <= lst;
             bool takes;
-            float dW;
+            float da;
             if constexpr (MODE == WIPES_2D_ADDITIVE) {
                 takes = reach && p.e2 >= thr2;
                 const float cg = S.r * g0 + S.g * g1 + S.b * g2;
@@ -730,8 +738,8 @@ __device__ __forceinline__ void bwd_tile(const ImgDesc* __restrict__ descs, int 
                 v[8] = ow * g0;
                 v[9] = ow * g1;
                 v[10] = ow * g2;
-                v[7] = takes ? p.W * cg : 0.0f;
-                dW = takes ? S.op * cg : 0.0f;
+                da = takes ? cg : 0.0f;
+                v[7] = p.W * da;
             } else {
                 takes = reach && a >= kp.alpha_min;
                 const float al = takes ? fminf(a, kp.alpha_max) : 0.0f;
@@ -747,13 +755,17 @@ __device__ __forceinline__ void bwd_tile(const ImgDesc* __restrict__ descs, int 
                 v[10] = wt * g2;
                 Sg = fmaf(al, cg - Sg, Sg);
                 T = Tb;
-                const float da = (takes && a <= kp.alpha_max) ? dal : 0.0f;
+                da = (takes && a <= kp.alpha_max) ? dal : 0.0f;
                 v[7] = p.W * da;
-                dW = S.op * da;
             }
-            pair_grads(v, p, dW);
+            pair_grads(v, p, da);
             // (a primitive no pixel takes reduces to exact zeros: every term has a zero factor)
-            const float tot = wave_reduce12_valu(v);
+            float tot = wave_reduce12_valu(v);
+            // the whole reduction runs with every lane on: left to itself the
+            // compiler moves its last DPP add under the store's lane mask,
+            // where the add can no longer read its neighbour in the same
+            // instruction (two extra moves per replay)
+            asm volatile("" : "+v"(tot));
             if (red_lane) mine[bp * kSlot + red_idx] = tot;
         };
         // back to front, two records a round in alternating registers: each
