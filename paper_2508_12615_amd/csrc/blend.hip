@@ -745,8 +745,9 @@ __device__ __forceinline__ void bwd_tile(const ImgDesc* __restrict__ descs, int 
                 const float al = takes ? fminf(a, kp.alpha_max) : 0.0f;
                 // T before this pair; the hardware reciprocal (1 ulp) keeps the
                 // recovery within a few ulp of the forward's T.  A pair that takes
-                // no part keeps T exactly (selected, not divided by 1).
-                const float Tb = takes ? T * __builtin_amdgcn_rcpf(1.0f - al) : T;
+                // no part has al = 0 and keeps T exactly: the reciprocal of 1 is
+                // exactly 1 (checked on the device), so no select is needed.
+                const float Tb = T * __builtin_amdgcn_rcpf(1.0f - al);
                 const float cg = S.r * g0 + S.g * g1 + S.b * g2;
                 const float dal = Tb * (cg - Sg);
                 const float wt = Tb * al;
