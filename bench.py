@@ -57,8 +57,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--prims", type=int, default=1_000_000)
     ap.add_argument("--tile", type=str, default="16x16")
-    ap.add_argument("--persistent", type=int, default=2,
-                    help="blend launch form: 0 grid, 1 persistent tile queue, 2 queue with longest lists first")
+    ap.add_argument("--persistent", type=int, default=3,
+                    help="blend launch form: 0 grid, 1 persistent tile queue, 2 queue with longest lists first, "
+                         "3 grid with longest lists first")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--extras", type=str, default="plain2d,batched,fit,serve,deform",
                     help="comma list of secondary workloads (plain2d, batched, fit, serve, deform) or none")
@@ -743,7 +744,7 @@ def main():
                data="synthetic",
                config=dict(workload="3D static view synthesis: %d wavelet primitives, %dx%d, alpha blending, "
                                     "fwd+bwd" % (a.prims, W, H), tile="%dx%d" % (tw, th),
-                           launch=("grid", "tile queue", "tile queue, longest first")[a.persistent], instances=K),
+                           launch=("grid", "tile queue", "tile queue, longest first", "grid, longest first")[a.persistent], instances=K),
                roofline=roof,
                step_roofline=dict(t_roof_ms=t_roof * 1e3, frac=t_roof * 1e3 / ms_step),
                stages_ms={k: round(v, 4) for k, v in stages.items()},

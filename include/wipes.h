@@ -87,8 +87,10 @@ typedef struct {
     int32_t freq_xform;   /* wipes_freq_xform */
     int32_t tile_w;       /* tile width in pixels: 8, 16 or 32 */
     int32_t tile_h;       /* tile height in pixels: 8 or 16; tile_w * tile_h in {64, 128, 256, 512} */
-    int32_t persistent;   /* 0: grid launch, a workgroup per tile; 1: persistent tile queue in
-                             tile order; 2: persistent queue, longest tile list first (default) */
+    int32_t persistent;   /* blend launch form: 0: grid launch, a workgroup per tile, in tile
+                             order; 1: persistent tile queue in tile order; 2: persistent queue,
+                             longest tile list first; 3: grid launch, longest tile list first
+                             (default).  Other values: WIPES_ERR_INVALID */
     float alpha_min;      /* 1/255: pairs with o W' below it are skipped (alpha) */
     float alpha_max;      /* 0.99: clamp of o W' (alpha) */
     float T_min;          /* 1e-4: termination threshold on transmittance (alpha) */
@@ -446,8 +448,9 @@ wipes_status wipes_adam(wipes_ctx* ctx, int32_t n_groups, const wipes_adam_group
 
 /* Candidates the autotuner tries, in the order of its times_ms output:
  * tile shapes 8x8, 16x8, 8x16, 16x16, 32x8, 32x16, each as a grid launch
- * (persistent 0), a persistent queue in tile order (1) and a persistent queue
- * longest list first (2).  Fills up to max entries; returns the count. */
+ * (persistent 0), a persistent queue in tile order (1), a persistent queue
+ * longest list first (2) and a grid launch longest list first (3).  Fills up
+ * to max entries; returns the count. */
 int32_t wipes_autotune_candidates(int32_t* tile_w, int32_t* tile_h, int32_t* persistent, int32_t max);
 
 /* Time the render path of this batch (project, bin/sort, forward, and the

@@ -86,6 +86,8 @@ wipes_status validate(wipes_ctx* ctx, const wipes_params* p, const wipes_batch* 
     if (p->sh_degree < -1 || p->sh_degree > 3) return fail(ctx, WIPES_ERR_INVALID, "sh_degree must be -1..3");
     if (p->sh_degree >= 0 && p->mode != WIPES_3D_ALPHA)
         return fail(ctx, WIPES_ERR_INVALID, "spherical-harmonic colour needs 3D mode");
+    if (p->persistent < 0 || p->persistent > 3)
+        return fail(ctx, WIPES_ERR_INVALID, "persistent must be 0..3 (blend launch form)");
     if (p->lds_batch != 0 && p->lds_batch != 64)
         return fail(ctx, WIPES_ERR_INVALID, "lds_batch must be 0 or 64 (the blend stages one 64-position word)");
     if (!tile_ok(p->tile_w, p->tile_h)) return fail(ctx, WIPES_ERR_INVALID, "unsupported tile %dx%d", p->tile_w, p->tile_h);
@@ -436,7 +438,7 @@ void wipes_params_default(int32_t mode, wipes_params* p)
     p->freq_xform = WIPES_FREQ_VECTOR;
     p->tile_w = 16;
     p->tile_h = 16;
-    p->persistent = 2;
+    p->persistent = 3;
     p->alpha_min = 1.0f / 255.0f;
     p->alpha_max = 0.99f;
     p->T_min = 1e-4f;

@@ -1,6 +1,6 @@
 // Autotuner: times the render path of a given batch for every supported tile
 // shape and launch form (grid; persistent queue in tile order; persistent
-// queue longest list first) and returns the fastest.  The per-pixel rule is
+// queue longest list first; grid longest list first) and returns the fastest.  The per-pixel rule is
 // tile-independent, so every candidate computes the same image (to FP32
 // rounding of tile-relative coordinates); only speed differs.  This is an
 // offline call: it allocates and frees its own scratch and synchronises.
@@ -21,7 +21,8 @@ struct Cand {
 
 const Cand kCands[] = {{8, 8, 0},  {16, 8, 0},  {8, 16, 0},  {16, 16, 0},  {32, 8, 0},  {32, 16, 0},
                        {8, 8, 1},  {16, 8, 1},  {8, 16, 1},  {16, 16, 1},  {32, 8, 1},  {32, 16, 1},
-                       {8, 8, 2},  {16, 8, 2},  {8, 16, 2},  {16, 16, 2},  {32, 8, 2},  {32, 16, 2}};
+                       {8, 8, 2},  {16, 8, 2},  {8, 16, 2},  {16, 16, 2},  {32, 8, 2},  {32, 16, 2},
+                       {8, 8, 3},  {16, 8, 3},  {8, 16, 3},  {16, 16, 3},  {32, 8, 3},  {32, 16, 3}};
 constexpr int kNCand = sizeof(kCands) / sizeof(kCands[0]);
 
 struct Scratch {

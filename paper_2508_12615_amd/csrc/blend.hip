@@ -435,6 +435,10 @@ __device__ __forceinline__ void fwd_block(const ImgDesc* __restrict__ descs, int
 // Grid form: one workgroup per tile, one wave per block.  Tiles map to
 // workgroups one to one, so the XCDs (which take workgroups round-robin)
 // share the heavy tiles of a cluster instead of one XCD taking a whole band.
+// With `order` (a permutation of the tiles, longest list first) workgroup i
+// takes tile order[i]: the hardware dispatcher, which starts workgroups in
+// index order as earlier ones retire, then hands out the heavy tiles first
+// with no queue atomics and no workgroup barrier between tiles.
 template <int MODE, int TW, int TH>
 __global__ void __launch_bounds__(TW * TH) k_blend_fwd(const ImgDesc* __restrict__ descs, int B, KParams kp,
                                                              const Rec* __restrict__ recs,
@@ -444,12 +448,12 @@ __global__ void __launch_bounds__(TW * TH) k_blend_fwd(const ImgDesc* __restrict
                                                              float* __restrict__ image, float* __restrict__ T_final,
                                                              int32_t* __restrict__ last,
                                                              unsigned long long* __restrict__ cmask,
-                                                             uint32_t cmask_words)
+                                                             uint32_t cmask_words, const uint32_t* __restrict__ order)
 {
     __shared__ Staged stage[(TW / 8) * (TH / 8)][kWave];
     if (*ovf) return;
-    const uint32_t t = blockIdx.x;
-    if (t >= n_tiles) return;
+    if (blockIdx.x >= n_tiles) return;
+    const uint32_t t = order ? order[blockIdx.x] : blockIdx.x;
     const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     fwd_block<MODE, TW, TH>(descs, B, kp, recs, vals, ranges, t, w, image, T_final, last, cmask, cmask_words,
                             stage[w]);
@@ -838,7 +842,7 @@ __global__ void __launch_bounds__(TW * TH) k_blend_bwd(const ImgDesc* __restrict
                                                              float* __restrict__ slots,
                                                              uint32_t* __restrict__ valid,
                                                              const unsigned long long* __restrict__ cmask,
-                                                             uint32_t cmask_words)
+                                                             uint32_t cmask_words, const uint32_t* __restrict__ order)
 {
     constexpr int NB = (TW / 8) * (TH / 8);
     __shared__ Staged stage[NB][kWave];
@@ -846,8 +850,8 @@ __global__ void __launch_bounds__(TW * TH) k_blend_bwd(const ImgDesc* __restrict
     __shared__ uint32_t top[NB];
     __shared__ uint64_t hitm[2 * NB];
     if (*ovf) return;
-    const uint32_t t = blockIdx.x;
-    if (t >= n_tiles) return;
+    if (blockIdx.x >= n_tiles) return;
+    const uint32_t t = order ? order[blockIdx.x] : blockIdx.x;
     bwd_tile<MODE, TW, TH>(descs, B, kp, recs, vals, pk, ranges, t, T_final, last, dLdC, slots, valid, cmask,
                            cmask_words, stage, part, top, hitm);
 }
@@ -978,7 +982,7 @@ static void launch_fwd_t(const ImgDesc* descs, int B, const KParams& kp, const R
     }
     if (n_tiles == 0) return;
     hipLaunchKernelGGL((k_blend_fwd<MODE, TW, TH>), dim3(n_tiles), dim3(TW * TH), 0, s, descs, B, kp, recs, vals,
-                       ranges, ovf, n_tiles, image, T_final, last, cmask, cmask_words);
+                       ranges, ovf, n_tiles, image, T_final, last, cmask, cmask_words, order);
 }
 
 template <int MODE, int TW, int TH>
@@ -998,7 +1002,7 @@ static void launch_bwd_t(const ImgDesc* descs, int B, const KParams& kp, const R
     }
     if (n_tiles == 0) return;
     hipLaunchKernelGGL((k_blend_bwd<MODE, TW, TH>), dim3(n_tiles), dim3(TW * TH), 0, s, descs, B, kp, recs, vals,
-                       pk, ranges, ovf, n_tiles, T_final, last, dLdC, slots, valid, cmask, cmask_words);
+                       pk, ranges, ovf, n_tiles, T_final, last, dLdC, slots, valid, cmask, cmask_words, order);
 }
 
 #define WIPES_TILE_DISPATCH(FN, MODE, ...)                                          \

@@ -69,7 +69,7 @@ static Views views(const Layout& L, const void* screen, const void* bins)
     return v;
 }
 
-// The longest-first tile order (persistent == 2), written by bin_sort_core.
+// The longest-first tile order (persistent 2 and 3), written by bin_sort_core.
 static const uint32_t* tile_order(const Layout& L, const Views& v)
 {
     (void)L;
@@ -169,7 +169,7 @@ wipes_status bin_sort_core(wipes_ctx* ctx, const wipes_params* p, const wipes_ba
     const uint32_t* skeys = in_b ? v.keys_b : v.keys_a;
     StageScope sc(ctx, kStRanges, s);
     HIP_TRY(launch_ranges(skeys, v.ctrl + kCtrlNEff, max_k, v.ranges, s), "ranges");
-    if (p->persistent == 2)   // longest tile list first for the persistent queue
+    if (p->persistent >= 2)   // longest tile list first (persistent queue or ordered grid)
         HIP_TRY(launch_tile_lpt_order(v.ranges, (uint32_t)L.tiles, (uint32_t*)((char*)bins + L.b_lpt), v.order, s),
                 "lpt order");
     return WIPES_OK;
@@ -185,8 +185,8 @@ wipes_status render_fwd_core(wipes_ctx* ctx, const wipes_params* p, const wipes_
     const uint32_t* svals = L.tile_result_b ? v.vals_b : v.vals_a;
     uint32_t* queue = nullptr;
     uint32_t pblocks = 0;
-    const uint32_t* order = p->persistent == 2 ? tile_order(L, v) : nullptr;
-    if (p->persistent) {
+    const uint32_t* order = p->persistent >= 2 ? tile_order(L, v) : nullptr;
+    if (p->persistent == 1 || p->persistent == 2) {
         queue = v.ctrl + kCtrlQueueFwd;
         pblocks = (uint32_t)ctx->n_cu * 8u;
     }
@@ -217,8 +217,8 @@ wipes_status render_bwd_core(wipes_ctx* ctx, const wipes_params* p, const wipes_
     const uint32_t* svals = L.tile_result_b ? v.vals_b : v.vals_a;
     uint32_t* queue = nullptr;
     uint32_t pblocks = 0;
-    const uint32_t* order = p->persistent == 2 ? tile_order(L, v) : nullptr;
-    if (p->persistent) {
+    const uint32_t* order = p->persistent >= 2 ? tile_order(L, v) : nullptr;
+    if (p->persistent == 1 || p->persistent == 2) {
         queue = v.ctrl + kCtrlQueueBwd;
         pblocks = (uint32_t)ctx->n_cu * 8u;
     }

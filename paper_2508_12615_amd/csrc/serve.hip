@@ -446,8 +446,9 @@ wipes_status wipes_serve_create(const wipes_serve_config* cfg, const wipes_param
     if (!cfg || !p || !out) return fail(nullptr, WIPES_ERR_INVALID, "config, params and out must be set");
     *out = nullptr;
     if (p->mode != WIPES_3D_ALPHA || cfg->max_slots < 1 || cfg->max_batch < 1 || cfg->max_pending < 1 ||
-        cfg->hbm_budget_bytes < (1 << 20))
-        return fail(nullptr, WIPES_ERR_INVALID, "serving needs alpha mode, positive limits and >= 1 MiB budget");
+        cfg->hbm_budget_bytes < (1 << 20) || cfg->persistent < 0 || cfg->persistent > 3)
+        return fail(nullptr, WIPES_ERR_INVALID,
+                    "serving needs alpha mode, positive limits, >= 1 MiB budget and a launch form 0..3");
     wipes_server* S = new wipes_server();
     S->cfg = *cfg;
     S->params = *p;

@@ -130,7 +130,7 @@ class BatchedFit:
     [offset_b, offset_b + n_b).
     """
 
-    def __init__(self, images, device=None, tile=(16, 16), persistent=2, cov: int = B.WIPES_COV_RS,
+    def __init__(self, images, device=None, tile=(16, 16), persistent=3, cov: int = B.WIPES_COV_RS,
                  capacity_margin: float = 1.3):
         self.device = torch.device(device) if device is not None else images[0]["target"].device
         self.rast = Rasterizer(B.WIPES_2D_ADDITIVE, device=self.device, cov=cov, tile_w=tile[0], tile_h=tile[1],

@@ -39,7 +39,7 @@ def test_every_declared_symbol_is_exported(B):
 
 def test_params_default(B):
     p = B.wipes_params_default(B.WIPES_3D_ALPHA)
-    assert (p.tile_w, p.tile_h, p.cov, p.persistent) == (16, 16, B.WIPES_COV_QUAT_SCALE, 2)
+    assert (p.tile_w, p.tile_h, p.cov, p.persistent) == (16, 16, B.WIPES_COV_QUAT_SCALE, 3)
     assert abs(p.alpha_min - 1 / 255) < 1e-9 and abs(p.alpha_max - 0.99) < 1e-7 and abs(p.T_min - 1e-4) < 1e-10
     assert abs(p.blur_eps - 0.3) < 1e-7 and p.q_add == 9.0
     q = B.wipes_params_default(B.WIPES_2D_ADDITIVE)
@@ -68,7 +68,7 @@ def test_workspace_size_grows_with_inputs(B):
 
 
 @pytest.mark.parametrize("bad", ["tile", "cov", "alpha", "size", "freq", "sh_degree", "sh_missing", "sh_2d",
-                                 "lds_batch"])
+                                 "lds_batch", "launch_form"])
 def test_validation_rejects_bad_arguments(B, bad):
     p = B.wipes_params_default(B.WIPES_3D_ALPHA if bad != "sh_2d" else B.WIPES_2D_ADDITIVE)
     b, keep = _batch(B, 10)
@@ -90,6 +90,8 @@ def test_validation_rejects_bad_arguments(B, bad):
         p.sh_degree = 0
     elif bad == "lds_batch":
         p.lds_batch = 128
+    elif bad == "launch_form":
+        p.persistent = 4
     sb, bb = C.c_size_t(), C.c_size_t()
     st = B.lib().wipes_workspace_size(C.byref(p), C.byref(b), 100, 0, C.byref(sb), C.byref(bb))
     assert st == B.WIPES_ERR_INVALID

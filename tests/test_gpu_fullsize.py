@@ -42,7 +42,7 @@ def _say(msg):
 
 
 def test_config3_full_frame_against_o2():
-    """1M primitives, 1920x1080, alpha, persistent longest-first queue (the benchmark's launch):
+    """1M primitives, 1920x1080, alpha, grid launch longest list first (the benchmark's launch):
     the full frame and all gradients against O2."""
     c = synth.config3()
     cam = c["camera"]

@@ -302,7 +302,7 @@ def test_tile_shape_and_launch_form_do_not_change_results(mode):
     base = None
     for tile in [(16, 16), (8, 8), (16, 8), (8, 16), (32, 8), (32, 16)]:
         same_tile = None
-        for persistent in (0, 1, 2):
+        for persistent in (0, 1, 2, 3):
             r = Rasterizer(mode, tile_w=tile[0], tile_h=tile[1], persistent=persistent)
             f = r.forward([dict(camera=cam, prims=tp)], with_backward=True)
             gr = r.backward([dict(camera=cam, prims=tp)], f, g)[0]
@@ -321,7 +321,7 @@ def test_tile_shape_and_launch_form_do_not_change_results(mode):
                 assert rel_err(out[1][k], base[1][k]) < 1e-4, (tile, persistent, k)
 
 
-@pytest.mark.parametrize("launch", [(16, 16, 0), (32, 16, 2), (8, 8, 1)])
+@pytest.mark.parametrize("launch", [(16, 16, 0), (32, 16, 2), (8, 8, 1), (8, 16, 3)])
 @pytest.mark.parametrize("mode", [B.WIPES_2D_ADDITIVE, B.WIPES_3D_ALPHA])
 def test_batched_equals_single(mode, launch):
     """Several images of different sizes rendered in one call give, bit for bit, the images and
