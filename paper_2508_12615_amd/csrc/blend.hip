@@ -667,38 +667,51 @@ __device__ __forceinline__ void bwd_tile(const ImgDesc* __restrict__ descs, int 
         const uint32_t lo = c0 - b, hb = min(c1 - 1u, (uint32_t)btop) - b;
         return cm_row[b >> 6] & ((~0ull >> (63u - hb)) & (~0ull << lo));
     };
+    // List entries are read for every lane, at positions clamped into the
+    // tile's list, so that they are in flight together with the chunk's
+    // contribution word instead of waiting for it; only the hit lanes' record
+    // loads depend on the word.
+    const uint32_t e1 = G.end - 1u;
     uint32_t c1 = hi, c0 = lo_of(hi);
+    const uint32_t p0 = vals[min((c0 & ~63u) + (uint32_t)l, e1)];
     uint64_t m = hits_of(c0, c1);
     Rec cur{};
-    if ((m >> l) & 1ull) cur = recs[vals[(c0 & ~63u) + (uint32_t)l]];
+    if ((m >> l) & 1ull) cur = recs[p0];
     // the next chunk's hits and list entries
     uint32_t n1 = c0, n0 = c0 > G.start ? lo_of(c0) : c0;
     uint64_t mn = c0 > G.start ? hits_of(n0, n1) : 0ull;
-    uint32_t pn = 0;
-    if ((mn >> l) & 1ull) pn = vals[(n0 & ~63u) + (uint32_t)l];
+    uint32_t pn = vals[min((n0 & ~63u) + (uint32_t)l, e1)];
     // The combine step gives four threads to each list position of the chunk
-    // (three slot values each), in CR rounds of NT / 4 positions; the
-    // positions' primitives (and, in one round, their packs) are loaded at
-    // the chunk's start and used after the replay.
+    // (three slot values each), in CR rounds of NT / 4 positions.  The
+    // positions' primitives are loaded a chunk ahead (in the previous chunk's
+    // prologue) and, in one round, their packs after the previous chunk's
+    // replay, so the combine finds both in registers.
     constexpr int CR = NT >= 4 * kWave ? 1 : (4 * kWave) / NT;
     constexpr uint32_t CP = (uint32_t)NT / 4u;
     const uint32_t co0 = (uint32_t)tid >> 2, cc3 = ((uint32_t)tid & 3u) * 3u;
     const int tcx = G.ox / TW, tcy = G.oy / TH;   // this tile in its image
+    auto combine_entries = [&](uint32_t lo, uint32_t hi1, bool (&cm)[CR], uint32_t (&cp)[CR]) {
+        const uint32_t bb = lo & ~63u;
+#pragma unroll
+        for (int r = 0; r < CR; ++r) {
+            const uint32_t co = co0 + (uint32_t)r * CP;
+            cm[r] = co < (uint32_t)kWave && bb + co >= lo && bb + co < hi1;
+            cp[r] = cm[r] ? vals[bb + co] : 0u;
+        }
+    };
+    bool cmine[CR];
+    uint32_t cprim[CR];
+    combine_entries(c0, c1, cmine, cprim);
+    PrimPack cq{};
+    if (CR == 1 && cmine[0]) cq = pk[cprim[0]];
     for (;;) {
         const uint32_t b = c0 & ~63u;
         float* pcur = part + (size_t)pbuf * (NB * kWave * kSlot);
         uint64_t* hcur = hitm + pbuf * NB;
         float* mine = pcur + (size_t)w * kWave * kSlot;
-        bool cmine[CR];
-        uint32_t cprim[CR];
-#pragma unroll
-        for (int r = 0; r < CR; ++r) {
-            const uint32_t co = co0 + (uint32_t)r * CP;
-            cmine[r] = co < (uint32_t)kWave && b + co >= c0 && b + co < c1;
-            cprim[r] = cmine[r] ? vals[b + co] : 0u;
-        }
-        PrimPack cq{};
-        if (CR == 1 && cmine[0]) cq = pk[cprim[0]];
+        bool cmine_n[CR] = {};
+        uint32_t cprim_n[CR] = {};
+        if (c0 > G.start) combine_entries(n0, n1, cmine_n, cprim_n);
         if ((m >> l) & 1ull) {
             st[__popcll(m & below)] = stage_fwd(cur, bx, by);
         } else {
@@ -716,7 +729,7 @@ __device__ __forceinline__ void bwd_tile(const ImgDesc* __restrict__ descs, int 
             if (n0 > G.start) {
                 nn0 = lo_of(n0);
                 mnn = hits_of(nn0, nn1);
-                if ((mnn >> l) & 1ull) pnn = vals[(nn0 & ~63u) + (uint32_t)l];
+                pnn = vals[min((nn0 & ~63u) + (uint32_t)l, e1)];
             }
         }
         if (l == 0) hcur[w] = m;
@@ -790,6 +803,8 @@ __device__ __forceinline__ void bwd_tile(const ImgDesc* __restrict__ descs, int 
             Sa = st[j > 1 ? j - 2 : 0];
             replay(Sb, top_pos());
         }
+        PrimPack cq_n{};
+        if (CR == 1 && cmine_n[0]) cq_n = pk[cprim_n[0]];
         __syncthreads();
         // positions some block staged get their slot written and marked
         uint64_t anyhit = 0ull;
@@ -818,6 +833,12 @@ __device__ __forceinline__ void bwd_tile(const ImgDesc* __restrict__ descs, int 
         }
         pbuf ^= 1u;
         if (!more) break;
+#pragma unroll
+        for (int r = 0; r < CR; ++r) {
+            cmine[r] = cmine_n[r];
+            cprim[r] = cprim_n[r];
+        }
+        cq = cq_n;
         cur = nx;
         m = mn;
         c1 = n1;
