@@ -394,7 +394,7 @@ __device__ __forceinline__ void fwd_block(const ImgDesc* __restrict__ descs, int
                 C0 = fmaf(wt, cr, C0);
                 C1 = fmaf(wt, cg, C1);
                 C2 = fmaf(wt, cb, C2);
-                T = T * (1.0f - al);
+                T = T - wt;   // T (1 - al)
                 lst = adds ? (int32_t)(base + bp) : lst;
                 if (addm) contrib |= 1ull << bp;
                 const uint64_t diedm = addm & __builtin_amdgcn_ballot_w64(T < kp.T_min);
