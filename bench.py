@@ -74,6 +74,8 @@ def parse():
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pmc_traffic_3d_1080p_1M_alpha.md")
+# blend launch forms (wipes_params.persistent)
+LAUNCH_NAMES = ("grid", "tile queue", "tile queue, longest first", "grid, longest first")
 
 
 def measured_traffic(kernel):
@@ -303,8 +305,7 @@ def bench_batched(rates, log):
     return dict(workload="64 uneven 2D fits (%d pixels, %d primitives) fwd+L2+bwd" % (npx, int(fit.offsets[-1])),
                 graph_ms=t_graph * 1e3, plain_ms=t_plain * 1e3, images_per_s_graph=64 / t_graph,
                 images_per_s_plain=64 / t_plain, speedup=t_plain / t_graph,
-                autotuned=dict(tile="%dx%d" % best[:2], launch=("grid", "tile queue", "tile queue, longest first")[
-                    best[2]], candidates_ms={"%dx%d/%d" % c: round(v, 3) for c, v in times.items()}),
+                autotuned=dict(tile="%dx%d" % best[:2], launch=LAUNCH_NAMES[best[2]], candidates_ms={"%dx%d/%d" % c: round(v, 3) for c, v in times.items()}),
                 stages_ms={k: round(v, 4) for k, v in st.items()},
                 roofline_blend={k: blend_roofline("add", k, stats["support_" + k], st["blend_" + k], rates,
                                                   "blend_" + k) for k in ("fwd", "bwd")},
@@ -464,7 +465,7 @@ def bench_serving(n_req, n_warm, log, rates, budget=3 << 29):
         views = [dict(camera=r["camera"], prims=scenes[r["scene"]])]
         pairs.append(rast.stats(views, rast.forward(views))["support_fwd"])
     pairs_per_request = float(np.mean(pairs))
-    srv = Server(max_slots=16, max_batch=8, persistent=2, hbm_budget_bytes=budget)
+    srv = Server(max_slots=16, max_batch=8, persistent=3, hbm_budget_bytes=budget)
     ids = [srv.load_scene(sc) for sc in scenes]
     pct = lambda v, q: float(np.percentile(v, q))  # noqa: E731
     runs = []
@@ -744,7 +745,7 @@ def main():
                data="synthetic",
                config=dict(workload="3D static view synthesis: %d wavelet primitives, %dx%d, alpha blending, "
                                     "fwd+bwd" % (a.prims, W, H), tile="%dx%d" % (tw, th),
-                           launch=("grid", "tile queue", "tile queue, longest first", "grid, longest first")[a.persistent], instances=K),
+                           launch=LAUNCH_NAMES[a.persistent], instances=K),
                roofline=roof,
                step_roofline=dict(t_roof_ms=t_roof * 1e3, frac=t_roof * 1e3 / ms_step),
                stages_ms={k: round(v, 4) for k, v in stages.items()},

@@ -23,7 +23,7 @@ def simulate(cfg: dict, t_arrive, footprint, prep_s, blend_s):
     """Host-only scheduler model (fake executor).  Returns dict of numpy arrays."""
     n = len(t_arrive)
     c = wipes_serve_config(int(cfg["max_slots"]), int(cfg["max_pending"]), int(cfg["max_batch"]),
-                           int(cfg.get("persistent", 1)), int(cfg["hbm_budget_bytes"]))
+                           int(cfg.get("persistent", 3)), int(cfg["hbm_budget_bytes"]))
     ta = np.ascontiguousarray(t_arrive, np.float64)
     fp = np.ascontiguousarray(footprint, np.int64)
     ps = np.ascontiguousarray(prep_s, np.float64)
@@ -43,7 +43,7 @@ class Server:
     """A wipes_server: load scenes, submit cameras, poll or drain, read stats."""
 
     def __init__(self, device: int = 0, max_slots: int = 16, max_pending: int = 4096, max_batch: int = 8,
-                 persistent: int = 1, hbm_budget_bytes: int = 4 << 30, **overrides):
+                 persistent: int = 3, hbm_budget_bytes: int = 4 << 30, **overrides):
         self.params = B.wipes_params_default(B.WIPES_3D_ALPHA)
         for k, v in overrides.items():
             if k == "bg":
