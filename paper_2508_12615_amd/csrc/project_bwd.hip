@@ -88,7 +88,11 @@ __device__ __forceinline__ int sh_poly(int deg, float ux, float uy, float uz, Po
     return 16;
 }
 
-__global__ void __launch_bounds__(256) k_project_bwd(const ImgDesc* __restrict__ descs_mem, int B, int32_t n_total,
+// Five waves per SIMD (at most 96 registers; left free the compiler takes
+// 101 and four fit): the kernel streams slots, parameters and gradients, and
+// the fifth wave hides more of that memory latency than the few registers it
+// costs (six waves spill and are slower).
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) k_project_bwd(const ImgDesc* __restrict__ descs_mem, int B, int32_t n_total,
                                                       KParams kp, const Rec* __restrict__ recs,
                                                       const uint32_t* __restrict__ count,
                                                       const uint32_t* __restrict__ off_id,
@@ -302,8 +306,10 @@ __global__ void __launch_bounds__(256) k_project_bwd(const ImgDesc* __restrict__
         M[1][k] = J11 * Rw[1][k] + J12 * Rw[2][k];
     }
     const real q0r = d.quat[4 * j], q1r = d.quat[4 * j + 1], q2r = d.quat[4 * j + 2], q3r = d.quat[4 * j + 3];
-    const real qn = sqrtf(q0r * q0r + q1r * q1r + q2r * q2r + q3r * q3r);
-    const real w = q0r / qn, x = q1r / qn, y = q2r / qn, z = q3r / qn;
+    // one reciprocal of |q| serves the normalisation and its derivative (a
+    // division costs about ten instructions, a multiply one)
+    const real iqn = 1.0f / sqrtf(q0r * q0r + q1r * q1r + q2r * q2r + q3r * q3r);
+    const real w = q0r * iqn, x = q1r * iqn, y = q2r * iqn, z = q3r * iqn;
     const real Rq[3][3] = {{1.0f - 2.0f * (y * y + z * z), 2.0f * (x * y - w * z), 2.0f * (x * z + w * y)},
                              {2.0f * (x * y + w * z), 1.0f - 2.0f * (x * x + z * z), 2.0f * (y * z - w * x)},
                              {2.0f * (x * z - w * y), 2.0f * (y * z + w * x), 1.0f - 2.0f * (x * x + y * y)}};
@@ -329,7 +335,7 @@ __global__ void __launch_bounds__(256) k_project_bwd(const ImgDesc* __restrict__
     // covector frequency: A = J3 W, f'3 = A^-T f, dL/df = A^-1 (dfp, 0),
     // dL/dA = -f'3 (dL/df)^T (rows 0-1 into dM; row 2 through t/|t| below)
     real dfw[3] = {0.0f, 0.0f, 0.0f}, dA2[3] = {0.0f, 0.0f, 0.0f};
-    const real tl = sqrtf(t[0] * t[0] + t[1] * t[1] + tz * tz);
+    const real tl = cov_f ? sqrtf(t[0] * t[0] + t[1] * t[1] + tz * tz) : 1.0f;   // |t|, covector path only
     if (cov_f) {
         real A[3][3];
         for (int k = 0; k < 3; ++k) {
@@ -384,10 +390,10 @@ __global__ void __launch_bounds__(256) k_project_bwd(const ImgDesc* __restrict__
         const real dz = 2.0f * (-2.0f * z * dR[0][0] - w * dR[0][1] + x * dR[0][2] + w * dR[1][0] -
                                  2.0f * z * dR[1][1] + y * dR[1][2] + x * dR[2][0] + y * dR[2][1]);
         const real dot = w * dw + x * dx + y * dy + z * dz;
-        d.g_quat[4 * j] = (float)((dw - w * dot) / qn);
-        d.g_quat[4 * j + 1] = (float)((dx - x * dot) / qn);
-        d.g_quat[4 * j + 2] = (float)((dy - y * dot) / qn);
-        d.g_quat[4 * j + 3] = (float)((dz - z * dot) / qn);
+        d.g_quat[4 * j] = (float)((dw - w * dot) * iqn);
+        d.g_quat[4 * j + 1] = (float)((dx - x * dot) * iqn);
+        d.g_quat[4 * j + 2] = (float)((dy - y * dot) * iqn);
+        d.g_quat[4 * j + 3] = (float)((dz - z * dot) * iqn);
     }
     if (d.g_freq)
         for (int k = 0; k < 3; ++k) d.g_freq[3 * j + k] = cov_f ? dfw[k] : (float)(M[0][k] * dfp[0] + M[1][k] * dfp[1]);
