@@ -362,14 +362,19 @@ __device__ __forceinline__ void fwd_block(const ImgDesc* __restrict__ descs, int
                 pn = vals[min(cn + (uint32_t)(kWave + l), e1)];
             }
             wave_lds_sync();
-            const int nh = __popcll(m);
             bool left = true;
             uint64_t contrib = 0;   // bit (pos & 63): the primitive at pos contributed to a pixel of the block
             uint64_t rest = m;      // staged positions not yet blended (bit = position - base)
-            for (int j = 0; j < nh; ++j) {
-                const Staged S = stage[j];
+            // the staged entries in order: the k-th set bit of the hit mask is
+            // stage[k]; the loop runs while bits are left (scalar work per
+            // step matters here: the SIMD's scalar issue is shared with the
+            // other waves of the block's CU)
+            const Staged* sp = stage;
+            while (rest) {
+                const Staged S = *sp++;
                 const uint32_t bp = (uint32_t)__builtin_ctzll(rest);   // this entry's position - base
-                rest &= rest - 1ull;
+                const uint64_t bit = 1ull << bp;
+                rest ^= bit;
                 const float cr = S.r, cg = S.g, cb = S.b;
                 const PairEval p = eval_at(S.mrx, S.mry, S.c0, S.c1, S.c2, S.f0, S.f1, S.ph, lx, ly);
                 if constexpr (MODE == WIPES_2D_ADDITIVE) {
@@ -378,7 +383,7 @@ __device__ __forceinline__ void fwd_block(const ImgDesc* __restrict__ descs, int
                     C0 = fmaf(S.r, w, C0);
                     C1 = fmaf(S.g, w, C1);
                     C2 = fmaf(S.b, w, C2);
-                    if (__builtin_amdgcn_ballot_w64(in) & vm) contrib |= 1ull << bp;
+                    if (__builtin_amdgcn_ballot_w64(in) & vm) contrib |= bit;
                     continue;
                 }
                 const float a = S.op * p.W;
@@ -396,15 +401,16 @@ __device__ __forceinline__ void fwd_block(const ImgDesc* __restrict__ descs, int
                 C2 = fmaf(wt, cb, C2);
                 T = T - wt;   // T (1 - al)
                 lst = adds ? (int32_t)(base + bp) : lst;
-                if (addm) contrib |= 1ull << bp;
+                contrib |= addm ? bit : 0ull;
                 const uint64_t diedm = addm & __builtin_amdgcn_ballot_w64(T < kp.T_min);
                 if (diedm) {
                     am &= ~diedm;
-                    if (am == 0ull) {
+                    if (am == 0ull) {   // every pixel has ended: no entry is left to blend
                         left = false;
-                        break;
+                        rest = 0ull;
+                    } else {
+                        live = block_box(am, bx, by);
                     }
-                    live = block_box(am, bx, by);
                 }
             }
             // a word can be shared with the neighbouring tile's list: OR, not store
