@@ -370,6 +370,7 @@ __device__ __forceinline__ void fwd_block(const ImgDesc* __restrict__ descs, int
             // step matters here: the SIMD's scalar issue is shared with the
             // other waves of the block's CU)
             const Staged* sp = stage;
+            const uint64_t am0 = am;
             while (rest) {
                 const Staged S = *sp++;
                 const uint32_t bp = (uint32_t)__builtin_ctzll(rest);   // this entry's position - base
@@ -408,11 +409,12 @@ __device__ __forceinline__ void fwd_block(const ImgDesc* __restrict__ descs, int
                     if (am == 0ull) {   // every pixel has ended: no entry is left to blend
                         left = false;
                         rest = 0ull;
-                    } else {
-                        live = block_box(am, bx, by);
                     }
                 }
             }
+            // the box of the pixels still transmitting, for the next chunk's
+            // prefilter: once per chunk, not at every pixel's end
+            if (left && am != am0) live = block_box(am, bx, by);
             // a word can be shared with the neighbouring tile's list: OR, not store
             if (cm_row && contrib && l == 0) atomicOr(cm_row + (base >> 6), (unsigned long long)contrib);
             if (!left || !more) break;
