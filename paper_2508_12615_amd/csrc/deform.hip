@@ -214,61 +214,71 @@ __device__ __forceinline__ void copy_chunk(int c, const __bf16* shi, const __bf1
     }
 }
 
-template <bool SPLIT, bool KEEP>
-__global__ void __launch_bounds__(256, 1) k_deform_fwd(int32_t n, const float* __restrict__ mean, float t,
+// RB rows per workgroup: 128 (one workgroup per CU, the layout the stored
+// forward uses) or 64 (two workgroups per CU, so that one's epilogue and LDS
+// traffic overlap the other's products; the forward without storage).
+template <bool SPLIT, bool KEEP, int RB>
+__global__ void __launch_bounds__(256, 128 / RB) k_deform_fwd(int32_t n, const float* __restrict__ mean, float t,
                                                        const __bf16* __restrict__ whi,
                                                        const __bf16* __restrict__ wlo,
                                                        const float* __restrict__ bias, float* __restrict__ delta,
                                                        __bf16* __restrict__ save, uint32_t* __restrict__ mask)
 {
     using namespace dmlp;
-    __shared__ __attribute__((aligned(16))) __bf16 ahi[kRB * kAS];
-    __shared__ __attribute__((aligned(16))) __bf16 alo[kRB * kAS];
+    static_assert(RB == 128 || RB == 64, "64 or 128 rows per workgroup");
+    static_assert(!KEEP || RB == kRB, "the stored forward uses the backward's block of kRB rows");
+    constexpr int RT = RB / 32;    // row tiles (each wave: all of them, for its 64 units)
+    constexpr int RPT = RB / 16;   // encoding rows per thread and stage
+    __shared__ __attribute__((aligned(16))) __bf16 ahi[RB * kAS];
+    __shared__ __attribute__((aligned(16))) __bf16 alo[RB * kAS];
     // encoding columns 16 s .. 16 s + 15 of every row, two stages; the block's positions
-    __shared__ __attribute__((aligned(16))) __bf16 ehi[2][kRB * kES];
-    __shared__ __attribute__((aligned(16))) __bf16 elo[2][kRB * kES];
-    __shared__ float xs[kRB * 3];
+    __shared__ __attribute__((aligned(16))) __bf16 ehi[2][RB * kES];
+    __shared__ __attribute__((aligned(16))) __bf16 elo[2][RB * kES];
+    __shared__ float xs[RB * 3];
     const int tid = (int)threadIdx.x, w = tid >> 6, l = tid & 63;
     // lane roles in v_mfma_f32_32x32x16_bf16: A row / B column = l % 32, K run 8 (l / 32) .. + 7;
     // result element e of a lane: column l % 32, row 8 (e / 4) + 4 (l / 32) + e % 4
     const int lr = l & 31, lk = (l >> 5) * 8, hs = l >> 5;
-    const int32_t row0 = (int32_t)blockIdx.x * kRB;
+    const int32_t row0 = (int32_t)blockIdx.x * RB;
     __bf16* sv = KEEP ? save + save_block(blockIdx.x) : nullptr;
-    for (int q = tid; q < kRB * 3; q += 256)
+    for (int q = tid; q < RB * 3; q += 256)
         xs[q] = row0 + q / 3 < n ? mean[3 * (size_t)row0 + q] : 0.0f;
     __syncthreads();
     // Encoding columns 16 s .. + 15 into stage b, computed once for the workgroup: thread t takes
-    // column 16 s + t / 16 (uniform over 16 lanes) for rows 8 (t % 16) .. + 7; in layer 0 it also
-    // stores them for the backward (eight consecutive rows of one column: 16 bytes per plane).
+    // column 16 s + t / 16 (uniform over 16 lanes) for rows RPT (t % 16) .. + RPT - 1; in layer 0 of
+    // the stored forward it also stores them for the backward (eight consecutive rows of one
+    // column: 16 bytes per plane).
     auto enc_stage = [&](int st, int b, bool store) __attribute__((always_inline)) {
-        const int jj = tid >> 4, r0 = 8 * (tid & 15), j = 16 * st + jj;
-        __bf16 eh[8], el[8];
+        const int jj = tid >> 4, r0 = RPT * (tid & 15), j = 16 * st + jj;
+        __bf16 eh[RPT], el[RPT];
 #pragma unroll
-        for (int i = 0; i < 8; ++i) {
+        for (int i = 0; i < RPT; ++i) {
             const float x3[3] = {xs[3 * (r0 + i)], xs[3 * (r0 + i) + 1], xs[3 * (r0 + i) + 2]};
             const float v = j < kIn ? encode_entry(j, x3, t) : 0.0f;
             split_bf16(v, eh[i], el[i]);
             ehi[b][(r0 + i) * kES + jj] = eh[i];
             elo[b][(r0 + i) * kES + jj] = el[i];
         }
-        if (store) {
-            const uint4 hv = make_uint4(pack4(eh).x, pack4(eh).y, pack4(eh + 4).x, pack4(eh + 4).y);
-            const uint4 lv = make_uint4(pack4(el).x, pack4(el).y, pack4(el + 4).x, pack4(el + 4).y);
-            *reinterpret_cast<uint4*>(sv + cm(j, r0, kSaveCols)) = hv;
-            *reinterpret_cast<uint4*>(sv + (size_t)kSaveCols * kRB + cm(j, r0, kSaveCols)) = lv;
+        if constexpr (KEEP) {
+            if (store) {
+                const uint4 hv = make_uint4(pack4(eh).x, pack4(eh).y, pack4(eh + 4).x, pack4(eh + 4).y);
+                const uint4 lv = make_uint4(pack4(el).x, pack4(el).y, pack4(el + 4).x, pack4(el + 4).y);
+                *reinterpret_cast<uint4*>(sv + cm(j, r0, kSaveCols)) = hv;
+                *reinterpret_cast<uint4*>(sv + (size_t)kSaveCols * kRB + cm(j, r0, kSaveCols)) = lv;
+            }
         }
     };
-    // hidden layers: this wave's units 64 w .. 64 w + 63 (two tiles) for the four row tiles
+    // hidden layers: this wave's units 64 w .. 64 w + 63 (two tiles) for the RT row tiles
     for (int layer = 0; layer < kDepth; ++layer) {
         const int klen = dlayer(layer).klen;
         const int nks = klen / 16;
         const __bf16* wh = whi + dw_off(layer) + 8 * l;
         const __bf16* wl = wlo + dw_off(layer) + 8 * l;
-        f32x16 acc[2][4];
+        f32x16 acc[2][RT];
 #pragma unroll
         for (int q = 0; q < 2; ++q)
 #pragma unroll
-            for (int bt = 0; bt < 4; ++bt)
+            for (int bt = 0; bt < RT; ++bt)
 #pragma unroll
                 for (int e = 0; e < 16; ++e) acc[q][bt][e] = 0.0f;
         // weight fragments of K step k (weight column k) are loaded one step ahead of their products
@@ -292,23 +302,23 @@ __global__ void __launch_bounds__(256, 1) k_deform_fwd(int32_t n, const float* _
             }
         };
         // activation fragments of K step k (LDS), and one K step's products
-        auto load_a = [&](int k, bf16x8(&ah)[4], bf16x8(&al)[4]) __attribute__((always_inline)) {
+        auto load_a = [&](int k, bf16x8(&ah)[RT], bf16x8(&al)[RT]) __attribute__((always_inline)) {
 #pragma unroll
-            for (int bt = 0; bt < 4; ++bt) {
+            for (int bt = 0; bt < RT; ++bt) {
                 const int ao = (32 * bt + lr) * kAS + k + lk;
                 ah[bt] = *reinterpret_cast<const bf16x8*>(ahi + ao);
                 if (SPLIT) al[bt] = *reinterpret_cast<const bf16x8*>(alo + ao);
             }
         };
-        auto step_h = [&](const bf16x8(&ah)[4], const bf16x8(&al)[4], const bf16x8(&bh)[2], const bf16x8(&bl)[2])
+        auto step_h = [&](const bf16x8(&ah)[RT], const bf16x8(&al)[RT], const bf16x8(&bh)[2], const bf16x8(&bl)[2])
             __attribute__((always_inline)) {
 #pragma unroll
-            for (int bt = 0; bt < 4; ++bt) mma(bt, ah[bt], al[bt], bh, bl);
+            for (int bt = 0; bt < RT; ++bt) mma(bt, ah[bt], al[bt], bh, bl);
         };
         // one K step over the encoding (fragments from stage b)
         auto step_e = [&](int b, const bf16x8(&bh)[2], const bf16x8(&bl)[2]) __attribute__((always_inline)) {
 #pragma unroll
-            for (int bt = 0; bt < 4; ++bt) {
+            for (int bt = 0; bt < RT; ++bt) {
                 const int eo2 = (32 * bt + lr) * kES + lk;
                 mma(bt, *reinterpret_cast<const bf16x8*>(&ehi[b][eo2]), *reinterpret_cast<const bf16x8*>(&elo[b][eo2]),
                     bh, bl);
@@ -320,7 +330,7 @@ __global__ void __launch_bounds__(256, 1) k_deform_fwd(int32_t n, const float* _
             // products (the scheduling barriers keep the compiler from sinking them); the stored
             // copy of this layer's input h_layer (and its ReLU mask bytes) goes out a few chunks per
             // step, its stores overlapping the products
-            bf16x8 ah0[4], al0[4], ah1[4], al1[4];
+            bf16x8 ah0[RT], al0[RT], ah1[RT], al1[RT];
             uint8_t* mb = KEEP ? reinterpret_cast<uint8_t*>(mask + mask_words_per_block() * blockIdx.x) +
                                      (size_t)(layer - 1) * kW * 16
                                : nullptr;
@@ -330,7 +340,7 @@ __global__ void __launch_bounds__(256, 1) k_deform_fwd(int32_t n, const float* _
             for (int k = 0; k < kW; k += 32) {
                 load_b(k + 16, bh1, bl1);
                 load_a(k + 16, ah1, al1);
-                if (KEEP) {
+                if constexpr (KEEP) {
 #pragma unroll
                     for (int i = 0; i < kCopyChunks / 256 / (kW / 32); ++i)
                         copy_chunk(tid + 256 * ((k / 32) * (kCopyChunks / 256 / (kW / 32)) + i), ahi, alo, sv,
@@ -380,7 +390,7 @@ __global__ void __launch_bounds__(256, 1) k_deform_fwd(int32_t n, const float* _
             const int col = 64 * w + 32 * q + lr;
             const float bcol = bias[(size_t)layer * kW + col];
 #pragma unroll
-            for (int bt = 0; bt < 4; ++bt) {
+            for (int bt = 0; bt < RT; ++bt) {
 #pragma unroll
                 for (int g = 0; g < 4; ++g) {
                     const int r = 32 * bt + 8 * g + 4 * hs;   // this lane's rows r .. r + 3
@@ -396,7 +406,8 @@ __global__ void __launch_bounds__(256, 1) k_deform_fwd(int32_t n, const float* _
         }
         __syncthreads();   // the next layer reads the rows just written
     }
-    // output layer: units 0..31 (13 real) of row tile w, K over the 256 hidden units
+    // output layer: units 0..31 (13 real) of row tile w, K over the 256 hidden units (waves
+    // past the block's row tiles only help store h_8)
     {
         const __bf16* wh = whi + dw_off(kDepth) + 8 * l;
         const __bf16* wl = wlo + dw_off(kDepth) + 8 * l;
@@ -408,12 +419,13 @@ __global__ void __launch_bounds__(256, 1) k_deform_fwd(int32_t n, const float* _
                            : nullptr;
 #pragma unroll 4
         for (int k = 0; k < kW; k += 16) {
-            if (KEEP) {   // the stored copy of h_8, two chunks per step
+            if constexpr (KEEP) {   // the stored copy of h_8, two chunks per step
 #pragma unroll
                 for (int i = 0; i < kCopyChunks / 256 / (kW / 16); ++i)
                     copy_chunk(tid + 256 * ((k / 16) * (kCopyChunks / 256 / (kW / 16)) + i), ahi, alo, sv,
                                (size_t)kSaveCols * kRB, kSaveCols, (int)save_col_h(kDepth), mb);
             }
+            if (w >= RT) continue;   // wave-uniform
             const int ao = (32 * w + lr) * kAS + k + lk;
             const bf16x8 ah = *reinterpret_cast<const bf16x8*>(ahi + ao);
             const bf16x8 bh = *reinterpret_cast<const bf16x8*>(wh + frag_at(0, k >> 4, kW / 16));
@@ -426,10 +438,12 @@ __global__ void __launch_bounds__(256, 1) k_deform_fwd(int32_t n, const float* _
             }
         }
         const float bcol = bias[(size_t)kDepth * kW + lr];
+        if (w < RT) {
 #pragma unroll
-        for (int e = 0; e < 16; ++e) {
-            const int32_t p = row0 + 32 * w + 8 * (e >> 2) + 4 * hs + (e & 3);
-            if (lr < kOut && p < n) delta[(size_t)p * kOut + lr] = acc[e] + bcol;
+            for (int e = 0; e < 16; ++e) {
+                const int32_t p = row0 + 32 * w + 8 * (e >> 2) + 4 * hs + (e & 3);
+                if (lr < kOut && p < n) delta[(size_t)p * kOut + lr] = acc[e] + bcol;
+            }
         }
     }
 }
@@ -451,21 +465,21 @@ hipError_t launch_deform_fwd(int32_t n, const float* mean, float t, const float*
     hipLaunchKernelGGL(k_deform_split, dim3((unsigned)((dw_total() + 255) / 256)), dim3(256), 0, s, params, whi,
                        wlo, bias);
     if (n > 0) {
-        const dim3 grid((unsigned)((n + kRB - 1) / kRB));
+        const dim3 grid((unsigned)((n + kRB - 1) / kRB)), grid64((unsigned)((n + 63) / 64));
         __bf16* sv = (__bf16*)save;
         uint32_t* mk = save ? save_masks(sv, n) : nullptr;
         if (split && save)
-            hipLaunchKernelGGL((k_deform_fwd<true, true>), grid, dim3(256), 0, s, n, mean, t, whi, wlo, bias, delta, sv,
-                               mk);
+            hipLaunchKernelGGL((k_deform_fwd<true, true, kRB>), grid, dim3(256), 0, s, n, mean, t, whi, wlo, bias,
+                               delta, sv, mk);
         else if (split)
-            hipLaunchKernelGGL((k_deform_fwd<true, false>), grid, dim3(256), 0, s, n, mean, t, whi, wlo, bias, delta,
-                               sv, mk);
+            hipLaunchKernelGGL((k_deform_fwd<true, false, 64>), grid64, dim3(256), 0, s, n, mean, t, whi, wlo, bias,
+                               delta, sv, mk);
         else if (save)
-            hipLaunchKernelGGL((k_deform_fwd<false, true>), grid, dim3(256), 0, s, n, mean, t, whi, wlo, bias, delta,
-                               sv, mk);
+            hipLaunchKernelGGL((k_deform_fwd<false, true, kRB>), grid, dim3(256), 0, s, n, mean, t, whi, wlo, bias,
+                               delta, sv, mk);
         else
-            hipLaunchKernelGGL((k_deform_fwd<false, false>), grid, dim3(256), 0, s, n, mean, t, whi, wlo, bias, delta,
-                               sv, mk);
+            hipLaunchKernelGGL((k_deform_fwd<false, false, 64>), grid64, dim3(256), 0, s, n, mean, t, whi, wlo, bias,
+                               delta, sv, mk);
     }
     return hipGetLastError();
 }
