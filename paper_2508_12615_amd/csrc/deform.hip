@@ -188,35 +188,43 @@ __host__ __device__ constexpr size_t save_col_h(int j) { return (size_t)dmlp::kI
 // per block; the backward reads these instead of the 64 KB hi plane of each h_j).
 __host__ __device__ constexpr size_t mask_words_per_block() { return (size_t)dmlp::kDepth * dmlp::kW * 4; }
 
-// Copy-out of a layer's 128 x 256 activations (or gradients) from LDS (row major, hi and lo arrays) to a
-// stored per-block array in the row-group order of cm(): chunk c (0 .. 8191) is 8 rows of one unit of one
-// plane -- r8 = c % 4, unit (c / 4) % 256, row group (c / 1024) % 4, plane c / 4096 -- read as 8 LDS
-// values and written as one 16-byte store, consecutive chunks contiguous in memory.  With mbytes the hi
+// Copy-out of a layer's RB x 256 activations (or gradients) from LDS (row major, hi and lo arrays) to a
+// stored per-block array of 128-row blocks in the row-group order of cm(), the RB rows starting at row
+// rb of the block: chunk c (0 .. 2 RB 256 / 8 - 1) is 8 rows of one unit of one plane -- r8 = c % 4,
+// unit (c / 4) % 256, row group (c / 1024) % (RB / 32), plane c / (256 RB / 8) -- read as 8 LDS values
+// and written as one 16-byte store, consecutive chunks contiguous in memory.  With mbytes the hi
 // plane's chunks also store their ReLU mask byte (bit i: row 8 r8 + i of the group is positive).
-constexpr int kCopyChunks = 2 * dmlp::kRB * dmlp::kW / 8;
+template <int RB>
+constexpr int copy_chunks() { return 2 * RB * dmlp::kW / 8; }
+constexpr int kCopyChunks = copy_chunks<dmlp::kRB>();
+template <int RB = dmlp::kRB>
 __device__ __forceinline__ void copy_chunk(int c, const __bf16* shi, const __bf16* slo, __bf16* dst,
-                                           size_t plane_stride, int ncols, int col0, uint8_t* mbytes)
+                                           size_t plane_stride, int ncols, int col0, uint8_t* mbytes, int rb = 0)
 {
     using namespace dmlp;
-    const int r8 = c & 3, u = (c >> 2) & (kW - 1), g = (c >> 10) & 3, p = c >> 12;
+    constexpr int GB = RB / 32, PS = RB == 128 ? 12 : 11;   // row groups; chunks per plane = 1 << PS
+    static_assert((1 << PS) == RB * kW / 8, "chunks per plane");
+    const int r8 = c & 3, u = (c >> 2) & (kW - 1), g = (c >> 10) & (GB - 1), p = c >> PS;
     const int r0 = 32 * g + 8 * r8;
     const __bf16* src = p ? slo : shi;
     __bf16 v[8];
 #pragma unroll
     for (int i = 0; i < 8; ++i) v[i] = src[(r0 + i) * kAS + u];
     const uint2 a = pack4(v), b = pack4(v + 4);
-    *reinterpret_cast<uint4*>(dst + (size_t)p * plane_stride + cm(col0 + u, r0, ncols)) = make_uint4(a.x, a.y, b.x, b.y);
+    *reinterpret_cast<uint4*>(dst + (size_t)p * plane_stride + cm(col0 + u, rb + r0, ncols)) =
+        make_uint4(a.x, a.y, b.x, b.y);
     if (mbytes && p == 0) {
         uint32_t m = 0;
 #pragma unroll
         for (int i = 0; i < 8; ++i) m |= (float)v[i] > 0.0f ? 1u << i : 0u;
-        mbytes[u * 16 + g * 4 + r8] = (uint8_t)m;
+        mbytes[u * 16 + (rb / 32 + g) * 4 + r8] = (uint8_t)m;
     }
 }
 
-// RB rows per workgroup: 128 (one workgroup per CU, the layout the stored
-// forward uses) or 64 (two workgroups per CU, so that one's epilogue and LDS
-// traffic overlap the other's products; the forward without storage).
+// RB rows per workgroup: 128 (one workgroup per CU) or 64 (two workgroups
+// per CU, so that one's epilogue and LDS traffic overlap the other's
+// products).  The stored forward writes the backward's blocks of 128 rows:
+// with RB = 64 workgroup 2 b + h fills rows 64 h .. 64 h + 63 of block b.
 template <bool SPLIT, bool KEEP, int RB>
 __global__ void __launch_bounds__(256, 128 / RB) k_deform_fwd(int32_t n, const float* __restrict__ mean, float t,
                                                        const __bf16* __restrict__ whi,
@@ -226,7 +234,7 @@ __global__ void __launch_bounds__(256, 128 / RB) k_deform_fwd(int32_t n, const f
 {
     using namespace dmlp;
     static_assert(RB == 128 || RB == 64, "64 or 128 rows per workgroup");
-    static_assert(!KEEP || RB == kRB, "the stored forward uses the backward's block of kRB rows");
+    static_assert(kRB == 128, "stored blocks of 128 rows");
     constexpr int RT = RB / 32;    // row tiles (each wave: all of them, for its 64 units)
     constexpr int RPT = RB / 16;   // encoding rows per thread and stage
     __shared__ __attribute__((aligned(16))) __bf16 ahi[RB * kAS];
@@ -240,7 +248,9 @@ __global__ void __launch_bounds__(256, 128 / RB) k_deform_fwd(int32_t n, const f
     // result element e of a lane: column l % 32, row 8 (e / 4) + 4 (l / 32) + e % 4
     const int lr = l & 31, lk = (l >> 5) * 8, hs = l >> 5;
     const int32_t row0 = (int32_t)blockIdx.x * RB;
-    __bf16* sv = KEEP ? save + save_block(blockIdx.x) : nullptr;
+    const uint32_t sblk = blockIdx.x / (kRB / RB);          // the stored block
+    const int rb = RB == kRB ? 0 : 64 * (blockIdx.x & 1);   // this workgroup's first row in it
+    __bf16* sv = KEEP ? save + save_block(sblk) : nullptr;
     for (int q = tid; q < RB * 3; q += 256)
         xs[q] = row0 + q / 3 < n ? mean[3 * (size_t)row0 + q] : 0.0f;
     __syncthreads();
@@ -261,10 +271,15 @@ __global__ void __launch_bounds__(256, 128 / RB) k_deform_fwd(int32_t n, const f
         }
         if constexpr (KEEP) {
             if (store) {
-                const uint4 hv = make_uint4(pack4(eh).x, pack4(eh).y, pack4(eh + 4).x, pack4(eh + 4).y);
-                const uint4 lv = make_uint4(pack4(el).x, pack4(el).y, pack4(el + 4).x, pack4(el + 4).y);
-                *reinterpret_cast<uint4*>(sv + cm(j, r0, kSaveCols)) = hv;
-                *reinterpret_cast<uint4*>(sv + (size_t)kSaveCols * kRB + cm(j, r0, kSaveCols)) = lv;
+                if constexpr (RPT == 8) {
+                    const uint4 hv = make_uint4(pack4(eh).x, pack4(eh).y, pack4(eh + 4).x, pack4(eh + 4).y);
+                    const uint4 lv = make_uint4(pack4(el).x, pack4(el).y, pack4(el + 4).x, pack4(el + 4).y);
+                    *reinterpret_cast<uint4*>(sv + cm(j, rb + r0, kSaveCols)) = hv;
+                    *reinterpret_cast<uint4*>(sv + (size_t)kSaveCols * kRB + cm(j, rb + r0, kSaveCols)) = lv;
+                } else {   // four consecutive rows of one column: 8 bytes per plane
+                    *reinterpret_cast<uint2*>(sv + cm(j, rb + r0, kSaveCols)) = pack4(eh);
+                    *reinterpret_cast<uint2*>(sv + (size_t)kSaveCols * kRB + cm(j, rb + r0, kSaveCols)) = pack4(el);
+                }
             }
         }
     };
@@ -331,7 +346,7 @@ __global__ void __launch_bounds__(256, 128 / RB) k_deform_fwd(int32_t n, const f
             // copy of this layer's input h_layer (and its ReLU mask bytes) goes out a few chunks per
             // step, its stores overlapping the products
             bf16x8 ah0[RT], al0[RT], ah1[RT], al1[RT];
-            uint8_t* mb = KEEP ? reinterpret_cast<uint8_t*>(mask + mask_words_per_block() * blockIdx.x) +
+            uint8_t* mb = KEEP ? reinterpret_cast<uint8_t*>(mask + mask_words_per_block() * sblk) +
                                      (size_t)(layer - 1) * kW * 16
                                : nullptr;
             load_b(0, bh0, bl0);
@@ -341,10 +356,11 @@ __global__ void __launch_bounds__(256, 128 / RB) k_deform_fwd(int32_t n, const f
                 load_b(k + 16, bh1, bl1);
                 load_a(k + 16, ah1, al1);
                 if constexpr (KEEP) {
+                    constexpr int CPS = copy_chunks<RB>() / 256 / (kW / 32);   // chunks per thread and step
 #pragma unroll
-                    for (int i = 0; i < kCopyChunks / 256 / (kW / 32); ++i)
-                        copy_chunk(tid + 256 * ((k / 32) * (kCopyChunks / 256 / (kW / 32)) + i), ahi, alo, sv,
-                                   (size_t)kSaveCols * kRB, kSaveCols, (int)save_col_h(layer), mb);
+                    for (int i = 0; i < CPS; ++i)
+                        copy_chunk<RB>(tid + 256 * ((k / 32) * CPS + i), ahi, alo, sv, (size_t)kSaveCols * kRB,
+                                       kSaveCols, (int)save_col_h(layer), mb, rb);
                 }
                 __builtin_amdgcn_sched_barrier(0);
                 step_h(ah0, al0, bh0, bl0);
@@ -414,16 +430,17 @@ __global__ void __launch_bounds__(256, 128 / RB) k_deform_fwd(int32_t n, const f
         f32x16 acc;
 #pragma unroll
         for (int e = 0; e < 16; ++e) acc[e] = 0.0f;
-        uint8_t* mb = KEEP ? reinterpret_cast<uint8_t*>(mask + mask_words_per_block() * blockIdx.x) +
+        uint8_t* mb = KEEP ? reinterpret_cast<uint8_t*>(mask + mask_words_per_block() * sblk) +
                                  (size_t)(kDepth - 1) * kW * 16
                            : nullptr;
 #pragma unroll 4
         for (int k = 0; k < kW; k += 16) {
-            if constexpr (KEEP) {   // the stored copy of h_8, two chunks per step
+            if constexpr (KEEP) {   // the stored copy of h_8, a few chunks per step
+                constexpr int CPS = copy_chunks<RB>() / 256 / (kW / 16);
 #pragma unroll
-                for (int i = 0; i < kCopyChunks / 256 / (kW / 16); ++i)
-                    copy_chunk(tid + 256 * ((k / 16) * (kCopyChunks / 256 / (kW / 16)) + i), ahi, alo, sv,
-                               (size_t)kSaveCols * kRB, kSaveCols, (int)save_col_h(kDepth), mb);
+                for (int i = 0; i < CPS; ++i)
+                    copy_chunk<RB>(tid + 256 * ((k / 16) * CPS + i), ahi, alo, sv, (size_t)kSaveCols * kRB,
+                                   kSaveCols, (int)save_col_h(kDepth), mb, rb);
             }
             if (w >= RT) continue;   // wave-uniform
             const int ao = (32 * w + lr) * kAS + k + lk;
@@ -465,18 +482,19 @@ hipError_t launch_deform_fwd(int32_t n, const float* mean, float t, const float*
     hipLaunchKernelGGL(k_deform_split, dim3((unsigned)((dw_total() + 255) / 256)), dim3(256), 0, s, params, whi,
                        wlo, bias);
     if (n > 0) {
-        const dim3 grid((unsigned)((n + kRB - 1) / kRB)), grid64((unsigned)((n + 63) / 64));
+        // the stored forward fills whole blocks of 128 rows (the backward reads every row of a block)
+        const dim3 grid64((unsigned)((n + 63) / 64)), grid64k((unsigned)(2 * ((n + kRB - 1) / kRB)));
         __bf16* sv = (__bf16*)save;
         uint32_t* mk = save ? save_masks(sv, n) : nullptr;
         if (split && save)
-            hipLaunchKernelGGL((k_deform_fwd<true, true, kRB>), grid, dim3(256), 0, s, n, mean, t, whi, wlo, bias,
+            hipLaunchKernelGGL((k_deform_fwd<true, true, 64>), grid64k, dim3(256), 0, s, n, mean, t, whi, wlo, bias,
                                delta, sv, mk);
         else if (split)
             hipLaunchKernelGGL((k_deform_fwd<true, false, 64>), grid64, dim3(256), 0, s, n, mean, t, whi, wlo, bias,
                                delta, sv, mk);
         else if (save)
-            hipLaunchKernelGGL((k_deform_fwd<false, true, kRB>), grid, dim3(256), 0, s, n, mean, t, whi, wlo, bias,
-                               delta, sv, mk);
+            hipLaunchKernelGGL((k_deform_fwd<false, true, 64>), grid64k, dim3(256), 0, s, n, mean, t, whi, wlo,
+                               bias, delta, sv, mk);
         else
             hipLaunchKernelGGL((k_deform_fwd<false, false, 64>), grid64, dim3(256), 0, s, n, mean, t, whi, wlo, bias,
                                delta, sv, mk);
