@@ -553,8 +553,11 @@ __host__ __device__ constexpr size_t dz_cols_total() { return (size_t)dmlp::kDep
 __host__ __device__ inline size_t dz_region(int j) { return (size_t)j * dmlp::kW * 2 * dmlp::kRB; }
 __host__ __device__ constexpr int dz_units(int j) { return j == dmlp::kDepth ? dmlp::kOutPad : dmlp::kW; }
 
-template <bool SPLIT>
-__global__ void __launch_bounds__(256, 1) k_deform_bwd_rows(int32_t n, const float* __restrict__ mean,
+// RB = 64: two workgroups per CU; workgroup 2 b + h takes rows 64 h .. 64 h
+// + 63 of the 128-row block b (its stored inputs, masks and dZ), and keeps
+// bias partials of its own.
+template <bool SPLIT, int RB>
+__global__ void __launch_bounds__(256, 128 / RB) k_deform_bwd_rows(int32_t n, const float* __restrict__ mean,
                                                             const float* __restrict__ ddelta,
                                                             const __bf16* __restrict__ thi,
                                                             const __bf16* __restrict__ tlo,
@@ -563,29 +566,32 @@ __global__ void __launch_bounds__(256, 1) k_deform_bwd_rows(int32_t n, const flo
                                                             const uint32_t* __restrict__ mask)
 {
     using namespace dmlp;
-    __shared__ __attribute__((aligned(16))) __bf16 ghi[kRB * kAS];
-    __shared__ __attribute__((aligned(16))) __bf16 glo[kRB * kAS];
+    static_assert(RB == 128 || RB == 64, "64 or 128 rows per workgroup");
+    constexpr int RT = RB / 32;
+    __shared__ __attribute__((aligned(16))) __bf16 ghi[RB * kAS];
+    __shared__ __attribute__((aligned(16))) __bf16 glo[RB * kAS];
     const int tid = (int)threadIdx.x, w = tid >> 6, l = tid & 63;
     const int lr = l & 31, lk = (l >> 5) * 8, hs = l >> 5;
-    const size_t blk = blockIdx.x;
-    const int32_t row0 = (int32_t)blk * kRB;
+    const size_t blk = blockIdx.x / (kRB / RB);              // the 128-row block
+    const int rb = RB == kRB ? 0 : 64 * (blockIdx.x & 1);    // this workgroup's first row in it
+    const int32_t row0 = (int32_t)blockIdx.x * RB;
     __bf16* dzb = dz + blk * dz_cols_total() * 2 * kRB;
-    float* dbb = dbp + blk * (kDepth + 1) * kW;
+    float* dbb = dbp + (size_t)blockIdx.x * (kDepth + 1) * kW;
     // dZ_8 = dL/d offsets (13 of 32 units; rows past n are zero), in LDS and stored
-    for (int q = tid; q < kRB * kOutPad; q += 256) {
-        const int r = q % kRB, c = q / kRB;
+    for (int q = tid; q < RB * kOutPad; q += 256) {
+        const int r = q % RB, c = q / RB;
         const int32_t p = row0 + r;
         const float v = (c < kOut && p < n) ? ddelta[(size_t)p * kOut + c] : 0.0f;
         __bf16 h, o;
         split_bf16(v, h, o);
         ghi[r * kAS + c] = h;
         glo[r * kAS + c] = o;
-        dzb[dz_region(kDepth) + cm(c, r, kOutPad)] = h;
-        dzb[dz_region(kDepth) + (size_t)kOutPad * kRB + cm(c, r, kOutPad)] = o;
+        dzb[dz_region(kDepth) + cm(c, rb + r, kOutPad)] = h;
+        dzb[dz_region(kDepth) + (size_t)kOutPad * kRB + cm(c, rb + r, kOutPad)] = o;
     }
     if (tid < kOutPad) {   // bias gradient of the output layer: column sums of dZ_8, row order
         float s = 0.0f;
-        for (int r = 0; r < kRB; ++r) {
+        for (int r = 0; r < RB; ++r) {
             const int32_t p = row0 + r;
             s += (tid < kOut && p < n) ? ddelta[(size_t)p * kOut + tid] : 0.0f;
         }
@@ -599,19 +605,27 @@ __global__ void __launch_bounds__(256, 1) k_deform_bwd_rows(int32_t n, const flo
         const bool hpass = j >= 1;                            // input units 0..255 are hidden units
         const bool epass = (j == 0 || j == kSkip) && w < 3;   // encoding inputs: 3 tiles of 32
         const int eo = j == 0 ? 0 : kW;                       // their first row in WT_j
-        // the ReLU mask words of h_j for this lane's two units, in flight during the products
-        uint4 mk[2];
+        // the ReLU mask words of h_j for this lane's two units (one per row tile of this
+        // workgroup), in flight during the products
+        uint32_t mk[2][RT];
         if (hpass) {
 #pragma unroll
-            for (int q = 0; q < 2; ++q)
-                mk[q] = *reinterpret_cast<const uint4*>(mask + mask_words_per_block() * blk +
-                                                        ((size_t)(j - 1) * kW + 64 * w + 32 * q + lr) * 4);
+            for (int q = 0; q < 2; ++q) {
+                const uint32_t* mw = mask + mask_words_per_block() * blk + ((size_t)(j - 1) * kW + 64 * w + 32 * q + lr) * 4;
+                if constexpr (RT == 4) {
+                    const uint4 v = *reinterpret_cast<const uint4*>(mw);
+                    mk[q][0] = v.x; mk[q][1] = v.y; mk[q][2] = v.z; mk[q][3] = v.w;
+                } else {
+                    const uint2 v = *reinterpret_cast<const uint2*>(mw + rb / 32);
+                    mk[q][0] = v.x; mk[q][1] = v.y;
+                }
+            }
         }
         // encoding inputs first: the skip layer's part goes to scratch, and layer 0's is added to
         // it by the same lanes (same elements); the position gradient reads the sum
-        f32x16 acce[4];
+        f32x16 acce[RT];
 #pragma unroll
-        for (int bt = 0; bt < 4; ++bt)
+        for (int bt = 0; bt < RT; ++bt)
 #pragma unroll
             for (int e = 0; e < 16; ++e) acce[bt][e] = 0.0f;
         if (epass) {
@@ -622,7 +636,7 @@ __global__ void __launch_bounds__(256, 1) k_deform_bwd_rows(int32_t n, const flo
             };
             auto step_e = [&](int k, const bf16x8& bh, const bf16x8& bl) __attribute__((always_inline)) {
 #pragma unroll
-                for (int bt = 0; bt < 4; ++bt) {
+                for (int bt = 0; bt < RT; ++bt) {
                     const int ao = (32 * bt + lr) * kAS + k + lk;
                     const bf16x8 ah = *reinterpret_cast<const bf16x8*>(ghi + ao);
                     acce[bt] = mfma(ah, bh, acce[bt]);
@@ -643,7 +657,7 @@ __global__ void __launch_bounds__(256, 1) k_deform_bwd_rows(int32_t n, const flo
             }
             const int u = 32 * w + lr;
 #pragma unroll
-            for (int bt = 0; bt < 4; ++bt)
+            for (int bt = 0; bt < RT; ++bt)
 #pragma unroll
                 for (int e = 0; e < 16; ++e) {
                     const int r = 32 * bt + 8 * (e >> 2) + 4 * hs + (e & 3);
@@ -651,9 +665,9 @@ __global__ void __launch_bounds__(256, 1) k_deform_bwd_rows(int32_t n, const flo
                     if (u < kInPad) *sc = j == kSkip ? acce[bt][e] : acce[bt][e] + *sc;
                 }
         }
-        f32x16 acc[2][4];
+        f32x16 acc[2][RT];
 #pragma unroll
-        for (int bt = 0; bt < 4; ++bt)
+        for (int bt = 0; bt < RT; ++bt)
 #pragma unroll
             for (int e = 0; e < 16; ++e) acc[0][bt][e] = acc[1][bt][e] = 0.0f;
         if (hpass) {
@@ -665,18 +679,18 @@ __global__ void __launch_bounds__(256, 1) k_deform_bwd_rows(int32_t n, const flo
                     if (SPLIT) bl[q] = *reinterpret_cast<const bf16x8*>(tl + wo);
                 }
             };
-            auto load_a = [&](int k, bf16x8(&ah)[4], bf16x8(&al)[4]) __attribute__((always_inline)) {
+            auto load_a = [&](int k, bf16x8(&ah)[RT], bf16x8(&al)[RT]) __attribute__((always_inline)) {
 #pragma unroll
-                for (int bt = 0; bt < 4; ++bt) {
+                for (int bt = 0; bt < RT; ++bt) {
                     const int ao = (32 * bt + lr) * kAS + k + lk;
                     ah[bt] = *reinterpret_cast<const bf16x8*>(ghi + ao);
                     if (SPLIT) al[bt] = *reinterpret_cast<const bf16x8*>(glo + ao);
                 }
             };
-            auto step_h = [&](const bf16x8(&ah)[4], const bf16x8(&al)[4], const bf16x8(&bh)[2],
+            auto step_h = [&](const bf16x8(&ah)[RT], const bf16x8(&al)[RT], const bf16x8(&bh)[2],
                               const bf16x8(&bl)[2]) __attribute__((always_inline)) {
 #pragma unroll
-                for (int bt = 0; bt < 4; ++bt) {
+                for (int bt = 0; bt < RT; ++bt) {
 #pragma unroll
                     for (int q = 0; q < 2; ++q) {
                         acc[q][bt] = mfma(ah[bt], bh[q], acc[q][bt]);
@@ -688,7 +702,7 @@ __global__ void __launch_bounds__(256, 1) k_deform_bwd_rows(int32_t n, const flo
                 }
             };
             // software pipeline as in the forward
-            bf16x8 bh0[2], bl0[2], bh1[2], bl1[2], ah0[4], al0[4], ah1[4], al1[4];
+            bf16x8 bh0[2], bl0[2], bh1[2], bl1[2], ah0[RT], al0[RT], ah1[RT], al1[RT];
             load_h(0, bh0, bl0);
             load_a(0, ah0, al0);
 #pragma unroll 1
@@ -715,8 +729,8 @@ __global__ void __launch_bounds__(256, 1) k_deform_bwd_rows(int32_t n, const flo
                 const int u = 64 * w + 32 * q + lr;
                 float cs = 0.0f;
 #pragma unroll
-                for (int bt = 0; bt < 4; ++bt) {
-                    const uint32_t mw = bt == 0 ? mk[q].x : bt == 1 ? mk[q].y : bt == 2 ? mk[q].z : mk[q].w;
+                for (int bt = 0; bt < RT; ++bt) {
+                    const uint32_t mw = mk[q][bt];
 #pragma unroll
                     for (int g = 0; g < 4; ++g) {
                         const int r = 32 * bt + 8 * g + 4 * hs;
@@ -734,13 +748,13 @@ __global__ void __launch_bounds__(256, 1) k_deform_bwd_rows(int32_t n, const flo
         }
         __syncthreads();
         if (hpass) {   // dZ_{j-1} from LDS to its stored copy (16-byte chunks, contiguous over the workgroup)
-            for (int c = tid; c < kCopyChunks; c += 256)
-                copy_chunk(c, ghi, glo, dzb + dz_region(j - 1), (size_t)kW * kRB, kW, 0, nullptr);
+            for (int c = tid; c < copy_chunks<RB>(); c += 256)
+                copy_chunk<RB>(c, ghi, glo, dzb + dz_region(j - 1), (size_t)kW * kRB, kW, 0, nullptr, rb);
         }
     }
     // dL/dmean: the encoding's derivative, FP32 with the forward's range reduction
     const float* des = de_scr + (size_t)row0 * kInPad;   // written by this workgroup before the last barrier
-    for (int q = tid; q < kRB * 3; q += 256) {
+    for (int q = tid; q < RB * 3; q += 256) {
         const int r = q / 3, c = q % 3;
         const int32_t p = row0 + r;
         if (p >= n) continue;
@@ -937,7 +951,7 @@ size_t deform_save_bytes(int64_t n)
     return up256(save_block((size_t)blocks) * sizeof(__bf16) + (size_t)blocks * mask_words_per_block() * 4);
 }
 
-// Backward scratch: WT | dZ per block | bias partials per block | encoding
+// Backward scratch: WT | dZ per block | bias partials per half block | encoding
 // gradient of the skip layer | bias partials per chunk | weight partials per chunk.
 struct BwdScratch {
     size_t wt, dz, dbp, de, bpart, part, total;
@@ -953,7 +967,7 @@ static BwdScratch bwd_scratch(int64_t n)
     s.wt = 0;
     s.dz = s.wt + up256(dwt_total() * 2 * sizeof(__bf16));
     s.dbp = s.dz + up256((size_t)blocks * dz_cols_total() * 2 * kRB * sizeof(__bf16));
-    s.de = s.dbp + up256((size_t)blocks * (kDepth + 1) * kW * sizeof(float));
+    s.de = s.dbp + up256((size_t)2 * blocks * (kDepth + 1) * kW * sizeof(float));   // per 64-row workgroup
     s.bpart = s.de + up256((size_t)blocks * kRB * kInPad * sizeof(float));
     s.part = s.bpart + up256((size_t)chunks * (kDepth + 1) * kW * sizeof(float));
     s.total = s.part + up256((size_t)chunks * dw_total() * sizeof(float));
@@ -983,19 +997,21 @@ hipError_t launch_deform_bwd(int32_t n, const float* mean, const float* params, 
     hipLaunchKernelGGL(k_deform_splitT, dim3((unsigned)((dwt_total() + 255) / 256)), dim3(256), 0, s, params, thi,
                        tlo);
     if (blocks > 0) {
+        // two 64-row workgroups per block: every row of every block gets its dZ (zero past n)
         if (split)
-            hipLaunchKernelGGL(k_deform_bwd_rows<true>, dim3((unsigned)blocks), dim3(256), 0, s, n, mean, ddelta,
-                               thi, tlo, dz, dbp, de, dmean, save_masks((__bf16*)save, n));
+            hipLaunchKernelGGL((k_deform_bwd_rows<true, 64>), dim3((unsigned)(2 * blocks)), dim3(256), 0, s, n, mean,
+                               ddelta, thi, tlo, dz, dbp, de, dmean, save_masks((__bf16*)save, n));
         else
-            hipLaunchKernelGGL(k_deform_bwd_rows<false>, dim3((unsigned)blocks), dim3(256), 0, s, n, mean, ddelta,
-                               thi, tlo, dz, dbp, de, dmean, save_masks((__bf16*)save, n));
+            hipLaunchKernelGGL((k_deform_bwd_rows<false, 64>), dim3((unsigned)(2 * blocks)), dim3(256), 0, s, n,
+                               mean, ddelta, thi, tlo, dz, dbp, de, dmean, save_masks((__bf16*)save, n));
         const dim3 grid((unsigned)chunks, (unsigned)kWParts);
         if (split)
             hipLaunchKernelGGL(k_deform_wgrad<true>, grid, dim3(512), 0, s, blocks, bpc, dz, save, part);
         else
             hipLaunchKernelGGL(k_deform_wgrad<false>, grid, dim3(512), 0, s, blocks, bpc, dz, save, part);
+        // bias partials of the 64-row halves, summed in order over each chunk's blocks
         hipLaunchKernelGGL(k_deform_bias_part, dim3((unsigned)chunks, (unsigned)(kDepth + 1)), dim3(256), 0, s,
-                           blocks, bpc, dbp, bpart);
+                           2 * blocks, 2 * bpc, dbp, bpart);
     }
     const size_t total = dsrc_off(kDepth + 1);
     hipLaunchKernelGGL(k_deform_reduce, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s,
