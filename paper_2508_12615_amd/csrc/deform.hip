@@ -791,6 +791,17 @@ __host__ __device__ constexpr WPart wpart(int v)
                     : WPart{kDepth, 1, 8, (int)save_col_h(kDepth), kW, 0};
 }
 
+// The weight-gradient kernel maps waves to tiles for these three part shapes only.
+constexpr bool wpart_shapes_known()
+{
+    for (int v = 0; v < kWParts; ++v) {
+        const WPart P = wpart(v);
+        if (!((P.mt == 8 && P.nt == 8) || (P.mt == 8 && P.nt == 3) || (P.mt == 1 && P.nt == 8))) return false;
+    }
+    return true;
+}
+static_assert(wpart_shapes_known(), "weight-gradient part shapes");
+
 template <bool SPLIT>
 __global__ void __launch_bounds__(512) k_deform_wgrad(int32_t n_blocks, int blocks_per_chunk,
                                                       const __bf16* __restrict__ dz, const __bf16* __restrict__ save,
@@ -853,48 +864,66 @@ __global__ void __launch_bounds__(512) k_deform_wgrad(int32_t n_blocks, int bloc
         sstore(0);
     }
     __syncthreads();
-    for (int st = 0; st < steps; ++st) {
-        const int cur = st & 1;
-        if (st + 1 < steps) gload(st + 1);   // in flight during this step's products
-#pragma unroll
-        for (int kk = 0; kk < 32; kk += 16) {
-#pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                const int ti = w + 8 * i;
-                if (ti >= T) break;
-                const int mi = ti / P.nt, ni = ti - mi * P.nt;
-                const int ao = (32 * mi + lr) * kZS + kk + lk, bo = (32 * ni + lr) * kZS + kk + lk;
-                const bf16x8 a_h = *reinterpret_cast<const bf16x8*>(&zs[cur][0][ao]);
-                const bf16x8 b_h = *reinterpret_cast<const bf16x8*>(&as[cur][0][bo]);
-                acc[i] = mfma(a_h, b_h, acc[i]);
-                if (SPLIT) {
-                    const bf16x8 a_l = *reinterpret_cast<const bf16x8*>(&zs[cur][1][ao]);
-                    const bf16x8 b_l = *reinterpret_cast<const bf16x8*>(&as[cur][1][bo]);
-                    acc[i] = mfma(a_h, b_l, acc[i]);
-                    acc[i] = mfma(a_l, b_h, acc[i]);
-                }
-            }
-        }
-        // the other stage was last read in the previous step, before the barrier that ended it
-        if (st + 1 < steps) sstore(cur ^ 1);
-        __syncthreads();
-    }
-    // result element e of tile (mi, ni): unit 32 mi + 8 (e / 4) + 4 (l / 32) + e % 4, input 32 ni + l % 32
     const DLayer L = dlayer(P.j);
     float* pc = part + (size_t)blockIdx.x * dw_total() + dw_off(P.j);
+    // Each wave takes an RM x RN block of 32x32 tiles at (mi0, ni0), so it reads
+    // RM + RN fragment pairs from LDS per 16-deep step for RM * RN products.
+    auto run = [&](auto rmc, auto rnc, int mi0, int ni0) __attribute__((always_inline)) {
+        constexpr int RM = decltype(rmc)::value, RN = decltype(rnc)::value;
+        for (int st = 0; st < steps; ++st) {
+            const int cur = st & 1;
+            if (st + 1 < steps) gload(st + 1);   // in flight during this step's products
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-        const int ti = w + 8 * i;
-        if (ti >= T) break;
-        const int mi = ti / P.nt, ni = ti - mi * P.nt;
-        const int col = 32 * ni + lr;
-        if (col >= P.avalid) continue;
+            for (int kk = 0; kk < 32; kk += 16) {
+                bf16x8 ah[RM], al[RM], bh[RN], bl[RN];
 #pragma unroll
-        for (int e = 0; e < 16; ++e) {
-            const int row = 32 * mi + 8 * (e >> 2) + 4 * hs + (e & 3);
-            pc[(size_t)row * L.klen + P.ccol + col] = acc[i][e];
+                for (int a = 0; a < RM; ++a) {
+                    const int ao = (32 * (mi0 + a) + lr) * kZS + kk + lk;
+                    ah[a] = *reinterpret_cast<const bf16x8*>(&zs[cur][0][ao]);
+                    if (SPLIT) al[a] = *reinterpret_cast<const bf16x8*>(&zs[cur][1][ao]);
+                }
+#pragma unroll
+                for (int b = 0; b < RN; ++b) {
+                    const int bo = (32 * (ni0 + b) + lr) * kZS + kk + lk;
+                    bh[b] = *reinterpret_cast<const bf16x8*>(&as[cur][0][bo]);
+                    if (SPLIT) bl[b] = *reinterpret_cast<const bf16x8*>(&as[cur][1][bo]);
+                }
+#pragma unroll
+                for (int a = 0; a < RM; ++a)
+#pragma unroll
+                    for (int b = 0; b < RN; ++b) {
+                        f32x16& c = acc[a * RN + b];
+                        c = mfma(ah[a], bh[b], c);
+                        if (SPLIT) {
+                            c = mfma(ah[a], bl[b], c);
+                            c = mfma(al[a], bh[b], c);
+                        }
+                    }
+            }
+            // the other stage was last read in the previous step, before the barrier that ended it
+            if (st + 1 < steps) sstore(cur ^ 1);
+            __syncthreads();
         }
-    }
+        // result element e of tile (mi, ni): unit 32 mi + 8 (e / 4) + 4 (l / 32) + e % 4, input 32 ni + l % 32
+#pragma unroll
+        for (int i = 0; i < RM * RN; ++i) {
+            const int mi = mi0 + i / RN, ni = ni0 + i % RN;
+            const int col = 32 * ni + lr;
+            if (col >= P.avalid) continue;
+#pragma unroll
+            for (int e = 0; e < 16; ++e) {
+                const int row = 32 * mi + 8 * (e >> 2) + 4 * hs + (e & 3);
+                pc[(size_t)row * L.klen + P.ccol + col] = acc[i][e];
+            }
+        }
+    };
+    using I1 = std::integral_constant<int, 1>;
+    if (P.nt == 8 && P.mt == 8)   // 8 x 8 tiles: waves in 2 x 4, 4 x 2 tiles each
+        run(std::integral_constant<int, 4>{}, std::integral_constant<int, 2>{}, 4 * (w & 1), 2 * (w >> 1));
+    else if (P.nt == 3)           // 8 x 3 tiles: one row of tiles per wave
+        run(I1{}, std::integral_constant<int, 3>{}, w, 0);
+    else                          // 1 x 8 tiles: one tile per wave
+        run(I1{}, I1{}, 0, w);
 }
 
 // Bias gradients per chunk: thread r of (chunk k, layer j) sums unit r of
