@@ -143,7 +143,8 @@ def test_param_count_matches_oracle():
     assert B.wipes_deform_param_count() == D.param_count()
 
 
-@pytest.mark.parametrize("n", [1, 31, 32, 33, 1000])
+# sizes around the 32-row tiles, the 64-row workgroups and the 128-row stored blocks
+@pytest.mark.parametrize("n", [1, 31, 32, 33, 63, 64, 65, 128, 129, 1000])
 def test_forward_backward_parity(n):
     params, x, t, dout = _inputs(n, 300 + n)
     dout = sanitize(dout, params, x, t)
@@ -251,7 +252,7 @@ def test_full_size_sampled():
     x = synth.scene_3d(n, 2025)["mean"]
     t = float(np.float32(0.625))
     g = np.random.default_rng(2026)
-    rows = np.unique(np.r_[g.integers(0, n, 40), [0, 31, 32, n - 33, n - 32, n - 1]])
+    rows = np.unique(np.r_[g.integers(0, n, 40), [0, 31, 32, 63, 64, 127, 128, n - 65, n - 64, n - 33, n - 32, n - 1]])
     dout = np.zeros((n, D.N_OUT), np.float32)
     dout[rows] = sanitize(g.normal(0.0, 1.0, (rows.size, D.N_OUT)), params, x[rows], t)
     _say("deform full size n=%d, %d sampled rows" % (n, rows.size))
