@@ -86,8 +86,14 @@ __device__ __forceinline__ PrimU load_prim(const Rec* __restrict__ recs, uint32_
     return u;
 }
 
+// One (pixel, primitive) evaluation: offsets from the mean, e2 = the
+// Gaussian's base-2 exponent minus one, E = exp2(e2) (half the Gaussian
+// factor), the phase in turns and W = E (1 + cos phi), which is W' (the
+// Gaussian times the raised cosine (1 + cos phi) / 2).  Taking the half
+// into the exponent, where the last product of the quadratic form becomes a
+// fused multiply-add, saves the instruction that would scale the cosine.
 struct PairEval {
-    float dx, dy, e2, E, ph, K, W;
+    float dx, dy, e2, E, ph, W;
 };
 
 __device__ __forceinline__ PairEval eval_at(float mrx, float mry, float ca2, float cb2, float cc2, float fxr, float fyr,
@@ -97,11 +103,10 @@ __device__ __forceinline__ PairEval eval_at(float mrx, float mry, float ca2, flo
     p.dx = lx - mrx;
     p.dy = ly - mry;
     const float t = fmaf(ca2, p.dx, cb2 * p.dy);
-    p.e2 = fmaf(t, p.dx, (cc2 * p.dy) * p.dy);
+    p.e2 = fmaf(t, p.dx, fmaf(cc2 * p.dy, p.dy, -1.0f));
     p.ph = fmaf(fxr, p.dx, fmaf(fyr, p.dy, ph0));
     p.E = __builtin_amdgcn_exp2f(p.e2);
-    p.K = fmaf(0.5f, __builtin_amdgcn_cosf(__builtin_amdgcn_fractf(p.ph)), 0.5f);
-    p.W = p.K * p.E;
+    p.W = fmaf(p.E, __builtin_amdgcn_cosf(__builtin_amdgcn_fractf(p.ph)), p.E);
     return p;
 }
 
@@ -327,7 +332,7 @@ __device__ __forceinline__ void fwd_block(const ImgDesc* __restrict__ descs, int
     const uint64_t vm = __builtin_amdgcn_ballot_w64(valid);
     uint64_t am = vm;
     PixBox live = block_box(am, bx, by);
-    const float thr2 = kp.q_add * kConicScale;
+    const float thr2 = fmaf(kp.q_add, kConicScale, -1.0f);   // support test on e2 (exponent minus one)
     const float lg2_amin = __builtin_amdgcn_logf(kp.alpha_min);
     unsigned long long* cm_row = cmask ? cmask + (size_t)blk * cmask_words : nullptr;
     if (G.start < G.end) {
@@ -561,11 +566,12 @@ __device__ __forceinline__ int reduce12_index(int l)
 // conic and f' as coefficients (dL/dmu'x = -2 (ca S_qx + cb S_qy) - f'x S_phi,
 // dL/dcb = 2 S_qxy, ...), so the projection backward applies them once per
 // primitive instead of every pair paying for them.  The same holds for the
-// factor -o/2 that dq and dphi share: with d = dL/d(o W') of the pair,
-// dL/dq = -o/2 W' d and dL/dphi = -o/2 E sin(phi) d (E the Gaussian factor,
-// W' = E (1 + cos phi) / 2), so the slots hold the sums without it (the
-// first seven values and the last) and the projection backward multiplies
-// them by -o/2.
+// opacity factors: with d = dL/d(o W') of the pair, G the Gaussian factor
+// and W' = G (1 + cos phi) / 2, dL/dq = -o/2 W' d and dL/dphi =
+// -o/2 G sin(phi) d = -o (G/2) sin(phi) d.  The slots hold the dq terms (the
+// first five values) without -o/2 and the dphi terms (values 5, 6 and the
+// last), built from the evaluation's G/2, without -o; the projection
+// backward multiplies them by -o/2 and -o.
 constexpr int kSlot = 12;
 
 // Per-pair gradient terms shared by both modes: d = dL/d(o W') of the pair,
@@ -574,7 +580,7 @@ __device__ __forceinline__ void pair_grads(float v[12], const PairEval& p, float
 {
     const float sn = __builtin_amdgcn_sinf(__builtin_amdgcn_fractf(p.ph));
     const float dq = v[7];                 // dL/dq / (-o/2)
-    const float dph = (p.E * sn) * d;      // dL/dphi (radians) / (-o/2)
+    const float dph = (p.E * sn) * d;      // dL/dphi (radians) / (-o): p.E is half the Gaussian factor
     const float qx = dq * p.dx, qy = dq * p.dy;
     v[0] = qx;
     v[1] = qy;
@@ -642,7 +648,7 @@ __device__ __forceinline__ void bwd_tile(const ImgDesc* __restrict__ descs, int 
         g2 = dLdC[3 * pix + 2];
     }
     float Sg = kp.bg[0] * g0 + kp.bg[1] * g1 + kp.bg[2] * g2;   // dL/dC . colour behind (alpha)
-    const float thr2 = kp.q_add * kConicScale;
+    const float thr2 = fmaf(kp.q_add, kConicScale, -1.0f);   // support test on e2, as in the forward
     const float lx = (float)(l & 7) + 0.5f, ly = (float)(l >> 3) + 0.5f;
     const int32_t btop = __builtin_amdgcn_readfirstlane(wave_max_i32(on ? lst : -1));
     if (l == 0) top[w] = (uint32_t)(btop + 1);
@@ -967,7 +973,7 @@ __global__ void __launch_bounds__(kWave * kWpb) k_pair_stats(const ImgDesc* __re
         uint32_t b0, b1;
         const PrimU u = load_prim(recs, prim, G.ox, G.oy, &b0, &b1);
         const uint32_t m = subblock_mask<TW, TH>(b0, b1, G.ox, G.oy);
-        const float thr = kq * (MODE == WIPES_2D_ADDITIVE ? kp.q_add : 2.0f * logf(u.op / kp.alpha_min));
+        const float thr = fmaf(kq, MODE == WIPES_2D_ADDITIVE ? kp.q_add : 2.0f * logf(u.op / kp.alpha_min), -1.0f);
 #pragma unroll
         for (int k = 0; k < NSB; ++k) {
             if (!(m & (1u << k))) continue;

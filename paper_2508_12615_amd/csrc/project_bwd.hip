@@ -210,16 +210,19 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) k
     if (!inr) return;
     // The slots hold sums of (dq dx, dq dy, dq dx^2, dq dx dy, dq dy^2,
     // dphi dx, dphi dy, opacity, colour, dphi) over the primitive's pixels,
-    // the dq and dphi terms without their common factor -o/2, applied here:
+    // the dq terms without their factor -o/2 and the dphi terms without -o
+    // (the blend builds them from half the Gaussian factor), applied here:
     // with its conic and f' they give d/d(mu', conic, f') (q = ca dx^2 +
     // 2 cb dx dy + cc dy^2 and phi = f' . (x - mu')).  A primitive with no
     // instance keeps all-zero sums (its record need not be finite).
     if (c) {
         const Rec& R0 = recs[i];
-        const float hop = -0.5f * R0.op;
+        const float hop = -0.5f * R0.op, mop = -R0.op;
 #pragma unroll
-        for (int k = 0; k < 7; ++k) acc[k] *= hop;
-        acc[11] *= hop;
+        for (int k = 0; k < 5; ++k) acc[k] *= hop;
+        acc[5] *= mop;
+        acc[6] *= mop;
+        acc[11] *= mop;
         const float sqx = acc[0], sqy = acc[1], sph = acc[11];
         acc[0] = -2.0f * (R0.ca * sqx + R0.cb * sqy) - R0.fx * sph;
         acc[1] = -2.0f * (R0.cb * sqx + R0.cc * sqy) - R0.fy * sph;
