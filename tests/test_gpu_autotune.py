@@ -7,12 +7,15 @@ mode, the same final transmittance; the stopping position is an index into
 the tile-ordered list, so only whether a pixel has one is compared).  Gradients sum
 the same per-pixel terms in a different grouping per tile shape, so they
 agree to FP32 rounding of those sums (1e-4 relative per tensor, the bar of the
-other cross-tile-shape comparisons).
+other cross-tile-shape comparisons; the derivation and the measured values,
+2.3e-5 at most here, are given with test_tile_shape_and_launch_form_do_not_change_results).
 """
 import numpy as np
 import pytest
 
 from helpers import rel_err, small_scene_2d, small_scene_3d, to_torch
+
+XSHAPE_GRAD_TOL = 1e-4   # FP32 reordering across tile shapes (see test_gpu_parity)
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -46,6 +49,7 @@ def _check_all_candidates(mode, views, dL, label):
     assert best in cands and times[best] == min(times.values())
     _say("%s: autotuner chose %s (%.3f ms)" % (label, best, times[best]))
     ref = _render(Rasterizer(mode), views, dL)
+    worst = 0.0
     for (tw, th, pe) in cands:
         got = _render(Rasterizer(mode, tile_w=tw, tile_h=th, persistent=pe), views, dL)
         for k in ("image", "T"):
@@ -55,7 +59,10 @@ def _check_all_candidates(mode, views, dL, label):
             assert np.array_equal(got["last"] < 0, ref["last"] < 0), (label, (tw, th, pe))
         for gi, ri in zip(got["grads"], ref["grads"]):
             for k in ri:
-                assert rel_err(gi[k], ri[k]) < 1e-4, (label, (tw, th, pe), k)
+                e = rel_err(gi[k], ri[k])
+                worst = max(worst, e)
+                assert e < XSHAPE_GRAD_TOL, (label, (tw, th, pe), k)
+    _say("%s: worst cross-candidate gradient rel err %.2e" % (label, worst))
 
 
 def test_autotune_2d_batch():

@@ -24,6 +24,10 @@ from paper_2508_12615_amd.raster import Rasterizer, render  # noqa: E402
 
 COV = {"rs": (B.WIPES_COV_RS, O.COV_RS), "cholesky": (B.WIPES_COV_CHOLESKY, O.COV_CHOLESKY)}
 
+# Gradients across tile shapes: FP32 reordering of the same per-pixel sums (derivation and measured
+# values in test_tile_shape_and_launch_form_do_not_change_results).
+XSHAPE_GRAD_TOL = 1e-4
+
 
 def rast2d(cov="rs", **kw):
     return Rasterizer(B.WIPES_2D_ADDITIVE, cov=COV[cov][0], **kw)
@@ -289,7 +293,12 @@ def test_tile_shape_and_launch_form_do_not_change_results(mode):
     """The per-pixel rule is tile-independent.  Grid, queue and longest-first queue launches of one
     tile shape give bit-identical images and gradients.  Across tile shapes the images are
     bit-identical too (every 8x8 block sees the same primitives in the same order, in block-relative
-    coordinates); gradients agree to FP32 rounding of the per-tile sums (1e-4 relative)."""
+    coordinates).  Gradients sum the same per-pixel terms grouped differently (block, tile and slot
+    sums), so they differ by FP32 reordering: about sqrt(n) u of the terms' magnitude for n terms
+    (u = 2^-24; n up to ~8e3 pixels per primitive here gives ~5e-6), more where a gradient's terms
+    cancel.  Measured per tensor: 6.1e-6 (2D) and 7.1e-6 (3D) here, 2.3e-5 over the autotuner's 2D
+    batch (primitives of up to ~1e4 pixels).  The bar, 1e-4 relative per tensor, keeps a 4x margin
+    over the largest and sits far inside the oracle bar (1e-3)."""
     if mode == B.WIPES_2D_ADDITIVE:
         W, H = 131, 77
         prims = synth.prims_2d(900, W, H, 51)
@@ -300,6 +309,7 @@ def test_tile_shape_and_launch_form_do_not_change_results(mode):
     tp = to_torch(prims)
     g = torch.from_numpy(np.random.default_rng(7).normal(0, 1, (W * H, 3)).astype(np.float32)).cuda()
     base = None
+    worst = 0.0
     for tile in [(16, 16), (8, 8), (16, 8), (8, 16), (32, 8), (32, 16)]:
         same_tile = None
         for persistent in (0, 1, 2, 3):
@@ -318,7 +328,10 @@ def test_tile_shape_and_launch_form_do_not_change_results(mode):
                 continue
             assert np.array_equal(out[0], base[0]), (tile, persistent)
             for k in base[1]:
-                assert rel_err(out[1][k], base[1][k]) < 1e-4, (tile, persistent, k)
+                e = rel_err(out[1][k], base[1][k])
+                worst = max(worst, e)
+                assert e < XSHAPE_GRAD_TOL, (tile, persistent, k)
+    print("worst cross-shape gradient rel err %.2e" % worst, flush=True)
 
 
 @pytest.mark.parametrize("launch", [(16, 16, 0), (32, 16, 2), (8, 8, 1), (8, 16, 3)])
