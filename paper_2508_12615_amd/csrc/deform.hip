@@ -12,18 +12,21 @@
 // hi*hi only (three times fewer matrix instructions, ~2^-8 relative).
 //
 // Row kernels (forward, and the backward through the layers): one workgroup
-// of 4 waves per block of 128 primitives, one workgroup per CU (the block's
-// activations fill 132 KB of LDS: 128 rows x 256 hidden units as bf16 hi/lo
-// pairs).  Each wave computes 64 output units for all 128 rows -- 8 tiles of
-// v_mfma_f32_32x32x16_bf16 -- so every weight fragment it streams from L2
-// feeds four row tiles and every activation fragment it reads from LDS feeds
-// two unit tiles.  The encoding (76 values per row) is not kept in LDS: the
-// first and the sixth layer compute their encoding fragments in registers
-// (exact range reduction, hardware sine and cosine in revolutions).  Bias,
-// ReLU and the hi/lo split happen in the epilogue, written back into the same
-// LDS rows after a barrier.
+// of 4 waves per 64 primitives, two workgroups per CU (each holds its rows'
+// activations in 66 KB of LDS: 64 rows x 256 hidden units as bf16 hi/lo
+// pairs), so one workgroup's epilogue and barriers overlap the other's
+// matrix products.  Each wave computes 64 output units for all 64 rows -- 4
+// tiles of v_mfma_f32_32x32x16_bf16 -- so every weight fragment it streams
+// from L2 feeds two row tiles and every activation fragment it reads from
+// LDS feeds two unit tiles.  The encoding (76 values per row) is computed
+// once per workgroup into a double-buffered LDS stage, 16 columns per K step
+// of the first and the sixth layer (exact range reduction, hardware sine and
+// cosine in revolutions).  Bias, ReLU and the hi/lo split happen in the
+// epilogue, written back into the same LDS rows after a barrier.
 //
-// For the backward the forward stores every layer input per block, column
+// Stored arrays (the backward's inputs) are kept per block of 128 rows; the
+// two 64-row workgroups of a block each write their half.  For the backward
+// the forward stores every layer input per block, column
 // major over groups of 32 rows (each lane holds four consecutive rows of one
 // unit after the matrix product: one 8-byte store per plane), the layout in
 // which the weight-gradient products read their K runs (the rows) as
@@ -44,7 +47,7 @@ constexpr int kDepth = 8;
 constexpr int kSkip = 5;
 constexpr int kOut = 13;
 constexpr int kOutPad = 32;
-constexpr int kRB = 128;                          // primitives per block (workgroup of the row kernels)
+constexpr int kRB = 128;                          // primitives per stored block (two row-kernel workgroups)
 constexpr int kAS = kW + 8;                       // LDS row stride of the activations (bf16 elements)
 constexpr int kSaveCols = kInPad + kDepth * kW;   // stored layer inputs per row: e, then h_1..h_8
 constexpr int kZS = 32 + 8;                       // LDS row stride of the weight-gradient stage
@@ -504,17 +507,18 @@ hipError_t launch_deform_fwd(int32_t n, const float* mean, float t, const float*
 
 // ------------------------------------------------------------------ backward
 //
-// Rows kernel, per block of 128 rows, the forward's tiling with the
-// transposed split weights as the B operand: dIn_j = dZ_j W_j for j = 8 .. 0
-// (dZ_8 = dL/d offsets; dZ_{j-1} = dIn_j where the stored h_j > 0), the
-// encoding's gradient collected from layer 0 and from the skip layer's
-// encoding inputs, then dL/dmean through the encoding's derivative.  Each
-// dZ_j is also stored per block column major over the rows, with its column
-// sums (the bias gradients).
+// Rows kernel, per 64 rows (two workgroups per 128-row stored block), the
+// forward's tiling with the transposed split weights as the B operand:
+// dIn_j = dZ_j W_j for j = 8 .. 0 (dZ_8 = dL/d offsets; dZ_{j-1} = dIn_j
+// where the stored h_j > 0), the encoding's gradient collected from layer 0
+// and from the skip layer's encoding inputs, then dL/dmean through the
+// encoding's derivative.  Each dZ_j is also stored per block column major
+// over the rows, with its column sums per workgroup (the bias gradients).
 //
 // Weight gradients dW_j = sum over rows of dZ_j^T a_j: one workgroup of 8
 // waves per (chunk of blocks, layer part) stages 32 rows of dZ_j and a_j at a
-// time in LDS and accumulates its layer's whole 256 x 256 (at most) product;
+// time in LDS and accumulates its layer's whole 256 x 256 (at most) product,
+// each wave a block of 4 x 2 (or 1 x 3, 1 x 1) tiles of 32 x 32;
 // a last kernel adds the chunks' partial sums in a fixed order (deterministic)
 // into the caller's parameter layout.
 
