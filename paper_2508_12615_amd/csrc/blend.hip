@@ -696,13 +696,14 @@ __device__ __forceinline__ void bwd_tile(const ImgDesc* __restrict__ descs, int 
     uint64_t mn = c0 > G.start ? hits_of(n0, n1) : 0ull;
     uint32_t pn = vals[min((n0 & ~63u) + (uint32_t)l, e1)];
     // The combine step gives four threads to each list position of the chunk
-    // (three slot values each), in CR rounds of NT / 4 positions.  The
+    // (the first three take four slot values each, as one 16-byte piece), in
+    // CR rounds of NT / 4 positions.  The
     // positions' primitives are loaded a chunk ahead (in the previous chunk's
     // prologue) and, in one round, their packs after the previous chunk's
     // replay, so the combine finds both in registers.
     constexpr int CR = NT >= 4 * kWave ? 1 : (4 * kWave) / NT;
     constexpr uint32_t CP = (uint32_t)NT / 4u;
-    const uint32_t co0 = (uint32_t)tid >> 2, cc3 = ((uint32_t)tid & 3u) * 3u;
+    const uint32_t co0 = (uint32_t)tid >> 2, cc4 = ((uint32_t)tid & 3u) * 4u;
     const int tcx = G.ox / TW, tcy = G.oy / TH;   // this tile in its image
     auto combine_entries = [&](uint32_t lo, uint32_t hi1, bool (&cm)[CR], uint32_t (&cp)[CR]) {
         const uint32_t bb = lo & ~63u;
@@ -827,22 +828,21 @@ __device__ __forceinline__ void bwd_tile(const ImgDesc* __restrict__ descs, int 
 #pragma unroll
         for (int r = 0; r < CR; ++r) {
             const uint32_t co = co0 + (uint32_t)r * CP;
-            if (cmine[r] && ((anyhit >> co) & 1ull)) {
+            if (cc4 < (uint32_t)kSlot && cmine[r] && ((anyhit >> co) & 1ull)) {
                 const uint32_t ce = slot_of<TW, TH>(CR == 1 ? cq : pk[cprim[r]], tcx, tcy);
-                const uint32_t rr = co * kSlot + cc3;
-                float s3[3];
+                // 16-byte pieces: a position's 12 values are 48 bytes in LDS and in the slots
+                const uint32_t rr = co * kSlot + cc4;
+                float4 sum = *reinterpret_cast<const float4*>(pcur + rr);
 #pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    float sum = pcur[rr + c];
-#pragma unroll
-                    for (int k = 1; k < NB; ++k) sum += pcur[(size_t)k * kWave * kSlot + rr + c];
-                    s3[c] = sum;
+                for (int k = 1; k < NB; ++k) {   // blocks added in order
+                    const float4 x = *reinterpret_cast<const float4*>(pcur + (size_t)k * kWave * kSlot + rr);
+                    sum.x += x.x;
+                    sum.y += x.y;
+                    sum.z += x.z;
+                    sum.w += x.w;
                 }
-                float* dst = slots + (size_t)ce * kSlot + cc3;
-                dst[0] = s3[0];
-                dst[1] = s3[1];
-                dst[2] = s3[2];
-                if (cc3 == 0) atomicOr(smark + (ce >> 5), 1u << (ce & 31u));
+                *reinterpret_cast<float4*>(slots + (size_t)ce * kSlot + cc4) = sum;
+                if (cc4 == 0) atomicOr(smark + (ce >> 5), 1u << (ce & 31u));
             }
         }
         pbuf ^= 1u;
