@@ -684,17 +684,27 @@ __device__ __forceinline__ void bwd_tile(const ImgDesc* __restrict__ descs, int 
     // List entries are read for every lane, at positions clamped into the
     // tile's list, so that they are in flight together with the chunk's
     // contribution word instead of waiting for it; only the hit lanes' record
-    // loads depend on the word.
+    // loads depend on the word.  Records are loaded two chunks ahead (a
+    // chunk with few hits in this block gives its loads little time), list
+    // entries and hits three.  A chunk that does not exist has c0 = c1 = start.
     const uint32_t e1 = G.end - 1u;
     uint32_t c1 = hi, c0 = lo_of(hi);
     const uint32_t p0 = vals[min((c0 & ~63u) + (uint32_t)l, e1)];
     uint64_t m = hits_of(c0, c1);
     Rec cur{};
     if ((m >> l) & 1ull) cur = recs[p0];
-    // the next chunk's hits and list entries
+    // the next chunk: hits and records
     uint32_t n1 = c0, n0 = c0 > G.start ? lo_of(c0) : c0;
     uint64_t mn = c0 > G.start ? hits_of(n0, n1) : 0ull;
-    uint32_t pn = vals[min((n0 & ~63u) + (uint32_t)l, e1)];
+    Rec nx1{};
+    {
+        const uint32_t p1 = vals[min((n0 & ~63u) + (uint32_t)l, e1)];
+        if ((mn >> l) & 1ull) nx1 = recs[p1];
+    }
+    // the chunk after it: hits and list entries
+    uint32_t nn1 = n0, nn0 = n0 > G.start ? lo_of(n0) : n0;
+    uint64_t mnn = n0 > G.start ? hits_of(nn0, nn1) : 0ull;
+    uint32_t pn2 = vals[min((nn0 & ~63u) + (uint32_t)l, e1)];
     // The combine step gives four threads to each list position of the chunk
     // (the first three take four slot values each, as one 16-byte piece), in
     // CR rounds of NT / 4 positions.  The
@@ -736,15 +746,17 @@ __device__ __forceinline__ void bwd_tile(const ImgDesc* __restrict__ descs, int 
             z[2] = make_float4(0.f, 0.f, 0.f, 0.f);
         }
         const bool more = c0 > G.start;   // uniform over the workgroup
-        Rec nx{};
-        uint32_t nn1 = n0, nn0 = n0, pnn = 0;
-        uint64_t mnn = 0ull;
-        if (more) {   // the next chunk's records (and the one after's entries) are in flight
-            if ((mn >> l) & 1ull) nx = recs[pn];
-            if (n0 > G.start) {
-                nn0 = lo_of(n0);
-                mnn = hits_of(nn0, nn1);
-                pnn = vals[min((nn0 & ~63u) + (uint32_t)l, e1)];
+        // the records of the chunk after next (and the entries of the one
+        // after that) go in flight; the next chunk's are already
+        Rec nx2{};
+        uint32_t m31 = nn0, m30 = nn0, p3 = 0;
+        uint64_t h3 = 0ull;
+        if (n0 > G.start) {
+            if ((mnn >> l) & 1ull) nx2 = recs[pn2];
+            if (nn0 > G.start) {
+                m30 = lo_of(nn0);
+                h3 = hits_of(m30, m31);
+                p3 = vals[min((m30 & ~63u) + (uint32_t)l, e1)];
             }
         }
         if (l == 0) hcur[w] = m;
@@ -853,14 +865,18 @@ __device__ __forceinline__ void bwd_tile(const ImgDesc* __restrict__ descs, int 
             cprim[r] = cprim_n[r];
         }
         cq = cq_n;
-        cur = nx;
+        cur = nx1;
+        nx1 = nx2;
         m = mn;
+        mn = mnn;
+        mnn = h3;
+        pn2 = p3;
         c1 = n1;
         c0 = n0;
-        mn = mnn;
-        pn = pnn;
         n1 = nn1;
         n0 = nn0;
+        nn1 = m31;
+        nn0 = m30;
     }
 }
 
