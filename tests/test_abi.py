@@ -106,3 +106,12 @@ def test_null_context_is_rejected_before_any_device_work(B):
     k = C.c_int64()
     assert B.lib().wipes_bin_sort(None, C.byref(p), C.byref(b), C.byref(buf), C.byref(buf), C.byref(k),
                                   None) == B.WIPES_ERR_INVALID
+
+
+def test_missing_library_raises(monkeypatch):
+    """Without the built library the binding refuses to load: there is no fallback path."""
+    from paper_2508_12615_amd import binding
+    monkeypatch.setattr(binding, "_lib", None)
+    monkeypatch.setattr(binding, "LIB_PATH", os.path.join(os.path.dirname(binding.LIB_PATH), "no_such_libwipes.so"))
+    with pytest.raises(ImportError):
+        binding.lib()
