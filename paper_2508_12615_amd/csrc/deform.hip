@@ -625,6 +625,10 @@ __global__ void __launch_bounds__(256, 128 / RB) k_deform_bwd_rows(int32_t n, co
                 }
             }
         }
+        if (!SPLIT && j == 0) {   // dZ_0 from LDS to its stored copy (layer 0 has no hidden-unit K loop to spread it over)
+            for (int c = tid; c < copy_chunks<RB>(); c += 256)
+                copy_chunk<RB>(c, ghi, glo, dzb + dz_region(0), (size_t)kW * kRB, kW, 0, nullptr, rb);
+        }
         // encoding inputs first: the skip layer's part goes to scratch, and layer 0's is added to
         // it by the same lanes (same elements); the position gradient reads the sum
         f32x16 acce[RT];
@@ -705,7 +709,10 @@ __global__ void __launch_bounds__(256, 128 / RB) k_deform_bwd_rows(int32_t n, co
                     }
                 }
             };
-            // software pipeline as in the forward
+            // software pipeline as in the forward.  In the one-product (bf16) form dZ_j (j < 8: dZ_8
+            // was stored directly) goes to its stored copy a few 16-byte chunks per step, the stores
+            // overlapping the products; the three-product form has no registers to spare for it
+            // (it would spill) and stores dZ_{j-1} in one pass after the epilogue instead
             bf16x8 bh0[2], bl0[2], bh1[2], bl1[2], ah0[RT], al0[RT], ah1[RT], al1[RT];
             load_h(0, bh0, bl0);
             load_a(0, ah0, al0);
@@ -713,6 +720,14 @@ __global__ void __launch_bounds__(256, 128 / RB) k_deform_bwd_rows(int32_t n, co
             for (int k = 0; k < Kb; k += 32) {
                 load_h(k + 16, bh1, bl1);
                 load_a(k + 16, ah1, al1);
+                if (!SPLIT && j < kDepth) {   // Kb = kW here: kW / 32 steps
+                    constexpr int CPS = copy_chunks<RB>() / 256 / (kW / 32);   // chunks per thread and step
+                    static_assert(CPS * 256 * (kW / 32) == copy_chunks<RB>(), "the copy divides over the steps");
+#pragma unroll
+                    for (int i = 0; i < CPS; ++i)
+                        copy_chunk<RB>(tid + 256 * ((k / 32) * CPS + i), ghi, glo, dzb + dz_region(j),
+                                       (size_t)kW * kRB, kW, 0, nullptr, rb);
+                }
                 __builtin_amdgcn_sched_barrier(0);
                 step_h(ah0, al0, bh0, bl0);
                 __builtin_amdgcn_sched_barrier(0);
@@ -750,8 +765,8 @@ __global__ void __launch_bounds__(256, 128 / RB) k_deform_bwd_rows(int32_t n, co
                 if (hs == 0) dbb[(size_t)(j - 1) * kW + u] = cs;
             }
         }
-        __syncthreads();
-        if (hpass) {   // dZ_{j-1} from LDS to its stored copy (16-byte chunks, contiguous over the workgroup)
+        __syncthreads();   // the next layer reads dZ_{j-1}
+        if (SPLIT && hpass) {   // dZ_{j-1} from LDS to its stored copy (16-byte chunks, contiguous over the workgroup)
             for (int c = tid; c < copy_chunks<RB>(); c += 256)
                 copy_chunk<RB>(c, ghi, glo, dzb + dz_region(j - 1), (size_t)kW * kRB, kW, 0, nullptr, rb);
         }
