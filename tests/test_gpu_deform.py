@@ -158,8 +158,10 @@ def test_forward_backward_parity(n):
     _say("  worst |err|/sigma %.2f, max rel %.2e" % (worst, float(np.abs(off - ref).max() / np.abs(ref).max())))
 
 
-def test_bf16_mode():
-    n = 500
+# 65 and 129 rows end inside the second 64-row workgroup of a 128-row block: the bf16 backward
+# stores dZ during the next layer's products, so its half-block offsets are exercised here
+@pytest.mark.parametrize("n", [65, 129, 500])
+def test_bf16_mode(n):
     params, x, t, dout = _inputs(n, 77)
     net = GD.Deformation(precision=B.WIPES_DEFORM_BF16)
     off, dp, dm = _run(net, params, x, t, dout)
